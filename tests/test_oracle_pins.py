@@ -1,0 +1,706 @@
+"""Pins of the FP64 oracle against closed forms, conservation laws, brute force and Monte Carlo.
+
+Each test checks the oracle against something other than itself, chosen so that a plausible
+mistake (a dropped term, a wrong sign or index, a transposed operand) fails at least one of them.
+All run on the CPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_10470_amd import workloads as W
+
+G = 9.81
+
+
+def _params(**kw):
+    p = W.SimParams()
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _env(actors, pairs=None, name="t"):
+    if pairs is None:
+        pairs = W._plane_pairs(actors)
+    return W.EnvSpec(name, list(actors), pairs)
+
+
+# ----------------------------------------------------------------------------- mass properties
+def _mc_mass_props(inside, lo, hi, n, seed):
+    """Monte Carlo volume, centroid and inertia (unit density) of the set `inside` within a box."""
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(lo, hi, size=(n, 3))
+    k = inside(pts)
+    vol_box = np.prod(np.array(hi) - np.array(lo))
+    p = pts[k]
+    V = vol_box * k.mean()
+    c = p.mean(axis=0)
+    d = p - c
+    r2 = (d * d).sum(1)
+    I = (np.eye(3)[None] * r2[:, None, None] - d[:, :, None] * d[:, None, :]).mean(0) * V
+    return V, c, I
+
+
+def _seg_dist(pts, a, b):
+    ab = b - a
+    t = np.clip(((pts - a) @ ab) / (ab @ ab), 0.0, 1.0)
+    return np.linalg.norm(pts - (a + t[:, None] * ab), axis=1)
+
+
+@pytest.mark.parametrize("p0,p1,r", [((0, 0, 0), (0, 0, 0.1), 0.1), ((0.05, -0.02, 0.01), (0.2, 0.1, -0.12), 0.06)])
+def test_capsule_mass_props_monte_carlo(p0, p1, r):
+    """Capsule = cylinder + two hemispherical caps (the caps dominate in the first case)."""
+    rho = 1000.0
+    shape = W.Shape("capsule", p0, p1, r, density=rho)
+    actor = W.Actor("c", [W.Link("b", -1, "free", shapes=[shape])])
+    # frame must sit at the COM for a free root: use a fixed root instead
+    actor.links[0].joint = "fixed"
+    oe = O.OracleEnv(_env([actor], []))
+    m, c, I = oe.mass_props()
+    a, b = np.array(p0, float), np.array(p1, float)
+    lo = np.minimum(a, b) - r
+    hi = np.maximum(a, b) + r
+    V, cm, Im = _mc_mass_props(lambda x: _seg_dist(x, a, b) <= r, lo, hi, 4_000_000, 1)
+    assert abs(m[0] - rho * V) < 4e-3 * m[0]
+    np.testing.assert_allclose(c[0], (a + b) / 2, atol=1e-12)
+    np.testing.assert_allclose(cm, (a + b) / 2, atol=5e-4)
+    np.testing.assert_allclose(I[0], rho * Im, atol=5e-3 * np.abs(I[0]).max())
+
+
+def test_sphere_and_box_mass_props_monte_carlo():
+    rho = 750.0
+    s = W.Shape("sphere", (0.1, 0.2, -0.3), radius=0.2, density=rho)
+    bx = W.Shape("box", (0.0, 0.0, 0.0), half=(0.1, 0.2, 0.05), density=rho)
+    actors = [W.Actor("s", [W.Link("b", -1, "fixed", shapes=[s])]), W.Actor("x", [W.Link("b", -1, "fixed", shapes=[bx])])]
+    oe = O.OracleEnv(_env(actors, []))
+    m, c, I = oe.mass_props()
+    V, cm, Im = _mc_mass_props(lambda x: np.linalg.norm(x - np.array(s.p0), axis=1) <= 0.2,
+                               np.array(s.p0) - 0.2, np.array(s.p0) + 0.2, 2_000_000, 2)
+    assert abs(m[0] - rho * V) < 4e-3 * m[0]
+    np.testing.assert_allclose(I[0], rho * Im, atol=5e-3 * np.abs(I[0]).max())
+    # the box is sampled exactly by a midpoint grid
+    n = 60
+    g = [(np.arange(n) + 0.5) / n * 2 * h - h for h in bx.half]
+    X, Y, Z = np.meshgrid(*g, indexing="ij")
+    dv = np.prod(np.array(bx.half) * 2) / n ** 3
+    Ixx = rho * dv * (Y ** 2 + Z ** 2).sum()
+    Iyy = rho * dv * (X ** 2 + Z ** 2).sum()
+    Izz = rho * dv * (X ** 2 + Y ** 2).sum()
+    np.testing.assert_allclose(np.diag(I[1]), [Ixx, Iyy, Izz], rtol=1e-3)
+    assert abs(m[1] - rho * 8 * 0.1 * 0.2 * 0.05) < 1e-12
+
+
+def test_given_mass_scales_distribution():
+    bx = W.free_box(half=(0.025, 0.025, 0.025), mass=0.125)
+    oe = O.OracleEnv(_env([bx], []))
+    m, c, I = oe.mass_props()
+    assert abs(m[0] - 0.125) < 1e-15
+    np.testing.assert_allclose(np.diag(I[0]), [0.125 / 3 * 2 * 0.025 ** 2] * 3, rtol=1e-12)
+
+
+def test_free_root_off_com_rejected():
+    bad = W.Actor("bad", [W.Link("b", -1, "free", shapes=[W.Shape("sphere", (0.1, 0, 0), radius=0.1)])])
+    with pytest.raises(ValueError):
+        O.OracleEnv(_env([bad], []))
+
+
+# ----------------------------------------------------------------------------- kinematics
+def test_fk_two_link_chain_by_hand():
+    a = W.Actor("arm", [W.Link("base", -1, "fixed"),
+                        W.Link("l1", 0, "revolute", anchor=(0.0, 0.0, 0.1), axis=(0, 0, 1),
+                               shapes=[W._capsule((0, 0, 0), (0.3, 0, 0), 0.02)]),
+                        W.Link("l2", 1, "revolute", anchor=(0.3, 0.0, 0.0), axis=(0, 1, 0),
+                               shapes=[W._capsule((0, 0, 0), (0.2, 0, 0), 0.02)]),
+                        W.Link("l3", 2, "prismatic", anchor=(0.2, 0.0, 0.0), axis=(1, 0, 0),
+                               shapes=[W._capsule((0, 0, 0), (0.1, 0, 0), 0.02)])],
+                root_pos=(1.0, 2.0, 0.5))
+    oe = O.OracleEnv(_env([a], []))
+    q1, q2, q3 = 0.7, -0.4, 0.05
+    root = np.array([[1.0, 2.0, 0.5, 0, 0, 0, 1] + [0] * 6])
+    dof = np.array([[q1, 0], [q2, 0], [q3, 0]])
+    R, p = oe.fk(root, dof)
+    Rz = np.array([[math.cos(q1), -math.sin(q1), 0], [math.sin(q1), math.cos(q1), 0], [0, 0, 1]])
+    Ry = np.array([[math.cos(q2), 0, math.sin(q2)], [0, 1, 0], [-math.sin(q2), 0, math.cos(q2)]])
+    o1 = np.array([1.0, 2.0, 0.6])
+    o2 = o1 + Rz @ [0.3, 0, 0]
+    o3 = o2 + Rz @ Ry @ [0.2 + q3, 0, 0]
+    np.testing.assert_allclose(p[1], o1, atol=1e-15)
+    np.testing.assert_allclose(p[2], o2, atol=1e-15)
+    np.testing.assert_allclose(p[3], o3, atol=1e-15)
+    np.testing.assert_allclose(R[2], Rz @ Ry, atol=1e-15)
+    for b in range(4):
+        np.testing.assert_allclose(R[b] @ R[b].T, np.eye(3), atol=1e-14)
+
+
+def test_fk_root_quaternion_convention():
+    """xyzw: a quarter turn about z maps the body x axis onto world y."""
+    s = W.free_sphere()
+    oe = O.OracleEnv(_env([s], []))
+    root = np.array([[0, 0, 1, 0, 0, math.sin(math.pi / 4), math.cos(math.pi / 4)] + [0] * 6])
+    R, p = oe.fk(root, np.zeros((0, 2)))
+    np.testing.assert_allclose(R[0] @ [1, 0, 0], [0, 1, 0], atol=1e-15)
+
+
+# ----------------------------------------------------------------------------- joint-space dynamics
+def _bob_pendulum(l, r, axis=(0, 1, 0)):
+    return W.Actor("p", [W.Link("base", -1, "fixed"),
+                         W.Link("bob", 0, "revolute", axis=axis, shapes=[W.Shape("sphere", (0, 0, -l), radius=r)])],
+                   root_pos=(0, 0, 2))
+
+
+def test_single_pendulum_closed_form():
+    """qdd = -g l sin q / (l^2 + 2 r^2 / 5) for a solid sphere bob on a massless rod."""
+    l, r = 0.7, 0.05
+    oe = O.OracleEnv(_env([_bob_pendulum(l, r)], []))
+    p = _params()
+    root = np.array([0, 0, 2, 0, 0, 0, 1] + [0] * 6, float)[None]
+    for q in (0.3, -1.1, 2.5):
+        M, C, qdd, qdd_aba = oe.dynamics(p, root, np.array([[q, 0.0]]), np.zeros(1))
+        expect = -G * l * math.sin(q) / (l * l + 0.4 * r * r)
+        assert abs(qdd[0] - expect) < 1e-12 * abs(expect)
+        assert abs(qdd_aba[0] - expect) < 1e-12 * abs(expect)
+
+
+def _double_pendulum_lagrangian(q, qd, l1, l2, m1, m2, I1, I2):
+    """Planar double pendulum with sphere bobs (rotation angle positive about +y, hanging at q = 0)."""
+    def Mq(q):
+        c = math.cos(q[1])
+        m11 = (m1 + m2) * l1 ** 2 + m2 * l2 ** 2 + 2 * m2 * l1 * l2 * c + I1 + I2
+        m12 = m2 * l2 ** 2 + m2 * l1 * l2 * c + I2
+        m22 = m2 * l2 ** 2 + I2
+        return np.array([[m11, m12], [m12, m22]])
+
+    def V(q):
+        z1 = -l1 * math.cos(q[0])
+        z2 = z1 - l2 * math.cos(q[0] + q[1])
+        return G * (m1 * z1 + m2 * z2)
+
+    eps = 1e-6
+    dM = []
+    dV = []
+    for k in range(2):
+        e = np.zeros(2)
+        e[k] = eps
+        dM.append((Mq(q + e) - Mq(q - e)) / (2 * eps))
+        dV.append((V(q + e) - V(q - e)) / (2 * eps))
+    Mdot = dM[0] * qd[0] + dM[1] * qd[1]
+    C = Mdot @ qd - 0.5 * np.array([qd @ dM[k] @ qd for k in range(2)]) + np.array(dV)
+    return Mq(q), C
+
+
+def test_double_pendulum_lagrangian():
+    l1, l2, r1, r2 = 0.5, 0.4, 0.06, 0.05
+    a = W.Actor("dp", [W.Link("base", -1, "fixed"),
+                       W.Link("a", 0, "revolute", axis=(0, 1, 0), shapes=[W.Shape("sphere", (0, 0, -l1), radius=r1)]),
+                       W.Link("b", 1, "revolute", anchor=(0, 0, -l1), axis=(0, 1, 0),
+                              shapes=[W.Shape("sphere", (0, 0, -l2), radius=r2)])], root_pos=(0, 0, 3))
+    oe = O.OracleEnv(_env([a], []))
+    m1 = 1000 * 4 / 3 * math.pi * r1 ** 3
+    m2 = 1000 * 4 / 3 * math.pi * r2 ** 3
+    I1, I2 = 0.4 * m1 * r1 ** 2, 0.4 * m2 * r2 ** 2
+    root = np.array([0, 0, 3, 0, 0, 0, 1] + [0] * 6, float)[None]
+    for q, qd in [((0.4, -0.9), (1.3, -2.1)), ((2.0, 1.0), (-0.5, 3.0))]:
+        q, qd = np.array(q), np.array(qd)
+        M, C, qdd, _ = oe.dynamics(_params(), root, np.stack([q, qd], 1), np.zeros(2))
+        Me, Ce = _double_pendulum_lagrangian(q, qd, l1, l2, m1, m2, I1, I2)
+        np.testing.assert_allclose(M, Me, rtol=1e-12, atol=1e-14)
+        np.testing.assert_allclose(C, Ce, rtol=1e-7, atol=1e-8)
+
+
+def _random_state(env, seed, vscale=1.0):
+    rng = np.random.default_rng(seed)
+    root, dof = W.initial_state(env, 1, seed)
+    for ai, a in enumerate(env.actors):
+        q = rng.normal(size=4)
+        root[0, ai, 3:7] = q / np.linalg.norm(q)
+        root[0, ai, 7:13] = rng.normal(size=6) * vscale
+    dof[0, :, 0] = rng.uniform(-1, 1, env.n_dof)
+    dof[0, :, 1] = rng.normal(size=env.n_dof) * vscale
+    return root[0], dof[0]
+
+
+@pytest.mark.parametrize("make", [W.humanoid, W.ant, W.arm_with_gripper])
+def test_crba_rnea_aba_agree(make):
+    env = _env([make()], [])
+    oe = O.OracleEnv(env)
+    rng = np.random.default_rng(3)
+    for seed in range(3):
+        root, dof = _random_state(env, seed)
+        tau = rng.normal(size=oe.n_v) * 10
+        if not env.actors[0].fixed_base:
+            tau[:6] = 0
+        M, C, q1, q2 = oe.dynamics(_params(), root, dof, tau)
+        np.testing.assert_allclose(M, M.T, atol=1e-12)
+        assert np.linalg.eigvalsh(M).min() > 0
+        np.testing.assert_allclose(q1, q2, rtol=1e-10, atol=1e-10 * np.abs(q1).max())
+        np.testing.assert_allclose(M @ q1 + C, tau, atol=1e-9 * (1 + np.abs(tau).max()))
+
+
+# --- Newton-Euler laws of the whole system from finite differences of kinematics only
+def _exp_quat(theta):
+    a = np.linalg.norm(theta)
+    if a < 1e-15:
+        return np.array([*(theta / 2), 1.0])
+    return np.array([*(math.sin(a / 2) * theta / a), math.cos(a / 2)])
+
+
+def _quat_mul(a, b):
+    av, bv = a[:3], b[:3]
+    return np.array([*(a[3] * bv + b[3] * av + np.cross(av, bv)), a[3] * b[3] - av @ bv])
+
+
+def _advance(env, root, dof, dq):
+    """State moved along generalized displacement dq (root: position + world rotation vector)."""
+    root = root.copy()
+    dof = dof.copy()
+    c = 0
+    j = 0
+    for ai, a in enumerate(env.actors):
+        if not a.fixed_base:
+            root[ai, 0:3] += dq[c:c + 3]
+            root[ai, 3:7] = _quat_mul(_exp_quat(dq[c + 3:c + 6]), root[ai, 3:7])
+            c += 6
+        for _ in range(a.n_dof):
+            dof[j, 0] += dq[c]
+            c += 1
+            j += 1
+    return root, dof
+
+
+def _momenta(oe, env, root, dof, qd, m, com, Ic, delta=1e-6):
+    """Linear momentum and angular momentum about the world origin from FK finite differences."""
+    R, p = oe.fk(*_advance(env, root, dof, np.zeros(len(qd))))
+    Rp, pp = oe.fk(*_advance(env, root, dof, delta * qd))
+    Rm, pm = oe.fk(*_advance(env, root, dof, -delta * qd))
+    c = p + np.einsum("bij,bj->bi", R, com)
+    cd = ((pp + np.einsum("bij,bj->bi", Rp, com)) - (pm + np.einsum("bij,bj->bi", Rm, com))) / (2 * delta)
+    P = (m[:, None] * cd).sum(0)
+    L = np.zeros(3)
+    for b in range(len(m)):
+        S = (Rp[b] - Rm[b]) / (2 * delta) @ R[b].T
+        w = np.array([S[2, 1], S[0, 2], S[1, 0]])
+        L += np.cross(c[b], m[b] * cd[b]) + R[b] @ Ic[b] @ R[b].T @ w
+    return P, L, c
+
+
+def _system_velocity(env, root, dof):
+    qd = []
+    j = 0
+    for ai, a in enumerate(env.actors):
+        if not a.fixed_base:
+            qd.extend(root[ai, 7:13])
+        qd.extend(dof[j:j + a.n_dof, 1])
+        j += a.n_dof
+    return np.array(qd)
+
+
+@pytest.mark.parametrize("make,grav", [(W.humanoid, True), (W.humanoid, False), (W.ant, True)])
+def test_momentum_rate_matches_external_forces(make, grav):
+    """d/dt (P, L_O) along the trajectory generated by the oracle's qdd equals the gravity wrench;
+    internal joint torques cancel.  Momenta come from FK finite differences, not the oracle's algebra."""
+    env = _env([make()], [])
+    oe = O.OracleEnv(env)
+    m, com, Ic = oe.mass_props()
+    p = _params(gravity=(0.0, 0.0, -G) if grav else (0.0, 0.0, 0.0))
+    root, dof = _random_state(env, 11, vscale=0.7)
+    qd = _system_velocity(env, root, dof)
+    rng = np.random.default_rng(5)
+    tau = np.zeros(oe.n_v)
+    tau[6:] = rng.normal(size=oe.n_v - 6) * 5
+    _, _, qdd, _ = oe.dynamics(p, root, dof, tau)
+    eps = 1e-4
+    vals = []
+    for s in (+1, -1):
+        r2, d2 = _advance(env, root, dof, s * eps * qd + 0.5 * eps * eps * qdd)
+        qd2 = qd + s * eps * qdd
+        # write velocities back into the state arrays
+        r2[0, 7:13] = qd2[:6]
+        d2[:, 1] = qd2[6:]
+        vals.append(_momenta(oe, env, r2, d2, qd2, m, com, Ic))
+    Pdot = (vals[0][0] - vals[1][0]) / (2 * eps)
+    Ldot = (vals[0][1] - vals[1][1]) / (2 * eps)
+    g = np.array(p.gravity)
+    _, _, c = _momenta(oe, env, root, dof, qd, m, com, Ic)
+    F = m.sum() * g
+    Tq = sum(np.cross(c[b], m[b] * g) for b in range(len(m)))
+    scale = 1.0 + np.abs(m.sum() * 9.81)
+    np.testing.assert_allclose(Pdot, F, atol=2e-5 * scale)
+    np.testing.assert_allclose(Ldot, Tq, atol=2e-5 * scale)
+
+
+def test_energy_rate_equals_actuator_power():
+    """d/dt (T + V) = tau . qd for a free humanoid (T from FK finite differences)."""
+    env = _env([W.humanoid()], [])
+    oe = O.OracleEnv(env)
+    m, com, Ic = oe.mass_props()
+    p = _params()
+    root, dof = _random_state(env, 21, vscale=0.5)
+    qd = _system_velocity(env, root, dof)
+    tau = np.zeros(oe.n_v)
+    tau[6:] = np.random.default_rng(2).normal(size=oe.n_v - 6) * 3
+    _, _, qdd, _ = oe.dynamics(p, root, dof, tau)
+
+    def energy(r, d, v):
+        delta = 1e-6
+        R, pos = oe.fk(r, d)
+        Rp, pp = oe.fk(*_advance(env, r, d, delta * v))
+        Rm, pm = oe.fk(*_advance(env, r, d, -delta * v))
+        T = 0.0
+        V = 0.0
+        for b in range(len(m)):
+            c = pos[b] + R[b] @ com[b]
+            cd = ((pp[b] + Rp[b] @ com[b]) - (pm[b] + Rm[b] @ com[b])) / (2 * delta)
+            S = (Rp[b] - Rm[b]) / (2 * delta) @ R[b].T
+            w = np.array([S[2, 1], S[0, 2], S[1, 0]])
+            T += 0.5 * m[b] * cd @ cd + 0.5 * w @ (R[b] @ Ic[b] @ R[b].T) @ w
+            V += m[b] * G * c[2]
+        return T + V
+
+    eps = 1e-4
+    Es = []
+    for s in (+1, -1):
+        r2, d2 = _advance(env, root, dof, s * eps * qd + 0.5 * eps * eps * qdd)
+        v2 = qd + s * eps * qdd
+        r2[0, 7:13] = v2[:6]
+        d2[:, 1] = v2[6:]
+        Es.append(energy(r2, d2, v2))
+    Edot = (Es[0] - Es[1]) / (2 * eps)
+    assert abs(Edot - tau @ qd) < 1e-4 * (1 + abs(tau @ qd))
+
+
+# ----------------------------------------------------------------------------- integration
+def test_free_fall_discrete_closed_form():
+    """Semi-implicit Euler: z_n = z0 + v0 n h - g h^2 n (n + 1) / 2 exactly; no contact within reach."""
+    env = _env([W.free_sphere(radius=0.1, z=50.0)])
+    oe = O.OracleEnv(env)
+    p = _params()
+    h = p.dt / p.substeps
+    root = np.array([[[0, 0, 50.0, 0, 0, 0, 1, 0, 0, 1.5, 0, 0, 0]]])
+    dof = np.zeros((1, 0, 2))
+    for step in range(1, 11):
+        o = oe.step(p, root, dof, np.zeros((1, 0)))
+        root = o["root"]
+        n = step * p.substeps
+        z = 50.0 + 1.5 * n * h - G * h * h * n * (n + 1) / 2
+        assert abs(root[0, 0, 2] - z) < 1e-12
+        assert abs(root[0, 0, 9] - (1.5 - G * h * n)) < 1e-12
+
+
+def test_torque_free_spin_exact_exponential_map():
+    env = _env([W.free_sphere(radius=0.1, z=50.0)])
+    oe = O.OracleEnv(env)
+    p = _params(gravity=(0.0, 0.0, 0.0))
+    h = p.dt / p.substeps
+    w = np.array([1.0, -2.0, 0.5])
+    q0 = np.array([0.1, 0.2, 0.3, 0.9])
+    q0 /= np.linalg.norm(q0)
+    root = np.array([[[0, 0, 50.0, *q0, 0, 0, 0, *w]]])
+    for step in range(1, 6):
+        root = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))["root"]
+    n = 5 * p.substeps
+    expect = _quat_mul(_exp_quat(n * h * w), q0)
+    np.testing.assert_allclose(root[0, 0, 3:7], expect, atol=1e-13)
+    np.testing.assert_allclose(root[0, 0, 10:13], w, atol=1e-14)
+
+
+def test_asymmetric_free_body_energy_error_scales_with_h():
+    """Torque-free asymmetric box: |L| and E drift at O(h) under semi-implicit Euler."""
+    box = W.free_box(half=(0.3, 0.1, 0.05), pos=(0, 0, 50))
+    env = _env([box], [])
+    oe = O.OracleEnv(env)
+    m, com, Ic = oe.mass_props()
+    errs = []
+    for sub in (4, 8):
+        p = _params(gravity=(0.0, 0.0, 0.0), substeps=sub)
+        root = np.array([[[0, 0, 50, 0, 0, 0, 1, 0, 0, 0, 0.3, 4.0, 0.2]]])
+        R0 = np.eye(3)
+        E0 = 0.5 * root[0, 0, 10:13] @ Ic[0] @ root[0, 0, 10:13]
+        worst = 0.0
+        for _ in range(30):
+            root = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))["root"]
+            R, _ = oe.fk(root[0], np.zeros((0, 2)))
+            w = root[0, 0, 10:13]
+            E = 0.5 * w @ R[0] @ Ic[0] @ R[0].T @ w
+            worst = max(worst, abs(E - E0) / E0)
+        errs.append(worst)
+    assert errs[0] < 0.05
+    assert 1.6 < errs[0] / errs[1] < 2.5
+
+
+# ----------------------------------------------------------------------------- contacts and PGS
+def test_resting_sphere_single_sweep_exact():
+    r = 0.1
+    env = _env([W.free_sphere(radius=r, z=r)])
+    oe = O.OracleEnv(env)
+    m = oe.mass_props()[0][0]
+    p = _params(substeps=1, pgs_iters=1)
+    h = p.dt
+    root = np.array([[[0, 0, r, 0, 0, 0, 1, 0, 0, 0, 0, 0, 0]]])
+    o = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))
+    assert o["row_count"][0, 0] == 3
+    assert o["row_key"][0, 0, 0] == (3 << 24)
+    assert abs(o["row_lambda"][0, 0, 0] - m * G * h) < 1e-14
+    assert abs(o["row_lambda"][0, 0, 1]) < 1e-15 and abs(o["row_lambda"][0, 0, 2]) < 1e-15
+    np.testing.assert_allclose(o["root"][0, 0, 7:13], 0, atol=1e-15)
+    np.testing.assert_allclose(o["contact_force"][0, 0], [0, 0, m * G], rtol=1e-14)
+
+
+def test_sphere_slides_then_rolls_closed_form():
+    """Coulomb friction on a sliding sphere: dv = -mu g h, dw = 5 mu g h / (2 r) per substep until
+    rolling (v = w r, reached at v = 5/7 u)."""
+    r, mu, u = 0.1, 0.4, 2.0
+    env = _env([W.free_sphere(radius=r, z=r)])
+    oe = O.OracleEnv(env)
+    p = _params(mu=mu, substeps=1, pgs_iters=1)
+    h = p.dt
+    root = np.array([[[0, 0, r, 0, 0, 0, 1, u, 0, 0, 0, 0, 0]]])
+    v, w = u, 0.0
+    for k in range(40):
+        o = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))
+        root = o["root"]
+        slip = v - w * r
+        if slip > 3.5 * mu * G * h:
+            v -= mu * G * h
+            w += 2.5 * mu * G * h / r
+            assert abs(root[0, 0, 7] - v) < 1e-12, k
+            assert abs(root[0, 0, 11] - w) < 1e-10, k
+        else:
+            break
+    # eventually rolls at 5/7 u
+    for _ in range(100):
+        root = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))["root"]
+    assert abs(root[0, 0, 7] - 5.0 / 7.0 * u) < 1e-9
+    assert abs(root[0, 0, 7] - root[0, 0, 11] * r) < 1e-9
+
+
+@pytest.mark.parametrize("theta,stick", [(0.3, True), (0.6, False)])
+def test_box_on_incline_sticks_iff_tan_le_mu(theta, stick):
+    mu = 0.5  # atan(0.5) = 0.4636
+    half = 0.05
+    box = W.free_box(half=(half, half, half), pos=(0, 0, half))
+    env = _env([box])
+    oe = O.OracleEnv(env)
+    g = (G * math.sin(theta), 0.0, -G * math.cos(theta))
+    p = _params(mu=mu, gravity=g, pgs_iters=200)
+    root = np.array([[[0, 0, half, 0, 0, 0, 1] + [0] * 6]])
+    T = 30
+    for _ in range(T):
+        root = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))["root"]
+    vx = root[0, 0, 7]
+    if stick:
+        assert abs(vx) < 1e-6
+    else:
+        a = G * (math.sin(theta) - mu * math.cos(theta))
+        assert abs(vx - a * T * p.dt) < 1e-3 * a * T * p.dt
+
+
+def test_pgs_converges_to_brute_force_lcp():
+    """A tilted box touching the plane with two corners: PGS with many sweeps reaches the unique
+    solution of the friction LCP, found here by enumerating every active set."""
+    half = np.array([0.1, 0.05, 0.04])
+    box = W.free_box(half=tuple(half), pos=(0, 0, 0.2))
+    env = _env([box])
+    oe = O.OracleEnv(env)
+    m, _, Ic = oe.mass_props()
+    m, Ic = m[0], Ic[0]
+    ang = 0.3
+    qrot = np.array([math.sin(ang / 2), 0, 0, math.cos(ang / 2)])  # tilt about x: two corners lowest
+    R = oe.fk(np.array([[0, 0, 0, *qrot, 0, 0, 0, 0, 0, 0]]), np.zeros((0, 2)))[0][0]
+    corners = np.array([[sx * half[0], sy * half[1], sz * half[2]] for sz in (-1, 1) for sy in (-1, 1) for sx in (-1, 1)])
+    z0 = -(corners @ R.T)[:, 2].min() - 0.001
+    vel = np.array([0.3, -0.2, -0.5, 0.4, 0.1, -0.3])
+    mu = 0.6
+    p = _params(mu=mu, substeps=1, pgs_iters=20000)
+    h = p.dt
+    root = np.array([[[0, 0, z0, *qrot, *vel]]])
+    o = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))
+    n_rows = o["row_count"][0, 0]
+    keys = o["row_key"][0, 0, :n_rows]
+    lam = o["row_lambda"][0, 0, :n_rows]
+    # rebuild the problem with single-rigid-body algebra
+    Iw = R @ Ic @ R.T
+    Minv = np.zeros((6, 6))
+    Minv[:3, :3] = np.eye(3) / m
+    Minv[3:, 3:] = np.linalg.inv(Iw)
+    vstar = vel + h * np.array([0, 0, -G, 0, 0, 0]) + h * np.concatenate([[0, 0, 0], -np.linalg.solve(Iw, np.cross(vel[3:], Iw @ vel[3:]))])
+    rows, b = [], []
+    for k in keys:
+        kind, slot = k >> 24, k & 0xFF
+        sx, sy, sz = (1 if slot & 1 else -1), (1 if slot & 2 else -1), (1 if slot & 4 else -1)
+        x = np.array([0, 0, z0]) + R @ (half * [sx, sy, sz])
+        d = {3: [0, 0, 1], 4: [1, 0, 0], 5: [0, 1, 0]}[kind]
+        r = x - [0, 0, z0]
+        rows.append(np.concatenate([d, np.cross(r, d)]))
+        b.append((x[2] / h if x[2] >= 0 else p.baumgarte * x[2] / h) if kind == 3 else 0.0)
+    J = np.array(rows)
+    A = J @ Minv @ J.T
+    c = J @ vstar + np.array(b)
+    n = len(keys)
+    normal_of = [i if (keys[i] >> 24) == 3 else max(j for j in range(i) if (keys[j] >> 24) == 3) for i in range(n)]
+    import itertools
+    sols = []
+    for states in itertools.product(range(3), repeat=n):
+        # normal rows: 0 -> lambda = 0, 1 -> residual = 0; tangent rows: 1 -> residual 0, 0/2 -> at -/+ bound
+        if any((keys[i] >> 24) == 3 and states[i] == 2 for i in range(n)):
+            continue
+        Msys = np.zeros((n, n))
+        rhs = np.zeros(n)
+        for i in range(n):
+            kind = keys[i] >> 24
+            if states[i] == 1:
+                Msys[i] = A[i]
+                rhs[i] = -c[i]
+            elif kind == 3:
+                Msys[i, i] = 1.0
+            else:
+                Msys[i, i] = 1.0
+                Msys[i, normal_of[i]] -= (mu if states[i] == 2 else -mu)
+        try:
+            lam_s = np.linalg.solve(Msys, rhs)
+        except np.linalg.LinAlgError:
+            continue
+        res = A @ lam_s + c
+        ok = True
+        for i in range(n):
+            kind = keys[i] >> 24
+            if kind == 3:
+                ok &= lam_s[i] >= -1e-12 and res[i] >= -1e-9 and (states[i] == 1 or res[i] >= -1e-12)
+            else:
+                bound = mu * lam_s[normal_of[i]]
+                if states[i] == 1:
+                    ok &= abs(lam_s[i]) <= bound + 1e-12
+                elif states[i] == 2:
+                    ok &= res[i] <= 1e-12
+                else:
+                    ok &= res[i] >= -1e-12
+        if ok:
+            sols.append(lam_s)
+    assert sols, "no LCP solution found"
+    assert n >= 6
+    # friction sharing between corners is not unique; what is unique is the normal impulses and the
+    # resulting velocity, and the PGS limit must satisfy every complementarity condition itself
+    normals = [i for i in range(n) if (keys[i] >> 24) == 3]
+    for s_ in sols:
+        np.testing.assert_allclose(lam[normals], s_[normals], atol=1e-9)
+        np.testing.assert_allclose(o["root"][0, 0, 7:13], vstar + Minv @ J.T @ s_, atol=1e-9)
+    res = A @ lam + c
+    for i in range(n):
+        if (keys[i] >> 24) == 3:
+            assert lam[i] >= 0 and res[i] >= -1e-9 and abs(lam[i] * res[i]) < 1e-9
+        else:
+            bound = mu * lam[normal_of[i]]
+            assert abs(lam[i]) <= bound + 1e-12
+            if abs(lam[i]) < bound - 1e-9:
+                assert abs(res[i]) < 1e-9
+            else:
+                assert res[i] * lam[i] <= 1e-12
+
+
+def test_joint_limit_speculative_row_is_exact():
+    """A pendulum swinging into its lower limit stops exactly on it (single speculative row)."""
+    a = _bob_pendulum(0.5, 0.05)
+    a.links[1].lower, a.links[1].upper = -0.2, 3.0
+    env = _env([a], [])
+    oe = O.OracleEnv(env)
+    p = _params(substeps=1, pgs_iters=1, gravity=(0, 0, 0))
+    root = np.array([[[0, 0, 2, 0, 0, 0, 1] + [0] * 6]])
+    dof = np.array([[[-0.15, -12.0]]])
+    o = oe.step(p, root, dof, np.zeros((1, 1)))
+    assert o["row_count"][0, 0] == 1 and o["row_key"][0, 0, 0] == (1 << 24)
+    assert abs(o["dof"][0, 0, 0] - (-0.2)) < 1e-14
+
+
+def test_implicit_pd_linear_recurrence():
+    """(I + h kd + h^2 kp) qdd = kp (q* - q - h qd) - kd qd: exact linear recurrence (no gravity)."""
+    l, r, kp, kd = 0.3, 0.04, 50.0, 2.0
+    a = _bob_pendulum(l, r)
+    a.links[1].kp, a.links[1].kd = kp, kd
+    env = _env([a], [])
+    oe = O.OracleEnv(env)
+    mb = 1000 * 4 / 3 * math.pi * r ** 3
+    I = mb * (l * l + 0.4 * r * r)
+    p = _params(gravity=(0, 0, 0))
+    h = p.dt / p.substeps
+    root = np.array([[[0, 0, 2, 0, 0, 0, 1] + [0] * 6]])
+    dof = np.array([[[0.0, 0.0]]])
+    q, qd, qt = 0.0, 0.0, 0.8
+    for step in range(20):
+        o = oe.step(p, root, dof, np.zeros((1, 1)), pos_tgt=np.array([[qt]]))
+        dof = o["dof"]
+        for _ in range(p.substeps):
+            qdd = (kp * (qt - q - h * qd) - kd * qd) / (I + h * kd + h * h * kp)
+            qd += h * qdd
+            q += h * qd
+        assert abs(dof[0, 0, 0] - q) < 1e-12 and abs(dof[0, 0, 1] - qd) < 1e-11
+
+
+# ----------------------------------------------------------------------------- narrow phase
+def test_plane_slots_closed_form():
+    env = _env([W.humanoid()])
+    oe = O.OracleEnv(env)
+    root, dof = _random_state(env, 4)
+    phi, n, x, ba, bb = oe.slots(root, dof)
+    R, p = oe.fk(root, dof)
+    k = 0
+    for pr in env.pairs:
+        s = env.actors[pr.a_actor].links[pr.a_link].shapes[pr.a_shape]
+        for c in (s.p0, s.p1):
+            centre = p[pr.a_link] + R[pr.a_link] @ np.array(c)
+            assert abs(phi[k] - (centre[2] - s.radius)) < 1e-14
+            np.testing.assert_allclose(x[k], centre - [0, 0, s.radius], atol=1e-14)
+            np.testing.assert_allclose(n[k], [0, 0, 1])
+            assert ba[k] == pr.a_link and bb[k] == -1
+            k += 1
+    assert k == len(phi) == 26
+
+
+def _box_surface_points(half, n=120):
+    pts = []
+    g = np.linspace(-1, 1, n)
+    U, V = np.meshgrid(g, g, indexing="ij")
+    for ax in range(3):
+        o = [a for a in range(3) if a != ax]
+        for s in (-1, 1):
+            P = np.zeros((n * n, 3))
+            P[:, ax] = s * half[ax]
+            P[:, o[0]] = U.ravel() * half[o[0]]
+            P[:, o[1]] = V.ravel() * half[o[1]]
+            pts.append(P)
+    return np.concatenate(pts)
+
+
+def test_capsule_box_slots_brute_force():
+    """Sphere-cap and midpoint slots against a rotated box: signed distance from dense surface sampling."""
+    arm = W.Actor("c", [W.Link("base", -1, "fixed"),
+                        W.Link("l", 0, "revolute", axis=(0, 0, 1), shapes=[W._capsule((0, 0, 0), (0.3, 0.0, 0.0), 0.03)])],
+                  root_pos=(0, 0, 0))
+    box = W.free_box(half=(0.05, 0.08, 0.04), pos=(0.15, 0.02, 0.05))
+    env = W.EnvSpec("cb", [arm, box], [W.Pair(0, 1, 0, 1, 0, 0)])
+    oe = O.OracleEnv(env)
+    half = np.array([0.05, 0.08, 0.04])
+    surf = _box_surface_points(half)
+    rng = np.random.default_rng(7)
+    for trial in range(6):
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        root = np.array([[0, 0, 0, 0, 0, 0, 1] + [0] * 6,
+                         [0.15 + rng.uniform(-0.05, 0.05), 0.02 + rng.uniform(-0.05, 0.05), 0.05, *q, 0, 0, 0, 0, 0, 0]])
+        dof = np.array([[rng.uniform(-0.5, 0.5), 0.0]])
+        phi, n, x, ba, bb = oe.slots(root, dof)
+        R, p = oe.fk(root, dof)
+        Rb, cb = R[2], p[2]
+        for k, loc in enumerate([(0, 0, 0), (0.3, 0, 0), (0.15, 0, 0)]):
+            centre = p[1] + R[1] @ np.array(loc)
+            xl = Rb.T @ (centre - cb)
+            d = np.linalg.norm(surf - xl, axis=1).min()
+            inside = np.all(np.abs(xl) <= half)
+            sd = -d if inside else d
+            assert abs(phi[k] - (sd - 0.03)) < 2e-3, (trial, k)
+            # normal points from the box towards the sphere centre and the point lies on the cap
+            np.testing.assert_allclose(np.linalg.norm(n[k]), 1.0, atol=1e-12)
+            np.testing.assert_allclose(x[k], centre - 0.03 * n[k], atol=1e-12)
+            if not inside:
+                assert n[k] @ (centre - (cb + Rb @ np.clip(xl, -half, half))) > 0
