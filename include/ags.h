@@ -1,0 +1,174 @@
+/*
+ * ags — batched articulated-body physics step for AMD MI355X (gfx950).
+ *
+ * C ABI of the hot path of the simulator described in "Isaac Gym: High Performance GPU-Based
+ * Physics Simulation For Robot Learning" (arXiv 2108.10470): thousands of independent robot
+ * environments, each a set of reduced-coordinate articulations (Section 3), advanced together on
+ * one GPU with the physics state kept in flat device tensors (Section 2.3, Tables 1-2).
+ *
+ * Conventions
+ *  - All tensors are float32, row-major, on the device, owned by the caller (e.g. PyTorch): the
+ *    library reads and writes them in place ("zero-copy" tensor wrapping, Section 2.3.1).
+ *  - Spatial quantities use z-up, ground plane z = 0, quaternions xyzw (actor root state columns
+ *    0:3 position, 3:7 quaternion, 7:10 linear velocity, 10:13 angular velocity; Section 2.3.2).
+ *    The position and linear velocity of a free root are those of its centre of mass: a free
+ *    root link's frame must sit at its centre of mass (ags_model_create rejects it otherwise).
+ *  - DOF units are radians (revolute) and metres (prismatic) (Section 2.3.2).
+ *  - Environments are laid out env-major: env e's actors, DOFs and bodies are contiguous rows of
+ *    the global tensors, in the order of its model's actors and their links.
+ *  - Every call returns 0 on success or a negative AGS_E_* code; ags_last_error() returns a
+ *    thread-local message for the last failure.  Calls that enqueue GPU work are asynchronous on
+ *    the stream passed to them and never synchronise the host.
+ *  - A sim is not thread-safe; different sims are independent.
+ */
+#ifndef AGS_H
+#define AGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+enum {
+  AGS_OK = 0,
+  AGS_E_ARG = -1,      /* bad argument (null pointer, out-of-range index, unsupported size) */
+  AGS_E_MODEL = -2,    /* inconsistent model description */
+  AGS_E_HIP = -3,      /* HIP runtime error (message has the HIP error string) */
+  AGS_E_NOMEM = -4,    /* device allocation failed */
+  AGS_E_UNBOUND = -5   /* a tensor the call needs is not bound */
+};
+const char* ags_last_error(void);
+
+/* ---------------------------------------------------------------- model description
+ * An actor is an articulation: a tree of links with parent index < child index (Section 3;
+ * "actor", "rigid bodies" and "DOF states", Section 2.2).  Joint types: the root link has a free
+ * (floating-base) or fixed joint; every other link has a 1-DOF revolute or prismatic joint
+ * (Section 2.2: fixed 0 DOF, revolute and prismatic 1 DOF; a spherical joint is expressed as a
+ * chain of revolutes through massless links).  A rigid body is a one-link articulation. */
+enum { AGS_JOINT_FREE = 0, AGS_JOINT_FIXED = 1, AGS_JOINT_REVOLUTE = 2, AGS_JOINT_PRISMATIC = 3 };
+enum { AGS_SHAPE_SPHERE = 0, AGS_SHAPE_CAPSULE = 1, AGS_SHAPE_BOX = 2 };
+
+typedef struct {
+  int32_t parent;      /* actor-local parent link, -1 for the root */
+  int32_t joint;       /* AGS_JOINT_* */
+  float anchor[3];     /* joint origin in the parent link frame (link frames coincide with the parent's at q = 0) */
+  float axis[3];       /* joint axis (normalised by the library) */
+  float lower, upper;  /* DOF limits (+-INFINITY: none), enforced as unilateral constraint rows */
+  float kp, kd;        /* PD drive stiffness and damping (Table 3 "drive stiffness/damping"), 0: no drive */
+  float armature;      /* joint armature (Table 3) */
+  float mass;          /* > 0: link mass (shapes then only give its distribution); 0: from shape densities */
+} ags_link_desc;
+
+typedef struct {
+  int32_t link;        /* actor-local link */
+  int32_t kind;        /* AGS_SHAPE_* */
+  float p0[3];         /* sphere / box centre, or first capsule cap centre, in the link frame */
+  float p1[3];         /* second capsule cap centre */
+  float radius;        /* sphere / capsule radius */
+  float half[3];       /* box half extents (box axes = link frame axes) */
+  float density;       /* kg / m^3 */
+} ags_shape_desc;
+
+typedef struct {
+  int32_t n_links, n_shapes;
+  const ags_link_desc* links;
+  const ags_shape_desc* shapes;
+} ags_actor_desc;
+
+/* Collision pair: shape a_shape of actor a_actor against the ground plane (b_actor = -1) or
+ * against box b_shape of actor b_actor (a sphere or capsule vs a box of another actor).
+ * Pairs never cross environments (Section 2.1: environments do not interact). */
+typedef struct {
+  int32_t a_actor, a_shape, b_actor, b_shape;
+} ags_pair_desc;
+
+typedef struct ags_model ags_model;
+
+/* Compile one environment template (its actors and collision pairs).  Host-only; copies
+ * everything it needs.  Limits: at most 64 links, 64 generalized velocities and 256 contact
+ * slots per environment. */
+int ags_model_create(const ags_actor_desc* actors, int32_t n_actors, const ags_pair_desc* pairs,
+                     int32_t n_pairs, ags_model** out);
+void ags_model_destroy(ags_model* model);
+
+typedef struct {
+  int32_t n_actors, n_links, n_dof, n_v, n_slots, max_rows;
+} ags_model_info;
+int ags_model_get_info(const ags_model* model, ags_model_info* out);
+
+/* Per-link mass, COM (link frame) and inertia about the COM (link frame, 3x3 row-major), host
+ * arrays of n_links, 3 n_links and 9 n_links floats. */
+int ags_model_mass_props(const ags_model* model, float* mass, float* com, float* inertia);
+
+/* ---------------------------------------------------------------- simulation
+ * Parameters of Table 3 that the step uses.  One env-step advances dt with `substeps` substeps of
+ * h = dt / substeps, the controls held over the step (Table 4: sim dt 1/120 s, control dt 1/60 s).
+ * Contacts and limits are unilateral constraint rows solved by pgs_iters sweeps of projected
+ * Gauss-Seidel ("position iterations"), with Coulomb friction mu (Table 3) and a Baumgarte
+ * factor for penetration ("max bias coefficient"). */
+typedef struct {
+  float dt;
+  int32_t substeps;
+  float gravity[3];
+  int32_t pgs_iters;
+  float mu;
+  float baumgarte;
+  float contact_margin;     /* a contact row exists when phi + h min(0, v_n) < contact_margin */
+  float limit_margin_rev;   /* same test for revolute limits (rad) */
+  float limit_margin_pri;   /* and prismatic limits (m) */
+  int32_t compute_fp64;     /* 0: compute in FP32; 1: compute in FP64 (tensors stay FP32) */
+} ags_sim_params;
+
+typedef struct ags_sim ags_sim;
+
+/* Create a batch of n_envs environments; env_model[e] (host array) indexes models[] and selects
+ * the template of env e (heterogeneous batches allowed).  Allocates the device-side model tables
+ * and scratch; tensors are bound separately. */
+int ags_sim_create(const ags_model* const* models, int32_t n_models, const int32_t* env_model, int32_t n_envs,
+                   const ags_sim_params* params, ags_sim** out);
+void ags_sim_destroy(ags_sim* sim);
+
+/* Tensor shapes (rows, cols) follow Tables 1-2:
+ *   AGS_ROOT_STATE         (N_A, 13)  get/set  actor root states
+ *   AGS_DOF_STATE          (N_D, 2)   get/set  DOF position, velocity
+ *   AGS_DOF_ACTUATION      (N_D, 1)   control  DOF actuation forces (torques or forces)
+ *   AGS_DOF_POS_TARGET     (N_D, 1)   control  PD position targets
+ *   AGS_DOF_VEL_TARGET     (N_D, 1)   control  PD velocity targets
+ *   AGS_NET_CONTACT_FORCE  (N_B, 3)   get      net contact force on each rigid body (world frame)
+ *   AGS_DOF_FORCE          (N_D, 1)   get      force applied at each DOF (actuation + drive), step average
+ *   AGS_DEBUG_QDD_FREE     (E, substeps * max n_v)       unconstrained joint accelerations per substep
+ *   AGS_DEBUG_ROW_COUNT    (E, substeps)  int32          constraint rows per substep
+ *   AGS_DEBUG_ROW_KEY      (E, substeps * max rows) int32  row keys (kind << 24 | a << 8 | b)
+ *   AGS_DEBUG_ROW_LAMBDA   (E, substeps * max rows)      row impulses after the last sweep
+ * Outputs and debug tensors are written only when bound.  N_A, N_D and N_B count actors, DOFs
+ * and links of all environments. */
+enum {
+  AGS_ROOT_STATE = 0, AGS_DOF_STATE, AGS_DOF_ACTUATION, AGS_DOF_POS_TARGET, AGS_DOF_VEL_TARGET,
+  AGS_NET_CONTACT_FORCE, AGS_DOF_FORCE, AGS_DEBUG_QDD_FREE, AGS_DEBUG_ROW_COUNT, AGS_DEBUG_ROW_KEY,
+  AGS_DEBUG_ROW_LAMBDA, AGS_NUM_TENSORS
+};
+int ags_sim_tensor_shape(const ags_sim* sim, int32_t which, int64_t* rows, int64_t* cols);
+/* Bind a device pointer (NULL unbinds).  The memory must hold rows x cols elements and stay valid
+ * while steps that use it are in flight. */
+int ags_sim_bind(ags_sim* sim, int32_t which, void* device_ptr);
+
+/* One env-step of every environment, enqueued on hip_stream (a hipStream_t; NULL = default).
+ * Reads and rewrites the bound root and DOF state tensors in place; needs ROOT_STATE, DOF_STATE
+ * and DOF_ACTUATION bound (the PD target tensors are read only when bound; unbound targets are 0). */
+int ags_sim_step(ags_sim* sim, void* hip_stream);
+
+/* Copy rows of src (same shape as the bound tensor) into the bound root / DOF state tensor for the
+ * actors listed in actor_idx (device int32 array of n global actor indices; NULL = all actors).
+ * Setting a root teleports the actor without changing its DOF poses; setting DOFs leaves roots
+ * unchanged (Section 2.3.2). */
+int ags_sim_set_root_state_indexed(ags_sim* sim, const float* src, const int32_t* actor_idx, int32_t n,
+                                   void* hip_stream);
+int ags_sim_set_dof_state_indexed(ags_sim* sim, const float* src, const int32_t* actor_idx, int32_t n,
+                                  void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

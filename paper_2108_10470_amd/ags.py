@@ -1,0 +1,225 @@
+"""Python binding of libags (ctypes): argument marshalling only.
+
+Every step of the physics runs in the HIP kernels of libags.so; PyTorch supplies device memory and
+streams.  The library must be built (``python -m paper_2108_10470_amd.build``); importing this
+module fails loudly when it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libags.so")
+
+JOINT = {"free": 0, "fixed": 1, "revolute": 2, "prismatic": 3}
+SHAPE = {"sphere": 0, "capsule": 1, "box": 2}
+
+ROOT_STATE, DOF_STATE, DOF_ACTUATION, DOF_POS_TARGET, DOF_VEL_TARGET, NET_CONTACT_FORCE, DOF_FORCE, \
+    DEBUG_QDD_FREE, DEBUG_ROW_COUNT, DEBUG_ROW_KEY, DEBUG_ROW_LAMBDA, NUM_TENSORS = range(12)
+
+
+class LinkDesc(ctypes.Structure):
+    _fields_ = [("parent", ctypes.c_int32), ("joint", ctypes.c_int32), ("anchor", ctypes.c_float * 3),
+                ("axis", ctypes.c_float * 3), ("lower", ctypes.c_float), ("upper", ctypes.c_float),
+                ("kp", ctypes.c_float), ("kd", ctypes.c_float), ("armature", ctypes.c_float), ("mass", ctypes.c_float)]
+
+
+class ShapeDesc(ctypes.Structure):
+    _fields_ = [("link", ctypes.c_int32), ("kind", ctypes.c_int32), ("p0", ctypes.c_float * 3),
+                ("p1", ctypes.c_float * 3), ("radius", ctypes.c_float), ("half", ctypes.c_float * 3),
+                ("density", ctypes.c_float)]
+
+
+class ActorDesc(ctypes.Structure):
+    _fields_ = [("n_links", ctypes.c_int32), ("n_shapes", ctypes.c_int32), ("links", ctypes.POINTER(LinkDesc)),
+                ("shapes", ctypes.POINTER(ShapeDesc))]
+
+
+class PairDesc(ctypes.Structure):
+    _fields_ = [("a_actor", ctypes.c_int32), ("a_shape", ctypes.c_int32), ("b_actor", ctypes.c_int32),
+                ("b_shape", ctypes.c_int32)]
+
+
+class ModelInfo(ctypes.Structure):
+    _fields_ = [("n_actors", ctypes.c_int32), ("n_links", ctypes.c_int32), ("n_dof", ctypes.c_int32),
+                ("n_v", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("max_rows", ctypes.c_int32)]
+
+
+class SimParams(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_float), ("substeps", ctypes.c_int32), ("gravity", ctypes.c_float * 3),
+                ("pgs_iters", ctypes.c_int32), ("mu", ctypes.c_float), ("baumgarte", ctypes.c_float),
+                ("contact_margin", ctypes.c_float), ("limit_margin_rev", ctypes.c_float),
+                ("limit_margin_pri", ctypes.c_float), ("compute_fp64", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libags; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libags.so not built ({LIB_PATH}); run python -m paper_2108_10470_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+        L.ags_last_error.restype = ctypes.c_char_p
+        L.ags_model_create.argtypes = [ctypes.POINTER(ActorDesc), i32, ctypes.POINTER(PairDesc), i32, ctypes.POINTER(vp)]
+        L.ags_model_destroy.argtypes = [vp]
+        L.ags_model_get_info.argtypes = [vp, ctypes.POINTER(ModelInfo)]
+        L.ags_model_mass_props.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                           ctypes.POINTER(ctypes.c_float)]
+        L.ags_sim_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_int32), i32,
+                                     ctypes.POINTER(SimParams), ctypes.POINTER(vp)]
+        L.ags_sim_destroy.argtypes = [vp]
+        L.ags_sim_tensor_shape.argtypes = [vp, i32, i64p, i64p]
+        L.ags_sim_bind.argtypes = [vp, i32, vp]
+        L.ags_sim_step.argtypes = [vp, vp]
+        L.ags_sim_set_root_state_indexed.argtypes = [vp, vp, vp, i32, vp]
+        L.ags_sim_set_dof_state_indexed.argtypes = [vp, vp, vp, i32, vp]
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["ags_last_error", "ags_model_create", "ags_model_destroy", "ags_model_get_info", "ags_model_mass_props",
+            "ags_sim_create", "ags_sim_destroy", "ags_sim_tensor_shape", "ags_sim_bind", "ags_sim_step",
+            "ags_sim_set_root_state_indexed", "ags_sim_set_dof_state_indexed"]
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"{what} failed ({rc}): {lib().ags_last_error().decode()}")
+
+
+def _f3(v):
+    return (ctypes.c_float * 3)(*[float(x) for x in v])
+
+
+class Model:
+    """One compiled environment template (actors + collision pairs) from a workloads.EnvSpec."""
+
+    def __init__(self, env):
+        self.spec = env
+        keep = []
+        actors = (ActorDesc * len(env.actors))()
+        shape_index = {}
+        for ai, a in enumerate(env.actors):
+            links = (LinkDesc * len(a.links))()
+            shapes = []
+            for li, l in enumerate(a.links):
+                links[li] = LinkDesc(l.parent, JOINT[l.joint], _f3(l.anchor), _f3(l.axis), l.lower, l.upper, l.kp, l.kd,
+                                     l.armature, l.mass)
+                for si, s in enumerate(l.shapes):
+                    shape_index[(ai, li, si)] = len(shapes)
+                    shapes.append(ShapeDesc(li, SHAPE[s.kind], _f3(s.p0), _f3(s.p1), s.radius, _f3(s.half), s.density))
+            sarr = (ShapeDesc * max(1, len(shapes)))(*shapes)
+            keep += [links, sarr]
+            actors[ai] = ActorDesc(len(a.links), len(shapes), links, sarr)
+        pairs = (PairDesc * max(1, len(env.pairs)))()
+        for k, p in enumerate(env.pairs):
+            pairs[k] = PairDesc(p.a_actor, shape_index[(p.a_actor, p.a_link, p.a_shape)], p.b_actor,
+                                shape_index[(p.b_actor, p.b_link, p.b_shape)] if p.b_actor >= 0 else -1)
+        h = ctypes.c_void_p()
+        _check(lib().ags_model_create(actors, len(env.actors), pairs, len(env.pairs), ctypes.byref(h)), "ags_model_create")
+        self.h = h
+        info = ModelInfo()
+        _check(lib().ags_model_get_info(h, ctypes.byref(info)), "ags_model_get_info")
+        self.info = info
+
+    def mass_props(self):
+        n = self.info.n_links
+        m = (ctypes.c_float * n)()
+        c = (ctypes.c_float * (3 * n))()
+        I = (ctypes.c_float * (9 * n))()
+        _check(lib().ags_model_mass_props(self.h, m, c, I), "ags_model_mass_props")
+        import numpy as np
+        return (np.array(m[:]), np.array(c[:]).reshape(n, 3), np.array(I[:]).reshape(n, 3, 3))
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ags_model_destroy(self.h)
+            self.h = None
+
+
+def sim_params(p, fp64: bool = False) -> SimParams:
+    return SimParams(p.dt, p.substeps, _f3(p.gravity), p.pgs_iters, p.mu, p.baumgarte, p.contact_margin,
+                     p.limit_margin_rev, p.limit_margin_pri, 1 if fp64 else 0)
+
+
+class Sim:
+    """A batch of environments with its state and control tensors allocated by torch on `device`."""
+
+    def __init__(self, models: Sequence[Model], env_model: Sequence[int], params, device="cuda:0",
+                 debug: bool = False, pd: bool = False, fp64: bool = False):
+        self.models = list(models)
+        self.params = params
+        self.device = torch.device(device)
+        self.n_envs = len(env_model)
+        handles = (ctypes.c_void_p * len(self.models))(*[m.h for m in self.models])
+        ids = (ctypes.c_int32 * self.n_envs)(*[int(x) for x in env_model])
+        h = ctypes.c_void_p()
+        self._p = sim_params(params, fp64)
+        _check(lib().ags_sim_create(handles, len(self.models), ids, self.n_envs, ctypes.byref(self._p), ctypes.byref(h)),
+               "ags_sim_create")
+        self.h = h
+        self.tensors: Dict[int, torch.Tensor] = {}
+        shapes = {}
+        for w in range(NUM_TENSORS):
+            r, c = ctypes.c_int64(), ctypes.c_int64()
+            _check(lib().ags_sim_tensor_shape(h, w, ctypes.byref(r), ctypes.byref(c)), "ags_sim_tensor_shape")
+            shapes[w] = (r.value, c.value)
+        self.shapes = shapes
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.root_state = self._alloc(ROOT_STATE, torch.zeros(shapes[ROOT_STATE], **f32))
+        self.dof_state = self._alloc(DOF_STATE, torch.zeros(shapes[DOF_STATE], **f32))
+        self.actuation = self._alloc(DOF_ACTUATION, torch.zeros(shapes[DOF_ACTUATION][0], **f32))
+        self.contact_force = self._alloc(NET_CONTACT_FORCE, torch.zeros(shapes[NET_CONTACT_FORCE], **f32))
+        self.dof_force = self._alloc(DOF_FORCE, torch.zeros(shapes[DOF_FORCE][0], **f32))
+        if pd:
+            self.pos_target = self._alloc(DOF_POS_TARGET, torch.zeros(shapes[DOF_POS_TARGET][0], **f32))
+            self.vel_target = self._alloc(DOF_VEL_TARGET, torch.zeros(shapes[DOF_VEL_TARGET][0], **f32))
+        if debug:
+            self.dbg_qdd = self._alloc(DEBUG_QDD_FREE, torch.zeros(shapes[DEBUG_QDD_FREE], **f32))
+            self.dbg_rc = self._alloc(DEBUG_ROW_COUNT, torch.zeros(shapes[DEBUG_ROW_COUNT], dtype=torch.int32, device=self.device))
+            self.dbg_key = self._alloc(DEBUG_ROW_KEY, torch.full(shapes[DEBUG_ROW_KEY], -1, dtype=torch.int32, device=self.device))
+            self.dbg_lam = self._alloc(DEBUG_ROW_LAMBDA, torch.zeros(shapes[DEBUG_ROW_LAMBDA], **f32))
+
+    def _alloc(self, which: int, t: torch.Tensor) -> torch.Tensor:
+        self.bind(which, t)
+        return t
+
+    def bind(self, which: int, t: Optional[torch.Tensor]):
+        if t is not None:
+            assert t.is_contiguous() and t.device == self.device
+        self.tensors[which] = t
+        _check(lib().ags_sim_bind(self.h, which, ctypes.c_void_p(t.data_ptr() if t is not None else 0)), "ags_sim_bind")
+
+    def step(self, stream: Optional[torch.cuda.Stream] = None):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(lib().ags_sim_step(self.h, ctypes.c_void_p(s.cuda_stream)), "ags_sim_step")
+
+    def set_root_state_indexed(self, src: torch.Tensor, actor_idx: Optional[torch.Tensor] = None):
+        s = torch.cuda.current_stream(self.device)
+        n = 0 if actor_idx is None else actor_idx.numel()
+        if actor_idx is None:
+            n = self.shapes[ROOT_STATE][0]
+        _check(lib().ags_sim_set_root_state_indexed(self.h, ctypes.c_void_p(src.data_ptr()),
+                                                    ctypes.c_void_p(actor_idx.data_ptr() if actor_idx is not None else 0),
+                                                    n, ctypes.c_void_p(s.cuda_stream)), "ags_sim_set_root_state_indexed")
+
+    def set_dof_state_indexed(self, src: torch.Tensor, actor_idx: Optional[torch.Tensor] = None):
+        s = torch.cuda.current_stream(self.device)
+        n = self.shapes[ROOT_STATE][0] if actor_idx is None else actor_idx.numel()
+        _check(lib().ags_sim_set_dof_state_indexed(self.h, ctypes.c_void_p(src.data_ptr()),
+                                                   ctypes.c_void_p(actor_idx.data_ptr() if actor_idx is not None else 0),
+                                                   n, ctypes.c_void_p(s.cuda_stream)), "ags_sim_set_dof_state_indexed")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.ags_sim_destroy(self.h)
+            self.h = None

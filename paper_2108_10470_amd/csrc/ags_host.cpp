@@ -1,0 +1,652 @@
+// Host side of libags: model compilation, device tables, tensor binding and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ags.h"
+#include "ags_internal.h"
+
+using namespace ags;
+
+namespace {
+thread_local std::string g_err;
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? AGS_E_NOMEM : AGS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- mass properties (closed forms)
+struct Mass {
+  double m = 0, c[3] = {0, 0, 0}, I[9] = {0};  // I about the COM, link frame
+};
+
+void add_outer(double* I, const double* a, const double* b, double s) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) I[3 * i + j] += s * a[i] * b[j];
+}
+
+Mass shape_mass(const ags_shape_desc& s) {
+  const double pi = 3.14159265358979323846;
+  Mass r;
+  double rho = s.density;
+  if (s.kind == AGS_SHAPE_SPHERE) {
+    double rad = s.radius;
+    r.m = rho * 4.0 / 3.0 * pi * rad * rad * rad;
+    for (int k = 0; k < 3; ++k) r.c[k] = s.p0[k];
+    for (int k = 0; k < 3; ++k) r.I[4 * k] = 0.4 * r.m * rad * rad;
+  } else if (s.kind == AGS_SHAPE_CAPSULE) {
+    double d[3] = {double(s.p1[0]) - s.p0[0], double(s.p1[1]) - s.p0[1], double(s.p1[2]) - s.p0[2]};
+    double len = std::sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]), rad = s.radius;
+    double m_cyl = rho * pi * rad * rad * len;
+    double m_caps = rho * 4.0 / 3.0 * pi * rad * rad * rad;
+    r.m = m_cyl + m_caps;
+    for (int k = 0; k < 3; ++k) r.c[k] = 0.5 * (double(s.p0[k]) + s.p1[k]);
+    // axial: cylinder m r^2 / 2, caps (a full sphere) 2/5 m r^2; transverse: cylinder m (r^2/4 + L^2/12),
+    // each cap about its own COM (3r/8 from its base) 83/320 m r^2, moved out to L/2 + 3r/8
+    double ax = 0.5 * m_cyl * rad * rad + 0.4 * m_caps * rad * rad;
+    double arm = 0.5 * len + 0.375 * rad;
+    double tr = m_cyl * (rad * rad / 4.0 + len * len / 12.0) + m_caps * (83.0 / 320.0 * rad * rad + arm * arm);
+    double u[3] = {0, 0, 1};
+    if (len > 0)
+      for (int k = 0; k < 3; ++k) u[k] = d[k] / len;
+    for (int k = 0; k < 3; ++k) r.I[4 * k] = tr;
+    add_outer(r.I, u, u, ax - tr);
+  } else {
+    double a = s.half[0], b = s.half[1], c = s.half[2];
+    r.m = rho * 8.0 * a * b * c;
+    for (int k = 0; k < 3; ++k) r.c[k] = s.p0[k];
+    r.I[0] = r.m / 3.0 * (b * b + c * c);
+    r.I[4] = r.m / 3.0 * (a * a + c * c);
+    r.I[8] = r.m / 3.0 * (a * a + b * b);
+  }
+  return r;
+}
+
+Mass link_mass(const std::vector<const ags_shape_desc*>& shapes, double given) {
+  Mass tot;
+  std::vector<Mass> parts;
+  for (auto* s : shapes) {
+    parts.push_back(shape_mass(*s));
+    tot.m += parts.back().m;
+    for (int k = 0; k < 3; ++k) tot.c[k] += parts.back().m * parts.back().c[k];
+  }
+  if (tot.m > 0)
+    for (int k = 0; k < 3; ++k) tot.c[k] /= tot.m;
+  for (const Mass& p : parts) {
+    double d[3] = {p.c[0] - tot.c[0], p.c[1] - tot.c[1], p.c[2] - tot.c[2]};
+    double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    for (int k = 0; k < 9; ++k) tot.I[k] += p.I[k];
+    for (int k = 0; k < 3; ++k) tot.I[4 * k] += p.m * dd;
+    add_outer(tot.I, d, d, -p.m);
+  }
+  if (given > 0 && tot.m > 0) {
+    double sc = given / tot.m;
+    tot.m = given;
+    for (int k = 0; k < 9; ++k) tot.I[k] *= sc;
+  }
+  return tot;
+}
+}  // namespace
+
+struct ags_model {
+  ags_model_info info{};
+  int n_levels = 0, n_anc = 0;
+  std::vector<int> li, level_begin, level_links, children, anc_link, dof_link, si, body_slot_begin, body_slot, ai;
+  std::vector<double> lf, sf;
+  std::vector<int> jtype;  // per link, to fill the limit margins at sim creation
+  std::vector<float> mass, com, inertia;
+};
+
+extern "C" const char* ags_last_error(void) { return g_err.c_str(); }
+
+extern "C" int ags_model_create(const ags_actor_desc* actors, int32_t n_actors, const ags_pair_desc* pairs,
+                                int32_t n_pairs, ags_model** out) {
+  if (!actors || n_actors <= 0 || !out || (n_pairs > 0 && !pairs)) return fail(AGS_E_ARG, "model: bad arguments");
+  *out = nullptr;
+  ags_model* M = new ags_model();
+  std::vector<int> link_off(n_actors), shape_off(n_actors);
+  int nl = 0, ncol = 0, ndof = 0;
+  M->ai.assign((size_t)n_actors * AI_COLS, 0);
+  std::vector<int> depth;
+  std::vector<std::vector<const ags_shape_desc*>> link_shapes;
+  // links, columns, DOFs
+  for (int a = 0; a < n_actors; ++a) {
+    const ags_actor_desc& A = actors[a];
+    if (A.n_links <= 0 || !A.links || (A.n_shapes > 0 && !A.shapes)) {
+      delete M;
+      return fail(AGS_E_MODEL, "model: actor without links");
+    }
+    link_off[a] = nl;
+    const ags_link_desc& root = A.links[0];
+    if (root.parent != -1 || (root.joint != AGS_JOINT_FREE && root.joint != AGS_JOINT_FIXED)) {
+      delete M;
+      return fail(AGS_E_MODEL, "model: the first link of an actor must be a free or fixed root");
+    }
+    const bool fixed = root.joint == AGS_JOINT_FIXED;
+    M->ai[a * AI_COLS + AI_ROOT] = nl;
+    M->ai[a * AI_COLS + AI_FIXED] = fixed;
+    M->ai[a * AI_COLS + AI_COL] = fixed ? -1 : ncol;
+    int rootcol = fixed ? -1 : ncol;
+    if (!fixed) ncol += 6;
+    for (int i = 0; i < A.n_links; ++i) {
+      const ags_link_desc& L = A.links[i];
+      if (i > 0 && (L.parent < 0 || L.parent >= i || (L.joint != AGS_JOINT_REVOLUTE && L.joint != AGS_JOINT_PRISMATIC))) {
+        delete M;
+        return fail(AGS_E_MODEL, "model: links must be in topological order with 1-DOF revolute/prismatic joints");
+      }
+      std::vector<int> row(LI_COLS, -1);
+      std::vector<double> frow(LF_COLS, 0.0);
+      row[LI_PARENT] = i == 0 ? -1 : link_off[a] + L.parent;
+      row[LI_JTYPE] = L.joint;
+      row[LI_ROOT] = link_off[a];
+      row[LI_ROOTCOL] = rootcol;
+      if (i == 0) {
+        row[LI_COL] = rootcol;
+        row[LI_DOF] = -1;
+        depth.push_back(0);
+      } else {
+        row[LI_COL] = ncol++;
+        row[LI_DOF] = ndof++;
+        M->dof_link.push_back(nl);
+        depth.push_back(depth[row[LI_PARENT]] + 1);
+      }
+      double an = std::sqrt(double(L.axis[0]) * L.axis[0] + double(L.axis[1]) * L.axis[1] + double(L.axis[2]) * L.axis[2]);
+      for (int k = 0; k < 3; ++k) {
+        frow[LF_ANCHOR + k] = L.anchor[k];
+        frow[LF_AXIS + k] = (i > 0 && an > 0) ? L.axis[k] / an : L.axis[k];
+      }
+      if (i > 0 && !(an > 0)) {
+        delete M;
+        return fail(AGS_E_MODEL, "model: zero joint axis");
+      }
+      frow[LF_LO] = L.lower;
+      frow[LF_HI] = L.upper;
+      frow[LF_KP] = L.kp;
+      frow[LF_KD] = L.kd;
+      frow[LF_ARM] = L.armature;
+      M->li.insert(M->li.end(), row.begin(), row.end());
+      M->lf.insert(M->lf.end(), frow.begin(), frow.end());
+      M->jtype.push_back(L.joint);
+      link_shapes.emplace_back();
+      ++nl;
+    }
+    for (int k = 0; k < A.n_shapes; ++k) {
+      const ags_shape_desc& S = A.shapes[k];
+      if (S.link < 0 || S.link >= A.n_links || S.kind < 0 || S.kind > 2) {
+        delete M;
+        return fail(AGS_E_MODEL, "model: bad shape");
+      }
+      link_shapes[link_off[a] + S.link].push_back(&S);
+    }
+  }
+  if (nl > kMaxLinks || ncol > kMaxV) {
+    delete M;
+    return fail(AGS_E_ARG, "model: more than 64 links or 64 generalized velocities per environment");
+  }
+  // mass properties
+  M->mass.resize(nl);
+  M->com.resize(3 * nl);
+  M->inertia.resize(9 * nl);
+  {
+    int g = 0;
+    for (int a = 0; a < n_actors; ++a)
+      for (int i = 0; i < actors[a].n_links; ++i, ++g) {
+        Mass ms = link_mass(link_shapes[g], actors[a].links[i].mass);
+        if (actors[a].links[i].mass > 0 && link_shapes[g].empty()) {
+          delete M;
+          return fail(AGS_E_MODEL, "model: a given link mass needs shapes for its distribution");
+        }
+        if (i == 0 && actors[a].links[0].joint == AGS_JOINT_FREE) {
+          double cn = std::sqrt(ms.c[0] * ms.c[0] + ms.c[1] * ms.c[1] + ms.c[2] * ms.c[2]);
+          if (cn > 1e-6 || ms.m <= 0) {
+            delete M;
+            return fail(AGS_E_MODEL, "model: a free root link must have mass and its frame at its centre of mass");
+          }
+        }
+        double* fr = &M->lf[(size_t)g * LF_COLS];
+        fr[LF_MASS] = ms.m;
+        for (int k = 0; k < 3; ++k) fr[LF_COM + k] = ms.c[k];
+        fr[LF_IC + 0] = ms.I[0];
+        fr[LF_IC + 1] = ms.I[4];
+        fr[LF_IC + 2] = ms.I[8];
+        fr[LF_IC + 3] = 0.5 * (ms.I[1] + ms.I[3]);
+        fr[LF_IC + 4] = 0.5 * (ms.I[2] + ms.I[6]);
+        fr[LF_IC + 5] = 0.5 * (ms.I[5] + ms.I[7]);
+        M->mass[g] = (float)ms.m;
+        for (int k = 0; k < 3; ++k) M->com[3 * g + k] = (float)ms.c[k];
+        for (int k = 0; k < 9; ++k) M->inertia[9 * g + k] = (float)ms.I[k];
+      }
+  }
+  // every joint must carry inertia: a subtree without mass needs armature (its D would be 0)
+  {
+    std::vector<double> sub_mass(nl, 0.0);
+    for (int i = nl - 1; i >= 0; --i) {
+      sub_mass[i] += M->lf[(size_t)i * LF_COLS + LF_MASS];
+      int p = M->li[i * LI_COLS + LI_PARENT];
+      if (p >= 0) sub_mass[p] += sub_mass[i];
+    }
+    for (int i = 0; i < nl; ++i)
+      if (M->li[i * LI_COLS + LI_PARENT] >= 0 && !(sub_mass[i] > 0) && !(M->lf[(size_t)i * LF_COLS + LF_ARM] > 0)) {
+        delete M;
+        return fail(AGS_E_MODEL, "model: a joint moves neither mass nor armature");
+      }
+  }
+  // levels
+  int maxd = 0;
+  for (int d : depth) maxd = std::max(maxd, d);
+  M->n_levels = maxd + 1;
+  M->level_begin.assign(M->n_levels + 1, 0);
+  for (int d = 0; d < M->n_levels; ++d) {
+    M->level_begin[d] = (int)M->level_links.size();
+    for (int i = 0; i < nl; ++i)
+      if (depth[i] == d) M->level_links.push_back(i);
+  }
+  M->level_begin[M->n_levels] = nl;
+  // children and non-root ancestors (CSR)
+  for (int i = 0; i < nl; ++i) {
+    M->li[i * LI_COLS + LI_CHILD_BEGIN] = (int)M->children.size();
+    for (int c = i + 1; c < nl; ++c)
+      if (M->li[c * LI_COLS + LI_PARENT] == i) M->children.push_back(c);
+    M->li[i * LI_COLS + LI_CHILD_END] = (int)M->children.size();
+    M->li[i * LI_COLS + LI_ANC_BEGIN] = (int)M->anc_link.size();
+    std::vector<int> anc;
+    int p = M->li[i * LI_COLS + LI_PARENT];
+    while (p >= 0 && M->li[p * LI_COLS + LI_PARENT] >= 0) {
+      anc.push_back(p);
+      p = M->li[p * LI_COLS + LI_PARENT];
+    }
+    std::reverse(anc.begin(), anc.end());
+    M->anc_link.insert(M->anc_link.end(), anc.begin(), anc.end());
+    M->li[i * LI_COLS + LI_ANC_END] = (int)M->anc_link.size();
+  }
+  M->n_anc = (int)M->anc_link.size();
+  // contact slots: plane pairs (sphere 1, capsule 2 caps, box 8 corners); box pairs (sphere 1, capsule 2 caps + midpoint)
+  std::vector<std::vector<int>> body_entries(nl);
+  int limited = 0;
+  for (int i = 0; i < nl; ++i)
+    if (M->jtype[i] == AGS_JOINT_REVOLUTE || M->jtype[i] == AGS_JOINT_PRISMATIC)
+      limited += std::isfinite(M->lf[i * LF_COLS + LF_LO]) + std::isfinite(M->lf[i * LF_COLS + LF_HI]);
+  for (int p = 0; p < n_pairs; ++p) {
+    const ags_pair_desc& P = pairs[p];
+    if (P.a_actor < 0 || P.a_actor >= n_actors || P.a_shape < 0 || P.a_shape >= actors[P.a_actor].n_shapes ||
+        P.b_actor >= n_actors || (P.b_actor >= 0 && (P.b_shape < 0 || P.b_shape >= actors[P.b_actor].n_shapes))) {
+      delete M;
+      return fail(AGS_E_MODEL, "model: bad pair");
+    }
+    const ags_shape_desc& A = actors[P.a_actor].shapes[P.a_shape];
+    const int ka = link_off[P.a_actor] + A.link;
+    std::vector<std::vector<double>> pts;  // sphere centres or corners in link a's frame
+    int type;
+    int kb = -1;
+    const ags_shape_desc* B = nullptr;
+    if (P.b_actor < 0) {
+      if (A.kind == AGS_SHAPE_BOX) {
+        type = SLOT_CORNER_PLANE;
+        for (int c = 0; c < 8; ++c)
+          pts.push_back({double(A.p0[0]) + ((c & 1) ? A.half[0] : -A.half[0]),
+                         double(A.p0[1]) + ((c & 2) ? A.half[1] : -A.half[1]),
+                         double(A.p0[2]) + ((c & 4) ? A.half[2] : -A.half[2])});
+      } else {
+        type = SLOT_SPHERE_PLANE;
+        pts.push_back({A.p0[0], A.p0[1], A.p0[2]});
+        if (A.kind == AGS_SHAPE_CAPSULE) pts.push_back({A.p1[0], A.p1[1], A.p1[2]});
+      }
+    } else {
+      B = &actors[P.b_actor].shapes[P.b_shape];
+      if (B->kind != AGS_SHAPE_BOX || A.kind == AGS_SHAPE_BOX || P.b_actor == P.a_actor) {
+        delete M;
+        return fail(AGS_E_MODEL, "model: body pairs must be a sphere or capsule against a box of another actor");
+      }
+      type = SLOT_SPHERE_BOX;
+      kb = link_off[P.b_actor] + B->link;
+      pts.push_back({A.p0[0], A.p0[1], A.p0[2]});
+      if (A.kind == AGS_SHAPE_CAPSULE) {
+        pts.push_back({A.p1[0], A.p1[1], A.p1[2]});
+        pts.push_back({0.5 * (double(A.p0[0]) + A.p1[0]), 0.5 * (double(A.p0[1]) + A.p1[1]),
+                       0.5 * (double(A.p0[2]) + A.p1[2])});
+      }
+    }
+    for (size_t k = 0; k < pts.size(); ++k) {
+      int slot = (int)(M->si.size() / SI_COLS);
+      M->si.insert(M->si.end(), {type, ka, kb, (p << 8) | (int)k});
+      std::vector<double> f(SF_COLS, 0.0);
+      for (int q = 0; q < 3; ++q) f[SF_P + q] = pts[k][q];
+      f[SF_R] = type == SLOT_CORNER_PLANE ? 0.0 : A.radius;
+      if (B)
+        for (int q = 0; q < 3; ++q) {
+          f[SF_BOXC + q] = B->p0[q];
+          f[SF_HALF + q] = B->half[q];
+        }
+      M->sf.insert(M->sf.end(), f.begin(), f.end());
+      body_entries[ka].push_back(2 * slot);
+      if (kb >= 0) body_entries[kb].push_back(2 * slot + 1);
+    }
+  }
+  const int ns = (int)(M->si.size() / SI_COLS);
+  if (ns > kMaxSlots) {
+    delete M;
+    return fail(AGS_E_ARG, "model: more than 256 contact slots per environment");
+  }
+  M->body_slot_begin.assign(nl + 1, 0);
+  for (int i = 0; i < nl; ++i) {
+    M->body_slot_begin[i] = (int)M->body_slot.size();
+    M->body_slot.insert(M->body_slot.end(), body_entries[i].begin(), body_entries[i].end());
+  }
+  M->body_slot_begin[nl] = (int)M->body_slot.size();
+  M->info.n_actors = n_actors;
+  M->info.n_links = nl;
+  M->info.n_dof = ndof;
+  M->info.n_v = ncol;
+  M->info.n_slots = ns;
+  M->info.max_rows = limited + 3 * ns;
+  *out = M;
+  return AGS_OK;
+}
+
+extern "C" void ags_model_destroy(ags_model* m) { delete m; }
+
+extern "C" int ags_model_get_info(const ags_model* m, ags_model_info* out) {
+  if (!m || !out) return fail(AGS_E_ARG, "bad arguments");
+  *out = m->info;
+  return AGS_OK;
+}
+
+extern "C" int ags_model_mass_props(const ags_model* m, float* mass, float* com, float* inertia) {
+  if (!m) return fail(AGS_E_ARG, "bad arguments");
+  if (mass) std::copy(m->mass.begin(), m->mass.end(), mass);
+  if (com) std::copy(m->com.begin(), m->com.end(), com);
+  if (inertia) std::copy(m->inertia.begin(), m->inertia.end(), inertia);
+  return AGS_OK;
+}
+
+// ---------------------------------------------------------------- simulation
+namespace {
+struct TypeDev {
+  DevModel dm{};
+  Lds lds{};
+  void* block = nullptr;       // device tables
+  int* env_list = nullptr;     // device env ids of this type
+  int n_envs = 0;
+  void* scratch = nullptr;
+  long long scratch_stride = 0;  // elements of the compute type per env
+};
+
+Lds make_layout(const ags_model_info& info, int n_levels, int n_anc) {
+  (void)n_levels;
+  Lds L{};
+  int off = 0;
+  auto take = [&](int words) {
+    int o = off;
+    off += (words + 1) & ~1;  // keep 8-byte alignment
+    return o;
+  };
+  const int nl = info.n_links, na = info.n_actors, nd = info.n_dof, nv = info.n_v, ns = info.n_slots;
+  const int rc = std::max(1, info.max_rows);
+  L.R = take(9 * nl); L.o = take(3 * nl); L.ax = take(3 * nl); L.v = take(6 * nl); L.c = take(6 * nl);
+  L.IA = take(21 * nl); L.pA = take(6 * nl); L.U = take(6 * nl); L.Dinv = take(nl); L.u = take(nl);
+  L.a = take(6 * nl); L.Ubar = take(6 * nl); L.F = take(3 * nl);
+  L.L0 = take(27 * na);
+  L.qj = take(std::max(1, nd)); L.qd = take(nv); L.tau = take(nv); L.arm = take(nv); L.qddf = take(nv); L.vstar = take(nv);
+  L.root = take(13 * na);
+  L.G = take(std::max(1, n_anc));
+  L.phi = take(std::max(1, ns)); L.n = take(3 * ns); L.x = take(3 * ns); L.t1 = take(3 * ns); L.t2 = take(3 * ns);
+  L.slotrow = take(std::max(1, ns)); L.act = take(std::max(1, ns));
+  L.rkind = take(rc); L.rref = take(rc); L.rnorm = take(rc); L.rkey = take(rc); L.rbias = take(rc);
+  L.rinvA = take(rc); L.rlam = take(rc);
+  L.wstride = nv | 1;
+  L.W = take(kTeam * L.wstride);
+  L.misc = take(8);
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+struct ags_sim {
+  ags_sim_params params{};
+  int n_envs = 0;
+  std::vector<TypeDev> types;
+  std::vector<int> env_model;
+  int* env_tables = nullptr;  // device: actor base, dof base, body base (3 x n_envs)
+  int* actor_rows = nullptr;  // device: root row begin, root count(1), dof begin, dof count (4 x N_A)
+  int n_actors_total = 0, n_dof_total = 0, n_bodies_total = 0, max_nv = 0, max_rows = 0;
+  void* bound[AGS_NUM_TENSORS] = {nullptr};
+};
+
+extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, const int32_t* env_model,
+                              int32_t n_envs, const ags_sim_params* p, ags_sim** out) {
+  if (!models || n_models <= 0 || !env_model || n_envs <= 0 || !p || !out) return fail(AGS_E_ARG, "sim: bad arguments");
+  if (!(p->dt > 0) || p->substeps < 1 || p->pgs_iters < 0) return fail(AGS_E_ARG, "sim: bad parameters");
+  *out = nullptr;
+  for (int e = 0; e < n_envs; ++e)
+    if (env_model[e] < 0 || env_model[e] >= n_models || !models[env_model[e]])
+      return fail(AGS_E_ARG, "sim: bad env model index");
+  ags_sim* S = new ags_sim();
+  S->params = *p;
+  S->n_envs = n_envs;
+  S->env_model.assign(env_model, env_model + n_envs);
+  std::vector<int> tables(3 * (size_t)n_envs), rows;
+  std::vector<std::vector<int>> lists(n_models);
+  int ab = 0, db = 0, bb = 0;
+  for (int e = 0; e < n_envs; ++e) {
+    const ags_model* M = models[env_model[e]];
+    tables[e] = ab;
+    tables[n_envs + e] = db;
+    tables[2 * n_envs + e] = bb;
+    int d = db;
+    for (int a = 0; a < M->info.n_actors; ++a) {
+      int root = M->ai[a * AI_COLS + AI_ROOT];
+      int next_root = a + 1 < M->info.n_actors ? M->ai[(a + 1) * AI_COLS + AI_ROOT] : M->info.n_links;
+      int nd = next_root - root - 1;
+      rows.insert(rows.end(), {ab + a, 1, d, nd});
+      d += nd;
+    }
+    lists[env_model[e]].push_back(e);
+    ab += M->info.n_actors;
+    db += M->info.n_dof;
+    bb += M->info.n_links;
+    S->max_nv = std::max(S->max_nv, M->info.n_v);
+    S->max_rows = std::max(S->max_rows, M->info.max_rows);
+  }
+  S->n_actors_total = ab;
+  S->n_dof_total = db;
+  S->n_bodies_total = bb;
+  hipError_t err;
+  if ((err = hipMalloc(&S->env_tables, tables.size() * sizeof(int))) != hipSuccess ||
+      (err = hipMemcpy(S->env_tables, tables.data(), tables.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
+      (err = hipMalloc(&S->actor_rows, rows.size() * sizeof(int))) != hipSuccess ||
+      (err = hipMemcpy(S->actor_rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) {
+    ags_sim_destroy(S);
+    return hip_fail(err, "sim: upload");
+  }
+  for (int t = 0; t < n_models; ++t) {
+    if (lists[t].empty()) continue;
+    const ags_model* M = models[t];
+    TypeDev T;
+    T.n_envs = (int)lists[t].size();
+    T.lds = make_layout(M->info, M->n_levels, M->n_anc);
+    // limit margins per joint type
+    std::vector<double> lf = M->lf;
+    for (int i = 0; i < M->info.n_links; ++i)
+      lf[i * LF_COLS + LF_ML] = M->jtype[i] == AGS_JOINT_PRISMATIC ? p->limit_margin_pri : p->limit_margin_rev;
+    // one device block: ints then floats
+    std::vector<std::pair<const void*, size_t>> parts = {
+        {M->li.data(), M->li.size() * 4}, {M->level_begin.data(), M->level_begin.size() * 4},
+        {M->level_links.data(), M->level_links.size() * 4}, {M->children.data(), M->children.size() * 4},
+        {M->anc_link.data(), M->anc_link.size() * 4}, {M->dof_link.data(), M->dof_link.size() * 4},
+        {M->si.data(), M->si.size() * 4}, {M->body_slot_begin.data(), M->body_slot_begin.size() * 4},
+        {M->body_slot.data(), M->body_slot.size() * 4}, {M->ai.data(), M->ai.size() * 4},
+        {lists[t].data(), lists[t].size() * 4}, {lf.data(), lf.size() * 8}, {M->sf.data(), M->sf.size() * 8}};
+    size_t total = 0;
+    std::vector<size_t> offs;
+    for (auto& q : parts) {
+      offs.push_back(total);
+      total += (q.second + 255) & ~size_t(255);
+    }
+    if ((err = hipMalloc(&T.block, std::max<size_t>(total, 256))) != hipSuccess) {
+      S->types.push_back(T);
+      ags_sim_destroy(S);
+      return hip_fail(err, "sim: model tables");
+    }
+    std::vector<char> host(total, 0);
+    for (size_t k = 0; k < parts.size(); ++k)
+      if (parts[k].second) std::memcpy(host.data() + offs[k], parts[k].first, parts[k].second);
+    if ((err = hipMemcpy(T.block, host.data(), total, hipMemcpyHostToDevice)) != hipSuccess) {
+      S->types.push_back(T);
+      ags_sim_destroy(S);
+      return hip_fail(err, "sim: model upload");
+    }
+    char* b = static_cast<char*>(T.block);
+    DevModel& D = T.dm;
+    D.n_links = M->info.n_links;
+    D.n_actors = M->info.n_actors;
+    D.n_dof = M->info.n_dof;
+    D.n_v = M->info.n_v;
+    D.n_slots = M->info.n_slots;
+    D.n_levels = M->n_levels;
+    D.n_anc = M->n_anc;
+    D.r_cap = std::max(1, M->info.max_rows);
+    D.li = (const int*)(b + offs[0]);
+    D.level_begin = (const int*)(b + offs[1]);
+    D.level_links = (const int*)(b + offs[2]);
+    D.children = (const int*)(b + offs[3]);
+    D.anc_link = (const int*)(b + offs[4]);
+    D.dof_link = (const int*)(b + offs[5]);
+    D.si = (const int*)(b + offs[6]);
+    D.body_slot_begin = (const int*)(b + offs[7]);
+    D.body_slot = (const int*)(b + offs[8]);
+    D.ai = (const int*)(b + offs[9]);
+    T.env_list = (int*)(b + offs[10]);
+    D.lf = (const double*)(b + offs[11]);
+    D.sf = (const double*)(b + offs[12]);
+    T.scratch_stride = 2ll * D.r_cap * std::max(1, D.n_v);
+    T.scratch_stride = (T.scratch_stride + 63) & ~63ll;
+    const size_t elem = p->compute_fp64 ? sizeof(double) : sizeof(float);
+    if ((err = hipMalloc(&T.scratch, (size_t)T.scratch_stride * T.n_envs * elem)) != hipSuccess) {
+      S->types.push_back(T);
+      ags_sim_destroy(S);
+      return hip_fail(err, "sim: scratch");
+    }
+    const size_t lds_bytes = (size_t)T.lds.total * elem;
+    if (lds_bytes > 160 * 1024) {
+      S->types.push_back(T);
+      ags_sim_destroy(S);
+      return fail(AGS_E_ARG, "sim: model too large for one workgroup's LDS");
+    }
+    if (lds_bytes > 64 * 1024 && (err = set_lds_limit(p->compute_fp64, lds_bytes)) != hipSuccess) {
+      S->types.push_back(T);
+      ags_sim_destroy(S);
+      return hip_fail(err, "sim: LDS limit");
+    }
+    S->types.push_back(T);
+  }
+  *out = S;
+  return AGS_OK;
+}
+
+extern "C" void ags_sim_destroy(ags_sim* S) {
+  if (!S) return;
+  for (TypeDev& T : S->types) {
+    if (T.block) (void)hipFree(T.block);
+    if (T.scratch) (void)hipFree(T.scratch);
+  }
+  if (S->env_tables) (void)hipFree(S->env_tables);
+  if (S->actor_rows) (void)hipFree(S->actor_rows);
+  delete S;
+}
+
+extern "C" int ags_sim_tensor_shape(const ags_sim* S, int32_t which, int64_t* rows, int64_t* cols) {
+  if (!S || !rows || !cols) return fail(AGS_E_ARG, "bad arguments");
+  const int sub = S->params.substeps;
+  switch (which) {
+    case AGS_ROOT_STATE: *rows = S->n_actors_total; *cols = 13; break;
+    case AGS_DOF_STATE: *rows = S->n_dof_total; *cols = 2; break;
+    case AGS_DOF_ACTUATION: case AGS_DOF_POS_TARGET: case AGS_DOF_VEL_TARGET: case AGS_DOF_FORCE:
+      *rows = S->n_dof_total; *cols = 1; break;
+    case AGS_NET_CONTACT_FORCE: *rows = S->n_bodies_total; *cols = 3; break;
+    case AGS_DEBUG_QDD_FREE: *rows = S->n_envs; *cols = (int64_t)sub * S->max_nv; break;
+    case AGS_DEBUG_ROW_COUNT: *rows = S->n_envs; *cols = sub; break;
+    case AGS_DEBUG_ROW_KEY: case AGS_DEBUG_ROW_LAMBDA: *rows = S->n_envs; *cols = (int64_t)sub * std::max(1, S->max_rows); break;
+    default: return fail(AGS_E_ARG, "unknown tensor");
+  }
+  return AGS_OK;
+}
+
+extern "C" int ags_sim_bind(ags_sim* S, int32_t which, void* ptr) {
+  if (!S || which < 0 || which >= AGS_NUM_TENSORS) return fail(AGS_E_ARG, "bind: bad arguments");
+  S->bound[which] = ptr;
+  return AGS_OK;
+}
+
+extern "C" int ags_sim_step(ags_sim* S, void* stream) {
+  if (!S) return fail(AGS_E_ARG, "step: null sim");
+  if (!S->bound[AGS_ROOT_STATE] || !S->bound[AGS_DOF_STATE] || !S->bound[AGS_DOF_ACTUATION])
+    return fail(AGS_E_UNBOUND, "step: root state, DOF state and DOF actuation tensors must be bound");
+  const ags_sim_params& p = S->params;
+  const bool rows_dbg = S->bound[AGS_DEBUG_ROW_COUNT] && S->bound[AGS_DEBUG_ROW_KEY] && S->bound[AGS_DEBUG_ROW_LAMBDA];
+  for (TypeDev& T : S->types) {
+    StepArgs a{};
+    a.m = T.dm;
+    a.lds = T.lds;
+    a.env_list = T.env_list;
+    a.env_actor_base = S->env_tables;
+    a.env_dof_base = S->env_tables + S->n_envs;
+    a.env_body_base = S->env_tables + 2 * S->n_envs;
+    a.root_state = (float*)S->bound[AGS_ROOT_STATE];
+    a.dof_state = (float*)S->bound[AGS_DOF_STATE];
+    a.act = (const float*)S->bound[AGS_DOF_ACTUATION];
+    a.pos_tgt = (const float*)S->bound[AGS_DOF_POS_TARGET];
+    a.vel_tgt = (const float*)S->bound[AGS_DOF_VEL_TARGET];
+    a.contact_force = (float*)S->bound[AGS_NET_CONTACT_FORCE];
+    a.dof_force = (float*)S->bound[AGS_DOF_FORCE];
+    a.dbg_qdd = (float*)S->bound[AGS_DEBUG_QDD_FREE];
+    a.dbg_qdd_stride = p.substeps * S->max_nv;
+    a.dbg_qdd_sub = S->max_nv;
+    a.dbg_rc = rows_dbg ? (int*)S->bound[AGS_DEBUG_ROW_COUNT] : nullptr;
+    a.dbg_key = rows_dbg ? (int*)S->bound[AGS_DEBUG_ROW_KEY] : nullptr;
+    a.dbg_lam = rows_dbg ? (float*)S->bound[AGS_DEBUG_ROW_LAMBDA] : nullptr;
+    a.dbg_row_stride = p.substeps * std::max(1, S->max_rows);
+    a.dbg_row_sub = std::max(1, S->max_rows);
+    a.scratch = T.scratch;
+    a.scratch_stride = T.scratch_stride;
+    a.dt = p.dt;
+    a.h = (double)p.dt / p.substeps;
+    a.gx = p.gravity[0];
+    a.gy = p.gravity[1];
+    a.gz = p.gravity[2];
+    a.mu = p.mu;
+    a.beta = p.baumgarte;
+    a.mc = p.contact_margin;
+    a.substeps = p.substeps;
+    a.iters = p.pgs_iters;
+    hipError_t e = launch_step(a, T.n_envs, p.compute_fp64, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "step: launch");
+  }
+  return AGS_OK;
+}
+
+static int set_indexed(ags_sim* S, int which, const float* src, const int32_t* idx, int32_t n, void* stream) {
+  if (!S || !src || n < 0 || (!idx && n != 0 && n != S->n_actors_total)) return fail(AGS_E_ARG, "set: bad arguments");
+  if (!S->bound[which]) return fail(AGS_E_UNBOUND, "set: target tensor not bound");
+  const int width = which == AGS_ROOT_STATE ? 13 : 2;
+  hipError_t e = launch_set_rows((float*)S->bound[which], src, idx, idx ? n : S->n_actors_total, S->n_actors_total,
+                                 S->actor_rows, which == AGS_ROOT_STATE ? 0 : 2, width, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "set: launch");
+  return AGS_OK;
+}
+
+extern "C" int ags_sim_set_root_state_indexed(ags_sim* S, const float* src, const int32_t* idx, int32_t n,
+                                              void* stream) {
+  return set_indexed(S, AGS_ROOT_STATE, src, idx, n, stream);
+}
+
+extern "C" int ags_sim_set_dof_state_indexed(ags_sim* S, const float* src, const int32_t* idx, int32_t n,
+                                             void* stream) {
+  return set_indexed(S, AGS_DOF_STATE, src, idx, n, stream);
+}

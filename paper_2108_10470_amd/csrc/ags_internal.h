@@ -1,0 +1,91 @@
+// Internal layout shared by the host side and the HIP kernels of libags.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ags {
+
+constexpr int kTeam = 64;       // lanes per environment: one wavefront
+constexpr int kMaxLinks = 64;
+constexpr int kMaxV = 64;       // generalized velocities per environment (one lane each in the solver)
+constexpr int kMaxSlots = 256;
+constexpr float kMinRowMass = 1e-6f;  // rows with J M~^-1 J^T below this are dropped (immovable)
+
+// per-link integer table
+enum { LI_PARENT = 0, LI_JTYPE, LI_COL, LI_DOF, LI_ROOT, LI_CHILD_BEGIN, LI_CHILD_END, LI_ANC_BEGIN, LI_ANC_END,
+       LI_ROOTCOL, LI_COLS };
+// per-link float table (link frame quantities)
+enum { LF_ANCHOR = 0, LF_AXIS = 3, LF_MASS = 6, LF_COM = 7, LF_IC = 10 /* xx yy zz xy xz yz */,
+       LF_LO = 16, LF_HI, LF_KP, LF_KD, LF_ARM, LF_ML, LF_COLS };
+// per-slot tables
+enum { SLOT_SPHERE_PLANE = 0, SLOT_CORNER_PLANE = 1, SLOT_SPHERE_BOX = 2 };
+enum { SI_TYPE = 0, SI_LINK_A, SI_LINK_B, SI_KEY, SI_COLS };
+enum { SF_P = 0, SF_R = 3, SF_BOXC = 4, SF_HALF = 7, SF_COLS = 10 };
+// per-actor table
+enum { AI_ROOT = 0, AI_FIXED, AI_COL, AI_COLS };
+// joint types (same numbering as the public header)
+enum { J_FREE = 0, J_FIXED = 1, J_REV = 2, J_PRI = 3 };
+
+// LDS layout of one environment's workgroup, offsets in 4-byte words
+struct Lds {
+  int R, o, ax, v, c, IA, pA, U, Dinv, u, a, Ubar, F;  // per link
+  int L0;                                             // per actor: packed Cholesky factor (21) + 1/diag (6)
+  int qj, qd, tau, arm, qddf, vstar;                  // per DOF / column
+  int root;                                           // per actor: 13-float root state
+  int G;                                              // per ancestor pair
+  int phi, n, x, t1, t2, slotrow, act;                // per slot
+  int rkind, rref, rnorm, rkey, rbias, rinvA, rlam;   // per row
+  int W, wstride;                                     // 64-row chunk of W rows
+  int misc;                                           // a few ints
+  int total;
+};
+
+struct DevModel {
+  int n_links, n_actors, n_dof, n_v, n_slots, n_levels, n_anc, r_cap;
+  const int* li;
+  const double* lf;
+  const int* level_begin;
+  const int* level_links;
+  const int* children;
+  const int* anc_link;
+  const int* dof_link;   // link of each env DOF
+  const int* si;
+  const double* sf;
+  const int* body_slot_begin;  // CSR per link: entries 2*slot + (1 if the link is side b)
+  const int* body_slot;
+  const int* ai;
+};
+
+struct StepArgs {
+  DevModel m;
+  Lds lds;
+  const int* env_list;
+  const int* env_actor_base;
+  const int* env_dof_base;
+  const int* env_body_base;
+  float* root_state;
+  float* dof_state;
+  const float* act;
+  const float* pos_tgt;
+  const float* vel_tgt;
+  float* contact_force;
+  float* dof_force;
+  float* dbg_qdd;
+  int dbg_qdd_stride, dbg_qdd_sub;  // per env, per substep (sim-wide maximum n_v)
+  int* dbg_rc;
+  int* dbg_key;
+  float* dbg_lam;
+  int dbg_row_stride, dbg_row_sub;  // per env, per substep (sim-wide maximum rows)
+  void* scratch;           // per env: J rows then W rows, r_cap x n_v each, in the compute type
+  long long scratch_stride;
+  double dt, h, gx, gy, gz, mu, beta, mc;
+  int substeps, iters;
+};
+
+hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, hipStream_t stream);
+hipError_t set_lds_limit(int fp64, size_t bytes);
+hipError_t launch_set_rows(float* dst, const float* src, const int* idx, int n, int n_actors, const int* table,
+                           int field, int width, hipStream_t stream);
+
+}  // namespace ags

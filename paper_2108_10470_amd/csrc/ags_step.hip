@@ -1,0 +1,1050 @@
+// Batched articulated-physics step for gfx950: one wavefront (64 lanes) per environment.
+//
+// Per substep h = dt / substeps, for every environment (Section 3: reduced-coordinate
+// articulations; Table 3: sim parameters; Table 4: 2 substeps per control step):
+//   controls -> joint forces (actuation + implicit PD drive)
+//   forward sweep: kinematics, link inertias, velocities, velocity-product and bias forces
+//   articulated-body algorithm (Featherstone 2008, ch. 7): inward sweep, root solve, outward sweep
+//   narrow phase (sphere/capsule/box vs plane, sphere/capsule vs box) with speculative activation
+//   constraint rows: joint limits and contacts (normal + 2 friction directions)
+//   row responses W_r = M~^-1 J_r^T by articulated unit-load sweeps reusing the ABA factors
+//   fixed-sweep projected Gauss-Seidel on the joint velocities
+//   semi-implicit integration and output accumulation
+//
+// Frames: every spatial quantity of link i is expressed with world-aligned axes about the link's
+// own joint origin o_i (a free root: its centre of mass), positions relative to the first actor's
+// root.  Moving a quantity between links is a pure translation, so the inward sweep needs no
+// rotations and every lever arm stays at the size of one link.
+//
+// The kernel is a template over the compute type R.  R = float is the FP32 path; R = double keeps
+// the same FP32 tensors but computes in FP64, which gfx950's vector units issue at the FP32
+// (unpacked) rate; joint-space conditioning of the humanoid (cond(M~) ~ 2e3) puts FP32 results about
+// 1e-4 away from the exact ones.
+#include "ags_internal.h"
+
+namespace ags {
+namespace {
+
+// ---------------------------------------------------------------- scalar helpers
+__device__ __forceinline__ float rsqrt_(float x) { return 1.0f / sqrtf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float min_(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double min_(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float max_(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double max_(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float abs_(float a) { return fabsf(a); }
+__device__ __forceinline__ double abs_(double a) { return fabs(a); }
+__device__ __forceinline__ void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename R>
+struct V3 {
+  R x, y, z;
+};
+template <typename R>
+__device__ __forceinline__ V3<R> mk(R x, R y, R z) {
+  return {x, y, z};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> add(V3<R> a, V3<R> b) {
+  return {a.x + b.x, a.y + b.y, a.z + b.z};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> sub(V3<R> a, V3<R> b) {
+  return {a.x - b.x, a.y - b.y, a.z - b.z};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> mul(V3<R> a, R s) {
+  return {a.x * s, a.y * s, a.z * s};
+}
+template <typename R>
+__device__ __forceinline__ R dot(V3<R> a, V3<R> b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <typename R>
+__device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename R, typename T>
+__device__ __forceinline__ V3<R> ld3(const T* p) {
+  return {R(p[0]), R(p[1]), R(p[2])};
+}
+template <typename R>
+__device__ __forceinline__ void st3(R* p, V3<R> v) {
+  p[0] = v.x;
+  p[1] = v.y;
+  p[2] = v.z;
+}
+// 3x3 row-major helpers
+template <typename R>
+__device__ __forceinline__ V3<R> mv(const R* M, V3<R> v) {
+  return {M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z,
+          M[6] * v.x + M[7] * v.y + M[8] * v.z};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> mtv(const R* M, V3<R> v) {
+  return {M[0] * v.x + M[3] * v.y + M[6] * v.z, M[1] * v.x + M[4] * v.y + M[7] * v.z,
+          M[2] * v.x + M[5] * v.y + M[8] * v.z};
+}
+// symmetric 3x3 stored xx yy zz xy xz yz
+template <typename R>
+__device__ __forceinline__ V3<R> symv(const R* S, V3<R> v) {
+  return {S[0] * v.x + S[3] * v.y + S[4] * v.z, S[3] * v.x + S[1] * v.y + S[5] * v.z,
+          S[4] * v.x + S[5] * v.y + S[2] * v.z};
+}
+template <typename R>
+__device__ __forceinline__ void mm3(const R* A, const R* B, R* C) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+// ---------------------------------------------------------------- spatial inertia (21 words)
+// A (sym 3x3, angular block), B (3x3 row-major coupling), M (sym 3x3): I [w; v] = [A w + B v; B^T w + M v]
+template <typename R>
+struct SI {
+  R A[6], B[9], M[6];
+};
+template <typename R>
+__device__ __forceinline__ void si_load(SI<R>& I, const R* p) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) I.A[k] = p[k];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) I.B[k] = p[6 + k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) I.M[k] = p[15 + k];
+}
+template <typename R>
+__device__ __forceinline__ void si_store(const SI<R>& I, R* p) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) p[k] = I.A[k];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) p[6 + k] = I.B[k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) p[15 + k] = I.M[k];
+}
+template <typename R>
+__device__ __forceinline__ void si_addload(SI<R>& I, const R* p) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) I.A[k] += p[k];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) I.B[k] += p[6 + k];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) I.M[k] += p[15 + k];
+}
+template <typename R>
+__device__ __forceinline__ void si_mul(const SI<R>& I, V3<R> w, V3<R> v, V3<R>& ra, V3<R>& rl) {
+  ra = add(symv(I.A, w), mv(I.B, v));
+  rl = add(mtv(I.B, w), symv(I.M, v));
+}
+template <typename R>
+__device__ __forceinline__ R si_at(const SI<R>& I, int r, int c) {
+  const int sidx[9] = {0, 3, 4, 3, 1, 5, 4, 5, 2};
+  if (r < 3 && c < 3) return I.A[sidx[3 * r + c]];
+  if (r < 3) return I.B[3 * r + (c - 3)];
+  if (c < 3) return I.B[3 * c + (r - 3)];
+  return I.M[sidx[3 * (r - 3) + (c - 3)]];
+}
+// Move an inertia from point Q to point P = Q - r (translation only): I_P = X^T I_Q X with
+// X = [1 0; -r^ 1].  Then M' = M, B' = B + r^ M, A' = A - B r^ + r^ B'^T.
+template <typename R>
+__device__ __forceinline__ void si_shift(SI<R>& I, V3<R> r) {
+  const int sidx[9] = {0, 3, 4, 3, 1, 5, 4, 5, 2};
+  R Mf[9], Bn[9], Af[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) Mf[k] = I.M[sidx[k]];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {  // columns of B': B[:, j] + r x M[:, j]
+    V3<R> x = cross(r, mk(Mf[j], Mf[3 + j], Mf[6 + j]));
+    Bn[j] = I.B[j] + x.x;
+    Bn[3 + j] = I.B[3 + j] + x.y;
+    Bn[6 + j] = I.B[6 + j] + x.z;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {  // rows of -B r^: -(B row i) x r
+    V3<R> q = cross(mk(I.B[3 * i], I.B[3 * i + 1], I.B[3 * i + 2]), r);
+    Af[3 * i + 0] = -q.x;
+    Af[3 * i + 1] = -q.y;
+    Af[3 * i + 2] = -q.z;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {  // columns of r^ B'^T: r x (B' row i)
+    V3<R> pc = cross(r, mk(Bn[3 * i], Bn[3 * i + 1], Bn[3 * i + 2]));
+    Af[0 + i] += pc.x;
+    Af[3 + i] += pc.y;
+    Af[6 + i] += pc.z;
+  }
+  const R half = R(0.5);
+  I.A[0] += Af[0];
+  I.A[1] += Af[4];
+  I.A[2] += Af[8];
+  I.A[3] += half * (Af[1] + Af[3]);
+  I.A[4] += half * (Af[2] + Af[6]);
+  I.A[5] += half * (Af[5] + Af[7]);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) I.B[k] = Bn[k];
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+__device__ __forceinline__ unsigned long long lanes_below(int t) { return (1ull << t) - 1ull; }
+
+// Cholesky of a 6x6 SPD matrix (packed lower, index i(i+1)/2 + j) and the reciprocal diagonal
+template <typename R>
+__device__ void chol6(const SI<R>& K, R* L, R* dinv) {
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    R d = si_at(K, j, j);
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= L[j * (j + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+    d = sqrt_(max_(d, R(1e-30)));
+    L[j * (j + 1) / 2 + j] = d;
+    R inv = R(1) / d;
+    dinv[j] = inv;
+#pragma unroll
+    for (int i = j + 1; i < 6; ++i) {
+      R s = si_at(K, i, j);
+#pragma unroll
+      for (int k = 0; k < j; ++k) s -= L[i * (i + 1) / 2 + k] * L[j * (j + 1) / 2 + k];
+      L[i * (i + 1) / 2 + j] = s * inv;
+    }
+  }
+}
+template <typename R>
+__device__ void chol6_solve(const R* L, const R* dinv, R* x) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    R s = x[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= L[i * (i + 1) / 2 + k] * x[k];
+    x[i] = s * dinv[i];
+  }
+#pragma unroll
+  for (int i = 5; i >= 0; --i) {
+    R s = x[i];
+#pragma unroll
+    for (int k = i + 1; k < 6; ++k) s -= L[k * (k + 1) / 2 + i] * x[k];
+    x[i] = s * dinv[i];
+  }
+}
+
+// rotation of angle q about unit axis a (Rodrigues), row-major
+template <typename R>
+__device__ __forceinline__ void axis_angle(V3<R> a, R q, R* M) {
+  R s, c;
+  sincos_(q, &s, &c);
+  R t = R(1) - c;
+  M[0] = c + t * a.x * a.x;
+  M[1] = t * a.x * a.y - s * a.z;
+  M[2] = t * a.x * a.z + s * a.y;
+  M[3] = t * a.x * a.y + s * a.z;
+  M[4] = c + t * a.y * a.y;
+  M[5] = t * a.y * a.z - s * a.x;
+  M[6] = t * a.x * a.z - s * a.y;
+  M[7] = t * a.y * a.z + s * a.x;
+  M[8] = c + t * a.z * a.z;
+}
+
+// tangent basis of a contact normal: t1 = normalised projection of the world axis least aligned with n
+// (lowest index on ties), t2 = n x t1
+template <typename R>
+__device__ __forceinline__ void tangents(V3<R> n, V3<R>& t1, V3<R>& t2) {
+  R ax = abs_(n.x), ay = abs_(n.y), az = abs_(n.z);
+  int k = 0;
+  R best = ax;
+  if (ay < best) {
+    best = ay;
+    k = 1;
+  }
+  if (az < best) k = 2;
+  V3<R> e = k == 0 ? mk(R(1), R(0), R(0)) : (k == 1 ? mk(R(0), R(1), R(0)) : mk(R(0), R(0), R(1)));
+  V3<R> t = sub(e, mul(n, dot(n, e)));
+  t1 = mul(t, rsqrt_(dot(t, t)));
+  t2 = cross(n, t1);
+}
+
+// LDS views of one environment (layout offsets are in units of R)
+template <typename R>
+struct Ctx {
+  R *Rm, *o, *ax, *v, *c, *IA, *pA, *U, *Dinv, *u, *a, *Ubar, *F, *L0;
+  R *qj, *qd, *tau, *arm, *qddf, *vstar, *root, *G;
+  R *phi, *n, *x, *t1, *t2;
+  int *slotrow, *act;
+  int *rkind, *rref, *rnorm, *rkey;
+  R *rbias, *rinvA, *rlam, *W;
+  int* misc;
+  __device__ void init(R* smem, const Lds& L) {
+    Rm = smem + L.R; o = smem + L.o; ax = smem + L.ax; v = smem + L.v; c = smem + L.c;
+    IA = smem + L.IA; pA = smem + L.pA; U = smem + L.U; Dinv = smem + L.Dinv; u = smem + L.u;
+    a = smem + L.a; Ubar = smem + L.Ubar; F = smem + L.F; L0 = smem + L.L0;
+    qj = smem + L.qj; qd = smem + L.qd; tau = smem + L.tau; arm = smem + L.arm; qddf = smem + L.qddf;
+    vstar = smem + L.vstar; root = smem + L.root; G = smem + L.G;
+    phi = smem + L.phi; n = smem + L.n; x = smem + L.x; t1 = smem + L.t1; t2 = smem + L.t2;
+    slotrow = reinterpret_cast<int*>(smem + L.slotrow); act = reinterpret_cast<int*>(smem + L.act);
+    rkind = reinterpret_cast<int*>(smem + L.rkind); rref = reinterpret_cast<int*>(smem + L.rref);
+    rnorm = reinterpret_cast<int*>(smem + L.rnorm); rkey = reinterpret_cast<int*>(smem + L.rkey);
+    rbias = smem + L.rbias; rinvA = smem + L.rinvA; rlam = smem + L.rlam; W = smem + L.W;
+    misc = reinterpret_cast<int*>(smem + L.misc);
+  }
+};
+
+__device__ __forceinline__ int actor_of_root(const DevModel& M, int link) {
+  int a = 0;
+  for (int k = 0; k < M.n_actors; ++k)
+    if (M.ai[k * AI_COLS + AI_ROOT] == link) a = k;
+  return a;
+}
+
+// Adds the joint loads of one unit test load to Wrow (u_k at each joint column on the path of link k)
+// and the resulting bias force at a free root ([n; f] in the root's 6 columns).  The load is a spatial
+// force given by its bias contribution (pn, pf) = -f about o_k, or a joint force tau0 at link k.
+template <typename R>
+__device__ void unit_load_inward(const DevModel& M, const Ctx<R>& s, int k, V3<R> pn, V3<R> pf, R tau0, R* Wrow) {
+  while (true) {
+    const int* li = M.li + k * LI_COLS;
+    const int jt = li[LI_JTYPE];
+    if (jt == J_FIXED) return;
+    if (jt == J_FREE) {
+      const int c = li[LI_ROOTCOL];
+      Wrow[c + 0] += pn.x; Wrow[c + 1] += pn.y; Wrow[c + 2] += pn.z;
+      Wrow[c + 3] += pf.x; Wrow[c + 4] += pf.y; Wrow[c + 5] += pf.z;
+      return;
+    }
+    const V3<R> ax = ld3<R>(s.ax + 3 * k);
+    const V3<R> Ua = ld3<R>(s.U + 6 * k), Ul = ld3<R>(s.U + 6 * k + 3);
+    const R u = tau0 - (jt == J_REV ? dot(ax, pn) : dot(ax, pf));
+    tau0 = R(0);
+    Wrow[li[LI_COL]] += u;
+    const R ud = u * s.Dinv[k];
+    pn = add(pn, mul(Ua, ud));
+    pf = add(pf, mul(Ul, ud));
+    const int p = li[LI_PARENT];
+    pn = add(pn, cross(sub(ld3<R>(s.o + 3 * k), ld3<R>(s.o + 3 * p)), pf));
+    k = p;
+  }
+}
+
+// Row of a point load along d at point x on link k (sign +-1): adds J entries to Jrow when non-null and
+// returns sum_j J_j Wrow_j when Wrow is non-null.
+template <typename R>
+__device__ R point_row(const DevModel& M, const Ctx<R>& s, int k, V3<R> x, V3<R> d, R sign, R* Jrow, const R* Wrow) {
+  R acc = R(0);
+  while (true) {
+    const int* li = M.li + k * LI_COLS;
+    const int jt = li[LI_JTYPE];
+    if (jt == J_FIXED) break;
+    if (jt == J_FREE) {
+      const int c = li[LI_ROOTCOL];
+      const V3<R> mo = cross(sub(x, ld3<R>(s.o + 3 * k)), d);
+      const R j6[6] = {d.x, d.y, d.z, mo.x, mo.y, mo.z};
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        if (Jrow) Jrow[c + q] += sign * j6[q];
+        if (Wrow) acc += sign * j6[q] * Wrow[c + q];
+      }
+      break;
+    }
+    const V3<R> ax = ld3<R>(s.ax + 3 * k);
+    const R jv = jt == J_REV ? dot(ax, cross(sub(x, ld3<R>(s.o + 3 * k)), d)) : dot(ax, d);
+    const int c = li[LI_COL];
+    if (Jrow) Jrow[c] += sign * jv;
+    if (Wrow) acc += sign * jv * Wrow[c];
+    k = li[LI_PARENT];
+  }
+  return acc;
+}
+
+}  // namespace
+
+template <typename R>
+__global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* smem = reinterpret_cast<R*>(smem_raw);
+  const DevModel& M = P.m;
+  const Lds& L = P.lds;
+  const int t = threadIdx.x;
+  const int env = P.env_list[blockIdx.x];
+  Ctx<R> s;
+  s.init(smem, L);
+
+  const int nl = M.n_links, nd = M.n_dof, nv = M.n_v, ns = M.n_slots, na = M.n_actors;
+  const int abase = P.env_actor_base[env], dbase = P.env_dof_base[env], bbase = P.env_body_base[env];
+  const R h = R(P.h);
+  const V3<R> grav = mk(R(P.gx), R(P.gy), R(P.gz));
+  R* Jg = reinterpret_cast<R*>(P.scratch) + (long long)blockIdx.x * P.scratch_stride;
+  R* Wg = Jg + (long long)M.r_cap * nv;
+
+  // ---------------------------------------------------------------- load state
+  for (int k = t; k < 13 * na; k += kTeam) s.root[k] = R(P.root_state[(long long)abase * 13 + k]);
+  for (int j = t; j < nd; j += kTeam) {
+    const int lk = M.dof_link[j];
+    s.qj[j] = R(P.dof_state[2ll * (dbase + j)]);
+    s.qd[M.li[lk * LI_COLS + LI_COL]] = R(P.dof_state[2ll * (dbase + j) + 1]);
+  }
+  for (int k = t; k < 3 * nl; k += kTeam) s.F[k] = R(0);
+  __syncthreads();
+  for (int k = t; k < na; k += kTeam) {
+    const int* ai = M.ai + k * AI_COLS;
+    if (!ai[AI_FIXED])
+      for (int q = 0; q < 6; ++q) s.qd[ai[AI_COL] + q] = s.root[13 * k + 7 + q];
+  }
+  R dof_force_acc = R(0);
+  __syncthreads();
+  const V3<R> origin = ld3<R>(s.root);
+
+  for (int sub_i = 0; sub_i < P.substeps; ++sub_i) {
+    // ---------------------------------------------------- controls: actuation + implicit PD drive
+    // the drive kp (q* - q+) + kd (qd* - qd+) at the end of the substep splits into an explicit part
+    // and the armature h kd + h^2 kp added to the joint's diagonal of M~
+    for (int j = t; j < nd; j += kTeam) {
+      const int lk = M.dof_link[j];
+      const double* lf = M.lf + lk * LF_COLS;
+      const int c = M.li[lk * LI_COLS + LI_COL];
+      const R pt = P.pos_tgt ? R(P.pos_tgt[dbase + j]) : R(0);
+      const R vt = P.vel_tgt ? R(P.vel_tgt[dbase + j]) : R(0);
+      const R kp = R(lf[LF_KP]), kd = R(lf[LF_KD]);
+      s.tau[c] = R(P.act[dbase + j]) + kp * (pt - s.qj[j] - h * s.qd[c]) + kd * (vt - s.qd[c]);
+      s.arm[c] = R(lf[LF_ARM]) + h * kd + h * h * kp;
+    }
+    __syncthreads();
+
+    // ---------------------------------------------------- forward sweep by depth
+    for (int d = 0; d < M.n_levels; ++d) {
+      for (int idx = M.level_begin[d] + t; idx < M.level_begin[d + 1]; idx += kTeam) {
+        const int i = M.level_links[idx];
+        const int* li = M.li + i * LI_COLS;
+        const double* lf = M.lf + i * LF_COLS;
+        const int jt = li[LI_JTYPE];
+        R Rw[9];
+        V3<R> o, w, vl, ca = mk(R(0), R(0), R(0)), cl = mk(R(0), R(0), R(0)), ax = mk(R(0), R(0), R(0));
+        if (jt == J_FREE || jt == J_FIXED) {
+          // root pose from the root state (quaternion xyzw, normalised on read)
+          const R* rs = s.root + 13 * actor_of_root(M, i);
+          R qx = rs[3], qy = rs[4], qz = rs[5], qw = rs[6];
+          const R inv = rsqrt_(qx * qx + qy * qy + qz * qz + qw * qw);
+          qx *= inv; qy *= inv; qz *= inv; qw *= inv;
+          const R one = R(1), two = R(2);
+          Rw[0] = one - two * (qy * qy + qz * qz); Rw[1] = two * (qx * qy - qz * qw); Rw[2] = two * (qx * qz + qy * qw);
+          Rw[3] = two * (qx * qy + qz * qw); Rw[4] = one - two * (qx * qx + qz * qz); Rw[5] = two * (qy * qz - qx * qw);
+          Rw[6] = two * (qx * qz - qy * qw); Rw[7] = two * (qy * qz + qx * qw); Rw[8] = one - two * (qx * qx + qy * qy);
+          o = sub(ld3<R>(rs), origin);
+          if (jt == J_FREE) {
+            const int c = li[LI_ROOTCOL];
+            vl = ld3<R>(s.qd + c);
+            w = ld3<R>(s.qd + c + 3);
+          } else {
+            vl = mk(R(0), R(0), R(0));
+            w = vl;
+          }
+        } else {
+          const int p = li[LI_PARENT];
+          const R* Rp = s.Rm + 9 * p;
+          const V3<R> axl = ld3<R>(lf + LF_AXIS);
+          V3<R> tl = ld3<R>(lf + LF_ANCHOR);
+          const R q = s.qj[li[LI_DOF]], qd = s.qd[li[LI_COL]];
+          if (jt == J_REV) {
+            R Rr[9];
+            axis_angle(axl, q, Rr);
+            mm3(Rp, Rr, Rw);
+          } else {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Rw[k] = Rp[k];
+            tl = add(tl, mul(axl, q));
+          }
+          ax = mv(Rp, axl);
+          const V3<R> op = ld3<R>(s.o + 3 * p);
+          o = add(op, mv(Rp, tl));
+          w = ld3<R>(s.v + 6 * p);
+          vl = add(ld3<R>(s.v + 6 * p + 3), cross(w, sub(o, op)));
+          if (jt == J_REV) {
+            w = add(w, mul(ax, qd));
+            ca = mul(cross(w, ax), qd);
+            cl = mul(cross(vl, ax), qd);
+          } else {
+            vl = add(vl, mul(ax, qd));
+            cl = mul(cross(w, ax), qd);
+          }
+        }
+        // spatial inertia about o (world axes): A = Ic_w + m (|d|^2 1 - d d^T), B = m d^, M = m 1
+        const R m = R(lf[LF_MASS]);
+        const V3<R> d = mv(Rw, ld3<R>(lf + LF_COM));
+        const double* Icl = lf + LF_IC;
+        const R Ic[9] = {R(Icl[0]), R(Icl[3]), R(Icl[4]), R(Icl[3]), R(Icl[1]), R(Icl[5]), R(Icl[4]), R(Icl[5]), R(Icl[2])};
+        R T[9], Iw[9];
+        mm3(Rw, Ic, T);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+            Iw[3 * a + b] = T[3 * a] * Rw[3 * b] + T[3 * a + 1] * Rw[3 * b + 1] + T[3 * a + 2] * Rw[3 * b + 2];
+        SI<R> I;
+        const R dd = dot(d, d), half = R(0.5);
+        I.A[0] = Iw[0] + m * (dd - d.x * d.x);
+        I.A[1] = Iw[4] + m * (dd - d.y * d.y);
+        I.A[2] = Iw[8] + m * (dd - d.z * d.z);
+        I.A[3] = half * (Iw[1] + Iw[3]) - m * d.x * d.y;
+        I.A[4] = half * (Iw[2] + Iw[6]) - m * d.x * d.z;
+        I.A[5] = half * (Iw[5] + Iw[7]) - m * d.y * d.z;
+        I.B[0] = R(0); I.B[1] = -m * d.z; I.B[2] = m * d.y;
+        I.B[3] = m * d.z; I.B[4] = R(0); I.B[5] = -m * d.x;
+        I.B[6] = -m * d.y; I.B[7] = m * d.x; I.B[8] = R(0);
+        I.M[0] = m; I.M[1] = m; I.M[2] = m; I.M[3] = R(0); I.M[4] = R(0); I.M[5] = R(0);
+        // bias force p = v x* (I v) - f_gravity (gravity m g at the COM)
+        V3<R> ha, hl;
+        si_mul(I, w, vl, ha, hl);
+        const V3<R> fg = mul(grav, m);
+        const V3<R> pn = sub(add(cross(w, ha), cross(vl, hl)), cross(d, fg));
+        const V3<R> pf = sub(cross(w, hl), fg);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) s.Rm[9 * i + k] = Rw[k];
+        st3(s.o + 3 * i, o);
+        st3(s.ax + 3 * i, ax);
+        st3(s.v + 6 * i, w);
+        st3(s.v + 6 * i + 3, vl);
+        st3(s.c + 6 * i, ca);
+        st3(s.c + 6 * i + 3, cl);
+        si_store(I, s.IA + 21 * i);
+        st3(s.pA + 6 * i, pn);
+        st3(s.pA + 6 * i + 3, pf);
+      }
+      __syncthreads();
+    }
+
+    // ---------------------------------------------------- ABA inward sweep (deepest level first)
+    for (int d = M.n_levels - 1; d >= 0; --d) {
+      for (int idx = M.level_begin[d] + t; idx < M.level_begin[d + 1]; idx += kTeam) {
+        const int i = M.level_links[idx];
+        const int* li = M.li + i * LI_COLS;
+        const int jt = li[LI_JTYPE];
+        if (jt == J_FIXED) continue;
+        SI<R> I;
+        si_load(I, s.IA + 21 * i);
+        V3<R> pn = ld3<R>(s.pA + 6 * i), pf = ld3<R>(s.pA + 6 * i + 3);
+        for (int q = li[LI_CHILD_BEGIN]; q < li[LI_CHILD_END]; ++q) {  // children hold I^a, p^a moved to o_i
+          const int ch = M.children[q];
+          si_addload(I, s.IA + 21 * ch);
+          pn = add(pn, ld3<R>(s.pA + 6 * ch));
+          pf = add(pf, ld3<R>(s.pA + 6 * ch + 3));
+        }
+        if (jt == J_FREE) {
+          st3(s.pA + 6 * i, pn);
+          st3(s.pA + 6 * i + 3, pf);
+          const int a = actor_of_root(M, i);
+          chol6(I, s.L0 + 27 * a, s.L0 + 27 * a + 21);
+          continue;
+        }
+        const int c = li[LI_COL];
+        const V3<R> ax = ld3<R>(s.ax + 3 * i);
+        V3<R> Ua, Ul;
+        R D, u;
+        if (jt == J_REV) {
+          Ua = symv(I.A, ax);
+          Ul = mtv(I.B, ax);
+          D = dot(ax, Ua);
+          u = s.tau[c] - dot(ax, pn);
+        } else {
+          Ua = mv(I.B, ax);
+          Ul = symv(I.M, ax);
+          D = dot(ax, Ul);
+          u = s.tau[c] - dot(ax, pf);
+        }
+        D += s.arm[c];
+        const R Dinv = R(1) / D;
+        // I^a = I^A - U U^T / D
+        I.A[0] -= Ua.x * Ua.x * Dinv; I.A[1] -= Ua.y * Ua.y * Dinv; I.A[2] -= Ua.z * Ua.z * Dinv;
+        I.A[3] -= Ua.x * Ua.y * Dinv; I.A[4] -= Ua.x * Ua.z * Dinv; I.A[5] -= Ua.y * Ua.z * Dinv;
+        I.M[0] -= Ul.x * Ul.x * Dinv; I.M[1] -= Ul.y * Ul.y * Dinv; I.M[2] -= Ul.z * Ul.z * Dinv;
+        I.M[3] -= Ul.x * Ul.y * Dinv; I.M[4] -= Ul.x * Ul.z * Dinv; I.M[5] -= Ul.y * Ul.z * Dinv;
+        const R ua[3] = {Ua.x, Ua.y, Ua.z}, ul[3] = {Ul.x, Ul.y, Ul.z};
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) I.B[3 * a + b] -= ua[a] * ul[b] * Dinv;
+        // p^a = p^A + I^a c + U u / D
+        V3<R> ia, il;
+        si_mul(I, ld3<R>(s.c + 6 * i), ld3<R>(s.c + 6 * i + 3), ia, il);
+        const R ud = u * Dinv;
+        pn = add(add(pn, ia), mul(Ua, ud));
+        pf = add(add(pf, il), mul(Ul, ud));
+        // move to the parent's point
+        const V3<R> r = sub(ld3<R>(s.o + 3 * i), ld3<R>(s.o + 3 * li[LI_PARENT]));
+        si_shift(I, r);
+        pn = add(pn, cross(r, pf));
+        si_store(I, s.IA + 21 * i);
+        st3(s.pA + 6 * i, pn);
+        st3(s.pA + 6 * i + 3, pf);
+        st3(s.U + 6 * i, Ua);
+        st3(s.U + 6 * i + 3, Ul);
+        s.Dinv[i] = Dinv;
+        s.u[i] = u;
+      }
+      __syncthreads();
+    }
+
+    // ---------------------------------------------------- root solve and ABA outward sweep
+    for (int d = 0; d < M.n_levels; ++d) {
+      for (int idx = M.level_begin[d] + t; idx < M.level_begin[d + 1]; idx += kTeam) {
+        const int i = M.level_links[idx];
+        const int* li = M.li + i * LI_COLS;
+        const int jt = li[LI_JTYPE];
+        V3<R> aa, al;
+        if (jt == J_FIXED) {
+          aa = mk(R(0), R(0), R(0));
+          al = aa;
+        } else if (jt == J_FREE) {
+          const int a = actor_of_root(M, i);
+          R x[6];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) x[q] = -s.pA[6 * i + q];
+          chol6_solve(s.L0 + 27 * a, s.L0 + 27 * a + 21, x);
+          aa = mk(x[0], x[1], x[2]);
+          al = mk(x[3], x[4], x[5]);
+          // classical acceleration of the centre of mass: a_lin + w x v_com
+          const int c = li[LI_ROOTCOL];
+          st3(s.qddf + c, add(al, cross(ld3<R>(s.qd + c + 3), ld3<R>(s.qd + c))));
+          st3(s.qddf + c + 3, aa);
+        } else {
+          const int p = li[LI_PARENT];
+          const V3<R> r = sub(ld3<R>(s.o + 3 * i), ld3<R>(s.o + 3 * p));
+          aa = ld3<R>(s.a + 6 * p);
+          al = add(ld3<R>(s.a + 6 * p + 3), cross(aa, r));
+          aa = add(aa, ld3<R>(s.c + 6 * i));
+          al = add(al, ld3<R>(s.c + 6 * i + 3));
+          const R qdd = (s.u[i] - dot(ld3<R>(s.U + 6 * i), aa) - dot(ld3<R>(s.U + 6 * i + 3), al)) * s.Dinv[i];
+          const V3<R> ax = ld3<R>(s.ax + 3 * i);
+          if (jt == J_REV) aa = add(aa, mul(ax, qdd));
+          else al = add(al, mul(ax, qdd));
+          s.qddf[li[LI_COL]] = qdd;
+        }
+        st3(s.a + 6 * i, aa);
+        st3(s.a + 6 * i + 3, al);
+      }
+      __syncthreads();
+    }
+    for (int c = t; c < nv; c += kTeam) s.vstar[c] = s.qd[c] + h * s.qddf[c];
+    if (P.dbg_qdd)
+      for (int c = t; c < nv; c += kTeam)
+        P.dbg_qdd[(long long)env * P.dbg_qdd_stride + sub_i * P.dbg_qdd_sub + c] = float(s.qddf[c]);
+    __syncthreads();
+
+    // ---------------------------------------------------- link velocities under v*, U about roots, G table
+    for (int d = 0; d < M.n_levels; ++d) {
+      for (int idx = M.level_begin[d] + t; idx < M.level_begin[d + 1]; idx += kTeam) {
+        const int i = M.level_links[idx];
+        const int* li = M.li + i * LI_COLS;
+        const int jt = li[LI_JTYPE];
+        V3<R> w, vl;
+        if (jt == J_FIXED) {
+          w = mk(R(0), R(0), R(0));
+          vl = w;
+        } else if (jt == J_FREE) {
+          const int c = li[LI_ROOTCOL];
+          vl = ld3<R>(s.vstar + c);
+          w = ld3<R>(s.vstar + c + 3);
+        } else {
+          const int p = li[LI_PARENT];
+          const V3<R> oi = ld3<R>(s.o + 3 * i);
+          w = ld3<R>(s.v + 6 * p);
+          vl = add(ld3<R>(s.v + 6 * p + 3), cross(w, sub(oi, ld3<R>(s.o + 3 * p))));
+          const V3<R> ax = ld3<R>(s.ax + 3 * i);
+          const R qd = s.vstar[li[LI_COL]];
+          if (jt == J_REV) w = add(w, mul(ax, qd));
+          else vl = add(vl, mul(ax, qd));
+          // U moved to the root point, and G_ik = U_i . (s_k moved to o_i) for every ancestor joint k
+          const V3<R> Ua = ld3<R>(s.U + 6 * i), Ul = ld3<R>(s.U + 6 * i + 3);
+          st3(s.Ubar + 6 * i, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * li[LI_ROOT])), Ul)));
+          st3(s.Ubar + 6 * i + 3, Ul);
+          for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q) {
+            const int k = M.anc_link[q];
+            const V3<R> ak = ld3<R>(s.ax + 3 * k);
+            s.G[q] = M.li[k * LI_COLS + LI_JTYPE] == J_REV ? dot(ak, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * k)), Ul)))
+                                                          : dot(ak, Ul);
+          }
+        }
+        st3(s.v + 6 * i, w);
+        st3(s.v + 6 * i + 3, vl);
+      }
+      __syncthreads();
+    }
+
+    // ---------------------------------------------------- narrow phase and activation (one slot per lane)
+    for (int sb = 0; sb < ns; sb += kTeam) {
+      const int sl = sb + t;
+      if (sl < ns) {
+        const int* si = M.si + sl * SI_COLS;
+        const double* sf = M.sf + sl * SF_COLS;
+        const int ka = si[SI_LINK_A], kb = si[SI_LINK_B];
+        const R rad = R(sf[SF_R]);
+        const V3<R> xc = add(ld3<R>(s.o + 3 * ka), mv(s.Rm + 9 * ka, ld3<R>(sf + SF_P)));
+        R phi;
+        V3<R> nrm, x;
+        if (si[SI_TYPE] == SLOT_SPHERE_PLANE) {
+          phi = origin.z + xc.z - rad;
+          nrm = mk(R(0), R(0), R(1));
+          x = sub(xc, mk(R(0), R(0), rad));
+        } else if (si[SI_TYPE] == SLOT_CORNER_PLANE) {
+          phi = origin.z + xc.z;
+          nrm = mk(R(0), R(0), R(1));
+          x = xc;
+        } else {
+          // sphere against box: closest point, or the face of least penetration when inside
+          const R* Rb = s.Rm + 9 * kb;
+          const V3<R> cb = add(ld3<R>(s.o + 3 * kb), mv(Rb, ld3<R>(sf + SF_BOXC)));
+          const V3<R> hb = ld3<R>(sf + SF_HALF);
+          const V3<R> xl = mtv(Rb, sub(xc, cb));
+          const V3<R> ql = mk(min_(max_(xl.x, -hb.x), hb.x), min_(max_(xl.y, -hb.y), hb.y), min_(max_(xl.z, -hb.z), hb.z));
+          const bool inside = ql.x == xl.x && ql.y == xl.y && ql.z == xl.z;
+          const V3<R> dl = sub(xl, ql);
+          const R dn = sqrt_(dot(dl, dl));
+          V3<R> nl;
+          if (!inside && dn > R(1e-12)) {
+            phi = dn - rad;
+            nl = mul(dl, R(1) / dn);
+          } else {
+            const R pen[3] = {hb.x - abs_(xl.x), hb.y - abs_(xl.y), hb.z - abs_(xl.z)};
+            const R xs[3] = {xl.x, xl.y, xl.z};
+            int kbest = 0;
+            if (pen[1] < pen[kbest]) kbest = 1;
+            if (pen[2] < pen[kbest]) kbest = 2;
+            const R sg = xs[kbest] >= R(0) ? R(1) : R(-1);
+            nl = kbest == 0 ? mk(sg, R(0), R(0)) : (kbest == 1 ? mk(R(0), sg, R(0)) : mk(R(0), R(0), sg));
+            phi = -pen[kbest] - rad;
+          }
+          nrm = mv(Rb, nl);
+          x = sub(xc, mul(nrm, rad));
+        }
+        // normal velocity of body a relative to body b at x under v*
+        V3<R> ua = add(ld3<R>(s.v + 6 * ka + 3), cross(ld3<R>(s.v + 6 * ka), sub(x, ld3<R>(s.o + 3 * ka))));
+        if (kb >= 0) ua = sub(ua, add(ld3<R>(s.v + 6 * kb + 3), cross(ld3<R>(s.v + 6 * kb), sub(x, ld3<R>(s.o + 3 * kb)))));
+        const R vn = dot(nrm, ua);
+        V3<R> t1, t2;
+        tangents(nrm, t1, t2);
+        s.phi[sl] = phi;
+        st3(s.n + 3 * sl, nrm);
+        st3(s.x + 3 * sl, x);
+        st3(s.t1 + 3 * sl, t1);
+        st3(s.t2 + 3 * sl, t2);
+        s.act[sl] = (phi + h * min_(R(0), vn)) < R(P.mc);
+      }
+    }
+    __syncthreads();
+
+    // ---------------------------------------------------- constraint rows: limits (by DOF), then contacts
+    {
+      int running = 0;
+      for (int jb = 0; jb < nd; jb += kTeam) {
+        const int j = jb + t;
+        int alo = 0, ahi = 0;
+        R glo = R(0), ghi = R(0);
+        if (j < nd) {
+          const int lk = M.dof_link[j];
+          const double* lf = M.lf + lk * LF_COLS;
+          const R vs = s.vstar[M.li[lk * LI_COLS + LI_COL]];
+          const R ml = R(lf[LF_ML]), q = s.qj[j];
+          if (isfinite(lf[LF_LO])) {
+            glo = q - R(lf[LF_LO]);
+            alo = min_(glo, glo + h * vs) < ml;
+          }
+          if (isfinite(lf[LF_HI])) {
+            ghi = R(lf[LF_HI]) - q;
+            ahi = min_(ghi, ghi - h * vs) < ml;
+          }
+        }
+        const unsigned long long mlo = __ballot(alo), mhi = __ballot(ahi);
+        const int base = running + __popcll(mlo & lanes_below(t)) + __popcll(mhi & lanes_below(t));
+        if (alo) {
+          s.rkind[base] = 1; s.rref[base] = j; s.rnorm[base] = -1; s.rkey[base] = (1 << 24) | (j << 8);
+          s.rbias[base] = glo >= R(0) ? glo / h : R(P.beta) * glo / h;
+        }
+        if (ahi) {
+          const int r = base + alo;
+          s.rkind[r] = 2; s.rref[r] = j; s.rnorm[r] = -1; s.rkey[r] = (2 << 24) | (j << 8);
+          s.rbias[r] = ghi >= R(0) ? ghi / h : R(P.beta) * ghi / h;
+        }
+        running += __popcll(mlo) + __popcll(mhi);
+      }
+      for (int sb = 0; sb < ns; sb += kTeam) {
+        const int sl = sb + t;
+        const int a = sl < ns ? s.act[sl] : 0;
+        const unsigned long long m = __ballot(a);
+        const int base = running + 3 * __popcll(m & lanes_below(t));
+        if (sl < ns) s.slotrow[sl] = a ? base : -1;
+        if (a) {
+          const int key = M.si[sl * SI_COLS + SI_KEY];
+          const R phi = s.phi[sl];
+          for (int k = 0; k < 3; ++k) {
+            s.rkind[base + k] = 3 + k;
+            s.rref[base + k] = sl;
+            s.rnorm[base + k] = base;
+            s.rkey[base + k] = ((3 + k) << 24) | key;
+            s.rbias[base + k] = k == 0 ? (phi >= R(0) ? phi / h : R(P.beta) * phi / h) : R(0);
+          }
+        }
+        running += 3 * __popcll(m);
+      }
+      if (t == 0) s.misc[0] = running;
+    }
+    __syncthreads();
+    const int Rn = s.misc[0];
+
+    // ---------------------------------------------------- row Jacobians and responses W_r = M~^-1 J_r^T
+    for (int k = t; k < Rn * nv; k += kTeam) Jg[k] = R(0);
+    __syncthreads();
+    for (int rb = 0; rb < Rn; rb += kTeam) {
+      const int r = rb + t;
+      R* Wrow = s.W + t * L.wstride;
+      for (int c = 0; c < nv; ++c) Wrow[c] = R(0);
+      if (r < Rn) {
+        const int kind = s.rkind[r];
+        R* Jrow = Jg + (long long)r * nv;
+        if (kind <= 2) {
+          const int lk = M.dof_link[s.rref[r]];
+          const R sg = kind == 1 ? R(1) : R(-1);
+          Jrow[M.li[lk * LI_COLS + LI_COL]] = sg;
+          unit_load_inward(M, s, lk, mk(R(0), R(0), R(0)), mk(R(0), R(0), R(0)), sg, Wrow);
+        } else {
+          const int sl = s.rref[r];
+          const R* dp = kind == 3 ? s.n : (kind == 4 ? s.t1 : s.t2);
+          const V3<R> dd = ld3<R>(dp + 3 * sl), x = ld3<R>(s.x + 3 * sl);
+          const int ka = M.si[sl * SI_COLS + SI_LINK_A], kb = M.si[sl * SI_COLS + SI_LINK_B];
+          point_row(M, s, ka, x, dd, R(1), Jrow, (const R*)nullptr);
+          unit_load_inward(M, s, ka, mul(cross(sub(x, ld3<R>(s.o + 3 * ka)), dd), R(-1)), mul(dd, R(-1)), R(0), Wrow);
+          if (kb >= 0) {
+            point_row(M, s, kb, x, dd, R(-1), Jrow, (const R*)nullptr);
+            unit_load_inward(M, s, kb, cross(sub(x, ld3<R>(s.o + 3 * kb)), dd), dd, R(0), Wrow);
+          }
+        }
+        // roots: a = -(I^A_root)^-1 (accumulated bias force); generalized root columns are (v_com, w)
+        for (int k = 0; k < na; ++k) {
+          const int* ai = M.ai + k * AI_COLS;
+          if (ai[AI_FIXED]) continue;
+          const int c = ai[AI_COL];
+          R x6[6];
+#pragma unroll
+          for (int q = 0; q < 6; ++q) x6[q] = -Wrow[c + q];
+          chol6_solve(s.L0 + 27 * k, s.L0 + 27 * k + 21, x6);
+          Wrow[c + 0] = x6[3]; Wrow[c + 1] = x6[4]; Wrow[c + 2] = x6[5];
+          Wrow[c + 3] = x6[0]; Wrow[c + 4] = x6[1]; Wrow[c + 5] = x6[2];
+        }
+        // outward: qdd_i = (u_i - Ubar_i . a_root - sum_k G_ik qdd_k) / D_i in topological order
+        for (int i = 0; i < nl; ++i) {
+          const int* li = M.li + i * LI_COLS;
+          const int jt = li[LI_JTYPE];
+          if (jt == J_FREE || jt == J_FIXED) continue;
+          R acc = R(0);
+          const int rc = li[LI_ROOTCOL];
+          if (rc >= 0) {
+            const R* ub = s.Ubar + 6 * i;
+            acc = ub[0] * Wrow[rc + 3] + ub[1] * Wrow[rc + 4] + ub[2] * Wrow[rc + 5] + ub[3] * Wrow[rc + 0] +
+                  ub[4] * Wrow[rc + 1] + ub[5] * Wrow[rc + 2];
+          }
+          for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q)
+            acc += s.G[q] * Wrow[M.li[M.anc_link[q] * LI_COLS + LI_COL]];
+          const int c = li[LI_COL];
+          Wrow[c] = (Wrow[c] - acc) * s.Dinv[i];
+        }
+        // A_rr = J_r W_r
+        R A;
+        if (kind <= 2) {
+          const int lk = M.dof_link[s.rref[r]];
+          A = (kind == 1 ? R(1) : R(-1)) * Wrow[M.li[lk * LI_COLS + LI_COL]];
+        } else {
+          const int sl = s.rref[r];
+          const R* dp = kind == 3 ? s.n : (kind == 4 ? s.t1 : s.t2);
+          const V3<R> dd = ld3<R>(dp + 3 * sl), x = ld3<R>(s.x + 3 * sl);
+          const int ka = M.si[sl * SI_COLS + SI_LINK_A], kb = M.si[sl * SI_COLS + SI_LINK_B];
+          A = point_row(M, s, ka, x, dd, R(1), (R*)nullptr, Wrow);
+          if (kb >= 0) A += point_row(M, s, kb, x, dd, R(-1), (R*)nullptr, Wrow);
+        }
+        s.rinvA[r] = A >= R(kMinRowMass) ? R(1) / A : R(0);
+        s.rlam[r] = R(0);
+      }
+      __syncthreads();
+      const int rows_here = min(kTeam, Rn - rb);
+      for (int q = 0; q < rows_here; ++q)
+        for (int c = t; c < nv; c += kTeam) Wg[(long long)(rb + q) * nv + c] = s.W[q * L.wstride + c];
+      __syncthreads();
+    }
+    for (int r = t; r < Rn; r += kTeam)  // friction rows of a dropped normal row are dropped too
+      if (s.rkind[r] >= 4 && s.rinvA[s.rnorm[r]] == R(0)) s.rinvA[r] = R(0);
+    __syncthreads();
+
+    // ---------------------------------------------------- projected Gauss-Seidel, lanes over velocity columns
+    R vj = t < nv ? s.vstar[t] : R(0);
+    const R mu = R(P.mu);
+    for (int it = 0; it < P.iters; ++it) {
+      for (int r = 0; r < Rn; ++r) {
+        const R invA = s.rinvA[r];
+        if (invA == R(0)) continue;
+        const R Jr = t < nv ? Jg[(long long)r * nv + t] : R(0);
+        const R Wr = t < nv ? Wg[(long long)r * nv + t] : R(0);
+        const R res = wave_sum(Jr * vj) + s.rbias[r];
+        const R lam = s.rlam[r];
+        R nlam = lam - res * invA;
+        if (s.rkind[r] >= 4) {
+          const R hi = mu * s.rlam[s.rnorm[r]];
+          nlam = min_(max_(nlam, -hi), hi);
+        } else {
+          nlam = max_(nlam, R(0));
+        }
+        vj += Wr * (nlam - lam);
+        s.rlam[r] = nlam;
+      }
+    }
+    __syncthreads();
+
+    // ---------------------------------------------------- outputs of the substep and integration
+    if (P.dbg_rc) {
+      int running = 0;
+      for (int rb = 0; rb < Rn; rb += kTeam) {
+        const int r = rb + t;
+        const int keep = r < Rn && s.rinvA[r] != R(0);
+        const unsigned long long m = __ballot(keep);
+        const int pos = running + __popcll(m & lanes_below(t));
+        if (keep && pos < M.r_cap) {
+          const long long o = (long long)env * P.dbg_row_stride + (long long)sub_i * P.dbg_row_sub + pos;
+          P.dbg_key[o] = s.rkey[r];
+          P.dbg_lam[o] = float(s.rlam[r]);
+        }
+        running += __popcll(m);
+      }
+      if (t == 0) P.dbg_rc[env * P.substeps + sub_i] = running;
+    }
+    // contact impulses of each slot -> force on its bodies (summed over the step, divided by dt)
+    for (int sb = 0; sb < ns; sb += kTeam) {
+      const int sl = sb + t;
+      if (sl < ns) {
+        const int r = s.slotrow[sl];
+        V3<R> F = mk(R(0), R(0), R(0));
+        if (r >= 0)
+          F = add(add(mul(ld3<R>(s.n + 3 * sl), s.rlam[r]), mul(ld3<R>(s.t1 + 3 * sl), s.rlam[r + 1])),
+                  mul(ld3<R>(s.t2 + 3 * sl), s.rlam[r + 2]));
+        st3(s.x + 3 * sl, F);  // the contact point is no longer needed
+      }
+    }
+    __syncthreads();
+    for (int b = t; b < nl; b += kTeam) {
+      V3<R> acc = ld3<R>(s.F + 3 * b);
+      for (int q = M.body_slot_begin[b]; q < M.body_slot_begin[b + 1]; ++q) {
+        const int e = M.body_slot[q];
+        const V3<R> F = ld3<R>(s.x + 3 * (e >> 1));
+        acc = (e & 1) ? sub(acc, F) : add(acc, F);
+      }
+      st3(s.F + 3 * b, acc);
+    }
+    // DOF forces at the end-of-substep velocity, and joint integration q+ = q + h qd+
+    if (t < nv) s.qd[t] = vj;
+    __syncthreads();
+    for (int j = t; j < nd; j += kTeam) {
+      const int lk = M.dof_link[j];
+      const double* lf = M.lf + lk * LF_COLS;
+      const int c = M.li[lk * LI_COLS + LI_COL];
+      const R pt = P.pos_tgt ? R(P.pos_tgt[dbase + j]) : R(0);
+      const R vt = P.vel_tgt ? R(P.vel_tgt[dbase + j]) : R(0);
+      const R qdp = s.qd[c];
+      dof_force_acc += R(P.act[dbase + j]) + R(lf[LF_KP]) * (pt - s.qj[j] - h * qdp) + R(lf[LF_KD]) * (vt - qdp);
+      s.qj[j] += h * qdp;
+    }
+    // free roots: p+ = p + h v+, quat+ = normalize(Exp(h w+) (x) quat)
+    for (int k = t; k < na; k += kTeam) {
+      const int* ai = M.ai + k * AI_COLS;
+      if (ai[AI_FIXED]) continue;
+      const int c = ai[AI_COL];
+      R* rs = s.root + 13 * k;
+      const V3<R> vc = ld3<R>(s.qd + c), w = ld3<R>(s.qd + c + 3);
+      st3(rs, add(ld3<R>(rs), mul(vc, h)));
+      const V3<R> th = mul(w, h);
+      const R ang = sqrt_(dot(th, th));
+      R dx, dy, dz, dw;
+      if (ang < R(1e-8)) {
+        dx = R(0.5) * th.x; dy = R(0.5) * th.y; dz = R(0.5) * th.z; dw = R(1);
+      } else {
+        R sn, cs;
+        sincos_(R(0.5) * ang, &sn, &cs);
+        const R sc = sn / ang;
+        dx = th.x * sc; dy = th.y * sc; dz = th.z * sc; dw = cs;
+      }
+      const R qx = rs[3], qy = rs[4], qz = rs[5], qw = rs[6];
+      // Hamilton product (dx, dy, dz, dw) (x) (qx, qy, qz, qw)
+      const R nx = dw * qx + qw * dx + (dy * qz - dz * qy);
+      const R ny = dw * qy + qw * dy + (dz * qx - dx * qz);
+      const R nz = dw * qz + qw * dz + (dx * qy - dy * qx);
+      const R nw = dw * qw - (dx * qx + dy * qy + dz * qz);
+      const R inv = rsqrt_(nx * nx + ny * ny + nz * nz + nw * nw);
+      rs[3] = nx * inv; rs[4] = ny * inv; rs[5] = nz * inv; rs[6] = nw * inv;
+      st3(rs + 7, vc);
+      st3(rs + 10, w);
+    }
+    __syncthreads();
+  }
+
+  // ---------------------------------------------------------------- write back
+  for (int k = t; k < na; k += kTeam) {
+    const int* ai = M.ai + k * AI_COLS;
+    float* dst = P.root_state + (long long)(abase + k) * 13;
+    for (int q = 0; q < 7; ++q) dst[q] = float(s.root[13 * k + q]);
+    for (int q = 7; q < 13; ++q) dst[q] = ai[AI_FIXED] ? 0.0f : float(s.root[13 * k + q]);
+  }
+  for (int j = t; j < nd; j += kTeam) {
+    const int lk = M.dof_link[j];
+    P.dof_state[2ll * (dbase + j)] = float(s.qj[j]);
+    P.dof_state[2ll * (dbase + j) + 1] = float(s.qd[M.li[lk * LI_COLS + LI_COL]]);
+    if (P.dof_force) P.dof_force[dbase + j] = float(dof_force_acc / R(P.substeps));
+  }
+  if (P.contact_force) {
+    const R inv_dt = R(1) / R(P.dt);
+    for (int k = t; k < 3 * nl; k += kTeam) P.contact_force[(long long)bbase * 3 + k] = float(s.F[k] * inv_dt);
+  }
+}
+
+// Copy the rows of the listed actors from src to dst (same layout).  table holds 4 ints per actor:
+// root row, root row count (1), first DOF row, DOF row count; `field` selects the pair (0 root, 2 DOF).
+__global__ void set_rows_kernel(float* dst, const float* src, const int* idx, int n, int n_actors, const int* table,
+                                int field, int width) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long long)n * kTeam) return;
+  const int k = (int)(gid / kTeam), lane = (int)(gid % kTeam);
+  const int a = idx ? idx[k] : k;
+  if (a < 0 || a >= n_actors) return;  // invalid indices are ignored
+  const int rb = table[4 * a + field], rc = table[4 * a + field + 1];
+  for (int e = lane; e < rc * width; e += kTeam) {
+    const long long off = (long long)rb * width + e;
+    dst[off] = src[off];
+  }
+}
+
+hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, hipStream_t stream) {
+  if (n_envs <= 0) return hipSuccess;
+  const size_t lds = (size_t)a.lds.total * (fp64 ? 8 : 4);
+  if (fp64)
+    hipLaunchKernelGGL(step_kernel<double>, dim3(n_envs), dim3(kTeam), lds, stream, a);
+  else
+    hipLaunchKernelGGL(step_kernel<float>, dim3(n_envs), dim3(kTeam), lds, stream, a);
+  return hipGetLastError();
+}
+
+hipError_t set_lds_limit(int fp64, size_t bytes) {
+  if (fp64)
+    return hipFuncSetAttribute((const void*)step_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return hipFuncSetAttribute((const void*)step_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_set_rows(float* dst, const float* src, const int* idx, int n, int n_actors, const int* table,
+                           int field, int width, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const long long threads = (long long)n * kTeam;
+  const int block = 256;
+  const int grid = (int)((threads + block - 1) / block);
+  hipLaunchKernelGGL(set_rows_kernel, dim3(grid), dim3(block), 0, stream, dst, src, idx, n, n_actors, table, field,
+                     width);
+  return hipGetLastError();
+}
+
+}  // namespace ags

@@ -190,10 +190,14 @@ def ant(limit_deg_hip: float = 40.0, limit_deg_knee: float = 70.0, gear: float =
 _AXES = {"x": (1.0, 0.0, 0.0), "y": (0.0, 1.0, 0.0), "z": (0.0, 0.0, 1.0)}
 
 
-def humanoid(limit_seed: int = 0, gear: float = 67.5) -> Actor:
+def humanoid(limit_seed: int = 0, gear: float = 67.5, armature: float = 0.02, damping: float = 1.0) -> Actor:
     """Humanoid-like: 13 capsule bodies, free root, 21 revolute DOFs.  Multi-axis joints are chains
     of 1-DOF revolutes through massless links whose anchors coincide (the last link of a chain
     carries the capsule).  Joint limits are +-w with w ~ U[0.5, 1.5] seeded per DOF.
+
+    Every DOF has joint armature 0.02 kg m^2 and joint damping 1 N m s/rad (Table 3 lists both as
+    per-joint parameters; the values are stand-ins: without them 67.5 N m random torques on ~1 kg
+    links make the model itself diverge within a second, even in FP64).
 
     The torso capsule is centred on the root frame so that the free root frame sits at the root
     centre of mass (the root-state position is the root COM)."""
@@ -224,7 +228,7 @@ def humanoid(limit_seed: int = 0, gear: float = 67.5) -> Actor:
             links.append(Link(name if last else f"{name}_{ax}", parent, "revolute",
                               anchor=tuple(map(float, anchor)) if ai == 0 else (0.0, 0.0, 0.0),
                               axis=_AXES[ax], lower=-float(w[j]), upper=float(w[j]), gear=gear,
-                              shapes=[_capsule(c0, c1, r)] if last else []))
+                              armature=armature, kd=damping, shapes=[_capsule(c0, c1, r)] if last else []))
             j += 1
             parent = len(links) - 1
         index[name] = len(links) - 1
@@ -353,3 +357,40 @@ def pd_targets(env: EnvSpec, n_envs: int, n_steps: int, seed: int = 0) -> np.nda
 
 
 PARAMS_DEFAULT = SimParams()
+
+
+# ----------------------------------------------------------------------------
+# single-precision-representable copies (the library's description structs are float32)
+# ----------------------------------------------------------------------------
+def _r32(x):
+    return float(np.float32(x))
+
+
+def as_f32(env: EnvSpec) -> EnvSpec:
+    """Deep copy of env with every number rounded to float32, so that a consumer reading float32
+    fields and one reading float64 fields see identical values."""
+    import copy
+    e = copy.deepcopy(env)
+    for a in e.actors:
+        a.root_pos = tuple(_r32(v) for v in a.root_pos)
+        a.root_quat = tuple(_r32(v) for v in a.root_quat)
+        for l in a.links:
+            l.anchor = tuple(_r32(v) for v in l.anchor)
+            l.axis = tuple(_r32(v) for v in l.axis)
+            for f in ("lower", "upper", "kp", "kd", "armature", "mass", "gear"):
+                setattr(l, f, _r32(getattr(l, f)))
+            for sh in l.shapes:
+                sh.p0 = tuple(_r32(v) for v in sh.p0)
+                sh.p1 = tuple(_r32(v) for v in sh.p1)
+                sh.half = tuple(_r32(v) for v in sh.half)
+                sh.radius = _r32(sh.radius)
+                sh.density = _r32(sh.density)
+    return e
+
+
+def params_f32(p: SimParams) -> SimParams:
+    """Copy of p with every float parameter rounded to float32."""
+    return SimParams(dt=_r32(p.dt), substeps=p.substeps, gravity=tuple(_r32(g) for g in p.gravity),
+                     pgs_iters=p.pgs_iters, mu=_r32(p.mu), baumgarte=_r32(p.baumgarte),
+                     contact_margin=_r32(p.contact_margin), limit_margin_rev=_r32(p.limit_margin_rev),
+                     limit_margin_pri=_r32(p.limit_margin_pri))

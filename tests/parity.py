@@ -1,0 +1,128 @@
+"""GPU-vs-oracle single-step parity: both sides take one env-step from the same FP32 state.
+
+States come from FP64 oracle rollouts of the seeded initial states (never from the GPU path), are
+rounded to FP32, and are fed to the HIP path and to the oracle.  The tolerance is elementwise
+|g - o| <= 1e-5 + 1e-4 |o| on the unconstrained accelerations, positions (incl. quaternions) and
+constraint impulses.  Env-substeps the oracle marks as near a mode switch (a row whose existence
+flips within the guard width) are reported separately and excluded from the gate.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from oracle import oracle as O
+from paper_2108_10470_amd import ags, workloads as W
+
+RTOL = 1e-4
+ATOL = 1e-5
+
+
+def gpu_step(sim: "ags.Sim", env, root, dof, act, pos_tgt=None):
+    """One GPU env-step of a batch given as float arrays; returns numpy outputs (float64)."""
+    E = root.shape[0]
+    dev = sim.device
+    sim.root_state.copy_(torch.from_numpy(np.ascontiguousarray(root.reshape(-1, 13), dtype=np.float32)).to(dev))
+    sim.dof_state.copy_(torch.from_numpy(np.ascontiguousarray(dof.reshape(-1, 2), dtype=np.float32)).to(dev))
+    sim.actuation.copy_(torch.from_numpy(np.ascontiguousarray(act.reshape(-1), dtype=np.float32)).to(dev))
+    if pos_tgt is not None:
+        sim.pos_target.copy_(torch.from_numpy(np.ascontiguousarray(pos_tgt.reshape(-1), dtype=np.float32)).to(dev))
+    sim.dbg_rc.zero_()
+    sim.dbg_key.fill_(-1)
+    sim.step()
+    torch.cuda.synchronize(dev)
+    S = sim.params.substeps
+    nv = env.n_v
+    return dict(
+        root=sim.root_state.double().cpu().numpy().reshape(E, env.n_actors, 13),
+        dof=sim.dof_state.double().cpu().numpy().reshape(E, env.n_dof, 2),
+        qdd_free=sim.dbg_qdd.double().cpu().numpy().reshape(E, S, -1)[:, :, :nv],
+        row_count=sim.dbg_rc.cpu().numpy().reshape(E, S),
+        row_key=sim.dbg_key.cpu().numpy().reshape(E, S, -1),
+        row_lambda=sim.dbg_lam.double().cpu().numpy().reshape(E, S, -1),
+        contact_force=sim.contact_force.double().cpu().numpy().reshape(E, env.n_bodies, 3),
+        dof_force=sim.dof_force.double().cpu().numpy().reshape(E, env.n_dof),
+    )
+
+
+def ratio(g, o):
+    return np.abs(g - o) / (ATOL + RTOL * np.abs(o))
+
+
+def compare(env, params, g, o):
+    """Per-env worst ratio for each gated quantity; envs the oracle flags near a switch are masked."""
+    E = g["root"].shape[0]
+    S = params.substeps
+    near = (o["near"] != 0).any(axis=1)
+    out = {"near": near}
+    out["qdd_free0"] = ratio(g["qdd_free"][:, 0], o["qdd_free"][:, 0]).max(axis=1)
+    out["qdd_free"] = np.array([ratio(g["qdd_free"][e], o["qdd_free"][e]).max() for e in range(E)])
+    pos_g = np.concatenate([g["root"][:, :, :7].reshape(E, -1), g["dof"][:, :, 0]], axis=1)
+    pos_o = np.concatenate([o["root"][:, :, :7].reshape(E, -1), o["dof"][:, :, 0]], axis=1)
+    out["q"] = ratio(pos_g, pos_o).max(axis=1)
+    vel_g = np.concatenate([g["root"][:, :, 7:].reshape(E, -1), g["dof"][:, :, 1]], axis=1)
+    vel_o = np.concatenate([o["root"][:, :, 7:].reshape(E, -1), o["dof"][:, :, 1]], axis=1)
+    out["qd"] = ratio(vel_g, vel_o).max(axis=1)
+    lam = np.zeros(E)
+    rows_match = np.ones(E, dtype=bool)
+    for e in range(E):
+        worst = 0.0
+        for s in range(S):
+            ng, no = g["row_count"][e, s], o["row_count"][e, s]
+            kg, ko = g["row_key"][e, s, :ng], o["row_key"][e, s, :no]
+            if ng != no or not np.array_equal(kg, ko):
+                rows_match[e] = False
+                continue
+            if no:
+                worst = max(worst, ratio(g["row_lambda"][e, s, :ng], o["row_lambda"][e, s, :no]).max())
+        lam[e] = worst
+    out["lambda"] = lam
+    out["rows_match"] = rows_match
+    return out
+
+
+def summarize(c):
+    ok = ~c["near"]
+    keys = ["qdd_free0", "qdd_free", "q", "lambda", "qd"]
+    s = {"envs": int(len(ok)), "near_switch": int((~ok).sum()), "rows_mismatch_not_near": int((~c["rows_match"] & ok).sum())}
+    for k in keys:
+        s[k + "_max_ratio"] = float(c[k][ok].max()) if ok.any() else 0.0
+        s[k + "_pass_rate"] = float((c[k][ok] <= 1.0).mean()) if ok.any() else 1.0
+    s["qdd_free0_all_max_ratio"] = float(c["qdd_free0"].max())
+    return s
+
+
+def oracle_states(env, params, n_envs, n_steps, every, seed=0):
+    """Seeded initial states rolled out by the FP64 oracle; returns the states before every
+    `every`-th step and the actions applied there, stacked along the env axis."""
+    env = W.as_f32(env)
+    params = W.params_f32(params)
+    oe = O.OracleEnv(env)
+    root, dof = W.initial_state(env, n_envs, seed)
+    acts = W.actuation(env, n_envs, n_steps, seed)
+    roots, dofs, a = [], [], []
+    for t in range(n_steps):
+        if t % every == 0:
+            roots.append(root)
+            dofs.append(dof)
+            a.append(acts[t])
+        o = oe.step(params, root, dof, acts[t])
+        root, dof = o["root"], o["dof"]
+    return oe, np.concatenate(roots), np.concatenate(dofs), np.concatenate(a)
+
+
+def run(env, params, root, dof, act, oe=None, pos_tgt=None, device="cuda:0", fp64=False):
+    """One env-step of every given state on the GPU and in the oracle: the same FP32 state, controls,
+    model description and parameters on both sides."""
+    env = W.as_f32(env)
+    params = W.params_f32(params)
+    root32 = root.astype(np.float32).astype(np.float64)
+    dof32 = dof.astype(np.float32).astype(np.float64)
+    act32 = act.astype(np.float32).astype(np.float64)
+    pt32 = None if pos_tgt is None else pos_tgt.astype(np.float32).astype(np.float64)
+    oe = oe or O.OracleEnv(env)
+    model = ags.Model(env)
+    sim = ags.Sim([model], [0] * root.shape[0], params, device=device, debug=True, pd=pos_tgt is not None, fp64=fp64)
+    g = gpu_step(sim, env, root32, dof32, act32, pt32)
+    o = oe.step(params, root32, dof32, act32, pos_tgt=pt32, r_cap=g["row_key"].shape[2])
+    return g, o

@@ -1,0 +1,73 @@
+"""HIP path vs FP64 oracle, one env-step from identical FP32 states (see tests/parity.py)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2108_10470_amd import ags, workloads as W
+
+from . import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _report(name, summary):
+    print(name, json.dumps(summary), flush=True)
+    if os.path.isdir(OUT):
+        with open(os.path.join(OUT, "parity.jsonl"), "a") as f:
+            f.write(json.dumps({"case": name, **summary}) + "\n")
+
+
+def _assert_pass(s):
+    assert s["rows_mismatch_not_near"] == 0, s
+    for k in ("qdd_free", "q", "lambda"):
+        assert s[k + "_pass_rate"] == 1.0, (k, s)
+
+
+def test_pendulum_free_swing():
+    env = W.EnvSpec("pend", [W.pendulum()], [])
+    p = W.SimParams()
+    E = 16
+    root, dof = W.initial_state(env, E)
+    dof[:, 0, 0] = np.linspace(-2.5, 2.5, E)
+    dof[:, 0, 1] = np.linspace(3.0, -3.0, E)
+    g, o = PT.run(env, p, root, dof, np.zeros((E, 1)))
+    s = PT.summarize(PT.compare(env, p, g, o))
+    _report("pendulum", s)
+    _assert_pass(s)
+    # closed form of the oracle pin: qdd = -m g l_c sin q / I_pivot is what both sides must reproduce
+    assert np.all(g["row_count"] == 0)
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_humanoid_parity_from_oracle_states(fp64):
+    env = W.env_humanoid()
+    p = W.SimParams()
+    oe, root, dof, act = PT.oracle_states(env, p, n_envs=32, n_steps=120, every=8)
+    g, o = PT.run(env, p, root, dof, act, oe=oe, fp64=fp64)
+    c = PT.compare(env, p, g, o)
+    s = PT.summarize(c)
+    s["mean_rows"] = float(o["row_count"].mean())
+    _report("humanoid_" + ("fp64" if fp64 else "fp32"), s)
+    _assert_pass(s)
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_ant_parity_every_step(fp64):
+    """Ant-like quadruped, 64 envs, every one of 100 steps (states from the oracle rollout)."""
+    env = W.env_ant()
+    p = W.SimParams()
+    oe, root, dof, act = PT.oracle_states(env, p, n_envs=64, n_steps=100, every=1)
+    g, o = PT.run(env, p, root, dof, act, oe=oe, fp64=fp64)
+    c = PT.compare(env, p, g, o)
+    s = PT.summarize(c)
+    s["mean_rows"] = float(o["row_count"].mean())
+    _report("ant_" + ("fp64" if fp64 else "fp32"), s)
+    _assert_pass(s)

@@ -1,0 +1,72 @@
+"""Host-side checks of libags that need no GPU: it loads, exports every declared symbol, and its
+model compilation (host code only) agrees with the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2108_10470_amd import ags, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "ags.h")).read()
+    return sorted(set(re.findall(r"\b(ags_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(ags.LIB_PATH)
+    declared = _declared_functions()
+    assert len(declared) >= 12
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(ags.EXPORTED) == declared
+
+
+@pytest.mark.parametrize("make", [W.env_humanoid, W.env_ant, W.env_arm_box])
+def test_model_sizes_and_mass_props_match_oracle(make):
+    env = make()
+    m = ags.Model(env)
+    oe = O.OracleEnv(env)
+    assert m.info.n_dof == oe.n_dof == env.n_dof
+    assert m.info.n_v == oe.n_v == env.n_v
+    assert m.info.n_links == oe.n_bodies
+    assert m.info.n_slots == oe.n_slots
+    assert m.info.max_rows == oe.max_rows
+    gm, gc, gI = m.mass_props()
+    om, oc, oI = oe.mass_props()
+    np.testing.assert_allclose(gm, om, rtol=1e-6)
+    np.testing.assert_allclose(gc, oc, atol=1e-7)
+    np.testing.assert_allclose(gI, oI, rtol=1e-6, atol=1e-9)
+
+
+def test_humanoid_counts():
+    env = W.env_humanoid()
+    m = ags.Model(env)
+    assert (m.info.n_dof, m.info.n_v, m.info.n_links, m.info.n_slots) == (21, 27, 22, 26)
+    assert sum(l.shapes != [] for l in env.actors[0].links) == 13
+
+
+def test_model_errors_are_reported():
+    bad = W.Actor("bad", [W.Link("b", -1, "free", shapes=[W.Shape("sphere", (0.2, 0, 0), radius=0.1)])])
+    with pytest.raises(RuntimeError, match="centre of mass"):
+        ags.Model(W.EnvSpec("bad", [bad], []))
+    massless = W.Actor("m", [W.Link("base", -1, "fixed"), W.Link("l", 0, "revolute")])
+    with pytest.raises(RuntimeError, match="neither mass nor armature"):
+        ags.Model(W.EnvSpec("m", [massless], []))
+    order = W.Actor("o", [W.Link("base", -1, "fixed"), W.Link("l", 2, "revolute"), W.Link("k", 0, "revolute")])
+    with pytest.raises(RuntimeError, match="topological"):
+        ags.Model(W.EnvSpec("o", [order], []))
+
+
+def test_product_path_does_not_import_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2108_10470_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text and "oracle.h" not in text, f

@@ -224,8 +224,11 @@ def _random_state(env, seed, vscale=1.0):
 
 @pytest.mark.parametrize("make", [W.humanoid, W.ant, W.arm_with_gripper])
 def test_crba_rnea_aba_agree(make):
+    """CRBA + RNEA + Cholesky and ABA solve (M + diag(armature)) qdd = tau - C identically."""
     env = _env([make()], [])
     oe = O.OracleEnv(env)
+    arm = np.zeros(oe.n_v)
+    arm[oe.n_v - env.n_dof:] = [l.armature for l in env.actors[0].links[1:]]
     rng = np.random.default_rng(3)
     for seed in range(3):
         root, dof = _random_state(env, seed)
@@ -236,7 +239,7 @@ def test_crba_rnea_aba_agree(make):
         np.testing.assert_allclose(M, M.T, atol=1e-12)
         assert np.linalg.eigvalsh(M).min() > 0
         np.testing.assert_allclose(q1, q2, rtol=1e-10, atol=1e-10 * np.abs(q1).max())
-        np.testing.assert_allclose(M @ q1 + C, tau, atol=1e-9 * (1 + np.abs(tau).max()))
+        np.testing.assert_allclose((M + np.diag(arm)) @ q1 + C, tau, atol=1e-9 * (1 + np.abs(tau).max()))
 
 
 # --- Newton-Euler laws of the whole system from finite differences of kinematics only
@@ -297,7 +300,11 @@ def _system_velocity(env, root, dof):
     return np.array(qd)
 
 
-@pytest.mark.parametrize("make,grav", [(W.humanoid, True), (W.humanoid, False), (W.ant, True)])
+def _bare_humanoid():
+    return W.humanoid(armature=0.0, damping=0.0)
+
+
+@pytest.mark.parametrize("make,grav", [(_bare_humanoid, True), (_bare_humanoid, False), (W.ant, True)])
 def test_momentum_rate_matches_external_forces(make, grav):
     """d/dt (P, L_O) along the trajectory generated by the oracle's qdd equals the gravity wrench;
     internal joint torques cancel.  Momenta come from FK finite differences, not the oracle's algebra."""
@@ -333,7 +340,7 @@ def test_momentum_rate_matches_external_forces(make, grav):
 
 def test_energy_rate_equals_actuator_power():
     """d/dt (T + V) = tau . qd for a free humanoid (T from FK finite differences)."""
-    env = _env([W.humanoid()], [])
+    env = _env([_bare_humanoid()], [])
     oe = O.OracleEnv(env)
     m, com, Ic = oe.mass_props()
     p = _params()
