@@ -39,9 +39,11 @@ def parse():
     ap.add_argument("--envs", type=int, default=4096)
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both")
     ap.add_argument("--cpu-envs", type=int, default=4096, help="oracle sample: envs")
-    ap.add_argument("--cpu-steps", type=int, default=48, help="oracle sample: steps from the seeded start")
+    ap.add_argument("--cpu-steps", type=int, default=600, help="oracle sample: steps from the seeded start")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="skip the replay that measures mean active rows")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (scale reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -110,7 +112,7 @@ def cpu_baseline(env, params, n_envs, n_steps):
     dt = time.perf_counter() - t0
     return {"value": n_envs * n_steps / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_envs} humanoid envs x {n_steps} env-steps from the seeded standing start "
-                      f"(the fall and first ground contacts), FP64, {dt:.1f} s"}
+                      f"(standing, falling, lying), FP64, {dt:.1f} s"}
 
 
 def main():
@@ -131,6 +133,14 @@ def main():
     root0 = torch.from_numpy(root.reshape(-1, 13).astype(np.float32)).to("cuda:0")
     dof0 = torch.from_numpy(dof.reshape(-1, 2).astype(np.float32)).to("cuda:0")
     print(f"[bench] humanoid envs={E} steps={K} warmup={Wm}", file=sys.stderr, flush=True)
+    if args.calib_copy_mb:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     variants = {"both": [True, False], "fp64": [True], "fp32": [False]}[args.precision]
     res = {}

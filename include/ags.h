@@ -119,6 +119,7 @@ typedef struct {
   float limit_margin_rev;   /* same test for revolute limits (rad) */
   float limit_margin_pri;   /* and prismatic limits (m) */
   int32_t compute_fp64;     /* 0: compute in FP32; 1: compute in FP64 (tensors stay FP32) */
+  int32_t lanes_per_env;    /* 0: automatic; 32 or 64: lanes of a wavefront given to one environment */
 } ags_sim_params;
 
 typedef struct ags_sim ags_sim;
@@ -142,12 +143,15 @@ void ags_sim_destroy(ags_sim* sim);
  *   AGS_DEBUG_ROW_COUNT    (E, substeps)  int32          constraint rows per substep
  *   AGS_DEBUG_ROW_KEY      (E, substeps * max rows) int32  row keys (kind << 24 | a << 8 | b)
  *   AGS_DEBUG_ROW_LAMBDA   (E, substeps * max rows)      row impulses after the last sweep
+ *   AGS_DEBUG_PHASE_CYCLES (E, 10)  int64                shader-clock cycles per phase of the step (controls,
+ *                          forward sweep, inward sweep, outward sweep, v* sweep, narrow phase, rows,
+ *                          row responses, Gauss-Seidel, outputs), for profiling
  * Outputs and debug tensors are written only when bound.  N_A, N_D and N_B count actors, DOFs
  * and links of all environments. */
 enum {
   AGS_ROOT_STATE = 0, AGS_DOF_STATE, AGS_DOF_ACTUATION, AGS_DOF_POS_TARGET, AGS_DOF_VEL_TARGET,
   AGS_NET_CONTACT_FORCE, AGS_DOF_FORCE, AGS_DEBUG_QDD_FREE, AGS_DEBUG_ROW_COUNT, AGS_DEBUG_ROW_KEY,
-  AGS_DEBUG_ROW_LAMBDA, AGS_NUM_TENSORS
+  AGS_DEBUG_ROW_LAMBDA, AGS_DEBUG_PHASE_CYCLES, AGS_NUM_TENSORS
 };
 int ags_sim_tensor_shape(const ags_sim* sim, int32_t which, int64_t* rows, int64_t* cols);
 /* Bind a device pointer (NULL unbinds).  The memory must hold rows x cols elements and stay valid

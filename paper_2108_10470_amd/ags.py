@@ -20,7 +20,8 @@ JOINT = {"free": 0, "fixed": 1, "revolute": 2, "prismatic": 3}
 SHAPE = {"sphere": 0, "capsule": 1, "box": 2}
 
 ROOT_STATE, DOF_STATE, DOF_ACTUATION, DOF_POS_TARGET, DOF_VEL_TARGET, NET_CONTACT_FORCE, DOF_FORCE, \
-    DEBUG_QDD_FREE, DEBUG_ROW_COUNT, DEBUG_ROW_KEY, DEBUG_ROW_LAMBDA, NUM_TENSORS = range(12)
+    DEBUG_QDD_FREE, DEBUG_ROW_COUNT, DEBUG_ROW_KEY, DEBUG_ROW_LAMBDA, DEBUG_PHASE_CYCLES, NUM_TENSORS = range(13)
+PHASES = ["controls", "forward", "inward", "outward", "vstar", "narrow", "rows", "responses", "pgs", "outputs"]
 
 
 class LinkDesc(ctypes.Structure):
@@ -54,7 +55,8 @@ class SimParams(ctypes.Structure):
     _fields_ = [("dt", ctypes.c_float), ("substeps", ctypes.c_int32), ("gravity", ctypes.c_float * 3),
                 ("pgs_iters", ctypes.c_int32), ("mu", ctypes.c_float), ("baumgarte", ctypes.c_float),
                 ("contact_margin", ctypes.c_float), ("limit_margin_rev", ctypes.c_float),
-                ("limit_margin_pri", ctypes.c_float), ("compute_fp64", ctypes.c_int32)]
+                ("limit_margin_pri", ctypes.c_float), ("compute_fp64", ctypes.c_int32),
+                ("lanes_per_env", ctypes.c_int32)]
 
 
 _lib = None
@@ -146,16 +148,17 @@ class Model:
             self.h = None
 
 
-def sim_params(p, fp64: bool = False) -> SimParams:
+def sim_params(p, fp64: bool = False, lanes_per_env: int = 0) -> SimParams:
     return SimParams(p.dt, p.substeps, _f3(p.gravity), p.pgs_iters, p.mu, p.baumgarte, p.contact_margin,
-                     p.limit_margin_rev, p.limit_margin_pri, 1 if fp64 else 0)
+                     p.limit_margin_rev, p.limit_margin_pri, 1 if fp64 else 0, lanes_per_env)
 
 
 class Sim:
     """A batch of environments with its state and control tensors allocated by torch on `device`."""
 
     def __init__(self, models: Sequence[Model], env_model: Sequence[int], params, device="cuda:0",
-                 debug: bool = False, pd: bool = False, fp64: bool = False):
+                 debug: bool = False, pd: bool = False, fp64: bool = False, phase_cycles: bool = False,
+                 lanes_per_env: int = 0):
         self.models = list(models)
         self.params = params
         self.device = torch.device(device)
@@ -163,7 +166,7 @@ class Sim:
         handles = (ctypes.c_void_p * len(self.models))(*[m.h for m in self.models])
         ids = (ctypes.c_int32 * self.n_envs)(*[int(x) for x in env_model])
         h = ctypes.c_void_p()
-        self._p = sim_params(params, fp64)
+        self._p = sim_params(params, fp64, lanes_per_env)
         _check(lib().ags_sim_create(handles, len(self.models), ids, self.n_envs, ctypes.byref(self._p), ctypes.byref(h)),
                "ags_sim_create")
         self.h = h
@@ -183,6 +186,9 @@ class Sim:
         if pd:
             self.pos_target = self._alloc(DOF_POS_TARGET, torch.zeros(shapes[DOF_POS_TARGET][0], **f32))
             self.vel_target = self._alloc(DOF_VEL_TARGET, torch.zeros(shapes[DOF_VEL_TARGET][0], **f32))
+        if phase_cycles:
+            self.dbg_cycles = self._alloc(DEBUG_PHASE_CYCLES, torch.zeros(shapes[DEBUG_PHASE_CYCLES], dtype=torch.int64,
+                                                                          device=self.device))
         if debug:
             self.dbg_qdd = self._alloc(DEBUG_QDD_FREE, torch.zeros(shapes[DEBUG_QDD_FREE], **f32))
             self.dbg_rc = self._alloc(DEBUG_ROW_COUNT, torch.zeros(shapes[DEBUG_ROW_COUNT], dtype=torch.int32, device=self.device))

@@ -369,6 +369,7 @@ extern "C" int ags_model_mass_props(const ags_model* m, float* mass, float* com,
 // ---------------------------------------------------------------- simulation
 namespace {
 struct TypeDev {
+  int team = 64;
   DevModel dm{};
   Lds lds{};
   void* block = nullptr;       // device tables
@@ -378,20 +379,25 @@ struct TypeDev {
   long long scratch_stride = 0;  // elements of the compute type per env
 };
 
-Lds make_layout(const ags_model_info& info, int n_levels, int n_anc) {
-  (void)n_levels;
+Lds make_layout(const ags_model_info& info, int n_levels, int n_anc, int n_body_slot, int team) {
   Lds L{};
   int off = 0;
   auto take = [&](int words) {
     int o = off;
-    off += (words + 1) & ~1;  // keep 8-byte alignment
+    off += (words + 1) & ~1;  // keep 8-byte alignment of every array
     return o;
   };
   const int nl = info.n_links, na = info.n_actors, nd = info.n_dof, nv = info.n_v, ns = info.n_slots;
   const int rc = std::max(1, info.max_rows);
-  L.R = take(9 * nl); L.o = take(3 * nl); L.ax = take(3 * nl); L.v = take(6 * nl); L.c = take(6 * nl);
-  L.IA = take(21 * nl); L.pA = take(6 * nl); L.U = take(6 * nl); L.Dinv = take(nl); L.u = take(nl);
-  L.a = take(6 * nl); L.Ubar = take(6 * nl); L.F = take(3 * nl);
+  // model tables, shared by the environments of a workgroup
+  L.t_li = take(nl * LI_COLS); L.t_lev = take(n_levels + 1); L.t_links = take(nl); L.t_child = take(std::max(1, nl));
+  L.t_anc = take(std::max(1, n_anc)); L.t_dof = take(std::max(1, nd)); L.t_si = take(std::max(1, ns) * SI_COLS);
+  L.t_bsb = take(nl + 1); L.t_bs = take(std::max(1, n_body_slot)); L.t_ai = take(na * AI_COLS);
+  L.t_lf = take(nl * LF_COLS); L.t_sf = take(std::max(1, ns) * SF_COLS);
+  L.team_base = off;
+  // per environment, offsets relative to its region
+  off = 0;
+  L.o = take(3 * nl); L.ax = take(3 * nl); L.U = take(6 * nl); L.Dinv = take(nl); L.Ubar = take(6 * nl); L.F = take(3 * nl);
   L.L0 = take(27 * na);
   L.qj = take(std::max(1, nd)); L.qd = take(nv); L.tau = take(nv); L.arm = take(nv); L.qddf = take(nv); L.vstar = take(nv);
   L.root = take(13 * na);
@@ -400,10 +406,19 @@ Lds make_layout(const ags_model_info& info, int n_levels, int n_anc) {
   L.slotrow = take(std::max(1, ns)); L.act = take(std::max(1, ns));
   L.rkind = take(rc); L.rref = take(rc); L.rnorm = take(rc); L.rkey = take(rc); L.rbias = take(rc);
   L.rinvA = take(rc); L.rlam = take(rc);
-  L.wstride = nv | 1;
-  L.W = take(kTeam * L.wstride);
   L.misc = take(8);
-  L.total = off;
+  // dynamics-only arrays and the constraint-phase row chunks are never live together: one region
+  const int shared = off;
+  L.R = take(9 * nl); L.v = take(6 * nl); L.c = take(6 * nl); L.IA = take(21 * nl); L.pA = take(6 * nl);
+  L.a = take(6 * nl); L.u = take(nl);
+  const int dyn_end = off;
+  off = shared;
+  L.wstride = nv | 1;
+  L.W = take(team * L.wstride);
+  L.J = take(team * L.wstride);
+  off = std::max(off, dyn_end);
+  L.team_stride = off;
+  L.total = L.team_base + (kTeam / team) * L.team_stride;
   return L;
 }
 }  // namespace
@@ -470,7 +485,9 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     const ags_model* M = models[t];
     TypeDev T;
     T.n_envs = (int)lists[t].size();
-    T.lds = make_layout(M->info, M->n_levels, M->n_anc);
+    // lanes per environment: 32 (two environments per wavefront) when every per-lane loop fits
+    T.team = (p->lanes_per_env == 32 || (p->lanes_per_env == 0 && M->info.n_v <= 32)) && M->info.n_v <= 32 ? 32 : 64;
+    T.lds = make_layout(M->info, M->n_levels, M->n_anc, (int)M->body_slot.size(), T.team);
     // limit margins per joint type
     std::vector<double> lf = M->lf;
     for (int i = 0; i < M->info.n_links; ++i)
@@ -512,6 +529,7 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     D.n_levels = M->n_levels;
     D.n_anc = M->n_anc;
     D.r_cap = std::max(1, M->info.max_rows);
+    D.n_body_slot = (int)M->body_slot.size();
     D.li = (const int*)(b + offs[0]);
     D.level_begin = (const int*)(b + offs[1]);
     D.level_links = (const int*)(b + offs[2]);
@@ -528,7 +546,9 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     T.scratch_stride = 2ll * D.r_cap * std::max(1, D.n_v);
     T.scratch_stride = (T.scratch_stride + 63) & ~63ll;
     const size_t elem = p->compute_fp64 ? sizeof(double) : sizeof(float);
-    if ((err = hipMalloc(&T.scratch, (size_t)T.scratch_stride * T.n_envs * elem)) != hipSuccess) {
+    const int epw = kTeam / T.team;
+    const size_t padded = (size_t)((T.n_envs + epw - 1) / epw) * epw;
+    if ((err = hipMalloc(&T.scratch, (size_t)T.scratch_stride * padded * elem)) != hipSuccess) {
       S->types.push_back(T);
       ags_sim_destroy(S);
       return hip_fail(err, "sim: scratch");
@@ -539,7 +559,7 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
       ags_sim_destroy(S);
       return fail(AGS_E_ARG, "sim: model too large for one workgroup's LDS");
     }
-    if (lds_bytes > 64 * 1024 && (err = set_lds_limit(p->compute_fp64, lds_bytes)) != hipSuccess) {
+    if (lds_bytes > 64 * 1024 && (err = set_lds_limit(p->compute_fp64, T.team, lds_bytes)) != hipSuccess) {
       S->types.push_back(T);
       ags_sim_destroy(S);
       return hip_fail(err, "sim: LDS limit");
@@ -573,6 +593,7 @@ extern "C" int ags_sim_tensor_shape(const ags_sim* S, int32_t which, int64_t* ro
     case AGS_DEBUG_QDD_FREE: *rows = S->n_envs; *cols = (int64_t)sub * S->max_nv; break;
     case AGS_DEBUG_ROW_COUNT: *rows = S->n_envs; *cols = sub; break;
     case AGS_DEBUG_ROW_KEY: case AGS_DEBUG_ROW_LAMBDA: *rows = S->n_envs; *cols = (int64_t)sub * std::max(1, S->max_rows); break;
+    case AGS_DEBUG_PHASE_CYCLES: *rows = S->n_envs; *cols = kPhases; break;
     default: return fail(AGS_E_ARG, "unknown tensor");
   }
   return AGS_OK;
@@ -613,6 +634,7 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
     a.dbg_lam = rows_dbg ? (float*)S->bound[AGS_DEBUG_ROW_LAMBDA] : nullptr;
     a.dbg_row_stride = p.substeps * std::max(1, S->max_rows);
     a.dbg_row_sub = std::max(1, S->max_rows);
+    a.dbg_cycles = (long long*)S->bound[AGS_DEBUG_PHASE_CYCLES];
     a.scratch = T.scratch;
     a.scratch_stride = T.scratch_stride;
     a.dt = p.dt;
@@ -625,7 +647,7 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
     a.mc = p.contact_margin;
     a.substeps = p.substeps;
     a.iters = p.pgs_iters;
-    hipError_t e = launch_step(a, T.n_envs, p.compute_fp64, (hipStream_t)stream);
+    hipError_t e = launch_step(a, T.n_envs, p.compute_fp64, T.team, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "step: launch");
   }
   return AGS_OK;

@@ -11,6 +11,7 @@ constexpr int kMaxLinks = 64;
 constexpr int kMaxV = 64;       // generalized velocities per environment (one lane each in the solver)
 constexpr int kMaxSlots = 256;
 constexpr float kMinRowMass = 1e-6f;  // rows with J M~^-1 J^T below this are dropped (immovable)
+constexpr int kPhases = 10;           // controls, forward, inward, outward, v*, narrow, rows, responses, PGS, outputs
 
 // per-link integer table
 enum { LI_PARENT = 0, LI_JTYPE, LI_COL, LI_DOF, LI_ROOT, LI_CHILD_BEGIN, LI_CHILD_END, LI_ANC_BEGIN, LI_ANC_END,
@@ -29,6 +30,8 @@ enum { J_FREE = 0, J_FIXED = 1, J_REV = 2, J_PRI = 3 };
 
 // LDS layout of one environment's workgroup, offsets in 4-byte words
 struct Lds {
+  // model tables staged from global memory once per launch (ints, then compute-type floats)
+  int t_li, t_lev, t_links, t_child, t_anc, t_dof, t_si, t_bsb, t_bs, t_ai, t_lf, t_sf;
   int R, o, ax, v, c, IA, pA, U, Dinv, u, a, Ubar, F;  // per link
   int L0;                                             // per actor: packed Cholesky factor (21) + 1/diag (6)
   int qj, qd, tau, arm, qddf, vstar;                  // per DOF / column
@@ -36,13 +39,14 @@ struct Lds {
   int G;                                              // per ancestor pair
   int phi, n, x, t1, t2, slotrow, act;                // per slot
   int rkind, rref, rnorm, rkey, rbias, rinvA, rlam;   // per row
-  int W, wstride;                                     // 64-row chunk of W rows
+  int W, J, wstride;                                  // TEAM-row chunks of W and J rows
   int misc;                                           // a few ints
-  int total;
+  int team_base, team_stride;                         // per-environment region: base + team * stride
+  int total;                                          // words for all teams of a workgroup
 };
 
 struct DevModel {
-  int n_links, n_actors, n_dof, n_v, n_slots, n_levels, n_anc, r_cap;
+  int n_links, n_actors, n_dof, n_v, n_slots, n_levels, n_anc, r_cap, n_body_slot;
   const int* li;
   const double* lf;
   const int* level_begin;
@@ -77,14 +81,15 @@ struct StepArgs {
   int* dbg_key;
   float* dbg_lam;
   int dbg_row_stride, dbg_row_sub;  // per env, per substep (sim-wide maximum rows)
+  long long* dbg_cycles;            // per env: shader-clock cycles spent in each phase (kPhases)
   void* scratch;           // per env: J rows then W rows, r_cap x n_v each, in the compute type
   long long scratch_stride;
   double dt, h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
 };
 
-hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, hipStream_t stream);
-hipError_t set_lds_limit(int fp64, size_t bytes);
+hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStream_t stream);
+hipError_t set_lds_limit(int fp64, int team, size_t bytes);
 hipError_t launch_set_rows(float* dst, const float* src, const int* idx, int n, int n_actors, const int* table,
                            int field, int width, hipStream_t stream);
 

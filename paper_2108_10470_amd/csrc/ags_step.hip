@@ -67,9 +67,15 @@ template <typename R>
 __device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b) {
   return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
 }
-template <typename R, typename T>
-__device__ __forceinline__ V3<R> ld3(const T* p) {
+template <typename R, typename P>
+__device__ __forceinline__ V3<R> ld3(const P& p) {
   return {R(p[0]), R(p[1]), R(p[2])};
+}
+template <typename R, typename P>
+__device__ __forceinline__ void st3(const P& p, V3<R> v) {
+  p[0] = v.x;
+  p[1] = v.y;
+  p[2] = v.z;
 }
 template <typename R>
 __device__ __forceinline__ void st3(R* p, V3<R> v) {
@@ -78,13 +84,13 @@ __device__ __forceinline__ void st3(R* p, V3<R> v) {
   p[2] = v.z;
 }
 // 3x3 row-major helpers
-template <typename R>
-__device__ __forceinline__ V3<R> mv(const R* M, V3<R> v) {
+template <typename R, typename P>
+__device__ __forceinline__ V3<R> mv(const P& M, V3<R> v) {
   return {M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z,
           M[6] * v.x + M[7] * v.y + M[8] * v.z};
 }
-template <typename R>
-__device__ __forceinline__ V3<R> mtv(const R* M, V3<R> v) {
+template <typename R, typename P>
+__device__ __forceinline__ V3<R> mtv(const P& M, V3<R> v) {
   return {M[0] * v.x + M[3] * v.y + M[6] * v.z, M[1] * v.x + M[4] * v.y + M[7] * v.z,
           M[2] * v.x + M[5] * v.y + M[8] * v.z};
 }
@@ -94,8 +100,8 @@ __device__ __forceinline__ V3<R> symv(const R* S, V3<R> v) {
   return {S[0] * v.x + S[3] * v.y + S[4] * v.z, S[3] * v.x + S[1] * v.y + S[5] * v.z,
           S[4] * v.x + S[5] * v.y + S[2] * v.z};
 }
-template <typename R>
-__device__ __forceinline__ void mm3(const R* A, const R* B, R* C) {
+template <typename PA, typename PB, typename R>
+__device__ __forceinline__ void mm3(const PA& A, const PB& B, R* C) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -108,8 +114,8 @@ template <typename R>
 struct SI {
   R A[6], B[9], M[6];
 };
-template <typename R>
-__device__ __forceinline__ void si_load(SI<R>& I, const R* p) {
+template <typename R, typename P>
+__device__ __forceinline__ void si_load(SI<R>& I, const P& p) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) I.A[k] = p[k];
 #pragma unroll
@@ -117,8 +123,8 @@ __device__ __forceinline__ void si_load(SI<R>& I, const R* p) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) I.M[k] = p[15 + k];
 }
-template <typename R>
-__device__ __forceinline__ void si_store(const SI<R>& I, R* p) {
+template <typename R, typename P>
+__device__ __forceinline__ void si_store(const SI<R>& I, const P& p) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) p[k] = I.A[k];
 #pragma unroll
@@ -126,8 +132,8 @@ __device__ __forceinline__ void si_store(const SI<R>& I, R* p) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) p[15 + k] = I.M[k];
 }
-template <typename R>
-__device__ __forceinline__ void si_addload(SI<R>& I, const R* p) {
+template <typename R, typename P>
+__device__ __forceinline__ void si_addload(SI<R>& I, const P& p) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) I.A[k] += p[k];
 #pragma unroll
@@ -195,10 +201,59 @@ __device__ __forceinline__ R wave_sum(R x) {
   return x;
 }
 __device__ __forceinline__ unsigned long long lanes_below(int t) { return (1ull << t) - 1ull; }
+// ballot of one team (TEAM consecutive lanes starting at tm * TEAM), as a mask over its own lanes
+template <int TEAM>
+__device__ __forceinline__ unsigned long long team_ballot(int tm, int pred) {
+  const unsigned long long m = __ballot(pred);
+  if (TEAM == 64) return m;
+  return (m >> (tm * TEAM)) & ((1ull << TEAM) - 1ull);
+}
+// sum over the lanes of one team (butterfly within aligned groups of TEAM lanes)
+template <int TEAM, typename R>
+__device__ __forceinline__ R team_sum(R x) {
+#pragma unroll
+  for (int m = TEAM / 2; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+// value of x in lane l (l uniform across the wave)
+__device__ __forceinline__ int lane_read(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ float lane_read(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_read(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// value of x in lane r of this lane's team (r uniform); one readlane per team, then a select
+template <int TEAM, typename T>
+__device__ __forceinline__ T team_read(int tm, T x, int r) {
+  if (TEAM == 64) return lane_read(x, r);
+  T v = lane_read(x, r);
+#pragma unroll
+  for (int q = 1; q < 64 / TEAM; ++q) {
+    const T w = lane_read(x, q * TEAM + r);
+    v = tm == q ? w : v;
+  }
+  return v;
+}
+// x in the lane of this team given by the team-local index held in idx at team lane r
+template <int TEAM, typename T>
+__device__ __forceinline__ T team_read_at(T x, int idx, int r, int tm) {
+  if (TEAM == 64) return lane_read(x, lane_read(idx, r));
+  T v = lane_read(x, lane_read(idx, r));
+#pragma unroll
+  for (int q = 1; q < 64 / TEAM; ++q) {
+    const T w = lane_read(x, q * TEAM + lane_read(idx, q * TEAM + r));
+    v = tm == q ? w : v;
+  }
+  return v;
+}
 
 // Cholesky of a 6x6 SPD matrix (packed lower, index i(i+1)/2 + j) and the reciprocal diagonal
-template <typename R>
-__device__ void chol6(const SI<R>& K, R* L, R* dinv) {
+template <typename R, typename P>
+__device__ __forceinline__ void chol6(const SI<R>& K, const P& L, const P& dinv) {
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     R d = si_at(K, j, j);
@@ -217,8 +272,8 @@ __device__ void chol6(const SI<R>& K, R* L, R* dinv) {
     }
   }
 }
-template <typename R>
-__device__ void chol6_solve(const R* L, const R* dinv, R* x) {
+template <typename R, typename P>
+__device__ __forceinline__ void chol6_solve(const P& L, const P& dinv, R* x) {
 #pragma unroll
   for (int i = 0; i < 6; ++i) {
     R s = x[i];
@@ -270,32 +325,90 @@ __device__ __forceinline__ void tangents(V3<R> n, V3<R>& t1, V3<R>& t2) {
   t2 = cross(n, t1);
 }
 
-// LDS views of one environment (layout offsets are in units of R)
-template <typename R>
+// LDS array of one environment.  The EPW environments of a wavefront are interleaved element by
+// element (element k of team tm sits at base[k * EPW + tm]) so that every array base is the same for
+// the whole wavefront and only the team index varies per lane.  ints occupy compute-type slots.
+extern __shared__ __align__(16) unsigned char g_lds[];
+
+template <typename T, int EPW, int SLOT = 1>
+struct SP {
+  int off;  // element offset of the array base (uniform)
+  int tm;   // team of this lane
+  __device__ __forceinline__ T& operator[](int k) const {
+    return reinterpret_cast<T*>(g_lds)[(off + k * EPW + tm) * SLOT];
+  }
+  __device__ __forceinline__ SP operator+(int k) const { return {off + k * EPW, tm}; }
+};
+
+template <typename R, int EPW>
 struct Ctx {
-  R *Rm, *o, *ax, *v, *c, *IA, *pA, *U, *Dinv, *u, *a, *Ubar, *F, *L0;
-  R *qj, *qd, *tau, *arm, *qddf, *vstar, *root, *G;
-  R *phi, *n, *x, *t1, *t2;
-  int *slotrow, *act;
-  int *rkind, *rref, *rnorm, *rkey;
-  R *rbias, *rinvA, *rlam, *W;
-  int* misc;
-  __device__ void init(R* smem, const Lds& L) {
-    Rm = smem + L.R; o = smem + L.o; ax = smem + L.ax; v = smem + L.v; c = smem + L.c;
-    IA = smem + L.IA; pA = smem + L.pA; U = smem + L.U; Dinv = smem + L.Dinv; u = smem + L.u;
-    a = smem + L.a; Ubar = smem + L.Ubar; F = smem + L.F; L0 = smem + L.L0;
-    qj = smem + L.qj; qd = smem + L.qd; tau = smem + L.tau; arm = smem + L.arm; qddf = smem + L.qddf;
-    vstar = smem + L.vstar; root = smem + L.root; G = smem + L.G;
-    phi = smem + L.phi; n = smem + L.n; x = smem + L.x; t1 = smem + L.t1; t2 = smem + L.t2;
-    slotrow = reinterpret_cast<int*>(smem + L.slotrow); act = reinterpret_cast<int*>(smem + L.act);
-    rkind = reinterpret_cast<int*>(smem + L.rkind); rref = reinterpret_cast<int*>(smem + L.rref);
-    rnorm = reinterpret_cast<int*>(smem + L.rnorm); rkey = reinterpret_cast<int*>(smem + L.rkey);
-    rbias = smem + L.rbias; rinvA = smem + L.rinvA; rlam = smem + L.rlam; W = smem + L.W;
-    misc = reinterpret_cast<int*>(smem + L.misc);
+  using F = SP<R, EPW>;
+  using I = SP<int, EPW * (int)(sizeof(R) / sizeof(int)), 1>;
+  F Rm, o, ax, v, c, IA, pA, U, Dinv, u, a, Ubar, F_, L0;
+  F qj, qd, tau, arm, qddf, vstar, root, G;
+  F phi, n, x, t1, t2;
+  I slotrow, act;
+  I rkind, rref, rnorm, rkey;
+  F rbias, rinvA, rlam, W, J;
+  I misc;
+  __device__ __forceinline__ void init(int base, const Lds& L, int tm) {
+    // base: offset of the per-environment region in units of R
+    auto f = [&](int off) { return F{base + off * EPW, tm}; };
+    auto i = [&](int off) { return I{(base + off * EPW) * (int)(sizeof(R) / sizeof(int)), tm}; };
+    Rm = f(L.R); o = f(L.o); ax = f(L.ax); v = f(L.v); c = f(L.c);
+    IA = f(L.IA); pA = f(L.pA); U = f(L.U); Dinv = f(L.Dinv); u = f(L.u);
+    a = f(L.a); Ubar = f(L.Ubar); F_ = f(L.F); L0 = f(L.L0);
+    qj = f(L.qj); qd = f(L.qd); tau = f(L.tau); arm = f(L.arm); qddf = f(L.qddf);
+    vstar = f(L.vstar); root = f(L.root); G = f(L.G);
+    phi = f(L.phi); n = f(L.n); x = f(L.x); t1 = f(L.t1); t2 = f(L.t2);
+    slotrow = i(L.slotrow); act = i(L.act);
+    rkind = i(L.rkind); rref = i(L.rref); rnorm = i(L.rnorm); rkey = i(L.rkey);
+    rbias = f(L.rbias); rinvA = f(L.rinvA); rlam = f(L.rlam); W = f(L.W); J = f(L.J);
+    misc = i(L.misc);
   }
 };
 
-__device__ __forceinline__ int actor_of_root(const DevModel& M, int link) {
+// Model tables of one environment template, as seen by the kernel (LDS copies of the global tables)
+template <typename R>
+struct Tab {
+  int n_links, n_actors, n_dof, n_v, n_slots, n_levels, n_anc, r_cap;
+  const int *li, *level_begin, *level_links, *children, *anc_link, *dof_link, *si, *body_slot_begin, *body_slot, *ai;
+  const R *lf, *sf;
+};
+
+// Copies the model tables into this workgroup's LDS (all lanes cooperate) and returns the view.
+template <typename R>
+__device__ __forceinline__ Tab<R> stage_tables(const DevModel& G, R* smem, const Lds& L, int t, int nthreads) {
+  auto copy_i = [&](int off, const int* src, int n) {
+    int* dst = reinterpret_cast<int*>(smem + off);
+    for (int k = t; k < n; k += nthreads) dst[k] = src[k];
+    return (const int*)dst;
+  };
+  auto copy_r = [&](int off, const double* src, int n) {
+    R* dst = smem + off;
+    for (int k = t; k < n; k += nthreads) dst[k] = R(src[k]);
+    return (const R*)dst;
+  };
+  Tab<R> T;
+  T.n_links = G.n_links; T.n_actors = G.n_actors; T.n_dof = G.n_dof; T.n_v = G.n_v; T.n_slots = G.n_slots;
+  T.n_levels = G.n_levels; T.n_anc = G.n_anc; T.r_cap = G.r_cap;
+  T.li = copy_i(L.t_li, G.li, G.n_links * LI_COLS);
+  T.level_begin = copy_i(L.t_lev, G.level_begin, G.n_levels + 1);
+  T.level_links = copy_i(L.t_links, G.level_links, G.n_links);
+  T.children = copy_i(L.t_child, G.children, G.n_links - G.n_actors);
+  T.anc_link = copy_i(L.t_anc, G.anc_link, G.n_anc);
+  T.dof_link = copy_i(L.t_dof, G.dof_link, G.n_dof);
+  T.si = copy_i(L.t_si, G.si, G.n_slots * SI_COLS);
+  T.body_slot_begin = copy_i(L.t_bsb, G.body_slot_begin, G.n_links + 1);
+  T.body_slot = copy_i(L.t_bs, G.body_slot, G.n_body_slot);
+  T.ai = copy_i(L.t_ai, G.ai, G.n_actors * AI_COLS);
+  T.lf = copy_r(L.t_lf, G.lf, G.n_links * LF_COLS);
+  T.sf = copy_r(L.t_sf, G.sf, G.n_slots * SF_COLS);
+  return T;
+}
+
+template <typename R>
+__device__ __forceinline__ int actor_of_root(const Tab<R>& M, int link) {
   int a = 0;
   for (int k = 0; k < M.n_actors; ++k)
     if (M.ai[k * AI_COLS + AI_ROOT] == link) a = k;
@@ -305,8 +418,9 @@ __device__ __forceinline__ int actor_of_root(const DevModel& M, int link) {
 // Adds the joint loads of one unit test load to Wrow (u_k at each joint column on the path of link k)
 // and the resulting bias force at a free root ([n; f] in the root's 6 columns).  The load is a spatial
 // force given by its bias contribution (pn, pf) = -f about o_k, or a joint force tau0 at link k.
-template <typename R>
-__device__ void unit_load_inward(const DevModel& M, const Ctx<R>& s, int k, V3<R> pn, V3<R> pf, R tau0, R* Wrow) {
+template <typename R, int EPW, typename WP>
+__device__ __forceinline__ void unit_load_inward(const Tab<R>& M, const Ctx<R, EPW>& s, int k, V3<R> pn, V3<R> pf, R tau0,
+                                 const WP& Wrow) {
   while (true) {
     const int* li = M.li + k * LI_COLS;
     const int jt = li[LI_JTYPE];
@@ -333,8 +447,9 @@ __device__ void unit_load_inward(const DevModel& M, const Ctx<R>& s, int k, V3<R
 
 // Row of a point load along d at point x on link k (sign +-1): adds J entries to Jrow when non-null and
 // returns sum_j J_j Wrow_j when Wrow is non-null.
-template <typename R>
-__device__ R point_row(const DevModel& M, const Ctx<R>& s, int k, V3<R> x, V3<R> d, R sign, R* Jrow, const R* Wrow) {
+template <typename R, int EPW, typename JP, typename WP>
+__device__ __forceinline__ R point_row(const Tab<R>& M, const Ctx<R, EPW>& s, int k, V3<R> x, V3<R> d, R sign, const JP& Jrow,
+                       const WP& Wrow, bool want_j, bool want_w) {
   R acc = R(0);
   while (true) {
     const int* li = M.li + k * LI_COLS;
@@ -346,16 +461,16 @@ __device__ R point_row(const DevModel& M, const Ctx<R>& s, int k, V3<R> x, V3<R>
       const R j6[6] = {d.x, d.y, d.z, mo.x, mo.y, mo.z};
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        if (Jrow) Jrow[c + q] += sign * j6[q];
-        if (Wrow) acc += sign * j6[q] * Wrow[c + q];
+        if (want_j) Jrow[c + q] += sign * j6[q];
+        if (want_w) acc += sign * j6[q] * Wrow[c + q];
       }
       break;
     }
     const V3<R> ax = ld3<R>(s.ax + 3 * k);
     const R jv = jt == J_REV ? dot(ax, cross(sub(x, ld3<R>(s.o + 3 * k)), d)) : dot(ax, d);
     const int c = li[LI_COL];
-    if (Jrow) Jrow[c] += sign * jv;
-    if (Wrow) acc += sign * jv * Wrow[c];
+    if (want_j) Jrow[c] += sign * jv;
+    if (want_w) acc += sign * jv * Wrow[c];
     k = li[LI_PARENT];
   }
   return acc;
@@ -363,34 +478,39 @@ __device__ R point_row(const DevModel& M, const Ctx<R>& s, int k, V3<R> x, V3<R>
 
 }  // namespace
 
-template <typename R>
-__global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* smem = reinterpret_cast<R*>(smem_raw);
-  const DevModel& M = P.m;
+template <typename R, int TEAM>
+__global__ __launch_bounds__(64) void step_kernel(StepArgs P, int n_envs) {
+  R* smem = reinterpret_cast<R*>(g_lds);
   const Lds& L = P.lds;
-  const int t = threadIdx.x;
-  const int env = P.env_list[blockIdx.x];
-  Ctx<R> s;
-  s.init(smem, L);
+  constexpr int EPW = kTeam / TEAM;  // environments per wavefront
+  const int t = threadIdx.x;         // lane in the wavefront
+  const int tm = EPW == 1 ? 0 : t / TEAM;  // team (environment slot) of this lane
+  const int tt = EPW == 1 ? t : t % TEAM;  // lane within the team
+  const int gidx = blockIdx.x * EPW + tm;
+  const bool valid = gidx < n_envs;  // the last wavefront's spare teams recompute an env but write nothing
+  const int env = P.env_list[valid ? gidx : n_envs - 1];
+  const Tab<R> M = stage_tables<R>(P.m, smem, L, t, kTeam);
+  Ctx<R, EPW> s;
+  s.init(L.team_base, L, tm);
+  __syncthreads();
 
   const int nl = M.n_links, nd = M.n_dof, nv = M.n_v, ns = M.n_slots, na = M.n_actors;
   const int abase = P.env_actor_base[env], dbase = P.env_dof_base[env], bbase = P.env_body_base[env];
   const R h = R(P.h);
   const V3<R> grav = mk(R(P.gx), R(P.gy), R(P.gz));
-  R* Jg = reinterpret_cast<R*>(P.scratch) + (long long)blockIdx.x * P.scratch_stride;
+  R* Jg = reinterpret_cast<R*>(P.scratch) + (long long)gidx * P.scratch_stride;
   R* Wg = Jg + (long long)M.r_cap * nv;
 
   // ---------------------------------------------------------------- load state
-  for (int k = t; k < 13 * na; k += kTeam) s.root[k] = R(P.root_state[(long long)abase * 13 + k]);
-  for (int j = t; j < nd; j += kTeam) {
+  for (int k = tt; k < 13 * na; k += TEAM) s.root[k] = R(P.root_state[(long long)abase * 13 + k]);
+  for (int j = tt; j < nd; j += TEAM) {
     const int lk = M.dof_link[j];
     s.qj[j] = R(P.dof_state[2ll * (dbase + j)]);
     s.qd[M.li[lk * LI_COLS + LI_COL]] = R(P.dof_state[2ll * (dbase + j) + 1]);
   }
-  for (int k = t; k < 3 * nl; k += kTeam) s.F[k] = R(0);
+  for (int k = tt; k < 3 * nl; k += TEAM) s.F_[k] = R(0);
   __syncthreads();
-  for (int k = t; k < na; k += kTeam) {
+  for (int k = tt; k < na; k += TEAM) {
     const int* ai = M.ai + k * AI_COLS;
     if (!ai[AI_FIXED])
       for (int q = 0; q < 6; ++q) s.qd[ai[AI_COL] + q] = s.root[13 * k + 7 + q];
@@ -398,14 +518,26 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
   R dof_force_acc = R(0);
   __syncthreads();
   const V3<R> origin = ld3<R>(s.root);
+  // optional per-phase clock accounting (lane 0; only when the debug tensor is bound)
+  long long cyc[kPhases] = {0};
+  int cur_phase = -1;
+  long long t_mark = 0;
+#define PHASE_MARK(ph)                                              \
+  if (P.dbg_cycles) {                                               \
+    const long long now = (long long)clock64();                     \
+    if (cur_phase >= 0) cyc[cur_phase] += now - t_mark;             \
+    cur_phase = (ph);                                               \
+    t_mark = now;                                                   \
+  }
 
   for (int sub_i = 0; sub_i < P.substeps; ++sub_i) {
+    PHASE_MARK(0);
     // ---------------------------------------------------- controls: actuation + implicit PD drive
     // the drive kp (q* - q+) + kd (qd* - qd+) at the end of the substep splits into an explicit part
     // and the armature h kd + h^2 kp added to the joint's diagonal of M~
-    for (int j = t; j < nd; j += kTeam) {
+    for (int j = tt; j < nd; j += TEAM) {
       const int lk = M.dof_link[j];
-      const double* lf = M.lf + lk * LF_COLS;
+      const R* lf = M.lf + lk * LF_COLS;
       const int c = M.li[lk * LI_COLS + LI_COL];
       const R pt = P.pos_tgt ? R(P.pos_tgt[dbase + j]) : R(0);
       const R vt = P.vel_tgt ? R(P.vel_tgt[dbase + j]) : R(0);
@@ -415,18 +547,19 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
     }
     __syncthreads();
 
+    PHASE_MARK(1);
     // ---------------------------------------------------- forward sweep by depth
     for (int d = 0; d < M.n_levels; ++d) {
-      for (int idx = M.level_begin[d] + t; idx < M.level_begin[d + 1]; idx += kTeam) {
+      for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
         const int* li = M.li + i * LI_COLS;
-        const double* lf = M.lf + i * LF_COLS;
+        const R* lf = M.lf + i * LF_COLS;
         const int jt = li[LI_JTYPE];
         R Rw[9];
         V3<R> o, w, vl, ca = mk(R(0), R(0), R(0)), cl = mk(R(0), R(0), R(0)), ax = mk(R(0), R(0), R(0));
         if (jt == J_FREE || jt == J_FIXED) {
           // root pose from the root state (quaternion xyzw, normalised on read)
-          const R* rs = s.root + 13 * actor_of_root(M, i);
+          const auto rs = s.root + 13 * actor_of_root(M, i);
           R qx = rs[3], qy = rs[4], qz = rs[5], qw = rs[6];
           const R inv = rsqrt_(qx * qx + qy * qy + qz * qz + qw * qw);
           qx *= inv; qy *= inv; qz *= inv; qw *= inv;
@@ -445,7 +578,7 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
           }
         } else {
           const int p = li[LI_PARENT];
-          const R* Rp = s.Rm + 9 * p;
+          const auto Rp = s.Rm + 9 * p;
           const V3<R> axl = ld3<R>(lf + LF_AXIS);
           V3<R> tl = ld3<R>(lf + LF_ANCHOR);
           const R q = s.qj[li[LI_DOF]], qd = s.qd[li[LI_COL]];
@@ -475,8 +608,8 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
         // spatial inertia about o (world axes): A = Ic_w + m (|d|^2 1 - d d^T), B = m d^, M = m 1
         const R m = R(lf[LF_MASS]);
         const V3<R> d = mv(Rw, ld3<R>(lf + LF_COM));
-        const double* Icl = lf + LF_IC;
-        const R Ic[9] = {R(Icl[0]), R(Icl[3]), R(Icl[4]), R(Icl[3]), R(Icl[1]), R(Icl[5]), R(Icl[4]), R(Icl[5]), R(Icl[2])};
+        const R* Icl = lf + LF_IC;
+        const R Ic[9] = {Icl[0], Icl[3], Icl[4], Icl[3], Icl[1], Icl[5], Icl[4], Icl[5], Icl[2]};
         R T[9], Iw[9];
         mm3(Rw, Ic, T);
 #pragma unroll
@@ -517,9 +650,10 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
       __syncthreads();
     }
 
+    PHASE_MARK(2);
     // ---------------------------------------------------- ABA inward sweep (deepest level first)
     for (int d = M.n_levels - 1; d >= 0; --d) {
-      for (int idx = M.level_begin[d] + t; idx < M.level_begin[d + 1]; idx += kTeam) {
+      for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
         const int* li = M.li + i * LI_COLS;
         const int jt = li[LI_JTYPE];
@@ -588,9 +722,10 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
       __syncthreads();
     }
 
+    PHASE_MARK(3);
     // ---------------------------------------------------- root solve and ABA outward sweep
     for (int d = 0; d < M.n_levels; ++d) {
-      for (int idx = M.level_begin[d] + t; idx < M.level_begin[d + 1]; idx += kTeam) {
+      for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
         const int* li = M.li + i * LI_COLS;
         const int jt = li[LI_JTYPE];
@@ -628,15 +763,16 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
       }
       __syncthreads();
     }
-    for (int c = t; c < nv; c += kTeam) s.vstar[c] = s.qd[c] + h * s.qddf[c];
-    if (P.dbg_qdd)
-      for (int c = t; c < nv; c += kTeam)
+    for (int c = tt; c < nv; c += TEAM) s.vstar[c] = s.qd[c] + h * s.qddf[c];
+    if (P.dbg_qdd && valid)
+      for (int c = tt; c < nv; c += TEAM)
         P.dbg_qdd[(long long)env * P.dbg_qdd_stride + sub_i * P.dbg_qdd_sub + c] = float(s.qddf[c]);
     __syncthreads();
 
+    PHASE_MARK(4);
     // ---------------------------------------------------- link velocities under v*, U about roots, G table
     for (int d = 0; d < M.n_levels; ++d) {
-      for (int idx = M.level_begin[d] + t; idx < M.level_begin[d + 1]; idx += kTeam) {
+      for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
         const int* li = M.li + i * LI_COLS;
         const int jt = li[LI_JTYPE];
@@ -674,12 +810,13 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
       __syncthreads();
     }
 
+    PHASE_MARK(5);
     // ---------------------------------------------------- narrow phase and activation (one slot per lane)
-    for (int sb = 0; sb < ns; sb += kTeam) {
-      const int sl = sb + t;
+    for (int sb = 0; sb < ns; sb += TEAM) {
+      const int sl = sb + tt;
       if (sl < ns) {
         const int* si = M.si + sl * SI_COLS;
-        const double* sf = M.sf + sl * SF_COLS;
+        const R* sf = M.sf + sl * SF_COLS;
         const int ka = si[SI_LINK_A], kb = si[SI_LINK_B];
         const R rad = R(sf[SF_R]);
         const V3<R> xc = add(ld3<R>(s.o + 3 * ka), mv(s.Rm + 9 * ka, ld3<R>(sf + SF_P)));
@@ -695,7 +832,7 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
           x = xc;
         } else {
           // sphere against box: closest point, or the face of least penetration when inside
-          const R* Rb = s.Rm + 9 * kb;
+          const auto Rb = s.Rm + 9 * kb;
           const V3<R> cb = add(ld3<R>(s.o + 3 * kb), mv(Rb, ld3<R>(sf + SF_BOXC)));
           const V3<R> hb = ld3<R>(sf + SF_HALF);
           const V3<R> xl = mtv(Rb, sub(xc, cb));
@@ -736,16 +873,17 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
     }
     __syncthreads();
 
+    PHASE_MARK(6);
     // ---------------------------------------------------- constraint rows: limits (by DOF), then contacts
     {
       int running = 0;
-      for (int jb = 0; jb < nd; jb += kTeam) {
-        const int j = jb + t;
+      for (int jb = 0; jb < nd; jb += TEAM) {
+        const int j = jb + tt;
         int alo = 0, ahi = 0;
         R glo = R(0), ghi = R(0);
         if (j < nd) {
           const int lk = M.dof_link[j];
-          const double* lf = M.lf + lk * LF_COLS;
+          const R* lf = M.lf + lk * LF_COLS;
           const R vs = s.vstar[M.li[lk * LI_COLS + LI_COL]];
           const R ml = R(lf[LF_ML]), q = s.qj[j];
           if (isfinite(lf[LF_LO])) {
@@ -757,8 +895,8 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
             ahi = min_(ghi, ghi - h * vs) < ml;
           }
         }
-        const unsigned long long mlo = __ballot(alo), mhi = __ballot(ahi);
-        const int base = running + __popcll(mlo & lanes_below(t)) + __popcll(mhi & lanes_below(t));
+        const unsigned long long mlo = team_ballot<TEAM>(tm, alo), mhi = team_ballot<TEAM>(tm, ahi);
+        const int base = running + __popcll(mlo & lanes_below(tt)) + __popcll(mhi & lanes_below(tt));
         if (alo) {
           s.rkind[base] = 1; s.rref[base] = j; s.rnorm[base] = -1; s.rkey[base] = (1 << 24) | (j << 8);
           s.rbias[base] = glo >= R(0) ? glo / h : R(P.beta) * glo / h;
@@ -770,11 +908,11 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
         }
         running += __popcll(mlo) + __popcll(mhi);
       }
-      for (int sb = 0; sb < ns; sb += kTeam) {
-        const int sl = sb + t;
+      for (int sb = 0; sb < ns; sb += TEAM) {
+        const int sl = sb + tt;
         const int a = sl < ns ? s.act[sl] : 0;
-        const unsigned long long m = __ballot(a);
-        const int base = running + 3 * __popcll(m & lanes_below(t));
+        const unsigned long long m = team_ballot<TEAM>(tm, a);
+        const int base = running + 3 * __popcll(m & lanes_below(tt));
         if (sl < ns) s.slotrow[sl] = a ? base : -1;
         if (a) {
           const int key = M.si[sl * SI_COLS + SI_KEY];
@@ -789,35 +927,47 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
         }
         running += 3 * __popcll(m);
       }
-      if (t == 0) s.misc[0] = running;
+      if (tt == 0) s.misc[0] = running;
     }
     __syncthreads();
     const int Rn = s.misc[0];
 
+    PHASE_MARK(7);
     // ---------------------------------------------------- row Jacobians and responses W_r = M~^-1 J_r^T
-    for (int k = t; k < Rn * nv; k += kTeam) Jg[k] = R(0);
+    // Up to 64 rows (one per lane) keep J and W in LDS and are solved in registers below; more rows go
+    // through global scratch.
+    const bool fast = Rn <= TEAM;
+    if (!fast)
+      for (int k = tt; k < Rn * nv; k += TEAM) Jg[k] = R(0);
     __syncthreads();
-    for (int rb = 0; rb < Rn; rb += kTeam) {
-      const int r = rb + t;
-      R* Wrow = s.W + t * L.wstride;
+    for (int rb = 0; rb < Rn; rb += TEAM) {
+      const int r = rb + tt;
+      const auto Wrow = s.W + tt * L.wstride;
+      const auto JrowL = s.J + tt * L.wstride;
+      R* const JrowG = Jg + (long long)r * nv;
       for (int c = 0; c < nv; ++c) Wrow[c] = R(0);
+      if (fast)
+        for (int c = 0; c < nv; ++c) JrowL[c] = R(0);
       if (r < Rn) {
         const int kind = s.rkind[r];
-        R* Jrow = Jg + (long long)r * nv;
         if (kind <= 2) {
           const int lk = M.dof_link[s.rref[r]];
           const R sg = kind == 1 ? R(1) : R(-1);
-          Jrow[M.li[lk * LI_COLS + LI_COL]] = sg;
+          if (fast) JrowL[M.li[lk * LI_COLS + LI_COL]] = sg;
+          else JrowG[M.li[lk * LI_COLS + LI_COL]] = sg;
           unit_load_inward(M, s, lk, mk(R(0), R(0), R(0)), mk(R(0), R(0), R(0)), sg, Wrow);
         } else {
           const int sl = s.rref[r];
-          const R* dp = kind == 3 ? s.n : (kind == 4 ? s.t1 : s.t2);
+          auto dp = s.n;
+          dp.off = kind == 3 ? s.n.off : (kind == 4 ? s.t1.off : s.t2.off);
           const V3<R> dd = ld3<R>(dp + 3 * sl), x = ld3<R>(s.x + 3 * sl);
           const int ka = M.si[sl * SI_COLS + SI_LINK_A], kb = M.si[sl * SI_COLS + SI_LINK_B];
-          point_row(M, s, ka, x, dd, R(1), Jrow, (const R*)nullptr);
+          if (fast) point_row(M, s, ka, x, dd, R(1), JrowL, Wrow, true, false);
+          else point_row(M, s, ka, x, dd, R(1), JrowG, Wrow, true, false);
           unit_load_inward(M, s, ka, mul(cross(sub(x, ld3<R>(s.o + 3 * ka)), dd), R(-1)), mul(dd, R(-1)), R(0), Wrow);
           if (kb >= 0) {
-            point_row(M, s, kb, x, dd, R(-1), Jrow, (const R*)nullptr);
+            if (fast) point_row(M, s, kb, x, dd, R(-1), JrowL, Wrow, true, false);
+            else point_row(M, s, kb, x, dd, R(-1), JrowG, Wrow, true, false);
             unit_load_inward(M, s, kb, cross(sub(x, ld3<R>(s.o + 3 * kb)), dd), dd, R(0), Wrow);
           }
         }
@@ -841,7 +991,7 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
           R acc = R(0);
           const int rc = li[LI_ROOTCOL];
           if (rc >= 0) {
-            const R* ub = s.Ubar + 6 * i;
+            const auto ub = s.Ubar + 6 * i;
             acc = ub[0] * Wrow[rc + 3] + ub[1] * Wrow[rc + 4] + ub[2] * Wrow[rc + 5] + ub[3] * Wrow[rc + 0] +
                   ub[4] * Wrow[rc + 1] + ub[5] * Wrow[rc + 2];
           }
@@ -857,57 +1007,115 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
           A = (kind == 1 ? R(1) : R(-1)) * Wrow[M.li[lk * LI_COLS + LI_COL]];
         } else {
           const int sl = s.rref[r];
-          const R* dp = kind == 3 ? s.n : (kind == 4 ? s.t1 : s.t2);
+          auto dp = s.n;
+          dp.off = kind == 3 ? s.n.off : (kind == 4 ? s.t1.off : s.t2.off);
           const V3<R> dd = ld3<R>(dp + 3 * sl), x = ld3<R>(s.x + 3 * sl);
           const int ka = M.si[sl * SI_COLS + SI_LINK_A], kb = M.si[sl * SI_COLS + SI_LINK_B];
-          A = point_row(M, s, ka, x, dd, R(1), (R*)nullptr, Wrow);
-          if (kb >= 0) A += point_row(M, s, kb, x, dd, R(-1), (R*)nullptr, Wrow);
+          A = point_row(M, s, ka, x, dd, R(1), Wrow, Wrow, false, true);
+          if (kb >= 0) A += point_row(M, s, kb, x, dd, R(-1), Wrow, Wrow, false, true);
         }
         s.rinvA[r] = A >= R(kMinRowMass) ? R(1) / A : R(0);
         s.rlam[r] = R(0);
       }
       __syncthreads();
-      const int rows_here = min(kTeam, Rn - rb);
-      for (int q = 0; q < rows_here; ++q)
-        for (int c = t; c < nv; c += kTeam) Wg[(long long)(rb + q) * nv + c] = s.W[q * L.wstride + c];
-      __syncthreads();
+      if (!fast) {
+        const int rows_here = min(TEAM, Rn - rb);
+        for (int q = 0; q < rows_here; ++q)
+          for (int c = tt; c < nv; c += TEAM) Wg[(long long)(rb + q) * nv + c] = s.W[q * L.wstride + c];
+        __syncthreads();
+      }
     }
-    for (int r = t; r < Rn; r += kTeam)  // friction rows of a dropped normal row are dropped too
+    for (int r = tt; r < Rn; r += TEAM)  // friction rows of a dropped normal row are dropped too
       if (s.rkind[r] >= 4 && s.rinvA[s.rnorm[r]] == R(0)) s.rinvA[r] = R(0);
     __syncthreads();
 
-    // ---------------------------------------------------- projected Gauss-Seidel, lanes over velocity columns
-    R vj = t < nv ? s.vstar[t] : R(0);
+    PHASE_MARK(8);
+    // ---------------------------------------------------- projected Gauss-Seidel
     const R mu = R(P.mu);
-    for (int it = 0; it < P.iters; ++it) {
-      for (int r = 0; r < Rn; ++r) {
-        const R invA = s.rinvA[r];
-        if (invA == R(0)) continue;
-        const R Jr = t < nv ? Jg[(long long)r * nv + t] : R(0);
-        const R Wr = t < nv ? Wg[(long long)r * nv + t] : R(0);
-        const R res = wave_sum(Jr * vj) + s.rbias[r];
-        const R lam = s.rlam[r];
-        R nlam = lam - res * invA;
-        if (s.rkind[r] >= 4) {
-          const R hi = mu * s.rlam[s.rnorm[r]];
-          nlam = min_(max_(nlam, -hi), hi);
-        } else {
-          nlam = max_(nlam, R(0));
+    R vj;
+    if (fast) {
+      // Delassus form, one row per lane: lane k holds y_k = J_k v and column k of A = J M~^-1 J^T
+      // (Acol[r] = J_r W_k), so a row update is a few broadcasts, a clamp and one FMA per lane.
+      R Acol[TEAM];
+      const auto Wk = s.W + tt * L.wstride;
+#pragma unroll
+      for (int r = 0; r < TEAM; ++r) {
+        R acc = R(0);
+        if (r < Rn) {
+          const auto Jr = s.J + r * L.wstride;
+          for (int c = 0; c < nv; ++c) acc += Jr[c] * Wk[c];
         }
-        vj += Wr * (nlam - lam);
-        s.rlam[r] = nlam;
+        Acol[r] = acc;
+      }
+      R y = R(0);
+      {
+        const auto Jk = s.J + tt * L.wstride;
+        for (int c = 0; c < nv; ++c) y += Jk[c] * s.vstar[c];
+      }
+      const bool own = tt < Rn;
+      const R bias = own ? s.rbias[tt] : R(0);
+      const R ia = own ? s.rinvA[tt] : R(0);
+      const int kindv = own ? s.rkind[tt] : 0;
+      const int nrmv = own ? s.rnorm[tt] : 0;
+      R lam = R(0);
+      for (int it = 0; it < P.iters; ++it) {
+#pragma unroll
+        for (int r = 0; r < TEAM; ++r) {
+          const R iar = r < Rn ? team_read<TEAM>(tm, ia, r) : R(0);
+          if (iar != R(0)) {
+            const R lamr = team_read<TEAM>(tm, lam, r);
+            R nl = lamr - (team_read<TEAM>(tm, y, r) + team_read<TEAM>(tm, bias, r)) * iar;
+            if (team_read<TEAM>(tm, kindv, r) >= 4) {
+              const R hi = mu * team_read_at<TEAM>(lam, nrmv, r, tm);
+              nl = min_(max_(nl, -hi), hi);
+            } else {
+              nl = max_(nl, R(0));
+            }
+            if (tt == r) lam = nl;
+            y += Acol[r] * (nl - lamr);
+          }
+        }
+      }
+      if (own) s.rlam[tt] = lam;
+      __syncthreads();
+      // v+ = v* + sum_r W_r lambda_r, lanes over velocity columns
+      vj = tt < nv ? s.vstar[tt] : R(0);
+      if (tt < nv)
+        for (int r = 0; r < Rn; ++r) vj += s.rlam[r] * s.W[r * L.wstride + tt];
+    } else {
+      // lanes over velocity columns, rows streamed from global scratch
+      vj = tt < nv ? s.vstar[tt] : R(0);
+      for (int it = 0; it < P.iters; ++it) {
+        for (int r = 0; r < Rn; ++r) {
+          const R invA = s.rinvA[r];
+          if (invA == R(0)) continue;
+          const R Jr = tt < nv ? Jg[(long long)r * nv + tt] : R(0);
+          const R Wr = tt < nv ? Wg[(long long)r * nv + tt] : R(0);
+          const R res = team_sum<TEAM>(Jr * vj) + s.rbias[r];
+          const R lam = s.rlam[r];
+          R nlam = lam - res * invA;
+          if (s.rkind[r] >= 4) {
+            const R hi = mu * s.rlam[s.rnorm[r]];
+            nlam = min_(max_(nlam, -hi), hi);
+          } else {
+            nlam = max_(nlam, R(0));
+          }
+          vj += Wr * (nlam - lam);
+          s.rlam[r] = nlam;
+        }
       }
     }
     __syncthreads();
 
+    PHASE_MARK(9);
     // ---------------------------------------------------- outputs of the substep and integration
-    if (P.dbg_rc) {
+    if (P.dbg_rc && valid) {
       int running = 0;
-      for (int rb = 0; rb < Rn; rb += kTeam) {
-        const int r = rb + t;
+      for (int rb = 0; rb < Rn; rb += TEAM) {
+        const int r = rb + tt;
         const int keep = r < Rn && s.rinvA[r] != R(0);
-        const unsigned long long m = __ballot(keep);
-        const int pos = running + __popcll(m & lanes_below(t));
+        const unsigned long long m = team_ballot<TEAM>(tm, keep);
+        const int pos = running + __popcll(m & lanes_below(tt));
         if (keep && pos < M.r_cap) {
           const long long o = (long long)env * P.dbg_row_stride + (long long)sub_i * P.dbg_row_sub + pos;
           P.dbg_key[o] = s.rkey[r];
@@ -915,11 +1123,11 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
         }
         running += __popcll(m);
       }
-      if (t == 0) P.dbg_rc[env * P.substeps + sub_i] = running;
+      if (tt == 0) P.dbg_rc[env * P.substeps + sub_i] = running;
     }
     // contact impulses of each slot -> force on its bodies (summed over the step, divided by dt)
-    for (int sb = 0; sb < ns; sb += kTeam) {
-      const int sl = sb + t;
+    for (int sb = 0; sb < ns; sb += TEAM) {
+      const int sl = sb + tt;
       if (sl < ns) {
         const int r = s.slotrow[sl];
         V3<R> F = mk(R(0), R(0), R(0));
@@ -930,21 +1138,21 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
       }
     }
     __syncthreads();
-    for (int b = t; b < nl; b += kTeam) {
-      V3<R> acc = ld3<R>(s.F + 3 * b);
+    for (int b = tt; b < nl; b += TEAM) {
+      V3<R> acc = ld3<R>(s.F_ + 3 * b);
       for (int q = M.body_slot_begin[b]; q < M.body_slot_begin[b + 1]; ++q) {
         const int e = M.body_slot[q];
         const V3<R> F = ld3<R>(s.x + 3 * (e >> 1));
         acc = (e & 1) ? sub(acc, F) : add(acc, F);
       }
-      st3(s.F + 3 * b, acc);
+      st3(s.F_ + 3 * b, acc);
     }
     // DOF forces at the end-of-substep velocity, and joint integration q+ = q + h qd+
-    if (t < nv) s.qd[t] = vj;
+    if (tt < nv) s.qd[tt] = vj;
     __syncthreads();
-    for (int j = t; j < nd; j += kTeam) {
+    for (int j = tt; j < nd; j += TEAM) {
       const int lk = M.dof_link[j];
-      const double* lf = M.lf + lk * LF_COLS;
+      const R* lf = M.lf + lk * LF_COLS;
       const int c = M.li[lk * LI_COLS + LI_COL];
       const R pt = P.pos_tgt ? R(P.pos_tgt[dbase + j]) : R(0);
       const R vt = P.vel_tgt ? R(P.vel_tgt[dbase + j]) : R(0);
@@ -953,11 +1161,11 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
       s.qj[j] += h * qdp;
     }
     // free roots: p+ = p + h v+, quat+ = normalize(Exp(h w+) (x) quat)
-    for (int k = t; k < na; k += kTeam) {
+    for (int k = tt; k < na; k += TEAM) {
       const int* ai = M.ai + k * AI_COLS;
       if (ai[AI_FIXED]) continue;
       const int c = ai[AI_COL];
-      R* rs = s.root + 13 * k;
+      const auto rs = s.root + 13 * k;
       const V3<R> vc = ld3<R>(s.qd + c), w = ld3<R>(s.qd + c + 3);
       st3(rs, add(ld3<R>(rs), mul(vc, h)));
       const V3<R> th = mul(w, h);
@@ -983,24 +1191,29 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
       st3(rs + 10, w);
     }
     __syncthreads();
+    PHASE_MARK(-1);
   }
 
   // ---------------------------------------------------------------- write back
-  for (int k = t; k < na; k += kTeam) {
+  if (!valid) return;
+  for (int k = tt; k < na; k += TEAM) {
     const int* ai = M.ai + k * AI_COLS;
     float* dst = P.root_state + (long long)(abase + k) * 13;
     for (int q = 0; q < 7; ++q) dst[q] = float(s.root[13 * k + q]);
     for (int q = 7; q < 13; ++q) dst[q] = ai[AI_FIXED] ? 0.0f : float(s.root[13 * k + q]);
   }
-  for (int j = t; j < nd; j += kTeam) {
+  for (int j = tt; j < nd; j += TEAM) {
     const int lk = M.dof_link[j];
     P.dof_state[2ll * (dbase + j)] = float(s.qj[j]);
     P.dof_state[2ll * (dbase + j) + 1] = float(s.qd[M.li[lk * LI_COLS + LI_COL]]);
     if (P.dof_force) P.dof_force[dbase + j] = float(dof_force_acc / R(P.substeps));
   }
+  if (P.dbg_cycles && tt == 0)
+    for (int k = 0; k < kPhases; ++k) P.dbg_cycles[(long long)env * kPhases + k] = cyc[k];
+#undef PHASE_MARK
   if (P.contact_force) {
     const R inv_dt = R(1) / R(P.dt);
-    for (int k = t; k < 3 * nl; k += kTeam) P.contact_force[(long long)bbase * 3 + k] = float(s.F[k] * inv_dt);
+    for (int k = tt; k < 3 * nl; k += TEAM) P.contact_force[(long long)bbase * 3 + k] = float(s.F_[k] * inv_dt);
   }
 }
 
@@ -1020,20 +1233,25 @@ __global__ void set_rows_kernel(float* dst, const float* src, const int* idx, in
   }
 }
 
-hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, hipStream_t stream) {
-  if (n_envs <= 0) return hipSuccess;
-  const size_t lds = (size_t)a.lds.total * (fp64 ? 8 : 4);
-  if (fp64)
-    hipLaunchKernelGGL(step_kernel<double>, dim3(n_envs), dim3(kTeam), lds, stream, a);
-  else
-    hipLaunchKernelGGL(step_kernel<float>, dim3(n_envs), dim3(kTeam), lds, stream, a);
+template <typename R, int TEAM>
+static hipError_t launch_one(const StepArgs& a, int n_envs, hipStream_t stream) {
+  constexpr int EPW = kTeam / TEAM;
+  const size_t lds = (size_t)a.lds.total * sizeof(R);
+  const int grid = (n_envs + EPW - 1) / EPW;
+  hipLaunchKernelGGL((step_kernel<R, TEAM>), dim3(grid), dim3(kTeam), lds, stream, a, n_envs);
   return hipGetLastError();
 }
 
-hipError_t set_lds_limit(int fp64, size_t bytes) {
-  if (fp64)
-    return hipFuncSetAttribute((const void*)step_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  return hipFuncSetAttribute((const void*)step_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStream_t stream) {
+  if (n_envs <= 0) return hipSuccess;
+  if (fp64) return team == 32 ? launch_one<double, 32>(a, n_envs, stream) : launch_one<double, 64>(a, n_envs, stream);
+  return team == 32 ? launch_one<float, 32>(a, n_envs, stream) : launch_one<float, 64>(a, n_envs, stream);
+}
+
+hipError_t set_lds_limit(int fp64, int team, size_t bytes) {
+  const void* f = fp64 ? (team == 32 ? (const void*)step_kernel<double, 32> : (const void*)step_kernel<double, 64>)
+                       : (team == 32 ? (const void*)step_kernel<float, 32> : (const void*)step_kernel<float, 64>);
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_set_rows(float* dst, const float* src, const int* idx, int n, int n_actors, const int* table,

@@ -111,7 +111,7 @@ def oracle_states(env, params, n_envs, n_steps, every, seed=0):
     return oe, np.concatenate(roots), np.concatenate(dofs), np.concatenate(a)
 
 
-def run(env, params, root, dof, act, oe=None, pos_tgt=None, device="cuda:0", fp64=False):
+def run(env, params, root, dof, act, oe=None, pos_tgt=None, device="cuda:0", fp64=False, lanes_per_env=0):
     """One env-step of every given state on the GPU and in the oracle: the same FP32 state, controls,
     model description and parameters on both sides."""
     env = W.as_f32(env)
@@ -122,7 +122,8 @@ def run(env, params, root, dof, act, oe=None, pos_tgt=None, device="cuda:0", fp6
     pt32 = None if pos_tgt is None else pos_tgt.astype(np.float32).astype(np.float64)
     oe = oe or O.OracleEnv(env)
     model = ags.Model(env)
-    sim = ags.Sim([model], [0] * root.shape[0], params, device=device, debug=True, pd=pos_tgt is not None, fp64=fp64)
+    sim = ags.Sim([model], [0] * root.shape[0], params, device=device, debug=True, pd=pos_tgt is not None, fp64=fp64,
+                  lanes_per_env=lanes_per_env)
     g = gpu_step(sim, env, root32, dof32, act32, pt32)
     o = oe.step(params, root32, dof32, act32, pos_tgt=pt32, r_cap=g["row_key"].shape[2])
     return g, o

@@ -46,28 +46,31 @@ def test_pendulum_free_swing():
     assert np.all(g["row_count"] == 0)
 
 
+@pytest.mark.parametrize("lanes", [32, 64])
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
-def test_humanoid_parity_from_oracle_states(fp64):
+def test_humanoid_parity_from_oracle_states(fp64, lanes):
     env = W.env_humanoid()
     p = W.SimParams()
     oe, root, dof, act = PT.oracle_states(env, p, n_envs=32, n_steps=120, every=8)
-    g, o = PT.run(env, p, root, dof, act, oe=oe, fp64=fp64)
+    g, o = PT.run(env, p, root, dof, act, oe=oe, fp64=fp64, lanes_per_env=lanes)
     c = PT.compare(env, p, g, o)
     s = PT.summarize(c)
     s["mean_rows"] = float(o["row_count"].mean())
-    _report("humanoid_" + ("fp64" if fp64 else "fp32"), s)
+    s["max_rows"] = int(o["row_count"].max())
+    _report(f"humanoid_{'fp64' if fp64 else 'fp32'}_l{lanes}", s)
     _assert_pass(s)
 
 
+@pytest.mark.parametrize("lanes", [32, 64])
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
-def test_ant_parity_every_step(fp64):
+def test_ant_parity_every_step(fp64, lanes):
     """Ant-like quadruped, 64 envs, every one of 100 steps (states from the oracle rollout)."""
     env = W.env_ant()
     p = W.SimParams()
     oe, root, dof, act = PT.oracle_states(env, p, n_envs=64, n_steps=100, every=1)
-    g, o = PT.run(env, p, root, dof, act, oe=oe, fp64=fp64)
+    g, o = PT.run(env, p, root, dof, act, oe=oe, fp64=fp64, lanes_per_env=lanes)
     c = PT.compare(env, p, g, o)
     s = PT.summarize(c)
     s["mean_rows"] = float(o["row_count"].mean())
-    _report("ant_" + ("fp64" if fp64 else "fp32"), s)
+    _report(f"ant_{'fp64' if fp64 else 'fp32'}_l{lanes}", s)
     _assert_pass(s)
