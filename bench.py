@@ -29,6 +29,27 @@ FLOPS_BASE, FLOPS_PER_ROW = 37.0e3, 5.1e3
 BYTES_PER_ENV_STEP = 680.0
 PEAK_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP32 unpacked == FP64 vector)
 PEAK_HBM_GBS = 8000.0
+PROFILE = os.path.join(ROOT, "profiles", "step_kernel_humanoid4096.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2108_10470_amd", "csrc", f) for f in ("ags_step.hip", "ags_internal.h")]
+
+
+def measured_traffic(variant):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    try:
+        with open(PROFILE) as fh:
+            line = next(l for l in fh if l.startswith("traffic_bytes_per_launch"))
+    except (OSError, StopIteration):
+        return None
+    kv = dict(t.split("=") for t in line.split()[1:])
+    if kv.get("source") != h.hexdigest()[:16] or variant not in kv:
+        return None
+    return float(kv[variant])
 
 
 def parse():
@@ -169,11 +190,12 @@ def main():
                    "envs": E, "substeps": params.substeps, "pgs_iters": params.pgs_iters,
                    "tensors": "f32", "compute": head, "mean_rows_per_substep": rows},
         "roofline": {"bound": "alu", "achieved": ach_tf, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach_tf / PEAK_VALU_TFLOPS, "traffic": None,
+                     "frac": ach_tf / PEAK_VALU_TFLOPS, "traffic": measured_traffic(head),
                      "kernel": "step_kernel<double>" if head == "fp64" else "step_kernel<float>",
                      "launch_ms": t_launch * 1e3,
                      "hbm": {"achieved": ach_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach_gbs / PEAK_HBM_GBS,
-                             "bytes_per_env_step": BYTES_PER_ENV_STEP}},
+                             "bytes_per_env_step": BYTES_PER_ENV_STEP},
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"},
         "fwd_bwd": None,
         "variants": {k: {"env_steps_per_s": E * K / (v["total_ms"] / 1e3), "ms_per_step": v["total_ms"] / K,
                          "launch_ms": float(v["launch_ms"].mean()), "mean_rows_per_substep": v["rows"],
