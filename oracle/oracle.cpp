@@ -672,6 +672,7 @@ struct Params {
 
 struct Row {
   int key, kind;      // kind 1/2 limit, 3 normal, 4/5 tangents
+  int branch = 0;     // bias branch: 1 when the gap is negative (Baumgarte), 0 when speculative
   int normal_row;     // tangent rows: index of their normal row
   int slot;           // contact rows: index into the slot list
   std::vector<double> J, W;
@@ -680,7 +681,16 @@ struct Row {
 
 struct StepOut {
   double* qdd_free; int r_cap; int* row_count; int* row_key; double* row_lambda;
-  double* contact_force; double* dof_force; int* near;
+  double* contact_force; double* dof_force; int* near; unsigned long long* mode;
+};
+
+// FNV-1a over the discrete decisions of a step
+struct ModeHash {
+  unsigned long long h = 1469598103934665603ull;
+  void mix(long long v) {
+    h ^= (unsigned long long)v;
+    h *= 1099511628211ull;
+  }
 };
 
 // unpack env state into per-actor root arrays and the env generalized vectors
@@ -716,6 +726,7 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
     }
   std::vector<double> cforce(3 * E.n_bodies, 0.0), dforce(nd, 0.0);
   const double h = P.h;
+  ModeHash mode;
 
   for (int sub = 0; sub < P.substeps; ++sub) {
     // kinematics of every actor at the current state
@@ -770,6 +781,7 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
         r.J.assign(nv, 0.0);
         r.J[c] = side == 0 ? 1.0 : -1.0;
         r.bias = gap >= 0 ? gap / h : P.beta * gap / h;
+        r.branch = gap >= 0 ? 0 : 1;
         rows.push_back(r);
       }
     }
@@ -801,6 +813,7 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
         for (int c = 0; c < nv; ++c)
           r.J[c] = dirs[k][0] * Jp[c] + dirs[k][1] * Jp[nv + c] + dirs[k][2] * Jp[2 * nv + c];
         r.bias = k == 0 ? (s.phi >= 0 ? s.phi / h : P.beta * s.phi / h) : 0.0;
+        r.branch = k == 0 && s.phi < 0 ? 1 : 0;
         rows.push_back(r);
       }
     }
@@ -820,6 +833,11 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
       if (r.kind >= 4) r.normal_row = remap[r.normal_row];
       kept.push_back(r);
     }
+    for (const Row& r : kept) {
+      mode.mix(r.key);
+      mode.mix(r.branch);
+    }
+    mode.mix(-1);
     // ---- projected Gauss-Seidel: fixed sweeps from lambda = 0, v = v*
     std::vector<double> lam(kept.size(), 0.0), v = vstar;
     for (int it = 0; it < P.iters; ++it) {
@@ -831,6 +849,7 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
         double lo = 0.0, hi = INFINITY;
         if (r.kind >= 4) { hi = P.mu * lam[r.normal_row]; lo = -hi; }
         double nl = std::min(std::max(x, lo), hi);
+        mode.mix(x > hi ? 2 : (x < lo ? 1 : 0));
         double dl = nl - lam[ri];
         for (int c = 0; c < nv; ++c) v[c] += r.W[c] * dl;
         lam[ri] = nl;
@@ -902,6 +921,7 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
     for (int k = 0; k < 3 * E.n_bodies; ++k) O.contact_force[k] = cforce[k];
   if (O.dof_force)
     for (int j = 0; j < nd; ++j) O.dof_force[j] = dforce[j] / P.substeps;
+  if (O.mode) *O.mode = mode.h;
 }
 
 Params read_params(const double* p) {
@@ -1091,7 +1111,7 @@ int orc_slots(const void* env, const double* root_state, const double* dof_state
 int orc_step(const void* env, const double* params, int n_envs, const double* root_in, const double* dof_in,
              const double* act, const double* pos_tgt, const double* vel_tgt, double* root_out, double* dof_out,
              double* qdd_free, int r_cap, int* row_count, int* row_key, double* row_lambda,
-             double* contact_force, double* dof_force, int* near, int n_threads) {
+             double* contact_force, double* dof_force, int* near, unsigned long long* mode, int n_threads) {
   const Env* E = static_cast<const Env*>(env);
   if (!E || n_envs < 0 || !root_in || !dof_in || !act || !root_out || !dof_out) return -1;
   Params P = read_params(params);
@@ -1109,6 +1129,7 @@ int orc_step(const void* env, const double* params, int n_envs, const double* ro
       O.contact_force = contact_force ? contact_force + (size_t)e * nb * 3 : nullptr;
       O.dof_force = dof_force ? dof_force + (size_t)e * nd : nullptr;
       O.near = near ? near + (size_t)e * S : nullptr;
+      O.mode = mode ? mode + e : nullptr;
       step_env(*E, P, root_in + (size_t)e * na * 13, dof_in + (size_t)e * nd * 2, act + (size_t)e * nd,
                pos_tgt ? pos_tgt + (size_t)e * nd : zeros.data(), vel_tgt ? vel_tgt + (size_t)e * nd : zeros.data(),
                root_out + (size_t)e * na * 13, dof_out + (size_t)e * nd * 2, O);

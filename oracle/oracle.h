@@ -71,11 +71,14 @@ int orc_slots(const void* env, const double* root_state, const double* dof_state
  * root_in/out (n_envs, n_actors, 13); dof_in/out (n_envs, n_dof, 2); act/pos_tgt/vel_tgt (n_envs, n_dof);
  * qdd_free (n_envs, substeps, n_v); row_count (n_envs, substeps); row_key/row_lambda
  * (n_envs, substeps, r_cap); contact_force (n_envs, n_bodies, 3); dof_force (n_envs, n_dof);
- * near (n_envs, substeps).  Output pointers may be NULL.  Returns 0 or -1 on a bad argument. */
+ * near (n_envs, substeps); mode (n_envs): a hash of every discrete decision of the step (row keys, the
+ * bias branch of each row, the clamp taken by each Gauss-Seidel update), equal for two inputs exactly when
+ * they lie in the same smooth piece of the step (up to hash collisions).  Output pointers may be NULL.
+ * Returns 0 or -1 on a bad argument. */
 int orc_step(const void* env, const double* params, int n_envs, const double* root_in, const double* dof_in,
              const double* act, const double* pos_tgt, const double* vel_tgt, double* root_out, double* dof_out,
              double* qdd_free, int r_cap, int* row_count, int* row_key, double* row_lambda,
-             double* contact_force, double* dof_force, int* near, int n_threads);
+             double* contact_force, double* dof_force, int* near, unsigned long long* mode, int n_threads);
 
 #ifdef __cplusplus
 }

@@ -61,7 +61,7 @@ def lib():
         L.orc_slots.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, ip, ip]
         L.orc_slots.restype = ctypes.c_int
         L.orc_step.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, ip,
-                               ip, dp, dp, dp, ip, ctypes.c_int]
+                               ip, dp, dp, dp, ip, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
         L.orc_step.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -196,12 +196,14 @@ class OracleEnv:
             root=np.zeros_like(root), dof=np.zeros_like(dof), qdd_free=np.zeros((E, S, self.n_v)),
             row_count=np.zeros((E, S), dtype=np.int32), row_key=np.full((E, S, r_cap), -1, dtype=np.int32),
             row_lambda=np.zeros((E, S, r_cap)), contact_force=np.zeros((E, self.n_bodies, 3)),
-            dof_force=np.zeros((E, self.n_dof)), near=np.zeros((E, S), dtype=np.int32))
+            dof_force=np.zeros((E, self.n_dof)), near=np.zeros((E, S), dtype=np.int32),
+            mode=np.zeros(E, dtype=np.uint64))
         nt = n_threads or os.cpu_count() or 1
         rc = lib().orc_step(self.h, _dp(params_vector(params, guard_c, guard_l)), E, _dp(root), _dp(dof), _dp(act),
                             _dp(pt), _dp(vt), _dp(out["root"]), _dp(out["dof"]), _dp(out["qdd_free"]), r_cap,
                             _ip(out["row_count"]), _ip(out["row_key"]), _dp(out["row_lambda"]),
-                            _dp(out["contact_force"]), _dp(out["dof_force"]), _ip(out["near"]), nt)
+                            _dp(out["contact_force"]), _dp(out["dof_force"]), _ip(out["near"]),
+                            out["mode"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nt)
         if rc != 0:
             raise ValueError("oracle: bad step arguments")
         return out
