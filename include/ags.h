@@ -163,6 +163,44 @@ int ags_sim_bind(ags_sim* sim, int32_t which, void* device_ptr);
  * and DOF_ACTUATION bound (the PD target tensors are read only when bound; unbound targets are 0). */
 int ags_sim_step(ags_sim* sim, void* hip_stream);
 
+/* Reverse-mode derivative of one env-step (a hand-written adjoint; the paper's simulator is not
+ * differentiable, this is the differentiation pattern of training systems built on such batched
+ * steps).  Given the state at the START of a step (root_state (N_A,13), dof_state (N_D,2)), the
+ * controls it used (actuation (N_D); the bound PD targets, if any, are read as in ags_sim_step) and
+ * the adjoint of the state AFTER the step in root_adj / dof_adj (same shapes: dL/d of every state
+ * entry), this call overwrites root_adj / dof_adj with the adjoint of the state before the step
+ * and writes act_adj (N_D) = dL/d actuation of this step.  All pointers are device memory owned by
+ * the caller; nothing is allocated.
+ * The derivative is that of the smooth piece the state lies in: which rows exist, which bias
+ * branch each row takes and which bound each Gauss-Seidel update clamps to are held at the values
+ * the recomputed step takes (a mode switch is where the step is not differentiable).  Quaternion
+ * adjoints are tangent to the unit sphere; the pose of a fixed root is a constant (its adjoint rows
+ * come back zero); PD targets receive no adjoint.
+ * Limits: plane contacts only (models with sphere/capsule-vs-box pairs return AGS_E_MODEL), at most
+ * 32 Gauss-Seidel sweeps, at most 64 constraint rows per environment and substep: an environment
+ * whose substep has more gets zero adjoints and status[env] = 1 (status: optional device int32 per
+ * environment, 0 on success).  Computes in the precision of compute_fp64. */
+int ags_sim_step_backward(ags_sim* sim, const float* root_state, const float* dof_state, const float* actuation,
+                          float* root_adj, float* dof_adj, float* act_adj, int32_t* status, void* hip_stream);
+
+/* Rollouts with checkpoints (the checkpoint-every-k recomputation pattern of differentiable
+ * simulation).  A state is 13 N_A + 2 N_D floats: the root-state rows, then the DOF-state rows. */
+int ags_rollout_state_size(const ags_sim* sim, int64_t* floats);
+/* n_steps env-steps from the bound root/DOF state tensors (advanced in place to the final state) with
+ * actions[t] = actions + t N_D (device, n_steps x N_D) as the actuation of step t; the state before
+ * every `every`-th step (t = 0, every, 2 every, ...) is copied to ckpt (device, ceil(n_steps / every)
+ * states).  The bound actuation tensor is left as it was. */
+int ags_rollout_forward(ags_sim* sim, int32_t n_steps, int32_t every, const float* actions, float* ckpt,
+                        void* hip_stream);
+/* Reverse pass of a rollout made by ags_rollout_forward with the same n_steps, every, actions and
+ * ckpt: root_adj / dof_adj hold dL/d(final state) on entry and dL/d(initial state) on return;
+ * act_adj (device, n_steps x N_D) receives dL/d actions[t].  seg is caller-owned device scratch of
+ * `every` states: each segment is recomputed from its checkpoint with ags_sim_step (output tensors
+ * untouched) and its steps are reversed with ags_sim_step_backward (status as there). */
+int ags_rollout_backward(ags_sim* sim, int32_t n_steps, int32_t every, const float* actions, const float* ckpt,
+                         float* seg, float* root_adj, float* dof_adj, float* act_adj, int32_t* status,
+                         void* hip_stream);
+
 /* Copy rows of src (same shape as the bound tensor) into the bound root / DOF state tensor for the
  * actors listed in actor_idx (device int32 array of n global actor indices; NULL = all actors).
  * Setting a root teleports the actor without changing its DOF poses; setting DOFs leaves roots

@@ -84,13 +84,18 @@ def lib():
         L.ags_sim_step.argtypes = [vp, vp]
         L.ags_sim_set_root_state_indexed.argtypes = [vp, vp, vp, i32, vp]
         L.ags_sim_set_dof_state_indexed.argtypes = [vp, vp, vp, i32, vp]
+        L.ags_sim_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ags_rollout_state_size.argtypes = [vp, i64p]
+        L.ags_rollout_forward.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.ags_rollout_backward.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
 
 EXPORTED = ["ags_last_error", "ags_model_create", "ags_model_destroy", "ags_model_get_info", "ags_model_mass_props",
             "ags_sim_create", "ags_sim_destroy", "ags_sim_tensor_shape", "ags_sim_bind", "ags_sim_step",
-            "ags_sim_set_root_state_indexed", "ags_sim_set_dof_state_indexed"]
+            "ags_sim_set_root_state_indexed", "ags_sim_set_dof_state_indexed", "ags_sim_step_backward",
+            "ags_rollout_state_size", "ags_rollout_forward", "ags_rollout_backward"]
 
 
 def _check(rc: int, what: str):
@@ -209,6 +214,29 @@ class Sim:
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         _check(lib().ags_sim_step(self.h, ctypes.c_void_p(s.cuda_stream)), "ags_sim_step")
 
+    def _dev_f32(self, t: torch.Tensor, shape, what: str):
+        if t.dtype != torch.float32 or t.device != self.device or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{what}: expected a contiguous float32 tensor of shape {tuple(shape)} on {self.device}, "
+                             f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def step_backward(self, root_state: torch.Tensor, dof_state: torch.Tensor, actuation: torch.Tensor,
+                      root_adj: torch.Tensor, dof_adj: torch.Tensor, act_adj: torch.Tensor,
+                      status: Optional[torch.Tensor] = None, stream: Optional[torch.cuda.Stream] = None):
+        """Adjoint of one env-step started from (root_state, dof_state) with `actuation`: root_adj/dof_adj
+        hold dL/d(state after) on entry and dL/d(state before) on return; act_adj receives dL/d actuation."""
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        rs, ds, na = self.shapes[ROOT_STATE], self.shapes[DOF_STATE], self.shapes[DOF_ACTUATION][0]
+        args = [self._dev_f32(root_state, rs, "root_state"), self._dev_f32(dof_state, ds, "dof_state"),
+                self._dev_f32(actuation, (na,), "actuation"), self._dev_f32(root_adj, rs, "root_adj"),
+                self._dev_f32(dof_adj, ds, "dof_adj"), self._dev_f32(act_adj, (na,), "act_adj")]
+        st = ctypes.c_void_p(0)
+        if status is not None:
+            if status.dtype != torch.int32 or status.device != self.device or status.numel() != self.n_envs:
+                raise ValueError("status: expected an int32 tensor with one entry per environment")
+            st = ctypes.c_void_p(status.data_ptr())
+        _check(lib().ags_sim_step_backward(self.h, *args, st, ctypes.c_void_p(s.cuda_stream)), "ags_sim_step_backward")
+
     def set_root_state_indexed(self, src: torch.Tensor, actor_idx: Optional[torch.Tensor] = None):
         s = torch.cuda.current_stream(self.device)
         n = 0 if actor_idx is None else actor_idx.numel()
@@ -229,3 +257,54 @@ class Sim:
         if getattr(self, "h", None) and _lib is not None:
             _lib.ags_sim_destroy(self.h)
             self.h = None
+
+
+class Rollout(torch.autograd.Function):
+    """Differentiable rollout: final (root_state, dof_state) after T env-steps of `sim` from (root0, dof0)
+    with actions (T, N_D).  The forward pass keeps the state every `every` steps; the backward pass
+    recomputes each segment from its checkpoint and runs the adjoint of every step in reverse
+    (ags_rollout_forward / ags_rollout_backward).  Gradients flow to the actions and the initial state."""
+
+    @staticmethod
+    def forward(ctx, actions, root0, dof0, sim, every):
+        T = actions.shape[0]
+        actions = actions.contiguous()
+        sim._dev_f32(actions, (T, sim.shapes[DOF_ACTUATION][0]), "actions")
+        sim.root_state.copy_(root0)
+        sim.dof_state.copy_(dof0)
+        n = ctypes.c_int64()
+        _check(lib().ags_rollout_state_size(sim.h, ctypes.byref(n)), "ags_rollout_state_size")
+        ckpt = torch.empty(((T + every - 1) // every, n.value), dtype=torch.float32, device=sim.device)
+        s = torch.cuda.current_stream(sim.device)
+        _check(lib().ags_rollout_forward(sim.h, T, every, ctypes.c_void_p(actions.data_ptr()),
+                                         ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(s.cuda_stream)),
+               "ags_rollout_forward")
+        ctx.save_for_backward(actions, ckpt)
+        ctx.sim, ctx.every, ctx.state_words = sim, every, n.value
+        return sim.root_state.clone(), sim.dof_state.clone()
+
+    @staticmethod
+    def backward(ctx, g_root, g_dof):
+        actions, ckpt = ctx.saved_tensors
+        sim, every = ctx.sim, ctx.every
+        T = actions.shape[0]
+        root_adj = (g_root if g_root is not None else torch.zeros_like(sim.root_state)).float().contiguous().clone()
+        dof_adj = (g_dof if g_dof is not None else torch.zeros_like(sim.dof_state)).float().contiguous().clone()
+        act_adj = torch.empty_like(actions)
+        seg = torch.empty((every, ctx.state_words), dtype=torch.float32, device=sim.device)
+        status = torch.zeros(sim.n_envs, dtype=torch.int32, device=sim.device)
+        s = torch.cuda.current_stream(sim.device)
+        _check(lib().ags_rollout_backward(sim.h, T, every, ctypes.c_void_p(actions.data_ptr()),
+                                          ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(seg.data_ptr()),
+                                          ctypes.c_void_p(root_adj.data_ptr()), ctypes.c_void_p(dof_adj.data_ptr()),
+                                          ctypes.c_void_p(act_adj.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                                          ctypes.c_void_p(s.cuda_stream)), "ags_rollout_backward")
+        bad = int((status != 0).sum())
+        if bad:
+            raise RuntimeError(f"adjoint: {bad} environments exceeded the adjoint's row capacity (64 rows per substep)")
+        return act_adj, root_adj, dof_adj, None, None
+
+
+def rollout(sim: "Sim", actions: torch.Tensor, root0: torch.Tensor, dof0: torch.Tensor, every: int = 16):
+    """Differentiable T-step rollout (see Rollout)."""
+    return Rollout.apply(actions, root0, dof0, sim, every)

@@ -1,0 +1,1292 @@
+// Reverse-mode derivative of one env-step (hand-written adjoint), for gfx950: one wavefront per
+// environment.
+//
+// The paper's simulator is not differentiable; this adjoint differentiates the step implemented
+// by step_kernel (same readings: controls, free dynamics, speculative plane contacts and joint
+// limits, fixed-sweep projected Gauss-Seidel, semi-implicit integration) with the discrete
+// decisions (which rows exist, which bias branch and which clamp each Gauss-Seidel update took)
+// held fixed, i.e. the derivative of the smooth piece the state lies in.
+//
+// Inputs: the state at the start of the step, its controls, and the adjoint of the state after
+// the step.  The kernel recomputes the substeps (storing each substep's start state), then walks
+// them backwards: recompute the substep with everything it needs in LDS, reverse it.
+//
+// The recomputation uses its own formulation, chosen so that every derivative is a short sweep
+// over the tree: spatial vectors about a fixed reference point (the first actor's root position
+// at the start of the step), world axes; M~ assembled from composite inertias and factored
+// densely (Cholesky); C(q, qd) by the recursive Newton-Euler algorithm; row responses
+// W = M~^-1 J^T by triangular solves.  In reverse:
+//   * Gauss-Seidel is reversed row by row from a tape of (lambda before, lambda after, residual,
+//     clamp state), giving the adjoints of the initial row velocities y0 = J v*, the biases and the
+//     Delassus matrix A = J W (its diagonal through 1/A_rr);
+//   * every term in which M~ is differentiated (through W, the impulse response W lambda and the
+//     free accelerations) is gathered into one symmetric matrix P, and d tr(M P) / dq is taken in
+//     one pass in CRBA form: sum_k 2 s_k^T Ic_k y_k + P_kk s_k^T Ic_k s_k with y_k the P-weighted
+//     sum of the ancestor axes of column k;
+//   * the velocity-product and gravity terms C(q, qd) are differentiated by reversing RNEA;
+//   * each world quantity (axes, joint origins, centres of mass, inertias, contact points) receives
+//     an adjoint; these become one wrench per link, and the subtree sums of the wrenches dotted
+//     with the joint axes give the position adjoints (a free root: translation and the rotation
+//     vector, mapped to the quaternion).
+#include "ags_internal.h"
+
+namespace ags {
+namespace {
+
+__device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float min_(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double min_(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void sincos_(double x, double* s, double* c) { sincos(x, s, c); }
+
+template <typename R>
+struct V3 {
+  R x, y, z;
+};
+template <typename R>
+__device__ __forceinline__ V3<R> mk(R x, R y, R z) {
+  return {x, y, z};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> zero3() {
+  return {R(0), R(0), R(0)};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> add(V3<R> a, V3<R> b) {
+  return {a.x + b.x, a.y + b.y, a.z + b.z};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> sub(V3<R> a, V3<R> b) {
+  return {a.x - b.x, a.y - b.y, a.z - b.z};
+}
+template <typename R>
+__device__ __forceinline__ V3<R> mul(V3<R> a, R s) {
+  return {a.x * s, a.y * s, a.z * s};
+}
+template <typename R>
+__device__ __forceinline__ R dot(V3<R> a, V3<R> b) {
+  return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+template <typename R>
+__device__ __forceinline__ V3<R> cross(V3<R> a, V3<R> b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+template <typename R, typename T>
+__device__ __forceinline__ V3<R> ld3(const T* p) {
+  return {R(p[0]), R(p[1]), R(p[2])};
+}
+template <typename R>
+__device__ __forceinline__ void st3(R* p, V3<R> v) {
+  p[0] = v.x;
+  p[1] = v.y;
+  p[2] = v.z;
+}
+template <typename R>
+__device__ __forceinline__ void acc3(R* p, V3<R> v) {
+  p[0] += v.x;
+  p[1] += v.y;
+  p[2] += v.z;
+}
+template <typename R>
+__device__ __forceinline__ V3<R> mv(const R* M, V3<R> v) {
+  return {M[0] * v.x + M[1] * v.y + M[2] * v.z, M[3] * v.x + M[4] * v.y + M[5] * v.z,
+          M[6] * v.x + M[7] * v.y + M[8] * v.z};
+}
+// symmetric 3x3 stored xx yy zz xy xz yz
+template <typename R>
+__device__ __forceinline__ V3<R> symv(const R* S, V3<R> v) {
+  return {S[0] * v.x + S[3] * v.y + S[4] * v.z, S[3] * v.x + S[1] * v.y + S[5] * v.z,
+          S[4] * v.x + S[5] * v.y + S[2] * v.z};
+}
+
+// spatial vectors [angular; linear], linear parts about the reference point
+template <typename R>
+struct SV {
+  V3<R> w, v;
+};
+template <typename R>
+__device__ __forceinline__ SV<R> sz() {
+  return {zero3<R>(), zero3<R>()};
+}
+template <typename R>
+__device__ __forceinline__ SV<R> sadd(SV<R> a, SV<R> b) {
+  return {add(a.w, b.w), add(a.v, b.v)};
+}
+template <typename R>
+__device__ __forceinline__ SV<R> smul(SV<R> a, R s) {
+  return {mul(a.w, s), mul(a.v, s)};
+}
+template <typename R>
+__device__ __forceinline__ R sdot(SV<R> a, SV<R> b) {
+  return dot(a.w, b.w) + dot(a.v, b.v);
+}
+// motion cross product V x m and force cross product V x* f
+template <typename R>
+__device__ __forceinline__ SV<R> crm(SV<R> V, SV<R> m) {
+  return {cross(V.w, m.w), add(cross(V.w, m.v), cross(V.v, m.w))};
+}
+template <typename R>
+__device__ __forceinline__ SV<R> crf(SV<R> V, SV<R> f) {
+  return {add(cross(V.w, f.w), cross(V.v, f.v)), cross(V.w, f.v)};
+}
+template <typename R>
+__device__ __forceinline__ SV<R> lds6(const R* p) {
+  return {mk(p[0], p[1], p[2]), mk(p[3], p[4], p[5])};
+}
+template <typename R>
+__device__ __forceinline__ void sts6(R* p, SV<R> a) {
+  st3(p, a.w);
+  st3(p + 3, a.v);
+}
+template <typename R>
+__device__ __forceinline__ void acc6(R* p, SV<R> a) {
+  acc3(p, a.w);
+  acc3(p + 3, a.v);
+}
+// rigid body (mass m, COM c, inertia Iw about the COM) acting on a motion vector
+template <typename R>
+__device__ __forceinline__ SV<R> body_mul(R m, V3<R> c, const R* Iw, SV<R> X) {
+  const V3<R> u = mul(add(X.v, cross(X.w, c)), m);
+  return {add(symv(Iw, X.w), cross(c, u)), u};
+}
+// composite inertia [m, h = sum m c, J = sum (I + m (|c|^2 1 - c c^T)) as xx yy zz xy xz yz]
+template <typename R>
+__device__ __forceinline__ SV<R> comp_mul(const R* Ic, SV<R> X) {
+  const V3<R> h = mk(Ic[1], Ic[2], Ic[3]);
+  return {add(symv(Ic + 4, X.w), cross(h, X.v)), sub(mul(X.v, Ic[0]), cross(h, X.w))};
+}
+// adjoint of wgt <Y, I X> with respect to the body's COM (point) and orientation (torque)
+template <typename R>
+__device__ __forceinline__ void bil(R m, V3<R> c, const R* Iw, SV<R> Y, SV<R> X, R wgt, V3<R>& cb, V3<R>& tI) {
+  const V3<R> uY = add(Y.v, cross(Y.w, c)), uX = add(X.v, cross(X.w, c));
+  cb = add(cb, mul(add(cross(uY, X.w), cross(uX, Y.w)), wgt * m));
+  tI = add(tI, mul(add(cross(symv(Iw, X.w), Y.w), cross(symv(Iw, Y.w), X.w)), wgt));
+}
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R x) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+  return x;
+}
+__device__ __forceinline__ unsigned long long lanes_below(int t) { return (1ull << t) - 1ull; }
+__device__ __forceinline__ int lane_read(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ float lane_read(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_read(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Hamilton product, xyzw
+template <typename R>
+__device__ __forceinline__ void qmul(const R* a, const R* b, R* o) {
+  o[0] = a[3] * b[0] + a[0] * b[3] + a[1] * b[2] - a[2] * b[1];
+  o[1] = a[3] * b[1] - a[0] * b[2] + a[1] * b[3] + a[2] * b[0];
+  o[2] = a[3] * b[2] + a[0] * b[1] - a[1] * b[0] + a[2] * b[3];
+  o[3] = a[3] * b[3] - a[0] * b[0] - a[1] * b[1] - a[2] * b[2];
+}
+// rotation increment Exp(theta) = (sin(|t|/2) t/|t|, cos(|t|/2)); (t/2, 1) below 1e-8
+template <typename R>
+__device__ __forceinline__ void dq_of(V3<R> th, R* dq) {
+  const R ang = sqrt_(dot(th, th));
+  if (ang < R(1e-8)) {
+    dq[0] = R(0.5) * th.x; dq[1] = R(0.5) * th.y; dq[2] = R(0.5) * th.z; dq[3] = R(1);
+  } else {
+    R s, c;
+    sincos_(R(0.5) * ang, &s, &c);
+    const R sc = s / ang;
+    dq[0] = th.x * sc; dq[1] = th.y * sc; dq[2] = th.z * sc; dq[3] = c;
+  }
+}
+template <typename R>
+__device__ __forceinline__ V3<R> dq_adj(V3<R> th, const R* dqb) {
+  const R ang = sqrt_(dot(th, th));
+  const V3<R> gv = mk(dqb[0], dqb[1], dqb[2]);
+  if (ang < R(1e-8)) return mul(gv, R(0.5));
+  R s, c;
+  sincos_(R(0.5) * ang, &s, &c);
+  const R sc = s / ang;
+  const R dsc = (R(0.5) * c * ang - s) / (ang * ang);  // d(sin(a/2)/a)/da
+  return add(mul(gv, sc), mul(th, (dot(th, gv) * dsc - R(0.5) * s * dqb[3]) / ang));
+}
+
+// ---------------------------------------------------------------- per-environment context
+template <typename R>
+struct Env {
+  const AdjArgs* P;
+  R* r;      // LDS reals of this environment
+  int* ix;   // LDS ints
+  int lane;
+  int nl, nv, nd, na, ns, nlev, rc;
+  int abase, dbase;
+  R h;
+  V3<R> g, ref;
+  int R_;    // rows of the current substep
+  // table access
+  __device__ const int* li(int i) const { return P->m.li + i * LI_COLS; }
+  __device__ const double* lf(int i) const { return P->m.lf + i * LF_COLS; }
+  __device__ R* at(int off, int i, int w) const { return r + off + i * w; }
+};
+
+template <typename R>
+__device__ __forceinline__ void sync() {
+  __syncthreads();
+}
+
+// joint motion vector of link i (world axis ax, joint origin p)
+template <typename R>
+__device__ __forceinline__ SV<R> joint_s(const Env<R>& E, int i) {
+  const AdjLds& L = E.P->L;
+  const V3<R> ax = ld3<R>(E.at(L.ax, i, 3));
+  if (E.li(i)[LI_JTYPE] == J_REV) return {ax, cross(ld3<R>(E.at(L.p, i, 3)), ax)};
+  return {zero3<R>(), ax};
+}
+// motion vector of generalized column k (a joint's, or one of a free root's six)
+template <typename R>
+__device__ __forceinline__ SV<R> col_s(const Env<R>& E, int k) {
+  const int i = E.P->m.col_link[k];
+  const int* li = E.li(i);
+  if (li[LI_PARENT] >= 0) return joint_s(E, i);
+  const int a = k - li[LI_ROOTCOL];
+  V3<R> e = zero3<R>();
+  if ((a % 3) == 0) e.x = R(1);
+  else if ((a % 3) == 1) e.y = R(1);
+  else e.z = R(1);
+  if (a < 3) return {zero3<R>(), e};
+  return {e, cross(ld3<R>(E.at(E.P->L.c, i, 3)), e)};
+}
+// S_0 x for a free root with COM c0: (x_w, x_v + c0 x x_w)
+template <typename R>
+__device__ __forceinline__ SV<R> root_vel(V3<R> c0, const R* x) {
+  const V3<R> v = mk(x[0], x[1], x[2]), w = mk(x[3], x[4], x[5]);
+  return {w, add(v, cross(c0, w))};
+}
+
+// outward sweep: spatial velocity of every link under the generalized vector x (LDS, per column)
+template <typename R>
+__device__ void link_vel(const Env<R>& E, const R* x, int out) {
+  const AdjLds& L = E.P->L;
+  const DevModel& M = E.P->m;
+  for (int lev = 0; lev < E.nlev; ++lev) {
+    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    for (int t = b + E.lane; t < e; t += 64) {
+      const int i = M.level_links[t];
+      const int* li = E.li(i);
+      SV<R> V;
+      if (li[LI_PARENT] < 0) {
+        V = li[LI_JTYPE] == J_FREE ? root_vel(ld3<R>(E.at(L.c, i, 3)), x + li[LI_ROOTCOL]) : sz<R>();
+      } else {
+        V = sadd(lds6(E.at(out, li[LI_PARENT], 6)), smul(joint_s(E, i), x[li[LI_COL]]));
+      }
+      sts6(E.at(out, i, 6), V);
+    }
+    sync<R>();
+  }
+}
+
+// solve M~ x = b for one vector, lane c holding b_c (returns x_c); Lm holds the Cholesky factor
+template <typename R>
+__device__ R chol_solve_lanes(const Env<R>& E, R b) {
+  const R* Lm = E.r + E.P->L.Lm;
+  const int nvp = E.P->L.nvp, nv = E.nv, c = E.lane;
+  for (int k = 0; k < nv; ++k) {
+    const R xk = lane_read(b, k) / Lm[k * nvp + k];
+    if (c == k) b = xk;
+    if (c > k && c < nv) b -= Lm[c * nvp + k] * xk;
+  }
+  for (int k = nv - 1; k >= 0; --k) {
+    const R xk = lane_read(b, k) / Lm[k * nvp + k];
+    if (c == k) b = xk;
+    if (c < k) b -= Lm[k * nvp + c] * xk;
+  }
+  return c < nv ? b : R(0);
+}
+// solve in place on one LDS row per lane (row pointer y, length nv)
+template <typename R>
+__device__ void chol_solve_row(const Env<R>& E, R* y) {
+  const R* Lm = E.r + E.P->L.Lm;
+  const int nvp = E.P->L.nvp, nv = E.nv;
+  for (int k = 0; k < nv; ++k) {
+    R t = y[k];
+    for (int j = 0; j < k; ++j) t -= Lm[k * nvp + j] * y[j];
+    y[k] = t / Lm[k * nvp + k];
+  }
+  for (int k = nv - 1; k >= 0; --k) {
+    R t = y[k];
+    for (int j = k + 1; j < nv; ++j) t -= Lm[j * nvp + k] * y[j];
+    y[k] = t / Lm[k * nvp + k];
+  }
+}
+
+// ---------------------------------------------------------------- forward substep (recompute)
+// sin: state at the start of the substep; sout: state after it.  Returns false when the substep
+// has more constraint rows than the adjoint handles (wave-uniform).
+template <typename R>
+__device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
+  const AdjArgs& P = *E.P;
+  const AdjLds& L = P.L;
+  const DevModel& M = P.m;
+  const int lane = E.lane, nv = E.nv, nd = E.nd, na = E.na;
+  const R h = E.h;
+  R* nu = E.r + L.nu;
+  R* tau = E.r + L.tau;
+  R* arm = E.r + L.arm;
+  R* q = E.r + L.q;
+  // ---- controls, generalized velocity
+  for (int c = lane; c < nv; c += 64) {
+    tau[c] = R(0);
+    arm[c] = R(0);
+  }
+  sync<R>();
+  for (int a = lane; a < na; a += 64) {
+    const int* ai = M.ai + a * AI_COLS;
+    if (ai[AI_FIXED]) continue;
+    const int c = ai[AI_COL];
+    for (int k = 0; k < 6; ++k) nu[c + k] = sin[13 * a + 7 + k];
+  }
+  for (int j = lane; j < nd; j += 64) {
+    const int i = M.dof_link[j];
+    const int c = E.li(i)[LI_COL];
+    const double* lf = E.lf(i);
+    const R qj = sin[13 * na + 2 * j], qdj = sin[13 * na + 2 * j + 1];
+    q[j] = qj;
+    nu[c] = qdj;
+    const R pt = P.pos_tgt ? R(P.pos_tgt[E.dbase + j]) : R(0);
+    const R vt = P.vel_tgt ? R(P.vel_tgt[E.dbase + j]) : R(0);
+    const R kp = R(lf[LF_KP]), kd = R(lf[LF_KD]);
+    tau[c] = R(P.act[E.dbase + j]) + kp * (pt - qj - h * qdj) + kd * (vt - qdj);
+    arm[c] = R(lf[LF_ARM]) + h * kd + h * h * kp;
+  }
+  sync<R>();
+  // ---- kinematics, link inertias and velocities (outward by level)
+  for (int lev = 0; lev < E.nlev; ++lev) {
+    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    for (int t = b + lane; t < e; t += 64) {
+      const int i = M.level_links[t];
+      const int* li = E.li(i);
+      const double* lf = E.lf(i);
+      R* Rm = E.at(L.Rm, i, 9);
+      V3<R> pw;
+      SV<R> V;
+      if (li[LI_PARENT] < 0) {
+        int a = 0;
+        while (M.ai[a * AI_COLS + AI_ROOT] != i) ++a;
+        const R* rs = sin + 13 * a;
+        R qx = rs[3], qy = rs[4], qz = rs[5], qw = rs[6];
+        const R inv = R(1) / sqrt_(qx * qx + qy * qy + qz * qz + qw * qw);
+        qx *= inv; qy *= inv; qz *= inv; qw *= inv;
+        Rm[0] = R(1) - R(2) * (qy * qy + qz * qz); Rm[1] = R(2) * (qx * qy - qz * qw); Rm[2] = R(2) * (qx * qz + qy * qw);
+        Rm[3] = R(2) * (qx * qy + qz * qw); Rm[4] = R(1) - R(2) * (qx * qx + qz * qz); Rm[5] = R(2) * (qy * qz - qx * qw);
+        Rm[6] = R(2) * (qx * qz - qy * qw); Rm[7] = R(2) * (qy * qz + qx * qw); Rm[8] = R(1) - R(2) * (qx * qx + qy * qy);
+        pw = sub(ld3<R>(rs), E.ref);
+        st3(E.at(L.ax, i, 3), zero3<R>());
+      } else {
+        const int p = li[LI_PARENT];
+        const R* Rp = E.at(L.Rm, p, 9);
+        const V3<R> axl = ld3<R>(lf + LF_AXIS);
+        V3<R> tl = ld3<R>(lf + LF_ANCHOR);
+        const R qi = q[li[LI_DOF]];
+        if (li[LI_JTYPE] == J_REV) {
+          R s, c;
+          sincos_(qi, &s, &c);
+          const R t1 = R(1) - c;
+          const R Rr[9] = {c + t1 * axl.x * axl.x, t1 * axl.x * axl.y - s * axl.z, t1 * axl.x * axl.z + s * axl.y,
+                           t1 * axl.x * axl.y + s * axl.z, c + t1 * axl.y * axl.y, t1 * axl.y * axl.z - s * axl.x,
+                           t1 * axl.x * axl.z - s * axl.y, t1 * axl.y * axl.z + s * axl.x, c + t1 * axl.z * axl.z};
+#pragma unroll
+          for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+            for (int c0 = 0; c0 < 3; ++c0)
+              Rm[3 * r0 + c0] = Rp[3 * r0] * Rr[c0] + Rp[3 * r0 + 1] * Rr[3 + c0] + Rp[3 * r0 + 2] * Rr[6 + c0];
+        } else {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Rm[k] = Rp[k];
+          tl = add(tl, mul(axl, qi));
+        }
+        st3(E.at(L.ax, i, 3), mv(Rp, axl));
+        pw = add(ld3<R>(E.at(L.p, p, 3)), mv(Rp, tl));
+      }
+      st3(E.at(L.p, i, 3), pw);
+      // COM and world inertia
+      const V3<R> cw = add(pw, mv(Rm, ld3<R>(lf + LF_COM)));
+      st3(E.at(L.c, i, 3), cw);
+      const R I0[9] = {R(lf[LF_IC + 0]), R(lf[LF_IC + 3]), R(lf[LF_IC + 4]), R(lf[LF_IC + 3]), R(lf[LF_IC + 1]),
+                       R(lf[LF_IC + 5]), R(lf[LF_IC + 4]), R(lf[LF_IC + 5]), R(lf[LF_IC + 2])};
+      R T[9];  // Rm I0
+#pragma unroll
+      for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+        for (int c0 = 0; c0 < 3; ++c0) T[3 * r0 + c0] = Rm[3 * r0] * I0[c0] + Rm[3 * r0 + 1] * I0[3 + c0] + Rm[3 * r0 + 2] * I0[6 + c0];
+      R* Iw = E.at(L.Iw, i, 6);
+      auto TRt = [&](int a, int b2) { return T[3 * a] * Rm[3 * b2] + T[3 * a + 1] * Rm[3 * b2 + 1] + T[3 * a + 2] * Rm[3 * b2 + 2]; };
+      Iw[0] = TRt(0, 0); Iw[1] = TRt(1, 1); Iw[2] = TRt(2, 2); Iw[3] = TRt(0, 1); Iw[4] = TRt(0, 2); Iw[5] = TRt(1, 2);
+      // own part of the composite inertia
+      const R m = R(lf[LF_MASS]);
+      R* Ic = E.at(L.Ic, i, 10);
+      Ic[0] = m; Ic[1] = m * cw.x; Ic[2] = m * cw.y; Ic[3] = m * cw.z;
+      const R cc = dot(cw, cw);
+      Ic[4] = Iw[0] + m * (cc - cw.x * cw.x); Ic[5] = Iw[1] + m * (cc - cw.y * cw.y); Ic[6] = Iw[2] + m * (cc - cw.z * cw.z);
+      Ic[7] = Iw[3] - m * cw.x * cw.y; Ic[8] = Iw[4] - m * cw.x * cw.z; Ic[9] = Iw[5] - m * cw.y * cw.z;
+      // velocity
+      if (li[LI_PARENT] < 0) {
+        V = li[LI_JTYPE] == J_FREE ? root_vel(cw, nu + li[LI_ROOTCOL]) : sz<R>();
+      } else {
+        V = sadd(lds6(E.at(L.V, li[LI_PARENT], 6)), smul(joint_s(E, i), nu[li[LI_COL]]));
+      }
+      sts6(E.at(L.V, i, 6), V);
+    }
+    sync<R>();
+  }
+  // ---- composite inertias (inward by level, children gathered)
+  for (int lev = E.nlev - 2; lev >= 0; --lev) {
+    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    for (int t = b + lane; t < e; t += 64) {
+      const int i = M.level_links[t];
+      const int* li = E.li(i);
+      R* Ic = E.at(L.Ic, i, 10);
+      for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) {
+        const R* Cc = E.at(L.Ic, M.children[k], 10);
+#pragma unroll
+        for (int w = 0; w < 10; ++w) Ic[w] += Cc[w];
+      }
+    }
+    sync<R>();
+  }
+  // ---- M~ (lower triangle) from composite inertias: M_kj = s_j . (Ic_k s_k), j an ancestor column of k
+  R* Lm = E.r + L.Lm;
+  const int nvp = L.nvp;
+  for (int k = lane; k < nv; k += 64) {
+    const SV<R> sk = col_s(E, k);
+    const SV<R> F = comp_mul(E.at(L.Ic, M.col_link[k], 10), sk);
+    const unsigned long long anc = M.col_anc[k];
+    for (int j = 0; j < k; ++j) Lm[k * nvp + j] = ((anc >> j) & 1ull) ? sdot(col_s(E, j), F) : R(0);
+    Lm[k * nvp + k] = sdot(sk, F) + arm[k];
+  }
+  sync<R>();
+  // ---- dense Cholesky in place
+  for (int k = 0; k < nv; ++k) {
+    const R d = sqrt_(Lm[k * nvp + k]);
+    sync<R>();
+    for (int i = k + lane; i < nv; i += 64) Lm[i * nvp + k] = i == k ? d : Lm[i * nvp + k] / d;
+    sync<R>();
+    for (int i = k + 1 + lane; i < nv; i += 64) {
+      const R lik = Lm[i * nvp + k];
+      for (int j = k + 1; j <= i; ++j) Lm[i * nvp + j] -= lik * Lm[j * nvp + k];
+    }
+    sync<R>();
+  }
+  // ---- C(q, qd): RNEA with zero joint accelerations, gravity as a base acceleration
+  for (int lev = 0; lev < E.nlev; ++lev) {
+    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    for (int t = b + lane; t < e; t += 64) {
+      const int i = M.level_links[t];
+      const int* li = E.li(i);
+      SV<R> A;
+      if (li[LI_PARENT] < 0) {
+        A = {zero3<R>(), mul(E.g, R(-1))};
+        if (li[LI_JTYPE] == J_FREE) {
+          const R* x = nu + li[LI_ROOTCOL];
+          A.v = add(A.v, cross(mk(x[0], x[1], x[2]), mk(x[3], x[4], x[5])));
+        }
+      } else {
+        A = sadd(lds6(E.at(L.X1, li[LI_PARENT], 6)), smul(crm(lds6(E.at(L.V, li[LI_PARENT], 6)), joint_s(E, i)), nu[li[LI_COL]]));
+      }
+      sts6(E.at(L.X1, i, 6), A);
+      const R m = R(E.lf(i)[LF_MASS]);
+      const V3<R> cw = ld3<R>(E.at(L.c, i, 3));
+      const R* Iw = E.at(L.Iw, i, 6);
+      const SV<R> V = lds6(E.at(L.V, i, 6));
+      sts6(E.at(L.X2, i, 6), sadd(body_mul(m, cw, Iw, A), crf(V, body_mul(m, cw, Iw, V))));
+    }
+    sync<R>();
+  }
+  for (int lev = E.nlev - 2; lev >= 0; --lev) {
+    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    for (int t = b + lane; t < e; t += 64) {
+      const int i = M.level_links[t];
+      const int* li = E.li(i);
+      R* F = E.at(L.X2, i, 6);
+      for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) {
+        const R* Fc = E.at(L.X2, M.children[k], 6);
+#pragma unroll
+        for (int w = 0; w < 6; ++w) F[w] += Fc[w];
+      }
+    }
+    sync<R>();
+  }
+  R rhs = R(0);
+  if (lane < nv) {
+    const int i = M.col_link[lane];
+    const int* li = E.li(i);
+    const SV<R> F = lds6(E.at(L.X2, i, 6));
+    R C;
+    if (li[LI_PARENT] >= 0) {
+      C = sdot(joint_s(E, i), F);
+    } else {
+      const int a = lane - li[LI_ROOTCOL];
+      const V3<R> n0 = add(F.w, cross(F.v, ld3<R>(E.at(L.c, i, 3))));
+      C = a == 0 ? F.v.x : a == 1 ? F.v.y : a == 2 ? F.v.z : a == 3 ? n0.x : a == 4 ? n0.y : n0.z;
+    }
+    rhs = tau[lane] - C;
+  }
+  const R qddc = chol_solve_lanes(E, rhs);
+  R* vs = E.r + L.vs;
+  if (lane < nv) {
+    E.r[L.qdd + lane] = qddc;
+    vs[lane] = nu[lane] + h * qddc;
+  }
+  sync<R>();
+  link_vel(E, vs, L.Vs);
+  // ---- rows: joint limits (by DOF, lower before upper), then plane contacts (slot order; n, t1, t2)
+  int* rkind = E.ix + L.rkind;
+  int* rlink = E.ix + L.rlink;
+  int* rdof = E.ix + L.rdof;
+  int* rnrm = E.ix + L.rnrm;
+  R* rbc = E.r + L.rbc;
+  R* rb = E.r + L.rb;
+  R* rx = E.r + L.rx;
+  R* rcen = E.r + L.rcen;
+  R* rd = E.r + L.rd;
+  const int rcap = E.rc;
+  int nrows = 0;
+  {
+    bool alo = false, ahi = false;
+    R glo = R(0), ghi = R(0);
+    int i = 0;
+    if (lane < nd) {
+      i = M.dof_link[lane];
+      const double* lf = E.lf(i);
+      const R lo = R(lf[LF_LO]), hi = R(lf[LF_HI]), ml = R(lf[LF_ML]);
+      const R rate = vs[E.li(i)[LI_COL]];
+      glo = q[lane] - lo;
+      ghi = hi - q[lane];
+      alo = isfinite(lf[LF_LO]) && min_(glo, glo + h * rate) < ml;
+      ahi = isfinite(lf[LF_HI]) && min_(ghi, ghi - h * rate) < ml;
+    }
+    const unsigned long long mlo = __ballot(alo), mhi = __ballot(ahi);
+    const unsigned long long below = lanes_below(lane);
+    const int base = __popcll(mlo & below) + __popcll(mhi & below);
+    nrows = __popcll(mlo) + __popcll(mhi);
+    if (alo && base < rcap) {
+      rkind[base] = 1; rlink[base] = i; rdof[base] = lane; rnrm[base] = -1;
+      const R bc = glo >= R(0) ? R(1) / h : R(P.beta) / h;
+      rbc[base] = bc; rb[base] = bc * glo;
+      st3(rd + 3 * base, mk(R(1), R(0), R(0)));
+    }
+    const int bh = base + (alo ? 1 : 0);
+    if (ahi && bh < rcap) {
+      rkind[bh] = 2; rlink[bh] = i; rdof[bh] = lane; rnrm[bh] = -1;
+      const R bc = ghi >= R(0) ? R(1) / h : R(P.beta) / h;
+      rbc[bh] = bc; rb[bh] = bc * ghi;
+      st3(rd + 3 * bh, mk(R(-1), R(0), R(0)));
+    }
+  }
+  for (int s0 = 0; s0 < E.ns; s0 += 64) {
+    const int s = s0 + lane;
+    bool act = false;
+    V3<R> cen = zero3<R>(), x = zero3<R>();
+    R phi = R(0);
+    int i = 0;
+    if (s < E.ns) {
+      const int* si = M.si + s * SI_COLS;
+      const double* sf = M.sf + s * SF_COLS;
+      i = si[SI_LINK_A];
+      cen = add(ld3<R>(E.at(L.p, i, 3)), mv(E.at(L.Rm, i, 9), ld3<R>(sf + SF_P)));
+      const R rad = R(sf[SF_R]);
+      phi = cen.z + E.ref.z - rad;
+      x = sub(cen, mk(R(0), R(0), rad));
+      const SV<R> Vs = lds6(E.at(L.Vs, i, 6));
+      const R vn = add(Vs.v, cross(Vs.w, x)).z;
+      act = phi + h * min_(R(0), vn) < R(P.mc);
+    }
+    const unsigned long long m = __ballot(act);
+    const int base = nrows + 3 * __popcll(m & lanes_below(lane));
+    if (act && base + 2 < rcap) {
+      const R bc = phi >= R(0) ? R(1) / h : R(P.beta) / h;
+      for (int k = 0; k < 3; ++k) {
+        const int r = base + k;
+        rkind[r] = 3 + k; rlink[r] = i; rdof[r] = -1; rnrm[r] = k == 0 ? -1 : base;
+        rbc[r] = k == 0 ? bc : R(0);
+        rb[r] = k == 0 ? bc * phi : R(0);
+        st3(rx + 3 * r, x);
+        st3(rcen + 3 * r, cen);
+        st3(rd + 3 * r, k == 0 ? mk(R(0), R(0), R(1)) : k == 1 ? mk(R(1), R(0), R(0)) : mk(R(0), R(1), R(0)));
+      }
+    }
+    nrows += 3 * __popcll(m);
+  }
+  if (nrows > rcap) return false;
+  sync<R>();
+  // ---- J rows and responses W = M~^-1 J^T (one row per lane)
+  R* J = E.r + L.J;
+  R* W = E.r + L.W;
+  R Arr = R(0);
+  int kind = 0, nrm = -1;
+  if (lane < nrows) {
+    R* Jr = J + lane * nvp;
+    for (int c = 0; c < nv; ++c) Jr[c] = R(0);
+    kind = rkind[lane];
+    nrm = rnrm[lane];
+    const int i = rlink[lane];
+    const int* li = E.li(i);
+    if (kind <= 2) {
+      Jr[li[LI_COL]] = rd[3 * lane];
+    } else {
+      const V3<R> x = ld3<R>(rx + 3 * lane), d = ld3<R>(rd + 3 * lane);
+      if (li[LI_PARENT] >= 0) {
+        const SV<R> s = joint_s(E, i);
+        Jr[li[LI_COL]] = dot(d, add(s.v, cross(s.w, x)));
+      }
+      for (int k = li[LI_ANC_BEGIN]; k < li[LI_ANC_END]; ++k) {
+        const int a = M.anc_link[k];
+        const SV<R> s = joint_s(E, a);
+        Jr[E.li(a)[LI_COL]] = dot(d, add(s.v, cross(s.w, x)));
+      }
+      const int rt = li[LI_ROOT];
+      if (E.li(rt)[LI_JTYPE] == J_FREE) {
+        const int c0 = li[LI_ROOTCOL];
+        const V3<R> w = cross(sub(x, ld3<R>(E.at(L.c, rt, 3))), d);
+        Jr[c0] = d.x; Jr[c0 + 1] = d.y; Jr[c0 + 2] = d.z;
+        Jr[c0 + 3] = w.x; Jr[c0 + 4] = w.y; Jr[c0 + 5] = w.z;
+      }
+    }
+    R* Wr = W + lane * nvp;
+    for (int c = 0; c < nv; ++c) Wr[c] = Jr[c];
+    chol_solve_row(E, Wr);
+    for (int c = 0; c < nv; ++c) Arr += Jr[c] * Wr[c];
+  }
+  // rows that cannot move are dropped, with the friction rows of a dropped normal
+  bool keep = lane < nrows && Arr >= R(kMinRowMass);
+  const bool keepn = __shfl(keep, nrm < 0 ? lane : nrm, 64);
+  keep = keep && (kind < 4 || keepn);
+  const unsigned long long mk_ = __ballot(keep);
+  int* rmap = E.ix + L.rmap;
+  const int nkeep = __popcll(mk_);
+  const int newi = __popcll(mk_ & lanes_below(lane));
+  if (keep) rmap[newi] = lane;
+  E.R_ = nkeep;
+  sync<R>();
+  // gather the kept rows' metadata (register copies; tables rewritten below)
+  int o = lane < nkeep ? rmap[lane] : 0;
+  const int g_kind = __shfl(kind, o, 64), g_link = __shfl(lane < nrows ? rlink[lane] : 0, o, 64);
+  const int g_dof = __shfl(lane < nrows ? rdof[lane] : 0, o, 64);
+  const int g_nrm_old = __shfl(nrm, o, 64);
+  const int g_nrm = __shfl(newi, g_nrm_old < 0 ? 0 : g_nrm_old, 64);
+  R g_real[14];
+  {
+    R mine[14] = {lane < nrows ? rbc[lane] : R(0), lane < nrows ? rb[lane] : R(0), R(1) / (Arr > R(0) ? Arr : R(1))};
+    for (int k = 0; k < 3; ++k) {
+      mine[3 + k] = lane < nrows ? rx[3 * lane + k] : R(0);
+      mine[6 + k] = lane < nrows ? rcen[3 * lane + k] : R(0);
+      mine[9 + k] = lane < nrows ? rd[3 * lane + k] : R(0);
+    }
+    mine[12] = Arr;
+    mine[13] = R(0);
+#pragma unroll
+    for (int k = 0; k < 14; ++k) g_real[k] = __shfl(mine[k], o, 64);
+  }
+  sync<R>();
+  R invA = R(0), bias = R(0);
+  if (lane < nkeep) {
+    rkind[lane] = g_kind; rlink[lane] = g_link; rdof[lane] = g_dof; rnrm[lane] = g_kind >= 4 ? g_nrm : -1;
+    rbc[lane] = g_real[0]; rb[lane] = g_real[1];
+    E.r[L.rinvA + lane] = g_real[2];
+    for (int k = 0; k < 3; ++k) {
+      rx[3 * lane + k] = g_real[3 + k];
+      rcen[3 * lane + k] = g_real[6 + k];
+      rd[3 * lane + k] = g_real[9 + k];
+    }
+    invA = g_real[2];
+    bias = g_real[1];
+  }
+  kind = lane < nkeep ? g_kind : 0;
+  nrm = lane < nkeep && g_kind >= 4 ? g_nrm : -1;
+  sync<R>();
+  const int Rn = nkeep;
+  // ---- Delassus matrix A = J W (row s per lane)
+  R* A = E.r + L.A;
+  const int rcp = L.rcp;
+  if (lane < Rn) {
+    const R* Js = J + rmap[lane] * nvp;
+    for (int r = 0; r < Rn; ++r) {
+      const R* Wr = W + rmap[r] * nvp;
+      R t = R(0);
+      for (int c = 0; c < nv; ++c) t += Js[c] * Wr[c];
+      A[lane * rcp + r] = t;
+    }
+  }
+  // ---- Gauss-Seidel with its tape
+  R y = R(0), lam = R(0);
+  if (lane < Rn) {
+    const R* Js = J + rmap[lane] * nvp;
+    for (int c = 0; c < nv; ++c) y += Js[c] * vs[c];
+  }
+  sync<R>();
+  R* hlo = E.r + L.hlo;
+  R* hln = E.r + L.hln;
+  R* hres = E.r + L.hres;
+  int* hst = E.ix + L.hst;
+  const R mu = R(P.mu);
+  for (int it = 0; it < P.iters; ++it) {
+    for (int r = 0; r < Rn; ++r) {
+      const int kr = lane_read(kind, r);
+      const R lamn = kr >= 4 ? lane_read(lam, lane_read(nrm, r)) : R(0);
+      const R res = y + bias;
+      const R x = lam - res * invA;
+      R lo = R(0), hi = R(INFINITY);
+      if (kr >= 4) {
+        hi = mu * lamn;
+        lo = -hi;
+      }
+      const int st = x > hi ? 2 : (x < lo ? 1 : 0);
+      const R nl = st == 2 ? hi : (st == 1 ? lo : x);
+      const R dl = lane_read(nl - lam, r);
+      if (lane == r) {
+        hlo[it * rcp + r] = lam;
+        hln[it * rcp + r] = nl;
+        hres[it * rcp + r] = res;
+        hst[it * rcp + r] = st;
+        lam = nl;
+      }
+      if (lane < Rn) y += A[lane * rcp + r] * dl;
+    }
+  }
+  if (lane < Rn) E.r[L.rlam + lane] = lam;
+  sync<R>();
+  R* nu1 = E.r + L.nu1;
+  for (int c = lane; c < nv; c += 64) {
+    R t = vs[c];
+    for (int r = 0; r < Rn; ++r) t += W[rmap[r] * nvp + c] * E.r[L.rlam + r];
+    nu1[c] = t;
+  }
+  sync<R>();
+  // ---- semi-implicit integration into sout
+  for (int j = lane; j < nd; j += 64) {
+    const int c = E.li(M.dof_link[j])[LI_COL];
+    sout[13 * na + 2 * j] = q[j] + h * nu1[c];
+    sout[13 * na + 2 * j + 1] = nu1[c];
+  }
+  for (int a = lane; a < na; a += 64) {
+    const int* ai = M.ai + a * AI_COLS;
+    const R* rs = sin + 13 * a;
+    R* ro = sout + 13 * a;
+    if (ai[AI_FIXED]) {
+      for (int k = 0; k < 7; ++k) ro[k] = rs[k];
+      for (int k = 7; k < 13; ++k) ro[k] = R(0);
+      continue;
+    }
+    const R* v = nu1 + ai[AI_COL];
+    for (int k = 0; k < 3; ++k) ro[k] = rs[k] + h * v[k];
+    R dq[4], q1[4];
+    dq_of(mul(mk(v[3], v[4], v[5]), h), dq);
+    qmul(dq, rs + 3, q1);
+    const R inv = R(1) / sqrt_(q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2] + q1[3] * q1[3]);
+    for (int k = 0; k < 4; ++k) ro[3 + k] = q1[k] * inv;
+    for (int k = 0; k < 6; ++k) ro[7 + k] = v[k];
+  }
+  sync<R>();
+  return true;
+}
+
+// ---------------------------------------------------------------- reverse of one substep
+// rbar/dbar hold the adjoint of the state after the substep; on return, of the state before it.
+// The substep's internals are those left in LDS by fwd_substep(sin, ...).
+template <typename R>
+__device__ void rev_substep(Env<R>& E, const R* sin) {
+  const AdjArgs& P = *E.P;
+  const AdjLds& L = P.L;
+  const DevModel& M = P.m;
+  const int lane = E.lane, nl = E.nl, nv = E.nv, nd = E.nd, na = E.na;
+  const R h = E.h;
+  const int nvp = L.nvp, rcp = L.rcp, Rn = E.R_;
+  R* rbar = E.r + L.rbar;
+  R* dbar = E.r + L.dbar;
+  R* nrb = E.r + L.nrb;
+  R* nu = E.r + L.nu;
+  R* nu1 = E.r + L.nu1;
+  R* vs = E.r + L.vs;
+  R* qdd = E.r + L.qdd;
+  R* nub = E.r + L.nub;
+  R* vsb = E.r + L.vsb;
+  R* nui = E.r + L.nui;
+  R* zz = E.r + L.z;
+  R* ww = E.r + L.w;
+  R* qb = E.r + L.qb;
+  R* ab = E.r + L.ab;
+  R* J = E.r + L.J;
+  R* W = E.r + L.W;
+  R* A = E.r + L.A;
+  R* Ab = E.r + L.Ab;
+  R* Lm = E.r + L.Lm;
+  const int* rmap = E.ix + L.rmap;
+  const int* rkind = E.ix + L.rkind;
+  const int* rlink = E.ix + L.rlink;
+  const int* rdof = E.ix + L.rdof;
+  const int* rnrm = E.ix + L.rnrm;
+  // ---- clear accumulators
+  for (int k = lane; k < 6 * nl; k += 64) {
+    E.r[L.wr + k] = R(0);
+    E.r[L.sb + k] = R(0);
+  }
+  for (int k = lane; k < 3 * nl; k += 64) {
+    E.r[L.cb + k] = R(0);
+    E.r[L.tI + k] = R(0);
+  }
+  for (int c = lane; c < nv; c += 64) nub[c] = R(0);
+  for (int k = lane; k < 13 * na; k += 64) nrb[k] = R(0);
+  sync<R>();
+  // ---- integration reverse
+  for (int j = lane; j < nd; j += 64) {
+    const int c = E.li(M.dof_link[j])[LI_COL];
+    nub[c] = dbar[2 * j + 1] + h * dbar[2 * j];
+    qb[j] = dbar[2 * j];
+  }
+  for (int a = lane; a < na; a += 64) {
+    const int* ai = M.ai + a * AI_COLS;
+    if (ai[AI_FIXED]) continue;
+    const int c = ai[AI_COL];
+    const R* rb = rbar + 13 * a;
+    for (int k = 0; k < 3; ++k) {
+      nrb[13 * a + k] = rb[k];
+      nub[c + k] = rb[7 + k] + h * rb[k];
+    }
+    const V3<R> th = mul(mk(nu1[c + 3], nu1[c + 4], nu1[c + 5]), h);
+    R dq[4], q1[4];
+    dq_of(th, dq);
+    const R* q0 = sin + 13 * a + 3;
+    qmul(dq, q0, q1);
+    const R n1 = sqrt_(q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2] + q1[3] * q1[3]);
+    R qo[4], qb1[4];
+    R pr = R(0);
+    for (int k = 0; k < 4; ++k) {
+      qo[k] = rb[3 + k];
+      pr += (q1[k] / n1) * qo[k];
+    }
+    for (int k = 0; k < 4; ++k) qb1[k] = (qo[k] - (q1[k] / n1) * pr) / n1;
+    const R dqc[4] = {-dq[0], -dq[1], -dq[2], dq[3]};
+    const R q0c[4] = {-q0[0], -q0[1], -q0[2], q0[3]};
+    R q0b[4], dqb[4];
+    qmul(dqc, qb1, q0b);
+    qmul(qb1, q0c, dqb);
+    for (int k = 0; k < 4; ++k) nrb[13 * a + 3 + k] = q0b[k];
+    const V3<R> thb = dq_adj(th, dqb);
+    nub[c + 3] = rb[10] + h * thb.x;
+    nub[c + 4] = rb[11] + h * thb.y;
+    nub[c + 5] = rb[12] + h * thb.z;
+  }
+  sync<R>();
+  // ---- z = M~^-1 nu_bar;  lambda_bar = J z
+  const R zc = chol_solve_lanes(E, lane < nv ? nub[lane] : R(0));
+  if (lane < nv) zz[lane] = zc;
+  sync<R>();
+  const int kind = lane < Rn ? rkind[lane] : 0;
+  const int nrm = lane < Rn ? rnrm[lane] : -1;
+  const R invA = lane < Rn ? E.r[L.rinvA + lane] : R(0);
+  R lamb = R(0), ybar = R(0), bbar = R(0), invAb = R(0);
+  if (lane < Rn) {
+    const R* Jr = J + rmap[lane] * nvp;
+    for (int c = 0; c < nv; ++c) lamb += Jr[c] * zz[c];
+    for (int r = 0; r < Rn; ++r) Ab[lane * rcp + r] = R(0);
+  }
+  sync<R>();
+  // ---- Gauss-Seidel reverse
+  const R mu = R(P.mu);
+  const R* hlo = E.r + L.hlo;
+  const R* hln = E.r + L.hln;
+  const R* hres = E.r + L.hres;
+  const int* hst = E.ix + L.hst;
+  for (int it = P.iters - 1; it >= 0; --it) {
+    for (int r = Rn - 1; r >= 0; --r) {
+      const int st = hst[it * rcp + r];
+      const R dl = hln[it * rcp + r] - hlo[it * rcp + r];
+      const R prod = lane < Rn ? A[lane * rcp + r] * ybar : R(0);
+      const R sum = wave_sum(prod);
+      const R g = lane_read(lamb, r) + sum;
+      if (lane < Rn) Ab[lane * rcp + r] += ybar * dl;
+      const int kr = lane_read(kind, r);
+      if (lane == r) {
+        lamb = -sum;
+        if (st == 0) {
+          lamb += g;
+          ybar -= invA * g;
+          bbar -= invA * g;
+          invAb -= hres[it * rcp + r] * g;
+        }
+      }
+      if (st != 0 && kr >= 4) {
+        const int nr = lane_read(nrm, r);
+        if (lane == nr) lamb += (st == 2 ? mu : -mu) * g;
+      }
+    }
+  }
+  if (lane < Rn) {
+    Ab[lane * rcp + lane] -= invAb * invA * invA;
+    E.r[L.rybar + lane] = ybar;
+    E.r[L.rbbar + lane] = bbar;
+  }
+  sync<R>();
+  // ---- v*_bar = nu_bar + J^T ybar
+  for (int c = lane; c < nv; c += 64) {
+    R t = nub[c];
+    for (int r = 0; r < Rn; ++r) t += J[rmap[r] * nvp + c] * E.r[L.rybar + r];
+    vsb[c] = t;
+  }
+  // S = Abar + Abar^T into A (A is not needed any more)
+  if (lane < Rn)
+    for (int r = 0; r < Rn; ++r) A[lane * rcp + r] = Ab[lane * rcp + r] + Ab[r * rcp + lane];
+  sync<R>();
+  // ---- T_s = sum_r S_sr W_r into the J rows (J is not needed any more)
+  if (lane < Rn) {
+    R* Ts = J + rmap[lane] * nvp;
+    for (int c = 0; c < nv; ++c) {
+      R t = R(0);
+      for (int r = 0; r < Rn; ++r) t += A[lane * rcp + r] * W[rmap[r] * nvp + c];
+      Ts[c] = t;
+    }
+  }
+  // ---- w = M~^-1 (h v*_bar): the adjoint of the generalized forces
+  const R wc = chol_solve_lanes(E, lane < nv ? h * vsb[lane] : R(0));
+  if (lane < nv) ww[lane] = wc;
+  sync<R>();
+  // ---- P (dense, into Lm; the factor is not needed any more):
+  // P = 1/2 W S W^T + sym(dnu z^T) + sym(qdd w^T), dnu = nu+ - v*
+  for (int i = lane; i < nv; i += 64) {
+    const R dni = nu1[i] - vs[i], zi = zz[i], qi = qdd[i], wi = ww[i];
+    for (int k = 0; k < nv; ++k) {
+      R t = R(0);
+      for (int s = 0; s < Rn; ++s) t += J[rmap[s] * nvp + i] * W[rmap[s] * nvp + k];
+      Lm[i * nvp + k] = R(0.5) * (t + dni * zz[k] + zi * (nu1[k] - vs[k]) + qi * ww[k] + wi * qdd[k]);
+    }
+  }
+  sync<R>();
+  // ---- Jbar = T + lambda z^T + ybar v*^T
+  if (lane < Rn) {
+    R* Jr = J + rmap[lane] * nvp;
+    const R lr = E.r[L.rlam + lane];
+    for (int c = 0; c < nv; ++c) Jr[c] += lr * zz[c] + ybar * vs[c];
+  }
+  // ---- controls: actuation adjoint, explicit drive terms
+  for (int c = lane; c < nv; c += 64) nui[c] = vsb[c];
+  sync<R>();
+  for (int j = lane; j < nd; j += 64) {
+    const int i = M.dof_link[j];
+    const int c = E.li(i)[LI_COL];
+    const double* lf = E.lf(i);
+    const R kp = R(lf[LF_KP]), kd = R(lf[LF_KD]);
+    ab[j] += ww[c];
+    qb[j] -= kp * ww[c];
+    nui[c] -= (h * kp + kd) * ww[c];
+  }
+  // ---- d tr(M P)/dq, weight -1: per column y_k, s_bar and y_bar
+  R* colS = E.r + L.colS;
+  R* colY = E.r + L.colY;
+  R* colYv = E.r + L.colYv;
+  for (int k = lane; k < nv; k += 64) {
+    const SV<R> sk = col_s(E, k);
+    const unsigned long long anc = M.col_anc[k];
+    SV<R> y = sz<R>();
+    for (int j = 0; j < k; ++j)
+      if ((anc >> j) & 1ull) y = sadd(y, smul(col_s(E, j), Lm[k * nvp + j]));
+    const R* Ic = E.at(L.Ic, M.col_link[k], 10);
+    const SV<R> Is = comp_mul(Ic, sk), Iy = comp_mul(Ic, y);
+    sts6(colS + 6 * k, smul(sadd(Iy, smul(Is, Lm[k * nvp + k])), R(-2)));
+    sts6(colY + 6 * k, smul(Is, R(-2)));
+    sts6(colYv + 6 * k, y);
+  }
+  sync<R>();
+  for (int j = lane; j < nv; j += 64) {
+    SV<R> a = lds6(colS + 6 * j);
+    for (int k = j + 1; k < nv; ++k)
+      if ((M.col_anc[k] >> j) & 1ull) a = sadd(a, smul(lds6(colY + 6 * k), Lm[k * nvp + j]));
+    sts6(colS + 6 * j, a);
+  }
+  sync<R>();
+  // per link: inertia adjoints of sum_{k at or above i} -(2 <s_k, I_i y_k> + P_kk <s_k, I_i s_k>),
+  // and the column s_bar moved onto the owning link
+  for (int i = lane; i < nl; i += 64) {
+    const int* li = E.li(i);
+    const R m = R(E.lf(i)[LF_MASS]);
+    const V3<R> cw = ld3<R>(E.at(L.c, i, 3));
+    const R* Iw = E.at(L.Iw, i, 6);
+    V3<R> cb = zero3<R>(), tI = zero3<R>();
+    const unsigned long long la = M.link_anc[i];
+    for (int k = 0; k < nv; ++k) {
+      if (!((la >> M.col_link[k]) & 1ull)) continue;
+      const SV<R> sk = col_s(E, k);
+      bil(m, cw, Iw, sk, lds6(colYv + 6 * k), R(-2), cb, tI);
+      bil(m, cw, Iw, sk, sk, -Lm[k * nvp + k], cb, tI);
+    }
+    if (li[LI_PARENT] >= 0) {
+      acc6(E.at(L.sb, i, 6), lds6(colS + 6 * li[LI_COL]));
+    } else if (li[LI_JTYPE] == J_FREE) {
+      const int c0 = li[LI_ROOTCOL];
+      cb = add(cb, cross(mk(R(1), R(0), R(0)), ld3<R>(colS + 6 * (c0 + 3) + 3)));
+      cb = add(cb, cross(mk(R(0), R(1), R(0)), ld3<R>(colS + 6 * (c0 + 4) + 3)));
+      cb = add(cb, cross(mk(R(0), R(0), R(1)), ld3<R>(colS + 6 * (c0 + 5) + 3)));
+    }
+    acc3(E.at(L.cb, i, 3), cb);
+    acc3(E.at(L.tI, i, 3), tI);
+  }
+  sync<R>();
+  // ---- C(q, qd) reverse (weight -1, seed w): W_hat, A (RNEA accelerations) outward
+  link_vel(E, ww, L.X0);
+  for (int lev = 0; lev < E.nlev; ++lev) {
+    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    for (int t = b + lane; t < e; t += 64) {
+      const int i = M.level_links[t];
+      const int* li = E.li(i);
+      // X1 still holds the RNEA accelerations of the forward pass; per-link terms:
+      const R m = R(E.lf(i)[LF_MASS]);
+      const V3<R> cw = ld3<R>(E.at(L.c, i, 3));
+      const R* Iw = E.at(L.Iw, i, 6);
+      const SV<R> V = lds6(E.at(L.V, i, 6)), Wh = lds6(E.at(L.X0, i, 6)), Ai = lds6(E.at(L.X1, i, 6));
+      const SV<R> IV = body_mul(m, cw, Iw, V);
+      const SV<R> F = smul(sadd(body_mul(m, cw, Iw, Ai), crf(V, IV)), R(-1));
+      const SV<R> Ab_ = smul(body_mul(m, cw, Iw, Wh), R(-1));
+      V3<R> cb = zero3<R>(), tI = zero3<R>();
+      bil(m, cw, Iw, Wh, Ai, R(-1), cb, tI);
+      const SV<R> Y = smul(crm(V, Wh), R(-1));
+      bil(m, cw, Iw, Y, V, R(-1), cb, tI);
+      const SV<R> Vb = smul(sadd(smul(crf(Wh, IV), R(-1)), body_mul(m, cw, Iw, Y)), R(-1));
+      acc3(E.at(L.cb, i, 3), cb);
+      acc3(E.at(L.tI, i, 3), tI);
+      sts6(E.at(L.X2, i, 6), F);
+      sts6(E.at(L.X3, i, 6), Ab_);
+      sts6(E.at(L.X0, i, 6), Vb);
+      (void)li;
+    }
+  }
+  sync<R>();
+  // inward: subtree sums of F, Abar, Vbar (Vbar of a parent also receives qd crf(s, Abar) of each child)
+  for (int lev = E.nlev - 1; lev >= 0; --lev) {
+    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    for (int t = b + lane; t < e; t += 64) {
+      const int i = M.level_links[t];
+      const int* li = E.li(i);
+      SV<R> F = lds6(E.at(L.X2, i, 6)), Ab_ = lds6(E.at(L.X3, i, 6)), Vb = lds6(E.at(L.X0, i, 6));
+      for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) {
+        const int ch = M.children[k];
+        const SV<R> Ach = lds6(E.at(L.X3, ch, 6));
+        F = sadd(F, lds6(E.at(L.X2, ch, 6)));
+        Ab_ = sadd(Ab_, Ach);
+        Vb = sadd(Vb, sadd(lds6(E.at(L.X0, ch, 6)), smul(crf(joint_s(E, ch), Ach), nu[E.li(ch)[LI_COL]])));
+      }
+      sts6(E.at(L.X2, i, 6), F);
+      sts6(E.at(L.X3, i, 6), Ab_);
+      sts6(E.at(L.X0, i, 6), Vb);
+      if (li[LI_PARENT] >= 0) {
+        const int c = li[LI_COL];
+        const SV<R> s = joint_s(E, i), Vp = lds6(E.at(L.V, li[LI_PARENT], 6));
+        const SV<R> sb = sadd(sadd(smul(F, ww[c]), smul(crf(Vp, Ab_), -nu[c])), smul(Vb, nu[c]));
+        acc6(E.at(L.sb, i, 6), sb);
+        nui[c] += sdot(Ab_, crm(Vp, s)) + sdot(s, Vb);
+      } else if (li[LI_JTYPE] == J_FREE) {
+        const int c = li[LI_ROOTCOL];
+        const V3<R> v = mk(nu[c], nu[c + 1], nu[c + 2]), w = mk(nu[c + 3], nu[c + 4], nu[c + 5]);
+        const V3<R> wwv = mk(ww[c + 3], ww[c + 4], ww[c + 5]);
+        const V3<R> c0 = ld3<R>(E.at(L.c, i, 3));
+        V3<R> cb = add(cross(wwv, F.v), cross(w, Vb.v));
+        acc3(E.at(L.cb, i, 3), cb);
+        const V3<R> nv_ = add(cross(w, Ab_.v), Vb.v);
+        const V3<R> nw_ = add(add(cross(Ab_.v, v), Vb.w), cross(Vb.v, c0));
+        nui[c] += nv_.x; nui[c + 1] += nv_.y; nui[c + 2] += nv_.z;
+        nui[c + 3] += nw_.x; nui[c + 4] += nw_.y; nui[c + 5] += nw_.z;
+      }
+    }
+    sync<R>();
+  }
+  // ---- constraint rows: contact point / direction adjoints, bias adjoints
+  R* rxb = E.r + L.rxb;
+  R* rqb = E.r + L.rqb;
+  if (lane < Rn) {
+    const int i = rlink[lane];
+    const int* li = E.li(i);
+    const R* Jr = J + rmap[lane] * nvp;
+    const R bc = E.r[L.rbc + lane];
+    if (kind >= 3) {
+      SV<R> Vt = sz<R>();
+      if (li[LI_PARENT] >= 0) Vt = smul(joint_s(E, i), Jr[li[LI_COL]]);
+      for (int k = li[LI_ANC_BEGIN]; k < li[LI_ANC_END]; ++k) {
+        const int a = M.anc_link[k];
+        Vt = sadd(Vt, smul(joint_s(E, a), Jr[E.li(a)[LI_COL]]));
+      }
+      const int rt = li[LI_ROOT];
+      if (E.li(rt)[LI_JTYPE] == J_FREE) Vt = sadd(Vt, root_vel(ld3<R>(E.at(L.c, rt, 3)), Jr + li[LI_ROOTCOL]));
+      V3<R> xb = cross(ld3<R>(E.r + L.rd + 3 * lane), Vt.w);
+      if (kind == 3) xb.z += bbar * bc;
+      st3(rxb + 3 * lane, xb);
+      rqb[lane] = R(0);
+    } else {
+      st3(rxb + 3 * lane, zero3<R>());
+      rqb[lane] = bbar * bc * E.r[L.rd + 3 * lane];
+    }
+  }
+  sync<R>();
+  for (int i = lane; i < nl; i += 64) {
+    const int* li = E.li(i);
+    SV<R> sb = sz<R>();
+    V3<R> cb = zero3<R>();
+    SV<R> xw = sz<R>();
+    for (int r = 0; r < Rn; ++r) {
+      if (rkind[r] < 3) continue;
+      const int lr = rlink[r];
+      const R* Jr = J + rmap[r] * nvp;
+      const V3<R> x = ld3<R>(E.r + L.rx + 3 * r), d = ld3<R>(E.r + L.rd + 3 * r);
+      if (li[LI_PARENT] >= 0) {
+        if ((M.link_anc[lr] >> i) & 1ull) sb = sadd(sb, smul(SV<R>{cross(x, d), d}, Jr[li[LI_COL]]));
+      } else if (li[LI_JTYPE] == J_FREE && E.li(lr)[LI_ROOT] == i) {
+        cb = add(cb, cross(ld3<R>(Jr + li[LI_ROOTCOL] + 3), d));
+      }
+      if (lr == i) {
+        const V3<R> xb = ld3<R>(rxb + 3 * r), cen = ld3<R>(E.r + L.rcen + 3 * r);
+        xw = sadd(xw, SV<R>{cross(cen, xb), xb});
+      }
+    }
+    acc6(E.at(L.sb, i, 6), sb);
+    acc3(E.at(L.cb, i, 3), cb);
+    acc6(E.at(L.wr, i, 6), xw);
+  }
+  for (int j = lane; j < nd; j += 64)
+    for (int r = 0; r < Rn; ++r)
+      if (rkind[r] <= 2 && rdof[r] == j) qb[j] += rqb[r];
+  sync<R>();
+  // ---- world adjoints -> one wrench per link
+  for (int i = lane; i < nl; i += 64) {
+    const int* li = E.li(i);
+    const V3<R> cw = ld3<R>(E.at(L.c, i, 3)), cb = ld3<R>(E.at(L.cb, i, 3));
+    SV<R> Wr = sadd(lds6(E.at(L.wr, i, 6)), SV<R>{add(cross(cw, cb), ld3<R>(E.at(L.tI, i, 3))), cb});
+    if (li[LI_PARENT] >= 0) {
+      const SV<R> sb = lds6(E.at(L.sb, i, 6));
+      const V3<R> ax = ld3<R>(E.at(L.ax, i, 3)), o = ld3<R>(E.at(L.p, i, 3));
+      if (li[LI_JTYPE] == J_REV) {
+        const V3<R> axb = add(sb.w, cross(sb.v, o));
+        const V3<R> ob = cross(ax, sb.v);
+        Wr = sadd(Wr, SV<R>{add(cross(ax, axb), cross(o, ob)), ob});
+      } else {
+        Wr.w = add(Wr.w, cross(ax, sb.v));
+      }
+    }
+    sts6(E.at(L.wr, i, 6), Wr);
+  }
+  sync<R>();
+  // subtree sums (inward), position adjoints
+  for (int lev = E.nlev - 1; lev >= 0; --lev) {
+    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    for (int t = b + lane; t < e; t += 64) {
+      const int i = M.level_links[t];
+      const int* li = E.li(i);
+      SV<R> Wc = lds6(E.at(L.wr, i, 6));
+      for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) Wc = sadd(Wc, lds6(E.at(L.wr, M.children[k], 6)));
+      sts6(E.at(L.wr, i, 6), Wc);
+      if (li[LI_PARENT] >= 0) {
+        qb[li[LI_DOF]] += sdot(joint_s(E, i), Wc);
+      } else if (li[LI_JTYPE] == J_FREE) {
+        int a = 0;
+        while (M.ai[a * AI_COLS + AI_ROOT] != i) ++a;
+        const V3<R> p0 = ld3<R>(E.at(L.p, i, 3));
+        acc3(nrb + 13 * a, Wc.v);
+        const V3<R> dth = sub(Wc.w, cross(p0, Wc.v));
+        const R* q = sin + 13 * a + 3;
+        const R nq = sqrt_(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        const R t4[4] = {dth.x, dth.y, dth.z, R(0)};
+        const R qh[4] = {q[0] / nq, q[1] / nq, q[2] / nq, q[3] / nq};
+        R o4[4];
+        qmul(t4, qh, o4);
+        for (int k = 0; k < 4; ++k) nrb[13 * a + 3 + k] += R(2) * o4[k] / nq;
+      }
+    }
+    sync<R>();
+  }
+  // ---- adjoint of the substep's start state
+  for (int j = lane; j < nd; j += 64) {
+    dbar[2 * j] = qb[j];
+    dbar[2 * j + 1] = nui[E.li(M.dof_link[j])[LI_COL]];
+  }
+  for (int a = lane; a < na; a += 64) {
+    const int* ai = M.ai + a * AI_COLS;
+    R* rb = rbar + 13 * a;
+    if (ai[AI_FIXED]) {
+      for (int k = 0; k < 13; ++k) rb[k] = R(0);
+      continue;
+    }
+    const int c = ai[AI_COL];
+    for (int k = 0; k < 7; ++k) rb[k] = nrb[13 * a + k];
+    for (int k = 0; k < 6; ++k) rb[7 + k] = nui[c + k];
+  }
+  sync<R>();
+}
+
+template <typename R>
+__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
+  extern __shared__ double g_adj_lds[];
+  const int ei = blockIdx.x;
+  if (ei >= n_envs) return;
+  const AdjLds& L = P.L;
+  Env<R> E;
+  E.P = &P;
+  E.r = reinterpret_cast<R*>(g_adj_lds);
+  E.ix = reinterpret_cast<int*>(E.r + L.n_real);
+  E.lane = threadIdx.x;
+  E.nl = P.m.n_links;
+  E.nv = P.m.n_v;
+  E.nd = P.m.n_dof;
+  E.na = P.m.n_actors;
+  E.ns = P.m.n_slots;
+  E.nlev = P.m.n_levels;
+  E.rc = L.rows_cap;
+  const int env = P.env_list[ei];
+  E.abase = P.env_actor_base[env];
+  E.dbase = P.env_dof_base[env];
+  E.h = R(P.h);
+  E.g = mk(R(P.gx), R(P.gy), R(P.gz));
+  const int lane = E.lane, na = E.na, nd = E.nd, sw = L.state_words, S = P.substeps;
+  R* st = E.r + L.st;
+  // step start state and the adjoint of the step's end state
+  for (int k = lane; k < 13 * na; k += 64) {
+    st[k] = R(P.root_state[(long long)E.abase * 13 + k]);
+    E.r[L.rbar + k] = R(P.root_adj[(long long)E.abase * 13 + k]);
+  }
+  for (int k = lane; k < 2 * nd; k += 64) {
+    st[13 * na + k] = R(P.dof_state[(long long)E.dbase * 2 + k]);
+    E.r[L.dbar + k] = R(P.dof_adj[(long long)E.dbase * 2 + k]);
+  }
+  for (int j = lane; j < nd; j += 64) E.r[L.ab + j] = R(0);
+  sync<R>();
+  E.ref = mk(st[0], st[1], st[2]);
+  bool ok = true;
+  for (int s = 0; s + 1 < S && ok; ++s) ok = fwd_substep(E, st + s * sw, st + (s + 1) * sw);
+  for (int s = S - 1; s >= 0 && ok; --s) {
+    ok = fwd_substep(E, st + s * sw, st + S * sw);
+    if (ok) rev_substep(E, st + s * sw);
+  }
+  for (int k = lane; k < 13 * na; k += 64) P.root_adj[(long long)E.abase * 13 + k] = ok ? float(E.r[L.rbar + k]) : 0.0f;
+  for (int k = lane; k < 2 * nd; k += 64) P.dof_adj[(long long)E.dbase * 2 + k] = ok ? float(E.r[L.dbar + k]) : 0.0f;
+  for (int j = lane; j < nd; j += 64) P.act_adj[E.dbase + j] = ok ? float(E.r[L.ab + j]) : 0.0f;
+  if (P.status && lane == 0) P.status[env] = ok ? 0 : 1;
+}
+
+template <typename R>
+hipError_t launch_adj(const AdjArgs& a, int n_envs, hipStream_t stream) {
+  const size_t lds = (size_t)a.L.n_real * sizeof(R) + (size_t)a.L.n_int * sizeof(int);
+  hipLaunchKernelGGL(adjoint_kernel<R>, dim3(n_envs), dim3(64), lds, stream, a, n_envs);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t stream) {
+  if (n_envs <= 0) return hipSuccess;
+  return fp64 ? launch_adj<double>(a, n_envs, stream) : launch_adj<float>(a, n_envs, stream);
+}
+
+hipError_t set_adjoint_lds_limit(int fp64, size_t bytes) {
+  const void* f = fp64 ? (const void*)adjoint_kernel<double> : (const void*)adjoint_kernel<float>;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace ags

@@ -101,6 +101,9 @@ struct ags_model {
   std::vector<int> li, level_begin, level_links, children, anc_link, dof_link, si, body_slot_begin, body_slot, ai;
   std::vector<double> lf, sf;
   std::vector<int> jtype;  // per link, to fill the limit margins at sim creation
+  std::vector<unsigned long long> link_anc, col_anc;  // ancestor bit masks (links; generalized columns)
+  std::vector<int> col_link;                           // owning link of each generalized column
+  bool body_pairs = false;                             // has sphere/capsule-vs-box pairs
   std::vector<float> mass, com, inertia;
 };
 
@@ -267,6 +270,42 @@ extern "C" int ags_model_create(const ags_actor_desc* actors, int32_t n_actors, 
     M->li[i * LI_COLS + LI_ANC_END] = (int)M->anc_link.size();
   }
   M->n_anc = (int)M->anc_link.size();
+  // ancestor masks: links (ancestors and the link itself) and columns (columns preceding a column on
+  // its path to the root: a free root's lower-numbered columns, then every column of its ancestors)
+  M->link_anc.assign(nl, 0ull);
+  M->col_link.assign(ncol, 0);
+  M->col_anc.assign(ncol, 0ull);
+  for (int i = 0; i < nl; ++i) {
+    const int p = M->li[i * LI_COLS + LI_PARENT];
+    M->link_anc[i] = (p >= 0 ? M->link_anc[p] : 0ull) | (1ull << i);
+  }
+  for (int i = 0; i < nl; ++i) {
+    const int* row = &M->li[i * LI_COLS];
+    std::vector<int> own;
+    if (row[LI_PARENT] < 0) {
+      if (row[LI_ROOTCOL] >= 0)
+        for (int k = 0; k < 6; ++k) own.push_back(row[LI_ROOTCOL] + k);
+    } else {
+      own.push_back(row[LI_COL]);
+    }
+    unsigned long long above = 0ull;  // every column of the strict ancestors of link i
+    for (int j = 0; j < nl; ++j) {
+      if (j == i || !((M->link_anc[i] >> j) & 1ull)) continue;
+      const int* rj = &M->li[j * LI_COLS];
+      if (rj[LI_PARENT] < 0) {
+        if (rj[LI_ROOTCOL] >= 0)
+          for (int k = 0; k < 6; ++k) above |= 1ull << (rj[LI_ROOTCOL] + k);
+      } else {
+        above |= 1ull << rj[LI_COL];
+      }
+    }
+    for (size_t a = 0; a < own.size(); ++a) {
+      M->col_link[own[a]] = i;
+      unsigned long long m = above;
+      for (size_t b = 0; b < a; ++b) m |= 1ull << own[b];
+      M->col_anc[own[a]] = m;
+    }
+  }
   // contact slots: plane pairs (sphere 1, capsule 2 caps, box 8 corners); box pairs (sphere 1, capsule 2 caps + midpoint)
   std::vector<std::vector<int>> body_entries(nl);
   int limited = 0;
@@ -305,6 +344,7 @@ extern "C" int ags_model_create(const ags_actor_desc* actors, int32_t n_actors, 
         return fail(AGS_E_MODEL, "model: body pairs must be a sphere or capsule against a box of another actor");
       }
       type = SLOT_SPHERE_BOX;
+      M->body_pairs = true;
       kb = link_off[P.b_actor] + B->link;
       pts.push_back({A.p0[0], A.p0[1], A.p0[2]});
       if (A.kind == AGS_SHAPE_CAPSULE) {
@@ -377,7 +417,49 @@ struct TypeDev {
   int n_envs = 0;
   void* scratch = nullptr;
   long long scratch_stride = 0;  // elements of the compute type per env
+  AdjLds adj{};
+  size_t adj_bytes = 0;           // LDS of the adjoint kernel
+  bool body_pairs = false;
 };
+
+// LDS layout of the adjoint kernel for one environment (one wavefront per environment)
+AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters) {
+  AdjLds L{};
+  int off = 0;
+  auto take = [&](int n) {
+    const int o = off;
+    off += std::max(n, 1);
+    return o;
+  };
+  const int nl = info.n_links, nv = std::max(1, info.n_v), nd = std::max(1, info.n_dof), na = info.n_actors;
+  const int rc = std::min(std::max(1, info.max_rows), kAdjRows);
+  L.rows_cap = rc;
+  L.Rm = take(9 * nl); L.p = take(3 * nl); L.ax = take(3 * nl); L.c = take(3 * nl); L.Iw = take(6 * nl);
+  L.Ic = take(10 * nl); L.V = take(6 * nl); L.Vs = take(6 * nl); L.X0 = take(6 * nl); L.X1 = take(6 * nl);
+  L.X2 = take(6 * nl); L.X3 = take(6 * nl); L.wr = take(6 * nl); L.sb = take(6 * nl); L.cb = take(3 * nl);
+  L.tI = take(3 * nl);
+  L.nu = take(nv); L.qdd = take(nv); L.vs = take(nv); L.nu1 = take(nv); L.tau = take(nv); L.arm = take(nv);
+  L.z = take(nv); L.w = take(nv); L.nub = take(nv); L.vsb = take(nv); L.nui = take(nv); L.tmp = take(nv);
+  L.colS = take(6 * nv); L.colY = take(6 * nv); L.colYv = take(6 * nv);
+  L.q = take(nd); L.qb = take(nd); L.ab = take(nd);
+  L.state_words = 13 * na + 2 * info.n_dof;
+  L.st = take((substeps + 1) * L.state_words);
+  L.rbar = take(13 * na); L.dbar = take(2 * nd); L.nrb = take(13 * na);
+  L.nvp = nv | 1;
+  L.Lm = take(nv * L.nvp);
+  L.rcp = rc | 1;
+  L.J = take(rc * L.nvp); L.W = take(rc * L.nvp); L.A = take(rc * L.rcp); L.Ab = take(rc * L.rcp);
+  L.rbc = take(rc); L.rb = take(rc); L.rinvA = take(rc); L.rlam = take(rc); L.rybar = take(rc); L.rbbar = take(rc);
+  L.rqb = take(rc); L.rx = take(3 * rc); L.rcen = take(3 * rc); L.rd = take(3 * rc); L.rxb = take(3 * rc);
+  L.hlo = take(iters * L.rcp); L.hln = take(iters * L.rcp); L.hres = take(iters * L.rcp);
+  L.misc = take(8);
+  L.n_real = (off + 1) & ~1;
+  off = 0;
+  L.rkind = take(rc); L.rlink = take(rc); L.rdof = take(rc); L.rnrm = take(rc); L.rmap = take(rc);
+  L.hst = take(iters * L.rcp); L.flags = take(64);
+  L.n_int = off;
+  return L;
+}
 
 Lds make_layout(const ags_model_info& info, int n_levels, int n_anc, int n_body_slot, int team) {
   Lds L{};
@@ -480,6 +562,7 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     ags_sim_destroy(S);
     return hip_fail(err, "sim: upload");
   }
+  const size_t elem_size = p->compute_fp64 ? sizeof(double) : sizeof(float);
   for (int t = 0; t < n_models; ++t) {
     if (lists[t].empty()) continue;
     const ags_model* M = models[t];
@@ -499,7 +582,9 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
         {M->anc_link.data(), M->anc_link.size() * 4}, {M->dof_link.data(), M->dof_link.size() * 4},
         {M->si.data(), M->si.size() * 4}, {M->body_slot_begin.data(), M->body_slot_begin.size() * 4},
         {M->body_slot.data(), M->body_slot.size() * 4}, {M->ai.data(), M->ai.size() * 4},
-        {lists[t].data(), lists[t].size() * 4}, {lf.data(), lf.size() * 8}, {M->sf.data(), M->sf.size() * 8}};
+        {lists[t].data(), lists[t].size() * 4}, {lf.data(), lf.size() * 8}, {M->sf.data(), M->sf.size() * 8},
+        {M->link_anc.data(), M->link_anc.size() * 8}, {M->col_anc.data(), M->col_anc.size() * 8},
+        {M->col_link.data(), M->col_link.size() * 4}};
     size_t total = 0;
     std::vector<size_t> offs;
     for (auto& q : parts) {
@@ -543,6 +628,18 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     T.env_list = (int*)(b + offs[10]);
     D.lf = (const double*)(b + offs[11]);
     D.sf = (const double*)(b + offs[12]);
+    D.link_anc = (const unsigned long long*)(b + offs[13]);
+    D.col_anc = (const unsigned long long*)(b + offs[14]);
+    D.col_link = (const int*)(b + offs[15]);
+    T.body_pairs = M->body_pairs;
+    T.adj = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters));
+    T.adj_bytes = (size_t)T.adj.n_real * elem_size + (size_t)T.adj.n_int * sizeof(int);
+    if (T.adj_bytes <= 160 * 1024 && T.adj_bytes > 64 * 1024 &&
+        (err = set_adjoint_lds_limit(p->compute_fp64, T.adj_bytes)) != hipSuccess) {
+      S->types.push_back(T);
+      ags_sim_destroy(S);
+      return hip_fail(err, "sim: adjoint LDS limit");
+    }
     T.scratch_stride = 2ll * D.r_cap * std::max(1, D.n_v);
     T.scratch_stride = (T.scratch_stride + 63) & ~63ll;
     const size_t elem = p->compute_fp64 ? sizeof(double) : sizeof(float);
@@ -649,6 +746,126 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
     a.iters = p.pgs_iters;
     hipError_t e = launch_step(a, T.n_envs, p.compute_fp64, T.team, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "step: launch");
+  }
+  return AGS_OK;
+}
+
+extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const float* dof_state,
+                                     const float* actuation, float* root_adj, float* dof_adj, float* act_adj,
+                                     int32_t* status, void* stream) {
+  if (!S || !root_state || !dof_state || !actuation || !root_adj || !dof_adj || !act_adj)
+    return fail(AGS_E_ARG, "step_backward: bad arguments");
+  const ags_sim_params& p = S->params;
+  if (p.pgs_iters > kAdjIters) return fail(AGS_E_ARG, "step_backward: more Gauss-Seidel sweeps than the adjoint's tape holds (32)");
+  for (const TypeDev& T : S->types) {
+    if (T.body_pairs) return fail(AGS_E_MODEL, "step_backward: sphere/capsule-vs-box pairs are not differentiated");
+    if (T.adj_bytes > 160 * 1024) return fail(AGS_E_ARG, "step_backward: model too large for one workgroup's LDS");
+  }
+  for (TypeDev& T : S->types) {
+    AdjArgs a{};
+    a.m = T.dm;
+    a.L = T.adj;
+    a.env_list = T.env_list;
+    a.env_actor_base = S->env_tables;
+    a.env_dof_base = S->env_tables + S->n_envs;
+    a.root_state = root_state;
+    a.dof_state = dof_state;
+    a.act = actuation;
+    a.pos_tgt = (const float*)S->bound[AGS_DOF_POS_TARGET];
+    a.vel_tgt = (const float*)S->bound[AGS_DOF_VEL_TARGET];
+    a.root_adj = root_adj;
+    a.dof_adj = dof_adj;
+    a.act_adj = act_adj;
+    a.status = status;
+    a.h = (double)p.dt / p.substeps;
+    a.gx = p.gravity[0];
+    a.gy = p.gravity[1];
+    a.gz = p.gravity[2];
+    a.mu = p.mu;
+    a.beta = p.baumgarte;
+    a.mc = p.contact_margin;
+    a.substeps = p.substeps;
+    a.iters = p.pgs_iters;
+    hipError_t e = launch_adjoint(a, T.n_envs, p.compute_fp64, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "step_backward: launch");
+  }
+  return AGS_OK;
+}
+
+// ---------------------------------------------------------------- rollouts with checkpoints
+extern "C" int ags_rollout_state_size(const ags_sim* S, int64_t* floats) {
+  if (!S || !floats) return fail(AGS_E_ARG, "rollout_state_size: bad arguments");
+  *floats = 13ll * S->n_actors_total + 2ll * S->n_dof_total;
+  return AGS_OK;
+}
+
+namespace {
+// one env-step on the given state arrays with the given actuation; the output tensors are not written
+int step_on(ags_sim* S, float* root, float* dof, const float* act, hipStream_t stream) {
+  void* saved[AGS_NUM_TENSORS];
+  std::memcpy(saved, S->bound, sizeof(saved));
+  for (int w = AGS_NET_CONTACT_FORCE; w < AGS_NUM_TENSORS; ++w) S->bound[w] = nullptr;
+  S->bound[AGS_ROOT_STATE] = root;
+  S->bound[AGS_DOF_STATE] = dof;
+  S->bound[AGS_DOF_ACTUATION] = const_cast<float*>(act);
+  const int rc = ags_sim_step(S, stream);
+  std::memcpy(S->bound, saved, sizeof(saved));
+  return rc;
+}
+}  // namespace
+
+extern "C" int ags_rollout_forward(ags_sim* S, int32_t n_steps, int32_t every, const float* actions, float* ckpt,
+                                   void* stream) {
+  if (!S || n_steps < 1 || every < 1 || !actions || !ckpt) return fail(AGS_E_ARG, "rollout_forward: bad arguments");
+  if (!S->bound[AGS_ROOT_STATE] || !S->bound[AGS_DOF_STATE])
+    return fail(AGS_E_UNBOUND, "rollout_forward: root and DOF state tensors must be bound");
+  const size_t nr = 13ull * S->n_actors_total, nd = 2ull * S->n_dof_total, sw = nr + nd;
+  hipStream_t st = (hipStream_t)stream;
+  float* root = (float*)S->bound[AGS_ROOT_STATE];
+  float* dof = (float*)S->bound[AGS_DOF_STATE];
+  for (int t = 0; t < n_steps; ++t) {
+    if (t % every == 0) {
+      float* c = ckpt + (size_t)(t / every) * sw;
+      hipError_t e = hipMemcpyAsync(c, root, nr * sizeof(float), hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(c + nr, dof, nd * sizeof(float), hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return hip_fail(e, "rollout_forward: checkpoint copy");
+    }
+    void* saved = S->bound[AGS_DOF_ACTUATION];
+    S->bound[AGS_DOF_ACTUATION] = const_cast<float*>(actions + (size_t)t * S->n_dof_total);
+    const int rc = ags_sim_step(S, stream);
+    S->bound[AGS_DOF_ACTUATION] = saved;
+    if (rc != AGS_OK) return rc;
+  }
+  return AGS_OK;
+}
+
+extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, const float* actions,
+                                    const float* ckpt, float* seg, float* root_adj, float* dof_adj, float* act_adj,
+                                    int32_t* status, void* stream) {
+  if (!S || n_steps < 1 || every < 1 || !actions || !ckpt || !seg || !root_adj || !dof_adj || !act_adj)
+    return fail(AGS_E_ARG, "rollout_backward: bad arguments");
+  const size_t nr = 13ull * S->n_actors_total, nd = 2ull * S->n_dof_total, sw = nr + nd;
+  const size_t na = (size_t)S->n_dof_total;
+  hipStream_t st = (hipStream_t)stream;
+  const int n_seg = (n_steps + every - 1) / every;
+  for (int g = n_seg - 1; g >= 0; --g) {
+    const int t0 = g * every, t1 = std::min(n_steps, t0 + every);
+    hipError_t e = hipMemcpyAsync(seg, ckpt + (size_t)g * sw, sw * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "rollout_backward: copy");
+    for (int t = t0; t + 1 < t1; ++t) {  // recompute the states before steps t0+1 .. t1-1
+      float* a = seg + (size_t)(t - t0) * sw;
+      float* b = a + sw;
+      if ((e = hipMemcpyAsync(b, a, sw * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess)
+        return hip_fail(e, "rollout_backward: copy");
+      const int rc = step_on(S, b, b + nr, actions + (size_t)t * na, st);
+      if (rc != AGS_OK) return rc;
+    }
+    for (int t = t1 - 1; t >= t0; --t) {
+      const float* x = seg + (size_t)(t - t0) * sw;
+      const int rc = ags_sim_step_backward(S, x, x + nr, actions + (size_t)t * na, root_adj, dof_adj,
+                                           act_adj + (size_t)t * na, status, stream);
+      if (rc != AGS_OK) return rc;
+    }
   }
   return AGS_OK;
 }

@@ -59,6 +59,9 @@ struct DevModel {
   const int* body_slot_begin;  // CSR per link: entries 2*slot + (1 if the link is side b)
   const int* body_slot;
   const int* ai;
+  const unsigned long long* link_anc;  // per link: bit j set iff link j is an ancestor of it or itself
+  const unsigned long long* col_anc;   // per column: bit j set iff column j precedes it on its path to the root
+  const int* col_link;                 // per column: the link that owns it
 };
 
 struct StepArgs {
@@ -87,6 +90,53 @@ struct StepArgs {
   double dt, h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
 };
+
+// ---------------------------------------------------------------- adjoint of one env-step
+constexpr int kAdjRows = 64;   // constraint rows per substep the adjoint handles (one lane each)
+constexpr int kAdjIters = 32;  // Gauss-Seidel sweeps the adjoint's tape holds
+
+// per-environment LDS layout of the adjoint kernel: offsets in elements of the compute type (reals)
+// or in ints (integer region, placed after the reals)
+struct AdjLds {
+  int Rm, p, ax, c, Iw, Ic, V, Vs, X0, X1, X2, X3, wr, sb, cb, tI;  // per link
+  int nu, qdd, vs, nu1, tau, arm, z, w, nub, vsb, nui, tmp;        // per column
+  int colS, colY, colYv;                                           // per column, 6 each
+  int q, qb, ab;                                                   // per DOF
+  int st, rbar, dbar, nrb;                                             // state of each substep start, state adjoint
+  int Lm, nvp;                                                     // dense n_v x nvp matrix (factor, then P)
+  int J, W, A, Ab, rcp;                                            // rows: J, W (rows x nvp), A, Abar (rows x rcp)
+  int rbc, rb, rinvA, rlam, rybar, rbbar, rx, rcen, rd, rxb, rqb;  // per row reals
+  int hlo, hln, hres;                                              // tape: iters x rows
+  int misc;
+  int n_real;
+  // integer region
+  int rkind, rlink, rdof, rnrm, rmap, hst, flags;
+  int n_int;
+  int state_words;  // reals of one stored state: 13 per actor + 2 per DOF
+  int rows_cap;     // min(max rows, kAdjRows)
+};
+
+struct AdjArgs {
+  DevModel m;
+  AdjLds L;
+  const int* env_list;
+  const int* env_actor_base;
+  const int* env_dof_base;
+  const float* root_state;
+  const float* dof_state;
+  const float* act;
+  const float* pos_tgt;
+  const float* vel_tgt;
+  float* root_adj;
+  float* dof_adj;
+  float* act_adj;
+  int* status;
+  double h, gx, gy, gz, mu, beta, mc;
+  int substeps, iters;
+};
+
+hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t stream);
+hipError_t set_adjoint_lds_limit(int fp64, size_t bytes);
 
 hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStream_t stream);
 hipError_t set_lds_limit(int fp64, int team, size_t bytes);
