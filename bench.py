@@ -63,6 +63,13 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=600, help="oracle sample: steps from the seeded start")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="skip the replay that measures mean active rows")
+    ap.add_argument("--no-fwd-bwd", action="store_true", help="skip the forward+adjoint rollout measurement")
+    ap.add_argument("--fwd-bwd-steps", type=int, default=64)
+    ap.add_argument("--fwd-bwd-every", type=int, default=16)
+    ap.add_argument("--fwd-bwd-reps", type=int, default=3)
+    ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous-batch measurement")
+    ap.add_argument("--hetero-envs", type=int, default=16384)
+    ap.add_argument("--hetero-steps", type=int, default=100)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scale reference for HBM counters)")
     return ap.parse_args()
@@ -98,7 +105,29 @@ def run_gpu(env, params, n_envs, steps, warmup, fp64, actions_dev, root0, dof0):
     total_ms = start.elapsed_time(stop)
     launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
     finite = bool(torch.isfinite(sim.root_state).all() and torch.isfinite(sim.dof_state).all())
-    return dict(total_ms=total_ms, wall_s=wall, launch_ms=launch_ms, finite=finite)
+    # the same steps captured once in a HIP graph (one graph per 50 steps, replayed)
+    graph_ms = None
+    chunk = min(50, steps)
+    if chunk > 0:
+        sim.root_state.copy_(root0)
+        sim.dof_state.copy_(dof0)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for t in range(chunk):
+                sim.bind(ags.DOF_ACTUATION, actions_dev[warmup + t])
+                sim.step()
+        g.replay()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(1, steps // chunk)
+        a.record(stream)
+        for _ in range(reps):
+            g.replay()
+        b.record(stream)
+        torch.cuda.synchronize()
+        graph_ms = a.elapsed_time(b) / (reps * chunk)
+    return dict(total_ms=total_ms, wall_s=wall, launch_ms=launch_ms, finite=finite, graph_ms=graph_ms)
 
 
 def mean_rows(env, params, n_envs, steps, fp64, actions_dev, root0, dof0):
@@ -116,6 +145,120 @@ def mean_rows(env, params, n_envs, steps, fp64, actions_dev, root0, dof0):
         acc += sim.dbg_rc.double().mean()
     torch.cuda.synchronize()
     return float(acc.item() / steps)
+
+
+def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps):
+    """Forward rollout of T = len(actions) steps with a checkpoint every `every` steps, then the reverse
+    pass (segment recomputation + adjoint of every step) for L = sum of final root x positions."""
+    import ctypes
+    import torch
+    from paper_2108_10470_amd import ags
+    sim = ags.Sim([ags.Model(env)], [0] * n_envs, params, device="cuda:0", fp64=fp64)
+    L = ags.lib()
+    T = actions.shape[0]
+    n = ctypes.c_int64()
+    L.ags_rollout_state_size(sim.h, ctypes.byref(n))
+    f32 = dict(dtype=torch.float32, device="cuda:0")
+    ckpt = torch.empty(((T + every - 1) // every, n.value), **f32)
+    seg = torch.empty((every, n.value), **f32)
+    root_adj = torch.empty_like(sim.root_state)
+    dof_adj = torch.empty_like(sim.dof_state)
+    act_adj = torch.empty_like(actions)
+    status = torch.zeros(n_envs, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+
+    def one():
+        sim.root_state.copy_(root0)
+        sim.dof_state.copy_(dof0)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        ags._check(L.ags_rollout_forward(sim.h, T, every, P(actions), P(ckpt), sp), "rollout_forward")
+        e1.record(stream)
+        root_adj.zero_()
+        root_adj[:, 0] = 1.0
+        dof_adj.zero_()
+        ags._check(L.ags_rollout_backward(sim.h, T, every, P(actions), P(ckpt), P(seg), P(root_adj), P(dof_adj),
+                                          P(act_adj), P(status), sp), "rollout_backward")
+        e2.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), e1.elapsed_time(e2)
+
+    one()
+    times = [one() for _ in range(reps)]
+    fwd = float(np.median([t[0] for t in times]))
+    bwd = float(np.median([t[1] for t in times]))
+    # the adjoint kernel alone: one launch per step on a fixed state
+    x = seg[0]
+    nr = 13 * sim.shapes[ags.ROOT_STATE][0]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for a, b in evs:
+        a.record(stream)
+        L.ags_sim_step_backward(sim.h, P(x), ctypes.c_void_p(x.data_ptr() + 4 * nr), P(actions[0]), P(root_adj),
+                                P(dof_adj), P(act_adj[0]), P(status), sp)
+        b.record(stream)
+    torch.cuda.synchronize()
+    adj_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    return {"value": n_envs * T / ((fwd + bwd) / 1e3), "unit": "env-steps/s", "steps": T, "checkpoint_every": every,
+            "ms_forward": fwd, "ms_backward": bwd, "adjoint_launch_ms": adj_ms,
+            "envs_over_row_capacity": int((status != 0).sum()), "finite": bool(torch.isfinite(act_adj).all()),
+            "grad_abs_mean": float(act_adj.abs().mean()), "dtype": "f64" if fp64 else "f32",
+            "loss": "sum over envs of the final torso x position", "reps": reps}
+
+
+def run_hetero(params, n_envs, steps, fp64):
+    """Heterogeneous batch: ant-like, humanoid-like and arm+gripper+box environments in equal thirds,
+    interleaved; per-type launches vs the persistent launch, and the autotuner's pick."""
+    import torch
+    from paper_2108_10470_amd import ags, workloads as W
+    specs = [W.env_ant(), W.env_humanoid(), W.env_arm_box()]
+    models = [ags.Model(s) for s in specs]
+    env_model = [e % 3 for e in range(n_envs)]
+    counts = [env_model.count(k) for k in range(3)]
+    init = [W.initial_state(specs[k], counts[k], 0) for k in range(3)]
+    acts = [W.actuation(specs[k], counts[k], steps, 0).astype(np.float32) for k in range(3)]
+    roots, dofs, act_cols = [], [], []
+    seen = [0, 0, 0]
+    for e in range(n_envs):
+        k = env_model[e]
+        i = seen[k]
+        seen[k] += 1
+        roots.append(init[k][0][i].reshape(-1, 13))
+        dofs.append(init[k][1][i].reshape(-1, 2))
+        act_cols.append(acts[k][:, i])
+    dev = "cuda:0"
+    r0 = torch.tensor(np.concatenate(roots), dtype=torch.float32, device=dev)
+    d0 = torch.tensor(np.concatenate(dofs), dtype=torch.float32, device=dev)
+    a = torch.tensor(np.concatenate(act_cols, axis=1), dtype=torch.float32, device=dev)
+    out = {"workload": f"{n_envs} envs: ant-like, humanoid-like and arm+gripper+box (capsule-box and box-plane "
+                       f"contacts) in equal thirds, interleaved", "envs": n_envs, "steps": steps,
+           "dtype": "f64" if fp64 else "f32"}
+    stream = torch.cuda.current_stream()
+    for name, per in (("per_type", False), ("persistent", True)):
+        sim = ags.Sim(models, env_model, params, device=dev, fp64=fp64, persistent=per)
+        sim.root_state.copy_(r0)
+        sim.dof_state.copy_(d0)
+        for t in range(min(10, steps)):
+            sim.bind(ags.DOF_ACTUATION, a[t])
+            sim.step()
+        sim.root_state.copy_(r0)
+        sim.dof_state.copy_(d0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for t in range(steps):
+            sim.bind(ags.DOF_ACTUATION, a[t])
+            sim.step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"ms_per_step": ms, "env_steps_per_s": n_envs / (ms / 1e3),
+                     "finite": bool(torch.isfinite(sim.root_state).all())}
+        del sim
+    lanes, per, ms = ags.autotune(models, env_model, params, r0, d0, a[0].contiguous(), fp64=fp64, n_steps=10)
+    out["autotuned"] = {"lanes_per_env": lanes, "persistent": per, "ms_per_step": ms}
+    return out
 
 
 def cpu_baseline(env, params, n_envs, n_steps):
@@ -148,9 +291,10 @@ def main():
     params = W.SimParams()
     E, K, Wm = args.envs, args.steps, args.warmup
     root, dof = W.initial_state(env, E, 0)
-    acts = W.actuation(env, E, Wm + K, 0).astype(np.float32)
-    actions_dev = torch.from_numpy(acts).to("cuda:0").reshape(Wm + K, -1)
-    actions_dev = [actions_dev[t] for t in range(Wm + K)]
+    n_act = max(Wm + K, args.fwd_bwd_steps)
+    acts = W.actuation(env, E, n_act, 0).astype(np.float32)
+    actions_dev = torch.from_numpy(acts).to("cuda:0").reshape(n_act, -1)
+    actions_dev = [actions_dev[t] for t in range(n_act)]
     root0 = torch.from_numpy(root.reshape(-1, 13).astype(np.float32)).to("cuda:0")
     dof0 = torch.from_numpy(dof.reshape(-1, 2).astype(np.float32)).to("cuda:0")
     print(f"[bench] humanoid envs={E} steps={K} warmup={Wm}", file=sys.stderr, flush=True)
@@ -174,6 +318,17 @@ def main():
               f"rows/substep {r['rows']}, finite {r['finite']}", file=sys.stderr, flush=True)
 
     head = "fp64" if "fp64" in res else "fp32"
+    hetero = None
+    if not args.no_hetero:
+        hetero = run_hetero(params, args.hetero_envs, args.hetero_steps, head == "fp64")
+        print(f"[bench] heterogeneous batch: {json.dumps(hetero)}", file=sys.stderr, flush=True)
+    fwd_bwd = None
+    if not args.no_fwd_bwd:
+        T = args.fwd_bwd_steps
+        acts_fb = torch.stack(actions_dev[:T]).contiguous()
+        fwd_bwd = run_fwd_bwd(env, params, E, head == "fp64", acts_fb, root0, dof0, args.fwd_bwd_every,
+                              args.fwd_bwd_reps)
+        print(f"[bench] fwd+bwd ({head}): {json.dumps(fwd_bwd)}", file=sys.stderr, flush=True)
     h = res[head]
     value = E * K / (h["total_ms"] / 1e3)
     t_launch = float(h["launch_ms"].mean()) / 1e3
@@ -196,9 +351,11 @@ def main():
                      "hbm": {"achieved": ach_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach_gbs / PEAK_HBM_GBS,
                              "bytes_per_env_step": BYTES_PER_ENV_STEP},
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"},
-        "fwd_bwd": None,
+        "fwd_bwd": fwd_bwd,
+        "batching": hetero,
         "variants": {k: {"env_steps_per_s": E * K / (v["total_ms"] / 1e3), "ms_per_step": v["total_ms"] / K,
                          "launch_ms": float(v["launch_ms"].mean()), "mean_rows_per_substep": v["rows"],
+                         "graph_ms_per_step": v["graph_ms"],
                          "finite": v["finite"]} for k, v in res.items()},
     }
     if not args.no_cpu_baseline:

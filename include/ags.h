@@ -120,6 +120,8 @@ typedef struct {
   float limit_margin_pri;   /* and prismatic limits (m) */
   int32_t compute_fp64;     /* 0: compute in FP32; 1: compute in FP64 (tensors stay FP32) */
   int32_t lanes_per_env;    /* 0: automatic; 32 or 64: lanes of a wavefront given to one environment */
+  int32_t persistent;       /* 1: one launch for all environment types (a grid sized to the device walks a work
+                               list ordered by estimated cost, heaviest first); 0: one launch per type */
 } ags_sim_params;
 
 typedef struct ags_sim ags_sim;
@@ -182,6 +184,18 @@ int ags_sim_step(ags_sim* sim, void* hip_stream);
  * environment, 0 on success).  Computes in the precision of compute_fp64. */
 int ags_sim_step_backward(ags_sim* sim, const float* root_state, const float* dof_state, const float* actuation,
                           float* root_adj, float* dof_adj, float* act_adj, int32_t* status, void* hip_stream);
+
+/* Autotuner: picks the fastest mapping of environments onto wavefronts (lanes_per_env 64 or 32, the
+ * latter only when every environment has at most 32 generalized velocities) and launch form
+ * (persistent or per type) for this batch on the current device.  Each candidate sim is created,
+ * stepped n_steps times twice (the first time warms up) from private device copies of root_state /
+ * dof_state with the given actuation (device arrays shaped like the bound tensors), timed with HIP
+ * events on hip_stream (the call synchronises that stream), and destroyed; the caller's arrays are
+ * not modified.  On success params->lanes_per_env and params->persistent hold the winner and
+ * *ms_out (optional) its milliseconds per env-step. */
+int ags_autotune(const ags_model* const* models, int32_t n_models, const int32_t* env_model, int32_t n_envs,
+                 ags_sim_params* params, const float* root_state, const float* dof_state, const float* actuation,
+                 int32_t n_steps, float* ms_out, void* hip_stream);
 
 /* Rollouts with checkpoints (the checkpoint-every-k recomputation pattern of differentiable
  * simulation).  A state is 13 N_A + 2 N_D floats: the root-state rows, then the DOF-state rows. */

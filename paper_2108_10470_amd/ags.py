@@ -56,7 +56,7 @@ class SimParams(ctypes.Structure):
                 ("pgs_iters", ctypes.c_int32), ("mu", ctypes.c_float), ("baumgarte", ctypes.c_float),
                 ("contact_margin", ctypes.c_float), ("limit_margin_rev", ctypes.c_float),
                 ("limit_margin_pri", ctypes.c_float), ("compute_fp64", ctypes.c_int32),
-                ("lanes_per_env", ctypes.c_int32)]
+                ("lanes_per_env", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 _lib = None
@@ -86,6 +86,8 @@ def lib():
         L.ags_sim_set_dof_state_indexed.argtypes = [vp, vp, vp, i32, vp]
         L.ags_sim_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ags_rollout_state_size.argtypes = [vp, i64p]
+        L.ags_autotune.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_int32), i32, ctypes.POINTER(SimParams),
+                                   vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
         L.ags_rollout_forward.argtypes = [vp, i32, i32, vp, vp, vp]
         L.ags_rollout_backward.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
@@ -95,7 +97,7 @@ def lib():
 EXPORTED = ["ags_last_error", "ags_model_create", "ags_model_destroy", "ags_model_get_info", "ags_model_mass_props",
             "ags_sim_create", "ags_sim_destroy", "ags_sim_tensor_shape", "ags_sim_bind", "ags_sim_step",
             "ags_sim_set_root_state_indexed", "ags_sim_set_dof_state_indexed", "ags_sim_step_backward",
-            "ags_rollout_state_size", "ags_rollout_forward", "ags_rollout_backward"]
+            "ags_rollout_state_size", "ags_rollout_forward", "ags_rollout_backward", "ags_autotune"]
 
 
 def _check(rc: int, what: str):
@@ -153,9 +155,9 @@ class Model:
             self.h = None
 
 
-def sim_params(p, fp64: bool = False, lanes_per_env: int = 0) -> SimParams:
+def sim_params(p, fp64: bool = False, lanes_per_env: int = 0, persistent: bool = False) -> SimParams:
     return SimParams(p.dt, p.substeps, _f3(p.gravity), p.pgs_iters, p.mu, p.baumgarte, p.contact_margin,
-                     p.limit_margin_rev, p.limit_margin_pri, 1 if fp64 else 0, lanes_per_env)
+                     p.limit_margin_rev, p.limit_margin_pri, 1 if fp64 else 0, lanes_per_env, 1 if persistent else 0)
 
 
 class Sim:
@@ -163,7 +165,7 @@ class Sim:
 
     def __init__(self, models: Sequence[Model], env_model: Sequence[int], params, device="cuda:0",
                  debug: bool = False, pd: bool = False, fp64: bool = False, phase_cycles: bool = False,
-                 lanes_per_env: int = 0):
+                 lanes_per_env: int = 0, persistent: bool = False):
         self.models = list(models)
         self.params = params
         self.device = torch.device(device)
@@ -171,7 +173,7 @@ class Sim:
         handles = (ctypes.c_void_p * len(self.models))(*[m.h for m in self.models])
         ids = (ctypes.c_int32 * self.n_envs)(*[int(x) for x in env_model])
         h = ctypes.c_void_p()
-        self._p = sim_params(params, fp64, lanes_per_env)
+        self._p = sim_params(params, fp64, lanes_per_env, persistent)
         _check(lib().ags_sim_create(handles, len(self.models), ids, self.n_envs, ctypes.byref(self._p), ctypes.byref(h)),
                "ags_sim_create")
         self.h = h
@@ -308,3 +310,24 @@ class Rollout(torch.autograd.Function):
 def rollout(sim: "Sim", actions: torch.Tensor, root0: torch.Tensor, dof0: torch.Tensor, every: int = 16):
     """Differentiable T-step rollout (see Rollout)."""
     return Rollout.apply(actions, root0, dof0, sim, every)
+
+
+def autotune(models: Sequence[Model], env_model: Sequence[int], params, root_state: torch.Tensor,
+             dof_state: torch.Tensor, actuation: torch.Tensor, fp64: bool = False, n_steps: int = 10):
+    """The fastest (lanes_per_env, persistent) mapping for this batch (ags_autotune): returns
+    (lanes_per_env, persistent, ms per env-step)."""
+    handles = (ctypes.c_void_p * len(models))(*[m.h for m in models])
+    ids = (ctypes.c_int32 * len(env_model))(*[int(x) for x in env_model])
+    sp = sim_params(params, fp64)
+    ms = ctypes.c_float()
+    s = torch.cuda.current_stream(root_state.device)
+    n_a = sum(models[m].info.n_actors for m in env_model)
+    n_d = sum(models[m].info.n_dof for m in env_model)
+    for t, n, what in ((root_state, 13 * n_a, "root_state"), (dof_state, 2 * n_d, "dof_state"), (actuation, n_d, "actuation")):
+        if t.dtype != torch.float32 or not t.is_contiguous() or not t.is_cuda or t.numel() != n:
+            raise ValueError(f"autotune: {what} must be a contiguous float32 device tensor of {n} elements")
+    _check(lib().ags_autotune(handles, len(models), ids, len(env_model), ctypes.byref(sp),
+                              ctypes.c_void_p(root_state.data_ptr()), ctypes.c_void_p(dof_state.data_ptr()),
+                              ctypes.c_void_p(actuation.data_ptr()), n_steps, ctypes.byref(ms),
+                              ctypes.c_void_p(s.cuda_stream)), "ags_autotune")
+    return sp.lanes_per_env, bool(sp.persistent), ms.value

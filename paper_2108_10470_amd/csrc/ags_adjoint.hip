@@ -894,31 +894,34 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
     for (int r = 0; r < Rn; ++r) Ab[lane * rcp + r] = R(0);
   }
   sync<R>();
-  // ---- Gauss-Seidel reverse
+  // ---- Gauss-Seidel reverse.  q = A ybar is kept up to date (ybar changes in one entry per row
+  // update and A is symmetric), so (A^T ybar)_r is read from lane r instead of reduced over the wave.
   const R mu = R(P.mu);
   const R* hlo = E.r + L.hlo;
   const R* hln = E.r + L.hln;
   const R* hres = E.r + L.hres;
   const int* hst = E.ix + L.hst;
+  R qv = R(0);
   for (int it = P.iters - 1; it >= 0; --it) {
     for (int r = Rn - 1; r >= 0; --r) {
       const int st = hst[it * rcp + r];
       const R dl = hln[it * rcp + r] - hlo[it * rcp + r];
-      const R prod = lane < Rn ? A[lane * rcp + r] * ybar : R(0);
-      const R sum = wave_sum(prod);
+      const R Asr = lane < Rn ? A[lane * rcp + r] : R(0);
+      const R sum = lane_read(qv, r);
       const R g = lane_read(lamb, r) + sum;
       if (lane < Rn) Ab[lane * rcp + r] += ybar * dl;
       const int kr = lane_read(kind, r);
-      if (lane == r) {
-        lamb = -sum;
-        if (st == 0) {
+      if (lane == r) lamb = -sum;
+      if (st == 0) {
+        const R dy = -lane_read(invA, r) * g;
+        if (lane == r) {
           lamb += g;
-          ybar -= invA * g;
-          bbar -= invA * g;
+          ybar += dy;
+          bbar += dy;
           invAb -= hres[it * rcp + r] * g;
         }
-      }
-      if (st != 0 && kr >= 4) {
+        qv += Asr * dy;
+      } else if (kr >= 4) {
         const int nr = lane_read(nrm, r);
         if (lane == nr) lamb += (st == 2 ? mu : -mu) * g;
       }

@@ -514,6 +514,11 @@ struct ags_sim {
   int* actor_rows = nullptr;  // device: root row begin, root count(1), dof begin, dof count (4 x N_A)
   int n_actors_total = 0, n_dof_total = 0, n_bodies_total = 0, max_nv = 0, max_rows = 0;
   void* bound[AGS_NUM_TENSORS] = {nullptr};
+  // persistent (fused) launch
+  bool fused_ok = false;
+  int* units = nullptr;  // device: (type, group) pairs
+  int n_units = 0, fused_grid = 0, fused_team = 64;
+  size_t fused_lds = 0;
 };
 
 extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, const int32_t* env_model,
@@ -570,6 +575,12 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     T.n_envs = (int)lists[t].size();
     // lanes per environment: 32 (two environments per wavefront) when every per-lane loop fits
     T.team = (p->lanes_per_env == 32 || (p->lanes_per_env == 0 && M->info.n_v <= 32)) && M->info.n_v <= 32 ? 32 : 64;
+    if (p->persistent) {  // one lane count for all types: 32 only if every type fits
+      bool all32 = p->lanes_per_env != 64;
+      for (int u = 0; u < n_models; ++u)
+        if (!lists[u].empty() && models[u]->info.n_v > 32) all32 = false;
+      T.team = all32 ? 32 : 64;
+    }
     T.lds = make_layout(M->info, M->n_levels, M->n_anc, (int)M->body_slot.size(), T.team);
     // limit margins per joint type
     std::vector<double> lf = M->lf;
@@ -663,6 +674,46 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     }
     S->types.push_back(T);
   }
+  if (p->persistent && !S->types.empty() && (int)S->types.size() <= kMaxFusedTypes) {
+    // work list: (type, group) units, types ordered by estimated cost per group (heaviest first)
+    std::vector<int> order(S->types.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    auto cost = [&](const TypeDev& T) {
+      const double nv = T.dm.n_v;
+      return (nv * nv + 4.0 * T.dm.n_slots + 8.0 * T.dm.n_links) * (kTeam / T.team);
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(S->types[a]) > cost(S->types[b]); });
+    std::vector<int> units;
+    size_t lds_words = 0;
+    for (int k : order) {
+      const TypeDev& T = S->types[k];
+      const int epw = kTeam / T.team;
+      const int groups = (T.n_envs + epw - 1) / epw;
+      for (int g = 0; g < groups; ++g) units.insert(units.end(), {k, g});
+      lds_words = std::max(lds_words, (size_t)T.lds.total);
+    }
+    S->fused_team = S->types[0].team;
+    S->fused_lds = lds_words * elem_size;
+    S->n_units = (int)(units.size() / 2);
+    int dev = 0, cus = 0, per_cu = 0;
+    if (S->fused_lds <= 160 * 1024 &&
+        (err = hipGetDevice(&dev)) == hipSuccess &&
+        (err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) == hipSuccess &&
+        (S->fused_lds <= 64 * 1024 || (err = set_fused_lds_limit(p->compute_fp64, S->fused_team, S->fused_lds)) == hipSuccess) &&
+        (err = fused_blocks_per_cu(p->compute_fp64, S->fused_team, S->fused_lds, &per_cu)) == hipSuccess &&
+        (err = hipMalloc(&S->units, units.size() * sizeof(int))) == hipSuccess &&
+        (err = hipMemcpy(S->units, units.data(), units.size() * sizeof(int), hipMemcpyHostToDevice)) == hipSuccess) {
+      S->fused_grid = std::max(1, std::min(S->n_units, cus * std::max(1, per_cu)));
+      S->fused_ok = true;
+    } else {
+      ags_sim_destroy(S);
+      return err != hipSuccess ? hip_fail(err, "sim: persistent launch set-up")
+                               : fail(AGS_E_ARG, "sim: environment types too large for one persistent launch");
+    }
+  } else if (p->persistent) {
+    ags_sim_destroy(S);
+    return fail(AGS_E_ARG, "sim: a persistent launch takes at most 4 environment types");
+  }
   *out = S;
   return AGS_OK;
 }
@@ -674,6 +725,7 @@ extern "C" void ags_sim_destroy(ags_sim* S) {
     if (T.scratch) (void)hipFree(T.scratch);
   }
   if (S->env_tables) (void)hipFree(S->env_tables);
+  if (S->units) (void)hipFree(S->units);
   if (S->actor_rows) (void)hipFree(S->actor_rows);
   delete S;
 }
@@ -708,42 +760,58 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
     return fail(AGS_E_UNBOUND, "step: root state, DOF state and DOF actuation tensors must be bound");
   const ags_sim_params& p = S->params;
   const bool rows_dbg = S->bound[AGS_DEBUG_ROW_COUNT] && S->bound[AGS_DEBUG_ROW_KEY] && S->bound[AGS_DEBUG_ROW_LAMBDA];
+  StepArgs a{};
+  a.env_actor_base = S->env_tables;
+  a.env_dof_base = S->env_tables + S->n_envs;
+  a.env_body_base = S->env_tables + 2 * S->n_envs;
+  a.root_state = (float*)S->bound[AGS_ROOT_STATE];
+  a.dof_state = (float*)S->bound[AGS_DOF_STATE];
+  a.act = (const float*)S->bound[AGS_DOF_ACTUATION];
+  a.pos_tgt = (const float*)S->bound[AGS_DOF_POS_TARGET];
+  a.vel_tgt = (const float*)S->bound[AGS_DOF_VEL_TARGET];
+  a.contact_force = (float*)S->bound[AGS_NET_CONTACT_FORCE];
+  a.dof_force = (float*)S->bound[AGS_DOF_FORCE];
+  a.dbg_qdd = (float*)S->bound[AGS_DEBUG_QDD_FREE];
+  a.dbg_qdd_stride = p.substeps * S->max_nv;
+  a.dbg_qdd_sub = S->max_nv;
+  a.dbg_rc = rows_dbg ? (int*)S->bound[AGS_DEBUG_ROW_COUNT] : nullptr;
+  a.dbg_key = rows_dbg ? (int*)S->bound[AGS_DEBUG_ROW_KEY] : nullptr;
+  a.dbg_lam = rows_dbg ? (float*)S->bound[AGS_DEBUG_ROW_LAMBDA] : nullptr;
+  a.dbg_row_stride = p.substeps * std::max(1, S->max_rows);
+  a.dbg_row_sub = std::max(1, S->max_rows);
+  a.dbg_cycles = (long long*)S->bound[AGS_DEBUG_PHASE_CYCLES];
+  a.dt = p.dt;
+  a.h = (double)p.dt / p.substeps;
+  a.gx = p.gravity[0];
+  a.gy = p.gravity[1];
+  a.gz = p.gravity[2];
+  a.mu = p.mu;
+  a.beta = p.baumgarte;
+  a.mc = p.contact_margin;
+  a.substeps = p.substeps;
+  a.iters = p.pgs_iters;
+  auto type_args = [](const TypeDev& T) {
+    TypeArgs t{};
+    t.m = T.dm;
+    t.lds = T.lds;
+    t.env_list = T.env_list;
+    t.n_envs = T.n_envs;
+    t.scratch = T.scratch;
+    t.scratch_stride = T.scratch_stride;
+    return t;
+  };
+  if (S->fused_ok) {
+    FusedArgs f{};
+    f.base = a;
+    for (size_t k = 0; k < S->types.size(); ++k) f.types[k] = type_args(S->types[k]);
+    f.units = S->units;
+    f.n_units = S->n_units;
+    hipError_t e = launch_step_fused(f, S->fused_grid, S->fused_lds, p.compute_fp64, S->fused_team, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "step: launch");
+    return AGS_OK;
+  }
   for (TypeDev& T : S->types) {
-    StepArgs a{};
-    a.m = T.dm;
-    a.lds = T.lds;
-    a.env_list = T.env_list;
-    a.env_actor_base = S->env_tables;
-    a.env_dof_base = S->env_tables + S->n_envs;
-    a.env_body_base = S->env_tables + 2 * S->n_envs;
-    a.root_state = (float*)S->bound[AGS_ROOT_STATE];
-    a.dof_state = (float*)S->bound[AGS_DOF_STATE];
-    a.act = (const float*)S->bound[AGS_DOF_ACTUATION];
-    a.pos_tgt = (const float*)S->bound[AGS_DOF_POS_TARGET];
-    a.vel_tgt = (const float*)S->bound[AGS_DOF_VEL_TARGET];
-    a.contact_force = (float*)S->bound[AGS_NET_CONTACT_FORCE];
-    a.dof_force = (float*)S->bound[AGS_DOF_FORCE];
-    a.dbg_qdd = (float*)S->bound[AGS_DEBUG_QDD_FREE];
-    a.dbg_qdd_stride = p.substeps * S->max_nv;
-    a.dbg_qdd_sub = S->max_nv;
-    a.dbg_rc = rows_dbg ? (int*)S->bound[AGS_DEBUG_ROW_COUNT] : nullptr;
-    a.dbg_key = rows_dbg ? (int*)S->bound[AGS_DEBUG_ROW_KEY] : nullptr;
-    a.dbg_lam = rows_dbg ? (float*)S->bound[AGS_DEBUG_ROW_LAMBDA] : nullptr;
-    a.dbg_row_stride = p.substeps * std::max(1, S->max_rows);
-    a.dbg_row_sub = std::max(1, S->max_rows);
-    a.dbg_cycles = (long long*)S->bound[AGS_DEBUG_PHASE_CYCLES];
-    a.scratch = T.scratch;
-    a.scratch_stride = T.scratch_stride;
-    a.dt = p.dt;
-    a.h = (double)p.dt / p.substeps;
-    a.gx = p.gravity[0];
-    a.gy = p.gravity[1];
-    a.gz = p.gravity[2];
-    a.mu = p.mu;
-    a.beta = p.baumgarte;
-    a.mc = p.contact_margin;
-    a.substeps = p.substeps;
-    a.iters = p.pgs_iters;
+    a.ty = type_args(T);
     hipError_t e = launch_step(a, T.n_envs, p.compute_fp64, T.team, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "step: launch");
   }
@@ -867,6 +935,85 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
       if (rc != AGS_OK) return rc;
     }
   }
+  return AGS_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+extern "C" int ags_autotune(const ags_model* const* models, int32_t n_models, const int32_t* env_model, int32_t n_envs,
+                            ags_sim_params* params, const float* root_state, const float* dof_state,
+                            const float* actuation, int32_t n_steps, float* ms_out, void* stream) {
+  if (!models || !env_model || !params || !root_state || !dof_state || !actuation || n_steps < 1)
+    return fail(AGS_E_ARG, "autotune: bad arguments");
+  hipStream_t st = (hipStream_t)stream;
+  // candidate mappings: lanes per environment x persistent launch
+  std::vector<std::pair<int, int>> cands;
+  bool small = true;
+  for (int e = 0; e < n_envs; ++e)
+    if (env_model[e] < 0 || env_model[e] >= n_models || !models[env_model[e]]) return fail(AGS_E_ARG, "autotune: bad env model index");
+    else if (models[env_model[e]]->info.n_v > 32) small = false;
+  for (int lanes : {64, 32}) {
+    if (lanes == 32 && !small) continue;
+    for (int per : {0, 1}) cands.push_back({lanes, per});
+  }
+  ags_sim* probe = nullptr;
+  ags_sim_params p0 = *params;
+  p0.lanes_per_env = 64;
+  p0.persistent = 0;
+  int rc = ags_sim_create(models, n_models, env_model, n_envs, &p0, &probe);
+  if (rc != AGS_OK) return rc;
+  const size_t nr = 13ull * probe->n_actors_total, nd = 2ull * probe->n_dof_total, na = probe->n_dof_total;
+  ags_sim_destroy(probe);
+  float *root = nullptr, *dof = nullptr;
+  hipError_t e;
+  if ((e = hipMalloc(&root, nr * sizeof(float))) != hipSuccess) return hip_fail(e, "autotune: state copy");
+  if ((e = hipMalloc(&dof, nd * sizeof(float))) != hipSuccess) {
+    (void)hipFree(root);
+    return hip_fail(e, "autotune: state copy");
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  float best = 1e30f;
+  std::pair<int, int> pick = cands[0];
+  int status = AGS_OK;
+  for (auto c : cands) {
+    ags_sim_params pc = *params;
+    pc.lanes_per_env = c.first;
+    pc.persistent = c.second;
+    ags_sim* S = nullptr;
+    if (ags_sim_create(models, n_models, env_model, n_envs, &pc, &S) != AGS_OK) continue;  // mapping not possible
+    S->bound[AGS_ROOT_STATE] = root;
+    S->bound[AGS_DOF_STATE] = dof;
+    S->bound[AGS_DOF_ACTUATION] = const_cast<float*>(actuation);
+    float ms = 0.f;
+    for (int rep = 0; rep < 2 && status == AGS_OK; ++rep) {  // the first repetition warms up
+      if ((e = hipMemcpyAsync(root, root_state, nr * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+          (e = hipMemcpyAsync(dof, dof_state, nd * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess ||
+          (e = hipEventRecord(a, st)) != hipSuccess) {
+        status = hip_fail(e, "autotune: copy");
+        break;
+      }
+      for (int t = 0; t < n_steps && status == AGS_OK; ++t) status = ags_sim_step(S, stream);
+      if (status == AGS_OK && ((e = hipEventRecord(b, st)) != hipSuccess || (e = hipEventSynchronize(b)) != hipSuccess ||
+                               (e = hipEventElapsedTime(&ms, a, b)) != hipSuccess))
+        status = hip_fail(e, "autotune: timing");
+    }
+    ags_sim_destroy(S);
+    if (status != AGS_OK) break;
+    if (ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipFree(root);
+  (void)hipFree(dof);
+  (void)na;
+  if (status != AGS_OK) return status;
+  params->lanes_per_env = pick.first;
+  params->persistent = pick.second;
+  if (ms_out) *ms_out = best / n_steps;
   return AGS_OK;
 }
 

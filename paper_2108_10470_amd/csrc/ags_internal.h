@@ -64,10 +64,18 @@ struct DevModel {
   const int* col_link;                 // per column: the link that owns it
 };
 
-struct StepArgs {
+// one environment type of a step launch: its model tables, LDS layout, environments and scratch
+struct TypeArgs {
   DevModel m;
   Lds lds;
   const int* env_list;
+  int n_envs;
+  void* scratch;           // per env: J rows then W rows, r_cap x n_v each, in the compute type
+  long long scratch_stride;
+};
+
+struct StepArgs {
+  TypeArgs ty;  // the type of a per-type launch (unused by the fused launch)
   const int* env_actor_base;
   const int* env_dof_base;
   const int* env_body_base;
@@ -85,11 +93,22 @@ struct StepArgs {
   float* dbg_lam;
   int dbg_row_stride, dbg_row_sub;  // per env, per substep (sim-wide maximum rows)
   long long* dbg_cycles;            // per env: shader-clock cycles spent in each phase (kPhases)
-  void* scratch;           // per env: J rows then W rows, r_cap x n_v each, in the compute type
-  long long scratch_stride;
   double dt, h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
 };
+
+// One launch over every environment type: a grid sized to the device walks a work list of
+// (type, environment group) units ordered by estimated cost, heaviest first.
+constexpr int kMaxFusedTypes = 4;
+struct FusedArgs {
+  StepArgs base;
+  TypeArgs types[kMaxFusedTypes];
+  const int* units;  // 2 ints per unit: type, group
+  int n_units;
+};
+hipError_t launch_step_fused(const FusedArgs& a, int grid, size_t lds_bytes, int fp64, int team, hipStream_t stream);
+hipError_t set_fused_lds_limit(int fp64, int team, size_t bytes);
+hipError_t fused_blocks_per_cu(int fp64, int team, size_t lds_bytes, int* blocks);
 
 // ---------------------------------------------------------------- adjoint of one env-step
 constexpr int kAdjRows = 64;   // constraint rows per substep the adjoint handles (one lane each)

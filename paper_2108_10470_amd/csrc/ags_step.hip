@@ -378,15 +378,19 @@ struct Tab {
 
 // Copies the model tables into this workgroup's LDS (all lanes cooperate) and returns the view.
 template <typename R>
-__device__ __forceinline__ Tab<R> stage_tables(const DevModel& G, R* smem, const Lds& L, int t, int nthreads) {
+__device__ __forceinline__ Tab<R> stage_tables(const DevModel& G, R* smem, const Lds& L, int t, int nthreads,
+                                              bool copy) {
+  // copy = false: the tables of this type are already in LDS (pointers only)
   auto copy_i = [&](int off, const int* src, int n) {
     int* dst = reinterpret_cast<int*>(smem + off);
-    for (int k = t; k < n; k += nthreads) dst[k] = src[k];
+    if (copy)
+      for (int k = t; k < n; k += nthreads) dst[k] = src[k];
     return (const int*)dst;
   };
   auto copy_r = [&](int off, const double* src, int n) {
     R* dst = smem + off;
-    for (int k = t; k < n; k += nthreads) dst[k] = R(src[k]);
+    if (copy)
+      for (int k = t; k < n; k += nthreads) dst[k] = R(src[k]);
     return (const R*)dst;
   };
   Tab<R> T;
@@ -478,18 +482,21 @@ __device__ __forceinline__ R point_row(const Tab<R>& M, const Ctx<R, EPW>& s, in
 
 }  // namespace
 
+// One env-step of the environments of group `group` of type T (EPW environments per wavefront).
+// stage: copy T's model tables into LDS (false when the previous group of this workgroup had the same type).
 template <typename R, int TEAM>
-__global__ __launch_bounds__(64) void step_kernel(StepArgs P, int n_envs) {
+__device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T, int group, bool stage) {
   R* smem = reinterpret_cast<R*>(g_lds);
-  const Lds& L = P.lds;
+  const Lds& L = T.lds;
+  const int n_envs = T.n_envs;
   constexpr int EPW = kTeam / TEAM;  // environments per wavefront
   const int t = threadIdx.x;         // lane in the wavefront
   const int tm = EPW == 1 ? 0 : t / TEAM;  // team (environment slot) of this lane
   const int tt = EPW == 1 ? t : t % TEAM;  // lane within the team
-  const int gidx = blockIdx.x * EPW + tm;
+  const int gidx = group * EPW + tm;
   const bool valid = gidx < n_envs;  // the last wavefront's spare teams recompute an env but write nothing
-  const int env = P.env_list[valid ? gidx : n_envs - 1];
-  const Tab<R> M = stage_tables<R>(P.m, smem, L, t, kTeam);
+  const int env = T.env_list[valid ? gidx : n_envs - 1];
+  const Tab<R> M = stage_tables<R>(T.m, smem, L, t, kTeam, stage);
   Ctx<R, EPW> s;
   s.init(L.team_base, L, tm);
   __syncthreads();
@@ -498,7 +505,7 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P, int n_envs) {
   const int abase = P.env_actor_base[env], dbase = P.env_dof_base[env], bbase = P.env_body_base[env];
   const R h = R(P.h);
   const V3<R> grav = mk(R(P.gx), R(P.gy), R(P.gz));
-  R* Jg = reinterpret_cast<R*>(P.scratch) + (long long)gidx * P.scratch_stride;
+  R* Jg = reinterpret_cast<R*>(T.scratch) + (long long)gidx * T.scratch_stride;
   R* Wg = Jg + (long long)M.r_cap * nv;
 
   // ---------------------------------------------------------------- load state
@@ -1217,6 +1224,24 @@ __global__ __launch_bounds__(64) void step_kernel(StepArgs P, int n_envs) {
   }
 }
 
+template <typename R, int TEAM>
+__global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
+  step_group<R, TEAM>(P, P.ty, blockIdx.x, true);
+}
+
+// persistent form: each workgroup walks the work list with a grid stride; the list is ordered by
+// estimated cost, so the heaviest groups start first and the tail is made of the cheapest ones
+template <typename R, int TEAM>
+__global__ __launch_bounds__(64) void step_fused(FusedArgs A) {
+  int prev = -1;
+  for (int u = blockIdx.x; u < A.n_units; u += gridDim.x) {
+    const int ty = A.units[2 * u], grp = A.units[2 * u + 1];
+    __syncthreads();
+    step_group<R, TEAM>(A.base, A.types[ty], grp, ty != prev);
+    prev = ty;
+  }
+}
+
 // Copy the rows of the listed actors from src to dst (same layout).  table holds 4 ints per actor:
 // root row, root row count (1), first DOF row, DOF row count; `field` selects the pair (0 root, 2 DOF).
 __global__ void set_rows_kernel(float* dst, const float* src, const int* idx, int n, int n_actors, const int* table,
@@ -1236,16 +1261,45 @@ __global__ void set_rows_kernel(float* dst, const float* src, const int* idx, in
 template <typename R, int TEAM>
 static hipError_t launch_one(const StepArgs& a, int n_envs, hipStream_t stream) {
   constexpr int EPW = kTeam / TEAM;
-  const size_t lds = (size_t)a.lds.total * sizeof(R);
+  const size_t lds = (size_t)a.ty.lds.total * sizeof(R);
   const int grid = (n_envs + EPW - 1) / EPW;
-  hipLaunchKernelGGL((step_kernel<R, TEAM>), dim3(grid), dim3(kTeam), lds, stream, a, n_envs);
+  hipLaunchKernelGGL((step_kernel<R, TEAM>), dim3(grid), dim3(kTeam), lds, stream, a);
   return hipGetLastError();
+}
+
+template <typename R, int TEAM>
+static const void* fused_fn() {
+  return (const void*)step_fused<R, TEAM>;
+}
+static const void* fused_kernel(int fp64, int team) {
+  return fp64 ? (team == 32 ? fused_fn<double, 32>() : fused_fn<double, 64>())
+              : (team == 32 ? fused_fn<float, 32>() : fused_fn<float, 64>());
 }
 
 hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStream_t stream) {
   if (n_envs <= 0) return hipSuccess;
   if (fp64) return team == 32 ? launch_one<double, 32>(a, n_envs, stream) : launch_one<double, 64>(a, n_envs, stream);
   return team == 32 ? launch_one<float, 32>(a, n_envs, stream) : launch_one<float, 64>(a, n_envs, stream);
+}
+
+hipError_t launch_step_fused(const FusedArgs& a, int grid, size_t lds_bytes, int fp64, int team, hipStream_t stream) {
+  if (a.n_units <= 0) return hipSuccess;
+  if (fp64) {
+    if (team == 32) hipLaunchKernelGGL((step_fused<double, 32>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
+    else hipLaunchKernelGGL((step_fused<double, 64>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
+  } else {
+    if (team == 32) hipLaunchKernelGGL((step_fused<float, 32>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
+    else hipLaunchKernelGGL((step_fused<float, 64>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t set_fused_lds_limit(int fp64, int team, size_t bytes) {
+  return hipFuncSetAttribute(fused_kernel(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t fused_blocks_per_cu(int fp64, int team, size_t lds_bytes, int* blocks) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fused_kernel(fp64, team), kTeam, lds_bytes);
 }
 
 hipError_t set_lds_limit(int fp64, int team, size_t bytes) {

@@ -279,6 +279,39 @@ def arm_with_gripper() -> Actor:
     return Actor("arm", links, root_pos=(0.0, 0.0, 0.0), init_q_halfwidth=0.1)
 
 
+def hand(kp: float = 3.0, kd: float = 0.1, z: float = 0.3) -> Actor:
+    """Fixed-base hand-like tree with 24 DOFs, palm up: palm box 0.10 x 0.10 x 0.02 m carrying three palm-top
+    capsules (r 0.01) so that palm-object contact is capsule-box, four fingers of five links (abduction about
+    the palm normal, then four flexions) along +x and a four-link thumb along -y.  Finger capsules have
+    r = 0.01 and lengths 0.05, 0.04, 0.04, 0.03, 0.03; flexion limits [0, 1.57], abduction +-0.35.
+    Every DOF is driven by a PD drive (kp, kd)."""
+    palm_shapes = [Shape("box", (0.0, 0.0, 0.0), half=(0.05, 0.05, 0.01))]
+    for x in (-0.03, 0.0, 0.03):
+        palm_shapes.append(_capsule((x, -0.04, 0.0), (x, 0.04, 0.0), 0.01))
+    links = [Link("palm", -1, "fixed", shapes=palm_shapes)]
+    lengths = (0.05, 0.04, 0.04, 0.03, 0.03)
+
+    def chain(name, base_anchor, along, flex_axis, n_links):
+        parent = 0
+        anchor = base_anchor
+        for k in range(n_links):
+            L = lengths[k]
+            tip = tuple(L * a for a in along)
+            if k == 0:
+                links.append(Link(f"{name}_abd", parent, "revolute", anchor=anchor, axis=(0.0, 0.0, 1.0),
+                                  lower=-0.35, upper=0.35, kp=kp, kd=kd, gear=1.0, shapes=[_capsule((0, 0, 0), tip, 0.01)]))
+            else:
+                links.append(Link(f"{name}_f{k}", parent, "revolute", anchor=anchor, axis=flex_axis,
+                                  lower=0.0, upper=1.57, kp=kp, kd=kd, gear=1.0, shapes=[_capsule((0, 0, 0), tip, 0.01)]))
+            parent = len(links) - 1
+            anchor = tip
+
+    for i, y in enumerate((-0.0375, -0.0125, 0.0125, 0.0375)):
+        chain(f"finger{i}", (0.06, y, 0.0), (1.0, 0.0, 0.0), (0.0, -1.0, 0.0), 5)
+    chain("thumb", (-0.02, -0.06, 0.0), (0.0, -1.0, 0.0), (-1.0, 0.0, 0.0), 4)
+    return Actor("hand", links, root_pos=(0.0, 0.0, z))
+
+
 # ----------------------------------------------------------------------------
 # environments (actors + collision pairs)
 # ----------------------------------------------------------------------------
@@ -313,6 +346,24 @@ def env_arm_box() -> EnvSpec:
             if s.kind == "capsule":
                 pairs.append(Pair(0, li, si, 1, 0, 0))
     return EnvSpec("arm_box", actors, pairs)
+
+
+def env_hand_cube(z: float = 0.3) -> EnvSpec:
+    """The hand holding a free cube (edge 0.065 m, 0.1 kg) that rests on the palm-top capsules; pairs: every
+    capsule of the hand against the cube, and the cube against the ground."""
+    h = hand(z=z)
+    cube = free_box(half=(0.0325, 0.0325, 0.0325), mass=0.1, pos=(0.0, 0.0, z + 0.01 + 0.0325))
+    actors = [h, cube]
+    pairs = []
+    for li, l in enumerate(h.links):
+        for si, sh in enumerate(l.shapes):
+            if sh.kind == "capsule":
+                pairs.append(Pair(0, li, si, 1, 0, 0))
+    pairs.append(Pair(1, 0, 0))
+    return EnvSpec("hand_cube", actors, pairs)
+
+
+HAND_PARAMS = SimParams(pgs_iters=12, contact_margin=0.003)
 
 
 # ----------------------------------------------------------------------------

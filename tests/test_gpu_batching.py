@@ -1,0 +1,190 @@
+"""Batching on the GPU: heterogeneous environments in one sim, the indexed set API, and parity sampled
+from a full-size batch in the launch configuration the benchmark times."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2108_10470_amd import ags, workloads as W
+
+from . import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+
+
+def _report(name, d):
+    print(name, json.dumps(d), flush=True)
+    if os.path.isdir(OUT):
+        with open(os.path.join(OUT, "parity.jsonl"), "a") as f:
+            f.write(json.dumps({"case": name, **d}) + "\n")
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_heterogeneous_batch_matches_per_type_oracle(fp64):
+    """Ant-like, humanoid-like and arm+gripper+box environments interleaved in one sim (box-plane and
+    capsule-box contacts included); every env's step is compared with the oracle of its own type."""
+    specs = [W.env_ant(), W.env_humanoid(), W.env_arm_box()]
+    p = W.params_f32(W.SimParams())
+    per = []
+    for spec in specs:
+        oe, root, dof, act = PT.oracle_states(spec, W.SimParams(), n_envs=8, n_steps=60, every=6)
+        per.append((W.as_f32(spec), oe, root, dof, act))
+    n = min(x[2].shape[0] for x in per)
+    E = 3 * n
+    env_model = [e % 3 for e in range(E)]
+    models = [ags.Model(x[0]) for x in per]
+    sim = ags.Sim(models, env_model, p, device="cuda:0", debug=True, fp64=fp64)
+    r32 = lambda x: x.astype(np.float32).astype(np.float64)
+    roots, dofs, acts = [], [], []
+    for e in range(E):
+        t, k = e % 3, e // 3
+        roots.append(r32(per[t][2][k]).reshape(-1, 13))
+        dofs.append(r32(per[t][3][k]).reshape(-1, 2))
+        acts.append(r32(per[t][4][k]).reshape(-1))
+    dev = sim.device
+    sim.root_state.copy_(torch.tensor(np.concatenate(roots), dtype=torch.float32, device=dev))
+    sim.dof_state.copy_(torch.tensor(np.concatenate(dofs), dtype=torch.float32, device=dev))
+    sim.actuation.copy_(torch.tensor(np.concatenate(acts), dtype=torch.float32, device=dev))
+    sim.dbg_rc.zero_()
+    sim.dbg_key.fill_(-1)
+    sim.step()
+    torch.cuda.synchronize()
+    root_out = sim.root_state.double().cpu().numpy()
+    dof_out = sim.dof_state.double().cpu().numpy()
+    S = p.substeps
+    qdd = sim.dbg_qdd.double().cpu().numpy().reshape(E, S, -1)
+    rc = sim.dbg_rc.cpu().numpy().reshape(E, S)
+    key = sim.dbg_key.cpu().numpy().reshape(E, S, -1)
+    lam = sim.dbg_lam.double().cpu().numpy().reshape(E, S, -1)
+    abase = np.cumsum([0] + [specs[m].n_actors for m in env_model])
+    dbase = np.cumsum([0] + [specs[m].n_dof for m in env_model])
+    for t, (spec, oe, _, _, _) in enumerate(per):
+        ids = [e for e in range(E) if env_model[e] == t]
+        g = dict(root=np.stack([root_out[abase[e]:abase[e + 1]] for e in ids]),
+                 dof=np.stack([dof_out[dbase[e]:dbase[e + 1]] for e in ids]),
+                 qdd_free=qdd[ids][:, :, :spec.n_v], row_count=rc[ids], row_key=key[ids], row_lambda=lam[ids])
+        o = oe.step(p, np.stack([roots[e].reshape(spec.n_actors, 13) for e in ids]),
+                    np.stack([dofs[e].reshape(spec.n_dof, 2) for e in ids]), np.stack([acts[e] for e in ids]),
+                    r_cap=key.shape[2])
+        s = PT.summarize(PT.compare(spec, p, g, o))
+        s["mean_rows"] = float(o["row_count"].mean())
+        _report(f"hetero_{spec.name}_{'fp64' if fp64 else 'fp32'}", s)
+        assert np.isfinite(g["root"]).all() and np.isfinite(g["dof"]).all()
+        assert s["rows_mismatch_not_near"] == 0, s
+        if fp64:
+            for k in ("qdd_free", "q", "lambda"):
+                assert s[k + "_pass_rate"] == 1.0, (spec.name, k, s)
+
+
+def test_indexed_set_semantics():
+    """Setting root states teleports only the listed actors and leaves DOF states alone; setting DOF
+    states leaves root states alone (Section 2.3.2 indexed set)."""
+    env = W.env_humanoid()
+    E = 16
+    sim = ags.Sim([ags.Model(env)], [0] * E, W.SimParams(), device="cuda:0")
+    root, dof = W.initial_state(env, E, 0)
+    sim.root_state.copy_(torch.tensor(root.reshape(-1, 13), dtype=torch.float32))
+    sim.dof_state.copy_(torch.tensor(dof.reshape(-1, 2), dtype=torch.float32))
+    r0, d0 = sim.root_state.clone(), sim.dof_state.clone()
+    src_r = torch.randn_like(sim.root_state)
+    idx = torch.tensor([3, 7, 11], dtype=torch.int32, device="cuda:0")
+    sim.set_root_state_indexed(src_r, idx)
+    torch.cuda.synchronize()
+    want = r0.clone()
+    want[idx.long()] = src_r[idx.long()]
+    assert torch.equal(sim.root_state, want)
+    assert torch.equal(sim.dof_state, d0)
+    src_d = torch.randn_like(sim.dof_state)
+    sim.set_dof_state_indexed(src_d, idx)
+    torch.cuda.synchronize()
+    nd = env.n_dof
+    want_d = d0.clone()
+    for a in idx.tolist():
+        want_d[a * nd:(a + 1) * nd] = src_d[a * nd:(a + 1) * nd]
+    assert torch.equal(sim.dof_state, want_d)
+    assert torch.equal(sim.root_state, want)
+    # all actors (no index) and an out-of-range index (ignored)
+    sim.set_root_state_indexed(src_r, torch.tensor([E + 5], dtype=torch.int32, device="cuda:0"))
+    torch.cuda.synchronize()
+    assert torch.equal(sim.root_state, want)
+    sim.set_root_state_indexed(src_r)
+    torch.cuda.synchronize()
+    assert torch.equal(sim.root_state, src_r)
+
+
+def test_full_size_batch_sampled_parity():
+    """4096 humanoid-like envs stepped in the launch configuration the benchmark times (FP64 compute,
+    default lanes per env, no debug outputs).  At steps 0, 40 and 120, 64 sampled envs are stepped by the
+    oracle from the same FP32 state and compared on the next state's positions."""
+    env = W.as_f32(W.env_humanoid())
+    p = W.params_f32(W.SimParams())
+    E = 4096
+    oe = O.OracleEnv(env)
+    sim = ags.Sim([ags.Model(env)], [0] * E, p, device="cuda:0", fp64=True)
+    root, dof = W.initial_state(env, E, 0)
+    sim.root_state.copy_(torch.tensor(root.reshape(-1, 13), dtype=torch.float32))
+    sim.dof_state.copy_(torch.tensor(dof.reshape(-1, 2), dtype=torch.float32))
+    acts = W.actuation(env, E, 121, 0).astype(np.float32)
+    sample = np.random.default_rng(3).choice(E, 64, replace=False)
+    nd = env.n_dof
+    worst = []
+    for t in range(121):
+        check = t in (0, 40, 120)
+        if check:
+            r_in = sim.root_state.double().cpu().numpy().reshape(E, 1, 13)[sample]
+            d_in = sim.dof_state.double().cpu().numpy().reshape(E, nd, 2)[sample]
+        sim.actuation.copy_(torch.from_numpy(acts[t].reshape(-1)).to("cuda:0"))
+        sim.step()
+        if check:
+            torch.cuda.synchronize()
+            r_out = sim.root_state.double().cpu().numpy().reshape(E, 1, 13)[sample]
+            d_out = sim.dof_state.double().cpu().numpy().reshape(E, nd, 2)[sample]
+            o = oe.step(p, r_in, d_in, acts[t][sample].astype(np.float64))
+            near = (o["near"] != 0).any(axis=1)
+            pos_g = np.concatenate([r_out[:, :, :7].reshape(64, -1), d_out[:, :, 0]], axis=1)
+            pos_o = np.concatenate([o["root"][:, :, :7].reshape(64, -1), o["dof"][:, :, 0]], axis=1)
+            ratio = PT.ratio(pos_g, pos_o).max(axis=1)
+            worst.append(float(ratio[~near].max()) if (~near).any() else 0.0)
+            _report(f"fullsize_humanoid4096_step{t}", {"sampled": 64, "near_switch": int(near.sum()),
+                                                       "q_max_ratio": worst[-1]})
+    assert max(worst) <= 1.0
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_persistent_launch_is_bitwise_equal_to_per_type_launches(fp64):
+    """The one-launch persistent form over a heterogeneous batch gives exactly the per-type launches'
+    results (same arithmetic, different work distribution), over several steps."""
+    specs = [W.env_ant(), W.env_humanoid(), W.env_arm_box()]
+    E, T = 3 * 200 + 1, 5
+    env_model = [(e * 7) % 3 for e in range(E)]
+    p = W.SimParams()
+    sims = [ags.Sim([ags.Model(s) for s in specs], env_model, p, device="cuda:0", fp64=fp64, persistent=per)
+            for per in (False, True)]
+    roots, dofs, acts = [], [], []
+    for e in range(E):
+        spec = specs[env_model[e]]
+        r, d = W.initial_state(spec, 1, seed=e)
+        roots.append(r.reshape(-1, 13))
+        dofs.append(d.reshape(-1, 2))
+        acts.append(W.actuation(spec, 1, T, seed=e)[:, 0])
+    r0 = torch.tensor(np.concatenate(roots), dtype=torch.float32, device="cuda:0")
+    d0 = torch.tensor(np.concatenate(dofs), dtype=torch.float32, device="cuda:0")
+    a = torch.tensor(np.concatenate(acts, axis=1), dtype=torch.float32, device="cuda:0")
+    outs = []
+    for sim in sims:
+        sim.root_state.copy_(r0)
+        sim.dof_state.copy_(d0)
+        for t in range(T):
+            sim.actuation.copy_(a[t])
+            sim.step()
+        torch.cuda.synchronize()
+        outs.append((sim.root_state.clone(), sim.dof_state.clone(), sim.contact_force.clone(), sim.dof_force.clone()))
+    for x, y in zip(*outs):
+        assert torch.isfinite(x).all()
+        assert torch.equal(x, y)
