@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous-batch measurement")
     ap.add_argument("--hetero-envs", type=int, default=16384)
     ap.add_argument("--hetero-steps", type=int, default=100)
+    ap.add_argument("--no-hand", action="store_true", help="skip the 65536-env hand+cube measurement")
+    ap.add_argument("--hand-envs", type=int, default=65536)
+    ap.add_argument("--hand-steps", type=int, default=32)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scale reference for HBM counters)")
     return ap.parse_args()
@@ -147,13 +150,14 @@ def mean_rows(env, params, n_envs, steps, fp64, actions_dev, root0, dof0):
     return float(acc.item() / steps)
 
 
-def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps):
+def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, adjoint_precision=0):
     """Forward rollout of T = len(actions) steps with a checkpoint every `every` steps, then the reverse
     pass (segment recomputation + adjoint of every step) for L = sum of final root x positions."""
     import ctypes
     import torch
     from paper_2108_10470_amd import ags
-    sim = ags.Sim([ags.Model(env)], [0] * n_envs, params, device="cuda:0", fp64=fp64)
+    sim = ags.Sim([ags.Model(env)], [0] * n_envs, params, device="cuda:0", fp64=fp64,
+                  adjoint_precision=adjoint_precision)
     L = ags.lib()
     T = actions.shape[0]
     n = ctypes.c_int64()
@@ -174,12 +178,12 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps):
         sim.dof_state.copy_(dof0)
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record(stream)
-        ags._check(L.ags_rollout_forward(sim.h, T, every, P(actions), P(ckpt), sp), "rollout_forward")
+        ags._check(L.ags_rollout_forward(sim.h, T, every, ags.DOF_ACTUATION, P(actions), P(ckpt), sp), "rollout_forward")
         e1.record(stream)
         root_adj.zero_()
         root_adj[:, 0] = 1.0
         dof_adj.zero_()
-        ags._check(L.ags_rollout_backward(sim.h, T, every, P(actions), P(ckpt), P(seg), P(root_adj), P(dof_adj),
+        ags._check(L.ags_rollout_backward(sim.h, T, every, ags.DOF_ACTUATION, P(actions), P(ckpt), P(seg), P(root_adj), P(dof_adj),
                                           P(act_adj), P(status), sp), "rollout_backward")
         e2.record(stream)
         torch.cuda.synchronize()
@@ -204,6 +208,7 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps):
             "ms_forward": fwd, "ms_backward": bwd, "adjoint_launch_ms": adj_ms,
             "envs_over_row_capacity": int((status != 0).sum()), "finite": bool(torch.isfinite(act_adj).all()),
             "grad_abs_mean": float(act_adj.abs().mean()), "dtype": "f64" if fp64 else "f32",
+            "adjoint_dtype": "f64" if adjoint_precision == 64 or (adjoint_precision == 0 and fp64) else "f32",
             "loss": "sum over envs of the final torso x position", "reps": reps}
 
 
@@ -259,6 +264,41 @@ def run_hetero(params, n_envs, steps, fp64):
     lanes, per, ms = ags.autotune(models, env_model, params, r0, d0, a[0].contiguous(), fp64=fp64, n_steps=10)
     out["autotuned"] = {"lanes_per_env": lanes, "persistent": per, "ms_per_step": ms}
     return out
+
+
+def run_hand(n_envs, steps, fp64):
+    """Scale workload: hand-like 24-DOF tree holding a free cube, PD drive toward targets re-drawn every
+    step, capsule-box and box-plane contacts, 12 Gauss-Seidel sweeps; forward steps only."""
+    import torch
+    from paper_2108_10470_amd import ags, workloads as W
+    env = W.env_hand_cube()
+    p = W.HAND_PARAMS
+    sim = ags.Sim([ags.Model(env)], [0] * n_envs, p, device="cuda:0", fp64=fp64, pd=True)
+    root, dof = W.initial_state(env, n_envs, 0)
+    r0 = torch.tensor(root.reshape(-1, 13), dtype=torch.float32, device="cuda:0")
+    d0 = torch.tensor(dof.reshape(-1, 2), dtype=torch.float32, device="cuda:0")
+    tg = torch.tensor(W.pd_targets(env, n_envs, steps, 0).reshape(steps, -1), dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    sim.root_state.copy_(r0)
+    sim.dof_state.copy_(d0)
+    for t in range(min(5, steps)):
+        sim.bind(ags.DOF_POS_TARGET, tg[t])
+        sim.step()
+    sim.root_state.copy_(r0)
+    sim.dof_state.copy_(d0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for t in range(steps):
+        sim.bind(ags.DOF_POS_TARGET, tg[t])
+        sim.step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"workload": f"hand-like 24-DOF tree + free cube, {n_envs} envs, PD targets re-drawn each step, "
+                        "capsule-box and box-plane contacts, 12 sweeps", "envs": n_envs, "steps": steps,
+            "dtype": "f64" if fp64 else "f32", "ms_per_step": ms, "env_steps_per_s": n_envs / (ms / 1e3),
+            "finite": bool(torch.isfinite(sim.root_state).all() and torch.isfinite(sim.dof_state).all())}
 
 
 def cpu_baseline(env, params, n_envs, n_steps):
@@ -322,13 +362,21 @@ def main():
     if not args.no_hetero:
         hetero = run_hetero(params, args.hetero_envs, args.hetero_steps, head == "fp64")
         print(f"[bench] heterogeneous batch: {json.dumps(hetero)}", file=sys.stderr, flush=True)
+    hand = None
+    if not args.no_hand:
+        hand = run_hand(args.hand_envs, args.hand_steps, head == "fp64")
+        print(f"[bench] hand: {json.dumps(hand)}", file=sys.stderr, flush=True)
     fwd_bwd = None
     if not args.no_fwd_bwd:
         T = args.fwd_bwd_steps
         acts_fb = torch.stack(actions_dev[:T]).contiguous()
         fwd_bwd = run_fwd_bwd(env, params, E, head == "fp64", acts_fb, root0, dof0, args.fwd_bwd_every,
-                              args.fwd_bwd_reps)
-        print(f"[bench] fwd+bwd ({head}): {json.dumps(fwd_bwd)}", file=sys.stderr, flush=True)
+                              args.fwd_bwd_reps, adjoint_precision=32)
+        print(f"[bench] fwd+bwd ({head} forward, f32 adjoint): {json.dumps(fwd_bwd)}", file=sys.stderr, flush=True)
+        fb64 = run_fwd_bwd(env, params, E, head == "fp64", acts_fb, root0, dof0, args.fwd_bwd_every,
+                           args.fwd_bwd_reps, adjoint_precision=64)
+        print(f"[bench] fwd+bwd ({head} forward, f64 adjoint): {json.dumps(fb64)}", file=sys.stderr, flush=True)
+        fwd_bwd["f64_adjoint"] = {k: fb64[k] for k in ("value", "ms_forward", "ms_backward", "adjoint_launch_ms")}
     h = res[head]
     value = E * K / (h["total_ms"] / 1e3)
     t_launch = float(h["launch_ms"].mean()) / 1e3
@@ -353,6 +401,7 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0)"},
         "fwd_bwd": fwd_bwd,
         "batching": hetero,
+        "hand": hand,
         "variants": {k: {"env_steps_per_s": E * K / (v["total_ms"] / 1e3), "ms_per_step": v["total_ms"] / K,
                          "launch_ms": float(v["launch_ms"].mean()), "mean_rows_per_substep": v["rows"],
                          "graph_ms_per_step": v["graph_ms"],

@@ -122,6 +122,8 @@ typedef struct {
   int32_t lanes_per_env;    /* 0: automatic; 32 or 64: lanes of a wavefront given to one environment */
   int32_t persistent;       /* 1: one launch for all environment types (a grid sized to the device walks a work
                                list ordered by estimated cost, heaviest first); 0: one launch per type */
+  int32_t adjoint_precision;  /* ags_sim_step_backward computes in: 0 the precision of compute_fp64, 32 FP32,
+                                 64 FP64 */
 } ags_sim_params;
 
 typedef struct ags_sim ags_sim;
@@ -145,6 +147,10 @@ void ags_sim_destroy(ags_sim* sim);
  *   AGS_DEBUG_ROW_COUNT    (E, substeps)  int32          constraint rows per substep
  *   AGS_DEBUG_ROW_KEY      (E, substeps * max rows) int32  row keys (kind << 24 | a << 8 | b)
  *   AGS_DEBUG_ROW_LAMBDA   (E, substeps * max rows)      row impulses after the last sweep
+ *   AGS_DEBUG_ADJ_CYCLES   (E, 8)   int64                shader-clock cycles per phase of ags_sim_step_backward
+ *                          (recompute except Gauss-Seidel, recompute Gauss-Seidel, reverse Gauss-Seidel, reverse
+ *                          dense products, reverse mass-matrix terms, reverse RNEA, reverse rows and wrenches,
+ *                          reverse integration and solves), for profiling
  *   AGS_DEBUG_PHASE_CYCLES (E, 10)  int64                shader-clock cycles per phase of the step (controls,
  *                          forward sweep, inward sweep, outward sweep, v* sweep, narrow phase, rows,
  *                          row responses, Gauss-Seidel, outputs), for profiling
@@ -153,7 +159,7 @@ void ags_sim_destroy(ags_sim* sim);
 enum {
   AGS_ROOT_STATE = 0, AGS_DOF_STATE, AGS_DOF_ACTUATION, AGS_DOF_POS_TARGET, AGS_DOF_VEL_TARGET,
   AGS_NET_CONTACT_FORCE, AGS_DOF_FORCE, AGS_DEBUG_QDD_FREE, AGS_DEBUG_ROW_COUNT, AGS_DEBUG_ROW_KEY,
-  AGS_DEBUG_ROW_LAMBDA, AGS_DEBUG_PHASE_CYCLES, AGS_NUM_TENSORS
+  AGS_DEBUG_ROW_LAMBDA, AGS_DEBUG_PHASE_CYCLES, AGS_DEBUG_ADJ_CYCLES, AGS_NUM_TENSORS
 };
 int ags_sim_tensor_shape(const ags_sim* sim, int32_t which, int64_t* rows, int64_t* cols);
 /* Bind a device pointer (NULL unbinds).  The memory must hold rows x cols elements and stay valid
@@ -178,10 +184,9 @@ int ags_sim_step(ags_sim* sim, void* hip_stream);
  * the recomputed step takes (a mode switch is where the step is not differentiable).  Quaternion
  * adjoints are tangent to the unit sphere; the pose of a fixed root is a constant (its adjoint rows
  * come back zero); PD targets receive no adjoint.
- * Limits: plane contacts only (models with sphere/capsule-vs-box pairs return AGS_E_MODEL), at most
- * 32 Gauss-Seidel sweeps, at most 64 constraint rows per environment and substep: an environment
+ * Limits: at most 32 Gauss-Seidel sweeps, at most 64 constraint rows per environment and substep: an environment
  * whose substep has more gets zero adjoints and status[env] = 1 (status: optional device int32 per
- * environment, 0 on success).  Computes in the precision of compute_fp64. */
+ * environment, 0 on success).  Computes in the precision chosen by adjoint_precision. */
 int ags_sim_step_backward(ags_sim* sim, const float* root_state, const float* dof_state, const float* actuation,
                           float* root_adj, float* dof_adj, float* act_adj, int32_t* status, void* hip_stream);
 
@@ -201,19 +206,22 @@ int ags_autotune(const ags_model* const* models, int32_t n_models, const int32_t
  * simulation).  A state is 13 N_A + 2 N_D floats: the root-state rows, then the DOF-state rows. */
 int ags_rollout_state_size(const ags_sim* sim, int64_t* floats);
 /* n_steps env-steps from the bound root/DOF state tensors (advanced in place to the final state) with
- * actions[t] = actions + t N_D (device, n_steps x N_D) as the actuation of step t; the state before
- * every `every`-th step (t = 0, every, 2 every, ...) is copied to ckpt (device, ceil(n_steps / every)
- * states).  The bound actuation tensor is left as it was. */
-int ags_rollout_forward(ags_sim* sim, int32_t n_steps, int32_t every, const float* actions, float* ckpt,
-                        void* hip_stream);
-/* Reverse pass of a rollout made by ags_rollout_forward with the same n_steps, every, actions and
- * ckpt: root_adj / dof_adj hold dL/d(final state) on entry and dL/d(initial state) on return;
- * act_adj (device, n_steps x N_D) receives dL/d actions[t].  seg is caller-owned device scratch of
- * `every` states: each segment is recomputed from its checkpoint with ags_sim_step (output tensors
- * untouched) and its steps are reversed with ags_sim_step_backward (status as there). */
-int ags_rollout_backward(ags_sim* sim, int32_t n_steps, int32_t every, const float* actions, const float* ckpt,
-                         float* seg, float* root_adj, float* dof_adj, float* act_adj, int32_t* status,
-                         void* hip_stream);
+ * actions[t] = actions + t N_D (device, n_steps x N_D) as the control of step t: the actuation
+ * (control = AGS_DOF_ACTUATION) or the PD position targets (control = AGS_DOF_POS_TARGET; the bound
+ * actuation tensor then supplies the actuation of every step).  The state before every `every`-th step
+ * (t = 0, every, 2 every, ...) is copied to ckpt (device, ceil(n_steps / every) states).  The bound
+ * tensors are left as they were. */
+int ags_rollout_forward(ags_sim* sim, int32_t n_steps, int32_t every, int32_t control, const float* actions,
+                        float* ckpt, void* hip_stream);
+/* Reverse pass of a rollout made by ags_rollout_forward with the same n_steps, every, control, actions
+ * and ckpt: root_adj / dof_adj hold dL/d(final state) on entry and dL/d(initial state) on return;
+ * act_adj (device, n_steps x N_D) receives dL/d actions[t] (for PD targets, kp dL/d(joint force): the
+ * target enters the step only through the drive force kp (q* - q - h qd)).  seg is caller-owned device
+ * scratch of `every` states: each segment is recomputed from its checkpoint with ags_sim_step (output
+ * tensors untouched) and its steps are reversed with ags_sim_step_backward (status as there). */
+int ags_rollout_backward(ags_sim* sim, int32_t n_steps, int32_t every, int32_t control, const float* actions,
+                         const float* ckpt, float* seg, float* root_adj, float* dof_adj, float* act_adj,
+                         int32_t* status, void* hip_stream);
 
 /* Copy rows of src (same shape as the bound tensor) into the bound root / DOF state tensor for the
  * actors listed in actor_idx (device int32 array of n global actor indices; NULL = all actors).

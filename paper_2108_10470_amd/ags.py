@@ -20,7 +20,8 @@ JOINT = {"free": 0, "fixed": 1, "revolute": 2, "prismatic": 3}
 SHAPE = {"sphere": 0, "capsule": 1, "box": 2}
 
 ROOT_STATE, DOF_STATE, DOF_ACTUATION, DOF_POS_TARGET, DOF_VEL_TARGET, NET_CONTACT_FORCE, DOF_FORCE, \
-    DEBUG_QDD_FREE, DEBUG_ROW_COUNT, DEBUG_ROW_KEY, DEBUG_ROW_LAMBDA, DEBUG_PHASE_CYCLES, NUM_TENSORS = range(13)
+    DEBUG_QDD_FREE, DEBUG_ROW_COUNT, DEBUG_ROW_KEY, DEBUG_ROW_LAMBDA, DEBUG_PHASE_CYCLES, DEBUG_ADJ_CYCLES, \
+    NUM_TENSORS = range(14)
 PHASES = ["controls", "forward", "inward", "outward", "vstar", "narrow", "rows", "responses", "pgs", "outputs"]
 
 
@@ -56,7 +57,8 @@ class SimParams(ctypes.Structure):
                 ("pgs_iters", ctypes.c_int32), ("mu", ctypes.c_float), ("baumgarte", ctypes.c_float),
                 ("contact_margin", ctypes.c_float), ("limit_margin_rev", ctypes.c_float),
                 ("limit_margin_pri", ctypes.c_float), ("compute_fp64", ctypes.c_int32),
-                ("lanes_per_env", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("lanes_per_env", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("adjoint_precision", ctypes.c_int32)]
 
 
 _lib = None
@@ -88,8 +90,8 @@ def lib():
         L.ags_rollout_state_size.argtypes = [vp, i64p]
         L.ags_autotune.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_int32), i32, ctypes.POINTER(SimParams),
                                    vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
-        L.ags_rollout_forward.argtypes = [vp, i32, i32, vp, vp, vp]
-        L.ags_rollout_backward.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ags_rollout_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+        L.ags_rollout_backward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -155,9 +157,11 @@ class Model:
             self.h = None
 
 
-def sim_params(p, fp64: bool = False, lanes_per_env: int = 0, persistent: bool = False) -> SimParams:
+def sim_params(p, fp64: bool = False, lanes_per_env: int = 0, persistent: bool = False,
+               adjoint_precision: int = 0) -> SimParams:
     return SimParams(p.dt, p.substeps, _f3(p.gravity), p.pgs_iters, p.mu, p.baumgarte, p.contact_margin,
-                     p.limit_margin_rev, p.limit_margin_pri, 1 if fp64 else 0, lanes_per_env, 1 if persistent else 0)
+                     p.limit_margin_rev, p.limit_margin_pri, 1 if fp64 else 0, lanes_per_env, 1 if persistent else 0,
+                     adjoint_precision)
 
 
 class Sim:
@@ -165,7 +169,7 @@ class Sim:
 
     def __init__(self, models: Sequence[Model], env_model: Sequence[int], params, device="cuda:0",
                  debug: bool = False, pd: bool = False, fp64: bool = False, phase_cycles: bool = False,
-                 lanes_per_env: int = 0, persistent: bool = False):
+                 lanes_per_env: int = 0, persistent: bool = False, adjoint_precision: int = 0):
         self.models = list(models)
         self.params = params
         self.device = torch.device(device)
@@ -173,7 +177,7 @@ class Sim:
         handles = (ctypes.c_void_p * len(self.models))(*[m.h for m in self.models])
         ids = (ctypes.c_int32 * self.n_envs)(*[int(x) for x in env_model])
         h = ctypes.c_void_p()
-        self._p = sim_params(params, fp64, lanes_per_env, persistent)
+        self._p = sim_params(params, fp64, lanes_per_env, persistent, adjoint_precision)
         _check(lib().ags_sim_create(handles, len(self.models), ids, self.n_envs, ctypes.byref(self._p), ctypes.byref(h)),
                "ags_sim_create")
         self.h = h
@@ -268,7 +272,7 @@ class Rollout(torch.autograd.Function):
     (ags_rollout_forward / ags_rollout_backward).  Gradients flow to the actions and the initial state."""
 
     @staticmethod
-    def forward(ctx, actions, root0, dof0, sim, every):
+    def forward(ctx, actions, root0, dof0, sim, every, control=DOF_ACTUATION):
         T = actions.shape[0]
         actions = actions.contiguous()
         sim._dev_f32(actions, (T, sim.shapes[DOF_ACTUATION][0]), "actions")
@@ -278,11 +282,11 @@ class Rollout(torch.autograd.Function):
         _check(lib().ags_rollout_state_size(sim.h, ctypes.byref(n)), "ags_rollout_state_size")
         ckpt = torch.empty(((T + every - 1) // every, n.value), dtype=torch.float32, device=sim.device)
         s = torch.cuda.current_stream(sim.device)
-        _check(lib().ags_rollout_forward(sim.h, T, every, ctypes.c_void_p(actions.data_ptr()),
+        _check(lib().ags_rollout_forward(sim.h, T, every, control, ctypes.c_void_p(actions.data_ptr()),
                                          ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(s.cuda_stream)),
                "ags_rollout_forward")
         ctx.save_for_backward(actions, ckpt)
-        ctx.sim, ctx.every, ctx.state_words = sim, every, n.value
+        ctx.sim, ctx.every, ctx.state_words, ctx.control = sim, every, n.value, control
         return sim.root_state.clone(), sim.dof_state.clone()
 
     @staticmethod
@@ -296,7 +300,7 @@ class Rollout(torch.autograd.Function):
         seg = torch.empty((every, ctx.state_words), dtype=torch.float32, device=sim.device)
         status = torch.zeros(sim.n_envs, dtype=torch.int32, device=sim.device)
         s = torch.cuda.current_stream(sim.device)
-        _check(lib().ags_rollout_backward(sim.h, T, every, ctypes.c_void_p(actions.data_ptr()),
+        _check(lib().ags_rollout_backward(sim.h, T, every, ctx.control, ctypes.c_void_p(actions.data_ptr()),
                                           ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(seg.data_ptr()),
                                           ctypes.c_void_p(root_adj.data_ptr()), ctypes.c_void_p(dof_adj.data_ptr()),
                                           ctypes.c_void_p(act_adj.data_ptr()), ctypes.c_void_p(status.data_ptr()),
@@ -304,12 +308,14 @@ class Rollout(torch.autograd.Function):
         bad = int((status != 0).sum())
         if bad:
             raise RuntimeError(f"adjoint: {bad} environments exceeded the adjoint's row capacity (64 rows per substep)")
-        return act_adj, root_adj, dof_adj, None, None
+        return act_adj, root_adj, dof_adj, None, None, None
 
 
-def rollout(sim: "Sim", actions: torch.Tensor, root0: torch.Tensor, dof0: torch.Tensor, every: int = 16):
-    """Differentiable T-step rollout (see Rollout)."""
-    return Rollout.apply(actions, root0, dof0, sim, every)
+def rollout(sim: "Sim", actions: torch.Tensor, root0: torch.Tensor, dof0: torch.Tensor, every: int = 16,
+            control: int = DOF_ACTUATION):
+    """Differentiable T-step rollout (see Rollout); `control` selects what actions[t] drives: the
+    actuation (DOF_ACTUATION) or the PD position targets (DOF_POS_TARGET)."""
+    return Rollout.apply(actions, root0, dof0, sim, every, control)
 
 
 def autotune(models: Sequence[Model], env_model: Sequence[int], params, root_state: torch.Tensor,

@@ -215,6 +215,88 @@ __device__ __forceinline__ V3<R> dq_adj(V3<R> th, const R* dqb) {
   return add(mul(gv, sc), mul(th, (dot(th, gv) * dsc - R(0.5) * s * dqb[3]) / ang));
 }
 
+// tangent basis of a contact normal: t1 = normalised projection of the world axis least aligned with n
+// (lowest index on ties), t2 = n x t1 (the rule of the step kernel)
+template <typename R>
+__device__ __forceinline__ int tangents(V3<R> n, V3<R>& t1, V3<R>& t2, V3<R>& t) {
+  const R ax = n.x < R(0) ? -n.x : n.x, ay = n.y < R(0) ? -n.y : n.y, az = n.z < R(0) ? -n.z : n.z;
+  int k = 0;
+  R best = ax;
+  if (ay < best) {
+    best = ay;
+    k = 1;
+  }
+  if (az < best) k = 2;
+  const V3<R> e = k == 0 ? mk(R(1), R(0), R(0)) : (k == 1 ? mk(R(0), R(1), R(0)) : mk(R(0), R(0), R(1)));
+  t = sub(e, mul(n, dot(n, e)));
+  t1 = mul(t, R(1) / sqrt_(dot(t, t)));
+  t2 = cross(n, t1);
+  return k;
+}
+// adjoint of n through (t1, t2) = tangents(n)
+template <typename R>
+__device__ __forceinline__ V3<R> tangents_adj(V3<R> n, V3<R> t1b, V3<R> t2b) {
+  V3<R> t1, t2, t;
+  const int k = tangents(n, t1, t2, t);
+  V3<R> nb = cross(t1, t2b);
+  t1b = add(t1b, cross(t2b, n));
+  const V3<R> tb = mul(sub(t1b, mul(t1, dot(t1, t1b))), R(1) / sqrt_(dot(t, t)));
+  const R nk = k == 0 ? n.x : (k == 1 ? n.y : n.z);
+  nb = sub(nb, mul(tb, nk));
+  const R ntb = dot(n, tb);
+  if (k == 0) nb.x -= ntb;
+  else if (k == 1) nb.y -= ntb;
+  else nb.z -= ntb;
+  return nb;
+}
+// sphere (centre c, radius r) against a box (rotation Rb row-major, centre b, half extents hb): signed
+// distance and normal (from the box towards the sphere) by the closest point, or the face of least
+// penetration when the centre is inside (the step kernel's rule).  G (optional) = dn / d(c - moving box
+// point), row-major: Rb (1 - nl nl^T) diag(clamped axes) Rb^T / |d| outside, 0 inside.
+template <typename R>
+__device__ __forceinline__ void sphere_box(V3<R> c, const R* Rb, V3<R> b, V3<R> hb, R rad, R& phi, V3<R>& n, R* G) {
+  const V3<R> u = sub(c, b);
+  const V3<R> xl = mk(Rb[0] * u.x + Rb[3] * u.y + Rb[6] * u.z, Rb[1] * u.x + Rb[4] * u.y + Rb[7] * u.z,
+                      Rb[2] * u.x + Rb[5] * u.y + Rb[8] * u.z);
+  const V3<R> ql = mk(fmin(fmax(xl.x, -hb.x), hb.x), fmin(fmax(xl.y, -hb.y), hb.y), fmin(fmax(xl.z, -hb.z), hb.z));
+  const bool inside = ql.x == xl.x && ql.y == xl.y && ql.z == xl.z;
+  const V3<R> dl = sub(xl, ql);
+  const R dn = sqrt_(dot(dl, dl));
+  V3<R> nl;
+  if (!inside && dn > R(1e-12)) {
+    phi = dn - rad;
+    nl = mul(dl, R(1) / dn);
+    if (G) {
+      const R m[3] = {xl.x != ql.x ? R(1) : R(0), xl.y != ql.y ? R(1) : R(0), xl.z != ql.z ? R(1) : R(0)};
+      const R nv[3] = {nl.x, nl.y, nl.z};
+      R Lc[9];  // (1 - nl nl^T) diag(m) / dn in box coordinates
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Lc[3 * i + j] = ((i == j ? R(1) : R(0)) - nv[i] * nv[j]) * m[j] / dn;
+      R T[9];  // Rb Lc
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) T[3 * i + j] = Rb[3 * i] * Lc[j] + Rb[3 * i + 1] * Lc[3 + j] + Rb[3 * i + 2] * Lc[6 + j];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) G[3 * i + j] = T[3 * i] * Rb[3 * j] + T[3 * i + 1] * Rb[3 * j + 1] + T[3 * i + 2] * Rb[3 * j + 2];
+    }
+  } else {
+    const R pen[3] = {hb.x - (xl.x < R(0) ? -xl.x : xl.x), hb.y - (xl.y < R(0) ? -xl.y : xl.y),
+                      hb.z - (xl.z < R(0) ? -xl.z : xl.z)};
+    const R xs[3] = {xl.x, xl.y, xl.z};
+    int kb = 0;
+    if (pen[1] < pen[kb]) kb = 1;
+    if (pen[2] < pen[kb]) kb = 2;
+    const R sg = xs[kb] >= R(0) ? R(1) : R(-1);
+    nl = kb == 0 ? mk(sg, R(0), R(0)) : (kb == 1 ? mk(R(0), sg, R(0)) : mk(R(0), R(0), sg));
+    phi = -pen[kb] - rad;
+    if (G)
+      for (int k = 0; k < 9; ++k) G[k] = R(0);
+  }
+  n = mv(Rb, nl);
+}
+
+// packed symmetric storage: element (i, j) of a symmetric matrix
+__device__ __forceinline__ int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+
 // ---------------------------------------------------------------- per-environment context
 template <typename R>
 struct Env {
@@ -227,6 +309,16 @@ struct Env {
   R h;
   V3<R> g, ref;
   int R_;    // rows of the current substep
+  long long cyc[kAdjPhases];  // shader-clock cycles per phase (lane 0 keeps them; only when requested)
+  int cur;
+  long long mark;
+  __device__ void phase(int ph) {
+    if (!P->cycles) return;
+    const long long now = (long long)clock64();
+    if (cur >= 0) cyc[cur] += now - mark;
+    cur = ph;
+    mark = now;
+  }
   // table access
   __device__ const int* li(int i) const { return P->m.li + i * LI_COLS; }
   __device__ const double* lf(int i) const { return P->m.lf + i * LF_COLS; }
@@ -337,6 +429,7 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   R* tau = E.r + L.tau;
   R* arm = E.r + L.arm;
   R* q = E.r + L.q;
+  E.phase(0);
   // ---- controls, generalized velocity
   for (int c = lane; c < nv; c += 64) {
     tau[c] = R(0);
@@ -574,6 +667,7 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     nrows = __popcll(mlo) + __popcll(mhi);
     if (alo && base < rcap) {
       rkind[base] = 1; rlink[base] = i; rdof[base] = lane; rnrm[base] = -1;
+      E.ix[L.rlinkb + base] = -1; E.ix[L.rslot + base] = -1;
       const R bc = glo >= R(0) ? R(1) / h : R(P.beta) / h;
       rbc[base] = bc; rb[base] = bc * glo;
       st3(rd + 3 * base, mk(R(1), R(0), R(0)));
@@ -581,41 +675,58 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     const int bh = base + (alo ? 1 : 0);
     if (ahi && bh < rcap) {
       rkind[bh] = 2; rlink[bh] = i; rdof[bh] = lane; rnrm[bh] = -1;
+      E.ix[L.rlinkb + bh] = -1; E.ix[L.rslot + bh] = -1;
       const R bc = ghi >= R(0) ? R(1) / h : R(P.beta) / h;
       rbc[bh] = bc; rb[bh] = bc * ghi;
       st3(rd + 3 * bh, mk(R(-1), R(0), R(0)));
     }
   }
+  int* rlinkb = E.ix + L.rlinkb;
+  int* rslot = E.ix + L.rslot;
   for (int s0 = 0; s0 < E.ns; s0 += 64) {
     const int s = s0 + lane;
     bool act = false;
-    V3<R> cen = zero3<R>(), x = zero3<R>();
+    V3<R> cen = zero3<R>(), x = zero3<R>(), nrm = mk(R(0), R(0), R(1));
     R phi = R(0);
-    int i = 0;
+    int i = 0, kb = -1;
     if (s < E.ns) {
       const int* si = M.si + s * SI_COLS;
       const double* sf = M.sf + s * SF_COLS;
       i = si[SI_LINK_A];
       cen = add(ld3<R>(E.at(L.p, i, 3)), mv(E.at(L.Rm, i, 9), ld3<R>(sf + SF_P)));
       const R rad = R(sf[SF_R]);
-      phi = cen.z + E.ref.z - rad;
-      x = sub(cen, mk(R(0), R(0), rad));
-      const SV<R> Vs = lds6(E.at(L.Vs, i, 6));
-      const R vn = add(Vs.v, cross(Vs.w, x)).z;
-      act = phi + h * min_(R(0), vn) < R(P.mc);
+      if (si[SI_TYPE] == SLOT_SPHERE_BOX) {
+        kb = si[SI_LINK_B];
+        const R* Rb = E.at(L.Rm, kb, 9);
+        const V3<R> bc = add(ld3<R>(E.at(L.p, kb, 3)), mv(Rb, ld3<R>(sf + SF_BOXC)));
+        sphere_box(cen, Rb, bc, ld3<R>(sf + SF_HALF), rad, phi, nrm, (R*)nullptr);
+      } else {
+        phi = cen.z + E.ref.z - rad;
+      }
+      x = sub(cen, mul(nrm, rad));
+      const SV<R> Va = lds6(E.at(L.Vs, i, 6));
+      V3<R> u = add(Va.v, cross(Va.w, x));
+      if (kb >= 0) {
+        const SV<R> Vb = lds6(E.at(L.Vs, kb, 6));
+        u = sub(u, add(Vb.v, cross(Vb.w, x)));
+      }
+      act = phi + h * min_(R(0), dot(nrm, u)) < R(P.mc);
     }
     const unsigned long long m = __ballot(act);
     const int base = nrows + 3 * __popcll(m & lanes_below(lane));
     if (act && base + 2 < rcap) {
       const R bc = phi >= R(0) ? R(1) / h : R(P.beta) / h;
+      V3<R> t1, t2, tt;
+      tangents(nrm, t1, t2, tt);
       for (int k = 0; k < 3; ++k) {
         const int r = base + k;
         rkind[r] = 3 + k; rlink[r] = i; rdof[r] = -1; rnrm[r] = k == 0 ? -1 : base;
+        rlinkb[r] = kb; rslot[r] = s;
         rbc[r] = k == 0 ? bc : R(0);
         rb[r] = k == 0 ? bc * phi : R(0);
         st3(rx + 3 * r, x);
         st3(rcen + 3 * r, cen);
-        st3(rd + 3 * r, k == 0 ? mk(R(0), R(0), R(1)) : k == 1 ? mk(R(1), R(0), R(0)) : mk(R(0), R(1), R(0)));
+        st3(rd + 3 * r, k == 0 ? nrm : (k == 1 ? t1 : t2));
       }
     }
     nrows += 3 * __popcll(m);
@@ -654,6 +765,26 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
         Jr[c0] = d.x; Jr[c0 + 1] = d.y; Jr[c0 + 2] = d.z;
         Jr[c0 + 3] = w.x; Jr[c0 + 4] = w.y; Jr[c0 + 5] = w.z;
       }
+      const int kb = E.ix[L.rlinkb + lane];
+      if (kb >= 0) {  // body b of a two-body contact enters with the opposite sign
+        const int* lb = E.li(kb);
+        if (lb[LI_PARENT] >= 0) {
+          const SV<R> sv = joint_s(E, kb);
+          Jr[lb[LI_COL]] -= dot(d, add(sv.v, cross(sv.w, x)));
+        }
+        for (int k = lb[LI_ANC_BEGIN]; k < lb[LI_ANC_END]; ++k) {
+          const int a = M.anc_link[k];
+          const SV<R> sv = joint_s(E, a);
+          Jr[E.li(a)[LI_COL]] -= dot(d, add(sv.v, cross(sv.w, x)));
+        }
+        const int rtb = lb[LI_ROOT];
+        if (E.li(rtb)[LI_JTYPE] == J_FREE) {
+          const int c0 = lb[LI_ROOTCOL];
+          const V3<R> w = cross(sub(x, ld3<R>(E.at(L.c, rtb, 3))), d);
+          Jr[c0] -= d.x; Jr[c0 + 1] -= d.y; Jr[c0 + 2] -= d.z;
+          Jr[c0 + 3] -= w.x; Jr[c0 + 4] -= w.y; Jr[c0 + 5] -= w.z;
+        }
+      }
     }
     R* Wr = W + lane * nvp;
     for (int c = 0; c < nv; ++c) Wr[c] = Jr[c];
@@ -675,6 +806,8 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   int o = lane < nkeep ? rmap[lane] : 0;
   const int g_kind = __shfl(kind, o, 64), g_link = __shfl(lane < nrows ? rlink[lane] : 0, o, 64);
   const int g_dof = __shfl(lane < nrows ? rdof[lane] : 0, o, 64);
+  const int g_linkb = __shfl(lane < nrows ? E.ix[L.rlinkb + lane] : -1, o, 64);
+  const int g_slot = __shfl(lane < nrows ? E.ix[L.rslot + lane] : -1, o, 64);
   const int g_nrm_old = __shfl(nrm, o, 64);
   const int g_nrm = __shfl(newi, g_nrm_old < 0 ? 0 : g_nrm_old, 64);
   R g_real[14];
@@ -694,6 +827,7 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   R invA = R(0), bias = R(0);
   if (lane < nkeep) {
     rkind[lane] = g_kind; rlink[lane] = g_link; rdof[lane] = g_dof; rnrm[lane] = g_kind >= 4 ? g_nrm : -1;
+    E.ix[L.rlinkb + lane] = g_linkb; E.ix[L.rslot + lane] = g_slot;
     rbc[lane] = g_real[0]; rb[lane] = g_real[1];
     E.r[L.rinvA + lane] = g_real[2];
     for (int k = 0; k < 3; ++k) {
@@ -708,16 +842,16 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   nrm = lane < nkeep && g_kind >= 4 ? g_nrm : -1;
   sync<R>();
   const int Rn = nkeep;
-  // ---- Delassus matrix A = J W (row s per lane)
+  // ---- Delassus matrix A = J W (symmetric, packed; row s per lane, entries r <= s)
   R* A = E.r + L.A;
   const int rcp = L.rcp;
   if (lane < Rn) {
     const R* Js = J + rmap[lane] * nvp;
-    for (int r = 0; r < Rn; ++r) {
+    for (int r = 0; r <= lane; ++r) {
       const R* Wr = W + rmap[r] * nvp;
       R t = R(0);
       for (int c = 0; c < nv; ++c) t += Js[c] * Wr[c];
-      A[lane * rcp + r] = t;
+      A[tri(lane, r)] = t;
     }
   }
   // ---- Gauss-Seidel with its tape
@@ -728,10 +862,10 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   }
   sync<R>();
   R* hlo = E.r + L.hlo;
-  R* hln = E.r + L.hln;
   R* hres = E.r + L.hres;
   int* hst = E.ix + L.hst;
   const R mu = R(P.mu);
+  E.phase(1);
   for (int it = 0; it < P.iters; ++it) {
     for (int r = 0; r < Rn; ++r) {
       const int kr = lane_read(kind, r);
@@ -748,16 +882,16 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
       const R dl = lane_read(nl - lam, r);
       if (lane == r) {
         hlo[it * rcp + r] = lam;
-        hln[it * rcp + r] = nl;
         hres[it * rcp + r] = res;
         hst[it * rcp + r] = st;
         lam = nl;
       }
-      if (lane < Rn) y += A[lane * rcp + r] * dl;
+      if (lane < Rn) y += A[tri(lane, r)] * dl;
     }
   }
   if (lane < Rn) E.r[L.rlam + lane] = lam;
   sync<R>();
+  E.phase(0);
   R* nu1 = E.r + L.nu1;
   for (int c = lane; c < nv; c += 64) {
     R t = vs[c];
@@ -828,6 +962,7 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
   const int* rlink = E.ix + L.rlink;
   const int* rdof = E.ix + L.rdof;
   const int* rnrm = E.ix + L.rnrm;
+  E.phase(7);
   // ---- clear accumulators
   for (int k = lane; k < 6 * nl; k += 64) {
     E.r[L.wr + k] = R(0);
@@ -891,25 +1026,28 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
   if (lane < Rn) {
     const R* Jr = J + rmap[lane] * nvp;
     for (int c = 0; c < nv; ++c) lamb += Jr[c] * zz[c];
-    for (int r = 0; r < Rn; ++r) Ab[lane * rcp + r] = R(0);
   }
+  for (int k = lane; k < Rn * (Rn + 1) / 2; k += 64) Ab[k] = R(0);  // S = Abar + Abar^T, packed
   sync<R>();
   // ---- Gauss-Seidel reverse.  q = A ybar is kept up to date (ybar changes in one entry per row
   // update and A is symmetric), so (A^T ybar)_r is read from lane r instead of reduced over the wave.
   const R mu = R(P.mu);
   const R* hlo = E.r + L.hlo;
-  const R* hln = E.r + L.hln;
   const R* hres = E.r + L.hres;
+  const R* rlam = E.r + L.rlam;
   const int* hst = E.ix + L.hst;
   R qv = R(0);
+  E.phase(2);
   for (int it = P.iters - 1; it >= 0; --it) {
     for (int r = Rn - 1; r >= 0; --r) {
       const int st = hst[it * rcp + r];
-      const R dl = hln[it * rcp + r] - hlo[it * rcp + r];
-      const R Asr = lane < Rn ? A[lane * rcp + r] : R(0);
+      // lambda after this update: the next sweep's lambda before it, or the final lambda
+      const R dl = (it + 1 < P.iters ? hlo[(it + 1) * rcp + r] : rlam[r]) - hlo[it * rcp + r];
+      const R Asr = lane < Rn ? A[tri(lane, r)] : R(0);
       const R sum = lane_read(qv, r);
       const R g = lane_read(lamb, r) + sum;
-      if (lane < Rn) Ab[lane * rcp + r] += ybar * dl;
+      // Abar[s][r] += ybar_s dl enters S[s][r] and S[r][s]: one packed element, twice on the diagonal
+      if (lane < Rn) Ab[tri(lane, r)] += (lane == r ? R(2) : R(1)) * ybar * dl;
       const int kr = lane_read(kind, r);
       if (lane == r) lamb = -sum;
       if (st == 0) {
@@ -928,27 +1066,25 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
     }
   }
   if (lane < Rn) {
-    Ab[lane * rcp + lane] -= invAb * invA * invA;
+    Ab[tri(lane, lane)] -= R(2) * invAb * invA * invA;
     E.r[L.rybar + lane] = ybar;
     E.r[L.rbbar + lane] = bbar;
   }
   sync<R>();
+  E.phase(3);
   // ---- v*_bar = nu_bar + J^T ybar
   for (int c = lane; c < nv; c += 64) {
     R t = nub[c];
     for (int r = 0; r < Rn; ++r) t += J[rmap[r] * nvp + c] * E.r[L.rybar + r];
     vsb[c] = t;
   }
-  // S = Abar + Abar^T into A (A is not needed any more)
-  if (lane < Rn)
-    for (int r = 0; r < Rn; ++r) A[lane * rcp + r] = Ab[lane * rcp + r] + Ab[r * rcp + lane];
   sync<R>();
   // ---- T_s = sum_r S_sr W_r into the J rows (J is not needed any more)
   if (lane < Rn) {
     R* Ts = J + rmap[lane] * nvp;
     for (int c = 0; c < nv; ++c) {
       R t = R(0);
-      for (int r = 0; r < Rn; ++r) t += A[lane * rcp + r] * W[rmap[r] * nvp + c];
+      for (int r = 0; r < Rn; ++r) t += Ab[tri(lane, r)] * W[rmap[r] * nvp + c];
       Ts[c] = t;
     }
   }
@@ -985,6 +1121,7 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
     qb[j] -= kp * ww[c];
     nui[c] -= (h * kp + kd) * ww[c];
   }
+  E.phase(4);
   // ---- d tr(M P)/dq, weight -1: per column y_k, s_bar and y_bar
   R* colS = E.r + L.colS;
   R* colY = E.r + L.colY;
@@ -1036,6 +1173,7 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
     acc3(E.at(L.tI, i, 3), tI);
   }
   sync<R>();
+  E.phase(5);
   // ---- C(q, qd) reverse (weight -1, seed w): W_hat, A (RNEA accelerations) outward
   link_vel(E, ww, L.X0);
   for (int lev = 0; lev < E.nlev; ++lev) {
@@ -1103,31 +1241,89 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
     }
     sync<R>();
   }
-  // ---- constraint rows: contact point / direction adjoints, bias adjoints
+  E.phase(6);
+  // ---- constraint rows: per row, the adjoints of its contact point (x) and direction (d) from the
+  // velocities Jbar_r induces on its bodies; limit rows: the bias adjoint of the joint position
   R* rxb = E.r + L.rxb;
+  R* rdb = E.r + L.rdb;
   R* rqb = E.r + L.rqb;
-  if (lane < Rn) {
-    const int i = rlink[lane];
+  const int* rlinkb = E.ix + L.rlinkb;
+  auto path_vel = [&](int i, const R* Jr) {
     const int* li = E.li(i);
+    SV<R> Vt = sz<R>();
+    if (li[LI_PARENT] >= 0) Vt = smul(joint_s(E, i), Jr[li[LI_COL]]);
+    for (int k = li[LI_ANC_BEGIN]; k < li[LI_ANC_END]; ++k) {
+      const int a = M.anc_link[k];
+      Vt = sadd(Vt, smul(joint_s(E, a), Jr[E.li(a)[LI_COL]]));
+    }
+    const int rt = li[LI_ROOT];
+    if (E.li(rt)[LI_JTYPE] == J_FREE) Vt = sadd(Vt, root_vel(ld3<R>(E.at(L.c, rt, 3)), Jr + li[LI_ROOTCOL]));
+    return Vt;
+  };
+  if (lane < Rn) {
     const R* Jr = J + rmap[lane] * nvp;
     const R bc = E.r[L.rbc + lane];
     if (kind >= 3) {
-      SV<R> Vt = sz<R>();
-      if (li[LI_PARENT] >= 0) Vt = smul(joint_s(E, i), Jr[li[LI_COL]]);
-      for (int k = li[LI_ANC_BEGIN]; k < li[LI_ANC_END]; ++k) {
-        const int a = M.anc_link[k];
-        Vt = sadd(Vt, smul(joint_s(E, a), Jr[E.li(a)[LI_COL]]));
+      const V3<R> x = ld3<R>(E.r + L.rx + 3 * lane), d = ld3<R>(E.r + L.rd + 3 * lane);
+      const SV<R> Va = path_vel(rlink[lane], Jr);
+      V3<R> u = add(Va.v, cross(Va.w, x)), wd = Va.w;
+      const int kb = rlinkb[lane];
+      if (kb >= 0) {
+        const SV<R> Vb = path_vel(kb, Jr);
+        u = sub(u, add(Vb.v, cross(Vb.w, x)));
+        wd = sub(wd, Vb.w);
       }
-      const int rt = li[LI_ROOT];
-      if (E.li(rt)[LI_JTYPE] == J_FREE) Vt = sadd(Vt, root_vel(ld3<R>(E.at(L.c, rt, 3)), Jr + li[LI_ROOTCOL]));
-      V3<R> xb = cross(ld3<R>(E.r + L.rd + 3 * lane), Vt.w);
-      if (kind == 3) xb.z += bbar * bc;
-      st3(rxb + 3 * lane, xb);
+      st3(rxb + 3 * lane, cross(d, wd));
+      st3(rdb + 3 * lane, u);
       rqb[lane] = R(0);
     } else {
       st3(rxb + 3 * lane, zero3<R>());
+      st3(rdb + 3 * lane, zero3<R>());
       rqb[lane] = bbar * bc * E.r[L.rd + 3 * lane];
     }
+  }
+  sync<R>();
+  // per contact (the lane of its normal row): x = c - rad n, d = n, t1(n), t2(n), bias from phi; the
+  // sphere centre c moves with body a; for a box partner, phi and n move with c relative to the box
+  // (ub = phib n + G^T nb) and n turns with the box: body a gets (c x ca, ca) with ca = cb + ub, body b
+  // gets (n x nb - c x ub, -ub)
+  R* rwa = E.r + L.rwa;
+  R* rwb = E.r + L.rwb;
+  if (lane < Rn && kind == 3) {
+    const int sl = E.ix[L.rslot + lane];
+    const double* sf = M.sf + sl * SF_COLS;
+    const R rad = R(sf[SF_R]);
+    const V3<R> c = ld3<R>(E.r + L.rcen + 3 * lane), n = ld3<R>(E.r + L.rd + 3 * lane);
+    V3<R> cb = ld3<R>(rxb + 3 * lane), t1b = zero3<R>(), t2b = zero3<R>();
+    V3<R> nb = ld3<R>(rdb + 3 * lane);
+    for (int r = 0; r < Rn; ++r) {
+      if (rnrm[r] != lane) continue;
+      cb = add(cb, ld3<R>(rxb + 3 * r));
+      if (rkind[r] == 4) t1b = add(t1b, ld3<R>(rdb + 3 * r));
+      else t2b = add(t2b, ld3<R>(rdb + 3 * r));
+    }
+    nb = sub(nb, mul(cb, rad));
+    const R phib = bbar * E.r[L.rbc + lane];
+    const int kb = rlinkb[lane];
+    SV<R> wa, wb = sz<R>();
+    if (kb < 0) {
+      cb.z += phib;
+      wa = {cross(c, cb), cb};
+    } else {
+      nb = add(nb, tangents_adj(n, t1b, t2b));
+      const R* Rb = E.at(L.Rm, kb, 9);
+      const V3<R> bcen = add(ld3<R>(E.at(L.p, kb, 3)), mv(Rb, ld3<R>(sf + SF_BOXC)));
+      R phi_, G[9];
+      V3<R> n_;
+      sphere_box(c, Rb, bcen, ld3<R>(sf + SF_HALF), rad, phi_, n_, G);
+      const V3<R> ub = add(mul(n, phib), mk(G[0] * nb.x + G[3] * nb.y + G[6] * nb.z, G[1] * nb.x + G[4] * nb.y + G[7] * nb.z,
+                                            G[2] * nb.x + G[5] * nb.y + G[8] * nb.z));
+      const V3<R> ca = add(cb, ub);
+      wa = {cross(c, ca), ca};
+      wb = {sub(cross(n, nb), cross(c, ub)), mul(ub, R(-1))};
+    }
+    sts6(rwa + 6 * lane, wa);
+    sts6(rwb + 6 * lane, wb);
   }
   sync<R>();
   for (int i = lane; i < nl; i += 64) {
@@ -1137,17 +1333,22 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
     SV<R> xw = sz<R>();
     for (int r = 0; r < Rn; ++r) {
       if (rkind[r] < 3) continue;
-      const int lr = rlink[r];
+      const int la = rlink[r], lb = rlinkb[r];
       const R* Jr = J + rmap[r] * nvp;
       const V3<R> x = ld3<R>(E.r + L.rx + 3 * r), d = ld3<R>(E.r + L.rd + 3 * r);
-      if (li[LI_PARENT] >= 0) {
-        if ((M.link_anc[lr] >> i) & 1ull) sb = sadd(sb, smul(SV<R>{cross(x, d), d}, Jr[li[LI_COL]]));
-      } else if (li[LI_JTYPE] == J_FREE && E.li(lr)[LI_ROOT] == i) {
-        cb = add(cb, cross(ld3<R>(Jr + li[LI_ROOTCOL] + 3), d));
+      for (int side = 0; side < 2; ++side) {
+        const int lk = side == 0 ? la : lb;
+        if (lk < 0) continue;
+        const R sgn = side == 0 ? R(1) : R(-1);
+        if (li[LI_PARENT] >= 0) {
+          if ((M.link_anc[lk] >> i) & 1ull) sb = sadd(sb, smul(SV<R>{cross(x, d), d}, sgn * Jr[li[LI_COL]]));
+        } else if (li[LI_JTYPE] == J_FREE && E.li(lk)[LI_ROOT] == i) {
+          cb = add(cb, mul(cross(ld3<R>(Jr + li[LI_ROOTCOL] + 3), d), sgn));
+        }
       }
-      if (lr == i) {
-        const V3<R> xb = ld3<R>(rxb + 3 * r), cen = ld3<R>(E.r + L.rcen + 3 * r);
-        xw = sadd(xw, SV<R>{cross(cen, xb), xb});
+      if (rkind[r] == 3) {
+        if (la == i) xw = sadd(xw, lds6(rwa + 6 * r));
+        if (lb == i) xw = sadd(xw, lds6(rwb + 6 * r));
       }
     }
     acc6(E.at(L.sb, i, 6), sb);
@@ -1205,6 +1406,7 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
     }
     sync<R>();
   }
+  E.phase(7);
   // ---- adjoint of the substep's start state
   for (int j = lane; j < nd; j += 64) {
     dbar[2 * j] = qb[j];
@@ -1247,6 +1449,9 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
   E.dbase = P.env_dof_base[env];
   E.h = R(P.h);
   E.g = mk(R(P.gx), R(P.gy), R(P.gz));
+  for (int k = 0; k < kAdjPhases; ++k) E.cyc[k] = 0;
+  E.cur = -1;
+  E.mark = 0;
   const int lane = E.lane, na = E.na, nd = E.nd, sw = L.state_words, S = P.substeps;
   R* st = E.r + L.st;
   // step start state and the adjoint of the step's end state
@@ -1271,6 +1476,9 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
   for (int k = lane; k < 2 * nd; k += 64) P.dof_adj[(long long)E.dbase * 2 + k] = ok ? float(E.r[L.dbar + k]) : 0.0f;
   for (int j = lane; j < nd; j += 64) P.act_adj[E.dbase + j] = ok ? float(E.r[L.ab + j]) : 0.0f;
   if (P.status && lane == 0) P.status[env] = ok ? 0 : 1;
+  E.phase(-1);
+  if (P.cycles && lane == 0)
+    for (int k = 0; k < kAdjPhases; ++k) P.cycles[(long long)env * kAdjPhases + k] = E.cyc[k];
 }
 
 template <typename R>

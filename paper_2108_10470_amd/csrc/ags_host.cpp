@@ -422,6 +422,8 @@ struct TypeDev {
   bool body_pairs = false;
 };
 
+int adj_fp64(const ags_sim_params& p) { return p.adjoint_precision == 64 || (p.adjoint_precision == 0 && p.compute_fp64); }
+
 // LDS layout of the adjoint kernel for one environment (one wavefront per environment)
 AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters) {
   AdjLds L{};
@@ -448,14 +450,16 @@ AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters) {
   L.nvp = nv | 1;
   L.Lm = take(nv * L.nvp);
   L.rcp = rc | 1;
-  L.J = take(rc * L.nvp); L.W = take(rc * L.nvp); L.A = take(rc * L.rcp); L.Ab = take(rc * L.rcp);
+  L.J = take(rc * L.nvp); L.W = take(rc * L.nvp); L.A = take(rc * (rc + 1) / 2); L.Ab = take(rc * (rc + 1) / 2);
   L.rbc = take(rc); L.rb = take(rc); L.rinvA = take(rc); L.rlam = take(rc); L.rybar = take(rc); L.rbbar = take(rc);
   L.rqb = take(rc); L.rx = take(3 * rc); L.rcen = take(3 * rc); L.rd = take(3 * rc); L.rxb = take(3 * rc);
-  L.hlo = take(iters * L.rcp); L.hln = take(iters * L.rcp); L.hres = take(iters * L.rcp);
+  L.rdb = take(3 * rc); L.rwa = take(6 * rc); L.rwb = take(6 * rc);
+  L.hlo = take(iters * L.rcp); L.hres = take(iters * L.rcp);
   L.misc = take(8);
   L.n_real = (off + 1) & ~1;
   off = 0;
   L.rkind = take(rc); L.rlink = take(rc); L.rdof = take(rc); L.rnrm = take(rc); L.rmap = take(rc);
+  L.rlinkb = take(rc); L.rslot = take(rc);
   L.hst = take(iters * L.rcp); L.flags = take(64);
   L.n_int = off;
   return L;
@@ -514,6 +518,7 @@ struct ags_sim {
   int* actor_rows = nullptr;  // device: root row begin, root count(1), dof begin, dof count (4 x N_A)
   int n_actors_total = 0, n_dof_total = 0, n_bodies_total = 0, max_nv = 0, max_rows = 0;
   void* bound[AGS_NUM_TENSORS] = {nullptr};
+  float* kp_dof = nullptr;  // device: drive stiffness of every DOF (target adjoints)
   // persistent (fused) launch
   bool fused_ok = false;
   int* units = nullptr;  // device: (type, group) pairs
@@ -525,6 +530,8 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
                               int32_t n_envs, const ags_sim_params* p, ags_sim** out) {
   if (!models || n_models <= 0 || !env_model || n_envs <= 0 || !p || !out) return fail(AGS_E_ARG, "sim: bad arguments");
   if (!(p->dt > 0) || p->substeps < 1 || p->pgs_iters < 0) return fail(AGS_E_ARG, "sim: bad parameters");
+  if (p->adjoint_precision != 0 && p->adjoint_precision != 32 && p->adjoint_precision != 64)
+    return fail(AGS_E_ARG, "sim: adjoint_precision must be 0, 32 or 64");
   *out = nullptr;
   for (int e = 0; e < n_envs; ++e)
     if (env_model[e] < 0 || env_model[e] >= n_models || !models[env_model[e]])
@@ -566,6 +573,20 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
       (err = hipMemcpy(S->actor_rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) {
     ags_sim_destroy(S);
     return hip_fail(err, "sim: upload");
+  }
+  {
+    std::vector<float> kp(std::max(1, S->n_dof_total), 0.f);
+    for (int e = 0, d = 0; e < n_envs; ++e) {
+      const ags_model* M = models[env_model[e]];
+      for (int j = 0; j < M->info.n_dof; ++j)
+        kp[d + j] = (float)M->lf[(size_t)M->dof_link[j] * LF_COLS + LF_KP];
+      d += M->info.n_dof;
+    }
+    if ((err = hipMalloc(&S->kp_dof, kp.size() * sizeof(float))) != hipSuccess ||
+        (err = hipMemcpy(S->kp_dof, kp.data(), kp.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) {
+      ags_sim_destroy(S);
+      return hip_fail(err, "sim: drive table");
+    }
   }
   const size_t elem_size = p->compute_fp64 ? sizeof(double) : sizeof(float);
   for (int t = 0; t < n_models; ++t) {
@@ -644,9 +665,9 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     D.col_link = (const int*)(b + offs[15]);
     T.body_pairs = M->body_pairs;
     T.adj = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters));
-    T.adj_bytes = (size_t)T.adj.n_real * elem_size + (size_t)T.adj.n_int * sizeof(int);
+    T.adj_bytes = (size_t)T.adj.n_real * (adj_fp64(*p) ? sizeof(double) : sizeof(float)) + (size_t)T.adj.n_int * sizeof(int);
     if (T.adj_bytes <= 160 * 1024 && T.adj_bytes > 64 * 1024 &&
-        (err = set_adjoint_lds_limit(p->compute_fp64, T.adj_bytes)) != hipSuccess) {
+        (err = set_adjoint_lds_limit(adj_fp64(*p), T.adj_bytes)) != hipSuccess) {
       S->types.push_back(T);
       ags_sim_destroy(S);
       return hip_fail(err, "sim: adjoint LDS limit");
@@ -726,6 +747,7 @@ extern "C" void ags_sim_destroy(ags_sim* S) {
   }
   if (S->env_tables) (void)hipFree(S->env_tables);
   if (S->units) (void)hipFree(S->units);
+  if (S->kp_dof) (void)hipFree(S->kp_dof);
   if (S->actor_rows) (void)hipFree(S->actor_rows);
   delete S;
 }
@@ -743,6 +765,7 @@ extern "C" int ags_sim_tensor_shape(const ags_sim* S, int32_t which, int64_t* ro
     case AGS_DEBUG_ROW_COUNT: *rows = S->n_envs; *cols = sub; break;
     case AGS_DEBUG_ROW_KEY: case AGS_DEBUG_ROW_LAMBDA: *rows = S->n_envs; *cols = (int64_t)sub * std::max(1, S->max_rows); break;
     case AGS_DEBUG_PHASE_CYCLES: *rows = S->n_envs; *cols = kPhases; break;
+    case AGS_DEBUG_ADJ_CYCLES: *rows = S->n_envs; *cols = kAdjPhases; break;
     default: return fail(AGS_E_ARG, "unknown tensor");
   }
   return AGS_OK;
@@ -826,7 +849,6 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
   const ags_sim_params& p = S->params;
   if (p.pgs_iters > kAdjIters) return fail(AGS_E_ARG, "step_backward: more Gauss-Seidel sweeps than the adjoint's tape holds (32)");
   for (const TypeDev& T : S->types) {
-    if (T.body_pairs) return fail(AGS_E_MODEL, "step_backward: sphere/capsule-vs-box pairs are not differentiated");
     if (T.adj_bytes > 160 * 1024) return fail(AGS_E_ARG, "step_backward: model too large for one workgroup's LDS");
   }
   for (TypeDev& T : S->types) {
@@ -845,6 +867,7 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
     a.dof_adj = dof_adj;
     a.act_adj = act_adj;
     a.status = status;
+    a.cycles = (long long*)S->bound[AGS_DEBUG_ADJ_CYCLES];
     a.h = (double)p.dt / p.substeps;
     a.gx = p.gravity[0];
     a.gy = p.gravity[1];
@@ -854,7 +877,7 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
     a.mc = p.contact_margin;
     a.substeps = p.substeps;
     a.iters = p.pgs_iters;
-    hipError_t e = launch_adjoint(a, T.n_envs, p.compute_fp64, (hipStream_t)stream);
+    hipError_t e = launch_adjoint(a, T.n_envs, adj_fp64(p), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "step_backward: launch");
   }
   return AGS_OK;
@@ -868,23 +891,25 @@ extern "C" int ags_rollout_state_size(const ags_sim* S, int64_t* floats) {
 }
 
 namespace {
-// one env-step on the given state arrays with the given actuation; the output tensors are not written
-int step_on(ags_sim* S, float* root, float* dof, const float* act, hipStream_t stream) {
+// one env-step on the given state arrays with the given control; the output tensors are not written
+int step_on(ags_sim* S, float* root, float* dof, int control, const float* ctrl, hipStream_t stream) {
   void* saved[AGS_NUM_TENSORS];
   std::memcpy(saved, S->bound, sizeof(saved));
   for (int w = AGS_NET_CONTACT_FORCE; w < AGS_NUM_TENSORS; ++w) S->bound[w] = nullptr;
   S->bound[AGS_ROOT_STATE] = root;
   S->bound[AGS_DOF_STATE] = dof;
-  S->bound[AGS_DOF_ACTUATION] = const_cast<float*>(act);
+  S->bound[control] = const_cast<float*>(ctrl);
   const int rc = ags_sim_step(S, stream);
   std::memcpy(S->bound, saved, sizeof(saved));
   return rc;
 }
 }  // namespace
 
-extern "C" int ags_rollout_forward(ags_sim* S, int32_t n_steps, int32_t every, const float* actions, float* ckpt,
-                                   void* stream) {
-  if (!S || n_steps < 1 || every < 1 || !actions || !ckpt) return fail(AGS_E_ARG, "rollout_forward: bad arguments");
+extern "C" int ags_rollout_forward(ags_sim* S, int32_t n_steps, int32_t every, int32_t control, const float* actions,
+                                   float* ckpt, void* stream) {
+  if (!S || n_steps < 1 || every < 1 || !actions || !ckpt || (control != AGS_DOF_ACTUATION && control != AGS_DOF_POS_TARGET))
+    return fail(AGS_E_ARG, "rollout_forward: bad arguments");
+  if (!S->bound[AGS_DOF_ACTUATION]) return fail(AGS_E_UNBOUND, "rollout_forward: the actuation tensor must be bound");
   if (!S->bound[AGS_ROOT_STATE] || !S->bound[AGS_DOF_STATE])
     return fail(AGS_E_UNBOUND, "rollout_forward: root and DOF state tensors must be bound");
   const size_t nr = 13ull * S->n_actors_total, nd = 2ull * S->n_dof_total, sw = nr + nd;
@@ -898,20 +923,22 @@ extern "C" int ags_rollout_forward(ags_sim* S, int32_t n_steps, int32_t every, c
       if (e == hipSuccess) e = hipMemcpyAsync(c + nr, dof, nd * sizeof(float), hipMemcpyDeviceToDevice, st);
       if (e != hipSuccess) return hip_fail(e, "rollout_forward: checkpoint copy");
     }
-    void* saved = S->bound[AGS_DOF_ACTUATION];
-    S->bound[AGS_DOF_ACTUATION] = const_cast<float*>(actions + (size_t)t * S->n_dof_total);
+    void* saved = S->bound[control];
+    S->bound[control] = const_cast<float*>(actions + (size_t)t * S->n_dof_total);
     const int rc = ags_sim_step(S, stream);
-    S->bound[AGS_DOF_ACTUATION] = saved;
+    S->bound[control] = saved;
     if (rc != AGS_OK) return rc;
   }
   return AGS_OK;
 }
 
-extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, const float* actions,
+extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, int32_t control, const float* actions,
                                     const float* ckpt, float* seg, float* root_adj, float* dof_adj, float* act_adj,
                                     int32_t* status, void* stream) {
-  if (!S || n_steps < 1 || every < 1 || !actions || !ckpt || !seg || !root_adj || !dof_adj || !act_adj)
+  if (!S || n_steps < 1 || every < 1 || !actions || !ckpt || !seg || !root_adj || !dof_adj || !act_adj ||
+      (control != AGS_DOF_ACTUATION && control != AGS_DOF_POS_TARGET))
     return fail(AGS_E_ARG, "rollout_backward: bad arguments");
+  if (!S->bound[AGS_DOF_ACTUATION]) return fail(AGS_E_UNBOUND, "rollout_backward: the actuation tensor must be bound");
   const size_t nr = 13ull * S->n_actors_total, nd = 2ull * S->n_dof_total, sw = nr + nd;
   const size_t na = (size_t)S->n_dof_total;
   hipStream_t st = (hipStream_t)stream;
@@ -925,13 +952,22 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
       float* b = a + sw;
       if ((e = hipMemcpyAsync(b, a, sw * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return hip_fail(e, "rollout_backward: copy");
-      const int rc = step_on(S, b, b + nr, actions + (size_t)t * na, st);
+      const int rc = step_on(S, b, b + nr, control, actions + (size_t)t * na, st);
       if (rc != AGS_OK) return rc;
     }
     for (int t = t1 - 1; t >= t0; --t) {
       const float* x = seg + (size_t)(t - t0) * sw;
-      const int rc = ags_sim_step_backward(S, x, x + nr, actions + (size_t)t * na, root_adj, dof_adj,
-                                           act_adj + (size_t)t * na, status, stream);
+      void* saved = S->bound[control];
+      S->bound[control] = const_cast<float*>(actions + (size_t)t * na);
+      // the actuation the step used: the per-step array or the bound tensor
+      const float* act = (const float*)S->bound[AGS_DOF_ACTUATION];
+      int rc = ags_sim_step_backward(S, x, x + nr, act, root_adj, dof_adj, act_adj + (size_t)t * na, status, stream);
+      S->bound[control] = saved;
+      if (rc == AGS_OK && control == AGS_DOF_POS_TARGET) {
+        // the target enters the step only through tau = ... + kp q*: dL/dq* = kp dL/dtau
+        const hipError_t e2 = launch_scale_by_kp(act_adj + (size_t)t * na, S->kp_dof, (int)na, st);
+        if (e2 != hipSuccess) rc = hip_fail(e2, "rollout_backward: target adjoint");
+      }
       if (rc != AGS_OK) return rc;
     }
   }

@@ -113,6 +113,7 @@ hipError_t fused_blocks_per_cu(int fp64, int team, size_t lds_bytes, int* blocks
 // ---------------------------------------------------------------- adjoint of one env-step
 constexpr int kAdjRows = 64;   // constraint rows per substep the adjoint handles (one lane each)
 constexpr int kAdjIters = 32;  // Gauss-Seidel sweeps the adjoint's tape holds
+constexpr int kAdjPhases = 8;
 
 // per-environment LDS layout of the adjoint kernel: offsets in elements of the compute type (reals)
 // or in ints (integer region, placed after the reals)
@@ -123,13 +124,14 @@ struct AdjLds {
   int q, qb, ab;                                                   // per DOF
   int st, rbar, dbar, nrb;                                             // state of each substep start, state adjoint
   int Lm, nvp;                                                     // dense n_v x nvp matrix (factor, then P)
-  int J, W, A, Ab, rcp;                                            // rows: J, W (rows x nvp), A, Abar (rows x rcp)
+  int J, W, A, Ab, rcp;  // rows: J, W (rows x nvp); A and S = Abar + Abar^T (packed symmetric)
   int rbc, rb, rinvA, rlam, rybar, rbbar, rx, rcen, rd, rxb, rqb;  // per row reals
-  int hlo, hln, hres;                                              // tape: iters x rows
+  int rdb, rwa, rwb;                                               // per row: d adjoint, wrenches of bodies a, b
+  int hlo, hres;                                                   // tape: iters x rcp
   int misc;
   int n_real;
   // integer region
-  int rkind, rlink, rdof, rnrm, rmap, hst, flags;
+  int rkind, rlink, rdof, rnrm, rmap, rlinkb, rslot, hst, flags;
   int n_int;
   int state_words;  // reals of one stored state: 13 per actor + 2 per DOF
   int rows_cap;     // min(max rows, kAdjRows)
@@ -150,12 +152,15 @@ struct AdjArgs {
   float* dof_adj;
   float* act_adj;
   int* status;
+  long long* cycles;  // optional, per env: kAdjPhases shader-clock counters
   double h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
 };
 
 hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t stream);
 hipError_t set_adjoint_lds_limit(int fp64, size_t bytes);
+
+hipError_t launch_scale_by_kp(float* x, const float* kp, int n, hipStream_t stream);
 
 hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStream_t stream);
 hipError_t set_lds_limit(int fp64, int team, size_t bytes);

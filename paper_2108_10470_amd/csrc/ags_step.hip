@@ -1258,6 +1258,11 @@ __global__ void set_rows_kernel(float* dst, const float* src, const int* idx, in
   }
 }
 
+__global__ void scale_by_kp_kernel(float* x, const float* kp, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] *= kp[i];
+}
+
 template <typename R, int TEAM>
 static hipError_t launch_one(const StepArgs& a, int n_envs, hipStream_t stream) {
   constexpr int EPW = kTeam / TEAM;
@@ -1280,6 +1285,12 @@ hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStr
   if (n_envs <= 0) return hipSuccess;
   if (fp64) return team == 32 ? launch_one<double, 32>(a, n_envs, stream) : launch_one<double, 64>(a, n_envs, stream);
   return team == 32 ? launch_one<float, 32>(a, n_envs, stream) : launch_one<float, 64>(a, n_envs, stream);
+}
+
+hipError_t launch_scale_by_kp(float* x, const float* kp, int n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_by_kp_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, x, kp, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_step_fused(const FusedArgs& a, int grid, size_t lds_bytes, int fp64, int team, hipStream_t stream) {

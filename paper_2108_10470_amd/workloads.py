@@ -262,19 +262,26 @@ def free_box(half=(0.025, 0.025, 0.025), mass=0.0, pos=(0.0, 0.0, 0.5), density=
                  root_pos=tuple(pos))
 
 
-def arm_with_gripper() -> Actor:
+def arm_with_gripper(armature: float = 0.1, damping: float = 2.0, finger_armature: float = 0.05,
+                     finger_damping: float = 1.0) -> Actor:
     """Fixed-base 7-DOF serial arm (capsules len 0.3, r 0.05, axes z,y,z,y,z,y,z, limits +-2 rad)
-    with a 2-finger prismatic gripper (finger capsules len 0.05, r 0.01, range [0, 0.04] m)."""
+    with a 2-finger prismatic gripper (finger capsules len 0.05, r 0.01, range [0, 0.04] m).
+
+    Arm joints carry armature 0.1 kg m^2 and damping 2 N m s/rad, fingers 0.05 kg and 1 N s/m (Table 3
+    joint parameters; stand-in values): the z-axis joints turn a capsule about its own axis
+    (~0.005 kg m^2), and without them +-20 N m random torques slam them between their limits at
+    ~70 rad/s every step, a state in which a rounding-level perturbation grows without bound."""
     links = [Link("base", -1, "fixed")]
     for k, ax in enumerate("zyzyzyz"):
         links.append(Link(f"link{k}", len(links) - 1, "revolute",
                           anchor=(0.0, 0.0, 0.1 if k == 0 else 0.3), axis=_AXES[ax],
-                          lower=-2.0, upper=2.0, gear=20.0,
+                          lower=-2.0, upper=2.0, gear=20.0, armature=armature, kd=damping,
                           shapes=[_capsule((0, 0, 0), (0, 0, 0.3), 0.05)]))
     hand = len(links) - 1
     for side in (1.0, -1.0):
         links.append(Link(f"finger{'l' if side > 0 else 'r'}", hand, "prismatic",
                           anchor=(0.0, 0.0, 0.36), axis=(0.0, side, 0.0), lower=0.0, upper=0.04, gear=10.0,
+                          armature=finger_armature, kd=finger_damping,
                           shapes=[_capsule((0, 0, 0), (0, 0, 0.05), 0.01)]))
     return Actor("arm", links, root_pos=(0.0, 0.0, 0.0), init_q_halfwidth=0.1)
 

@@ -104,10 +104,11 @@ def f32_inputs(env, params, n_envs, steps_before, seed=0):
     return env, params, oe, r32(root), r32(dof), r32(acts[steps_before]), wr, wd
 
 
-def fd_rollout(oe, params, root0, dof0, acts, n_threads=None, h=None):
-    """Central differences (step h, default H) of L = sum over envs of the first actor's final root x
-    position after the rollout of acts (T, E, D), with respect to every action entry; NaN where any
-    step's mode changes.  Also returns the mode of every step of the unperturbed rollout (E, T)."""
+def fd_rollout(oe, params, root0, dof0, acts, n_threads=None, h=None, targets=False, actor=0):
+    """Central differences (step h, default H) of L = sum over envs of actor `actor`'s final root x
+    position after the rollout of acts (T, E, D) (the actuation, or with targets=True the PD position
+    targets with zero actuation), with respect to every entry; NaN where any step's mode changes.
+    Also returns the mode of every step of the unperturbed rollout (E, T)."""
     H_ = H if h is None else h
     T, E, nd = acts.shape
     n = T * nd
@@ -124,30 +125,35 @@ def fd_rollout(oe, params, root0, dof0, acts, n_threads=None, h=None):
     base_modes = np.zeros((E, T), dtype=np.uint64)
     with np.errstate(over="ignore"):
         for t in range(T):
-            o = oe.step(params, R, D, A[t].reshape(E * C, nd), n_threads=n_threads)
+            ctl = A[t].reshape(E * C, nd)
+            if targets:
+                o = oe.step(params, R, D, np.zeros_like(ctl), pos_tgt=ctl, n_threads=n_threads)
+            else:
+                o = oe.step(params, R, D, ctl, n_threads=n_threads)
             R, D = o["root"], o["dof"]
             mode = (mode * np.uint64(1099511628211)) ^ o["mode"]
             base_modes[:, t] = o["mode"].reshape(E, C)[:, 2 * n]
-    L = R.reshape(E, C, -1, 13)[:, :, 0, 0]
+    L = R.reshape(E, C, -1, 13)[:, :, actor, 0]
     mode = mode.reshape(E, C)
     g = (L[:, 0:2 * n:2] - L[:, 1:2 * n:2]) / (2 * H_)
     same = (mode[:, 0:2 * n:2] == mode[:, 2 * n:]) & (mode[:, 1:2 * n:2] == mode[:, 2 * n:])
     return np.where(same, g, np.nan).reshape(E, T, nd), base_modes
 
 
-def gpu_trajectory(env, params, root0, dof0, acts, fp64, device="cuda:0"):
+def gpu_trajectory(env, params, root0, dof0, acts, fp64, device="cuda:0", targets=False):
     """States of the GPU rollout of acts (T, E, D) before every step and after the last:
     roots (T + 1, E, A, 13), dofs (T + 1, E, D, 2)."""
     T, E, nd = acts.shape
-    sim = ags.Sim([ags.Model(env)], [0] * E, params, device=device, fp64=fp64)
+    sim = ags.Sim([ags.Model(env)], [0] * E, params, device=device, fp64=fp64, pd=targets)
     f32 = dict(dtype=torch.float32, device=device)
     sim.root_state.copy_(torch.tensor(root0.reshape(-1, 13), **f32))
     sim.dof_state.copy_(torch.tensor(dof0.reshape(-1, 2), **f32))
+    ctl = sim.pos_target if targets else sim.actuation
     roots, dofs = [], []
     for t in range(T):
         roots.append(sim.root_state.double().cpu().numpy().reshape(root0.shape))
         dofs.append(sim.dof_state.double().cpu().numpy().reshape(dof0.shape))
-        sim.actuation.copy_(torch.tensor(acts[t].reshape(-1), **f32))
+        ctl.copy_(torch.tensor(acts[t].reshape(-1), **f32))
         sim.step()
     torch.cuda.synchronize()
     roots.append(sim.root_state.double().cpu().numpy().reshape(root0.shape))
@@ -155,16 +161,19 @@ def gpu_trajectory(env, params, root0, dof0, acts, fp64, device="cuda:0"):
     return np.stack(roots), np.stack(dofs)
 
 
-def gpu_rollout_grad(env, params, root0, dof0, acts, every, fp64, device="cuda:0"):
+def gpu_rollout_grad(env, params, root0, dof0, acts, every, fp64, device="cuda:0", targets=False, actor=0,
+                     adjoint_precision=0):
     """The same gradient through ags.rollout (checkpoints every `every` steps) and torch autograd."""
     T, E, nd = acts.shape
-    sim = ags.Sim([ags.Model(env)], [0] * E, params, device=device, fp64=fp64)
+    sim = ags.Sim([ags.Model(env)], [0] * E, params, device=device, fp64=fp64, pd=targets,
+                  adjoint_precision=adjoint_precision)
     f32 = dict(dtype=torch.float32, device=device)
     a = torch.tensor(acts.reshape(T, E * nd), **f32).requires_grad_(True)
     r0 = torch.tensor(root0.reshape(-1, 13), **f32)
     d0 = torch.tensor(dof0.reshape(-1, 2), **f32)
-    root, dof = ags.rollout(sim, a, r0, d0, every=every)
-    loss = root.view(E, env.n_actors, 13)[:, 0, 0].sum()
+    root, dof = ags.rollout(sim, a, r0, d0, every=every,
+                            control=ags.DOF_POS_TARGET if targets else ags.DOF_ACTUATION)
+    loss = root.view(E, env.n_actors, 13)[:, actor, 0].sum()
     loss.backward()
     torch.cuda.synchronize()
     return a.grad.double().cpu().numpy().reshape(T, E, nd).transpose(1, 0, 2), root.detach().double().cpu().numpy()

@@ -29,10 +29,13 @@ def _report(name, d):
 
 
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
-@pytest.mark.parametrize("model,steps_before", [("ant", 40), ("humanoid", 45), ("humanoid", 80)])
+@pytest.mark.parametrize("model,steps_before", [("ant", 40), ("humanoid", 45), ("humanoid", 80), ("arm_box", 58),
+                                                ("hand_cube", 20)])
 def test_step_adjoint_vs_finite_differences(model, steps_before, fp64):
-    env = W.env_ant() if model == "ant" else W.env_humanoid()
-    env, params, oe, root, dof, act, wr, wd = A.f32_inputs(env, W.SimParams(), 16, steps_before)
+    """Gradients of one env-step; arm+box and hand+cube exercise two-body (sphere/capsule-vs-box) rows."""
+    env = {"ant": W.env_ant, "humanoid": W.env_humanoid, "arm_box": W.env_arm_box, "hand_cube": W.env_hand_cube}[model]()
+    p = W.HAND_PARAMS if model == "hand_cube" else W.SimParams()
+    env, params, oe, root, dof, act, wr, wd = A.f32_inputs(env, p, 16, steps_before)
     fd, ent = A.fd_grads(oe, params, root, dof, act, wr, wd)
     g, status = A.gpu_grads(env, params, root, dof, act, wr, wd, fp64)
     assert (status == 0).all(), status
@@ -61,8 +64,8 @@ def _ant_rollout_case(E=16, T=16, warm=30):
     return env, params, oe, r32(root), r32(dof), r32(acts[warm:])
 
 
-@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
-def test_rollout_gradient_ant(fp64):
+@pytest.mark.parametrize("adj", [64, 32], ids=["adj64", "adj32"])
+def test_rollout_gradient_ant(adj):
     """Ant-like envs, loss = sum of final torso x after 16 steps, gradient w.r.t. every action through
     ags.rollout with checkpoints every 4 steps, against central differences of FP64 oracle rollouts.
 
@@ -72,15 +75,17 @@ def test_rollout_gradient_ant(fp64):
     state matches the oracle's step from the same FP32 state (single-step tolerance) and that oracle
     step takes the unperturbed rollout's discrete decisions.  Each entry is allowed, on top of the 1e-3
     relative bound, the finite differences' own uncertainty |fd(H) - fd(10 H)| and the gradient's change
-    when the initial state moves by one FP32 ulp (the scale of the GPU's per-step rounding)."""
+    when the initial state moves by one FP32 ulp (the scale of the GPU's per-step rounding).  The forward
+    computes in FP64 (the configuration that meets the state tolerance); the adjoint in FP64 or FP32."""
     E, T, every = 16, 16, 4
+    fp64 = True
     env, params, oe, root, dof, acts = _ant_rollout_case(E, T)
     fd, modes = A.fd_rollout(oe, params, root, dof, acts)
     fd10, _ = A.fd_rollout(oe, params, root, dof, acts, h=10 * A.H)
     rng = np.random.default_rng(5)
     ulp = lambda x: x * (1.0 + rng.choice([-1.0, 1.0], size=x.shape) * 2.0 ** -23)
     fdp, _ = A.fd_rollout(oe, params, ulp(root), ulp(dof), acts)
-    g, _ = A.gpu_rollout_grad(env, params, root, dof, acts, every, fp64)
+    g, _ = A.gpu_rollout_grad(env, params, root, dof, acts, every, fp64, adjoint_precision=adj)
     roots, dofs = A.gpu_trajectory(env, params, root, dof, acts, fp64)
     on_path = np.ones(E, dtype=bool)
     for t in range(T):
@@ -93,7 +98,7 @@ def test_rollout_gradient_ant(fp64):
     unc = (np.abs(fd - fd10) + np.abs(fd - fdp)).reshape(E, -1)
     ok = ~np.isnan(fdf) & ~np.isnan(unc) & on_path[:, None]
     scale = np.nanmax(np.abs(fdf), axis=1, keepdims=True)
-    base = A.RTOL * np.abs(fdf) + 1e-6 * scale
+    base = A.RTOL * np.abs(fdf) + FLOOR[adj == 64] * scale
     ratio = np.where(ok, np.abs(gf - fdf) / (base + unc + 1e-30), 0.0)
     strict = np.where(ok, np.abs(gf - fdf) / (base + 1e-30), 0.0)
     worst = ratio.max(axis=1)
@@ -102,7 +107,7 @@ def test_rollout_gradient_ant(fp64):
          "worst_ratio": float(worst.max()), "worst_ratio_without_allowances": float(strict.max()),
          "median_ratio_without_allowances": float(np.median(strict[ok])) if ok.any() else 0.0,
          "grad_abs_max": float(np.nanmax(np.abs(fdf)))}
-    _report(f"rollout_ant_{'fp64' if fp64 else 'fp32'}", d)
+    _report(f"rollout_ant_adj{adj}", d)
     assert on_path.sum() >= E // 2, d
     assert (worst <= 1.0).all(), d
 
@@ -130,3 +135,47 @@ def test_rollout_equals_chained_step_adjoints(fp64):
         chain[:, t] = aa.double().cpu().numpy().reshape(E, env.n_dof)
     torch.cuda.synchronize()
     assert np.array_equal(chain, g), float(np.abs(chain - g).max())
+
+
+@pytest.mark.parametrize("adj", [64, 32], ids=["adj64", "adj32"])
+def test_rollout_gradient_hand_targets(adj):
+    """Hand+cube, PD targets as the controls (zero actuation), loss = sum of the cube's final x after 8
+    steps, gradient w.r.t. every target through ags.rollout (checkpoint every 4), on the envs whose GPU
+    trajectory stays on the oracle's (as in the ant rollout test)."""
+    E, T, every = 16, 8, 4
+    fp64 = True
+    env = W.as_f32(W.env_hand_cube())
+    params = W.params_f32(W.HAND_PARAMS)
+    oe = A.O.OracleEnv(env)
+    root, dof = W.initial_state(env, E, 0)
+    tg = W.pd_targets(env, E, 20 + T, 0)
+    zero = np.zeros((E, env.n_dof))
+    for t in range(20):
+        o = oe.step(params, root, dof, zero, pos_tgt=tg[t])
+        root, dof = o["root"], o["dof"]
+    r32 = lambda x: x.astype(np.float32).astype(np.float64)
+    root, dof, tg = r32(root), r32(dof), r32(tg[20:])
+    fd, modes = A.fd_rollout(oe, params, root, dof, tg, targets=True, actor=1)
+    fd10, _ = A.fd_rollout(oe, params, root, dof, tg, h=10 * A.H, targets=True, actor=1)
+    g, _ = A.gpu_rollout_grad(env, params, root, dof, tg, every, fp64, targets=True, actor=1, adjoint_precision=adj)
+    roots, dofs = A.gpu_trajectory(env, params, root, dof, tg, fp64, targets=True)
+    on_path = np.ones(E, dtype=bool)
+    for t in range(T):
+        o = oe.step(params, roots[t], dofs[t], zero, pos_tgt=tg[t])
+        on_path &= o["mode"] == modes[:, t]
+        st_g = np.concatenate([roots[t + 1].reshape(E, -1), dofs[t + 1].reshape(E, -1)], axis=1)
+        st_o = np.concatenate([o["root"].reshape(E, -1), o["dof"].reshape(E, -1)], axis=1)
+        on_path &= (np.abs(st_g - st_o) <= 1e-5 + 1e-4 * np.abs(st_o)).all(axis=1)
+    fdf, gf = fd.reshape(E, -1), g.reshape(E, -1)
+    unc = np.abs(fd - fd10).reshape(E, -1)
+    ok = ~np.isnan(fdf) & ~np.isnan(unc) & on_path[:, None]
+    scale = np.nanmax(np.abs(fdf), axis=1, keepdims=True)
+    base = A.RTOL * np.abs(fdf) + FLOOR[adj == 64] * scale
+    ratio = np.where(ok, np.abs(gf - fdf) / (base + unc + 1e-30), 0.0)
+    worst = ratio.max(axis=1)
+    d = {"envs": E, "steps": T, "every": every, "envs_on_oracle_path": int(on_path.sum()),
+         "entries_checked": int(ok.sum()), "excluded_switch": int(np.isnan(fdf).sum()),
+         "worst_ratio": float(worst.max()), "grad_abs_max": float(np.nanmax(np.abs(fdf)))}
+    _report(f"rollout_hand_targets_adj{adj}", d)
+    assert on_path.sum() >= E // 2, d
+    assert (worst <= 1.0).all(), d
