@@ -164,7 +164,9 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, ad
     L.ags_rollout_state_size(sim.h, ctypes.byref(n))
     f32 = dict(dtype=torch.float32, device="cuda:0")
     ckpt = torch.empty(((T + every - 1) // every, n.value), **f32)
-    seg = torch.empty((every, n.value), **f32)
+    nb = ctypes.c_int64()
+    L.ags_rollout_seg_bytes(sim.h, every, ctypes.byref(nb))
+    seg = torch.empty(nb.value, dtype=torch.uint8, device="cuda:0")
     root_adj = torch.empty_like(sim.root_state)
     dof_adj = torch.empty_like(sim.dof_state)
     act_adj = torch.empty_like(actions)
@@ -193,8 +195,8 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, ad
     times = [one() for _ in range(reps)]
     fwd = float(np.median([t[0] for t in times]))
     bwd = float(np.median([t[1] for t in times]))
-    # the adjoint kernel alone: one launch per step on a fixed state
-    x = seg[0]
+    # the adjoint kernel alone: one launch per step on a fixed state (the checkpoint of the first segment)
+    x = ckpt[0]
     nr = 13 * sim.shapes[ags.ROOT_STATE][0]
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
     for a, b in evs:

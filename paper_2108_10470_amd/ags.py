@@ -88,6 +88,7 @@ def lib():
         L.ags_sim_set_dof_state_indexed.argtypes = [vp, vp, vp, i32, vp]
         L.ags_sim_step_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ags_rollout_state_size.argtypes = [vp, i64p]
+        L.ags_rollout_seg_bytes.argtypes = [vp, i32, i64p]
         L.ags_autotune.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(ctypes.c_int32), i32, ctypes.POINTER(SimParams),
                                    vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
         L.ags_rollout_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp]
@@ -99,7 +100,8 @@ def lib():
 EXPORTED = ["ags_last_error", "ags_model_create", "ags_model_destroy", "ags_model_get_info", "ags_model_mass_props",
             "ags_sim_create", "ags_sim_destroy", "ags_sim_tensor_shape", "ags_sim_bind", "ags_sim_step",
             "ags_sim_set_root_state_indexed", "ags_sim_set_dof_state_indexed", "ags_sim_step_backward",
-            "ags_rollout_state_size", "ags_rollout_forward", "ags_rollout_backward", "ags_autotune"]
+            "ags_rollout_state_size", "ags_rollout_forward", "ags_rollout_backward", "ags_autotune",
+            "ags_rollout_seg_bytes"]
 
 
 def _check(rc: int, what: str):
@@ -297,7 +299,9 @@ class Rollout(torch.autograd.Function):
         root_adj = (g_root if g_root is not None else torch.zeros_like(sim.root_state)).float().contiguous().clone()
         dof_adj = (g_dof if g_dof is not None else torch.zeros_like(sim.dof_state)).float().contiguous().clone()
         act_adj = torch.empty_like(actions)
-        seg = torch.empty((every, ctx.state_words), dtype=torch.float32, device=sim.device)
+        nb = ctypes.c_int64()
+        _check(lib().ags_rollout_seg_bytes(sim.h, every, ctypes.byref(nb)), "ags_rollout_seg_bytes")
+        seg = torch.empty(nb.value, dtype=torch.uint8, device=sim.device)
         status = torch.zeros(sim.n_envs, dtype=torch.int32, device=sim.device)
         s = torch.cuda.current_stream(sim.device)
         _check(lib().ags_rollout_backward(sim.h, T, every, ctx.control, ctypes.c_void_p(actions.data_ptr()),

@@ -270,26 +270,34 @@ __device__ __forceinline__ void sphere_box(V3<R> c, const R* Rb, V3<R> b, V3<R> 
       const R m[3] = {xl.x != ql.x ? R(1) : R(0), xl.y != ql.y ? R(1) : R(0), xl.z != ql.z ? R(1) : R(0)};
       const R nv[3] = {nl.x, nl.y, nl.z};
       R Lc[9];  // (1 - nl nl^T) diag(m) / dn in box coordinates
+#pragma unroll
       for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) Lc[3 * i + j] = ((i == j ? R(1) : R(0)) - nv[i] * nv[j]) * m[j] / dn;
       R T[9];  // Rb Lc
+#pragma unroll
       for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) T[3 * i + j] = Rb[3 * i] * Lc[j] + Rb[3 * i + 1] * Lc[3 + j] + Rb[3 * i + 2] * Lc[6 + j];
+#pragma unroll
       for (int i = 0; i < 3; ++i)
+#pragma unroll
         for (int j = 0; j < 3; ++j) G[3 * i + j] = T[3 * i] * Rb[3 * j] + T[3 * i + 1] * Rb[3 * j + 1] + T[3 * i + 2] * Rb[3 * j + 2];
     }
   } else {
-    const R pen[3] = {hb.x - (xl.x < R(0) ? -xl.x : xl.x), hb.y - (xl.y < R(0) ? -xl.y : xl.y),
-                      hb.z - (xl.z < R(0) ? -xl.z : xl.z)};
-    const R xs[3] = {xl.x, xl.y, xl.z};
+    const R p0 = hb.x - (xl.x < R(0) ? -xl.x : xl.x), p1 = hb.y - (xl.y < R(0) ? -xl.y : xl.y),
+            p2 = hb.z - (xl.z < R(0) ? -xl.z : xl.z);
     int kb = 0;
-    if (pen[1] < pen[kb]) kb = 1;
-    if (pen[2] < pen[kb]) kb = 2;
-    const R sg = xs[kb] >= R(0) ? R(1) : R(-1);
+    R pb = p0, xb = xl.x;
+    if (p1 < pb) { kb = 1; pb = p1; xb = xl.y; }
+    if (p2 < pb) { kb = 2; pb = p2; xb = xl.z; }
+    const R sg = xb >= R(0) ? R(1) : R(-1);
     nl = kb == 0 ? mk(sg, R(0), R(0)) : (kb == 1 ? mk(R(0), sg, R(0)) : mk(R(0), R(0), sg));
-    phi = -pen[kb] - rad;
-    if (G)
+    phi = -pb - rad;
+    if (G) {
+#pragma unroll
       for (int k = 0; k < 9; ++k) G[k] = R(0);
+    }
   }
   n = mv(Rb, nl);
 }
@@ -312,10 +320,12 @@ struct Env {
   long long cyc[kAdjPhases];  // shader-clock cycles per phase (lane 0 keeps them; only when requested)
   int cur;
   long long mark;
-  __device__ void phase(int ph) {
+  __device__ __forceinline__ void phase(int ph) {
     if (!P->cycles) return;
     const long long now = (long long)clock64();
-    if (cur >= 0) cyc[cur] += now - mark;
+#pragma unroll
+    for (int k = 0; k < kAdjPhases; ++k)  // selects, not an indexed store: the counters stay in registers
+      if (cur == k) cyc[k] += now - mark;
     cur = ph;
     mark = now;
   }
@@ -338,9 +348,9 @@ __device__ __forceinline__ SV<R> joint_s(const Env<R>& E, int i) {
   if (E.li(i)[LI_JTYPE] == J_REV) return {ax, cross(ld3<R>(E.at(L.p, i, 3)), ax)};
   return {zero3<R>(), ax};
 }
-// motion vector of generalized column k (a joint's, or one of a free root's six)
+// motion vector of generalized column k (a joint's, or one of a free root's six), from geometry
 template <typename R>
-__device__ __forceinline__ SV<R> col_s(const Env<R>& E, int k) {
+__device__ __forceinline__ SV<R> col_s_geo(const Env<R>& E, int k) {
   const int i = E.P->m.col_link[k];
   const int* li = E.li(i);
   if (li[LI_PARENT] >= 0) return joint_s(E, i);
@@ -352,6 +362,12 @@ __device__ __forceinline__ SV<R> col_s(const Env<R>& E, int k) {
   if (a < 3) return {zero3<R>(), e};
   return {e, cross(ld3<R>(E.at(E.P->L.c, i, 3)), e)};
 }
+// the same, as stored once per substep after the kinematics
+template <typename R>
+__device__ __forceinline__ SV<R> col_s(const Env<R>& E, int k) {
+  return lds6(E.r + E.P->L.cs + 6 * k);
+}
+
 // S_0 x for a free root with COM c0: (x_w, x_v + c0 x x_w)
 template <typename R>
 __device__ __forceinline__ SV<R> root_vel(V3<R> c0, const R* x) {
@@ -398,20 +414,35 @@ __device__ R chol_solve_lanes(const Env<R>& E, R b) {
   }
   return c < nv ? b : R(0);
 }
-// solve in place on one LDS row per lane (row pointer y, length nv)
+// solve in place on one LDS row per lane (row pointer y, length nv); four partial sums per dot product
 template <typename R>
 __device__ void chol_solve_row(const Env<R>& E, R* y) {
   const R* Lm = E.r + E.P->L.Lm;
   const int nvp = E.P->L.nvp, nv = E.nv;
   for (int k = 0; k < nv; ++k) {
-    R t = y[k];
-    for (int j = 0; j < k; ++j) t -= Lm[k * nvp + j] * y[j];
-    y[k] = t / Lm[k * nvp + k];
+    const R* Lk = Lm + k * nvp;
+    R t0 = y[k], t1 = R(0), t2 = R(0), t3 = R(0);
+    int j = 0;
+    for (; j + 3 < k; j += 4) {
+      t0 -= Lk[j] * y[j];
+      t1 -= Lk[j + 1] * y[j + 1];
+      t2 -= Lk[j + 2] * y[j + 2];
+      t3 -= Lk[j + 3] * y[j + 3];
+    }
+    for (; j < k; ++j) t0 -= Lk[j] * y[j];
+    y[k] = ((t0 + t1) + (t2 + t3)) / Lk[k];
   }
   for (int k = nv - 1; k >= 0; --k) {
-    R t = y[k];
-    for (int j = k + 1; j < nv; ++j) t -= Lm[j * nvp + k] * y[j];
-    y[k] = t / Lm[k * nvp + k];
+    R t0 = y[k], t1 = R(0), t2 = R(0), t3 = R(0);
+    int j = k + 1;
+    for (; j + 3 < nv; j += 4) {
+      t0 -= Lm[j * nvp + k] * y[j];
+      t1 -= Lm[(j + 1) * nvp + k] * y[j + 1];
+      t2 -= Lm[(j + 2) * nvp + k] * y[j + 2];
+      t3 -= Lm[(j + 3) * nvp + k] * y[j + 3];
+    }
+    for (; j < nv; ++j) t0 -= Lm[j * nvp + k] * y[j];
+    y[k] = ((t0 + t1) + (t2 + t3)) / Lm[k * nvp + k];
   }
 }
 
@@ -550,6 +581,8 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     }
     sync<R>();
   }
+  for (int k = lane; k < nv; k += 64) sts6(E.r + L.cs + 6 * k, col_s_geo(E, k));
+  sync<R>();
   // ---- M~ (lower triangle) from composite inertias: M_kj = s_j . (Ic_k s_k), j an ancestor column of k
   R* Lm = E.r + L.Lm;
   const int nvp = L.nvp;
@@ -561,16 +594,25 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     Lm[k * nvp + k] = sdot(sk, F) + arm[k];
   }
   sync<R>();
-  // ---- dense Cholesky in place
+  // ---- dense Cholesky in place, left-looking: column k from the finished columns j < k (lane = row)
   for (int k = 0; k < nv; ++k) {
-    const R d = sqrt_(Lm[k * nvp + k]);
-    sync<R>();
-    for (int i = k + lane; i < nv; i += 64) Lm[i * nvp + k] = i == k ? d : Lm[i * nvp + k] / d;
-    sync<R>();
-    for (int i = k + 1 + lane; i < nv; i += 64) {
-      const R lik = Lm[i * nvp + k];
-      for (int j = k + 1; j <= i; ++j) Lm[i * nvp + j] -= lik * Lm[j * nvp + k];
+    R sacc = R(0);
+    if (lane >= k && lane < nv) {
+      const R* Li = Lm + lane * nvp;
+      const R* Lk = Lm + k * nvp;
+      R t0 = Li[k], t1 = R(0), t2 = R(0), t3 = R(0);
+      int j = 0;
+      for (; j + 3 < k; j += 4) {
+        t0 -= Li[j] * Lk[j];
+        t1 -= Li[j + 1] * Lk[j + 1];
+        t2 -= Li[j + 2] * Lk[j + 2];
+        t3 -= Li[j + 3] * Lk[j + 3];
+      }
+      for (; j < k; ++j) t0 -= Li[j] * Lk[j];
+      sacc = (t0 + t1) + (t2 + t3);
     }
+    const R d = sqrt_(lane_read(sacc, k));
+    if (lane >= k && lane < nv) Lm[lane * nvp + k] = lane == k ? d : sacc / d;
     sync<R>();
   }
   // ---- C(q, qd): RNEA with zero joint accelerations, gravity as a base acceleration
@@ -1467,7 +1509,17 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
   sync<R>();
   E.ref = mk(st[0], st[1], st[2]);
   bool ok = true;
-  for (int s = 0; s + 1 < S && ok; ++s) ok = fwd_substep(E, st + s * sw, st + (s + 1) * sw);
+  if (P.mid_root) {  // substep start states handed over by the forward step
+    for (int s = 1; s < S; ++s) {
+      const double* mr = P.mid_root + (long long)(s - 1) * P.mid_block + (long long)E.abase * 13;
+      const double* md = P.mid_dof + (long long)(s - 1) * P.mid_block + (long long)E.dbase * 2;
+      for (int k = lane; k < 13 * na; k += 64) st[s * sw + k] = R(mr[k]);
+      for (int k = lane; k < 2 * nd; k += 64) st[s * sw + 13 * na + k] = R(md[k]);
+    }
+    sync<R>();
+  } else {
+    for (int s = 0; s + 1 < S && ok; ++s) ok = fwd_substep(E, st + s * sw, st + (s + 1) * sw);
+  }
   for (int s = S - 1; s >= 0 && ok; --s) {
     ok = fwd_substep(E, st + s * sw, st + S * sw);
     if (ok) rev_substep(E, st + s * sw);

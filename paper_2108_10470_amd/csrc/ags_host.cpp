@@ -442,7 +442,7 @@ AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters) {
   L.tI = take(3 * nl);
   L.nu = take(nv); L.qdd = take(nv); L.vs = take(nv); L.nu1 = take(nv); L.tau = take(nv); L.arm = take(nv);
   L.z = take(nv); L.w = take(nv); L.nub = take(nv); L.vsb = take(nv); L.nui = take(nv); L.tmp = take(nv);
-  L.colS = take(6 * nv); L.colY = take(6 * nv); L.colYv = take(6 * nv);
+  L.colS = take(6 * nv); L.colY = take(6 * nv); L.colYv = take(6 * nv); L.cs = take(6 * nv);
   L.q = take(nd); L.qb = take(nd); L.ab = take(nd);
   L.state_words = 13 * na + 2 * info.n_dof;
   L.st = take((substeps + 1) * L.state_words);
@@ -519,6 +519,7 @@ struct ags_sim {
   int n_actors_total = 0, n_dof_total = 0, n_bodies_total = 0, max_nv = 0, max_rows = 0;
   void* bound[AGS_NUM_TENSORS] = {nullptr};
   float* kp_dof = nullptr;  // device: drive stiffness of every DOF (target adjoints)
+  double* mid_root = nullptr;  // set while a rollout recomputes: where the step writes substep states
   // persistent (fused) launch
   bool fused_ok = false;
   int* units = nullptr;  // device: (type, group) pairs
@@ -803,6 +804,9 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
   a.dbg_row_stride = p.substeps * std::max(1, S->max_rows);
   a.dbg_row_sub = std::max(1, S->max_rows);
   a.dbg_cycles = (long long*)S->bound[AGS_DEBUG_PHASE_CYCLES];
+  a.mid_root = S->mid_root;
+  a.mid_dof = S->mid_root ? S->mid_root + 13ll * S->n_actors_total : nullptr;
+  a.mid_block = 13ll * S->n_actors_total + 2ll * S->n_dof_total;
   a.dt = p.dt;
   a.h = (double)p.dt / p.substeps;
   a.gx = p.gravity[0];
@@ -868,6 +872,9 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
     a.act_adj = act_adj;
     a.status = status;
     a.cycles = (long long*)S->bound[AGS_DEBUG_ADJ_CYCLES];
+    a.mid_root = S->mid_root;
+    a.mid_dof = S->mid_root ? S->mid_root + 13ll * S->n_actors_total : nullptr;
+    a.mid_block = 13ll * S->n_actors_total + 2ll * S->n_dof_total;
     a.h = (double)p.dt / p.substeps;
     a.gx = p.gravity[0];
     a.gy = p.gravity[1];
@@ -887,6 +894,14 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
 extern "C" int ags_rollout_state_size(const ags_sim* S, int64_t* floats) {
   if (!S || !floats) return fail(AGS_E_ARG, "rollout_state_size: bad arguments");
   *floats = 13ll * S->n_actors_total + 2ll * S->n_dof_total;
+  return AGS_OK;
+}
+
+extern "C" int ags_rollout_seg_bytes(const ags_sim* S, int32_t every, int64_t* bytes) {
+  if (!S || every < 1 || !bytes) return fail(AGS_E_ARG, "rollout_seg_bytes: bad arguments");
+  const long long sw = 13ll * S->n_actors_total + 2ll * S->n_dof_total;
+  const long long mid = (long long)every * std::max(0, S->params.substeps - 1) * sw;
+  *bytes = ((every + 1) * sw * (long long)sizeof(float) + 255) / 256 * 256 + mid * (long long)sizeof(double);
   return AGS_OK;
 }
 
@@ -933,26 +948,34 @@ extern "C" int ags_rollout_forward(ags_sim* S, int32_t n_steps, int32_t every, i
 }
 
 extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, int32_t control, const float* actions,
-                                    const float* ckpt, float* seg, float* root_adj, float* dof_adj, float* act_adj,
+                                    const float* ckpt, void* seg_bytes, float* root_adj, float* dof_adj, float* act_adj,
                                     int32_t* status, void* stream) {
-  if (!S || n_steps < 1 || every < 1 || !actions || !ckpt || !seg || !root_adj || !dof_adj || !act_adj ||
+  if (!S || n_steps < 1 || every < 1 || !actions || !ckpt || !seg_bytes || !root_adj || !dof_adj || !act_adj ||
       (control != AGS_DOF_ACTUATION && control != AGS_DOF_POS_TARGET))
     return fail(AGS_E_ARG, "rollout_backward: bad arguments");
   if (!S->bound[AGS_DOF_ACTUATION]) return fail(AGS_E_UNBOUND, "rollout_backward: the actuation tensor must be bound");
   const size_t nr = 13ull * S->n_actors_total, nd = 2ull * S->n_dof_total, sw = nr + nd;
   const size_t na = (size_t)S->n_dof_total;
+  const int nmid = std::max(0, S->params.substeps - 1);
+  float* seg = static_cast<float*>(seg_bytes);  // every + 1 states, then every x nmid FP64 substep states
+  double* mid = reinterpret_cast<double*>(static_cast<char*>(seg_bytes) +
+                                          ((every + 1) * sw * sizeof(float) + 255) / 256 * 256);
   hipStream_t st = (hipStream_t)stream;
   const int n_seg = (n_steps + every - 1) / every;
   for (int g = n_seg - 1; g >= 0; --g) {
     const int t0 = g * every, t1 = std::min(n_steps, t0 + every);
     hipError_t e = hipMemcpyAsync(seg, ckpt + (size_t)g * sw, sw * sizeof(float), hipMemcpyDeviceToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "rollout_backward: copy");
-    for (int t = t0; t + 1 < t1; ++t) {  // recompute the states before steps t0+1 .. t1-1
+    // recompute the states before steps t0+1 .. t1-1 (the last step's end state is discarded) and the
+    // substep states of every step of the segment
+    for (int t = t0; t < t1; ++t) {
       float* a = seg + (size_t)(t - t0) * sw;
       float* b = a + sw;
       if ((e = hipMemcpyAsync(b, a, sw * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess)
         return hip_fail(e, "rollout_backward: copy");
+      S->mid_root = nmid ? mid + (size_t)(t - t0) * nmid * sw : nullptr;
       const int rc = step_on(S, b, b + nr, control, actions + (size_t)t * na, st);
+      S->mid_root = nullptr;
       if (rc != AGS_OK) return rc;
     }
     for (int t = t1 - 1; t >= t0; --t) {
@@ -961,7 +984,9 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
       S->bound[control] = const_cast<float*>(actions + (size_t)t * na);
       // the actuation the step used: the per-step array or the bound tensor
       const float* act = (const float*)S->bound[AGS_DOF_ACTUATION];
+      S->mid_root = nmid ? mid + (size_t)(t - t0) * nmid * sw : nullptr;
       int rc = ags_sim_step_backward(S, x, x + nr, act, root_adj, dof_adj, act_adj + (size_t)t * na, status, stream);
+      S->mid_root = nullptr;
       S->bound[control] = saved;
       if (rc == AGS_OK && control == AGS_DOF_POS_TARGET) {
         // the target enters the step only through tau = ... + kp q*: dL/dq* = kp dL/dtau

@@ -93,6 +93,11 @@ struct StepArgs {
   float* dbg_lam;
   int dbg_row_stride, dbg_row_sub;  // per env, per substep (sim-wide maximum rows)
   long long* dbg_cycles;            // per env: shader-clock cycles spent in each phase (kPhases)
+  // optional: the state after every substep but the last (FP64, the layout of a state: root rows then
+  // DOF rows; block s of mid_block doubles holds substep s)
+  double* mid_root;
+  double* mid_dof;
+  long long mid_block;
   double dt, h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
 };
@@ -120,7 +125,7 @@ constexpr int kAdjPhases = 8;
 struct AdjLds {
   int Rm, p, ax, c, Iw, Ic, V, Vs, X0, X1, X2, X3, wr, sb, cb, tI;  // per link
   int nu, qdd, vs, nu1, tau, arm, z, w, nub, vsb, nui, tmp;        // per column
-  int colS, colY, colYv;                                           // per column, 6 each
+  int colS, colY, colYv, cs;                                       // per column, 6 each
   int q, qb, ab;                                                   // per DOF
   int st, rbar, dbar, nrb;                                             // state of each substep start, state adjoint
   int Lm, nvp;                                                     // dense n_v x nvp matrix (factor, then P)
@@ -153,6 +158,9 @@ struct AdjArgs {
   float* act_adj;
   int* status;
   long long* cycles;  // optional, per env: kAdjPhases shader-clock counters
+  const double* mid_root;  // optional: substep start states from the forward step (see StepArgs)
+  const double* mid_dof;
+  long long mid_block;
   double h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
 };

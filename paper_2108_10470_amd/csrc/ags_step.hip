@@ -1198,6 +1198,15 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       st3(rs + 10, w);
     }
     __syncthreads();
+    if (P.mid_root && sub_i + 1 < P.substeps && valid) {  // state after this substep, for the adjoint
+      double* mr = P.mid_root + (long long)sub_i * P.mid_block + (long long)abase * 13;
+      double* md = P.mid_dof + (long long)sub_i * P.mid_block + (long long)dbase * 2;
+      for (int k = tt; k < 13 * na; k += TEAM) mr[k] = double(s.root[k]);
+      for (int j = tt; j < nd; j += TEAM) {
+        md[2 * j] = double(s.qj[j]);
+        md[2 * j + 1] = double(s.qd[M.li[M.dof_link[j] * LI_COLS + LI_COL]]);
+      }
+    }
     PHASE_MARK(-1);
   }
 

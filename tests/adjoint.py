@@ -104,7 +104,7 @@ def f32_inputs(env, params, n_envs, steps_before, seed=0):
     return env, params, oe, r32(root), r32(dof), r32(acts[steps_before]), wr, wd
 
 
-def fd_rollout(oe, params, root0, dof0, acts, n_threads=None, h=None, targets=False, actor=0):
+def fd_rollout(oe, params, root0, dof0, acts, n_threads=None, h=None, targets=False, actor=0, weights=None):
     """Central differences (step h, default H) of L = sum over envs of actor `actor`'s final root x
     position after the rollout of acts (T, E, D) (the actuation, or with targets=True the PD position
     targets with zero actuation), with respect to every entry; NaN where any step's mode changes.
@@ -133,7 +133,11 @@ def fd_rollout(oe, params, root0, dof0, acts, n_threads=None, h=None, targets=Fa
             R, D = o["root"], o["dof"]
             mode = (mode * np.uint64(1099511628211)) ^ o["mode"]
             base_modes[:, t] = o["mode"].reshape(E, C)[:, 2 * n]
-    L = R.reshape(E, C, -1, 13)[:, :, actor, 0]
+    if weights is None:
+        L = R.reshape(E, C, -1, 13)[:, :, actor, 0]
+    else:  # L = sum(wr * final root states) + sum(wd * final DOF states)
+        wr, wd = weights
+        L = ((R.reshape(E, C, -1) * wr.reshape(E, 1, -1)).sum(-1) + (D.reshape(E, C, -1) * wd.reshape(E, 1, -1)).sum(-1))
     mode = mode.reshape(E, C)
     g = (L[:, 0:2 * n:2] - L[:, 1:2 * n:2]) / (2 * H_)
     same = (mode[:, 0:2 * n:2] == mode[:, 2 * n:]) & (mode[:, 1:2 * n:2] == mode[:, 2 * n:])
@@ -162,7 +166,7 @@ def gpu_trajectory(env, params, root0, dof0, acts, fp64, device="cuda:0", target
 
 
 def gpu_rollout_grad(env, params, root0, dof0, acts, every, fp64, device="cuda:0", targets=False, actor=0,
-                     adjoint_precision=0):
+                     adjoint_precision=0, weights=None):
     """The same gradient through ags.rollout (checkpoints every `every` steps) and torch autograd."""
     T, E, nd = acts.shape
     sim = ags.Sim([ags.Model(env)], [0] * E, params, device=device, fp64=fp64, pd=targets,
@@ -173,7 +177,11 @@ def gpu_rollout_grad(env, params, root0, dof0, acts, every, fp64, device="cuda:0
     d0 = torch.tensor(dof0.reshape(-1, 2), **f32)
     root, dof = ags.rollout(sim, a, r0, d0, every=every,
                             control=ags.DOF_POS_TARGET if targets else ags.DOF_ACTUATION)
-    loss = root.view(E, env.n_actors, 13)[:, actor, 0].sum()
+    if weights is None:
+        loss = root.view(E, env.n_actors, 13)[:, actor, 0].sum()
+    else:
+        wr, wd = (torch.tensor(w.reshape(-1), **f32) for w in weights)
+        loss = (root.reshape(-1) * wr).sum() + (dof.reshape(-1) * wd).sum()
     loss.backward()
     torch.cuda.synchronize()
     return a.grad.double().cpu().numpy().reshape(T, E, nd).transpose(1, 0, 2), root.detach().double().cpu().numpy()
