@@ -29,16 +29,19 @@ FLOPS_BASE, FLOPS_PER_ROW = 37.0e3, 5.1e3
 BYTES_PER_ENV_STEP = 680.0
 PEAK_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP32 unpacked == FP64 vector)
 PEAK_HBM_GBS = 8000.0
-PROFILE = os.path.join(ROOT, "profiles", "step_kernel_humanoid4096.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2108_10470_amd", "csrc", f) for f in ("ags_step.hip", "ags_internal.h")]
+CSRC = os.path.join(ROOT, "paper_2108_10470_amd", "csrc")
+PROFILES = {"step": (os.path.join(ROOT, "profiles", "step_kernel_humanoid4096.md"), ("ags_step.hip", "ags_internal.h")),
+            "adjoint": (os.path.join(ROOT, "profiles", "adjoint_kernel_humanoid4096.md"),
+                        ("ags_adjoint.hip", "ags_internal.h"))}
 
 
-def measured_traffic(variant):
+def measured_traffic(variant, kernel="step"):
     """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the
     kernel source changed since the counters were taken."""
     import hashlib
+    PROFILE, sources = PROFILES[kernel]
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in (os.path.join(CSRC, x) for x in sources):
         with open(f, "rb") as fh:
             h.update(fh.read())
     try:
@@ -211,7 +214,9 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, ad
             "envs_over_row_capacity": int((status != 0).sum()), "finite": bool(torch.isfinite(act_adj).all()),
             "grad_abs_mean": float(act_adj.abs().mean()), "dtype": "f64" if fp64 else "f32",
             "adjoint_dtype": "f64" if adjoint_precision == 64 or (adjoint_precision == 0 and fp64) else "f32",
-            "loss": "sum over envs of the final torso x position", "reps": reps}
+            "loss": "sum over envs of the final torso x position", "reps": reps,
+            "adjoint_traffic_bytes_per_launch": measured_traffic(
+                "fp64" if adjoint_precision == 64 or (adjoint_precision == 0 and fp64) else "fp32", "adjoint")}
 
 
 def run_hetero(params, n_envs, steps, fp64):
@@ -382,9 +387,8 @@ def main():
     h = res[head]
     value = E * K / (h["total_ms"] / 1e3)
     t_launch = float(h["launch_ms"].mean()) / 1e3
-    rows = h["rows"] if h["rows"] is not None else float("nan")
-    flops = E * (FLOPS_BASE + FLOPS_PER_ROW * rows)
-    ach_tf = flops / t_launch / 1e12
+    rows = h["rows"]  # None with --no-rows: the flop count needs the measured row count
+    ach_tf = None if rows is None else E * (FLOPS_BASE + FLOPS_PER_ROW * rows) / t_launch / 1e12
     ach_gbs = E * BYTES_PER_ENV_STEP / t_launch / 1e9
     out = {
         "metric": METRIC, "value": value, "unit": "env-steps/s", "n_gpus": 1, "steps": K, "warmup": Wm,
@@ -395,7 +399,7 @@ def main():
                    "envs": E, "substeps": params.substeps, "pgs_iters": params.pgs_iters,
                    "tensors": "f32", "compute": head, "mean_rows_per_substep": rows},
         "roofline": {"bound": "alu", "achieved": ach_tf, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach_tf / PEAK_VALU_TFLOPS, "traffic": measured_traffic(head),
+                     "frac": None if ach_tf is None else ach_tf / PEAK_VALU_TFLOPS, "traffic": measured_traffic(head),
                      "kernel": "step_kernel<double>" if head == "fp64" else "step_kernel<float>",
                      "launch_ms": t_launch * 1e3,
                      "hbm": {"achieved": ach_gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": ach_gbs / PEAK_HBM_GBS,
