@@ -104,6 +104,7 @@ struct ags_model {
   std::vector<unsigned long long> link_anc, col_anc;  // ancestor bit masks (links; generalized columns)
   std::vector<int> col_link;                           // owning link of each generalized column
   bool body_pairs = false;                             // has sphere/capsule-vs-box pairs
+  int max_joint_entries = 0;  // most revolute/prismatic joints on the paths of one slot's two bodies
   std::vector<float> mass, com, inertia;
 };
 
@@ -370,6 +371,19 @@ extern "C" int ags_model_create(const ags_actor_desc* actors, int32_t n_actors, 
     }
   }
   const int ns = (int)(M->si.size() / SI_COLS);
+  {
+    auto joints_to_root = [&](int k) {
+      int n = 0;
+      for (; k >= 0; k = M->li[k * LI_COLS + LI_PARENT])
+        n += M->jtype[k] == AGS_JOINT_REVOLUTE || M->jtype[k] == AGS_JOINT_PRISMATIC;
+      return n;
+    };
+    for (int sl = 0; sl < ns; ++sl) {
+      const int* r = &M->si[(size_t)sl * SI_COLS];
+      M->max_joint_entries = std::max(M->max_joint_entries,
+                                      joints_to_root(r[SI_LINK_A]) + (r[SI_LINK_B] >= 0 ? joints_to_root(r[SI_LINK_B]) : 0));
+    }
+  }
   if (ns > kMaxSlots) {
     delete M;
     return fail(AGS_E_ARG, "model: more than 256 contact slots per environment");
@@ -465,43 +479,39 @@ AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters) {
   return L;
 }
 
-Lds make_layout(const ags_model_info& info, int n_levels, int n_anc, int n_body_slot, int team) {
+Lds make_layout(const ags_model_info& info, int n_levels, int n_anc, int team, size_t elem) {
   Lds L{};
   int off = 0;
+  const int ratio = (int)(elem / sizeof(int));  // ints per compute-type word
   auto take = [&](int words) {
     int o = off;
-    off += (words + 1) & ~1;  // keep 8-byte alignment of every array
+    off += (std::max(words, 1) + 1) & ~1;  // keep 8-byte alignment of every array
     return o;
   };
+  auto take_i = [&](int ints) { return take((ints + ratio - 1) / ratio); };
   const int nl = info.n_links, na = info.n_actors, nd = info.n_dof, nv = info.n_v, ns = info.n_slots;
   const int rc = std::max(1, info.max_rows);
-  // model tables, shared by the environments of a workgroup
-  L.t_li = take(nl * LI_COLS); L.t_lev = take(n_levels + 1); L.t_links = take(nl); L.t_child = take(std::max(1, nl));
-  L.t_anc = take(std::max(1, n_anc)); L.t_dof = take(std::max(1, nd)); L.t_si = take(std::max(1, ns) * SI_COLS);
-  L.t_bsb = take(nl + 1); L.t_bs = take(std::max(1, n_body_slot)); L.t_ai = take(na * AI_COLS);
-  L.t_lf = take(nl * LF_COLS); L.t_sf = take(std::max(1, ns) * SF_COLS);
+  // integer model tables, shared by the environments of a workgroup
+  L.t_li = take_i(nl * LI_COLS); L.t_lev = take_i(n_levels + 1); L.t_links = take_i(nl);
+  L.t_child = take_i(nl); L.t_anc = take_i(n_anc); L.t_dof = take_i(nd); L.t_ai = take_i(na * AI_COLS);
   L.team_base = off;
   // per environment, offsets relative to its region
   off = 0;
-  L.o = take(3 * nl); L.ax = take(3 * nl); L.U = take(6 * nl); L.Dinv = take(nl); L.Ubar = take(6 * nl); L.F = take(3 * nl);
-  L.L0 = take(27 * na);
-  L.qj = take(std::max(1, nd)); L.qd = take(nv); L.tau = take(nv); L.arm = take(nv); L.qddf = take(nv); L.vstar = take(nv);
-  L.root = take(13 * na);
-  L.G = take(std::max(1, n_anc));
-  L.phi = take(std::max(1, ns)); L.n = take(3 * ns); L.x = take(3 * ns); L.t1 = take(3 * ns); L.t2 = take(3 * ns);
-  L.slotrow = take(std::max(1, ns)); L.act = take(std::max(1, ns));
-  L.rkind = take(rc); L.rref = take(rc); L.rnorm = take(rc); L.rkey = take(rc); L.rbias = take(rc);
-  L.rinvA = take(rc); L.rlam = take(rc);
-  L.misc = take(8);
-  // dynamics-only arrays and the constraint-phase row chunks are never live together: one region
+  L.qj = take(nd); L.qd = take(nv); L.root = take(13 * na); L.F = take(3 * nl);
+  L.L0 = take(27 * na); L.vs = take(nv);
+  L.o = take(3 * nl); L.ax = take(3 * nl); L.U = take(6 * nl); L.Dinv = take(nl); L.Ubar = take(3 * nl);
+  L.G = take(n_anc);
+  L.phi = take(ns); L.n = take(3 * ns); L.x = take(3 * ns); L.sact = take_i(ns);
+  L.rkr = take_i(rc); L.rbias = take(rc); L.rinvA = take(rc); L.rlam = take(rc);
+  L.misc = take_i(8);
+  // the dynamics arrays (forward sweep to narrow phase) and the row-response chunks are never live together
   const int shared = off;
-  L.R = take(9 * nl); L.v = take(6 * nl); L.c = take(6 * nl); L.IA = take(21 * nl); L.pA = take(6 * nl);
-  L.a = take(6 * nl); L.u = take(nl);
+  L.q = take(4 * nl); L.v = take(6 * nl); L.IA = take(21 * nl); L.pA = take(6 * nl); L.u = take(nl);
+  L.tau = take(nv); L.arm = take(nv);
   const int dyn_end = off;
   off = shared;
   L.wstride = nv | 1;
   L.W = take(team * L.wstride);
-  L.J = take(team * L.wstride);
   off = std::max(off, dyn_end);
   L.team_stride = off;
   L.total = L.team_base + (kTeam / team) * L.team_stride;
@@ -603,7 +613,7 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
         if (!lists[u].empty() && models[u]->info.n_v > 32) all32 = false;
       T.team = all32 ? 32 : 64;
     }
-    T.lds = make_layout(M->info, M->n_levels, M->n_anc, (int)M->body_slot.size(), T.team);
+    T.lds = make_layout(M->info, M->n_levels, M->n_anc, T.team, elem_size);
     // limit margins per joint type
     std::vector<double> lf = M->lf;
     for (int i = 0; i < M->info.n_links; ++i)
@@ -648,6 +658,7 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     D.n_anc = M->n_anc;
     D.r_cap = std::max(1, M->info.max_rows);
     D.n_body_slot = (int)M->body_slot.size();
+    D.jfast = M->max_joint_entries <= kJointEntries;
     D.li = (const int*)(b + offs[0]);
     D.level_begin = (const int*)(b + offs[1]);
     D.level_links = (const int*)(b + offs[2]);

@@ -12,6 +12,7 @@ constexpr int kMaxV = 64;       // generalized velocities per environment (one l
 constexpr int kMaxSlots = 256;
 constexpr float kMinRowMass = 1e-6f;  // rows with J M~^-1 J^T below this are dropped (immovable)
 constexpr int kPhases = 10;           // controls, forward, inward, outward, v*, narrow, rows, responses, PGS, outputs
+constexpr int kJointEntries = 12;     // joint (non-root) entries of a compact Jacobian row
 
 // per-link integer table
 enum { LI_PARENT = 0, LI_JTYPE, LI_COL, LI_DOF, LI_ROOT, LI_CHILD_BEGIN, LI_CHILD_END, LI_ANC_BEGIN, LI_ANC_END,
@@ -30,23 +31,24 @@ enum { J_FREE = 0, J_FIXED = 1, J_REV = 2, J_PRI = 3 };
 
 // LDS layout of one environment's workgroup, offsets in 4-byte words
 struct Lds {
-  // model tables staged from global memory once per launch (ints, then compute-type floats)
-  int t_li, t_lev, t_links, t_child, t_anc, t_dof, t_si, t_bsb, t_bs, t_ai, t_lf, t_sf;
-  int R, o, ax, v, c, IA, pA, U, Dinv, u, a, Ubar, F;  // per link
-  int L0;                                             // per actor: packed Cholesky factor (21) + 1/diag (6)
-  int qj, qd, tau, arm, qddf, vstar;                  // per DOF / column
-  int root;                                           // per actor: 13-float root state
-  int G;                                              // per ancestor pair
-  int phi, n, x, t1, t2, slotrow, act;                // per slot
-  int rkind, rref, rnorm, rkey, rbias, rinvA, rlam;   // per row
-  int W, J, wstride;                                  // TEAM-row chunks of W and J rows
-  int misc;                                           // a few ints
-  int team_base, team_stride;                         // per-environment region: base + team * stride
-  int total;                                          // words for all teams of a workgroup
+  // integer model tables staged once per workgroup (the float tables stay in global memory)
+  int t_li, t_lev, t_links, t_child, t_anc, t_dof, t_ai;
+  // per environment, compute-type word offsets relative to its region; int arrays are packed
+  int qj, qd, root, F;                 // state carried across substeps, summed contact forces
+  int L0, vs;                          // per actor: root Cholesky factor (21) + 1/diag (6); per column: qdd, then v*
+  int o, ax, U, Dinv, Ubar, G;         // per link (Ubar: angular half of U moved to the root), per ancestor pair
+  int phi, n, x, sact;                 // per slot (sact: activity, then first row of the slot or -1)
+  int rkr, rbias, rinvA, rlam;         // per row (rkr: kind << 16 | DOF or slot)
+  int misc;                            // a few ints
+  int q, v, IA, pA, u, tau, arm;       // dynamics region, dead after the narrow phase (pA then holds accelerations) ...
+  int W, wstride;                      // ... shared with TEAM-row chunks of W
+  int team_base, team_stride;          // per-environment region: base + team * stride
+  int total;                           // words for all teams of a workgroup
 };
 
 struct DevModel {
   int n_links, n_actors, n_dof, n_v, n_slots, n_levels, n_anc, r_cap, n_body_slot;
+  int jfast;  // every contact row's Jacobian fits the compact register form (kJointEntries joint entries)
   const int* li;
   const double* lf;
   const int* level_begin;

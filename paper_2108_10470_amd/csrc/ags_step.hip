@@ -327,56 +327,49 @@ __device__ __forceinline__ void tangents(V3<R> n, V3<R>& t1, V3<R>& t2) {
 
 // LDS array of one environment.  The EPW environments of a wavefront are interleaved element by
 // element (element k of team tm sits at base[k * EPW + tm]) so that every array base is the same for
-// the whole wavefront and only the team index varies per lane.  ints occupy compute-type slots.
+// the whole wavefront and only the team index varies per lane.  Int arrays are packed (two per FP64 word).
 extern __shared__ __align__(16) unsigned char g_lds[];
 
-template <typename T, int EPW, int SLOT = 1>
+template <typename T, int EPW>
 struct SP {
   int off;  // element offset of the array base (uniform)
   int tm;   // team of this lane
-  __device__ __forceinline__ T& operator[](int k) const {
-    return reinterpret_cast<T*>(g_lds)[(off + k * EPW + tm) * SLOT];
-  }
+  __device__ __forceinline__ T& operator[](int k) const { return reinterpret_cast<T*>(g_lds)[off + k * EPW + tm]; }
   __device__ __forceinline__ SP operator+(int k) const { return {off + k * EPW, tm}; }
 };
 
 template <typename R, int EPW>
 struct Ctx {
   using F = SP<R, EPW>;
-  using I = SP<int, EPW * (int)(sizeof(R) / sizeof(int)), 1>;
-  F Rm, o, ax, v, c, IA, pA, U, Dinv, u, a, Ubar, F_, L0;
-  F qj, qd, tau, arm, qddf, vstar, root, G;
-  F phi, n, x, t1, t2;
-  I slotrow, act;
-  I rkind, rref, rnorm, rkey;
-  F rbias, rinvA, rlam, W, J;
-  I misc;
+  using I = SP<int, EPW>;
+  F qj, qd, root, F_, L0, vs, o, ax, U, Dinv, Ubar, G, phi, n, x, rbias, rinvA, rlam;
+  F q, v, IA, pA, u, tau, arm, W;
+  I sact, rkr, misc;
   __device__ __forceinline__ void init(int base, const Lds& L, int tm) {
     // base: offset of the per-environment region in units of R
+    constexpr int ratio = (int)(sizeof(R) / sizeof(int));
     auto f = [&](int off) { return F{base + off * EPW, tm}; };
-    auto i = [&](int off) { return I{(base + off * EPW) * (int)(sizeof(R) / sizeof(int)), tm}; };
-    Rm = f(L.R); o = f(L.o); ax = f(L.ax); v = f(L.v); c = f(L.c);
-    IA = f(L.IA); pA = f(L.pA); U = f(L.U); Dinv = f(L.Dinv); u = f(L.u);
-    a = f(L.a); Ubar = f(L.Ubar); F_ = f(L.F); L0 = f(L.L0);
-    qj = f(L.qj); qd = f(L.qd); tau = f(L.tau); arm = f(L.arm); qddf = f(L.qddf);
-    vstar = f(L.vstar); root = f(L.root); G = f(L.G);
-    phi = f(L.phi); n = f(L.n); x = f(L.x); t1 = f(L.t1); t2 = f(L.t2);
-    slotrow = i(L.slotrow); act = i(L.act);
-    rkind = i(L.rkind); rref = i(L.rref); rnorm = i(L.rnorm); rkey = i(L.rkey);
-    rbias = f(L.rbias); rinvA = f(L.rinvA); rlam = f(L.rlam); W = f(L.W); J = f(L.J);
-    misc = i(L.misc);
+    auto i = [&](int off) { return I{(base + off * EPW) * ratio, tm}; };
+    qj = f(L.qj); qd = f(L.qd); root = f(L.root); F_ = f(L.F); L0 = f(L.L0); vs = f(L.vs);
+    o = f(L.o); ax = f(L.ax); U = f(L.U); Dinv = f(L.Dinv); Ubar = f(L.Ubar); G = f(L.G);
+    phi = f(L.phi); n = f(L.n); x = f(L.x); sact = i(L.sact);
+    rkr = i(L.rkr); rbias = f(L.rbias); rinvA = f(L.rinvA); rlam = f(L.rlam); misc = i(L.misc);
+    q = f(L.q); v = f(L.v); IA = f(L.IA); pA = f(L.pA); u = f(L.u); tau = f(L.tau); arm = f(L.arm);
+    W = f(L.W);
   }
 };
 
-// Model tables of one environment template, as seen by the kernel (LDS copies of the global tables)
+// Model tables of one environment template as seen by the kernel: the integer tables of the sweeps
+// are LDS copies; slot tables and the float tables are read from global memory (cached).
 template <typename R>
 struct Tab {
-  int n_links, n_actors, n_dof, n_v, n_slots, n_levels, n_anc, r_cap;
-  const int *li, *level_begin, *level_links, *children, *anc_link, *dof_link, *si, *body_slot_begin, *body_slot, *ai;
-  const R *lf, *sf;
+  int n_links, n_actors, n_dof, n_v, n_slots, n_levels, n_anc, r_cap, jfast;
+  const int *li, *level_begin, *level_links, *children, *anc_link, *dof_link, *ai;
+  const int *si, *body_slot_begin, *body_slot;
+  const double *lf, *sf;
 };
 
-// Copies the model tables into this workgroup's LDS (all lanes cooperate) and returns the view.
+// Copies the integer model tables into this workgroup's LDS (all lanes cooperate) and returns the view.
 template <typename R>
 __device__ __forceinline__ Tab<R> stage_tables(const DevModel& G, R* smem, const Lds& L, int t, int nthreads,
                                               bool copy) {
@@ -387,27 +380,21 @@ __device__ __forceinline__ Tab<R> stage_tables(const DevModel& G, R* smem, const
       for (int k = t; k < n; k += nthreads) dst[k] = src[k];
     return (const int*)dst;
   };
-  auto copy_r = [&](int off, const double* src, int n) {
-    R* dst = smem + off;
-    if (copy)
-      for (int k = t; k < n; k += nthreads) dst[k] = R(src[k]);
-    return (const R*)dst;
-  };
   Tab<R> T;
   T.n_links = G.n_links; T.n_actors = G.n_actors; T.n_dof = G.n_dof; T.n_v = G.n_v; T.n_slots = G.n_slots;
-  T.n_levels = G.n_levels; T.n_anc = G.n_anc; T.r_cap = G.r_cap;
+  T.n_levels = G.n_levels; T.n_anc = G.n_anc; T.r_cap = G.r_cap; T.jfast = G.jfast;
   T.li = copy_i(L.t_li, G.li, G.n_links * LI_COLS);
   T.level_begin = copy_i(L.t_lev, G.level_begin, G.n_levels + 1);
   T.level_links = copy_i(L.t_links, G.level_links, G.n_links);
   T.children = copy_i(L.t_child, G.children, G.n_links - G.n_actors);
   T.anc_link = copy_i(L.t_anc, G.anc_link, G.n_anc);
   T.dof_link = copy_i(L.t_dof, G.dof_link, G.n_dof);
-  T.si = copy_i(L.t_si, G.si, G.n_slots * SI_COLS);
-  T.body_slot_begin = copy_i(L.t_bsb, G.body_slot_begin, G.n_links + 1);
-  T.body_slot = copy_i(L.t_bs, G.body_slot, G.n_body_slot);
   T.ai = copy_i(L.t_ai, G.ai, G.n_actors * AI_COLS);
-  T.lf = copy_r(L.t_lf, G.lf, G.n_links * LF_COLS);
-  T.sf = copy_r(L.t_sf, G.sf, G.n_slots * SF_COLS);
+  T.si = G.si;
+  T.body_slot_begin = G.body_slot_begin;
+  T.body_slot = G.body_slot;
+  T.lf = G.lf;
+  T.sf = G.sf;
   return T;
 }
 
@@ -417,6 +404,33 @@ __device__ __forceinline__ int actor_of_root(const Tab<R>& M, int link) {
   for (int k = 0; k < M.n_actors; ++k)
     if (M.ai[k * AI_COLS + AI_ROOT] == link) a = k;
   return a;
+}
+
+// rotation matrix (row-major) of a unit quaternion xyzw
+template <typename R>
+__device__ __forceinline__ void quat_R(R qx, R qy, R qz, R qw, R* M) {
+  const R one = R(1), two = R(2);
+  M[0] = one - two * (qy * qy + qz * qz); M[1] = two * (qx * qy - qz * qw); M[2] = two * (qx * qz + qy * qw);
+  M[3] = two * (qx * qy + qz * qw); M[4] = one - two * (qx * qx + qz * qz); M[5] = two * (qy * qz - qx * qw);
+  M[6] = two * (qx * qz - qy * qw); M[7] = two * (qy * qz + qx * qw); M[8] = one - two * (qx * qx + qy * qy);
+}
+template <typename R, typename P>
+__device__ __forceinline__ void quat_R(const P& q, R* M) {
+  quat_R(R(q[0]), R(q[1]), R(q[2]), R(q[3]), M);
+}
+
+// velocity-product acceleration of a joint (world axes about the joint origin), from the link's velocity
+// (w, v at o) after the joint's own motion: revolute ((w x s) qd, (v x s) qd), prismatic (0, (w x s) qd)
+template <typename R, int EPW>
+__device__ __forceinline__ void vel_product(const Ctx<R, EPW>& s, int i, int jt, V3<R> ax, R qd, V3<R>& ca, V3<R>& cl) {
+  const V3<R> w = ld3<R>(s.v + 6 * i), vl = ld3<R>(s.v + 6 * i + 3);
+  if (jt == J_REV) {
+    ca = mul(cross(w, ax), qd);
+    cl = mul(cross(vl, ax), qd);
+  } else {
+    ca = mk(R(0), R(0), R(0));
+    cl = mul(cross(w, ax), qd);
+  }
 }
 
 // Adds the joint loads of one unit test load to Wrow (u_k at each joint column on the path of link k)
@@ -478,6 +492,100 @@ __device__ __forceinline__ R point_row(const Tab<R>& M, const Ctx<R, EPW>& s, in
     k = li[LI_PARENT];
   }
   return acc;
+}
+
+
+// Compact Jacobian row of a constraint: its entries on the free-root columns of the two bodies' articulations
+// (6 each, about the root's point) and on up to kJointEntries joint columns; unused entries are zero.
+template <typename R>
+struct JRow {
+  int ra, rb;  // first root column of body a / body b, -1 if none
+  R ja[6], jb[6];
+  int c[kJointEntries];
+  R val[kJointEntries];
+};
+
+template <typename R>
+__device__ __forceinline__ void jrow_clear(JRow<R>& J) {
+  J.ra = -1;
+  J.rb = -1;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    J.ja[q] = R(0);
+    J.jb[q] = R(0);
+  }
+#pragma unroll
+  for (int e = 0; e < kJointEntries; ++e) {
+    J.c[e] = 0;
+    J.val[e] = R(0);
+  }
+}
+
+// sum_j J_j w_j
+template <typename R, typename WP>
+__device__ __forceinline__ R jrow_dot(const JRow<R>& J, const WP& w) {
+  R acc = R(0);
+#pragma unroll
+  for (int e = 0; e < kJointEntries; ++e) acc += J.val[e] * w[J.c[e]];
+  if (J.ra >= 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc += J.ja[q] * w[J.ra + q];
+  }
+  if (J.rb >= 0) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc += J.jb[q] * w[J.rb + q];
+  }
+  return acc;
+}
+
+// root part of a point load along d at x on the articulation of link k: sign (d, (x - o_root) x d)
+template <typename R, int EPW>
+__device__ __forceinline__ int jrow_root(const Tab<R>& M, const Ctx<R, EPW>& s, int k, V3<R> x, V3<R> d, R sign, R* j6) {
+  const int* li = M.li + k * LI_COLS;
+  const int rc = li[LI_ROOTCOL];
+  const V3<R> mo = cross(sub(x, ld3<R>(s.o + 3 * li[LI_ROOT])), d);
+  const bool on = rc >= 0;
+  j6[0] = on ? sign * d.x : R(0); j6[1] = on ? sign * d.y : R(0); j6[2] = on ? sign * d.z : R(0);
+  j6[3] = on ? sign * mo.x : R(0); j6[4] = on ? sign * mo.y : R(0); j6[5] = on ? sign * mo.z : R(0);
+  return rc;
+}
+
+// Row of a point load along d at x between link ka (+) and link kb (-, or none when kb < 0).  The joint
+// entries of ka's path to its root come first, then kb's; the walk is unrolled so the row stays in registers.
+template <typename R, int EPW>
+__device__ __forceinline__ void jrow_point(const Tab<R>& M, const Ctx<R, EPW>& s, int ka, int kb, V3<R> x, V3<R> d,
+                                           JRow<R>& J) {
+  J.ra = jrow_root(M, s, ka, x, d, R(1), J.ja);
+  if (kb >= 0) {
+    J.rb = jrow_root(M, s, kb, x, d, R(-1), J.jb);
+  } else {
+    J.rb = -1;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) J.jb[q] = R(0);
+  }
+  int k = ka;
+  R sg = R(1);
+  bool onb = false;
+#pragma unroll
+  for (int e = 0; e < kJointEntries; ++e) {
+    int jt = k >= 0 ? M.li[k * LI_COLS + LI_JTYPE] : J_FIXED;
+    if (jt != J_REV && jt != J_PRI && !onb) {  // body a's path ended: continue on body b's
+      onb = true;
+      k = kb;
+      sg = R(-1);
+      jt = k >= 0 ? M.li[k * LI_COLS + LI_JTYPE] : J_FIXED;
+    }
+    J.c[e] = 0;
+    J.val[e] = R(0);
+    if (jt == J_REV || jt == J_PRI) {
+      const int* li = M.li + k * LI_COLS;
+      const V3<R> ax = ld3<R>(s.ax + 3 * k);
+      const R jv = jt == J_REV ? dot(ax, cross(sub(x, ld3<R>(s.o + 3 * k)), d)) : dot(ax, d);
+      J.c[e] = li[LI_COL];
+      J.val[e] = sg * jv;
+      k = li[LI_PARENT];
+    }
+  }
 }
 
 }  // namespace
@@ -544,7 +652,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     // and the armature h kd + h^2 kp added to the joint's diagonal of M~
     for (int j = tt; j < nd; j += TEAM) {
       const int lk = M.dof_link[j];
-      const R* lf = M.lf + lk * LF_COLS;
+      const double* lf = M.lf + lk * LF_COLS;
       const int c = M.li[lk * LI_COLS + LI_COL];
       const R pt = P.pos_tgt ? R(P.pos_tgt[dbase + j]) : R(0);
       const R vt = P.vel_tgt ? R(P.vel_tgt[dbase + j]) : R(0);
@@ -560,20 +668,17 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
         const int* li = M.li + i * LI_COLS;
-        const R* lf = M.lf + i * LF_COLS;
+        const double* lf = M.lf + i * LF_COLS;
         const int jt = li[LI_JTYPE];
-        R Rw[9];
-        V3<R> o, w, vl, ca = mk(R(0), R(0), R(0)), cl = mk(R(0), R(0), R(0)), ax = mk(R(0), R(0), R(0));
+        R Rw[9], qq[4];
+        V3<R> o, w, vl, ax = mk(R(0), R(0), R(0));
         if (jt == J_FREE || jt == J_FIXED) {
           // root pose from the root state (quaternion xyzw, normalised on read)
           const auto rs = s.root + 13 * actor_of_root(M, i);
           R qx = rs[3], qy = rs[4], qz = rs[5], qw = rs[6];
           const R inv = rsqrt_(qx * qx + qy * qy + qz * qz + qw * qw);
-          qx *= inv; qy *= inv; qz *= inv; qw *= inv;
-          const R one = R(1), two = R(2);
-          Rw[0] = one - two * (qy * qy + qz * qz); Rw[1] = two * (qx * qy - qz * qw); Rw[2] = two * (qx * qz + qy * qw);
-          Rw[3] = two * (qx * qy + qz * qw); Rw[4] = one - two * (qx * qx + qz * qz); Rw[5] = two * (qy * qz - qx * qw);
-          Rw[6] = two * (qx * qz - qy * qw); Rw[7] = two * (qy * qz + qx * qw); Rw[8] = one - two * (qx * qx + qy * qy);
+          qq[0] = qx * inv; qq[1] = qy * inv; qq[2] = qz * inv; qq[3] = qw * inv;
+          quat_R(qq[0], qq[1], qq[2], qq[3], Rw);
           o = sub(ld3<R>(rs), origin);
           if (jt == J_FREE) {
             const int c = li[LI_ROOTCOL];
@@ -585,15 +690,25 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           }
         } else {
           const int p = li[LI_PARENT];
-          const auto Rp = s.Rm + 9 * p;
+          const auto qp = s.q + 4 * p;
+          const R px = qp[0], py = qp[1], pz = qp[2], pw = qp[3];
+          R Rp[9];
+          quat_R(px, py, pz, pw, Rp);
           const V3<R> axl = ld3<R>(lf + LF_AXIS);
           V3<R> tl = ld3<R>(lf + LF_ANCHOR);
           const R q = s.qj[li[LI_DOF]], qd = s.qd[li[LI_COL]];
           if (jt == J_REV) {
-            R Rr[9];
-            axis_angle(axl, q, Rr);
-            mm3(Rp, Rr, Rw);
+            // parent orientation composed with the joint rotation (angle q about the local axis)
+            R sh, ch;
+            sincos_(R(0.5) * q, &sh, &ch);
+            const R rx = axl.x * sh, ry = axl.y * sh, rz = axl.z * sh;
+            qq[0] = pw * rx + ch * px + (py * rz - pz * ry);
+            qq[1] = pw * ry + ch * py + (pz * rx - px * rz);
+            qq[2] = pw * rz + ch * pz + (px * ry - py * rx);
+            qq[3] = pw * ch - (px * rx + py * ry + pz * rz);
+            quat_R(qq[0], qq[1], qq[2], qq[3], Rw);
           } else {
+            qq[0] = px; qq[1] = py; qq[2] = pz; qq[3] = pw;
 #pragma unroll
             for (int k = 0; k < 9; ++k) Rw[k] = Rp[k];
             tl = add(tl, mul(axl, q));
@@ -603,27 +718,21 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           o = add(op, mv(Rp, tl));
           w = ld3<R>(s.v + 6 * p);
           vl = add(ld3<R>(s.v + 6 * p + 3), cross(w, sub(o, op)));
-          if (jt == J_REV) {
-            w = add(w, mul(ax, qd));
-            ca = mul(cross(w, ax), qd);
-            cl = mul(cross(vl, ax), qd);
-          } else {
-            vl = add(vl, mul(ax, qd));
-            cl = mul(cross(w, ax), qd);
-          }
+          if (jt == J_REV) w = add(w, mul(ax, qd));
+          else vl = add(vl, mul(ax, qd));
         }
         // spatial inertia about o (world axes): A = Ic_w + m (|d|^2 1 - d d^T), B = m d^, M = m 1
         const R m = R(lf[LF_MASS]);
         const V3<R> d = mv(Rw, ld3<R>(lf + LF_COM));
-        const R* Icl = lf + LF_IC;
-        const R Ic[9] = {Icl[0], Icl[3], Icl[4], Icl[3], Icl[1], Icl[5], Icl[4], Icl[5], Icl[2]};
-        R T[9], Iw[9];
-        mm3(Rw, Ic, T);
+        const double* Icl = lf + LF_IC;
+        const R Ic[9] = {R(Icl[0]), R(Icl[3]), R(Icl[4]), R(Icl[3]), R(Icl[1]), R(Icl[5]), R(Icl[4]), R(Icl[5]), R(Icl[2])};
+        R Tm[9], Iw[9];
+        mm3(Rw, Ic, Tm);
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int b = 0; b < 3; ++b)
-            Iw[3 * a + b] = T[3 * a] * Rw[3 * b] + T[3 * a + 1] * Rw[3 * b + 1] + T[3 * a + 2] * Rw[3 * b + 2];
+            Iw[3 * a + b] = Tm[3 * a] * Rw[3 * b] + Tm[3 * a + 1] * Rw[3 * b + 1] + Tm[3 * a + 2] * Rw[3 * b + 2];
         SI<R> I;
         const R dd = dot(d, d), half = R(0.5);
         I.A[0] = Iw[0] + m * (dd - d.x * d.x);
@@ -643,13 +752,11 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         const V3<R> pn = sub(add(cross(w, ha), cross(vl, hl)), cross(d, fg));
         const V3<R> pf = sub(cross(w, hl), fg);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) s.Rm[9 * i + k] = Rw[k];
+        for (int k = 0; k < 4; ++k) s.q[4 * i + k] = qq[k];
         st3(s.o + 3 * i, o);
         st3(s.ax + 3 * i, ax);
         st3(s.v + 6 * i, w);
         st3(s.v + 6 * i + 3, vl);
-        st3(s.c + 6 * i, ca);
-        st3(s.c + 6 * i + 3, cl);
         si_store(I, s.IA + 21 * i);
         st3(s.pA + 6 * i, pn);
         st3(s.pA + 6 * i + 3, pf);
@@ -709,8 +816,9 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 #pragma unroll
           for (int b = 0; b < 3; ++b) I.B[3 * a + b] -= ua[a] * ul[b] * Dinv;
         // p^a = p^A + I^a c + U u / D
-        V3<R> ia, il;
-        si_mul(I, ld3<R>(s.c + 6 * i), ld3<R>(s.c + 6 * i + 3), ia, il);
+        V3<R> ca, cl, ia, il;
+        vel_product(s, i, jt, ax, s.qd[c], ca, cl);
+        si_mul(I, ca, cl, ia, il);
         const R ud = u * Dinv;
         pn = add(add(pn, ia), mul(Ua, ud));
         pf = add(add(pf, il), mul(Ul, ud));
@@ -731,6 +839,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 
     PHASE_MARK(3);
     // ---------------------------------------------------- root solve and ABA outward sweep
+    // link accelerations overwrite the (consumed) bias forces: a_i lives in pA_i
     for (int d = 0; d < M.n_levels; ++d) {
       for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
@@ -750,30 +859,35 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           al = mk(x[3], x[4], x[5]);
           // classical acceleration of the centre of mass: a_lin + w x v_com
           const int c = li[LI_ROOTCOL];
-          st3(s.qddf + c, add(al, cross(ld3<R>(s.qd + c + 3), ld3<R>(s.qd + c))));
-          st3(s.qddf + c + 3, aa);
+          st3(s.vs + c, add(al, cross(ld3<R>(s.qd + c + 3), ld3<R>(s.qd + c))));
+          st3(s.vs + c + 3, aa);
         } else {
           const int p = li[LI_PARENT];
+          const int c = li[LI_COL];
           const V3<R> r = sub(ld3<R>(s.o + 3 * i), ld3<R>(s.o + 3 * p));
-          aa = ld3<R>(s.a + 6 * p);
-          al = add(ld3<R>(s.a + 6 * p + 3), cross(aa, r));
-          aa = add(aa, ld3<R>(s.c + 6 * i));
-          al = add(al, ld3<R>(s.c + 6 * i + 3));
-          const R qdd = (s.u[i] - dot(ld3<R>(s.U + 6 * i), aa) - dot(ld3<R>(s.U + 6 * i + 3), al)) * s.Dinv[i];
           const V3<R> ax = ld3<R>(s.ax + 3 * i);
+          V3<R> ca, cl;
+          vel_product(s, i, jt, ax, s.qd[c], ca, cl);
+          aa = ld3<R>(s.pA + 6 * p);
+          al = add(ld3<R>(s.pA + 6 * p + 3), cross(aa, r));
+          aa = add(aa, ca);
+          al = add(al, cl);
+          const R qdd = (s.u[i] - dot(ld3<R>(s.U + 6 * i), aa) - dot(ld3<R>(s.U + 6 * i + 3), al)) * s.Dinv[i];
           if (jt == J_REV) aa = add(aa, mul(ax, qdd));
           else al = add(al, mul(ax, qdd));
-          s.qddf[li[LI_COL]] = qdd;
+          s.vs[c] = qdd;
         }
-        st3(s.a + 6 * i, aa);
-        st3(s.a + 6 * i + 3, al);
+        st3(s.pA + 6 * i, aa);
+        st3(s.pA + 6 * i + 3, al);
       }
       __syncthreads();
     }
-    for (int c = tt; c < nv; c += TEAM) s.vstar[c] = s.qd[c] + h * s.qddf[c];
-    if (P.dbg_qdd && valid)
-      for (int c = tt; c < nv; c += TEAM)
-        P.dbg_qdd[(long long)env * P.dbg_qdd_stride + sub_i * P.dbg_qdd_sub + c] = float(s.qddf[c]);
+    // free accelerations (debug) and v* = qd + h qdd_free, in place
+    for (int c = tt; c < nv; c += TEAM) {
+      const R qdd = s.vs[c];
+      if (P.dbg_qdd && valid) P.dbg_qdd[(long long)env * P.dbg_qdd_stride + sub_i * P.dbg_qdd_sub + c] = float(qdd);
+      s.vs[c] = s.qd[c] + h * qdd;
+    }
     __syncthreads();
 
     PHASE_MARK(4);
@@ -789,21 +903,21 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           vl = w;
         } else if (jt == J_FREE) {
           const int c = li[LI_ROOTCOL];
-          vl = ld3<R>(s.vstar + c);
-          w = ld3<R>(s.vstar + c + 3);
+          vl = ld3<R>(s.vs + c);
+          w = ld3<R>(s.vs + c + 3);
         } else {
           const int p = li[LI_PARENT];
           const V3<R> oi = ld3<R>(s.o + 3 * i);
           w = ld3<R>(s.v + 6 * p);
           vl = add(ld3<R>(s.v + 6 * p + 3), cross(w, sub(oi, ld3<R>(s.o + 3 * p))));
           const V3<R> ax = ld3<R>(s.ax + 3 * i);
-          const R qd = s.vstar[li[LI_COL]];
+          const R qd = s.vs[li[LI_COL]];
           if (jt == J_REV) w = add(w, mul(ax, qd));
           else vl = add(vl, mul(ax, qd));
-          // U moved to the root point, and G_ik = U_i . (s_k moved to o_i) for every ancestor joint k
+          // U moved to the root point (its linear half is unchanged), and G_ik = U_i . (s_k moved to o_i)
+          // for every ancestor joint k
           const V3<R> Ua = ld3<R>(s.U + 6 * i), Ul = ld3<R>(s.U + 6 * i + 3);
-          st3(s.Ubar + 6 * i, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * li[LI_ROOT])), Ul)));
-          st3(s.Ubar + 6 * i + 3, Ul);
+          st3(s.Ubar + 3 * i, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * li[LI_ROOT])), Ul)));
           for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q) {
             const int k = M.anc_link[q];
             const V3<R> ak = ld3<R>(s.ax + 3 * k);
@@ -823,10 +937,12 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       const int sl = sb + tt;
       if (sl < ns) {
         const int* si = M.si + sl * SI_COLS;
-        const R* sf = M.sf + sl * SF_COLS;
+        const double* sf = M.sf + sl * SF_COLS;
         const int ka = si[SI_LINK_A], kb = si[SI_LINK_B];
         const R rad = R(sf[SF_R]);
-        const V3<R> xc = add(ld3<R>(s.o + 3 * ka), mv(s.Rm + 9 * ka, ld3<R>(sf + SF_P)));
+        R Ra[9];
+        quat_R(s.q + 4 * ka, Ra);
+        const V3<R> xc = add(ld3<R>(s.o + 3 * ka), mv(Ra, ld3<R>(sf + SF_P)));
         R phi;
         V3<R> nrm, x;
         if (si[SI_TYPE] == SLOT_SPHERE_PLANE) {
@@ -839,7 +955,8 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           x = xc;
         } else {
           // sphere against box: closest point, or the face of least penetration when inside
-          const auto Rb = s.Rm + 9 * kb;
+          R Rb[9];
+          quat_R(s.q + 4 * kb, Rb);
           const V3<R> cb = add(ld3<R>(s.o + 3 * kb), mv(Rb, ld3<R>(sf + SF_BOXC)));
           const V3<R> hb = ld3<R>(sf + SF_HALF);
           const V3<R> xl = mtv(Rb, sub(xc, cb));
@@ -868,20 +985,18 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         V3<R> ua = add(ld3<R>(s.v + 6 * ka + 3), cross(ld3<R>(s.v + 6 * ka), sub(x, ld3<R>(s.o + 3 * ka))));
         if (kb >= 0) ua = sub(ua, add(ld3<R>(s.v + 6 * kb + 3), cross(ld3<R>(s.v + 6 * kb), sub(x, ld3<R>(s.o + 3 * kb)))));
         const R vn = dot(nrm, ua);
-        V3<R> t1, t2;
-        tangents(nrm, t1, t2);
         s.phi[sl] = phi;
         st3(s.n + 3 * sl, nrm);
         st3(s.x + 3 * sl, x);
-        st3(s.t1 + 3 * sl, t1);
-        st3(s.t2 + 3 * sl, t2);
-        s.act[sl] = (phi + h * min_(R(0), vn)) < R(P.mc);
+        s.sact[sl] = (phi + h * min_(R(0), vn)) < R(P.mc);
       }
     }
     __syncthreads();
 
     PHASE_MARK(6);
     // ---------------------------------------------------- constraint rows: limits (by DOF), then contacts
+    // row descriptor: kind << 16 | DOF (kinds 1, 2: lower, upper limit) or slot (3, 4, 5: normal, t1, t2);
+    // the normal row of friction row r is r - (kind - 3)
     {
       int running = 0;
       for (int jb = 0; jb < nd; jb += TEAM) {
@@ -890,8 +1005,8 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         R glo = R(0), ghi = R(0);
         if (j < nd) {
           const int lk = M.dof_link[j];
-          const R* lf = M.lf + lk * LF_COLS;
-          const R vs = s.vstar[M.li[lk * LI_COLS + LI_COL]];
+          const double* lf = M.lf + lk * LF_COLS;
+          const R vs = s.vs[M.li[lk * LI_COLS + LI_COL]];
           const R ml = R(lf[LF_ML]), q = s.qj[j];
           if (isfinite(lf[LF_LO])) {
             glo = q - R(lf[LF_LO]);
@@ -905,30 +1020,26 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         const unsigned long long mlo = team_ballot<TEAM>(tm, alo), mhi = team_ballot<TEAM>(tm, ahi);
         const int base = running + __popcll(mlo & lanes_below(tt)) + __popcll(mhi & lanes_below(tt));
         if (alo) {
-          s.rkind[base] = 1; s.rref[base] = j; s.rnorm[base] = -1; s.rkey[base] = (1 << 24) | (j << 8);
+          s.rkr[base] = (1 << 16) | j;
           s.rbias[base] = glo >= R(0) ? glo / h : R(P.beta) * glo / h;
         }
         if (ahi) {
           const int r = base + alo;
-          s.rkind[r] = 2; s.rref[r] = j; s.rnorm[r] = -1; s.rkey[r] = (2 << 24) | (j << 8);
+          s.rkr[r] = (2 << 16) | j;
           s.rbias[r] = ghi >= R(0) ? ghi / h : R(P.beta) * ghi / h;
         }
         running += __popcll(mlo) + __popcll(mhi);
       }
       for (int sb = 0; sb < ns; sb += TEAM) {
         const int sl = sb + tt;
-        const int a = sl < ns ? s.act[sl] : 0;
+        const int a = sl < ns ? s.sact[sl] : 0;
         const unsigned long long m = team_ballot<TEAM>(tm, a);
         const int base = running + 3 * __popcll(m & lanes_below(tt));
-        if (sl < ns) s.slotrow[sl] = a ? base : -1;
+        if (sl < ns) s.sact[sl] = a ? base : -1;  // from here on: the slot's first row
         if (a) {
-          const int key = M.si[sl * SI_COLS + SI_KEY];
           const R phi = s.phi[sl];
           for (int k = 0; k < 3; ++k) {
-            s.rkind[base + k] = 3 + k;
-            s.rref[base + k] = sl;
-            s.rnorm[base + k] = base;
-            s.rkey[base + k] = ((3 + k) << 24) | key;
+            s.rkr[base + k] = ((3 + k) << 16) | sl;
             s.rbias[base + k] = k == 0 ? (phi >= R(0) ? phi / h : R(P.beta) * phi / h) : R(0);
           }
         }
@@ -941,42 +1052,55 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 
     PHASE_MARK(7);
     // ---------------------------------------------------- row Jacobians and responses W_r = M~^-1 J_r^T
-    // Up to 64 rows (one per lane) keep J and W in LDS and are solved in registers below; more rows go
-    // through global scratch.
-    const bool fast = Rn <= TEAM;
+    // Up to TEAM rows (one per lane) keep their Jacobian in registers (compact form) and W in LDS and are
+    // solved in registers below; more rows (or rows too long for the compact form) go through global scratch.
+    const bool fast = Rn <= TEAM && M.jfast;
     if (!fast)
       for (int k = tt; k < Rn * nv; k += TEAM) Jg[k] = R(0);
+    JRow<R> jr;  // fast path: this lane's row
+    jrow_clear(jr);
     __syncthreads();
     for (int rb = 0; rb < Rn; rb += TEAM) {
       const int r = rb + tt;
       const auto Wrow = s.W + tt * L.wstride;
-      const auto JrowL = s.J + tt * L.wstride;
       R* const JrowG = Jg + (long long)r * nv;
       for (int c = 0; c < nv; ++c) Wrow[c] = R(0);
-      if (fast)
-        for (int c = 0; c < nv; ++c) JrowL[c] = R(0);
       if (r < Rn) {
-        const int kind = s.rkind[r];
+        const int kr = s.rkr[r];
+        const int kind = kr >> 16, ref = kr & 0xffff;
+        int lk = 0, ka = 0, kb = -1;
+        R sg = R(0);
+        V3<R> dd = mk(R(0), R(0), R(0)), x = dd;
         if (kind <= 2) {
-          const int lk = M.dof_link[s.rref[r]];
-          const R sg = kind == 1 ? R(1) : R(-1);
-          if (fast) JrowL[M.li[lk * LI_COLS + LI_COL]] = sg;
-          else JrowG[M.li[lk * LI_COLS + LI_COL]] = sg;
+          lk = M.dof_link[ref];
+          sg = kind == 1 ? R(1) : R(-1);
+          const int col = M.li[lk * LI_COLS + LI_COL];
+          if (fast) {
+            jr.c[0] = col;
+            jr.val[0] = sg;
+          } else {
+            JrowG[col] = sg;
+          }
           unit_load_inward(M, s, lk, mk(R(0), R(0), R(0)), mk(R(0), R(0), R(0)), sg, Wrow);
         } else {
-          const int sl = s.rref[r];
-          auto dp = s.n;
-          dp.off = kind == 3 ? s.n.off : (kind == 4 ? s.t1.off : s.t2.off);
-          const V3<R> dd = ld3<R>(dp + 3 * sl), x = ld3<R>(s.x + 3 * sl);
-          const int ka = M.si[sl * SI_COLS + SI_LINK_A], kb = M.si[sl * SI_COLS + SI_LINK_B];
-          if (fast) point_row(M, s, ka, x, dd, R(1), JrowL, Wrow, true, false);
-          else point_row(M, s, ka, x, dd, R(1), JrowG, Wrow, true, false);
-          unit_load_inward(M, s, ka, mul(cross(sub(x, ld3<R>(s.o + 3 * ka)), dd), R(-1)), mul(dd, R(-1)), R(0), Wrow);
-          if (kb >= 0) {
-            if (fast) point_row(M, s, kb, x, dd, R(-1), JrowL, Wrow, true, false);
-            else point_row(M, s, kb, x, dd, R(-1), JrowG, Wrow, true, false);
-            unit_load_inward(M, s, kb, cross(sub(x, ld3<R>(s.o + 3 * kb)), dd), dd, R(0), Wrow);
+          const V3<R> nrm = ld3<R>(s.n + 3 * ref);
+          dd = nrm;
+          if (kind != 3) {
+            V3<R> t1, t2;
+            tangents(nrm, t1, t2);
+            dd = kind == 4 ? t1 : t2;
           }
+          x = ld3<R>(s.x + 3 * ref);
+          ka = M.si[ref * SI_COLS + SI_LINK_A];
+          kb = M.si[ref * SI_COLS + SI_LINK_B];
+          if (fast) {
+            jrow_point(M, s, ka, kb, x, dd, jr);
+          } else {
+            point_row(M, s, ka, x, dd, R(1), JrowG, Wrow, true, false);
+            if (kb >= 0) point_row(M, s, kb, x, dd, R(-1), JrowG, Wrow, true, false);
+          }
+          unit_load_inward(M, s, ka, mul(cross(sub(x, ld3<R>(s.o + 3 * ka)), dd), R(-1)), mul(dd, R(-1)), R(0), Wrow);
+          if (kb >= 0) unit_load_inward(M, s, kb, cross(sub(x, ld3<R>(s.o + 3 * kb)), dd), dd, R(0), Wrow);
         }
         // roots: a = -(I^A_root)^-1 (accumulated bias force); generalized root columns are (v_com, w)
         for (int k = 0; k < na; ++k) {
@@ -998,9 +1122,10 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           R acc = R(0);
           const int rc = li[LI_ROOTCOL];
           if (rc >= 0) {
-            const auto ub = s.Ubar + 6 * i;
-            acc = ub[0] * Wrow[rc + 3] + ub[1] * Wrow[rc + 4] + ub[2] * Wrow[rc + 5] + ub[3] * Wrow[rc + 0] +
-                  ub[4] * Wrow[rc + 1] + ub[5] * Wrow[rc + 2];
+            const auto ub = s.Ubar + 3 * i;
+            const auto ul = s.U + 6 * i + 3;
+            acc = ub[0] * Wrow[rc + 3] + ub[1] * Wrow[rc + 4] + ub[2] * Wrow[rc + 5] + ul[0] * Wrow[rc + 0] +
+                  ul[1] * Wrow[rc + 1] + ul[2] * Wrow[rc + 2];
           }
           for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q)
             acc += s.G[q] * Wrow[M.li[M.anc_link[q] * LI_COLS + LI_COL]];
@@ -1009,15 +1134,11 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         }
         // A_rr = J_r W_r
         R A;
-        if (kind <= 2) {
-          const int lk = M.dof_link[s.rref[r]];
-          A = (kind == 1 ? R(1) : R(-1)) * Wrow[M.li[lk * LI_COLS + LI_COL]];
+        if (fast) {
+          A = jrow_dot(jr, Wrow);
+        } else if (kind <= 2) {
+          A = sg * Wrow[M.li[lk * LI_COLS + LI_COL]];
         } else {
-          const int sl = s.rref[r];
-          auto dp = s.n;
-          dp.off = kind == 3 ? s.n.off : (kind == 4 ? s.t1.off : s.t2.off);
-          const V3<R> dd = ld3<R>(dp + 3 * sl), x = ld3<R>(s.x + 3 * sl);
-          const int ka = M.si[sl * SI_COLS + SI_LINK_A], kb = M.si[sl * SI_COLS + SI_LINK_B];
           A = point_row(M, s, ka, x, dd, R(1), Wrow, Wrow, false, true);
           if (kb >= 0) A += point_row(M, s, kb, x, dd, R(-1), Wrow, Wrow, false, true);
         }
@@ -1032,8 +1153,10 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         __syncthreads();
       }
     }
-    for (int r = tt; r < Rn; r += TEAM)  // friction rows of a dropped normal row are dropped too
-      if (s.rkind[r] >= 4 && s.rinvA[s.rnorm[r]] == R(0)) s.rinvA[r] = R(0);
+    for (int r = tt; r < Rn; r += TEAM) {  // friction rows of a dropped normal row are dropped too
+      const int kind = s.rkr[r] >> 16;
+      if (kind >= 4 && s.rinvA[r - (kind - 3)] == R(0)) s.rinvA[r] = R(0);
+    }
     __syncthreads();
 
     PHASE_MARK(8);
@@ -1042,28 +1165,16 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     R vj;
     if (fast) {
       // Delassus form, one row per lane: lane k holds y_k = J_k v and column k of A = J M~^-1 J^T
-      // (Acol[r] = J_r W_k), so a row update is a few broadcasts, a clamp and one FMA per lane.
+      // (Acol[r] = J_k W_r, A being symmetric), so a row update is a few broadcasts, a clamp and one FMA per lane.
       R Acol[TEAM];
-      const auto Wk = s.W + tt * L.wstride;
 #pragma unroll
-      for (int r = 0; r < TEAM; ++r) {
-        R acc = R(0);
-        if (r < Rn) {
-          const auto Jr = s.J + r * L.wstride;
-          for (int c = 0; c < nv; ++c) acc += Jr[c] * Wk[c];
-        }
-        Acol[r] = acc;
-      }
-      R y = R(0);
-      {
-        const auto Jk = s.J + tt * L.wstride;
-        for (int c = 0; c < nv; ++c) y += Jk[c] * s.vstar[c];
-      }
+      for (int r = 0; r < TEAM; ++r) Acol[r] = r < Rn ? jrow_dot(jr, s.W + r * L.wstride) : R(0);
+      R y = jrow_dot(jr, s.vs);
       const bool own = tt < Rn;
       const R bias = own ? s.rbias[tt] : R(0);
       const R ia = own ? s.rinvA[tt] : R(0);
-      const int kindv = own ? s.rkind[tt] : 0;
-      const int nrmv = own ? s.rnorm[tt] : 0;
+      const int kindv = own ? (s.rkr[tt] >> 16) : 0;
+      const int nrmv = kindv >= 4 ? tt - (kindv - 3) : tt;
       R lam = R(0);
       for (int it = 0; it < P.iters; ++it) {
 #pragma unroll
@@ -1086,12 +1197,12 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       if (own) s.rlam[tt] = lam;
       __syncthreads();
       // v+ = v* + sum_r W_r lambda_r, lanes over velocity columns
-      vj = tt < nv ? s.vstar[tt] : R(0);
+      vj = tt < nv ? s.vs[tt] : R(0);
       if (tt < nv)
         for (int r = 0; r < Rn; ++r) vj += s.rlam[r] * s.W[r * L.wstride + tt];
     } else {
       // lanes over velocity columns, rows streamed from global scratch
-      vj = tt < nv ? s.vstar[tt] : R(0);
+      vj = tt < nv ? s.vs[tt] : R(0);
       for (int it = 0; it < P.iters; ++it) {
         for (int r = 0; r < Rn; ++r) {
           const R invA = s.rinvA[r];
@@ -1101,8 +1212,9 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           const R res = team_sum<TEAM>(Jr * vj) + s.rbias[r];
           const R lam = s.rlam[r];
           R nlam = lam - res * invA;
-          if (s.rkind[r] >= 4) {
-            const R hi = mu * s.rlam[s.rnorm[r]];
+          const int kind = s.rkr[r] >> 16;
+          if (kind >= 4) {
+            const R hi = mu * s.rlam[r - (kind - 3)];
             nlam = min_(max_(nlam, -hi), hi);
           } else {
             nlam = max_(nlam, R(0));
@@ -1124,8 +1236,10 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         const unsigned long long m = team_ballot<TEAM>(tm, keep);
         const int pos = running + __popcll(m & lanes_below(tt));
         if (keep && pos < M.r_cap) {
+          const int kr = s.rkr[r];
+          const int kind = kr >> 16, ref = kr & 0xffff;
           const long long o = (long long)env * P.dbg_row_stride + (long long)sub_i * P.dbg_row_sub + pos;
-          P.dbg_key[o] = s.rkey[r];
+          P.dbg_key[o] = kind <= 2 ? (kind << 24) | (ref << 8) : (kind << 24) | M.si[ref * SI_COLS + SI_KEY];
           P.dbg_lam[o] = float(s.rlam[r]);
         }
         running += __popcll(m);
@@ -1136,11 +1250,14 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     for (int sb = 0; sb < ns; sb += TEAM) {
       const int sl = sb + tt;
       if (sl < ns) {
-        const int r = s.slotrow[sl];
+        const int r = s.sact[sl];
         V3<R> F = mk(R(0), R(0), R(0));
-        if (r >= 0)
-          F = add(add(mul(ld3<R>(s.n + 3 * sl), s.rlam[r]), mul(ld3<R>(s.t1 + 3 * sl), s.rlam[r + 1])),
-                  mul(ld3<R>(s.t2 + 3 * sl), s.rlam[r + 2]));
+        if (r >= 0) {
+          const V3<R> nrm = ld3<R>(s.n + 3 * sl);
+          V3<R> t1, t2;
+          tangents(nrm, t1, t2);
+          F = add(add(mul(nrm, s.rlam[r]), mul(t1, s.rlam[r + 1])), mul(t2, s.rlam[r + 2]));
+        }
         st3(s.x + 3 * sl, F);  // the contact point is no longer needed
       }
     }
@@ -1159,7 +1276,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     __syncthreads();
     for (int j = tt; j < nd; j += TEAM) {
       const int lk = M.dof_link[j];
-      const R* lf = M.lf + lk * LF_COLS;
+      const double* lf = M.lf + lk * LF_COLS;
       const int c = M.li[lk * LI_COLS + LI_COL];
       const R pt = P.pos_tgt ? R(P.pos_tgt[dbase + j]) : R(0);
       const R vt = P.vel_tgt ? R(P.vel_tgt[dbase + j]) : R(0);
