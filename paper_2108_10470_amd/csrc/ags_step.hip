@@ -1049,6 +1049,11 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     }
     __syncthreads();
     const int Rn = s.misc[0];
+    // largest row count of the wavefront's teams (uniform; read while every lane is active)
+    int rn_w = Rn;
+#pragma unroll
+    for (int q = 1; q < EPW; ++q) rn_w = max(rn_w, lane_read(Rn, q * TEAM));
+    rn_w = lane_read(rn_w, 0);
 
     PHASE_MARK(7);
     // ---------------------------------------------------- row Jacobians and responses W_r = M~^-1 J_r^T
@@ -1165,32 +1170,32 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     R vj;
     if (fast) {
       // Delassus form, one row per lane: lane k holds y_k = J_k v and column k of A = J M~^-1 J^T
-      // (Acol[r] = J_k W_r, A being symmetric), so a row update is a few broadcasts, a clamp and one FMA per lane.
-      R Acol[TEAM];
+      // (Acol[r] = J_k W_r, A being symmetric).  The wavefront runs the rows of its teams in lockstep, up to
+      // the larger row count rn_w.
+      R Acol[TEAM];  // rows r >= this team's count have W_r = 0
 #pragma unroll
-      for (int r = 0; r < TEAM; ++r) Acol[r] = r < Rn ? jrow_dot(jr, s.W + r * L.wstride) : R(0);
+      for (int r = 0; r < TEAM; ++r) Acol[r] = r < rn_w ? jrow_dot(jr, s.W + r * L.wstride) : R(0);
       R y = jrow_dot(jr, s.vs);
       const bool own = tt < Rn;
       const R bias = own ? s.rbias[tt] : R(0);
       const R ia = own ? s.rinvA[tt] : R(0);
       const int kindv = own ? (s.rkr[tt] >> 16) : 0;
-      const int nrmv = kindv >= 4 ? tt - (kindv - 3) : tt;
-      R lam = R(0);
+      const bool fric = kindv >= 4;
+      const int nrmv = fric ? tt - (kindv - 3) : -1;
+      // every lane evaluates the update of its own row; the one of row r is applied and its impulse change
+      // broadcast.  A friction lane follows its normal row's impulse through those broadcasts.
+      R lam = R(0), lamn = R(0);
       for (int it = 0; it < P.iters; ++it) {
 #pragma unroll
         for (int r = 0; r < TEAM; ++r) {
-          const R iar = r < Rn ? team_read<TEAM>(tm, ia, r) : R(0);
-          if (iar != R(0)) {
-            const R lamr = team_read<TEAM>(tm, lam, r);
-            R nl = lamr - (team_read<TEAM>(tm, y, r) + team_read<TEAM>(tm, bias, r)) * iar;
-            if (team_read<TEAM>(tm, kindv, r) >= 4) {
-              const R hi = mu * team_read_at<TEAM>(lam, nrmv, r, tm);
-              nl = min_(max_(nl, -hi), hi);
-            } else {
-              nl = max_(nl, R(0));
-            }
-            if (tt == r) lam = nl;
-            y += Acol[r] * (nl - lamr);
+          if (r < rn_w) {
+            const R hi = fric ? mu * lamn : R(INFINITY);
+            const R lo = fric ? -hi : R(0);
+            const R cand = ia != R(0) ? min_(max_(lam - (y + bias) * ia, lo), hi) : lam;
+            const R dl = team_read<TEAM>(tm, cand - lam, r);
+            if (tt == r) lam = cand;
+            if (nrmv == r) lamn += dl;
+            y += Acol[r] * dl;
           }
         }
       }
