@@ -511,7 +511,7 @@ Lds make_layout(const ags_model_info& info, int n_levels, int n_anc, int team, s
   const int dyn_end = off;
   off = shared;
   L.wstride = nv | 1;
-  L.W = take(team * L.wstride);
+  L.W = take(kFastRows * L.wstride);
   off = std::max(off, dyn_end);
   L.team_stride = off;
   L.total = L.team_base + (kTeam / team) * L.team_stride;
@@ -606,9 +606,12 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     TypeDev T;
     T.n_envs = (int)lists[t].size();
     // lanes per environment: 32 (two environments per wavefront) when every per-lane loop fits
-    T.team = (p->lanes_per_env == 32 || (p->lanes_per_env == 0 && M->info.n_v <= 32)) && M->info.n_v <= 32 ? 32 : 64;
+    // automatic: FP64 compute gives each environment a whole wavefront (its LDS then allows two wavefronts
+    // per SIMD); FP32 packs two environments per wavefront when every per-lane loop fits in 32 lanes
+    const bool auto32 = !p->compute_fp64 && M->info.n_v <= 32;
+    T.team = (p->lanes_per_env == 32 || (p->lanes_per_env == 0 && auto32)) && M->info.n_v <= 32 ? 32 : 64;
     if (p->persistent) {  // one lane count for all types: 32 only if every type fits
-      bool all32 = p->lanes_per_env != 64;
+      bool all32 = p->lanes_per_env == 32 || (p->lanes_per_env == 0 && !p->compute_fp64);
       for (int u = 0; u < n_models; ++u)
         if (!lists[u].empty() && models[u]->info.n_v > 32) all32 = false;
       T.team = all32 ? 32 : 64;

@@ -12,7 +12,8 @@ constexpr int kMaxV = 64;       // generalized velocities per environment (one l
 constexpr int kMaxSlots = 256;
 constexpr float kMinRowMass = 1e-6f;  // rows with J M~^-1 J^T below this are dropped (immovable)
 constexpr int kPhases = 10;           // controls, forward, inward, outward, v*, narrow, rows, responses, PGS, outputs
-constexpr int kJointEntries = 12;     // joint (non-root) entries of a compact Jacobian row
+constexpr int kJointEntries = 10;     // joint (non-root) entries of a compact Jacobian row
+constexpr int kFastRows = 32;         // rows solved in registers (one per lane); also the row-response chunk
 
 // per-link integer table
 enum { LI_PARENT = 0, LI_JTYPE, LI_COL, LI_DOF, LI_ROOT, LI_CHILD_BEGIN, LI_CHILD_END, LI_ANC_BEGIN, LI_ANC_END,

@@ -598,6 +598,8 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   const Lds& L = T.lds;
   const int n_envs = T.n_envs;
   constexpr int EPW = kTeam / TEAM;  // environments per wavefront
+  constexpr int FR = kFastRows;      // rows of the register Gauss-Seidel path and of one response chunk
+  static_assert(FR <= TEAM, "fast rows exceed the lanes of an environment");
   const int t = threadIdx.x;         // lane in the wavefront
   const int tm = EPW == 1 ? 0 : t / TEAM;  // team (environment slot) of this lane
   const int tt = EPW == 1 ? t : t % TEAM;  // lane within the team
@@ -1057,19 +1059,20 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 
     PHASE_MARK(7);
     // ---------------------------------------------------- row Jacobians and responses W_r = M~^-1 J_r^T
-    // Up to TEAM rows (one per lane) keep their Jacobian in registers (compact form) and W in LDS and are
+    // Up to FR rows (one per lane) keep their Jacobian in registers (compact form) and W in LDS and are
     // solved in registers below; more rows (or rows too long for the compact form) go through global scratch.
-    const bool fast = Rn <= TEAM && M.jfast;
+    const bool fast = Rn <= FR && M.jfast;
     if (!fast)
       for (int k = tt; k < Rn * nv; k += TEAM) Jg[k] = R(0);
     JRow<R> jr;  // fast path: this lane's row
     jrow_clear(jr);
     __syncthreads();
-    for (int rb = 0; rb < Rn; rb += TEAM) {
-      const int r = rb + tt;
-      const auto Wrow = s.W + tt * L.wstride;
+    for (int rb = 0; rb < Rn; rb += FR) {  // chunks of FR rows, one per lane
+      const int r = tt < FR ? rb + tt : Rn;
+      const auto Wrow = s.W + tt * L.wstride;  // only lanes tt < FR own a row of the block
       R* const JrowG = Jg + (long long)r * nv;
-      for (int c = 0; c < nv; ++c) Wrow[c] = R(0);
+      if (tt < FR)
+        for (int c = 0; c < nv; ++c) Wrow[c] = R(0);
       if (r < Rn) {
         const int kr = s.rkr[r];
         const int kind = kr >> 16, ref = kr & 0xffff;
@@ -1152,7 +1155,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       }
       __syncthreads();
       if (!fast) {
-        const int rows_here = min(TEAM, Rn - rb);
+        const int rows_here = min(FR, Rn - rb);
         for (int q = 0; q < rows_here; ++q)
           for (int c = tt; c < nv; c += TEAM) Wg[(long long)(rb + q) * nv + c] = s.W[q * L.wstride + c];
         __syncthreads();
@@ -1172,9 +1175,9 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       // Delassus form, one row per lane: lane k holds y_k = J_k v and column k of A = J M~^-1 J^T
       // (Acol[r] = J_k W_r, A being symmetric).  The wavefront runs the rows of its teams in lockstep, up to
       // the larger row count rn_w.
-      R Acol[TEAM];  // rows r >= this team's count have W_r = 0
+      R Acol[FR];  // rows r >= this team's count have W_r = 0
 #pragma unroll
-      for (int r = 0; r < TEAM; ++r) Acol[r] = r < rn_w ? jrow_dot(jr, s.W + r * L.wstride) : R(0);
+      for (int r = 0; r < FR; ++r) Acol[r] = r < rn_w ? jrow_dot(jr, s.W + r * L.wstride) : R(0);
       R y = jrow_dot(jr, s.vs);
       const bool own = tt < Rn;
       const R bias = own ? s.rbias[tt] : R(0);
@@ -1186,15 +1189,19 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       // broadcast.  A friction lane follows its normal row's impulse through those broadcasts.
       R lam = R(0), lamn = R(0);
       for (int it = 0; it < P.iters; ++it) {
+        // opaque copies of the lane's row and normal-row indices and of the row count: keeps the per-row
+        // compares inside the sweep instead of 3 x FR hoisted (and spilled) masks
+        int me = tt, mn = nrmv, rw = rn_w;
+        asm volatile("" : "+v"(me), "+v"(mn), "+s"(rw));
 #pragma unroll
-        for (int r = 0; r < TEAM; ++r) {
-          if (r < rn_w) {
+        for (int r = 0; r < FR; ++r) {
+          if (r < rw) {
             const R hi = fric ? mu * lamn : R(INFINITY);
             const R lo = fric ? -hi : R(0);
             const R cand = ia != R(0) ? min_(max_(lam - (y + bias) * ia, lo), hi) : lam;
             const R dl = team_read<TEAM>(tm, cand - lam, r);
-            if (tt == r) lam = cand;
-            if (nrmv == r) lamn += dl;
+            if (me == r) lam = cand;
+            if (mn == r) lamn += dl;
             y += Acol[r] * dl;
           }
         }
@@ -1355,15 +1362,20 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   }
 }
 
+// Register budget: two wavefronts per SIMD (<= 256 VGPRs) so that one hides the other's latency, except
+// for the FP64 two-environments-per-wavefront form whose LDS allows one workgroup per SIMD anyway.
 template <typename R, int TEAM>
-__global__ __launch_bounds__(64) void step_kernel(StepArgs P) {
+constexpr int kWavesPerEU = (sizeof(R) == 4 || TEAM == 64) ? 2 : 1;
+
+template <typename R, int TEAM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<R, TEAM>))) void step_kernel(StepArgs P) {
   step_group<R, TEAM>(P, P.ty, blockIdx.x, true);
 }
 
 // persistent form: each workgroup walks the work list with a grid stride; the list is ordered by
 // estimated cost, so the heaviest groups start first and the tail is made of the cheapest ones
 template <typename R, int TEAM>
-__global__ __launch_bounds__(64) void step_fused(FusedArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<R, TEAM>))) void step_fused(FusedArgs A) {
   int prev = -1;
   for (int u = blockIdx.x; u < A.n_units; u += gridDim.x) {
     const int ty = A.units[2 * u], grp = A.units[2 * u + 1];
