@@ -1472,7 +1472,7 @@ template <typename R>
 __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
   extern __shared__ double g_adj_lds[];
   const int ei = blockIdx.x;
-  if (ei >= n_envs) return;
+  if (ei >= n_envs || (P.list_count && ei >= *P.list_count)) return;
   const AdjLds& L = P.L;
   Env<R> E;
   E.P = &P;
@@ -1524,6 +1524,10 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
     ok = fwd_substep(E, st + s * sw, st + S * sw);
     if (ok) rev_substep(E, st + s * sw);
   }
+  if (!ok && P.retry) {  // more rows than this layout holds: hand the environment to the larger layout
+    if (lane == 0) P.retry[atomicAdd(P.retry_count, 1)] = env;
+    return;
+  }
   for (int k = lane; k < 13 * na; k += 64) P.root_adj[(long long)E.abase * 13 + k] = ok ? float(E.r[L.rbar + k]) : 0.0f;
   for (int k = lane; k < 2 * nd; k += 64) P.dof_adj[(long long)E.dbase * 2 + k] = ok ? float(E.r[L.dbar + k]) : 0.0f;
   for (int j = lane; j < nd; j += 64) P.act_adj[E.dbase + j] = ok ? float(E.r[L.ab + j]) : 0.0f;
@@ -1531,6 +1535,10 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
   E.phase(-1);
   if (P.cycles && lane == 0)
     for (int k = 0; k < kAdjPhases; ++k) P.cycles[(long long)env * kAdjPhases + k] = E.cyc[k];
+}
+
+__global__ void zero_count_kernel(int* c) {
+  if (threadIdx.x == 0) c[0] = 0;
 }
 
 template <typename R>
@@ -1545,6 +1553,11 @@ hipError_t launch_adj(const AdjArgs& a, int n_envs, hipStream_t stream) {
 hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t stream) {
   if (n_envs <= 0) return hipSuccess;
   return fp64 ? launch_adj<double>(a, n_envs, stream) : launch_adj<float>(a, n_envs, stream);
+}
+
+hipError_t launch_zero_count(int* c, hipStream_t stream) {
+  hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(64), 0, stream, c);
+  return hipGetLastError();
 }
 
 hipError_t set_adjoint_lds_limit(int fp64, size_t bytes) {

@@ -433,13 +433,16 @@ struct TypeDev {
   long long scratch_stride = 0;  // elements of the compute type per env
   AdjLds adj{};
   size_t adj_bytes = 0;           // LDS of the adjoint kernel
+  AdjLds adj_small{};             // the same with at most kAdjSmallRows rows (first pass of a two-pass adjoint)
+  size_t adj_small_bytes = 0;
+  bool adj_two = false;           // rows may exceed kAdjSmallRows: small layout first, overflow retried
   bool body_pairs = false;
 };
 
 int adj_fp64(const ags_sim_params& p) { return p.adjoint_precision == 64 || (p.adjoint_precision == 0 && p.compute_fp64); }
 
 // LDS layout of the adjoint kernel for one environment (one wavefront per environment)
-AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters) {
+AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters, int row_cap) {
   AdjLds L{};
   int off = 0;
   auto take = [&](int n) {
@@ -448,7 +451,7 @@ AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters) {
     return o;
   };
   const int nl = info.n_links, nv = std::max(1, info.n_v), nd = std::max(1, info.n_dof), na = info.n_actors;
-  const int rc = std::min(std::max(1, info.max_rows), kAdjRows);
+  const int rc = std::min(std::max(1, info.max_rows), row_cap);
   L.rows_cap = rc;
   L.Rm = take(9 * nl); L.p = take(3 * nl); L.ax = take(3 * nl); L.c = take(3 * nl); L.Iw = take(6 * nl);
   L.Ic = take(10 * nl); L.V = take(6 * nl); L.Vs = take(6 * nl); L.X0 = take(6 * nl); L.X1 = take(6 * nl);
@@ -530,6 +533,7 @@ struct ags_sim {
   void* bound[AGS_NUM_TENSORS] = {nullptr};
   float* kp_dof = nullptr;  // device: drive stiffness of every DOF (target adjoints)
   double* mid_root = nullptr;  // set while a rollout recomputes: where the step writes substep states
+  int* adj_retry = nullptr;    // device: count, then the environments the small adjoint layout could not hold
   // persistent (fused) launch
   bool fused_ok = false;
   int* units = nullptr;  // device: (type, group) pairs
@@ -600,6 +604,7 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     }
   }
   const size_t elem_size = p->compute_fp64 ? sizeof(double) : sizeof(float);
+  int max_type_envs = 0;
   for (int t = 0; t < n_models; ++t) {
     if (lists[t].empty()) continue;
     const ags_model* M = models[t];
@@ -679,8 +684,13 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     D.col_anc = (const unsigned long long*)(b + offs[14]);
     D.col_link = (const int*)(b + offs[15]);
     T.body_pairs = M->body_pairs;
-    T.adj = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters));
+    T.adj = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), kAdjRows);
     T.adj_bytes = (size_t)T.adj.n_real * (adj_fp64(*p) ? sizeof(double) : sizeof(float)) + (size_t)T.adj.n_int * sizeof(int);
+    T.adj_two = M->info.max_rows > kAdjSmallRows;
+    T.adj_small = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), kAdjSmallRows);
+    T.adj_small_bytes = (size_t)T.adj_small.n_real * (adj_fp64(*p) ? sizeof(double) : sizeof(float)) +
+                        (size_t)T.adj_small.n_int * sizeof(int);
+    max_type_envs = std::max(max_type_envs, T.n_envs);
     if (T.adj_bytes <= 160 * 1024 && T.adj_bytes > 64 * 1024 &&
         (err = set_adjoint_lds_limit(adj_fp64(*p), T.adj_bytes)) != hipSuccess) {
       S->types.push_back(T);
@@ -709,6 +719,10 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
       return hip_fail(err, "sim: LDS limit");
     }
     S->types.push_back(T);
+  }
+  if ((err = hipMalloc(&S->adj_retry, ((size_t)max_type_envs + 1) * sizeof(int))) != hipSuccess) {
+    ags_sim_destroy(S);
+    return hip_fail(err, "sim: adjoint retry list");
   }
   if (p->persistent && !S->types.empty() && (int)S->types.size() <= kMaxFusedTypes) {
     // work list: (type, group) units, types ordered by estimated cost per group (heaviest first)
@@ -760,6 +774,7 @@ extern "C" void ags_sim_destroy(ags_sim* S) {
     if (T.block) (void)hipFree(T.block);
     if (T.scratch) (void)hipFree(T.scratch);
   }
+  if (S->adj_retry) (void)hipFree(S->adj_retry);
   if (S->env_tables) (void)hipFree(S->env_tables);
   if (S->units) (void)hipFree(S->units);
   if (S->kp_dof) (void)hipFree(S->kp_dof);
@@ -898,7 +913,23 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
     a.mc = p.contact_margin;
     a.substeps = p.substeps;
     a.iters = p.pgs_iters;
-    hipError_t e = launch_adjoint(a, T.n_envs, adj_fp64(p), (hipStream_t)stream);
+    hipError_t e = hipSuccess;
+    if (T.adj_two) {
+      // pass 1 with the small layout (more workgroups per CU); environments with more rows are collected
+      // and pass 2 runs them with the full layout
+      AdjArgs a1 = a;
+      a1.L = T.adj_small;
+      a1.retry_count = S->adj_retry;
+      a1.retry = S->adj_retry + 1;
+      AdjArgs a2 = a;
+      a2.env_list = S->adj_retry + 1;
+      a2.list_count = S->adj_retry;
+      if ((e = launch_zero_count(S->adj_retry, (hipStream_t)stream)) == hipSuccess &&
+          (e = launch_adjoint(a1, T.n_envs, adj_fp64(p), (hipStream_t)stream)) == hipSuccess)
+        e = launch_adjoint(a2, T.n_envs, adj_fp64(p), (hipStream_t)stream);
+    } else {
+      e = launch_adjoint(a, T.n_envs, adj_fp64(p), (hipStream_t)stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "step_backward: launch");
   }
   return AGS_OK;

@@ -120,6 +120,7 @@ hipError_t fused_blocks_per_cu(int fp64, int team, size_t lds_bytes, int* blocks
 
 // ---------------------------------------------------------------- adjoint of one env-step
 constexpr int kAdjRows = 64;   // constraint rows per substep the adjoint handles (one lane each)
+constexpr int kAdjSmallRows = 32;  // row capacity of the first, smaller-LDS adjoint pass
 constexpr int kAdjIters = 32;  // Gauss-Seidel sweeps the adjoint's tape holds
 constexpr int kAdjPhases = 8;
 
@@ -164,12 +165,16 @@ struct AdjArgs {
   const double* mid_root;  // optional: substep start states from the forward step (see StepArgs)
   const double* mid_dof;
   long long mid_block;
+  int* retry;              // optional: environments whose rows exceed this layout's capacity are appended here
+  int* retry_count;        //   (count at *retry_count) instead of being written with a zero adjoint
+  const int* list_count;   // optional: number of valid entries of env_list (device), for a launch over a retry list
   double h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
 };
 
 hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t stream);
 hipError_t set_adjoint_lds_limit(int fp64, size_t bytes);
+hipError_t launch_zero_count(int* c, hipStream_t stream);
 
 hipError_t launch_scale_by_kp(float* x, const float* kp, int n, hipStream_t stream);
 

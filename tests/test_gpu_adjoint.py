@@ -51,6 +51,28 @@ def test_step_adjoint_vs_finite_differences(model, steps_before, fp64):
     assert (worst <= 1.0).all()
 
 
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_step_adjoint_rows_beyond_first_pass(fp64):
+    """Humanoid-like envs lying on the ground after 120 steps, chosen to include the ones with the most
+    constraint rows: env-substeps with more than 32 rows do not fit the first (smaller-LDS) adjoint pass
+    and are handed to the full-capacity pass; every env must still match the finite differences."""
+    env, params, oe, root, dof, act, wr, wd = A.f32_inputs(W.env_humanoid(), W.SimParams(), 128, 120)
+    rc = oe.step(params, root, dof, act)["row_count"].reshape(128, -1).max(axis=1)
+    order = np.argsort(-rc, kind="stable")
+    pick = np.concatenate([order[:16], order[-8:]])
+    assert rc[pick].max() > 32, rc.max()  # the second pass is exercised
+    root, dof, act, wr, wd = root[pick], dof[pick], act[pick], wr[pick], wd[pick]
+    fd, ent = A.fd_grads(oe, params, root, dof, act, wr, wd)
+    g, status = A.gpu_grads(env, params, root, dof, act, wr, wd, fp64)
+    assert (status == 0).all(), status
+    worst, ok = A.compare(g, fd, FLOOR[fp64])
+    d = {"envs": int(root.shape[0]), "envs_over_32_rows": int((rc[pick] > 32).sum()), "entries": int(ok.size),
+         "excluded_switch": int((~ok).sum()), "worst_ratio": float(worst.max()),
+         "pass_rate": float((worst <= 1.0).mean())}
+    _report(f"adjoint_humanoid_many_rows_{'fp64' if fp64 else 'fp32'}", d)
+    assert (worst <= 1.0).all()
+
+
 def _ant_rollout_case(E=16, T=16, warm=30):
     env = W.as_f32(W.env_ant())
     params = W.params_f32(W.SimParams())
