@@ -305,6 +305,51 @@ __device__ __forceinline__ void sphere_box(V3<R> c, const R* Rb, V3<R> b, V3<R> 
 // packed symmetric storage: element (i, j) of a symmetric matrix
 __device__ __forceinline__ int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
+// ---------------------------------------------------------------- wavefront GEMM on the matrix cores
+// C = X Y (M x N, inner dimension K, each at most 64) by one wavefront with 16x16x4 MFMA tiles.  x(i, k)
+// and y(k, j) return operand entries (called only inside the bounds); out(i, j, c) receives each entry of C.
+// Operand lanes: lane l supplies X[m0 + l % 16][k0 + l / 16] and Y[k0 + l / 16][n0 + l % 16]; result
+// value v of lane l is row 4 (l / 16) + v (FP32) or 4 v + l / 16 (FP64) of the tile, column l % 16.
+// Call from uniform control flow (all 64 lanes active).
+template <typename R>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 step(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 step(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <typename R, typename FX, typename FY, typename FO>
+__device__ __forceinline__ void wave_gemm(int M, int N, int K, int lane, const FX& x, const FY& y, const FO& out) {
+  using T = Mfma<R>;
+  const int lc = lane & 15, lk = lane >> 4;
+  for (int m0 = 0; m0 < M; m0 += 16)
+    for (int n0 = 0; n0 < N; n0 += 16) {
+      typename T::v4 c = {R(0), R(0), R(0), R(0)};
+      for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + lk;
+        const R a = (m0 + lc < M && k < K) ? x(m0 + lc, k) : R(0);
+        const R b = (k < K && n0 + lc < N) ? y(k, n0 + lc) : R(0);
+        c = T::step(a, b, c);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = m0 + T::row(lane, v), j = n0 + lc;
+        if (i < M && j < N) out(i, j, c[v]);
+      }
+    }
+}
+
 // ---------------------------------------------------------------- per-environment context
 template <typename R>
 struct Env {
@@ -401,14 +446,15 @@ __device__ void link_vel(const Env<R>& E, const R* x, int out) {
 template <typename R>
 __device__ R chol_solve_lanes(const Env<R>& E, R b) {
   const R* Lm = E.r + E.P->L.Lm;
+  const R* ldi = E.r + E.P->L.ldi;
   const int nvp = E.P->L.nvp, nv = E.nv, c = E.lane;
   for (int k = 0; k < nv; ++k) {
-    const R xk = lane_read(b, k) / Lm[k * nvp + k];
+    const R xk = lane_read(b, k) * ldi[k];
     if (c == k) b = xk;
     if (c > k && c < nv) b -= Lm[c * nvp + k] * xk;
   }
   for (int k = nv - 1; k >= 0; --k) {
-    const R xk = lane_read(b, k) / Lm[k * nvp + k];
+    const R xk = lane_read(b, k) * ldi[k];
     if (c == k) b = xk;
     if (c < k) b -= Lm[k * nvp + c] * xk;
   }
@@ -418,6 +464,7 @@ __device__ R chol_solve_lanes(const Env<R>& E, R b) {
 template <typename R>
 __device__ void chol_solve_row(const Env<R>& E, R* y) {
   const R* Lm = E.r + E.P->L.Lm;
+  const R* ldi = E.r + E.P->L.ldi;
   const int nvp = E.P->L.nvp, nv = E.nv;
   for (int k = 0; k < nv; ++k) {
     const R* Lk = Lm + k * nvp;
@@ -430,7 +477,7 @@ __device__ void chol_solve_row(const Env<R>& E, R* y) {
       t3 -= Lk[j + 3] * y[j + 3];
     }
     for (; j < k; ++j) t0 -= Lk[j] * y[j];
-    y[k] = ((t0 + t1) + (t2 + t3)) / Lk[k];
+    y[k] = ((t0 + t1) + (t2 + t3)) * ldi[k];
   }
   for (int k = nv - 1; k >= 0; --k) {
     R t0 = y[k], t1 = R(0), t2 = R(0), t3 = R(0);
@@ -442,7 +489,7 @@ __device__ void chol_solve_row(const Env<R>& E, R* y) {
       t3 -= Lm[(j + 3) * nvp + k] * y[j + 3];
     }
     for (; j < nv; ++j) t0 -= Lm[j * nvp + k] * y[j];
-    y[k] = ((t0 + t1) + (t2 + t3)) / Lm[k * nvp + k];
+    y[k] = ((t0 + t1) + (t2 + t3)) * ldi[k];
   }
 }
 
@@ -450,7 +497,7 @@ __device__ void chol_solve_row(const Env<R>& E, R* y) {
 // sin: state at the start of the substep; sout: state after it.  Returns false when the substep
 // has more constraint rows than the adjoint handles (wave-uniform).
 template <typename R>
-__device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
+__device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   const AdjArgs& P = *E.P;
   const AdjLds& L = P.L;
   const DevModel& M = P.m;
@@ -612,7 +659,9 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
       sacc = (t0 + t1) + (t2 + t3);
     }
     const R d = sqrt_(lane_read(sacc, k));
-    if (lane >= k && lane < nv) Lm[lane * nvp + k] = lane == k ? d : sacc / d;
+    const R di = R(1) / d;
+    if (lane >= k && lane < nv) Lm[lane * nvp + k] = lane == k ? d : sacc * di;
+    if (lane == 0) E.r[L.ldi + k] = di;
     sync<R>();
   }
   // ---- C(q, qd): RNEA with zero joint accelerations, gravity as a base acceleration
@@ -884,18 +933,15 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   nrm = lane < nkeep && g_kind >= 4 ? g_nrm : -1;
   sync<R>();
   const int Rn = nkeep;
-  // ---- Delassus matrix A = J W (symmetric, packed; row s per lane, entries r <= s)
+  // ---- Delassus matrix A = J W^T (symmetric, packed lower), on the matrix cores
   R* A = E.r + L.A;
   const int rcp = L.rcp;
-  if (lane < Rn) {
-    const R* Js = J + rmap[lane] * nvp;
-    for (int r = 0; r <= lane; ++r) {
-      const R* Wr = W + rmap[r] * nvp;
-      R t = R(0);
-      for (int c = 0; c < nv; ++c) t += Js[c] * Wr[c];
-      A[tri(lane, r)] = t;
-    }
-  }
+  wave_gemm<R>(
+      Rn, Rn, nv, lane, [&](int s, int c) { return J[rmap[s] * nvp + c]; },
+      [&](int c, int r) { return W[rmap[r] * nvp + c]; },
+      [&](int s, int r, R t) {
+        if (r <= s) A[tri(s, r)] = t;
+      });
   // ---- Gauss-Seidel with its tape
   R y = R(0), lam = R(0);
   if (lane < Rn) {
@@ -973,7 +1019,7 @@ __device__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
 // rbar/dbar hold the adjoint of the state after the substep; on return, of the state before it.
 // The substep's internals are those left in LDS by fwd_substep(sin, ...).
 template <typename R>
-__device__ void rev_substep(Env<R>& E, const R* sin) {
+__device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   const AdjArgs& P = *E.P;
   const AdjLds& L = P.L;
   const DevModel& M = P.m;
@@ -1122,28 +1168,21 @@ __device__ void rev_substep(Env<R>& E, const R* sin) {
   }
   sync<R>();
   // ---- T_s = sum_r S_sr W_r into the J rows (J is not needed any more)
-  if (lane < Rn) {
-    R* Ts = J + rmap[lane] * nvp;
-    for (int c = 0; c < nv; ++c) {
-      R t = R(0);
-      for (int r = 0; r < Rn; ++r) t += Ab[tri(lane, r)] * W[rmap[r] * nvp + c];
-      Ts[c] = t;
-    }
-  }
+  wave_gemm<R>(
+      Rn, nv, Rn, lane, [&](int s2, int r) { return Ab[tri(s2, r)]; }, [&](int r, int c) { return W[rmap[r] * nvp + c]; },
+      [&](int s2, int c, R t) { J[rmap[s2] * nvp + c] = t; });
   // ---- w = M~^-1 (h v*_bar): the adjoint of the generalized forces
   const R wc = chol_solve_lanes(E, lane < nv ? h * vsb[lane] : R(0));
   if (lane < nv) ww[lane] = wc;
   sync<R>();
   // ---- P (dense, into Lm; the factor is not needed any more):
   // P = 1/2 W S W^T + sym(dnu z^T) + sym(qdd w^T), dnu = nu+ - v*
-  for (int i = lane; i < nv; i += 64) {
-    const R dni = nu1[i] - vs[i], zi = zz[i], qi = qdd[i], wi = ww[i];
-    for (int k = 0; k < nv; ++k) {
-      R t = R(0);
-      for (int s = 0; s < Rn; ++s) t += J[rmap[s] * nvp + i] * W[rmap[s] * nvp + k];
-      Lm[i * nvp + k] = R(0.5) * (t + dni * zz[k] + zi * (nu1[k] - vs[k]) + qi * ww[k] + wi * qdd[k]);
-    }
-  }
+  // (W S W^T = T^T W with T in the J rows)
+  wave_gemm<R>(
+      nv, nv, Rn, lane, [&](int i, int s2) { return J[rmap[s2] * nvp + i]; }, [&](int s2, int k) { return W[rmap[s2] * nvp + k]; },
+      [&](int i, int k, R t) {
+        Lm[i * nvp + k] = R(0.5) * (t + (nu1[i] - vs[i]) * zz[k] + zz[i] * (nu1[k] - vs[k]) + qdd[i] * ww[k] + ww[i] * qdd[k]);
+      });
   sync<R>();
   // ---- Jbar = T + lambda z^T + ybar v*^T
   if (lane < Rn) {

@@ -466,6 +466,7 @@ AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters, int 
   L.rbar = take(13 * na); L.dbar = take(2 * nd); L.nrb = take(13 * na);
   L.nvp = nv | 1;
   L.Lm = take(nv * L.nvp);
+  L.ldi = take(nv);
   L.rcp = rc | 1;
   L.J = take(rc * L.nvp); L.W = take(rc * L.nvp); L.A = take(rc * (rc + 1) / 2); L.Ab = take(rc * (rc + 1) / 2);
   L.rbc = take(rc); L.rb = take(rc); L.rinvA = take(rc); L.rlam = take(rc); L.rybar = take(rc); L.rbbar = take(rc);

@@ -132,7 +132,7 @@ struct AdjLds {
   int colS, colY, colYv, cs;                                       // per column, 6 each
   int q, qb, ab;                                                   // per DOF
   int st, rbar, dbar, nrb;                                             // state of each substep start, state adjoint
-  int Lm, nvp;                                                     // dense n_v x nvp matrix (factor, then P)
+  int Lm, nvp, ldi;                                                // dense n_v x nvp matrix (factor, then P); 1 / diag of the factor
   int J, W, A, Ab, rcp;  // rows: J, W (rows x nvp); A and S = Abar + Abar^T (packed symmetric)
   int rbc, rb, rinvA, rlam, rybar, rbbar, rx, rcen, rd, rxb, rqb;  // per row reals
   int rdb, rwa, rwb;                                               // per row: d adjoint, wrenches of bodies a, b
