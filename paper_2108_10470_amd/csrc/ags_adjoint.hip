@@ -954,17 +954,21 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   int* hst = E.ix + L.hst;
   const R mu = R(P.mu);
   E.phase(1);
+  // every lane evaluates the update of its own row (with the impulse of its normal row, which a friction
+  // lane follows through the broadcasts); row r's change is broadcast and applied to every y.  The lane's
+  // entry of the next row's column of A is loaded one row ahead.
+  const bool fric = kind >= 4;
+  const int nrm_own = fric ? nrm : -1;
+  R lamn = R(0);
   for (int it = 0; it < P.iters; ++it) {
+    R a_next = lane < Rn && Rn > 0 ? A[tri(lane, 0)] : R(0);
     for (int r = 0; r < Rn; ++r) {
-      const int kr = lane_read(kind, r);
-      const R lamn = kr >= 4 ? lane_read(lam, lane_read(nrm, r)) : R(0);
+      const R a_r = a_next;
+      if (r + 1 < Rn) a_next = lane < Rn ? A[tri(lane, r + 1)] : R(0);
       const R res = y + bias;
       const R x = lam - res * invA;
-      R lo = R(0), hi = R(INFINITY);
-      if (kr >= 4) {
-        hi = mu * lamn;
-        lo = -hi;
-      }
+      const R hi = fric ? mu * lamn : R(INFINITY);
+      const R lo = fric ? -hi : R(0);
       const int st = x > hi ? 2 : (x < lo ? 1 : 0);
       const R nl = st == 2 ? hi : (st == 1 ? lo : x);
       const R dl = lane_read(nl - lam, r);
@@ -974,7 +978,8 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
         hst[it * rcp + r] = st;
         lam = nl;
       }
-      if (lane < Rn) y += A[tri(lane, r)] * dl;
+      if (nrm_own == r) lamn += dl;
+      y += a_r * dl;
     }
   }
   if (lane < Rn) E.r[L.rlam + lane] = lam;
