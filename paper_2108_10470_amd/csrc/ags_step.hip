@@ -34,6 +34,8 @@ __device__ __forceinline__ float min_(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ double min_(double a, double b) { return fmin(a, b); }
 __device__ __forceinline__ float max_(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ double max_(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float fma_(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
 __device__ __forceinline__ float abs_(float a) { return fabsf(a); }
 __device__ __forceinline__ double abs_(double a) { return fabs(a); }
 __device__ __forceinline__ void sincos_(float x, float* s, float* c) { sincosf(x, s, c); }
@@ -1186,22 +1188,29 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       const bool fric = kindv >= 4;
       const int nrmv = fric ? tt - (kindv - 3) : -1;
       // every lane evaluates the update of its own row; the one of row r is applied and its impulse change
-      // broadcast.  A friction lane follows its normal row's impulse through those broadcasts.
-      R lam = R(0), lamn = R(0);
+      // broadcast.  A friction lane follows its normal row's impulse through those broadcasts and keeps its
+      // box bounds +-mu lambda_n.  Rows without a response (1/A_rr = 0: dropped, or lanes past the row count)
+      // hold lambda = 0 and their update is a clamp of 0, so they need no test.  c = lambda - b / A_rr.
+      R lam = R(0), hi = fric ? R(0) : R(INFINITY), lo = R(0), c = -bias * ia;
       for (int it = 0; it < P.iters; ++it) {
         // opaque copies of the lane's row and normal-row indices and of the row count: keeps the per-row
         // compares inside the sweep instead of 3 x FR hoisted (and spilled) masks
         int me = tt, mn = nrmv, rw = rn_w;
-        asm volatile("" : "+v"(me), "+v"(mn), "+s"(rw));
+        R muv = mu;  // in a vector register: a spilled scalar copy would be reloaded at every row
+        asm volatile("" : "+v"(me), "+v"(mn), "+s"(rw), "+v"(muv));
 #pragma unroll
         for (int r = 0; r < FR; ++r) {
           if (r < rw) {
-            const R hi = fric ? mu * lamn : R(INFINITY);
-            const R lo = fric ? -hi : R(0);
-            const R cand = ia != R(0) ? min_(max_(lam - (y + bias) * ia, lo), hi) : lam;
+            const R cand = min_(max_(fma_(-y, ia, c), lo), hi);
             const R dl = team_read<TEAM>(tm, cand - lam, r);
-            if (me == r) lam = cand;
-            if (mn == r) lamn += dl;
+            if (me == r) {
+              lam = cand;
+              c = cand - bias * ia;
+            }
+            if (mn == r) {
+              hi += muv * dl;
+              lo = -hi;
+            }
             y += Acol[r] * dl;
           }
         }
