@@ -153,14 +153,16 @@ def mean_rows(env, params, n_envs, steps, fp64, actions_dev, root0, dof0):
     return float(acc.item() / steps)
 
 
-def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, adjoint_precision=0):
+def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, adjoint_precision=0, control=None):
     """Forward rollout of T = len(actions) steps with a checkpoint every `every` steps, then the reverse
-    pass (segment recomputation + adjoint of every step) for L = sum of final root x positions."""
+    pass (segment recomputation + adjoint of every step) for L = sum of final root x positions.  control:
+    the per-step control the actions drive (DOF actuation, or PD position targets)."""
     import ctypes
     import torch
     from paper_2108_10470_amd import ags
+    control = ags.DOF_ACTUATION if control is None else control
     sim = ags.Sim([ags.Model(env)], [0] * n_envs, params, device="cuda:0", fp64=fp64,
-                  adjoint_precision=adjoint_precision)
+                  adjoint_precision=adjoint_precision, pd=control == ags.DOF_POS_TARGET)
     L = ags.lib()
     T = actions.shape[0]
     n = ctypes.c_int64()
@@ -183,12 +185,12 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, ad
         sim.dof_state.copy_(dof0)
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record(stream)
-        ags._check(L.ags_rollout_forward(sim.h, T, every, ags.DOF_ACTUATION, P(actions), P(ckpt), sp), "rollout_forward")
+        ags._check(L.ags_rollout_forward(sim.h, T, every, control, P(actions), P(ckpt), sp), "rollout_forward")
         e1.record(stream)
         root_adj.zero_()
         root_adj[:, 0] = 1.0
         dof_adj.zero_()
-        ags._check(L.ags_rollout_backward(sim.h, T, every, ags.DOF_ACTUATION, P(actions), P(ckpt), P(seg), P(root_adj), P(dof_adj),
+        ags._check(L.ags_rollout_backward(sim.h, T, every, control, P(actions), P(ckpt), P(seg), P(root_adj), P(dof_adj),
                                           P(act_adj), P(status), sp), "rollout_backward")
         e2.record(stream)
         torch.cuda.synchronize()
@@ -308,6 +310,22 @@ def run_hand(n_envs, steps, fp64):
             "finite": bool(torch.isfinite(sim.root_state).all() and torch.isfinite(sim.dof_state).all())}
 
 
+def run_hand_fwd_bwd(n_envs, steps, fp64, every):
+    """Hand + cube fwd+bwd: rollout driven by PD position targets (re-drawn each step), FP32 adjoint,
+    loss = sum over envs of the final cube x position, gradient w.r.t. every target."""
+    import torch
+    from paper_2108_10470_amd import ags, workloads as W
+    env = W.env_hand_cube()
+    root, dof = W.initial_state(env, n_envs, 0)
+    r0 = torch.tensor(root.reshape(-1, 13), dtype=torch.float32, device="cuda:0")
+    d0 = torch.tensor(dof.reshape(-1, 2), dtype=torch.float32, device="cuda:0")
+    tg = torch.tensor(W.pd_targets(env, n_envs, steps, 0).reshape(steps, -1), dtype=torch.float32, device="cuda:0")
+    out = run_fwd_bwd(env, W.HAND_PARAMS, n_envs, fp64, tg, r0, d0, every, reps=1, adjoint_precision=32,
+                      control=ags.DOF_POS_TARGET)
+    out["loss"] = "sum over envs of the final cube x position (gradient w.r.t. PD targets)"
+    return out
+
+
 def cpu_baseline(env, params, n_envs, n_steps):
     """The FP64 oracle on the host cores over a bounded sample of the same workload."""
     from oracle import oracle as O
@@ -373,6 +391,9 @@ def main():
     if not args.no_hand:
         hand = run_hand(args.hand_envs, args.hand_steps, head == "fp64")
         print(f"[bench] hand: {json.dumps(hand)}", file=sys.stderr, flush=True)
+        if not args.no_fwd_bwd:
+            hand["fwd_bwd"] = run_hand_fwd_bwd(args.hand_envs, args.hand_steps, head == "fp64", args.fwd_bwd_every)
+            print(f"[bench] hand fwd+bwd: {json.dumps(hand['fwd_bwd'])}", file=sys.stderr, flush=True)
     fwd_bwd = None
     if not args.no_fwd_bwd:
         T = args.fwd_bwd_steps

@@ -1057,6 +1057,31 @@ void orc_fk(const void* env, const double* root_state, const double* dof_state, 
   }
 }
 
+void orc_body_states(const void* env, const double* root_state, const double* dof_state, double* out) {
+  const Env* E = static_cast<const Env*>(env);
+  std::vector<double> qj, qd;
+  split_state(*E, root_state, dof_state, qj, qd);
+  for (size_t ai = 0; ai < E->actors.size(); ++ai) {
+    const Actor& A = E->actors[ai];
+    Kin K;
+    kinematics(A, root_state + 13 * ai, &qj[A.dof_off], K);
+    const double* v = &qd[A.v_off];
+    std::vector<v6> vel(A.links.size());
+    for (size_t i = 0; i < A.links.size(); ++i) {
+      const Link& L = A.links[i];
+      if (i == 0) vel[0] = A.fixed ? v6{} : root_velocity(K.R[0], v);
+      else vel[i] = v6add(m6v(K.X[i], vel[L.parent]), v6scl(K.S[i], v[L.col]));
+      // link coordinates -> world: angular part and the linear velocity of the link origin
+      const v3 w = mv(K.R[i], v3{vel[i][0], vel[i][1], vel[i][2]});
+      const v3 u = mv(K.R[i], v3{vel[i][3], vel[i][4], vel[i][5]});
+      double* o = out + 18 * (A.body_off + i);
+      for (int k = 0; k < 3; ++k) o[k] = K.p[i][k];
+      for (int k = 0; k < 9; ++k) o[3 + k] = K.R[i][k];
+      for (int k = 0; k < 3; ++k) { o[12 + k] = u[k]; o[15 + k] = w[k]; }
+    }
+  }
+}
+
 int orc_dynamics(const void* env, const double* params, const double* root_state, const double* dof_state,
                  const double* tau, double* M, double* C, double* qdd_crba, double* qdd_aba) {
   const Env* E = static_cast<const Env*>(env);

@@ -57,6 +57,10 @@ void orc_mass_props(const void* env, double* mass, double* com, double* inertia)
 
 /* world pose of every link: rotation (3x3 row-major, link->world) and origin */
 void orc_fk(const void* env, const double* root_state, const double* dof_state, double* R, double* p);
+/* Rigid-body states of one env (Table 1 "rigid body states"): per body (link), 18 values: origin of the
+ * link frame (3), its rotation to world (9, row-major), the world velocity of the link origin (3) and the
+ * world angular velocity (3), from the spatial velocities v_i = X_i v_parent + S_i qd_i. */
+void orc_body_states(const void* env, const double* root_state, const double* dof_state, double* out);
 
 /* joint-space quantities of one env: M (n_v x n_v, without armature), C (RNEA with qdd = 0, gravity
  * from params), qdd from CRBA+Cholesky and from ABA for generalized force tau (n_v), model armature only */

@@ -56,6 +56,7 @@ def lib():
         L.orc_env_sizes.argtypes = [ctypes.c_void_p, ip]
         L.orc_mass_props.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.orc_fk.argtypes = [ctypes.c_void_p, dp, dp, dp, dp]
+        L.orc_body_states.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.orc_dynamics.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_dynamics.restype = ctypes.c_int
         L.orc_slots.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, ip, ip]
@@ -153,6 +154,15 @@ class OracleEnv:
         p = np.zeros((self.n_bodies, 3))
         lib().orc_fk(self.h, _dp(root), _dp(dof), _dp(R), _dp(p))
         return R, p
+
+    def body_states(self, root, dof):
+        """Per body: link-frame origin (3), rotation to world (3 x 3), velocity of the origin (3) and
+        angular velocity (3), world frame; one env (root (A, 13), dof (D, 2))."""
+        root = np.ascontiguousarray(root, dtype=np.float64)
+        dof = np.ascontiguousarray(dof, dtype=np.float64)
+        out = np.zeros((self.n_bodies, 18))
+        lib().orc_body_states(self.h, _dp(root), _dp(dof), _dp(out))
+        return out[:, :3], out[:, 3:12].reshape(-1, 3, 3), out[:, 12:15], out[:, 15:18]
 
     def dynamics(self, params, root, dof, tau):
         root = np.ascontiguousarray(root, dtype=np.float64)

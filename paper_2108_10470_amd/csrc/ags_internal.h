@@ -88,6 +88,7 @@ struct StepArgs {
   const float* pos_tgt;
   const float* vel_tgt;
   float* contact_force;
+  float* rb_state;  // optional (N_B, 13): link origin, quaternion, origin velocity, angular velocity
   float* dof_force;
   float* dbg_qdd;
   int dbg_qdd_stride, dbg_qdd_sub;  // per env, per substep (sim-wide maximum n_v)

@@ -421,6 +421,68 @@ __device__ __forceinline__ void quat_R(const P& q, R* M) {
   quat_R(R(q[0]), R(q[1]), R(q[2]), R(q[3]), M);
 }
 
+// Pose and velocity of link i (world axes; origin relative to `origin`) from its parent's stored
+// orientation (quaternion), origin and velocity and the joint's own position and rate: rotation Rw and
+// quaternion qq (xyzw), joint origin o, world joint axis ax (zero at a root), angular velocity w and
+// velocity vl of the point o.
+template <typename R, int EPW>
+__device__ __forceinline__ void link_kinematics(const Tab<R>& M, const Ctx<R, EPW>& s, int i, V3<R> origin, R* Rw,
+                                                R* qq, V3<R>& o, V3<R>& w, V3<R>& vl, V3<R>& ax) {
+  const int* li = M.li + i * LI_COLS;
+  const int jt = li[LI_JTYPE];
+  ax = mk(R(0), R(0), R(0));
+  if (jt == J_FREE || jt == J_FIXED) {
+    // root pose from the root state (quaternion xyzw, normalised on read)
+    const auto rs = s.root + 13 * actor_of_root(M, i);
+    const R qx = rs[3], qy = rs[4], qz = rs[5], qw = rs[6];
+    const R inv = rsqrt_(qx * qx + qy * qy + qz * qz + qw * qw);
+    qq[0] = qx * inv; qq[1] = qy * inv; qq[2] = qz * inv; qq[3] = qw * inv;
+    quat_R(qq[0], qq[1], qq[2], qq[3], Rw);
+    o = sub(ld3<R>(rs), origin);
+    if (jt == J_FREE) {
+      const int c = li[LI_ROOTCOL];
+      vl = ld3<R>(s.qd + c);
+      w = ld3<R>(s.qd + c + 3);
+    } else {
+      vl = mk(R(0), R(0), R(0));
+      w = vl;
+    }
+    return;
+  }
+  const double* lf = M.lf + i * LF_COLS;
+  const int p = li[LI_PARENT];
+  const auto qp = s.q + 4 * p;
+  const R px = qp[0], py = qp[1], pz = qp[2], pw = qp[3];
+  R Rp[9];
+  quat_R(px, py, pz, pw, Rp);
+  const V3<R> axl = ld3<R>(lf + LF_AXIS);
+  V3<R> tl = ld3<R>(lf + LF_ANCHOR);
+  const R q = s.qj[li[LI_DOF]], qd = s.qd[li[LI_COL]];
+  if (jt == J_REV) {
+    // parent orientation composed with the joint rotation (angle q about the local axis)
+    R sh, ch;
+    sincos_(R(0.5) * q, &sh, &ch);
+    const R rx = axl.x * sh, ry = axl.y * sh, rz = axl.z * sh;
+    qq[0] = pw * rx + ch * px + (py * rz - pz * ry);
+    qq[1] = pw * ry + ch * py + (pz * rx - px * rz);
+    qq[2] = pw * rz + ch * pz + (px * ry - py * rx);
+    qq[3] = pw * ch - (px * rx + py * ry + pz * rz);
+    quat_R(qq[0], qq[1], qq[2], qq[3], Rw);
+  } else {
+    qq[0] = px; qq[1] = py; qq[2] = pz; qq[3] = pw;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rw[k] = Rp[k];
+    tl = add(tl, mul(axl, q));
+  }
+  ax = mv(Rp, axl);
+  const V3<R> op = ld3<R>(s.o + 3 * p);
+  o = add(op, mv(Rp, tl));
+  w = ld3<R>(s.v + 6 * p);
+  vl = add(ld3<R>(s.v + 6 * p + 3), cross(w, sub(o, op)));
+  if (jt == J_REV) w = add(w, mul(ax, qd));
+  else vl = add(vl, mul(ax, qd));
+}
+
 // velocity-product acceleration of a joint (world axes about the joint origin), from the link's velocity
 // (w, v at o) after the joint's own motion: revolute ((w x s) qd, (v x s) qd), prismatic (0, (w x s) qd)
 template <typename R, int EPW>
@@ -671,60 +733,10 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     for (int d = 0; d < M.n_levels; ++d) {
       for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
-        const int* li = M.li + i * LI_COLS;
         const double* lf = M.lf + i * LF_COLS;
-        const int jt = li[LI_JTYPE];
         R Rw[9], qq[4];
-        V3<R> o, w, vl, ax = mk(R(0), R(0), R(0));
-        if (jt == J_FREE || jt == J_FIXED) {
-          // root pose from the root state (quaternion xyzw, normalised on read)
-          const auto rs = s.root + 13 * actor_of_root(M, i);
-          R qx = rs[3], qy = rs[4], qz = rs[5], qw = rs[6];
-          const R inv = rsqrt_(qx * qx + qy * qy + qz * qz + qw * qw);
-          qq[0] = qx * inv; qq[1] = qy * inv; qq[2] = qz * inv; qq[3] = qw * inv;
-          quat_R(qq[0], qq[1], qq[2], qq[3], Rw);
-          o = sub(ld3<R>(rs), origin);
-          if (jt == J_FREE) {
-            const int c = li[LI_ROOTCOL];
-            vl = ld3<R>(s.qd + c);
-            w = ld3<R>(s.qd + c + 3);
-          } else {
-            vl = mk(R(0), R(0), R(0));
-            w = vl;
-          }
-        } else {
-          const int p = li[LI_PARENT];
-          const auto qp = s.q + 4 * p;
-          const R px = qp[0], py = qp[1], pz = qp[2], pw = qp[3];
-          R Rp[9];
-          quat_R(px, py, pz, pw, Rp);
-          const V3<R> axl = ld3<R>(lf + LF_AXIS);
-          V3<R> tl = ld3<R>(lf + LF_ANCHOR);
-          const R q = s.qj[li[LI_DOF]], qd = s.qd[li[LI_COL]];
-          if (jt == J_REV) {
-            // parent orientation composed with the joint rotation (angle q about the local axis)
-            R sh, ch;
-            sincos_(R(0.5) * q, &sh, &ch);
-            const R rx = axl.x * sh, ry = axl.y * sh, rz = axl.z * sh;
-            qq[0] = pw * rx + ch * px + (py * rz - pz * ry);
-            qq[1] = pw * ry + ch * py + (pz * rx - px * rz);
-            qq[2] = pw * rz + ch * pz + (px * ry - py * rx);
-            qq[3] = pw * ch - (px * rx + py * ry + pz * rz);
-            quat_R(qq[0], qq[1], qq[2], qq[3], Rw);
-          } else {
-            qq[0] = px; qq[1] = py; qq[2] = pz; qq[3] = pw;
-#pragma unroll
-            for (int k = 0; k < 9; ++k) Rw[k] = Rp[k];
-            tl = add(tl, mul(axl, q));
-          }
-          ax = mv(Rp, axl);
-          const V3<R> op = ld3<R>(s.o + 3 * p);
-          o = add(op, mv(Rp, tl));
-          w = ld3<R>(s.v + 6 * p);
-          vl = add(ld3<R>(s.v + 6 * p + 3), cross(w, sub(o, op)));
-          if (jt == J_REV) w = add(w, mul(ax, qd));
-          else vl = add(vl, mul(ax, qd));
-        }
+        V3<R> o, w, vl, ax;
+        link_kinematics(M, s, i, origin, Rw, qq, o, w, vl, ax);
         // spatial inertia about o (world axes): A = Ic_w + m (|d|^2 1 - d d^T), B = m d^, M = m 1
         const R m = R(lf[LF_MASS]);
         const V3<R> d = mv(Rw, ld3<R>(lf + LF_COM));
@@ -1346,6 +1358,33 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       }
     }
     PHASE_MARK(-1);
+  }
+
+  // ---------------------------------------------------------------- rigid-body states of the new state
+  if (P.rb_state) {
+    for (int d = 0; d < M.n_levels; ++d) {
+      for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
+        const int i = M.level_links[idx];
+        R Rw[9], qq[4];
+        V3<R> o, w, vl, ax;
+        link_kinematics(M, s, i, origin, Rw, qq, o, w, vl, ax);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s.q[4 * i + k] = qq[k];
+        st3(s.o + 3 * i, o);
+        st3(s.v + 6 * i, w);
+        st3(s.v + 6 * i + 3, vl);
+        if (valid) {
+          float* dst = P.rb_state + (long long)(bbase + i) * 13;
+          const V3<R> x = add(o, origin);
+          dst[0] = float(x.x); dst[1] = float(x.y); dst[2] = float(x.z);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) dst[3 + k] = float(qq[k]);
+          dst[7] = float(vl.x); dst[8] = float(vl.y); dst[9] = float(vl.z);
+          dst[10] = float(w.x); dst[11] = float(w.y); dst[12] = float(w.z);
+        }
+      }
+      __syncthreads();
+    }
   }
 
   // ---------------------------------------------------------------- write back

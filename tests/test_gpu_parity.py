@@ -113,3 +113,46 @@ def test_hand_cube_parity(fp64):
     _report(f"hand_cube_{'fp64' if fp64 else 'fp32'}", s)
     assert np.isfinite(g["root"]).all() and np.isfinite(g["dof"]).all()
     _assert_pass(s) if fp64 else _assert_fp32(s)
+
+
+def _quat_to_R(q):
+    x, y, z, w = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    return np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                     2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                     2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)], axis=-1).reshape(q.shape[:-1] + (3, 3))
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("make", [W.env_humanoid, W.env_arm_box], ids=["humanoid", "arm_box"])
+def test_rigid_body_states_match_oracle(make, fp64):
+    """Rigid-body states after a step (Table 1): every link's origin, orientation, origin velocity and
+    angular velocity against the oracle's body states of the GPU's own next state (FP32 outputs), within
+    the parity tolerance."""
+    env = W.as_f32(make())
+    p = W.params_f32(W.SimParams())
+    oe = O.OracleEnv(env)
+    E = 16
+    root, dof = W.initial_state(env, E, 0)
+    acts = W.actuation(env, E, 31, 0)
+    for t in range(30):  # in contact
+        o = oe.step(p, root, dof, acts[t])
+        root, dof = o["root"], o["dof"]
+    sim = ags.Sim([ags.Model(env)], [0] * E, p, device="cuda:0", fp64=fp64, rigid_body_state=True)
+    f32 = dict(dtype=torch.float32, device="cuda:0")
+    sim.root_state.copy_(torch.tensor(root.reshape(-1, 13), **f32))
+    sim.dof_state.copy_(torch.tensor(dof.reshape(-1, 2), **f32))
+    sim.actuation.copy_(torch.tensor(acts[30].reshape(-1), **f32))
+    sim.step()
+    torch.cuda.synchronize()
+    rb = sim.rb_state.double().cpu().numpy().reshape(E, oe.n_bodies, 13)
+    r_out = sim.root_state.double().cpu().numpy().reshape(root.shape)
+    d_out = sim.dof_state.double().cpu().numpy().reshape(dof.shape)
+    worst = 0.0
+    for e in range(E):
+        pos, Rm, v, w = oe.body_states(r_out[e], d_out[e])
+        g = np.concatenate([rb[e, :, :3], _quat_to_R(rb[e, :, 3:7]).reshape(-1, 9), rb[e, :, 7:13]], axis=1)
+        o_ = np.concatenate([pos, Rm.reshape(-1, 9), v, w], axis=1)
+        worst = max(worst, float(PT.ratio(g, o_).max()))
+        assert np.isfinite(g).all()
+    _report(f"rigid_body_state_{env.name}_{'fp64' if fp64 else 'fp32'}", {"envs": E, "max_ratio": worst})
+    assert worst <= 1.0

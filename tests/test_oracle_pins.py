@@ -300,6 +300,35 @@ def _system_velocity(env, root, dof):
     return np.array(qd)
 
 
+@pytest.mark.parametrize("make", [W.env_humanoid, W.env_arm_box])
+def test_body_states_match_kinematic_differences(make):
+    """Rigid-body states (Table 1): link origins and rotations equal FK; origin velocities and angular
+    velocities equal central differences of FK along the state's own generalized velocity (a free root
+    moves by v_com and turns by Exp(h w)), not the oracle's velocity recursion."""
+    env = make()
+    oe = O.OracleEnv(env)
+    root, dof = W.initial_state(env, 1, 3)
+    root, dof = root[0], dof[0]
+    rng = np.random.default_rng(5)
+    for ai, a in enumerate(env.actors):
+        if not a.fixed_base:
+            root[ai, 7:13] = rng.uniform(-1.0, 1.0, 6)
+    dof[:, 1] = rng.uniform(-2.0, 2.0, len(dof))
+    p, R, v, w = oe.body_states(root, dof)
+    R0, p0 = oe.fk(root, dof)
+    assert np.abs(p - p0).max() <= 1e-14 and np.abs(R - R0).max() <= 1e-14
+    qd = _system_velocity(env, root, dof)
+    d = 1e-6
+    Rp, pp = oe.fk(*_advance(env, root, dof, d * qd))
+    Rm, pm = oe.fk(*_advance(env, root, dof, -d * qd))
+    vfd = (pp - pm) / (2 * d)
+    S = np.einsum("bij,bkj->bik", (Rp - Rm) / (2 * d), R)  # dR/dt R^T = [w]x
+    wfd = np.stack([S[:, 2, 1], S[:, 0, 2], S[:, 1, 0]], axis=1)
+    assert np.abs(v - vfd).max() <= 1e-6 * (1 + np.abs(v).max())
+    assert np.abs(w - wfd).max() <= 1e-6 * (1 + np.abs(w).max())
+    assert np.abs(w).max() > 0.1 and np.abs(v).max() > 0.1  # the check is not vacuous
+
+
 def _bare_humanoid():
     return W.humanoid(armature=0.0, damping=0.0)
 
