@@ -219,10 +219,12 @@ int ags_rollout_forward(ags_sim* sim, int32_t n_steps, int32_t every, int32_t co
  * and ckpt: root_adj / dof_adj hold dL/d(final state) on entry and dL/d(initial state) on return;
  * act_adj (device, n_steps x N_D) receives dL/d actions[t] (for PD targets, kp dL/d(joint force): the
  * target enters the step only through the drive force kp (q* - q - h qd)).  seg is caller-owned device
- * scratch of ags_rollout_seg_bytes(sim, every) bytes: each segment is recomputed from its checkpoint
- * with ags_sim_step (output tensors untouched), keeping every step's substep states, and its steps are
- * reversed with ags_sim_step_backward (status as there), which then starts from those states instead
- * of recomputing them. */
+ * scratch of ags_rollout_seg_bytes(sim, every) bytes (two segment buffers): each segment is recomputed
+ * from its checkpoint with ags_sim_step (output tensors untouched), keeping every step's substep states,
+ * and its steps are reversed with ags_sim_step_backward (status as there), which then starts from those
+ * states instead of recomputing them.  The recomputation of the next (earlier) segment runs on a second
+ * stream the sim owns, overlapping the current segment's adjoint; events order the two buffers, and all
+ * work is joined into hip_stream before the call's last launch. */
 int ags_rollout_seg_bytes(const ags_sim* sim, int32_t every, int64_t* bytes);
 int ags_rollout_backward(ags_sim* sim, int32_t n_steps, int32_t every, int32_t control, const float* actions,
                          const float* ckpt, void* seg, float* root_adj, float* dof_adj, float* act_adj,

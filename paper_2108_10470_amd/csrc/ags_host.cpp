@@ -535,6 +535,10 @@ struct ags_sim {
   float* kp_dof = nullptr;  // device: drive stiffness of every DOF (target adjoints)
   double* mid_root = nullptr;  // set while a rollout recomputes: where the step writes substep states
   int* adj_retry = nullptr;    // device: count, then the environments the small adjoint layout could not hold
+  // rollout backward: a second stream (default priority) recomputes the next segment while the adjoint of
+  // the current one runs; events order the two segment buffers between the streams
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
   // persistent (fused) launch
   bool fused_ok = false;
   int* units = nullptr;  // device: (type, group) pairs
@@ -776,6 +780,11 @@ extern "C" void ags_sim_destroy(ags_sim* S) {
     if (T.scratch) (void)hipFree(T.scratch);
   }
   if (S->adj_retry) (void)hipFree(S->adj_retry);
+  for (int k = 0; k < 2; ++k) {
+    if (S->ev_ready[k]) (void)hipEventDestroy(S->ev_ready[k]);
+    if (S->ev_free[k]) (void)hipEventDestroy(S->ev_free[k]);
+  }
+  if (S->aux) (void)hipStreamDestroy(S->aux);
   if (S->env_tables) (void)hipFree(S->env_tables);
   if (S->units) (void)hipFree(S->units);
   if (S->kp_dof) (void)hipFree(S->kp_dof);
@@ -945,16 +954,25 @@ extern "C" int ags_rollout_state_size(const ags_sim* S, int64_t* floats) {
   return AGS_OK;
 }
 
+namespace {
+long long seg_one_bytes(const ags_sim* S, int every);
+}
+
 extern "C" int ags_rollout_seg_bytes(const ags_sim* S, int32_t every, int64_t* bytes) {
   if (!S || every < 1 || !bytes) return fail(AGS_E_ARG, "rollout_seg_bytes: bad arguments");
-  const long long sw = 13ll * S->n_actors_total + 2ll * S->n_dof_total;
-  const long long mid = (long long)every * std::max(0, S->params.substeps - 1) * sw;
-  *bytes = ((every + 1) * sw * (long long)sizeof(float) + 255) / 256 * 256 + mid * (long long)sizeof(double);
+  *bytes = 2 * seg_one_bytes(S, every);  // two segment buffers (recompute of one overlaps the adjoint of the other)
   return AGS_OK;
 }
 
 namespace {
 // one env-step on the given state arrays with the given control; the output tensors are not written
+// bytes of one segment buffer: every + 1 FP32 states (256-byte aligned), then every x (substeps - 1) FP64 states
+long long seg_one_bytes(const ags_sim* S, int every) {
+  const long long sw = 13ll * S->n_actors_total + 2ll * S->n_dof_total;
+  const long long mid = (long long)every * std::max(0, S->params.substeps - 1) * sw;
+  return (((every + 1) * sw * (long long)sizeof(float) + 255) / 256 * 256 + mid * (long long)sizeof(double) + 255) / 256 * 256;
+}
+
 int step_on(ags_sim* S, float* root, float* dof, int control, const float* ctrl, hipStream_t stream) {
   void* saved[AGS_NUM_TENSORS];
   std::memcpy(saved, S->bound, sizeof(saved));
@@ -1005,35 +1023,64 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
   const size_t nr = 13ull * S->n_actors_total, nd = 2ull * S->n_dof_total, sw = nr + nd;
   const size_t na = (size_t)S->n_dof_total;
   const int nmid = std::max(0, S->params.substeps - 1);
-  float* seg = static_cast<float*>(seg_bytes);  // every + 1 states, then every x nmid FP64 substep states
-  double* mid = reinterpret_cast<double*>(static_cast<char*>(seg_bytes) +
-                                          ((every + 1) * sw * sizeof(float) + 255) / 256 * 256);
   hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (!S->aux) {  // created on first use, on the sim's current device; default priority
+    if ((e = hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "rollout_backward: stream");
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+      e = hipEventCreateWithFlags(&S->ev_ready[k], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_free[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) return hip_fail(e, "rollout_backward: events");
+  }
+  // two segment buffers, each: every + 1 FP32 states, then every x nmid FP64 substep states
+  const long long one = seg_one_bytes(S, every);
+  float* seg[2];
+  double* mid[2];
+  for (int k = 0; k < 2; ++k) {
+    char* base = static_cast<char*>(seg_bytes) + k * one;
+    seg[k] = reinterpret_cast<float*>(base);
+    mid[k] = reinterpret_cast<double*>(base + ((every + 1) * sw * sizeof(float) + 255) / 256 * 256);
+  }
   const int n_seg = (n_steps + every - 1) / every;
-  for (int g = n_seg - 1; g >= 0; --g) {
-    const int t0 = g * every, t1 = std::min(n_steps, t0 + every);
-    hipError_t e = hipMemcpyAsync(seg, ckpt + (size_t)g * sw, sw * sizeof(float), hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "rollout_backward: copy");
-    // recompute the states before steps t0+1 .. t1-1 (the last step's end state is discarded) and the
-    // substep states of every step of the segment
+  // recompute segment g into buffer g % 2 on the auxiliary stream: the states before its steps (the last
+  // step's end state is discarded) and the substep states of every step
+  auto recompute = [&](int g) -> int {
+    const int b = g & 1, t0 = g * every, t1 = std::min(n_steps, t0 + every);
+    hipError_t e2;
+    if ((e2 = hipStreamWaitEvent(S->aux, S->ev_free[b], 0)) != hipSuccess) return hip_fail(e2, "rollout_backward: wait");
+    if ((e2 = hipMemcpyAsync(seg[b], ckpt + (size_t)g * sw, sw * sizeof(float), hipMemcpyDeviceToDevice, S->aux)) != hipSuccess)
+      return hip_fail(e2, "rollout_backward: copy");
     for (int t = t0; t < t1; ++t) {
-      float* a = seg + (size_t)(t - t0) * sw;
-      float* b = a + sw;
-      if ((e = hipMemcpyAsync(b, a, sw * sizeof(float), hipMemcpyDeviceToDevice, st)) != hipSuccess)
-        return hip_fail(e, "rollout_backward: copy");
-      S->mid_root = nmid ? mid + (size_t)(t - t0) * nmid * sw : nullptr;
-      const int rc = step_on(S, b, b + nr, control, actions + (size_t)t * na, st);
+      float* a = seg[b] + (size_t)(t - t0) * sw;
+      float* x = a + sw;
+      if ((e2 = hipMemcpyAsync(x, a, sw * sizeof(float), hipMemcpyDeviceToDevice, S->aux)) != hipSuccess)
+        return hip_fail(e2, "rollout_backward: copy");
+      S->mid_root = nmid ? mid[b] + (size_t)(t - t0) * nmid * sw : nullptr;
+      const int rc = step_on(S, x, x + nr, control, actions + (size_t)t * na, S->aux);
       S->mid_root = nullptr;
       if (rc != AGS_OK) return rc;
     }
+    if ((e2 = hipEventRecord(S->ev_ready[b], S->aux)) != hipSuccess) return hip_fail(e2, "rollout_backward: record");
+    return AGS_OK;
+  };
+  // both buffers start free once the caller's earlier work on the stream is done
+  for (int k = 0; k < 2; ++k)
+    if ((e = hipEventRecord(S->ev_free[k], st)) != hipSuccess) return hip_fail(e, "rollout_backward: record");
+  int rc = recompute(n_seg - 1);
+  if (rc != AGS_OK) return rc;
+  for (int g = n_seg - 1; g >= 0; --g) {
+    const int b = g & 1, t0 = g * every, t1 = std::min(n_steps, t0 + every);
+    if (g > 0 && (rc = recompute(g - 1)) != AGS_OK) return rc;  // overlaps the adjoints below
+    if ((e = hipStreamWaitEvent(st, S->ev_ready[b], 0)) != hipSuccess) return hip_fail(e, "rollout_backward: wait");
     for (int t = t1 - 1; t >= t0; --t) {
-      const float* x = seg + (size_t)(t - t0) * sw;
+      const float* x = seg[b] + (size_t)(t - t0) * sw;
       void* saved = S->bound[control];
       S->bound[control] = const_cast<float*>(actions + (size_t)t * na);
       // the actuation the step used: the per-step array or the bound tensor
       const float* act = (const float*)S->bound[AGS_DOF_ACTUATION];
-      S->mid_root = nmid ? mid + (size_t)(t - t0) * nmid * sw : nullptr;
-      int rc = ags_sim_step_backward(S, x, x + nr, act, root_adj, dof_adj, act_adj + (size_t)t * na, status, stream);
+      S->mid_root = nmid ? mid[b] + (size_t)(t - t0) * nmid * sw : nullptr;
+      rc = ags_sim_step_backward(S, x, x + nr, act, root_adj, dof_adj, act_adj + (size_t)t * na, status, stream);
       S->mid_root = nullptr;
       S->bound[control] = saved;
       if (rc == AGS_OK && control == AGS_DOF_POS_TARGET) {
@@ -1043,6 +1090,7 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
       }
       if (rc != AGS_OK) return rc;
     }
+    if ((e = hipEventRecord(S->ev_free[b], st)) != hipSuccess) return hip_fail(e, "rollout_backward: record");
   }
   return AGS_OK;
 }
