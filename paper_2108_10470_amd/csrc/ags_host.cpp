@@ -459,7 +459,7 @@ AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters, int 
   L.tI = take(3 * nl);
   L.nu = take(nv); L.qdd = take(nv); L.vs = take(nv); L.nu1 = take(nv); L.tau = take(nv); L.arm = take(nv);
   L.z = take(nv); L.w = take(nv); L.nub = take(nv); L.vsb = take(nv); L.nui = take(nv); L.tmp = take(nv);
-  L.colS = take(6 * nv); L.colY = take(6 * nv); L.colYv = take(6 * nv); L.cs = take(6 * nv);
+  L.cs = take(6 * nv);
   L.q = take(nd); L.qb = take(nd); L.ab = take(nd);
   L.state_words = 13 * na + 2 * info.n_dof;
   L.st = take((substeps + 1) * L.state_words);
@@ -468,10 +468,17 @@ AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters, int 
   L.Lm = take(nv * L.nvp);
   L.ldi = take(nv);
   L.rcp = rc | 1;
-  L.J = take(rc * L.nvp); L.W = take(rc * L.nvp); L.A = take(rc * (rc + 1) / 2); L.Ab = take(rc * (rc + 1) / 2);
+  // arrays with disjoint lifetimes in a reverse substep share words: W is dead once P is formed, when the
+  // mass-matrix terms' column vectors are written; A and S = Abar + Abar^T are dead after the reverse
+  // Gauss-Seidel and T = S W, when the rows' reverse arrays are written
+  L.J = take(rc * L.nvp);
+  L.W = take(std::max(rc * L.nvp, 18 * nv));
+  L.colS = L.W; L.colY = L.W + 6 * nv; L.colYv = L.W + 12 * nv;
+  const int ntri = rc * (rc + 1) / 2;
+  L.A = take(std::max(2 * ntri, 19 * rc)); L.Ab = L.A + ntri;
+  L.rxb = L.A; L.rdb = L.A + 3 * rc; L.rqb = L.A + 6 * rc; L.rwa = L.A + 7 * rc; L.rwb = L.A + 13 * rc;
   L.rbc = take(rc); L.rb = take(rc); L.rinvA = take(rc); L.rlam = take(rc); L.rybar = take(rc); L.rbbar = take(rc);
-  L.rqb = take(rc); L.rx = take(3 * rc); L.rcen = take(3 * rc); L.rd = take(3 * rc); L.rxb = take(3 * rc);
-  L.rdb = take(3 * rc); L.rwa = take(6 * rc); L.rwb = take(6 * rc);
+  L.rx = take(3 * rc); L.rcen = take(3 * rc); L.rd = take(3 * rc);
   L.hlo = take(iters * L.rcp); L.hres = take(iters * L.rcp);
   L.misc = take(8);
   L.n_real = (off + 1) & ~1;
