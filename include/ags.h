@@ -145,6 +145,9 @@ void ags_sim_destroy(ags_sim* sim);
  *   AGS_DOF_FORCE          (N_D, 1)   get      force applied at each DOF (actuation + drive), step average
  *   AGS_RIGID_BODY_STATE   (N_B, 13)  get      rigid-body states after the step (Table 1): link-frame origin,
  *                          orientation quaternion xyzw, velocity of the origin, angular velocity (world)
+ *   AGS_ENV_STATUS         (E, 1)  int32  get  per-env status of the last step: bit 0 the new state is not
+ *                          finite, bit 1 a substep had more than 32 rows (or a Jacobian row too long for the
+ *                          register form) and took the slower row-response path; failures never fail the call
  *   AGS_DEBUG_QDD_FREE     (E, substeps * max n_v)       unconstrained joint accelerations per substep
  *   AGS_DEBUG_ROW_COUNT    (E, substeps)  int32          constraint rows per substep
  *   AGS_DEBUG_ROW_KEY      (E, substeps * max rows) int32  row keys (kind << 24 | a << 8 | b)
@@ -161,7 +164,8 @@ void ags_sim_destroy(ags_sim* sim);
 enum {
   AGS_ROOT_STATE = 0, AGS_DOF_STATE, AGS_DOF_ACTUATION, AGS_DOF_POS_TARGET, AGS_DOF_VEL_TARGET,
   AGS_NET_CONTACT_FORCE, AGS_DOF_FORCE, AGS_DEBUG_QDD_FREE, AGS_DEBUG_ROW_COUNT, AGS_DEBUG_ROW_KEY,
-  AGS_DEBUG_ROW_LAMBDA, AGS_DEBUG_PHASE_CYCLES, AGS_DEBUG_ADJ_CYCLES, AGS_RIGID_BODY_STATE, AGS_NUM_TENSORS
+  AGS_DEBUG_ROW_LAMBDA, AGS_DEBUG_PHASE_CYCLES, AGS_DEBUG_ADJ_CYCLES, AGS_RIGID_BODY_STATE, AGS_ENV_STATUS,
+  AGS_NUM_TENSORS
 };
 int ags_sim_tensor_shape(const ags_sim* sim, int32_t which, int64_t* rows, int64_t* cols);
 /* Bind a device pointer (NULL unbinds).  The memory must hold rows x cols elements and stay valid

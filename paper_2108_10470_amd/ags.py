@@ -21,7 +21,7 @@ SHAPE = {"sphere": 0, "capsule": 1, "box": 2}
 
 ROOT_STATE, DOF_STATE, DOF_ACTUATION, DOF_POS_TARGET, DOF_VEL_TARGET, NET_CONTACT_FORCE, DOF_FORCE, \
     DEBUG_QDD_FREE, DEBUG_ROW_COUNT, DEBUG_ROW_KEY, DEBUG_ROW_LAMBDA, DEBUG_PHASE_CYCLES, DEBUG_ADJ_CYCLES, \
-    RIGID_BODY_STATE, NUM_TENSORS = range(15)
+    RIGID_BODY_STATE, ENV_STATUS, NUM_TENSORS = range(16)
 PHASES = ["controls", "forward", "inward", "outward", "vstar", "narrow", "rows", "responses", "pgs", "outputs"]
 
 
@@ -172,7 +172,7 @@ class Sim:
     def __init__(self, models: Sequence[Model], env_model: Sequence[int], params, device="cuda:0",
                  debug: bool = False, pd: bool = False, fp64: bool = False, phase_cycles: bool = False,
                  lanes_per_env: int = 0, persistent: bool = False, adjoint_precision: int = 0,
-                 rigid_body_state: bool = False):
+                 rigid_body_state: bool = False, status: bool = False):
         self.models = list(models)
         self.params = params
         self.device = torch.device(device)
@@ -199,6 +199,9 @@ class Sim:
         self.dof_force = self._alloc(DOF_FORCE, torch.zeros(shapes[DOF_FORCE][0], **f32))
         if rigid_body_state:
             self.rb_state = self._alloc(RIGID_BODY_STATE, torch.zeros(shapes[RIGID_BODY_STATE], **f32))
+        if status:
+            self.env_status = self._alloc(ENV_STATUS, torch.zeros(shapes[ENV_STATUS][0], dtype=torch.int32,
+                                                                  device=self.device))
         if pd:
             self.pos_target = self._alloc(DOF_POS_TARGET, torch.zeros(shapes[DOF_POS_TARGET][0], **f32))
             self.vel_target = self._alloc(DOF_VEL_TARGET, torch.zeros(shapes[DOF_VEL_TARGET][0], **f32))

@@ -809,6 +809,7 @@ extern "C" int ags_sim_tensor_shape(const ags_sim* S, int32_t which, int64_t* ro
       *rows = S->n_dof_total; *cols = 1; break;
     case AGS_NET_CONTACT_FORCE: *rows = S->n_bodies_total; *cols = 3; break;
     case AGS_RIGID_BODY_STATE: *rows = S->n_bodies_total; *cols = 13; break;
+    case AGS_ENV_STATUS: *rows = S->n_envs; *cols = 1; break;
     case AGS_DEBUG_QDD_FREE: *rows = S->n_envs; *cols = (int64_t)sub * S->max_nv; break;
     case AGS_DEBUG_ROW_COUNT: *rows = S->n_envs; *cols = sub; break;
     case AGS_DEBUG_ROW_KEY: case AGS_DEBUG_ROW_LAMBDA: *rows = S->n_envs; *cols = (int64_t)sub * std::max(1, S->max_rows); break;
@@ -842,6 +843,7 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
   a.vel_tgt = (const float*)S->bound[AGS_DOF_VEL_TARGET];
   a.contact_force = (float*)S->bound[AGS_NET_CONTACT_FORCE];
   a.rb_state = (float*)S->bound[AGS_RIGID_BODY_STATE];
+  a.env_status = (int*)S->bound[AGS_ENV_STATUS];
   a.dof_force = (float*)S->bound[AGS_DOF_FORCE];
   a.dbg_qdd = (float*)S->bound[AGS_DEBUG_QDD_FREE];
   a.dbg_qdd_stride = p.substeps * S->max_nv;

@@ -89,6 +89,7 @@ struct StepArgs {
   const float* vel_tgt;
   float* contact_force;
   float* rb_state;  // optional (N_B, 13): link origin, quaternion, origin velocity, angular velocity
+  int* env_status;  // optional (E): bit 0 non-finite new state, bit 1 row-response slow path taken
   float* dof_force;
   float* dbg_qdd;
   int dbg_qdd_stride, dbg_qdd_sub;  // per env, per substep (sim-wide maximum n_v)

@@ -697,6 +697,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       for (int q = 0; q < 6; ++q) s.qd[ai[AI_COL] + q] = s.root[13 * k + 7 + q];
   }
   R dof_force_acc = R(0);
+  bool slow_any = false;  // some substep took the row-response slow path
   __syncthreads();
   const V3<R> origin = ld3<R>(s.root);
   // optional per-phase clock accounting (lane 0; only when the debug tensor is bound)
@@ -1076,6 +1077,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     // Up to FR rows (one per lane) keep their Jacobian in registers (compact form) and W in LDS and are
     // solved in registers below; more rows (or rows too long for the compact form) go through global scratch.
     const bool fast = Rn <= FR && M.jfast;
+    slow_any = slow_any || !fast;
     if (!fast)
       for (int k = tt; k < Rn * nv; k += TEAM) Jg[k] = R(0);
     JRow<R> jr;  // fast path: this lane's row
@@ -1385,6 +1387,17 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       }
       __syncthreads();
     }
+  }
+
+  // ---------------------------------------------------------------- status word
+  // bit 0: the new state is not finite; bit 1: a substep took the row-response slow path
+  if (P.env_status) {
+    int bad = 0;
+    for (int k = tt; k < 13 * na; k += TEAM) bad |= !isfinite(s.root[k]);
+    for (int j = tt; j < nd; j += TEAM) bad |= !isfinite(s.qj[j]);
+    for (int c = tt; c < nv; c += TEAM) bad |= !isfinite(s.qd[c]);
+    const unsigned long long m = team_ballot<TEAM>(tm, bad);
+    if (valid && tt == 0) P.env_status[env] = (m != 0ull ? 1 : 0) | (slow_any ? 2 : 0);
   }
 
   // ---------------------------------------------------------------- write back

@@ -190,3 +190,35 @@ def test_persistent_launch_is_bitwise_equal_to_per_type_launches(fp64):
     for x, y in zip(*outs):
         assert torch.isfinite(x).all()
         assert torch.equal(x, y)
+
+
+def test_env_status_flags():
+    """Per-env status word of the step: bit 1 (row-response slow path) is set on every env-step whose
+    kept rows exceed the 32 of the register path (debug row count); bit 0 (non-finite new state) only for
+    the env whose root state was set to NaN; no other bits."""
+    env = W.env_humanoid()
+    E = 64
+    sim = ags.Sim([ags.Model(env)], [0] * E, W.SimParams(), device="cuda:0", fp64=True, debug=True, status=True)
+    root, dof = W.initial_state(env, E, 0)
+    sim.root_state.copy_(torch.tensor(root.reshape(-1, 13), dtype=torch.float32))
+    sim.dof_state.copy_(torch.tensor(dof.reshape(-1, 2), dtype=torch.float32))
+    acts = torch.tensor(W.actuation(env, E, 121, 0).reshape(121, -1), dtype=torch.float32, device="cuda:0")
+    slow_seen = 0
+    for t in range(121):  # standing, falling, lying: row counts from a few to more than 32
+        sim.bind(ags.DOF_ACTUATION, acts[t])
+        sim.step()
+        torch.cuda.synchronize()
+        st = sim.env_status.cpu().numpy()
+        rc = sim.dbg_rc.cpu().numpy().reshape(E, -1).max(axis=1)
+        assert ((st & ~3) == 0).all() and ((st & 1) == 0).all()
+        assert ((st & 2) != 0)[rc > 32].all(), (t, st, rc)
+        slow_seen += int(((st & 2) != 0).sum())
+    assert slow_seen > 0  # the slow path was exercised
+    r = sim.root_state.clone()
+    r[3, 0] = float("nan")
+    sim.root_state.copy_(r)
+    sim.step()
+    torch.cuda.synchronize()
+    st = sim.env_status.cpu().numpy()
+    assert st[3] & 1
+    assert ((np.delete(st, 3) & 1) == 0).all()
