@@ -216,3 +216,79 @@ def test_rollout_gradient_hand_targets(adj):
     assert on_path.sum() >= E // 2, d
     assert d["grad_abs_max"] > 0.0, d
     assert (worst <= 1.0).all(), d
+
+
+def _pendulum_env(l=0.7, r=0.05, armature=0.01):
+    bob = W.Link("bob", 0, "revolute", axis=(0.0, 1.0, 0.0), armature=armature,
+                 shapes=[W.Shape("sphere", (0.0, 0.0, -l), radius=r)])
+    return W.EnvSpec("pendulum", [W.Actor("p", [W.Link("base", -1, "fixed"), bob], root_pos=(0.0, 0.0, 2.0))], [])
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_pendulum_adjoint_analytic(fp64):
+    """Single pendulum (sphere bob on a massless rod, armature a, no contacts or limits): one env-step is two
+    semi-implicit substeps of qdd = (tau - m g l sin q) / (I + a), whose derivatives are written out here by
+    forward-mode differentiation; the adjoint's gradient of L = wq q' + wv qd' w.r.t. tau, q and qd must match."""
+    l, r, arm = 0.7, 0.05, 0.01
+    env = W.as_f32(_pendulum_env(l, r, arm))
+    params = W.params_f32(W.SimParams())
+    oe = A.O.OracleEnv(env)
+    m = float(oe.mass_props()[0][1])
+    f32 = lambda x: float(np.float32(x))
+    l32, r32 = f32(l), f32(r)
+    Mt = m * (l32 * l32 + 0.4 * r32 * r32) + f32(arm)
+    k = m * f32(9.81) * l32
+    h = params.dt / params.substeps
+    rng = np.random.default_rng(11)
+    E = 16
+    q0 = rng.uniform(-2.5, 2.5, E).astype(np.float32).astype(np.float64)
+    v0 = rng.uniform(-3.0, 3.0, E).astype(np.float32).astype(np.float64)
+    tau = rng.uniform(-2.0, 2.0, E).astype(np.float32).astype(np.float64)
+    wq = rng.standard_normal(E).astype(np.float32).astype(np.float64)
+    wv = rng.standard_normal(E).astype(np.float32).astype(np.float64)
+    # forward-mode derivatives of (q, v) w.r.t. (q0, v0, tau), substep by substep
+    q, v = q0.copy(), v0.copy()
+    dq = np.stack([np.ones(E), np.zeros(E), np.zeros(E)], 1)
+    dv = np.stack([np.zeros(E), np.ones(E), np.zeros(E)], 1)
+    for _ in range(params.substeps):
+        acc = (tau - k * np.sin(q)) / Mt
+        dacc = (-k * np.cos(q) / Mt)[:, None] * dq + np.stack([np.zeros(E), np.zeros(E), np.full(E, 1.0 / Mt)], 1)
+        v = v + h * acc
+        dv = dv + h * dacc
+        q = q + h * v
+        dq = dq + h * dv
+    expect = wq[:, None] * dq + wv[:, None] * dv  # columns: d/dq0, d/dv0, d/dtau
+    root = np.tile(np.array([0.0, 0.0, 2.0, 0.0, 0.0, 0.0, 1.0] + [0.0] * 6), (E, 1, 1))
+    dof = np.stack([q0, v0], 1)[:, None, :]
+    wr = np.zeros_like(root)
+    wd = np.stack([wq, wv], 1)[:, None, :]
+    g, status = A.gpu_grads(env, params, root, dof, tau[:, None], wr, wd, fp64)
+    assert (status == 0).all()
+    ent = A.entries(env)
+    got = np.stack([g[:, ent.index(("dof", (0, 0)))], g[:, ent.index(("dof", (0, 1)))], g[:, ent.index(("act", (0,)))]], 1)
+    rel = np.abs(got - expect) / (np.abs(expect) + 1e-12 * np.abs(expect).max())
+    _report(f"adjoint_pendulum_analytic_{'fp64' if fp64 else 'fp32'}", {"envs": E, "max_rel": float(rel.max())})
+    # the seeds and gradients cross the interface as FP32: a few FP32 ulps (6e-8) bound the FP64 adjoint
+    assert rel.max() <= (5e-7 if fp64 else 2e-5), rel.max()
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_adjoint_is_linear_in_the_seed(fp64):
+    """The step's adjoint is a linear map of the incoming adjoint: seeds a, b and 2a - 3b give gradients
+    g(a), g(b) and 2 g(a) - 3 g(b) (humanoid-like envs in contact)."""
+    env, params, oe, root, dof, act, _, _ = A.f32_inputs(W.env_humanoid(), W.SimParams(), 16, 80)
+    rng = np.random.default_rng(23)
+    # small integers: 2a - 3b is exact in FP32, so the only rounding is that of the FP32 gradients
+    wr, wr2 = (rng.integers(-4, 5, root.shape).astype(np.float64) for _ in range(2))
+    wd, wd2 = (rng.integers(-4, 5, dof.shape).astype(np.float64) for _ in range(2))
+    ga, sa = A.gpu_grads(env, params, root, dof, act, wr, wd, fp64)
+    gb, sb = A.gpu_grads(env, params, root, dof, act, wr2, wd2, fp64)
+    gc, sc = A.gpu_grads(env, params, root, dof, act, 2 * wr - 3 * wr2, 2 * wd - 3 * wd2, fp64)
+    assert (sa == 0).all() and (sb == 0).all() and (sc == 0).all()
+    lin = 2 * ga - 3 * gb
+    scale = np.abs(lin).max(axis=1, keepdims=True)
+    err = (np.abs(gc - lin) / scale).max()
+    _report(f"adjoint_linearity_{'fp64' if fp64 else 'fp32'}", {"envs": 16, "max_err_over_scale": float(err)})
+    # FP64 adjoint: each gradient is rounded to FP32 (6e-8 relative) and 2 g(a) - 3 g(b) carries ~5 such
+    # roundings; FP32 adjoint: its own rounding, bounded like the finite-difference checks (FLOOR)
+    assert err <= (1e-6 if fp64 else FLOOR[False]), err
