@@ -1531,6 +1531,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
   E.nlev = P.m.n_levels;
   E.rc = L.rows_cap;
   const int env = P.env_list[ei];
+  if (P.big_rows && (P.big_rows[env] != 0) != (P.big_mode == 2)) return;  // the other pass runs this env
   E.abase = P.env_actor_base[env];
   E.dbase = P.env_dof_base[env];
   E.h = R(P.h);

@@ -546,6 +546,12 @@ struct ags_sim {
   // the current one runs; events order the two segment buffers between the streams
   hipStream_t aux = nullptr;
   hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
+  // the recomputation flags environments with many rows (big_out, per step); their adjoints then run with the
+  // full layout on a third stream beside the small-layout pass (adj_big: this step's flags, or none)
+  int* big_out = nullptr;
+  const int* adj_big = nullptr;
+  hipStream_t aux2 = nullptr;
+  hipEvent_t ev_big_start = nullptr, ev_big_done = nullptr;
   // persistent (fused) launch
   bool fused_ok = false;
   int* units = nullptr;  // device: (type, group) pairs
@@ -792,6 +798,9 @@ extern "C" void ags_sim_destroy(ags_sim* S) {
     if (S->ev_free[k]) (void)hipEventDestroy(S->ev_free[k]);
   }
   if (S->aux) (void)hipStreamDestroy(S->aux);
+  if (S->ev_big_start) (void)hipEventDestroy(S->ev_big_start);
+  if (S->ev_big_done) (void)hipEventDestroy(S->ev_big_done);
+  if (S->aux2) (void)hipStreamDestroy(S->aux2);
   if (S->env_tables) (void)hipFree(S->env_tables);
   if (S->units) (void)hipFree(S->units);
   if (S->kp_dof) (void)hipFree(S->kp_dof);
@@ -844,6 +853,7 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
   a.contact_force = (float*)S->bound[AGS_NET_CONTACT_FORCE];
   a.rb_state = (float*)S->bound[AGS_RIGID_BODY_STATE];
   a.env_status = (int*)S->bound[AGS_ENV_STATUS];
+  a.big_rows = S->big_out;
   a.dof_force = (float*)S->bound[AGS_DOF_FORCE];
   a.dbg_qdd = (float*)S->bound[AGS_DEBUG_QDD_FREE];
   a.dbg_qdd_stride = p.substeps * S->max_nv;
@@ -945,9 +955,25 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
       AdjArgs a2 = a;
       a2.env_list = S->adj_retry + 1;
       a2.list_count = S->adj_retry;
-      if ((e = launch_zero_count(S->adj_retry, (hipStream_t)stream)) == hipSuccess &&
-          (e = launch_adjoint(a1, T.n_envs, adj_fp64(p), (hipStream_t)stream)) == hipSuccess)
-        e = launch_adjoint(a2, T.n_envs, adj_fp64(p), (hipStream_t)stream);
+      const hipStream_t st = (hipStream_t)stream;
+      if (S->adj_big) {
+        // environments the forward flagged run with the full layout on the third stream, concurrently with
+        // pass 1 (which skips them); the caller's stream waits for them before its next work
+        a1.big_rows = S->adj_big;
+        a1.big_mode = 1;
+        AdjArgs ab = a;
+        ab.big_rows = S->adj_big;
+        ab.big_mode = 2;
+        if ((e = hipEventRecord(S->ev_big_start, st)) == hipSuccess &&
+            (e = hipStreamWaitEvent(S->aux2, S->ev_big_start, 0)) == hipSuccess &&
+            (e = launch_adjoint(ab, T.n_envs, adj_fp64(p), S->aux2)) == hipSuccess)
+          e = hipEventRecord(S->ev_big_done, S->aux2);
+        if (e != hipSuccess) return hip_fail(e, "step_backward: flagged pass");
+      }
+      if ((e = launch_zero_count(S->adj_retry, st)) == hipSuccess &&
+          (e = launch_adjoint(a1, T.n_envs, adj_fp64(p), st)) == hipSuccess)
+        e = launch_adjoint(a2, T.n_envs, adj_fp64(p), st);
+      if (e == hipSuccess && S->adj_big) e = hipStreamWaitEvent(st, S->ev_big_done, 0);
     } else {
       e = launch_adjoint(a, T.n_envs, adj_fp64(p), (hipStream_t)stream);
     }
@@ -975,11 +1001,14 @@ extern "C" int ags_rollout_seg_bytes(const ags_sim* S, int32_t every, int64_t* b
 
 namespace {
 // one env-step on the given state arrays with the given control; the output tensors are not written
-// bytes of one segment buffer: every + 1 FP32 states (256-byte aligned), then every x (substeps - 1) FP64 states
+// bytes of one segment buffer: every + 1 FP32 states (256-byte aligned), then every x (substeps - 1) FP64
+// states, then every x n_envs row-count flags
 long long seg_one_bytes(const ags_sim* S, int every) {
   const long long sw = 13ll * S->n_actors_total + 2ll * S->n_dof_total;
   const long long mid = (long long)every * std::max(0, S->params.substeps - 1) * sw;
-  return (((every + 1) * sw * (long long)sizeof(float) + 255) / 256 * 256 + mid * (long long)sizeof(double) + 255) / 256 * 256;
+  const long long flags = ((long long)every * S->n_envs * (long long)sizeof(int) + 255) / 256 * 256;
+  return (((every + 1) * sw * (long long)sizeof(float) + 255) / 256 * 256 + mid * (long long)sizeof(double) + 255) / 256 * 256 +
+         flags;
 }
 
 int step_on(ags_sim* S, float* root, float* dof, int control, const float* ctrl, hipStream_t stream) {
@@ -1040,16 +1069,24 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
       e = hipEventCreateWithFlags(&S->ev_ready[k], hipEventDisableTiming);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_free[k], hipEventDisableTiming);
     }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->aux2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_big_start, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_big_done, hipEventDisableTiming);
     if (e != hipSuccess) return hip_fail(e, "rollout_backward: events");
   }
-  // two segment buffers, each: every + 1 FP32 states, then every x nmid FP64 substep states
+  // two segment buffers, each: every + 1 FP32 states, then every x nmid FP64 substep states, then every x
+  // n_envs flags
   const long long one = seg_one_bytes(S, every);
+  const size_t states_bytes = ((every + 1) * sw * sizeof(float) + 255) / 256 * 256;
+  const size_t mid_bytes = ((size_t)every * nmid * sw * sizeof(double) + 255) / 256 * 256;
   float* seg[2];
   double* mid[2];
+  int* flags[2];
   for (int k = 0; k < 2; ++k) {
     char* base = static_cast<char*>(seg_bytes) + k * one;
     seg[k] = reinterpret_cast<float*>(base);
-    mid[k] = reinterpret_cast<double*>(base + ((every + 1) * sw * sizeof(float) + 255) / 256 * 256);
+    mid[k] = reinterpret_cast<double*>(base + states_bytes);
+    flags[k] = reinterpret_cast<int*>(base + states_bytes + mid_bytes);
   }
   const int n_seg = (n_steps + every - 1) / every;
   // recompute segment g into buffer g % 2 on the auxiliary stream: the states before its steps (the last
@@ -1066,8 +1103,10 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
       if ((e2 = hipMemcpyAsync(x, a, sw * sizeof(float), hipMemcpyDeviceToDevice, S->aux)) != hipSuccess)
         return hip_fail(e2, "rollout_backward: copy");
       S->mid_root = nmid ? mid[b] + (size_t)(t - t0) * nmid * sw : nullptr;
+      S->big_out = flags[b] + (size_t)(t - t0) * S->n_envs;
       const int rc = step_on(S, x, x + nr, control, actions + (size_t)t * na, S->aux);
       S->mid_root = nullptr;
+      S->big_out = nullptr;
       if (rc != AGS_OK) return rc;
     }
     if ((e2 = hipEventRecord(S->ev_ready[b], S->aux)) != hipSuccess) return hip_fail(e2, "rollout_backward: record");
@@ -1089,8 +1128,10 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
       // the actuation the step used: the per-step array or the bound tensor
       const float* act = (const float*)S->bound[AGS_DOF_ACTUATION];
       S->mid_root = nmid ? mid[b] + (size_t)(t - t0) * nmid * sw : nullptr;
+      S->adj_big = flags[b] + (size_t)(t - t0) * S->n_envs;
       rc = ags_sim_step_backward(S, x, x + nr, act, root_adj, dof_adj, act_adj + (size_t)t * na, status, stream);
       S->mid_root = nullptr;
+      S->adj_big = nullptr;
       S->bound[control] = saved;
       if (rc == AGS_OK && control == AGS_DOF_POS_TARGET) {
         // the target enters the step only through tau = ... + kp q*: dL/dq* = kp dL/dtau

@@ -90,6 +90,7 @@ struct StepArgs {
   float* contact_force;
   float* rb_state;  // optional (N_B, 13): link origin, quaternion, origin velocity, angular velocity
   int* env_status;  // optional (E): bit 0 non-finite new state, bit 1 row-response slow path taken
+  int* big_rows;    // optional (E): 1 where a substep had more than kAdjBigRowsAt rows (adjoint layout hint)
   float* dof_force;
   float* dbg_qdd;
   int dbg_qdd_stride, dbg_qdd_sub;  // per env, per substep (sim-wide maximum n_v)
@@ -123,6 +124,7 @@ hipError_t fused_blocks_per_cu(int fp64, int team, size_t lds_bytes, int* blocks
 // ---------------------------------------------------------------- adjoint of one env-step
 constexpr int kAdjRows = 64;   // constraint rows per substep the adjoint handles (one lane each)
 constexpr int kAdjSmallRows = 32;  // row capacity of the first, smaller-LDS adjoint pass
+constexpr int kAdjBigRowsAt = 29;  // rows above which the forward flags an env for the larger layout (one contact's margin)
 constexpr int kAdjIters = 32;  // Gauss-Seidel sweeps the adjoint's tape holds
 constexpr int kAdjPhases = 8;
 
@@ -170,6 +172,8 @@ struct AdjArgs {
   int* retry;              // optional: environments whose rows exceed this layout's capacity are appended here
   int* retry_count;        //   (count at *retry_count) instead of being written with a zero adjoint
   const int* list_count;   // optional: number of valid entries of env_list (device), for a launch over a retry list
+  const int* big_rows;     // optional (indexed by env): the forward's flag of envs with many rows
+  int big_mode;            // with big_rows: 1 skip flagged envs, 2 run only flagged envs
   double h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
 };

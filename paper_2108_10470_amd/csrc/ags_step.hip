@@ -698,6 +698,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   }
   R dof_force_acc = R(0);
   bool slow_any = false;  // some substep took the row-response slow path
+  int rows_max = 0;       // most rows of a substep
   __syncthreads();
   const V3<R> origin = ld3<R>(s.root);
   // optional per-phase clock accounting (lane 0; only when the debug tensor is bound)
@@ -1078,6 +1079,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     // solved in registers below; more rows (or rows too long for the compact form) go through global scratch.
     const bool fast = Rn <= FR && M.jfast;
     slow_any = slow_any || !fast;
+    rows_max = max(rows_max, Rn);
     if (!fast)
       for (int k = tt; k < Rn * nv; k += TEAM) Jg[k] = R(0);
     JRow<R> jr;  // fast path: this lane's row
@@ -1399,6 +1401,8 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     const unsigned long long m = team_ballot<TEAM>(tm, bad);
     if (valid && tt == 0) P.env_status[env] = (m != 0ull ? 1 : 0) | (slow_any ? 2 : 0);
   }
+
+  if (P.big_rows && valid && tt == 0) P.big_rows[env] = rows_max > kAdjBigRowsAt ? 1 : 0;
 
   // ---------------------------------------------------------------- write back
   if (!valid) return;

@@ -135,14 +135,35 @@ def test_rollout_gradient_ant(adj):
     assert (worst <= 1.0).all(), d
 
 
+def _humanoid_rows_case(T=8):
+    """Humanoid-like envs lying on the ground after 120 oracle steps: the 12 with the most constraint rows
+    at the next step (more than the first adjoint pass holds) and the 4 with the fewest."""
+    env, params, oe, root, dof, _, _, _ = A.f32_inputs(W.env_humanoid(), W.SimParams(), 128, 120)
+    r32 = lambda x: x.astype(np.float32).astype(np.float64)
+    acts = r32(W.actuation(env, 128, T, 3))
+    rc = oe.step(params, root, dof, acts[0])["row_count"].reshape(128, -1).max(axis=1)
+    order = np.argsort(-rc, kind="stable")
+    pick = np.concatenate([order[:12], order[-4:]])
+    assert rc[pick].max() > 32 and rc[pick].min() <= 29, rc[pick]
+    return env, params, oe, root[pick], dof[pick], acts[:, pick]
+
+
+@pytest.mark.parametrize("case", ["ant", "humanoid_many_rows"])
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
-def test_rollout_equals_chained_step_adjoints(fp64):
+def test_rollout_equals_chained_step_adjoints(fp64, case):
     """The checkpointed rollout's gradient (segments recomputed from checkpoints, each step's adjoint
     starting from the substep states the recomputing forward step kept) equals the chain of single-step
     adjoints over the stored forward states (which recompute those substep states themselves) to
-    rounding: a slip in the checkpoint/segment bookkeeping would be of the size of the gradient."""
-    E, T, every = 16, 16, 4
-    env, params, oe, root, dof, acts = _ant_rollout_case(E, T)
+    rounding: a slip in the checkpoint/segment bookkeeping would be of the size of the gradient.  In the
+    rollout, envs whose recomputed step had many rows run their adjoint in a separate full-layout launch
+    beside the small-layout one; the humanoid case, with envs on both sides of that split, checks that
+    this routing changes nothing."""
+    if case == "ant":
+        E, T, every = 16, 16, 4
+        env, params, oe, root, dof, acts = _ant_rollout_case(E, T)
+    else:
+        E, T, every = 16, 8, 4
+        env, params, oe, root, dof, acts = _humanoid_rows_case(T)
     g, _ = A.gpu_rollout_grad(env, params, root, dof, acts, every, fp64)
     roots, dofs = A.gpu_trajectory(env, params, root, dof, acts, fp64)
     roots, dofs = roots[:T], dofs[:T]
