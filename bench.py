@@ -68,7 +68,10 @@ def parse():
     ap.add_argument("--no-rows", action="store_true", help="skip the replay that measures mean active rows")
     ap.add_argument("--no-fwd-bwd", action="store_true", help="skip the forward+adjoint rollout measurement")
     ap.add_argument("--fwd-bwd-steps", type=int, default=64)
-    ap.add_argument("--fwd-bwd-every", type=int, default=16)
+    ap.add_argument("--fwd-bwd-every", type=int, default=0,
+                    help="checkpoint interval of the headline forward+adjoint rollout; 0 stores the whole tape")
+    ap.add_argument("--fwd-bwd-ckpt-every", type=int, default=16,
+                    help="checkpoint interval of the secondary (recomputing) forward+adjoint measurement")
     ap.add_argument("--fwd-bwd-reps", type=int, default=3)
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous-batch measurement")
     ap.add_argument("--hetero-envs", type=int, default=16384)
@@ -155,7 +158,8 @@ def mean_rows(env, params, n_envs, steps, fp64, actions_dev, root0, dof0):
 
 def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, adjoint_precision=0, control=None):
     """Forward rollout of T = len(actions) steps with a checkpoint every `every` steps, then the reverse
-    pass (segment recomputation + adjoint of every step) for L = sum of final root x positions.  control:
+    pass (segment recomputation + adjoint of every step) for L = sum of final root x positions; with
+    every = 0 the forward pass stores the whole tape and the reverse pass recomputes nothing.  control:
     the per-step control the actions drive (DOF actuation, or PD position targets)."""
     import ctypes
     import torch
@@ -168,10 +172,15 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, ad
     n = ctypes.c_int64()
     L.ags_rollout_state_size(sim.h, ctypes.byref(n))
     f32 = dict(dtype=torch.float32, device="cuda:0")
-    ckpt = torch.empty(((T + every - 1) // every, n.value), **f32)
     nb = ctypes.c_int64()
-    L.ags_rollout_seg_bytes(sim.h, every, ctypes.byref(nb))
-    seg = torch.empty(nb.value, dtype=torch.uint8, device="cuda:0")
+    if every == 0:
+        ags._check(L.ags_rollout_tape_bytes(sim.h, T, ctypes.byref(nb)), "rollout_tape_bytes")
+        tape = torch.empty(nb.value, dtype=torch.uint8, device="cuda:0")
+        ckpt = tape[:4 * n.value].view(torch.float32).view(1, n.value)  # the state before step 0
+    else:
+        ckpt = torch.empty(((T + every - 1) // every, n.value), **f32)
+        ags._check(L.ags_rollout_seg_bytes(sim.h, every, ctypes.byref(nb)), "rollout_seg_bytes")
+        seg = torch.empty(nb.value, dtype=torch.uint8, device="cuda:0")
     root_adj = torch.empty_like(sim.root_state)
     dof_adj = torch.empty_like(sim.dof_state)
     act_adj = torch.empty_like(actions)
@@ -184,14 +193,21 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, ad
         sim.root_state.copy_(root0)
         sim.dof_state.copy_(dof0)
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-        e0.record(stream)
-        ags._check(L.ags_rollout_forward(sim.h, T, every, control, P(actions), P(ckpt), sp), "rollout_forward")
-        e1.record(stream)
         root_adj.zero_()
         root_adj[:, 0] = 1.0
         dof_adj.zero_()
-        ags._check(L.ags_rollout_backward(sim.h, T, every, control, P(actions), P(ckpt), P(seg), P(root_adj), P(dof_adj),
-                                          P(act_adj), P(status), sp), "rollout_backward")
+        e0.record(stream)
+        if every == 0:
+            ags._check(L.ags_rollout_forward_tape(sim.h, T, control, P(actions), P(tape), sp), "rollout_forward_tape")
+        else:
+            ags._check(L.ags_rollout_forward(sim.h, T, every, control, P(actions), P(ckpt), sp), "rollout_forward")
+        e1.record(stream)
+        if every == 0:
+            ags._check(L.ags_rollout_backward_tape(sim.h, T, control, P(actions), P(tape), P(root_adj), P(dof_adj),
+                                                   P(act_adj), P(status), sp), "rollout_backward_tape")
+        else:
+            ags._check(L.ags_rollout_backward(sim.h, T, every, control, P(actions), P(ckpt), P(seg), P(root_adj),
+                                              P(dof_adj), P(act_adj), P(status), sp), "rollout_backward")
         e2.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1), e1.elapsed_time(e2)
@@ -211,7 +227,8 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, ad
         b.record(stream)
     torch.cuda.synchronize()
     adj_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    return {"value": n_envs * T / ((fwd + bwd) / 1e3), "unit": "env-steps/s", "steps": T, "checkpoint_every": every,
+    return {"value": n_envs * T / ((fwd + bwd) / 1e3), "unit": "env-steps/s", "steps": T,
+            "checkpoint_every": every if every else "none: whole tape stored in the forward pass",
             "ms_forward": fwd, "ms_backward": bwd, "adjoint_launch_ms": adj_ms,
             "envs_over_row_capacity": int((status != 0).sum()), "finite": bool(torch.isfinite(act_adj).all()),
             "grad_abs_mean": float(act_adj.abs().mean()), "dtype": "f64" if fp64 else "f32",
@@ -405,6 +422,12 @@ def main():
                            args.fwd_bwd_reps, adjoint_precision=64)
         print(f"[bench] fwd+bwd ({head} forward, f64 adjoint): {json.dumps(fb64)}", file=sys.stderr, flush=True)
         fwd_bwd["f64_adjoint"] = {k: fb64[k] for k in ("value", "ms_forward", "ms_backward", "adjoint_launch_ms")}
+        if args.fwd_bwd_ckpt_every != args.fwd_bwd_every:
+            fbc = run_fwd_bwd(env, params, E, head == "fp64", acts_fb, root0, dof0, args.fwd_bwd_ckpt_every,
+                              args.fwd_bwd_reps, adjoint_precision=32)
+            print(f"[bench] fwd+bwd ({head} forward, f32 adjoint, checkpoints every {args.fwd_bwd_ckpt_every}): "
+                  f"{json.dumps(fbc)}", file=sys.stderr, flush=True)
+            fwd_bwd["checkpointed"] = {k: fbc[k] for k in ("value", "checkpoint_every", "ms_forward", "ms_backward")}
     h = res[head]
     value = E * K / (h["total_ms"] / 1e3)
     t_launch = float(h["launch_ms"].mean()) / 1e3

@@ -234,6 +234,24 @@ int ags_rollout_backward(ags_sim* sim, int32_t n_steps, int32_t every, int32_t c
                          const float* ckpt, void* seg, float* root_adj, float* dof_adj, float* act_adj,
                          int32_t* status, void* hip_stream);
 
+/* Rollouts with a stored tape: the forward pass keeps everything the reverse pass needs, which then
+ * recomputes nothing (the store-everything end of the checkpointing trade-off, for when memory allows:
+ * about 660 B per humanoid env-step at two substeps).  The tape (device, caller-owned,
+ * ags_rollout_tape_bytes(sim, n_steps) bytes, 256-byte aligned parts) holds the FP32 state before every
+ * step, the FP64 state at the start of every non-first substep of every step, and a per-env flag of
+ * steps with many constraint rows (which adjoint layout to use).  ags_rollout_forward_tape advances the
+ * bound state tensors like ags_rollout_forward (same actions and control conventions, output tensors
+ * written by every step); ags_rollout_backward_tape, with the same n_steps, control, actions and tape,
+ * returns the same adjoints as ags_rollout_backward (root_adj / dof_adj in-out, act_adj, status), bit
+ * for bit, since the stored states are the ones a recomputation would produce.  The tape is read only;
+ * flagged envs' adjoints run on a stream the sim owns, joined into hip_stream after every step. */
+int ags_rollout_tape_bytes(const ags_sim* sim, int32_t n_steps, int64_t* bytes);
+int ags_rollout_forward_tape(ags_sim* sim, int32_t n_steps, int32_t control, const float* actions, void* tape,
+                             void* hip_stream);
+int ags_rollout_backward_tape(ags_sim* sim, int32_t n_steps, int32_t control, const float* actions,
+                              const void* tape, float* root_adj, float* dof_adj, float* act_adj, int32_t* status,
+                              void* hip_stream);
+
 /* Copy rows of src (same shape as the bound tensor) into the bound root / DOF state tensor for the
  * actors listed in actor_idx (device int32 array of n global actor indices; NULL = all actors).
  * Setting a root teleports the actor without changing its DOF poses; setting DOFs leaves roots

@@ -93,6 +93,9 @@ def lib():
                                    vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
         L.ags_rollout_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp]
         L.ags_rollout_backward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ags_rollout_tape_bytes.argtypes = [vp, i32, i64p]
+        L.ags_rollout_forward_tape.argtypes = [vp, i32, i32, vp, vp, vp]
+        L.ags_rollout_backward_tape.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -101,7 +104,7 @@ EXPORTED = ["ags_last_error", "ags_model_create", "ags_model_destroy", "ags_mode
             "ags_sim_create", "ags_sim_destroy", "ags_sim_tensor_shape", "ags_sim_bind", "ags_sim_step",
             "ags_sim_set_root_state_indexed", "ags_sim_set_dof_state_indexed", "ags_sim_step_backward",
             "ags_rollout_state_size", "ags_rollout_forward", "ags_rollout_backward", "ags_autotune",
-            "ags_rollout_seg_bytes"]
+            "ags_rollout_seg_bytes", "ags_rollout_tape_bytes", "ags_rollout_forward_tape", "ags_rollout_backward_tape"]
 
 
 def _check(rc: int, what: str):
@@ -275,24 +278,35 @@ class Sim:
 
 class Rollout(torch.autograd.Function):
     """Differentiable rollout: final (root_state, dof_state) after T env-steps of `sim` from (root0, dof0)
-    with actions (T, N_D).  The forward pass keeps the state every `every` steps; the backward pass
-    recomputes each segment from its checkpoint and runs the adjoint of every step in reverse
-    (ags_rollout_forward / ags_rollout_backward).  Gradients flow to the actions and the initial state."""
+    with actions (T, N_D).  With every >= 1 the forward pass keeps the state every `every` steps and the
+    backward pass recomputes each segment from its checkpoint (ags_rollout_forward / ags_rollout_backward);
+    with every = 0 the forward pass stores the whole tape and the backward pass recomputes nothing
+    (ags_rollout_forward_tape / ags_rollout_backward_tape).  Either way the adjoint of every step runs in
+    reverse; gradients flow to the actions and the initial state."""
 
     @staticmethod
     def forward(ctx, actions, root0, dof0, sim, every, control=DOF_ACTUATION):
         T = actions.shape[0]
         actions = actions.contiguous()
         sim._dev_f32(actions, (T, sim.shapes[DOF_ACTUATION][0]), "actions")
+        if every < 0:
+            raise ValueError("every must be >= 1 (checkpoints) or 0 (stored tape)")
         sim.root_state.copy_(root0)
         sim.dof_state.copy_(dof0)
         n = ctypes.c_int64()
-        _check(lib().ags_rollout_state_size(sim.h, ctypes.byref(n)), "ags_rollout_state_size")
-        ckpt = torch.empty(((T + every - 1) // every, n.value), dtype=torch.float32, device=sim.device)
         s = torch.cuda.current_stream(sim.device)
-        _check(lib().ags_rollout_forward(sim.h, T, every, control, ctypes.c_void_p(actions.data_ptr()),
-                                         ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(s.cuda_stream)),
-               "ags_rollout_forward")
+        if every == 0:
+            _check(lib().ags_rollout_tape_bytes(sim.h, T, ctypes.byref(n)), "ags_rollout_tape_bytes")
+            ckpt = torch.empty(n.value, dtype=torch.uint8, device=sim.device)
+            _check(lib().ags_rollout_forward_tape(sim.h, T, control, ctypes.c_void_p(actions.data_ptr()),
+                                                  ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(s.cuda_stream)),
+                   "ags_rollout_forward_tape")
+        else:
+            _check(lib().ags_rollout_state_size(sim.h, ctypes.byref(n)), "ags_rollout_state_size")
+            ckpt = torch.empty(((T + every - 1) // every, n.value), dtype=torch.float32, device=sim.device)
+            _check(lib().ags_rollout_forward(sim.h, T, every, control, ctypes.c_void_p(actions.data_ptr()),
+                                             ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(s.cuda_stream)),
+                   "ags_rollout_forward")
         ctx.save_for_backward(actions, ckpt)
         ctx.sim, ctx.every, ctx.state_words, ctx.control = sim, every, n.value, control
         return sim.root_state.clone(), sim.dof_state.clone()
@@ -305,16 +319,25 @@ class Rollout(torch.autograd.Function):
         root_adj = (g_root if g_root is not None else torch.zeros_like(sim.root_state)).float().contiguous().clone()
         dof_adj = (g_dof if g_dof is not None else torch.zeros_like(sim.dof_state)).float().contiguous().clone()
         act_adj = torch.empty_like(actions)
-        nb = ctypes.c_int64()
-        _check(lib().ags_rollout_seg_bytes(sim.h, every, ctypes.byref(nb)), "ags_rollout_seg_bytes")
-        seg = torch.empty(nb.value, dtype=torch.uint8, device=sim.device)
         status = torch.zeros(sim.n_envs, dtype=torch.int32, device=sim.device)
         s = torch.cuda.current_stream(sim.device)
-        _check(lib().ags_rollout_backward(sim.h, T, every, ctx.control, ctypes.c_void_p(actions.data_ptr()),
-                                          ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(seg.data_ptr()),
-                                          ctypes.c_void_p(root_adj.data_ptr()), ctypes.c_void_p(dof_adj.data_ptr()),
-                                          ctypes.c_void_p(act_adj.data_ptr()), ctypes.c_void_p(status.data_ptr()),
-                                          ctypes.c_void_p(s.cuda_stream)), "ags_rollout_backward")
+        if every == 0:
+            _check(lib().ags_rollout_backward_tape(sim.h, T, ctx.control, ctypes.c_void_p(actions.data_ptr()),
+                                                   ctypes.c_void_p(ckpt.data_ptr()),
+                                                   ctypes.c_void_p(root_adj.data_ptr()),
+                                                   ctypes.c_void_p(dof_adj.data_ptr()),
+                                                   ctypes.c_void_p(act_adj.data_ptr()),
+                                                   ctypes.c_void_p(status.data_ptr()),
+                                                   ctypes.c_void_p(s.cuda_stream)), "ags_rollout_backward_tape")
+        else:
+            nb = ctypes.c_int64()
+            _check(lib().ags_rollout_seg_bytes(sim.h, every, ctypes.byref(nb)), "ags_rollout_seg_bytes")
+            seg = torch.empty(nb.value, dtype=torch.uint8, device=sim.device)
+            _check(lib().ags_rollout_backward(sim.h, T, every, ctx.control, ctypes.c_void_p(actions.data_ptr()),
+                                              ctypes.c_void_p(ckpt.data_ptr()), ctypes.c_void_p(seg.data_ptr()),
+                                              ctypes.c_void_p(root_adj.data_ptr()), ctypes.c_void_p(dof_adj.data_ptr()),
+                                              ctypes.c_void_p(act_adj.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                                              ctypes.c_void_p(s.cuda_stream)), "ags_rollout_backward")
         bad = int((status != 0).sum())
         if bad:
             raise RuntimeError(f"adjoint: {bad} environments exceeded the adjoint's row capacity (64 rows per substep)")
@@ -323,8 +346,9 @@ class Rollout(torch.autograd.Function):
 
 def rollout(sim: "Sim", actions: torch.Tensor, root0: torch.Tensor, dof0: torch.Tensor, every: int = 16,
             control: int = DOF_ACTUATION):
-    """Differentiable T-step rollout (see Rollout); `control` selects what actions[t] drives: the
-    actuation (DOF_ACTUATION) or the PD position targets (DOF_POS_TARGET)."""
+    """Differentiable T-step rollout (see Rollout): checkpoints every `every` steps, or the whole tape
+    stored with every = 0; `control` selects what actions[t] drives: the actuation (DOF_ACTUATION) or the
+    PD position targets (DOF_POS_TARGET)."""
     return Rollout.apply(actions, root0, dof0, sim, every, control)
 
 

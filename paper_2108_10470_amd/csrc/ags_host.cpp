@@ -546,8 +546,8 @@ struct ags_sim {
   // the current one runs; events order the two segment buffers between the streams
   hipStream_t aux = nullptr;
   hipEvent_t ev_ready[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
-  // the recomputation flags environments with many rows (big_out, per step); their adjoints then run with the
-  // full layout on a third stream beside the small-layout pass (adj_big: this step's flags, or none)
+  // the forward flags environments with many rows (big_out, per step); their adjoints then run with the full
+  // layout on a third stream beside the small-layout pass (adj_big: this step's flags, or none)
   int* big_out = nullptr;
   const int* adj_big = nullptr;
   hipStream_t aux2 = nullptr;
@@ -1022,6 +1022,61 @@ int step_on(ags_sim* S, float* root, float* dof, int control, const float* ctrl,
   std::memcpy(S->bound, saved, sizeof(saved));
   return rc;
 }
+
+// the adjoints of steps t1-1 down to t0 of a segment: x holds the FP32 state before each of its steps,
+// mid the FP64 substep states and flags the row-count flags of each step (both from the step's forward)
+int reverse_steps(ags_sim* S, int t0, int t1, int control, const float* actions, const float* x, const double* mid,
+                  const int* flags, float* root_adj, float* dof_adj, float* act_adj, int32_t* status, hipStream_t st) {
+  const size_t nr = 13ull * S->n_actors_total, sw = nr + 2ull * S->n_dof_total;
+  const size_t na = (size_t)S->n_dof_total;
+  const int nmid = std::max(0, S->params.substeps - 1);
+  for (int t = t1 - 1; t >= t0; --t) {
+    const float* xt = x + (size_t)(t - t0) * sw;
+    void* saved = S->bound[control];
+    S->bound[control] = const_cast<float*>(actions + (size_t)t * na);
+    // the actuation the step used: the per-step array or the bound tensor
+    const float* act = (const float*)S->bound[AGS_DOF_ACTUATION];
+    S->mid_root = nmid ? const_cast<double*>(mid) + (size_t)(t - t0) * nmid * sw : nullptr;
+    S->adj_big = flags + (size_t)(t - t0) * S->n_envs;
+    int rc = ags_sim_step_backward(S, xt, xt + nr, act, root_adj, dof_adj, act_adj + (size_t)t * na, status, st);
+    S->mid_root = nullptr;
+    S->adj_big = nullptr;
+    S->bound[control] = saved;
+    if (rc == AGS_OK && control == AGS_DOF_POS_TARGET) {
+      // the target enters the step only through tau = ... + kp q*: dL/dq* = kp dL/dtau
+      const hipError_t e2 = launch_scale_by_kp(act_adj + (size_t)t * na, S->kp_dof, (int)na, st);
+      if (e2 != hipSuccess) rc = hip_fail(e2, "rollout_backward: target adjoint");
+    }
+    if (rc != AGS_OK) return rc;
+  }
+  return AGS_OK;
+}
+
+// the rollout's extra streams and events, created on first use on the sim's current device; default priority
+hipError_t ensure_streams(ags_sim* S) {
+  if (S->aux) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipEventCreateWithFlags(&S->ev_ready[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_free[k], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->aux2, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_big_start, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_big_done, hipEventDisableTiming);
+  return e;
+}
+
+// where the parts of a segment buffer of `every` steps start (the layout of seg_one_bytes)
+void seg_parts(const ags_sim* S, void* base, int every, float** x, double** mid, int** flags) {
+  const size_t sw = 13ull * S->n_actors_total + 2ull * S->n_dof_total;
+  const size_t nmid = (size_t)std::max(0, S->params.substeps - 1);
+  const size_t states_bytes = ((every + 1) * sw * sizeof(float) + 255) / 256 * 256;
+  const size_t mid_bytes = ((size_t)every * nmid * sw * sizeof(double) + 255) / 256 * 256;
+  char* b = static_cast<char*>(base);
+  *x = reinterpret_cast<float*>(b);
+  *mid = reinterpret_cast<double*>(b + states_bytes);
+  *flags = reinterpret_cast<int*>(b + states_bytes + mid_bytes);
+}
 }  // namespace
 
 extern "C" int ags_rollout_forward(ags_sim* S, int32_t n_steps, int32_t every, int32_t control, const float* actions,
@@ -1063,31 +1118,14 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
   const int nmid = std::max(0, S->params.substeps - 1);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = hipSuccess;
-  if (!S->aux) {  // created on first use, on the sim's current device; default priority
-    if ((e = hipStreamCreateWithFlags(&S->aux, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "rollout_backward: stream");
-    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-      e = hipEventCreateWithFlags(&S->ev_ready[k], hipEventDisableTiming);
-      if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_free[k], hipEventDisableTiming);
-    }
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->aux2, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_big_start, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_big_done, hipEventDisableTiming);
-    if (e != hipSuccess) return hip_fail(e, "rollout_backward: events");
-  }
+  if ((e = ensure_streams(S)) != hipSuccess) return hip_fail(e, "rollout_backward: streams");
   // two segment buffers, each: every + 1 FP32 states, then every x nmid FP64 substep states, then every x
   // n_envs flags
   const long long one = seg_one_bytes(S, every);
-  const size_t states_bytes = ((every + 1) * sw * sizeof(float) + 255) / 256 * 256;
-  const size_t mid_bytes = ((size_t)every * nmid * sw * sizeof(double) + 255) / 256 * 256;
   float* seg[2];
   double* mid[2];
   int* flags[2];
-  for (int k = 0; k < 2; ++k) {
-    char* base = static_cast<char*>(seg_bytes) + k * one;
-    seg[k] = reinterpret_cast<float*>(base);
-    mid[k] = reinterpret_cast<double*>(base + states_bytes);
-    flags[k] = reinterpret_cast<int*>(base + states_bytes + mid_bytes);
-  }
+  for (int k = 0; k < 2; ++k) seg_parts(S, static_cast<char*>(seg_bytes) + k * one, every, &seg[k], &mid[k], &flags[k]);
   const int n_seg = (n_steps + every - 1) / every;
   // recompute segment g into buffer g % 2 on the auxiliary stream: the states before its steps (the last
   // step's end state is discarded) and the substep states of every step
@@ -1121,28 +1159,70 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
     const int b = g & 1, t0 = g * every, t1 = std::min(n_steps, t0 + every);
     if (g > 0 && (rc = recompute(g - 1)) != AGS_OK) return rc;  // overlaps the adjoints below
     if ((e = hipStreamWaitEvent(st, S->ev_ready[b], 0)) != hipSuccess) return hip_fail(e, "rollout_backward: wait");
-    for (int t = t1 - 1; t >= t0; --t) {
-      const float* x = seg[b] + (size_t)(t - t0) * sw;
-      void* saved = S->bound[control];
-      S->bound[control] = const_cast<float*>(actions + (size_t)t * na);
-      // the actuation the step used: the per-step array or the bound tensor
-      const float* act = (const float*)S->bound[AGS_DOF_ACTUATION];
-      S->mid_root = nmid ? mid[b] + (size_t)(t - t0) * nmid * sw : nullptr;
-      S->adj_big = flags[b] + (size_t)(t - t0) * S->n_envs;
-      rc = ags_sim_step_backward(S, x, x + nr, act, root_adj, dof_adj, act_adj + (size_t)t * na, status, stream);
-      S->mid_root = nullptr;
-      S->adj_big = nullptr;
-      S->bound[control] = saved;
-      if (rc == AGS_OK && control == AGS_DOF_POS_TARGET) {
-        // the target enters the step only through tau = ... + kp q*: dL/dq* = kp dL/dtau
-        const hipError_t e2 = launch_scale_by_kp(act_adj + (size_t)t * na, S->kp_dof, (int)na, st);
-        if (e2 != hipSuccess) rc = hip_fail(e2, "rollout_backward: target adjoint");
-      }
-      if (rc != AGS_OK) return rc;
-    }
+    if ((rc = reverse_steps(S, t0, t1, control, actions, seg[b], mid[b], flags[b], root_adj, dof_adj, act_adj, status,
+                            st)) != AGS_OK)
+      return rc;
     if ((e = hipEventRecord(S->ev_free[b], st)) != hipSuccess) return hip_fail(e, "rollout_backward: record");
   }
   return AGS_OK;
+}
+
+// ---------------------------------------------------------------- rollouts with a stored tape
+extern "C" int ags_rollout_tape_bytes(const ags_sim* S, int32_t n_steps, int64_t* bytes) {
+  if (!S || n_steps < 1 || !bytes) return fail(AGS_E_ARG, "rollout_tape_bytes: bad arguments");
+  *bytes = seg_one_bytes(S, n_steps);
+  return AGS_OK;
+}
+
+extern "C" int ags_rollout_forward_tape(ags_sim* S, int32_t n_steps, int32_t control, const float* actions, void* tape,
+                                        void* stream) {
+  if (!S || n_steps < 1 || !actions || !tape || (control != AGS_DOF_ACTUATION && control != AGS_DOF_POS_TARGET))
+    return fail(AGS_E_ARG, "rollout_forward_tape: bad arguments");
+  if (!S->bound[AGS_DOF_ACTUATION]) return fail(AGS_E_UNBOUND, "rollout_forward_tape: the actuation tensor must be bound");
+  if (!S->bound[AGS_ROOT_STATE] || !S->bound[AGS_DOF_STATE])
+    return fail(AGS_E_UNBOUND, "rollout_forward_tape: root and DOF state tensors must be bound");
+  const size_t nr = 13ull * S->n_actors_total, nd = 2ull * S->n_dof_total, sw = nr + nd;
+  const int nmid = std::max(0, S->params.substeps - 1);
+  hipStream_t st = (hipStream_t)stream;
+  float* x;
+  double* mid;
+  int* flags;
+  seg_parts(S, tape, n_steps, &x, &mid, &flags);
+  float* root = (float*)S->bound[AGS_ROOT_STATE];
+  float* dof = (float*)S->bound[AGS_DOF_STATE];
+  for (int t = 0; t < n_steps; ++t) {
+    float* c = x + (size_t)t * sw;
+    hipError_t e = hipMemcpyAsync(c, root, nr * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c + nr, dof, nd * sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "rollout_forward_tape: state copy");
+    void* saved = S->bound[control];
+    S->bound[control] = const_cast<float*>(actions + (size_t)t * S->n_dof_total);
+    S->mid_root = nmid ? mid + (size_t)t * nmid * sw : nullptr;
+    S->big_out = flags + (size_t)t * S->n_envs;
+    const int rc = ags_sim_step(S, stream);
+    S->mid_root = nullptr;
+    S->big_out = nullptr;
+    S->bound[control] = saved;
+    if (rc != AGS_OK) return rc;
+  }
+  return AGS_OK;
+}
+
+extern "C" int ags_rollout_backward_tape(ags_sim* S, int32_t n_steps, int32_t control, const float* actions,
+                                         const void* tape, float* root_adj, float* dof_adj, float* act_adj,
+                                         int32_t* status, void* stream) {
+  if (!S || n_steps < 1 || !actions || !tape || !root_adj || !dof_adj || !act_adj ||
+      (control != AGS_DOF_ACTUATION && control != AGS_DOF_POS_TARGET))
+    return fail(AGS_E_ARG, "rollout_backward_tape: bad arguments");
+  if (!S->bound[AGS_DOF_ACTUATION]) return fail(AGS_E_UNBOUND, "rollout_backward_tape: the actuation tensor must be bound");
+  hipError_t e = ensure_streams(S);
+  if (e != hipSuccess) return hip_fail(e, "rollout_backward_tape: streams");
+  float* x;
+  double* mid;
+  int* flags;
+  seg_parts(S, const_cast<void*>(tape), n_steps, &x, &mid, &flags);
+  return reverse_steps(S, 0, n_steps, control, actions, x, mid, flags, root_adj, dof_adj, act_adj, status,
+                       (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------- autotuner

@@ -190,6 +190,40 @@ def test_rollout_equals_chained_step_adjoints(fp64, case):
         assert (rel <= 1e-3).mean() >= 0.75, rel
 
 
+@pytest.mark.parametrize("case", ["ant", "humanoid_many_rows"])
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_rollout_tape_equals_checkpoints(fp64, case):
+    """A rollout whose forward pass stores the whole tape (every = 0: states before every step, substep
+    states, row-count flags) and whose backward pass recomputes nothing gives the same final state and
+    the same gradients, bit for bit, as the checkpointed rollout (every 4) that recomputes them: the
+    stored values are the ones the recomputation produces."""
+    if case == "ant":
+        E, T = 16, 16
+        env, params, oe, root, dof, acts = _ant_rollout_case(E, T)
+    else:
+        E, T = 16, 8
+        env, params, oe, root, dof, acts = _humanoid_rows_case(T)
+    from paper_2108_10470_amd import ags
+    sim = ags.Sim([ags.Model(env)], [0] * E, params, device="cuda:0", fp64=fp64)
+    f32 = dict(dtype=torch.float32, device="cuda:0")
+    wr = torch.tensor(np.random.default_rng(11).standard_normal(E * env.n_actors * 13), **f32)
+    wd = torch.tensor(np.random.default_rng(12).standard_normal(E * env.n_dof * 2), **f32)
+    out = {}
+    for every in (4, 0):
+        a = torch.tensor(acts.reshape(T, E * env.n_dof), **f32).requires_grad_(True)
+        r0 = torch.tensor(root.reshape(-1, 13), **f32).requires_grad_(True)
+        d0 = torch.tensor(dof.reshape(-1, 2), **f32).requires_grad_(True)
+        r, d = ags.rollout(sim, a, r0, d0, every=every)
+        ((r.reshape(-1) * wr).sum() + (d.reshape(-1) * wd).sum()).backward()
+        torch.cuda.synchronize()
+        out[every] = [x.detach().clone() for x in (r, d, a.grad, r0.grad, d0.grad)]
+    names = ["root", "dof", "action grad", "root0 grad", "dof0 grad"]
+    for n, x, y in zip(names, out[4], out[0]):
+        assert torch.isfinite(x).all(), n
+        assert torch.equal(x, y), (n, float((x - y).abs().max()))
+    assert float(out[0][2].abs().max()) > 0.0
+
+
 @pytest.mark.parametrize("adj", [64, 32], ids=["adj64", "adj32"])
 def test_rollout_gradient_hand_targets(adj):
     """Hand+cube, PD targets as the controls (zero actuation), loss = seeded weights . final state (all
