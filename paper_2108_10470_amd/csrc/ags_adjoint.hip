@@ -1512,11 +1512,10 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   sync<R>();
 }
 
+// the adjoint of entry ei of the launch's env list, by one 64-lane workgroup
 template <typename R>
-__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
+__device__ __forceinline__ void adjoint_env(const AdjArgs& P, int ei) {
   extern __shared__ double g_adj_lds[];
-  const int ei = blockIdx.x;
-  if (ei >= n_envs || (P.list_count && ei >= *P.list_count)) return;
   const AdjLds& L = P.L;
   Env<R> E;
   E.P = &P;
@@ -1531,7 +1530,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
   E.nlev = P.m.n_levels;
   E.rc = L.rows_cap;
   const int env = P.env_list[ei];
-  if (P.big_rows && (P.big_rows[env] != 0) != (P.big_mode == 2)) return;  // the other pass runs this env
+  if (P.skip_flags && P.skip_flags[env] != 0) return;  // another launch runs this env
   E.abase = P.env_actor_base[env];
   E.dbase = P.env_dof_base[env];
   E.h = R(P.h);
@@ -1582,22 +1581,57 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
     for (int k = 0; k < kAdjPhases; ++k) P.cycles[(long long)env * kAdjPhases + k] = E.cyc[k];
 }
 
+// one env per workgroup
+template <typename R>
+__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
+  const int ei = blockIdx.x;
+  if (ei >= n_envs || (P.list_count && ei >= *P.list_count)) return;
+  adjoint_env<R>(P, ei);
+}
+// fewer workgroups than list entries, each striding over the device list (the flagged-env pass); kept apart
+// from adjoint_kernel because the loop costs registers (a few spilled in the FP32 form)
+template <typename R>
+__global__ __launch_bounds__(64) void adjoint_list_kernel(AdjArgs P, int n_envs) {
+  for (int ei = blockIdx.x; ei < n_envs; ei += gridDim.x) {
+    if (ei >= *P.list_count) return;
+    adjoint_env<R>(P, ei);
+    __syncthreads();  // the next entry reuses the LDS
+  }
+}
+
 __global__ void zero_count_kernel(int* c) {
   if (threadIdx.x == 0) c[0] = 0;
 }
 
+// list[0] = number of envs of env_list[0, n) whose flag is set, list[1 ...] = those envs (any order)
+__global__ void compact_flags_kernel(const int* env_list, int n, const int* flags, int* list) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int env = env_list[i];
+  if (flags[env] != 0) list[1 + atomicAdd(list, 1)] = env;
+}
+
 template <typename R>
-hipError_t launch_adj(const AdjArgs& a, int n_envs, hipStream_t stream) {
+hipError_t launch_adj(const AdjArgs& a, int n_envs, int grid, hipStream_t stream) {
   const size_t lds = (size_t)a.L.n_real * sizeof(R) + (size_t)a.L.n_int * sizeof(int);
-  hipLaunchKernelGGL(adjoint_kernel<R>, dim3(n_envs), dim3(64), lds, stream, a, n_envs);
+  if (grid < n_envs) hipLaunchKernelGGL(adjoint_list_kernel<R>, dim3(grid), dim3(64), lds, stream, a, n_envs);
+  else hipLaunchKernelGGL(adjoint_kernel<R>, dim3(grid), dim3(64), lds, stream, a, n_envs);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t stream) {
+hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t stream, int grid) {
   if (n_envs <= 0) return hipSuccess;
-  return fp64 ? launch_adj<double>(a, n_envs, stream) : launch_adj<float>(a, n_envs, stream);
+  grid = (grid > 0 && grid < n_envs) ? grid : n_envs;
+  if (grid < n_envs && !a.list_count) return hipErrorInvalidValue;
+  return fp64 ? launch_adj<double>(a, n_envs, grid, stream) : launch_adj<float>(a, n_envs, grid, stream);
+}
+
+hipError_t launch_compact_flags(const int* env_list, int n, const int* flags, int* list, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(compact_flags_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, env_list, n, flags, list);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_count(int* c, hipStream_t stream) {
@@ -1607,7 +1641,10 @@ hipError_t launch_zero_count(int* c, hipStream_t stream) {
 
 hipError_t set_adjoint_lds_limit(int fp64, size_t bytes) {
   const void* f = fp64 ? (const void*)adjoint_kernel<double> : (const void*)adjoint_kernel<float>;
-  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* g = fp64 ? (const void*)adjoint_list_kernel<double> : (const void*)adjoint_list_kernel<float>;
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return e;
 }
 
 }  // namespace ags

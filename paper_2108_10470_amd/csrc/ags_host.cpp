@@ -542,6 +542,8 @@ struct ags_sim {
   float* kp_dof = nullptr;  // device: drive stiffness of every DOF (target adjoints)
   double* mid_root = nullptr;  // set while a rollout recomputes: where the step writes substep states
   int* adj_retry = nullptr;    // device: count, then the environments the small adjoint layout could not hold
+  int* adj_big_list = nullptr; // device: count, then the flagged environments of the current type
+  int n_cu = 1;                // compute units of the sim's device
   // rollout backward: a second stream (default priority) recomputes the next segment while the adjoint of
   // the current one runs; events order the two segment buffers between the streams
   hipStream_t aux = nullptr;
@@ -738,10 +740,15 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     }
     S->types.push_back(T);
   }
-  if ((err = hipMalloc(&S->adj_retry, ((size_t)max_type_envs + 1) * sizeof(int))) != hipSuccess) {
+  int dev_cu = 0, n_cu = 0;
+  if ((err = hipMalloc(&S->adj_retry, ((size_t)max_type_envs + 1) * sizeof(int))) != hipSuccess ||
+      (err = hipMalloc(&S->adj_big_list, ((size_t)max_type_envs + 1) * sizeof(int))) != hipSuccess ||
+      (err = hipGetDevice(&dev_cu)) != hipSuccess ||
+      (err = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_cu)) != hipSuccess) {
     ags_sim_destroy(S);
-    return hip_fail(err, "sim: adjoint retry list");
+    return hip_fail(err, "sim: adjoint lists");
   }
+  S->n_cu = std::max(1, n_cu);
   if (p->persistent && !S->types.empty() && (int)S->types.size() <= kMaxFusedTypes) {
     // work list: (type, group) units, types ordered by estimated cost per group (heaviest first)
     std::vector<int> order(S->types.size());
@@ -793,6 +800,7 @@ extern "C" void ags_sim_destroy(ags_sim* S) {
     if (T.scratch) (void)hipFree(T.scratch);
   }
   if (S->adj_retry) (void)hipFree(S->adj_retry);
+  if (S->adj_big_list) (void)hipFree(S->adj_big_list);
   for (int k = 0; k < 2; ++k) {
     if (S->ev_ready[k]) (void)hipEventDestroy(S->ev_ready[k]);
     if (S->ev_free[k]) (void)hipEventDestroy(S->ev_free[k]);
@@ -958,15 +966,18 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
       const hipStream_t st = (hipStream_t)stream;
       if (S->adj_big) {
         // environments the forward flagged run with the full layout on the third stream, concurrently with
-        // pass 1 (which skips them); the caller's stream waits for them before its next work
-        a1.big_rows = S->adj_big;
-        a1.big_mode = 1;
+        // pass 1 (which skips them): a device list of them, strided over by one workgroup per CU (a launch
+        // of one workgroup per env would wait for LDS room for each of its mostly empty workgroups); the
+        // caller's stream waits for them before its next work
+        a1.skip_flags = S->adj_big;
         AdjArgs ab = a;
-        ab.big_rows = S->adj_big;
-        ab.big_mode = 2;
+        ab.env_list = S->adj_big_list + 1;
+        ab.list_count = S->adj_big_list;
         if ((e = hipEventRecord(S->ev_big_start, st)) == hipSuccess &&
             (e = hipStreamWaitEvent(S->aux2, S->ev_big_start, 0)) == hipSuccess &&
-            (e = launch_adjoint(ab, T.n_envs, adj_fp64(p), S->aux2)) == hipSuccess)
+            (e = launch_zero_count(S->adj_big_list, S->aux2)) == hipSuccess &&
+            (e = launch_compact_flags(T.env_list, T.n_envs, S->adj_big, S->adj_big_list, S->aux2)) == hipSuccess &&
+            (e = launch_adjoint(ab, T.n_envs, adj_fp64(p), S->aux2, S->n_cu)) == hipSuccess)
           e = hipEventRecord(S->ev_big_done, S->aux2);
         if (e != hipSuccess) return hip_fail(e, "step_backward: flagged pass");
       }

@@ -172,13 +172,16 @@ struct AdjArgs {
   int* retry;              // optional: environments whose rows exceed this layout's capacity are appended here
   int* retry_count;        //   (count at *retry_count) instead of being written with a zero adjoint
   const int* list_count;   // optional: number of valid entries of env_list (device), for a launch over a retry list
-  const int* big_rows;     // optional (indexed by env): the forward's flag of envs with many rows
-  int big_mode;            // with big_rows: 1 skip flagged envs, 2 run only flagged envs
+  const int* skip_flags;   // optional (indexed by env): envs whose flag is set are left to another launch
   double h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
 };
 
-hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t stream);
+// grid in (0, n_envs): that many workgroups stride over a device list (a.list_count required);
+// default: one workgroup per entry
+hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t stream, int grid = 0);
+// list[0] (zeroed beforehand) = count, list[1 ...] = the envs of env_list[0, n) with flags[env] != 0
+hipError_t launch_compact_flags(const int* env_list, int n, const int* flags, int* list, hipStream_t stream);
 hipError_t set_adjoint_lds_limit(int fp64, size_t bytes);
 hipError_t launch_zero_count(int* c, hipStream_t stream);
 
