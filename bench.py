@@ -238,6 +238,36 @@ def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, ad
                 "fp64" if adjoint_precision == 64 or (adjoint_precision == 0 and fp64) else "fp32", "adjoint")}
 
 
+def run_jacmass(env, params, n_envs, root0, dof0, reps=20):
+    """Jacobian and mass-matrix tensors of the whole batch at the start state (ags_sim_jacobian_mass):
+    mean launch time and the output bytes it writes."""
+    import torch
+    from paper_2108_10470_amd import ags
+    sim = ags.Sim([ags.Model(env)], [0] * n_envs, params, device="cuda:0")
+    sim.root_state.copy_(root0)
+    sim.dof_state.copy_(dof0)
+    info = sim.models[0].info
+    J = torch.empty((n_envs, info.n_links, 6, info.n_v), dtype=torch.float32, device="cuda:0")
+    M = torch.empty((n_envs, info.n_v, info.n_v), dtype=torch.float32, device="cuda:0")
+    import ctypes
+    L = ags.lib()
+    stream = torch.cuda.current_stream()
+    call = lambda: ags._check(L.ags_sim_jacobian_mass(sim.h, 0, ctypes.c_void_p(J.data_ptr()),
+                                                       ctypes.c_void_p(M.data_ptr()),
+                                                       ctypes.c_void_p(stream.cuda_stream)), "jacobian_mass")
+    call()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        call()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    out_bytes = 4 * (J.numel() + M.numel())
+    return {"envs": n_envs, "ms": ms, "output_bytes": out_bytes, "output_GB_per_s": out_bytes / (ms / 1e3) / 1e9,
+            "finite": bool(torch.isfinite(J).all() and torch.isfinite(M).all())}
+
+
 def run_hetero(params, n_envs, steps, fp64):
     """Heterogeneous batch: ant-like, humanoid-like and arm+gripper+box environments in equal thirds,
     interleaved; per-type launches vs the persistent launch, and the autotuner's pick."""
@@ -411,6 +441,8 @@ def main():
         if not args.no_fwd_bwd:
             hand["fwd_bwd"] = run_hand_fwd_bwd(args.hand_envs, args.hand_steps, head == "fp64", args.fwd_bwd_every)
             print(f"[bench] hand fwd+bwd: {json.dumps(hand['fwd_bwd'])}", file=sys.stderr, flush=True)
+    jacmass = run_jacmass(env, params, E, root0, dof0)
+    print(f"[bench] jacobian+mass: {json.dumps(jacmass)}", file=sys.stderr, flush=True)
     fwd_bwd = None
     if not args.no_fwd_bwd:
         T = args.fwd_bwd_steps
@@ -452,6 +484,7 @@ def main():
         "fwd_bwd": fwd_bwd,
         "batching": hetero,
         "hand": hand,
+        "jacobian_mass": jacmass,
         "variants": {k: {"env_steps_per_s": E * K / (v["total_ms"] / 1e3), "ms_per_step": v["total_ms"] / K,
                          "launch_ms": float(v["launch_ms"].mean()), "mean_rows_per_substep": v["rows"],
                          "graph_ms_per_step": v["graph_ms"],

@@ -208,6 +208,22 @@ int ags_autotune(const ags_model* const* models, int32_t n_models, const int32_t
                  ags_sim_params* params, const float* root_state, const float* dof_state, const float* actuation,
                  int32_t n_steps, float* ms_out, void* hip_stream);
 
+/* Jacobian and generalized mass-matrix tensors (Section 2.3, Table 1: available for articulated actors,
+ * per homogeneous group, for operational-space control and inverse kinematics) of the envs that use
+ * models[model] (the index among the models the sim was created with), in increasing env id, at the
+ * state in the bound root / DOF state tensors.  With nb = n_links and nv = n_v of that model
+ * (ags_model_get_info) and n its env count:
+ *   jac  (device, n x nb x 6 x nv, row-major): for every link (body) b of the env, rows 0-2 the world
+ *        velocity of b's frame origin and rows 3-5 b's world angular velocity per unit rate of each
+ *        generalized velocity column;
+ *   mass (device, n x nv x nv): the joint-space inertia M(q) in the same columns (symmetric; armature
+ *        not included), i.e. the kinetic energy is 1/2 qd^T M qd.
+ * Columns: per actor in order, a free root's world COM velocity (3) and world angular velocity (3), then
+ * the actor's joint rates; the columns of other actors of the env are zero for b.  Either output may be
+ * NULL; the call only enqueues work on hip_stream.  Errors: AGS_E_ARG (no env uses the model, both outputs
+ * NULL), AGS_E_UNBOUND (state tensors not bound). */
+int ags_sim_jacobian_mass(ags_sim* sim, int32_t model, float* jac, float* mass, void* hip_stream);
+
 /* Rollouts with checkpoints (the checkpoint-every-k recomputation pattern of differentiable
  * simulation).  A state is 13 N_A + 2 N_D floats: the root-state rows, then the DOF-state rows. */
 int ags_rollout_state_size(const ags_sim* sim, int64_t* floats);

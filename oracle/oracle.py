@@ -164,6 +164,44 @@ class OracleEnv:
         lib().orc_body_states(self.h, _dp(root), _dp(dof), _dp(out))
         return out[:, :3], out[:, 3:12].reshape(-1, 3, 3), out[:, 12:15], out[:, 15:18]
 
+    def set_velocity(self, root, dof, qd):
+        """Copies of one env's (root (A, 13), dof (D, 2)) with the generalized velocity qd (n_v) written in:
+        per actor, a free root's world COM velocity and angular velocity (root columns 7-12), then the
+        actor's joint rates."""
+        root = np.array(root, dtype=np.float64)
+        dof = np.array(dof, dtype=np.float64)
+        c = j = 0
+        for ai, a in enumerate(self.spec.actors):
+            if not a.fixed_base:
+                root[ai, 7:13] = qd[c:c + 6]
+                c += 6
+            dof[j:j + a.n_dof, 1] = qd[c:c + a.n_dof]
+            c += a.n_dof
+            j += a.n_dof
+        return root, dof
+
+    def jacobian(self, root, dof):
+        """Jacobian tensor of one env (Section 2.3, Table 1), (n_bodies, 6, n_v): the rigid-body velocities
+        (world velocity of each link origin, then its world angular velocity) are linear in the generalized
+        velocity, and column k is their value at the unit generalized velocity e_k."""
+        nv = self.n_v
+        J = np.zeros((self.n_bodies, 6, nv))
+        for k in range(nv):
+            e = np.zeros(nv)
+            e[k] = 1.0
+            _, _, v, w = self.body_states(*self.set_velocity(root, dof, e))
+            J[:, 0:3, k] = v
+            J[:, 3:6, k] = w
+        return J
+
+    def mass_matrix(self, root, dof):
+        """Generalized mass matrix of one env (Table 1), (n_v, n_v): the joint-space inertia M(q) of CRBA,
+        without armature."""
+        from types import SimpleNamespace
+        p = SimpleNamespace(dt=1.0, substeps=1, gravity=(0.0, 0.0, 0.0), pgs_iters=0, mu=0.0, baumgarte=0.0,
+                            contact_margin=0.0, limit_margin_rev=0.0, limit_margin_pri=0.0)
+        return self.dynamics(p, root, dof, np.zeros(self.n_v))[0]
+
     def dynamics(self, params, root, dof, tau):
         root = np.ascontiguousarray(root, dtype=np.float64)
         dof = np.ascontiguousarray(dof, dtype=np.float64)

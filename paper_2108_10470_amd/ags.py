@@ -94,6 +94,7 @@ def lib():
         L.ags_rollout_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp]
         L.ags_rollout_backward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.ags_rollout_tape_bytes.argtypes = [vp, i32, i64p]
+        L.ags_sim_jacobian_mass.argtypes = [vp, i32, vp, vp, vp]
         L.ags_rollout_forward_tape.argtypes = [vp, i32, i32, vp, vp, vp]
         L.ags_rollout_backward_tape.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
@@ -104,7 +105,8 @@ EXPORTED = ["ags_last_error", "ags_model_create", "ags_model_destroy", "ags_mode
             "ags_sim_create", "ags_sim_destroy", "ags_sim_tensor_shape", "ags_sim_bind", "ags_sim_step",
             "ags_sim_set_root_state_indexed", "ags_sim_set_dof_state_indexed", "ags_sim_step_backward",
             "ags_rollout_state_size", "ags_rollout_forward", "ags_rollout_backward", "ags_autotune",
-            "ags_rollout_seg_bytes", "ags_rollout_tape_bytes", "ags_rollout_forward_tape", "ags_rollout_backward_tape"]
+            "ags_rollout_seg_bytes", "ags_rollout_tape_bytes", "ags_rollout_forward_tape", "ags_rollout_backward_tape",
+            "ags_sim_jacobian_mass"]
 
 
 def _check(rc: int, what: str):
@@ -177,6 +179,7 @@ class Sim:
                  lanes_per_env: int = 0, persistent: bool = False, adjoint_precision: int = 0,
                  rigid_body_state: bool = False, status: bool = False):
         self.models = list(models)
+        self.env_model = [int(x) for x in env_model]
         self.params = params
         self.device = torch.device(device)
         self.n_envs = len(env_model)
@@ -253,6 +256,22 @@ class Sim:
                 raise ValueError("status: expected an int32 tensor with one entry per environment")
             st = ctypes.c_void_p(status.data_ptr())
         _check(lib().ags_sim_step_backward(self.h, *args, st, ctypes.c_void_p(s.cuda_stream)), "ags_sim_step_backward")
+
+    def jacobian_mass(self, model: int = 0, jacobian: bool = True, mass: bool = True,
+                      stream: Optional[torch.cuda.Stream] = None):
+        """Jacobian (n, n_links, 6, n_v) and generalized mass matrix (n, n_v, n_v) tensors of the n envs
+        that use models[model], in env order, at the bound state (ags_sim_jacobian_mass); None for an
+        output not asked for."""
+        n = sum(1 for m in self.env_model if m == model)
+        info = self.models[model].info
+        f32 = dict(dtype=torch.float32, device=self.device)
+        J = torch.empty((n, info.n_links, 6, info.n_v), **f32) if jacobian else None
+        M = torch.empty((n, info.n_v, info.n_v), **f32) if mass else None
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(lib().ags_sim_jacobian_mass(self.h, model, ctypes.c_void_p(J.data_ptr() if J is not None else 0),
+                                           ctypes.c_void_p(M.data_ptr() if M is not None else 0),
+                                           ctypes.c_void_p(s.cuda_stream)), "ags_sim_jacobian_mass")
+        return J, M
 
     def set_root_state_indexed(self, src: torch.Tensor, actor_idx: Optional[torch.Tensor] = None):
         s = torch.cuda.current_stream(self.device)

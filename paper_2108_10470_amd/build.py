@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libags.so")
-SOURCES = ["ags_step.hip", "ags_adjoint.hip", "ags_host.cpp"]
+SOURCES = ["ags_step.hip", "ags_adjoint.hip", "ags_jacmass.hip", "ags_host.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # packed FP32 instructions are disabled for every HIP translation unit

@@ -423,6 +423,7 @@ extern "C" int ags_model_mass_props(const ags_model* m, float* mass, float* com,
 // ---------------------------------------------------------------- simulation
 namespace {
 struct TypeDev {
+  int model = 0;  // index of the model among those the sim was created with
   int team = 64;
   DevModel dm{};
   Lds lds{};
@@ -629,6 +630,7 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     if (lists[t].empty()) continue;
     const ags_model* M = models[t];
     TypeDev T;
+    T.model = t;
     T.n_envs = (int)lists[t].size();
     // lanes per environment: 32 (two environments per wavefront) when every per-lane loop fits
     // automatic: FP64 compute gives each environment a whole wavefront (its LDS then allows two wavefronts
@@ -990,6 +992,31 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
     }
     if (e != hipSuccess) return hip_fail(e, "step_backward: launch");
   }
+  return AGS_OK;
+}
+
+// ---------------------------------------------------------------- Jacobian and mass-matrix tensors
+extern "C" int ags_sim_jacobian_mass(ags_sim* S, int32_t model, float* jac, float* mass, void* stream) {
+  if (!S || (!jac && !mass)) return fail(AGS_E_ARG, "jacobian_mass: bad arguments");
+  if (!S->bound[AGS_ROOT_STATE] || !S->bound[AGS_DOF_STATE])
+    return fail(AGS_E_UNBOUND, "jacobian_mass: root and DOF state tensors must be bound");
+  const TypeDev* T = nullptr;
+  for (const TypeDev& t : S->types)
+    if (t.model == model) T = &t;
+  if (!T) return fail(AGS_E_ARG, "jacobian_mass: no environment uses this model");
+  if (jacmass_lds_bytes(T->dm.n_links) > 64 * 1024) return fail(AGS_E_ARG, "jacobian_mass: model too large");
+  JacMassArgs a{};
+  a.m = T->dm;
+  a.env_list = T->env_list;
+  a.n_envs = T->n_envs;
+  a.env_actor_base = S->env_tables;
+  a.env_dof_base = S->env_tables + S->n_envs;
+  a.root_state = (const float*)S->bound[AGS_ROOT_STATE];
+  a.dof_state = (const float*)S->bound[AGS_DOF_STATE];
+  a.jac = jac;
+  a.mass = mass;
+  const hipError_t e = launch_jacmass(a, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "jacobian_mass: launch");
   return AGS_OK;
 }
 

@@ -121,6 +121,21 @@ hipError_t launch_step_fused(const FusedArgs& a, int grid, size_t lds_bytes, int
 hipError_t set_fused_lds_limit(int fp64, int team, size_t bytes);
 hipError_t fused_blocks_per_cu(int fp64, int team, size_t lds_bytes, int* blocks);
 
+// ---------------------------------------------------------------- Jacobian and mass-matrix tensors
+struct JacMassArgs {
+  DevModel m;
+  const int* env_list;  // the envs of one model type (output entry i is env_list[i])
+  int n_envs;
+  const int* env_actor_base;
+  const int* env_dof_base;
+  const float* root_state;
+  const float* dof_state;
+  float* jac;   // optional: n_envs x n_links x 6 x n_v
+  float* mass;  // optional: n_envs x n_v x n_v
+};
+size_t jacmass_lds_bytes(int n_links);
+hipError_t launch_jacmass(const JacMassArgs& a, hipStream_t stream);
+
 // ---------------------------------------------------------------- adjoint of one env-step
 constexpr int kAdjRows = 64;   // constraint rows per substep the adjoint handles (one lane each)
 constexpr int kAdjSmallRows = 32;  // row capacity of the first, smaller-LDS adjoint pass

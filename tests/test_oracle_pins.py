@@ -329,6 +329,78 @@ def test_body_states_match_kinematic_differences(make):
     assert np.abs(w).max() > 0.1 and np.abs(v).max() > 0.1  # the check is not vacuous
 
 
+def _state_with_random_pose(env, seed):
+    """One env's (root, dof) at seeded joint positions away from the initial pose, root turned."""
+    root, dof = W.initial_state(env, 1, seed)
+    root, dof = root[0], dof[0]
+    rng = np.random.default_rng(seed + 100)
+    dof[:, 0] += rng.uniform(-0.5, 0.5, len(dof))
+    for ai, a in enumerate(env.actors):
+        if not a.fixed_base:
+            q = rng.normal(size=4)
+            root[ai, 3:7] = q / np.linalg.norm(q)
+    return root, dof
+
+
+@pytest.mark.parametrize("make", [W.env_humanoid, W.env_arm_box, W.env_hand_cube])
+def test_jacobian_matches_kinematic_differences(make):
+    """Jacobian tensor (Table 1): J qd equals central differences of FK along qd (link-origin velocity and
+    angular velocity, a free root moving by its COM velocity and turning by Exp(h w)) for random qd, and
+    a column moves only the links below its joint."""
+    env = make()
+    oe = O.OracleEnv(env)
+    root, dof = _state_with_random_pose(env, 4)
+    J = oe.jacobian(root, dof)
+    assert J.shape == (oe.n_bodies, 6, oe.n_v)
+    rng = np.random.default_rng(9)
+    R, p = oe.fk(root, dof)
+    d = 1e-6
+    for _ in range(3):
+        qd = rng.normal(size=oe.n_v)
+        Rp, pp = oe.fk(*_advance(env, root, dof, d * qd))
+        Rm, pm = oe.fk(*_advance(env, root, dof, -d * qd))
+        vfd = (pp - pm) / (2 * d)
+        S = np.einsum("bij,bkj->bik", (Rp - Rm) / (2 * d), R)
+        wfd = np.stack([S[:, 2, 1], S[:, 0, 2], S[:, 1, 0]], axis=1)
+        Jq = J @ qd
+        scale = 1 + np.abs(Jq).max()
+        assert np.abs(Jq[:, :3] - vfd).max() <= 1e-6 * scale
+        assert np.abs(Jq[:, 3:] - wfd).max() <= 1e-6 * scale
+    # the first joint column of the first actor with joints moves its own link, not the root link
+    a0 = next(a for a in env.actors if a.n_dof > 0)
+    first = sum(6 for a in env.actors[:env.actors.index(a0)] if not a.fixed_base) + (0 if a0.fixed_base else 6)
+    base = sum(len(a.links) for a in env.actors[:env.actors.index(a0)])
+    assert np.abs(J[base, :, first]).max() == 0.0 and np.abs(J[base + 1, :, first]).max() > 0.1
+
+
+@pytest.mark.parametrize("make", [W.env_humanoid, W.env_arm_box, W.env_hand_cube])
+def test_mass_matrix_is_the_kinetic_energy_form(make):
+    """Generalized mass matrix (Table 1): for every pair of columns, M_kl = T(e_k + e_l) - T(e_k) - T(e_l)
+    and M_kk = 2 T(e_k), with T the kinetic energy summed body by body from the rigid-body states and the
+    mass properties (1/2 m |v_com|^2 + 1/2 w^T R I_c R^T w) - independent of the CRBA recursion."""
+    env = make()
+    oe = O.OracleEnv(env)
+    root, dof = _state_with_random_pose(env, 6)
+    M = oe.mass_matrix(root, dof)
+    m, com, Ic = oe.mass_props()
+    nv = oe.n_v
+
+    def T(qd):
+        p, R, v, w = oe.body_states(*oe.set_velocity(root, dof, qd))
+        vc = v + np.cross(w, np.einsum("bij,bj->bi", R, com))
+        Iw = np.einsum("bij,bjk,blk->bil", R, Ic, R)
+        return 0.5 * (m * (vc * vc).sum(1)).sum() + 0.5 * np.einsum("bi,bij,bj->", w, Iw, w)
+
+    E = np.eye(nv)
+    Tk = np.array([T(E[k]) for k in range(nv)])
+    Mt = np.diag(2 * Tk)
+    for k in range(nv):
+        for l in range(k + 1, nv):
+            Mt[k, l] = Mt[l, k] = T(E[k] + E[l]) - Tk[k] - Tk[l]
+    assert np.abs(M - Mt).max() <= 1e-12 * (1 + np.abs(M).max())
+    assert np.abs(M).max() > 0.01
+
+
 def _bare_humanoid():
     return W.humanoid(armature=0.0, damping=0.0)
 
