@@ -74,6 +74,7 @@ def parse():
                     help="checkpoint interval of the secondary (recomputing) forward+adjoint measurement")
     ap.add_argument("--fwd-bwd-reps", type=int, default=3)
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous-batch measurement")
+    ap.add_argument("--no-tgs", action="store_true", help="skip the temporal Gauss-Seidel variant's measurement")
     ap.add_argument("--hetero-envs", type=int, default=16384)
     ap.add_argument("--hetero-steps", type=int, default=100)
     ap.add_argument("--no-hand", action="store_true", help="skip the 65536-env hand+cube measurement")
@@ -441,6 +442,13 @@ def main():
         if not args.no_fwd_bwd:
             hand["fwd_bwd"] = run_hand_fwd_bwd(args.hand_envs, args.hand_steps, head == "fp64", args.fwd_bwd_every)
             print(f"[bench] hand fwd+bwd: {json.dumps(hand['fwd_bwd'])}", file=sys.stderr, flush=True)
+    tgs = None
+    if not args.no_tgs:  # the temporal Gauss-Seidel variant of the solver, same workload and precision
+        import dataclasses
+        r = run_gpu(env, dataclasses.replace(params, solver=1), E, K, Wm, head == "fp64", actions_dev, root0, dof0)
+        tgs = {"env_steps_per_s": E * K / (r["total_ms"] / 1e3), "ms_per_step": r["total_ms"] / K,
+               "launch_ms": float(r["launch_ms"].mean()), "finite": r["finite"], "dtype": head.replace("fp", "f")}
+        print(f"[bench] tgs: {json.dumps(tgs)}", file=sys.stderr, flush=True)
     jacmass = run_jacmass(env, params, E, root0, dof0)
     print(f"[bench] jacobian+mass: {json.dumps(jacmass)}", file=sys.stderr, flush=True)
     fwd_bwd = None
@@ -485,6 +493,7 @@ def main():
         "batching": hetero,
         "hand": hand,
         "jacobian_mass": jacmass,
+        "tgs": tgs,
         "variants": {k: {"env_steps_per_s": E * K / (v["total_ms"] / 1e3), "ms_per_step": v["total_ms"] / K,
                          "launch_ms": float(v["launch_ms"].mean()), "mean_rows_per_substep": v["rows"],
                          "graph_ms_per_step": v["graph_ms"],

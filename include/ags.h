@@ -124,7 +124,14 @@ typedef struct {
                                list ordered by estimated cost, heaviest first); 0: one launch per type */
   int32_t adjoint_precision;  /* ags_sim_step_backward computes in: 0 the precision of compute_fp64, 32 FP32,
                                  64 FP64 */
+  int32_t solver;           /* 0: projected Gauss-Seidel (AGS_SOLVER_PGS); 1: the temporal variant
+                               (AGS_SOLVER_TGS, Section 3): the same rows and sweeps, but after every sweep
+                               the velocity times h / pgs_iters is accumulated per row as J_r v, and each
+                               contact-normal and limit row's bias is recomputed from its position error
+                               plus that accumulated displacement.  The adjoint supports PGS only. */
 } ags_sim_params;
+
+enum { AGS_SOLVER_PGS = 0, AGS_SOLVER_TGS = 1 };
 
 typedef struct ags_sim ags_sim;
 

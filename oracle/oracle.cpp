@@ -667,6 +667,7 @@ void tangents(const v3& n, v3& t1, v3& t2, int& near) {
 struct Params {
   double dt, h, beta, mu, mc, ml_rev, ml_pri, guard_c, guard_l;
   int substeps, iters;
+  int tgs;  // 1: temporal Gauss-Seidel variant
   v3 g;
 };
 
@@ -677,6 +678,7 @@ struct Row {
   int slot;           // contact rows: index into the slot list
   std::vector<double> J, W;
   double bias, A;
+  double pos = 0.0;   // limit and contact-normal rows: the position error (gap or phi) the bias comes from
 };
 
 struct StepOut {
@@ -782,6 +784,7 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
         r.J[c] = side == 0 ? 1.0 : -1.0;
         r.bias = gap >= 0 ? gap / h : P.beta * gap / h;
         r.branch = gap >= 0 ? 0 : 1;
+        r.pos = gap;
         rows.push_back(r);
       }
     }
@@ -814,6 +817,7 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
           r.J[c] = dirs[k][0] * Jp[c] + dirs[k][1] * Jp[nv + c] + dirs[k][2] * Jp[2 * nv + c];
         r.bias = k == 0 ? (s.phi >= 0 ? s.phi / h : P.beta * s.phi / h) : 0.0;
         r.branch = k == 0 && s.phi < 0 ? 1 : 0;
+        r.pos = k == 0 ? s.phi : 0.0;
         rows.push_back(r);
       }
     }
@@ -838,9 +842,21 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
       mode.mix(r.branch);
     }
     mode.mix(-1);
-    // ---- projected Gauss-Seidel: fixed sweeps from lambda = 0, v = v*
-    std::vector<double> lam(kept.size(), 0.0), v = vstar;
+    // ---- projected Gauss-Seidel: fixed sweeps from lambda = 0, v = v*.  Temporal variant (Section 3):
+    // the velocity at the end of each sweep, times h / iters, is accumulated into a displacement; a limit
+    // or contact-normal row's bias is that of its position error plus the displacement along its row
+    // (the same two branches as above), recomputed before every sweep.
+    std::vector<double> lam(kept.size(), 0.0), v = vstar, disp(nv, 0.0);
     for (int it = 0; it < P.iters; ++it) {
+      if (P.tgs) {
+        for (Row& r : kept) {
+          if (r.kind >= 4) continue;
+          double C = r.pos;
+          for (int c = 0; c < nv; ++c) C += r.J[c] * disp[c];
+          r.bias = C >= 0 ? C / h : P.beta * C / h;
+          mode.mix(C >= 0 ? 0 : 1);  // the bias is continuous in C; only its slope switches
+        }
+      }
       for (size_t ri = 0; ri < kept.size(); ++ri) {
         const Row& r = kept[ri];
         double res = r.bias;
@@ -854,6 +870,8 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
         for (int c = 0; c < nv; ++c) v[c] += r.W[c] * dl;
         lam[ri] = nl;
       }
+      if (P.tgs)
+        for (int c = 0; c < nv; ++c) disp[c] += h / P.iters * v[c];
     }
     if (O.row_count) O.row_count[sub] = (int)kept.size();
     for (size_t ri = 0; ri < kept.size() && (int)ri < O.r_cap; ++ri) {
@@ -938,6 +956,7 @@ Params read_params(const double* p) {
   P.ml_pri = p[ORC_P_ML_PRI];
   P.guard_c = p[ORC_P_GUARD_C];
   P.guard_l = p[ORC_P_GUARD_L];
+  P.tgs = p[ORC_P_SOLVER] == 1.0 ? 1 : 0;
   return P;
 }
 

@@ -36,7 +36,9 @@ enum {
 /* params vector */
 enum {
   ORC_P_DT = 0, ORC_P_SUBSTEPS, ORC_P_GX, ORC_P_GY, ORC_P_GZ, ORC_P_ITERS, ORC_P_MU, ORC_P_BETA,
-  ORC_P_MC, ORC_P_ML_REV, ORC_P_ML_PRI, ORC_P_GUARD_C, ORC_P_GUARD_L, ORC_P_COLS
+  ORC_P_MC, ORC_P_ML_REV, ORC_P_ML_PRI, ORC_P_GUARD_C, ORC_P_GUARD_L,
+  ORC_P_SOLVER, /* 0 projected Gauss-Seidel, 1 its temporal variant (TGS) */
+  ORC_P_COLS
 };
 /* row key: kind * 2^24 + a * 2^8 + b; kind 1 lower limit / 2 upper limit (a = env DOF index),
  * 3 contact normal / 4 tangent 1 / 5 tangent 2 (a = pair index, b = slot index) */

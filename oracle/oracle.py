@@ -116,7 +116,8 @@ def env_tables(env):
 
 def params_vector(p, guard_c=GUARD_C, guard_l=GUARD_L):
     return np.array([p.dt, p.substeps, *p.gravity, p.pgs_iters, p.mu, p.baumgarte, p.contact_margin,
-                     p.limit_margin_rev, p.limit_margin_pri, guard_c, guard_l], dtype=np.float64)
+                     p.limit_margin_rev, p.limit_margin_pri, guard_c, guard_l, getattr(p, "solver", 0)],
+                    dtype=np.float64)
 
 
 class OracleEnv:

@@ -58,7 +58,7 @@ class SimParams(ctypes.Structure):
                 ("contact_margin", ctypes.c_float), ("limit_margin_rev", ctypes.c_float),
                 ("limit_margin_pri", ctypes.c_float), ("compute_fp64", ctypes.c_int32),
                 ("lanes_per_env", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("adjoint_precision", ctypes.c_int32)]
+                ("adjoint_precision", ctypes.c_int32), ("solver", ctypes.c_int32)]
 
 
 _lib = None
@@ -168,7 +168,7 @@ def sim_params(p, fp64: bool = False, lanes_per_env: int = 0, persistent: bool =
                adjoint_precision: int = 0) -> SimParams:
     return SimParams(p.dt, p.substeps, _f3(p.gravity), p.pgs_iters, p.mu, p.baumgarte, p.contact_margin,
                      p.limit_margin_rev, p.limit_margin_pri, 1 if fp64 else 0, lanes_per_env, 1 if persistent else 0,
-                     adjoint_precision)
+                     adjoint_precision, int(getattr(p, "solver", 0)))
 
 
 class Sim:

@@ -568,6 +568,7 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
   if (!(p->dt > 0) || p->substeps < 1 || p->pgs_iters < 0) return fail(AGS_E_ARG, "sim: bad parameters");
   if (p->adjoint_precision != 0 && p->adjoint_precision != 32 && p->adjoint_precision != 64)
     return fail(AGS_E_ARG, "sim: adjoint_precision must be 0, 32 or 64");
+  if (p->solver != AGS_SOLVER_PGS && p->solver != AGS_SOLVER_TGS) return fail(AGS_E_ARG, "sim: unknown solver");
   *out = nullptr;
   for (int e = 0; e < n_envs; ++e)
     if (env_model[e] < 0 || env_model[e] >= n_models || !models[env_model[e]])
@@ -887,6 +888,7 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
   a.mc = p.contact_margin;
   a.substeps = p.substeps;
   a.iters = p.pgs_iters;
+  a.solver = p.solver;
   auto type_args = [](const TypeDev& T) {
     TypeArgs t{};
     t.m = T.dm;
@@ -922,6 +924,7 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
     return fail(AGS_E_ARG, "step_backward: bad arguments");
   const ags_sim_params& p = S->params;
   if (p.pgs_iters > kAdjIters) return fail(AGS_E_ARG, "step_backward: more Gauss-Seidel sweeps than the adjoint's tape holds (32)");
+  if (p.solver != AGS_SOLVER_PGS) return fail(AGS_E_ARG, "step_backward: the adjoint supports the projected Gauss-Seidel solver only");
   for (const TypeDev& T : S->types) {
     if (T.adj_bytes > 160 * 1024) return fail(AGS_E_ARG, "step_backward: model too large for one workgroup's LDS");
   }

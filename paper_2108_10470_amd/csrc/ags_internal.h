@@ -106,6 +106,7 @@ struct StepArgs {
   long long mid_block;
   double dt, h, gx, gy, gz, mu, beta, mc;
   int substeps, iters;
+  int solver;  // 0 projected Gauss-Seidel, 1 temporal variant
 };
 
 // One launch over every environment type: a grid sized to the device walks a work list of

@@ -408,6 +408,13 @@ __device__ __forceinline__ int actor_of_root(const Tab<R>& M, int link) {
   return a;
 }
 
+// bias of a limit or contact-normal row from its position error C: speculative C / h when separated, the
+// Baumgarte fraction beta C / h when penetrating
+template <typename R>
+__device__ __forceinline__ R row_bias(R C, R h, R beta) {
+  return C >= R(0) ? C / h : beta * C / h;
+}
+
 // rotation matrix (row-major) of a unit quaternion xyzw
 template <typename R>
 __device__ __forceinline__ void quat_R(R qx, R qy, R qz, R qw, R* M) {
@@ -678,6 +685,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   const int nl = M.n_links, nd = M.n_dof, nv = M.n_v, ns = M.n_slots, na = M.n_actors;
   const int abase = P.env_actor_base[env], dbase = P.env_dof_base[env], bbase = P.env_body_base[env];
   const R h = R(P.h);
+  const bool tgs = P.solver == 1;  // temporal Gauss-Seidel variant
   const V3<R> grav = mk(R(P.gx), R(P.gy), R(P.gz));
   R* Jg = reinterpret_cast<R*>(T.scratch) + (long long)gidx * T.scratch_stride;
   R* Wg = Jg + (long long)M.r_cap * nv;
@@ -1037,14 +1045,16 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         }
         const unsigned long long mlo = team_ballot<TEAM>(tm, alo), mhi = team_ballot<TEAM>(tm, ahi);
         const int base = running + __popcll(mlo & lanes_below(tt)) + __popcll(mhi & lanes_below(tt));
+        // rbias: the row's bias, or with the temporal solver its position error (the bias is then formed
+        // before every sweep)
         if (alo) {
           s.rkr[base] = (1 << 16) | j;
-          s.rbias[base] = glo >= R(0) ? glo / h : R(P.beta) * glo / h;
+          s.rbias[base] = tgs ? glo : row_bias(glo, h, R(P.beta));
         }
         if (ahi) {
           const int r = base + alo;
           s.rkr[r] = (2 << 16) | j;
-          s.rbias[r] = ghi >= R(0) ? ghi / h : R(P.beta) * ghi / h;
+          s.rbias[r] = tgs ? ghi : row_bias(ghi, h, R(P.beta));
         }
         running += __popcll(mlo) + __popcll(mhi);
       }
@@ -1058,7 +1068,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           const R phi = s.phi[sl];
           for (int k = 0; k < 3; ++k) {
             s.rkr[base + k] = ((3 + k) << 16) | sl;
-            s.rbias[base + k] = k == 0 ? (phi >= R(0) ? phi / h : R(P.beta) * phi / h) : R(0);
+            s.rbias[base + k] = k == 0 ? (tgs ? phi : row_bias(phi, h, R(P.beta))) : R(0);
           }
         }
         running += 3 * __popcll(m);
@@ -1198,17 +1208,24 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       for (int r = 0; r < FR; ++r) Acol[r] = r < rn_w ? jrow_dot(jr, s.W + r * L.wstride) : R(0);
       R y = jrow_dot(jr, s.vs);
       const bool own = tt < Rn;
-      const R bias = own ? s.rbias[tt] : R(0);
       const R ia = own ? s.rinvA[tt] : R(0);
       const int kindv = own ? (s.rkr[tt] >> 16) : 0;
       const bool fric = kindv >= 4;
       const int nrmv = fric ? tt - (kindv - 3) : -1;
+      // temporal solver: pos is the row's position error, advanced by h / iters J_k v after every sweep
+      R pos = own && tgs ? s.rbias[tt] : R(0);
+      R bias = own ? (tgs ? (fric ? R(0) : row_bias(pos, h, R(P.beta))) : s.rbias[tt]) : R(0);
       // every lane evaluates the update of its own row; the one of row r is applied and its impulse change
       // broadcast.  A friction lane follows its normal row's impulse through those broadcasts and keeps its
       // box bounds +-mu lambda_n.  Rows without a response (1/A_rr = 0: dropped, or lanes past the row count)
       // hold lambda = 0 and their update is a clamp of 0, so they need no test.  c = lambda - b / A_rr.
       R lam = R(0), hi = fric ? R(0) : R(INFINITY), lo = R(0), c = -bias * ia;
+      const R hstep = h / R(max(P.iters, 1));
       for (int it = 0; it < P.iters; ++it) {
+        if (tgs && it > 0 && own && !fric) {
+          bias = row_bias(pos, h, R(P.beta));
+          c = lam - bias * ia;
+        }
         // opaque copies of the lane's row and normal-row indices and of the row count: keeps the per-row
         // compares inside the sweep instead of 3 x FR hoisted (and spilled) masks
         int me = tt, mn = nrmv, rw = rn_w;
@@ -1230,6 +1247,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
             y += Acol[r] * dl;
           }
         }
+        if (tgs) pos += hstep * y;  // y = J_k v at the end of the sweep
       }
       if (own) s.rlam[tt] = lam;
       __syncthreads();
@@ -1240,16 +1258,19 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     } else {
       // lanes over velocity columns, rows streamed from global scratch
       vj = tt < nv ? s.vs[tt] : R(0);
+      const R hstep = h / R(max(P.iters, 1));
       for (int it = 0; it < P.iters; ++it) {
         for (int r = 0; r < Rn; ++r) {
           const R invA = s.rinvA[r];
           if (invA == R(0)) continue;
           const R Jr = tt < nv ? Jg[(long long)r * nv + tt] : R(0);
           const R Wr = tt < nv ? Wg[(long long)r * nv + tt] : R(0);
-          const R res = team_sum<TEAM>(Jr * vj) + s.rbias[r];
+          const int kind = s.rkr[r] >> 16;
+          // temporal solver: rbias holds the position error of limit and normal rows
+          const R b = tgs ? (kind >= 4 ? R(0) : row_bias(s.rbias[r], h, R(P.beta))) : s.rbias[r];
+          const R res = team_sum<TEAM>(Jr * vj) + b;
           const R lam = s.rlam[r];
           R nlam = lam - res * invA;
-          const int kind = s.rkr[r] >> 16;
           if (kind >= 4) {
             const R hi = mu * s.rlam[r - (kind - 3)];
             nlam = min_(max_(nlam, -hi), hi);
@@ -1258,6 +1279,15 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           }
           vj += Wr * (nlam - lam);
           s.rlam[r] = nlam;
+        }
+        if (tgs) {  // advance the position errors by h / iters J_r v
+          for (int r = 0; r < Rn; ++r) {
+            const int kind = s.rkr[r] >> 16;
+            if (s.rinvA[r] == R(0) || kind >= 4) continue;
+            const R Jr = tt < nv ? Jg[(long long)r * nv + tt] : R(0);
+            const R nb = s.rbias[r] + hstep * team_sum<TEAM>(Jr * vj);
+            s.rbias[r] = nb;  // every lane of the team writes the same value
+          }
         }
       }
     }

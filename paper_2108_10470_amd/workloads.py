@@ -156,6 +156,7 @@ class SimParams:
     contact_margin: float = 0.01
     limit_margin_rev: float = 0.05
     limit_margin_pri: float = 0.005
+    solver: int = 0  # 0 projected Gauss-Seidel, 1 its temporal (TGS) variant
 
 
 # ----------------------------------------------------------------------------
@@ -451,4 +452,4 @@ def params_f32(p: SimParams) -> SimParams:
     return SimParams(dt=_r32(p.dt), substeps=p.substeps, gravity=tuple(_r32(g) for g in p.gravity),
                      pgs_iters=p.pgs_iters, mu=_r32(p.mu), baumgarte=_r32(p.baumgarte),
                      contact_margin=_r32(p.contact_margin), limit_margin_rev=_r32(p.limit_margin_rev),
-                     limit_margin_pri=_r32(p.limit_margin_pri))
+                     limit_margin_pri=_r32(p.limit_margin_pri), solver=p.solver)

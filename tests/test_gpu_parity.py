@@ -85,6 +85,54 @@ def test_ant_parity_every_step(fp64, lanes):
     _assert_pass(s) if fp64 else _assert_fp32(s)
 
 
+@pytest.mark.parametrize("lanes", [32, 64])
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_tgs_humanoid_parity_from_oracle_states(fp64, lanes):
+    """Temporal Gauss-Seidel variant (solver 1, Section 3): humanoid-like envs from a TGS oracle rollout,
+    including substeps with more than 32 rows (the row-response slow path, which advances the position
+    errors with cross-lane sums)."""
+    env = W.env_humanoid()
+    p = W.SimParams(solver=1)
+    oe, root, dof, act = PT.oracle_states(env, p, n_envs=32, n_steps=120, every=8)
+    g, o = PT.run(env, p, root, dof, act, oe=oe, fp64=fp64, lanes_per_env=lanes)
+    c = PT.compare(env, p, g, o)
+    s = PT.summarize(c)
+    s["mean_rows"] = float(o["row_count"].mean())
+    s["max_rows"] = int(o["row_count"].max())
+    _report(f"tgs_humanoid_{'fp64' if fp64 else 'fp32'}_l{lanes}", s)
+    assert s["max_rows"] > 32, s
+    _assert_pass(s) if fp64 else _assert_fp32(s)
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_tgs_ant_parity_every_step(fp64):
+    """Temporal variant, ant-like quadruped, 64 envs, every one of 100 steps of a TGS oracle rollout."""
+    env = W.env_ant()
+    p = W.SimParams(solver=1)
+    oe, root, dof, act = PT.oracle_states(env, p, n_envs=64, n_steps=100, every=1)
+    g, o = PT.run(env, p, root, dof, act, oe=oe, fp64=fp64)
+    c = PT.compare(env, p, g, o)
+    s = PT.summarize(c)
+    s["mean_rows"] = float(o["row_count"].mean())
+    _report(f"tgs_ant_{'fp64' if fp64 else 'fp32'}", s)
+    _assert_pass(s) if fp64 else _assert_fp32(s)
+
+
+def test_tgs_differs_from_pgs_and_rejects_the_adjoint():
+    """The temporal variant changes the impulses of penetrating contacts (it is not PGS under another
+    name), and the adjoint, written for projected Gauss-Seidel, refuses a TGS sim with an error."""
+    env = W.env_humanoid()
+    oe, root, dof, act = PT.oracle_states(env, W.SimParams(), n_envs=16, n_steps=120, every=60)
+    g1, _ = PT.run(env, W.SimParams(solver=1), root, dof, act, fp64=True)
+    g0, _ = PT.run(env, W.SimParams(solver=0), root, dof, act, fp64=True)
+    assert np.abs(g1["root"] - g0["root"]).max() > 1e-6
+    sim = ags.Sim([ags.Model(W.as_f32(env))], [0] * 4, W.SimParams(solver=1), device="cuda:0", fp64=True)
+    z = lambda t: torch.zeros_like(t)
+    with pytest.raises(RuntimeError, match="projected Gauss-Seidel"):
+        sim.step_backward(sim.root_state, sim.dof_state, sim.actuation, z(sim.root_state), z(sim.dof_state),
+                          z(sim.actuation))
+
+
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
 def test_hand_cube_parity(fp64):
     """Hand-like tree (24 PD-driven DOFs) holding a free cube: capsule-box contacts with the palm and

@@ -556,6 +556,56 @@ def test_resting_sphere_single_sweep_exact():
     np.testing.assert_allclose(o["contact_force"][0, 0], [0, 0, m * G], rtol=1e-14)
 
 
+@pytest.mark.parametrize("n_iters", [1, 2, 8])
+@pytest.mark.parametrize("case", ["penetrating", "speculative"])
+def test_tgs_single_contact_closed_form(case, n_iters):
+    """Temporal Gauss-Seidel (Section 3) on one frictionless sphere-plane contact, one substep h: a sweep
+    of the single row sets v_k = max(v*, -b(C_k)), and the position error advances by h / N v_k between
+    sweeps.  Penetrating (C_0 = phi_0 < 0, Baumgarte beta): C_k = phi_0 (1 - beta / N)^k, so the final
+    v = -beta phi_0 (1 - beta / N)^(N - 1) / h; speculative (phi_0 > 0, approaching fast): v = -phi_0
+    (1 - 1 / N)^(N - 1) / h.  N = 1 is projected Gauss-Seidel's -beta phi_0 / h and -phi_0 / h."""
+    r = 0.1
+    env = _env([W.free_sphere(radius=r, z=r)])
+    oe = O.OracleEnv(env)
+    p = _params(substeps=1, pgs_iters=n_iters, mu=0.0, solver=1)
+    h, N, beta = p.dt, n_iters, p.baumgarte
+    phi0, vz0 = (-0.01, 0.0) if case == "penetrating" else (0.004, -3.0)
+    root = np.array([[[0, 0, r + phi0, 0, 0, 0, 1, 0, 0, vz0, 0, 0, 0]]])
+    o = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))
+    assert o["row_count"][0, 0] == 3
+    if case == "penetrating":
+        v = -beta * phi0 * (1 - beta / N) ** (N - 1) / h
+    else:
+        v = -phi0 * (1 - 1 / N) ** (N - 1) / h
+    vstar = vz0 - 9.81 * h
+    assert v > vstar + 0.1  # the contact is active in every sweep
+    assert abs(o["root"][0, 0, 9] - v) < 1e-12
+    assert abs(o["root"][0, 0, 2] - (r + phi0 + h * v)) < 1e-12
+    pg = oe.step(_params(substeps=1, pgs_iters=n_iters, mu=0.0, solver=0), root, np.zeros((1, 0, 2)), np.zeros((1, 0)))
+    v_pgs = -(beta if case == "penetrating" else 1.0) * phi0 / h
+    assert abs(pg["root"][0, 0, 9] - v_pgs) < 1e-12
+
+
+def test_tgs_one_sweep_is_pgs():
+    """With a single sweep the temporal variant has accumulated nothing when it builds the biases, so a
+    humanoid step (contacts, limits, friction) equals projected Gauss-Seidel's bit for bit."""
+    env = W.env_humanoid()
+    oe = O.OracleEnv(env)
+    root, dof = W.initial_state(env, 8, 0)
+    acts = W.actuation(env, 8, 60, 0)
+    p = _params(pgs_iters=8)
+    for t in range(60):  # fall to the ground
+        o = oe.step(p, root, dof, acts[t])
+        root, dof = o["root"], o["dof"]
+    a = oe.step(_params(pgs_iters=1, solver=0), root, dof, acts[0])
+    b = oe.step(_params(pgs_iters=1, solver=1), root, dof, acts[0])
+    assert a["row_count"].max() > 10
+    for k in ("root", "dof", "row_lambda", "row_key", "contact_force"):
+        assert np.array_equal(a[k], b[k]), k
+    c = oe.step(_params(pgs_iters=8, solver=1), root, dof, acts[0])
+    assert np.abs(c["row_lambda"] - oe.step(_params(pgs_iters=8, solver=0), root, dof, acts[0])["row_lambda"]).max() > 1e-6
+
+
 def test_sphere_slides_then_rolls_closed_form():
     """Coulomb friction on a sliding sphere: dv = -mu g h, dw = 5 mu g h / (2 r) per substep until
     rolling (v = w r, reached at v = 5/7 u)."""
