@@ -74,7 +74,8 @@ def parse():
                     help="checkpoint interval of the secondary (recomputing) forward+adjoint measurement")
     ap.add_argument("--fwd-bwd-reps", type=int, default=3)
     ap.add_argument("--no-hetero", action="store_true", help="skip the heterogeneous-batch measurement")
-    ap.add_argument("--no-tgs", action="store_true", help="skip the temporal Gauss-Seidel variant's measurement")
+    ap.add_argument("--no-tgs", action="store_true",
+                    help="skip the temporal Gauss-Seidel and randomized-property variants' measurements")
     ap.add_argument("--hetero-envs", type=int, default=16384)
     ap.add_argument("--hetero-steps", type=int, default=100)
     ap.add_argument("--no-hand", action="store_true", help="skip the 65536-env hand+cube measurement")
@@ -85,11 +86,17 @@ def parse():
     return ap.parse_args()
 
 
-def run_gpu(env, params, n_envs, steps, warmup, fp64, actions_dev, root0, dof0):
+def run_gpu(env, params, n_envs, steps, warmup, fp64, actions_dev, root0, dof0, props=None):
     import torch
     from paper_2108_10470_amd import ags
     model = ags.Model(env)
     sim = ags.Sim([model], [0] * n_envs, params, device="cuda:0", fp64=fp64)
+    if props is not None:  # per-env property tensors (domain randomization)
+        t = {k: torch.tensor(v, dtype=torch.float32, device="cuda:0") for k, v in props.items()}
+        sim.set_properties(mass_scale=t["mass_scale"].reshape(-1).contiguous(),
+                           stiffness=t["stiffness"].reshape(-1).contiguous(),
+                           damping=t["damping"].reshape(-1).contiguous(), limits=t["limits"].reshape(-1, 2).contiguous(),
+                           friction=t["friction"].contiguous(), gravity=t["gravity"].contiguous())
     sim.root_state.copy_(root0)
     sim.dof_state.copy_(dof0)
     stream = torch.cuda.current_stream()
@@ -449,6 +456,15 @@ def main():
         tgs = {"env_steps_per_s": E * K / (r["total_ms"] / 1e3), "ms_per_step": r["total_ms"] / K,
                "launch_ms": float(r["launch_ms"].mean()), "finite": r["finite"], "dtype": head.replace("fp", "f")}
         print(f"[bench] tgs: {json.dumps(tgs)}", file=sys.stderr, flush=True)
+    randomized = None
+    if not args.no_tgs:  # every property tensor bound (masses, gains, limits, friction, gravity per env)
+        from paper_2108_10470_amd import workloads as W_
+        r = run_gpu(env, params, E, K, Wm, head == "fp64", actions_dev, root0, dof0,
+                    props=W_.random_properties(env, params, E, seed=0))
+        randomized = {"env_steps_per_s": E * K / (r["total_ms"] / 1e3), "ms_per_step": r["total_ms"] / K,
+                      "launch_ms": float(r["launch_ms"].mean()), "finite": r["finite"],
+                      "dtype": head.replace("fp", "f")}
+        print(f"[bench] randomized properties: {json.dumps(randomized)}", file=sys.stderr, flush=True)
     jacmass = run_jacmass(env, params, E, root0, dof0)
     print(f"[bench] jacobian+mass: {json.dumps(jacmass)}", file=sys.stderr, flush=True)
     fwd_bwd = None
@@ -494,6 +510,7 @@ def main():
         "hand": hand,
         "jacobian_mass": jacmass,
         "tgs": tgs,
+        "randomized_properties": randomized,
         "variants": {k: {"env_steps_per_s": E * K / (v["total_ms"] / 1e3), "ms_per_step": v["total_ms"] / K,
                          "launch_ms": float(v["launch_ms"].mean()), "mean_rows_per_substep": v["rows"],
                          "graph_ms_per_step": v["graph_ms"],

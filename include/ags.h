@@ -166,12 +166,24 @@ void ags_sim_destroy(ags_sim* sim);
  *   AGS_DEBUG_PHASE_CYCLES (E, 10)  int64                shader-clock cycles per phase of the step (controls,
  *                          forward sweep, inward sweep, outward sweep, v* sweep, narrow phase, rows,
  *                          row responses, Gauss-Seidel, outputs), for profiling
+ * Per-env physical properties (domain randomization, Section 2: copies of an environment may vary;
+ * the paper's hand setup randomizes masses, friction, joint limits, drive gains and gravity).  When
+ * bound they replace the model's or the parameters' value for each env; unbound, the model's apply.
+ * Read by ags_sim_step and ags_sim_jacobian_mass (mass scale); ags_sim_step_backward refuses a sim with
+ * any of them bound.
+ *   AGS_BODY_MASS_SCALE    (N_B, 1)   factor on each link's mass and rotational inertia (COM unchanged)
+ *   AGS_DOF_STIFFNESS      (N_D, 1)   drive kp of each DOF
+ *   AGS_DOF_DAMPING        (N_D, 1)   drive kd of each DOF
+ *   AGS_DOF_LIMITS         (N_D, 2)   lower, upper limit of each DOF (+-infinity: none)
+ *   AGS_ENV_FRICTION       (E, 1)     friction coefficient mu of each env
+ *   AGS_ENV_GRAVITY        (E, 3)     gravity vector of each env
  * Outputs and debug tensors are written only when bound.  N_A, N_D and N_B count actors, DOFs
  * and links of all environments. */
 enum {
   AGS_ROOT_STATE = 0, AGS_DOF_STATE, AGS_DOF_ACTUATION, AGS_DOF_POS_TARGET, AGS_DOF_VEL_TARGET,
   AGS_NET_CONTACT_FORCE, AGS_DOF_FORCE, AGS_DEBUG_QDD_FREE, AGS_DEBUG_ROW_COUNT, AGS_DEBUG_ROW_KEY,
   AGS_DEBUG_ROW_LAMBDA, AGS_DEBUG_PHASE_CYCLES, AGS_DEBUG_ADJ_CYCLES, AGS_RIGID_BODY_STATE, AGS_ENV_STATUS,
+  AGS_BODY_MASS_SCALE, AGS_DOF_STIFFNESS, AGS_DOF_DAMPING, AGS_DOF_LIMITS, AGS_ENV_FRICTION, AGS_ENV_GRAVITY,
   AGS_NUM_TENSORS
 };
 int ags_sim_tensor_shape(const ags_sim* sim, int32_t which, int64_t* rows, int64_t* cols);

@@ -21,7 +21,8 @@ SHAPE = {"sphere": 0, "capsule": 1, "box": 2}
 
 ROOT_STATE, DOF_STATE, DOF_ACTUATION, DOF_POS_TARGET, DOF_VEL_TARGET, NET_CONTACT_FORCE, DOF_FORCE, \
     DEBUG_QDD_FREE, DEBUG_ROW_COUNT, DEBUG_ROW_KEY, DEBUG_ROW_LAMBDA, DEBUG_PHASE_CYCLES, DEBUG_ADJ_CYCLES, \
-    RIGID_BODY_STATE, ENV_STATUS, NUM_TENSORS = range(16)
+    RIGID_BODY_STATE, ENV_STATUS, BODY_MASS_SCALE, DOF_STIFFNESS, DOF_DAMPING, DOF_LIMITS, ENV_FRICTION, \
+    ENV_GRAVITY, NUM_TENSORS = range(22)
 PHASES = ["controls", "forward", "inward", "outward", "vstar", "narrow", "rows", "responses", "pgs", "outputs"]
 
 
@@ -256,6 +257,26 @@ class Sim:
                 raise ValueError("status: expected an int32 tensor with one entry per environment")
             st = ctypes.c_void_p(status.data_ptr())
         _check(lib().ags_sim_step_backward(self.h, *args, st, ctypes.c_void_p(s.cuda_stream)), "ags_sim_step_backward")
+
+    def set_properties(self, mass_scale=None, stiffness=None, damping=None, limits=None, friction=None,
+                       gravity=None):
+        """Bind per-env property tensors (domain randomization; see ags.h): (N_B,) link mass factors, (N_D,)
+        drive kp and kd, (N_D, 2) limits, (E,) friction, (E, 3) gravity.  A None argument leaves that
+        property as it is; pass a tensor to replace the model's value, or call unbind_properties()."""
+        for which, t, shape in ((BODY_MASS_SCALE, mass_scale, (self.shapes[BODY_MASS_SCALE][0],)),
+                                (DOF_STIFFNESS, stiffness, (self.shapes[DOF_STIFFNESS][0],)),
+                                (DOF_DAMPING, damping, (self.shapes[DOF_DAMPING][0],)),
+                                (DOF_LIMITS, limits, self.shapes[DOF_LIMITS]),
+                                (ENV_FRICTION, friction, (self.n_envs,)),
+                                (ENV_GRAVITY, gravity, (self.n_envs, 3))):
+            if t is not None:
+                self._dev_f32(t, shape, "property tensor")
+                self.bind(which, t)
+
+    def unbind_properties(self):
+        for which in (BODY_MASS_SCALE, DOF_STIFFNESS, DOF_DAMPING, DOF_LIMITS, ENV_FRICTION, ENV_GRAVITY):
+            lib().ags_sim_bind(self.h, which, ctypes.c_void_p(0))
+            self.tensors.pop(which, None)
 
     def jacobian_mass(self, model: int = 0, jacobian: bool = True, mass: bool = True,
                       stream: Optional[torch.cuda.Stream] = None):

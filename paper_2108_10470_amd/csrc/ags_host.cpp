@@ -830,6 +830,11 @@ extern "C" int ags_sim_tensor_shape(const ags_sim* S, int32_t which, int64_t* ro
     case AGS_NET_CONTACT_FORCE: *rows = S->n_bodies_total; *cols = 3; break;
     case AGS_RIGID_BODY_STATE: *rows = S->n_bodies_total; *cols = 13; break;
     case AGS_ENV_STATUS: *rows = S->n_envs; *cols = 1; break;
+    case AGS_BODY_MASS_SCALE: *rows = S->n_bodies_total; *cols = 1; break;
+    case AGS_DOF_STIFFNESS: case AGS_DOF_DAMPING: *rows = S->n_dof_total; *cols = 1; break;
+    case AGS_DOF_LIMITS: *rows = S->n_dof_total; *cols = 2; break;
+    case AGS_ENV_FRICTION: *rows = S->n_envs; *cols = 1; break;
+    case AGS_ENV_GRAVITY: *rows = S->n_envs; *cols = 3; break;
     case AGS_DEBUG_QDD_FREE: *rows = S->n_envs; *cols = (int64_t)sub * S->max_nv; break;
     case AGS_DEBUG_ROW_COUNT: *rows = S->n_envs; *cols = sub; break;
     case AGS_DEBUG_ROW_KEY: case AGS_DEBUG_ROW_LAMBDA: *rows = S->n_envs; *cols = (int64_t)sub * std::max(1, S->max_rows); break;
@@ -865,6 +870,12 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
   a.rb_state = (float*)S->bound[AGS_RIGID_BODY_STATE];
   a.env_status = (int*)S->bound[AGS_ENV_STATUS];
   a.big_rows = S->big_out;
+  a.mass_scale = (const float*)S->bound[AGS_BODY_MASS_SCALE];
+  a.dof_kp = (const float*)S->bound[AGS_DOF_STIFFNESS];
+  a.dof_kd = (const float*)S->bound[AGS_DOF_DAMPING];
+  a.dof_limits = (const float*)S->bound[AGS_DOF_LIMITS];
+  a.env_mu = (const float*)S->bound[AGS_ENV_FRICTION];
+  a.env_gravity = (const float*)S->bound[AGS_ENV_GRAVITY];
   a.dof_force = (float*)S->bound[AGS_DOF_FORCE];
   a.dbg_qdd = (float*)S->bound[AGS_DEBUG_QDD_FREE];
   a.dbg_qdd_stride = p.substeps * S->max_nv;
@@ -917,6 +928,16 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
   return AGS_OK;
 }
 
+namespace {
+// what the adjoint does not differentiate, or NULL
+const char* adjoint_unsupported(const ags_sim* S) {
+  if (S->params.solver != AGS_SOLVER_PGS) return "adjoint: supports the projected Gauss-Seidel solver only";
+  for (int w = AGS_BODY_MASS_SCALE; w <= AGS_ENV_GRAVITY; ++w)
+    if (S->bound[w]) return "adjoint: per-env property tensors are not supported";
+  return nullptr;
+}
+}  // namespace
+
 extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const float* dof_state,
                                      const float* actuation, float* root_adj, float* dof_adj, float* act_adj,
                                      int32_t* status, void* stream) {
@@ -924,7 +945,7 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
     return fail(AGS_E_ARG, "step_backward: bad arguments");
   const ags_sim_params& p = S->params;
   if (p.pgs_iters > kAdjIters) return fail(AGS_E_ARG, "step_backward: more Gauss-Seidel sweeps than the adjoint's tape holds (32)");
-  if (p.solver != AGS_SOLVER_PGS) return fail(AGS_E_ARG, "step_backward: the adjoint supports the projected Gauss-Seidel solver only");
+  if (const char* why = adjoint_unsupported(S)) return fail(AGS_E_ARG, why);
   for (const TypeDev& T : S->types) {
     if (T.adj_bytes > 160 * 1024) return fail(AGS_E_ARG, "step_backward: model too large for one workgroup's LDS");
   }
@@ -1018,6 +1039,8 @@ extern "C" int ags_sim_jacobian_mass(ags_sim* S, int32_t model, float* jac, floa
   a.dof_state = (const float*)S->bound[AGS_DOF_STATE];
   a.jac = jac;
   a.mass = mass;
+  a.env_body_base = S->env_tables + 2 * S->n_envs;
+  a.mass_scale = (const float*)S->bound[AGS_BODY_MASS_SCALE];
   const hipError_t e = launch_jacmass(a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "jacobian_mass: launch");
   return AGS_OK;
@@ -1055,7 +1078,7 @@ long long seg_one_bytes(const ags_sim* S, int every) {
 int step_on(ags_sim* S, float* root, float* dof, int control, const float* ctrl, hipStream_t stream) {
   void* saved[AGS_NUM_TENSORS];
   std::memcpy(saved, S->bound, sizeof(saved));
-  for (int w = AGS_NET_CONTACT_FORCE; w < AGS_NUM_TENSORS; ++w) S->bound[w] = nullptr;
+  for (int w = AGS_NET_CONTACT_FORCE; w <= AGS_ENV_STATUS; ++w) S->bound[w] = nullptr;  // outputs only
   S->bound[AGS_ROOT_STATE] = root;
   S->bound[AGS_DOF_STATE] = dof;
   S->bound[control] = const_cast<float*>(ctrl);
@@ -1154,6 +1177,7 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
       (control != AGS_DOF_ACTUATION && control != AGS_DOF_POS_TARGET))
     return fail(AGS_E_ARG, "rollout_backward: bad arguments");
   if (!S->bound[AGS_DOF_ACTUATION]) return fail(AGS_E_UNBOUND, "rollout_backward: the actuation tensor must be bound");
+  if (const char* why = adjoint_unsupported(S)) return fail(AGS_E_ARG, why);
   const size_t nr = 13ull * S->n_actors_total, nd = 2ull * S->n_dof_total, sw = nr + nd;
   const size_t na = (size_t)S->n_dof_total;
   const int nmid = std::max(0, S->params.substeps - 1);
@@ -1256,6 +1280,7 @@ extern "C" int ags_rollout_backward_tape(ags_sim* S, int32_t n_steps, int32_t co
       (control != AGS_DOF_ACTUATION && control != AGS_DOF_POS_TARGET))
     return fail(AGS_E_ARG, "rollout_backward_tape: bad arguments");
   if (!S->bound[AGS_DOF_ACTUATION]) return fail(AGS_E_UNBOUND, "rollout_backward_tape: the actuation tensor must be bound");
+  if (const char* why = adjoint_unsupported(S)) return fail(AGS_E_ARG, why);
   hipError_t e = ensure_streams(S);
   if (e != hipSuccess) return hip_fail(e, "rollout_backward_tape: streams");
   float* x;

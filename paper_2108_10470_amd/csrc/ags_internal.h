@@ -91,6 +91,14 @@ struct StepArgs {
   float* rb_state;  // optional (N_B, 13): link origin, quaternion, origin velocity, angular velocity
   int* env_status;  // optional (E): bit 0 non-finite new state, bit 1 row-response slow path taken
   int* big_rows;    // optional (E): 1 where a substep had more than kAdjBigRowsAt rows (adjoint layout hint)
+  // optional per-env properties replacing the model's: link mass / inertia factor (N_B), drive kp, kd (N_D),
+  // limits (N_D x 2), friction (E), gravity (E x 3)
+  const float* mass_scale;
+  const float* dof_kp;
+  const float* dof_kd;
+  const float* dof_limits;
+  const float* env_mu;
+  const float* env_gravity;
   float* dof_force;
   float* dbg_qdd;
   int dbg_qdd_stride, dbg_qdd_sub;  // per env, per substep (sim-wide maximum n_v)
@@ -133,6 +141,8 @@ struct JacMassArgs {
   const float* dof_state;
   float* jac;   // optional: n_envs x n_links x 6 x n_v
   float* mass;  // optional: n_envs x n_v x n_v
+  const int* env_body_base;
+  const float* mass_scale;  // optional (N_B): per-link factor on mass and inertia
 };
 size_t jacmass_lds_bytes(int n_links);
 hipError_t launch_jacmass(const JacMassArgs& a, hipStream_t stream);

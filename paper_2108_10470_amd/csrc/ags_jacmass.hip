@@ -100,7 +100,7 @@ __global__ __launch_bounds__(64) void jacmass_kernel(JacMassArgs A) {
   const int ei = blockIdx.x;
   if (ei >= A.n_envs) return;
   const int env = A.env_list[ei];
-  const int abase = A.env_actor_base[env], dbase = A.env_dof_base[env];
+  const int abase = A.env_actor_base[env], dbase = A.env_dof_base[env], bbase = A.env_body_base[env];
   const Kin K = kin_arrays(g_jm_lds, nl);
   // 1. forward kinematics, one level at a time
   for (int lv = 0; lv < M.n_levels; ++lv) {
@@ -184,7 +184,8 @@ __global__ __launch_bounds__(64) void jacmass_kernel(JacMassArgs A) {
         D3 vk, wk, vl, wl;
         column(M, K, b, k, cb, vk, wk);
         column(M, K, b, l, cb, vl, wl);
-        m += M.lf[b * LF_COLS + LF_MASS] * dot(vk, vl) + dot(wk, sv(K.I + 6 * b, wl));
+        const double sc = A.mass_scale ? double(A.mass_scale[bbase + b]) : 1.0;
+        m += sc * (M.lf[b * LF_COLS + LF_MASS] * dot(vk, vl) + dot(wk, sv(K.I + 6 * b, wl)));
       }
       out[(long long)k * nv + l] = (float)m;
       out[(long long)l * nv + k] = (float)m;

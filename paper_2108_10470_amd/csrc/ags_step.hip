@@ -686,7 +686,8 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   const int abase = P.env_actor_base[env], dbase = P.env_dof_base[env], bbase = P.env_body_base[env];
   const R h = R(P.h);
   const bool tgs = P.solver == 1;  // temporal Gauss-Seidel variant
-  const V3<R> grav = mk(R(P.gx), R(P.gy), R(P.gz));
+  const V3<R> grav = P.env_gravity ? mk(R(P.env_gravity[3 * env]), R(P.env_gravity[3 * env + 1]), R(P.env_gravity[3 * env + 2]))
+                                   : mk(R(P.gx), R(P.gy), R(P.gz));
   R* Jg = reinterpret_cast<R*>(T.scratch) + (long long)gidx * T.scratch_stride;
   R* Wg = Jg + (long long)M.r_cap * nv;
 
@@ -732,7 +733,8 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       const int c = M.li[lk * LI_COLS + LI_COL];
       const R pt = P.pos_tgt ? R(P.pos_tgt[dbase + j]) : R(0);
       const R vt = P.vel_tgt ? R(P.vel_tgt[dbase + j]) : R(0);
-      const R kp = R(lf[LF_KP]), kd = R(lf[LF_KD]);
+      const R kp = R(P.dof_kp ? double(P.dof_kp[dbase + j]) : lf[LF_KP]);
+      const R kd = R(P.dof_kd ? double(P.dof_kd[dbase + j]) : lf[LF_KD]);
       s.tau[c] = R(P.act[dbase + j]) + kp * (pt - s.qj[j] - h * s.qd[c]) + kd * (vt - s.qd[c]);
       s.arm[c] = R(lf[LF_ARM]) + h * kd + h * h * kp;
     }
@@ -748,10 +750,12 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         V3<R> o, w, vl, ax;
         link_kinematics(M, s, i, origin, Rw, qq, o, w, vl, ax);
         // spatial inertia about o (world axes): A = Ic_w + m (|d|^2 1 - d d^T), B = m d^, M = m 1
-        const R m = R(lf[LF_MASS]);
+        const double msc = P.mass_scale ? double(P.mass_scale[bbase + i]) : 1.0;  // per-env mass factor
+        const R m = R(lf[LF_MASS] * msc);
         const V3<R> d = mv(Rw, ld3<R>(lf + LF_COM));
         const double* Icl = lf + LF_IC;
-        const R Ic[9] = {R(Icl[0]), R(Icl[3]), R(Icl[4]), R(Icl[3]), R(Icl[1]), R(Icl[5]), R(Icl[4]), R(Icl[5]), R(Icl[2])};
+        const R Ic[9] = {R(Icl[0] * msc), R(Icl[3] * msc), R(Icl[4] * msc), R(Icl[3] * msc), R(Icl[1] * msc),
+                         R(Icl[5] * msc), R(Icl[4] * msc), R(Icl[5] * msc), R(Icl[2] * msc)};
         R Tm[9], Iw[9];
         mm3(Rw, Ic, Tm);
 #pragma unroll
@@ -1034,12 +1038,14 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           const double* lf = M.lf + lk * LF_COLS;
           const R vs = s.vs[M.li[lk * LI_COLS + LI_COL]];
           const R ml = R(lf[LF_ML]), q = s.qj[j];
-          if (isfinite(lf[LF_LO])) {
-            glo = q - R(lf[LF_LO]);
+          const double lo = P.dof_limits ? double(P.dof_limits[2 * (dbase + j)]) : lf[LF_LO];
+          const double hi = P.dof_limits ? double(P.dof_limits[2 * (dbase + j) + 1]) : lf[LF_HI];
+          if (isfinite(lo)) {
+            glo = q - R(lo);
             alo = min_(glo, glo + h * vs) < ml;
           }
-          if (isfinite(lf[LF_HI])) {
-            ghi = R(lf[LF_HI]) - q;
+          if (isfinite(hi)) {
+            ghi = R(hi) - q;
             ahi = min_(ghi, ghi - h * vs) < ml;
           }
         }
@@ -1197,7 +1203,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 
     PHASE_MARK(8);
     // ---------------------------------------------------- projected Gauss-Seidel
-    const R mu = R(P.mu);
+    const R mu = R(P.env_mu ? double(P.env_mu[env]) : P.mu);
     R vj;
     if (fast) {
       // Delassus form, one row per lane: lane k holds y_k = J_k v and column k of A = J M~^-1 J^T
@@ -1348,7 +1354,9 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       const R pt = P.pos_tgt ? R(P.pos_tgt[dbase + j]) : R(0);
       const R vt = P.vel_tgt ? R(P.vel_tgt[dbase + j]) : R(0);
       const R qdp = s.qd[c];
-      dof_force_acc += R(P.act[dbase + j]) + R(lf[LF_KP]) * (pt - s.qj[j] - h * qdp) + R(lf[LF_KD]) * (vt - qdp);
+      const R kp = R(P.dof_kp ? double(P.dof_kp[dbase + j]) : lf[LF_KP]);
+      const R kd = R(P.dof_kd ? double(P.dof_kd[dbase + j]) : lf[LF_KD]);
+      dof_force_acc += R(P.act[dbase + j]) + kp * (pt - s.qj[j] - h * qdp) + kd * (vt - qdp);
       s.qj[j] += h * qdp;
     }
     // free roots: p+ = p + h v+, quat+ = normalize(Exp(h w+) (x) quat)

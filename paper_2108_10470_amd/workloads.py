@@ -54,6 +54,7 @@ STREAM_INIT_Q = 2
 STREAM_ACTIONS = 3
 STREAM_TARGETS = 4
 STREAM_PERTURB = 5
+STREAM_PROPS = 6
 
 
 # ----------------------------------------------------------------------------
@@ -445,6 +446,71 @@ def as_f32(env: EnvSpec) -> EnvSpec:
                 sh.radius = _r32(sh.radius)
                 sh.density = _r32(sh.density)
     return e
+
+
+def _normal(seed: int, stream: int, shape) -> np.ndarray:
+    """Standard normals by Box-Muller from two uniform streams."""
+    u1 = uniform(seed, stream, shape, 0.0, 1.0)
+    u2 = uniform(seed, stream + 1000, shape, 0.0, 1.0)
+    return np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def random_properties(env: EnvSpec, params: SimParams, n_envs: int, seed: int = 0) -> dict:
+    """Per-env physical properties drawn as in the paper's table of physics randomizations (hand
+    experiments): link masses x U[0.5, 1.5], friction x U[0.7, 1.3], joint damping x loguniform[0.3, 3],
+    drive stiffness (P gain) x loguniform[0.75, 1.5], joint limits + N(0, 0.15) (radians; prismatic limits
+    scaled to metres by 0.1), gravity + N(0, 0.4) per coordinate.  Float32 arrays shaped like the sim's
+    property tensors: mass_scale (E, N_B/E), stiffness, damping (E, D), limits (E, D, 2), friction (E,),
+    gravity (E, 3).  Limits stay ordered (lower <= upper)."""
+    nb, nd = env.n_bodies, env.n_dof
+    base = seed * 16 + 7
+    links = [l for a in env.actors for l in a.links[1:]]
+    kp = np.array([l.kp for l in links])
+    kd = np.array([l.kd for l in links])
+    lo = np.array([l.lower for l in links])
+    hi = np.array([l.upper for l in links])
+    scale_lim = np.array([0.1 if l.joint == "prismatic" else 1.0 for l in links])
+    lu = lambda k, a, b: np.exp(uniform(base, STREAM_PROPS * 100 + k, (n_envs, nd), np.log(a), np.log(b)))
+    dlo = 0.15 * scale_lim * _normal(base, STREAM_PROPS * 100 + 3, (n_envs, nd))
+    dhi = 0.15 * scale_lim * _normal(base, STREAM_PROPS * 100 + 4, (n_envs, nd))
+    nlo, nhi = lo + dlo, hi + dhi
+    swap = nlo > nhi
+    nlo[swap], nhi[swap] = (nlo[swap] + nhi[swap]) / 2, (nlo[swap] + nhi[swap]) / 2
+    out = {
+        "mass_scale": uniform(base, STREAM_PROPS * 100 + 0, (n_envs, nb), 0.5, 1.5),
+        "stiffness": kp * lu(1, 0.75, 1.5),
+        "damping": kd * lu(2, 0.3, 3.0),
+        "limits": np.stack([nlo, nhi], axis=-1),
+        "friction": params.mu * uniform(base, STREAM_PROPS * 100 + 5, (n_envs,), 0.7, 1.3),
+        "gravity": np.array(params.gravity) + 0.4 * _normal(base, STREAM_PROPS * 100 + 6, (n_envs, 3)),
+    }
+    return {k: v.astype(np.float32) for k, v in out.items()}
+
+
+def env_with_properties(env: EnvSpec, params: SimParams, props: dict, e: int):
+    """The model and parameters that env e of a batch with per-env properties `props` (as returned by
+    random_properties, float32) simulates: link masses and inertias scaled by scaling every shape's density
+    (and a given mass), drive gains and limits replaced, friction and gravity in the parameters."""
+    import copy
+    import dataclasses
+    spec = copy.deepcopy(env)
+    b = d = 0
+    for a in spec.actors:
+        for i, l in enumerate(a.links):
+            s = float(props["mass_scale"][e, b])
+            if l.mass > 0:
+                l.mass = l.mass * s
+            for sh in l.shapes:
+                sh.density = sh.density * s
+            if i > 0:
+                l.kp = float(props["stiffness"][e, d])
+                l.kd = float(props["damping"][e, d])
+                l.lower = float(props["limits"][e, d, 0])
+                l.upper = float(props["limits"][e, d, 1])
+                d += 1
+            b += 1
+    p = dataclasses.replace(params, mu=float(props["friction"][e]), gravity=tuple(float(g) for g in props["gravity"][e]))
+    return spec, p
 
 
 def params_f32(p: SimParams) -> SimParams:
