@@ -93,6 +93,26 @@ int ags_model_create(const ags_actor_desc* actors, int32_t n_actors, const ags_p
                      int32_t n_pairs, ags_model** out);
 void ags_model_destroy(ags_model* model);
 
+/* Fixed tendon (appendix on tendons: a mechanism coupling DOFs of one articulation).  A tree of n_joints
+ * tendon joints, each following the incoming 1-DOF joint of link[j] (actor-local, not the root) with
+ * coefficient coef[j]; parent[j] is its parent tendon joint (-1 for the root; parents listed first).  The
+ * length at joint j is l_j = l_parent + coef[j] q_link[j].  At every tendon joint the force
+ * f_j = stiffness (l_j - rest_length) + damping dl_j/dt, plus limit_stiffness (l_j - upper) above upper and
+ * limit_stiffness (l_j - lower) below lower, acts on each DOF of the path from the tendon's root to j as
+ * the generalized force -f_j coef.  Forces are explicit: evaluated at the state at the start of each
+ * substep (stable while (stiffness + limit_stiffness) h^2 is small against the joints' effective
+ * inertia).  The adjoint does not support models with tendons. */
+typedef struct {
+  int32_t actor, n_joints;
+  const int32_t* link;
+  const int32_t* parent;
+  const float* coef;
+  float stiffness, damping, rest_length, lower, upper, limit_stiffness;
+} ags_tendon_desc;
+/* Add fixed tendons to a model (before any sim is created from it).  Errors: AGS_E_ARG (bad pointers),
+ * AGS_E_MODEL (actor, link or parent out of range, a root link, a parent listed after its child). */
+int ags_model_add_tendons(ags_model* model, const ags_tendon_desc* tendons, int32_t n_tendons);
+
 typedef struct {
   int32_t n_actors, n_links, n_dof, n_v, n_slots, max_rows;
 } ags_model_info;

@@ -259,9 +259,18 @@ struct Pair {
   int aa, al, as, ba, bl, bs;  // as/bs are actor-local shape indices
 };
 
+// fixed tendon (appendix on tendons): a tree of tendon joints, each following one DOF with a coefficient;
+// the length at a tendon joint is its parent's length plus coefficient x joint position
+struct Tendon {
+  std::vector<int> dof, parent;  // per tendon joint: env DOF index, parent tendon joint (-1 root)
+  std::vector<double> coef;
+  double k, d, rest, lo, hi, klim;
+};
+
 struct Env {
   std::vector<Actor> actors;
   std::vector<Pair> pairs;
+  std::vector<Tendon> tendons;
   int n_dof = 0, n_v = 0, n_bodies = 0, n_slots = 0, max_rows = 0;
 };
 
@@ -743,6 +752,24 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
       tau[c] = act[j] + L->kp * (pos_tgt[j] - qj[j] - h * qd[c]) + L->kd * (vel_tgt[j] - qd[c]);
       arm[c] = L->armature + h * L->kd + h * h * L->kp;
     }
+    // fixed tendons: at each tendon joint a spring-damper on the length l (stiffness k about the rest length,
+    // damping d on dl/dt) plus a limit spring klim beyond [lo, hi]; the force f acts on every DOF of the path
+    // from the tendon's root to that joint as the generalized force -f dl/dq = -f coef
+    for (const Tendon& T : E.tendons) {
+      const int n = (int)T.dof.size();
+      std::vector<double> len(n), rate(n);
+      for (int j = 0; j < n; ++j) {
+        const int c = dcol[T.dof[j]];
+        len[j] = (T.parent[j] >= 0 ? len[T.parent[j]] : 0.0) + T.coef[j] * qj[T.dof[j]];
+        rate[j] = (T.parent[j] >= 0 ? rate[T.parent[j]] : 0.0) + T.coef[j] * qd[c];
+      }
+      for (int j = 0; j < n; ++j) {
+        double f = T.k * (len[j] - T.rest) + T.d * rate[j];
+        if (len[j] > T.hi) f += T.klim * (len[j] - T.hi);
+        if (len[j] < T.lo) f += T.klim * (len[j] - T.lo);
+        for (int p = j; p >= 0; p = T.parent[p]) tau[dcol[T.dof[p]]] -= f * T.coef[p];
+      }
+    }
     // M~ = blockdiag(M_actor) + diag(a~);  C from RNEA with qdd = 0
     std::vector<double> M(nv * nv, 0.0), C(nv, 0.0), zero(nv, 0.0);
     for (int ai = 0; ai < na; ++ai) {
@@ -964,6 +991,23 @@ Params read_params(const double* p) {
 
 // ====================================================================== C API
 extern "C" {
+
+void orc_env_set_tendons(void* env, int n_tendons, const double* params, int n_joints, const double* joints) {
+  Env& E = *static_cast<Env*>(env);
+  E.tendons.assign(n_tendons, Tendon{});
+  for (int t = 0; t < n_tendons; ++t) {
+    const double* p = params + 6 * t;
+    Tendon& T = E.tendons[t];
+    T.k = p[0]; T.d = p[1]; T.rest = p[2]; T.lo = p[3]; T.hi = p[4]; T.klim = p[5];
+  }
+  for (int j = 0; j < n_joints; ++j) {
+    const double* r = joints + 4 * j;
+    Tendon& T = E.tendons[(int)r[0]];
+    T.dof.push_back((int)r[1]);
+    T.parent.push_back((int)r[2]);
+    T.coef.push_back(r[3]);
+  }
+}
 
 void* orc_env_create(int n_actors, int n_links, const double* links, int n_shapes, const double* shapes,
                      int n_pairs, const int* pairs, char* err, int errlen) {

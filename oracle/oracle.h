@@ -51,6 +51,10 @@ enum {
 void* orc_env_create(int n_actors, int n_links, const double* links, int n_shapes, const double* shapes,
                      int n_pairs, const int* pairs, char* err, int errlen);
 void orc_env_destroy(void* env);
+/* fixed tendons (appendix on tendons): params n_tendons x 6 (stiffness, damping, rest length, lower, upper,
+ * limit stiffness); joints n_joints x 4 (tendon, env DOF index, parent tendon joint within the tendon or -1,
+ * coefficient), each tendon's joints in tree order (a parent before its children) */
+void orc_env_set_tendons(void* env, int n_tendons, const double* params, int n_joints, const double* joints);
 /* sizes: out[0]=n_dof, [1]=n_v, [2]=n_bodies, [3]=n_actors, [4]=max rows per substep, [5]=n_slots */
 void orc_env_sizes(const void* env, int* out);
 

@@ -54,6 +54,7 @@ def lib():
                                      ctypes.c_char_p, ctypes.c_int]
         L.orc_env_destroy.argtypes = [ctypes.c_void_p]
         L.orc_env_sizes.argtypes = [ctypes.c_void_p, ip]
+        L.orc_env_set_tendons.argtypes = [ctypes.c_void_p, ctypes.c_int, dp, ctypes.c_int, dp]
         L.orc_mass_props.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.orc_fk.argtypes = [ctypes.c_void_p, dp, dp, dp, dp]
         L.orc_body_states.argtypes = [ctypes.c_void_p, dp, dp, dp]
@@ -132,6 +133,19 @@ class OracleEnv:
         if not h:
             raise ValueError("oracle: " + err.value.decode())
         self.h = h
+        tparams, tjoints = [], []
+        dof_off = 0
+        for a in env.actors:
+            for t in a.tendons:
+                tid = len(tparams)
+                tparams.append([t.stiffness, t.damping, t.rest_length, t.lower, t.upper, t.limit_stiffness])
+                for link, par, c in zip(t.links, t.parents, t.coefs):
+                    tjoints.append([tid, dof_off + link - 1, par, c])
+            dof_off += a.n_dof
+        if tparams:
+            tp = np.ascontiguousarray(tparams, dtype=np.float64)
+            tj = np.ascontiguousarray(tjoints, dtype=np.float64)
+            lib().orc_env_set_tendons(h, len(tparams), _dp(tp), len(tjoints), _dp(tj))
         s = np.zeros(6, dtype=np.int32)
         lib().orc_env_sizes(h, _ip(s))
         self.n_dof, self.n_v, self.n_bodies, self.n_actors, self.max_rows, self.n_slots = map(int, s)

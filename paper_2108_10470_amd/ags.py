@@ -48,6 +48,13 @@ class PairDesc(ctypes.Structure):
                 ("b_shape", ctypes.c_int32)]
 
 
+class TendonDesc(ctypes.Structure):
+    _fields_ = [("actor", ctypes.c_int32), ("n_joints", ctypes.c_int32), ("link", ctypes.POINTER(ctypes.c_int32)),
+                ("parent", ctypes.POINTER(ctypes.c_int32)), ("coef", ctypes.POINTER(ctypes.c_float)),
+                ("stiffness", ctypes.c_float), ("damping", ctypes.c_float), ("rest_length", ctypes.c_float),
+                ("lower", ctypes.c_float), ("upper", ctypes.c_float), ("limit_stiffness", ctypes.c_float)]
+
+
 class ModelInfo(ctypes.Structure):
     _fields_ = [("n_actors", ctypes.c_int32), ("n_links", ctypes.c_int32), ("n_dof", ctypes.c_int32),
                 ("n_v", ctypes.c_int32), ("n_slots", ctypes.c_int32), ("max_rows", ctypes.c_int32)]
@@ -76,6 +83,7 @@ def lib():
         L.ags_last_error.restype = ctypes.c_char_p
         L.ags_model_create.argtypes = [ctypes.POINTER(ActorDesc), i32, ctypes.POINTER(PairDesc), i32, ctypes.POINTER(vp)]
         L.ags_model_destroy.argtypes = [vp]
+        L.ags_model_add_tendons.argtypes = [vp, ctypes.POINTER(TendonDesc), i32]
         L.ags_model_get_info.argtypes = [vp, ctypes.POINTER(ModelInfo)]
         L.ags_model_mass_props.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
                                            ctypes.POINTER(ctypes.c_float)]
@@ -107,7 +115,7 @@ EXPORTED = ["ags_last_error", "ags_model_create", "ags_model_destroy", "ags_mode
             "ags_sim_set_root_state_indexed", "ags_sim_set_dof_state_indexed", "ags_sim_step_backward",
             "ags_rollout_state_size", "ags_rollout_forward", "ags_rollout_backward", "ags_autotune",
             "ags_rollout_seg_bytes", "ags_rollout_tape_bytes", "ags_rollout_forward_tape", "ags_rollout_backward_tape",
-            "ags_sim_jacobian_mass"]
+            "ags_sim_jacobian_mass", "ags_model_add_tendons"]
 
 
 def _check(rc: int, what: str):
@@ -146,6 +154,16 @@ class Model:
         h = ctypes.c_void_p()
         _check(lib().ags_model_create(actors, len(env.actors), pairs, len(env.pairs), ctypes.byref(h)), "ags_model_create")
         self.h = h
+        tds = []
+        for ai, a in enumerate(env.actors):
+            for t in a.tendons:
+                n = len(t.links)
+                arrs = ((ctypes.c_int32 * n)(*t.links), (ctypes.c_int32 * n)(*t.parents), (ctypes.c_float * n)(*t.coefs))
+                keep.append(arrs)
+                tds.append(TendonDesc(ai, n, arrs[0], arrs[1], arrs[2], t.stiffness, t.damping, t.rest_length,
+                                      t.lower, t.upper, t.limit_stiffness))
+        if tds:
+            _check(lib().ags_model_add_tendons(h, (TendonDesc * len(tds))(*tds), len(tds)), "ags_model_add_tendons")
         info = ModelInfo()
         _check(lib().ags_model_get_info(h, ctypes.byref(info)), "ags_model_get_info")
         self.info = info

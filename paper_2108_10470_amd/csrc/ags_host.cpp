@@ -106,9 +106,40 @@ struct ags_model {
   bool body_pairs = false;                             // has sphere/capsule-vs-box pairs
   int max_joint_entries = 0;  // most revolute/prismatic joints on the paths of one slot's two bodies
   std::vector<float> mass, com, inertia;
+  // fixed tendons: per tendon joint (tendon, model DOF, model column, parent tendon joint or -1) and its
+  // coefficient; per tendon stiffness, damping, rest length, lower, upper, limit stiffness
+  std::vector<int> tj_i;
+  std::vector<double> tj_f, tp;
+  std::vector<int> actor_link_off;  // first link of each actor, then the link count
 };
 
 extern "C" const char* ags_last_error(void) { return g_err.c_str(); }
+
+extern "C" int ags_model_add_tendons(ags_model* M, const ags_tendon_desc* T, int32_t n) {
+  if (!M || n < 0 || (n > 0 && !T)) return fail(AGS_E_ARG, "tendons: bad arguments");
+  std::vector<int> ti = M->tj_i;
+  std::vector<double> tf = M->tj_f, tp = M->tp;
+  for (int t = 0; t < n; ++t) {
+    const ags_tendon_desc& d = T[t];
+    if (d.actor < 0 || d.actor >= M->info.n_actors || d.n_joints <= 0 || !d.link || !d.parent || !d.coef)
+      return fail(AGS_E_MODEL, "tendons: bad tendon description");
+    const int tid = (int)tp.size() / 6, base = (int)tf.size();
+    const int a = d.actor, lo = M->actor_link_off[a], hi = M->actor_link_off[a + 1];
+    for (int j = 0; j < d.n_joints; ++j) {
+      const int l = d.link[j], par = d.parent[j];
+      if (l < 1 || lo + l >= hi || par < -1 || par >= j)
+        return fail(AGS_E_MODEL, "tendons: link or parent out of range (parents first, no root links)");
+      const int gl = lo + l;
+      ti.insert(ti.end(), {tid, M->li[(size_t)gl * LI_COLS + LI_DOF], M->li[(size_t)gl * LI_COLS + LI_COL], par < 0 ? -1 : base + par});
+      tf.push_back(d.coef[j]);
+    }
+    tp.insert(tp.end(), {d.stiffness, d.damping, d.rest_length, d.lower, d.upper, d.limit_stiffness});
+  }
+  M->tj_i = ti;
+  M->tj_f = tf;
+  M->tp = tp;
+  return AGS_OK;
+}
 
 extern "C" int ags_model_create(const ags_actor_desc* actors, int32_t n_actors, const ags_pair_desc* pairs,
                                 int32_t n_pairs, ags_model** out) {
@@ -395,6 +426,8 @@ extern "C" int ags_model_create(const ags_actor_desc* actors, int32_t n_actors, 
   }
   M->body_slot_begin[nl] = (int)M->body_slot.size();
   M->info.n_actors = n_actors;
+  M->actor_link_off.assign(link_off.begin(), link_off.end());
+  M->actor_link_off.push_back(nl);
   M->info.n_links = nl;
   M->info.n_dof = ndof;
   M->info.n_v = ncol;
@@ -658,7 +691,8 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
         {M->body_slot.data(), M->body_slot.size() * 4}, {M->ai.data(), M->ai.size() * 4},
         {lists[t].data(), lists[t].size() * 4}, {lf.data(), lf.size() * 8}, {M->sf.data(), M->sf.size() * 8},
         {M->link_anc.data(), M->link_anc.size() * 8}, {M->col_anc.data(), M->col_anc.size() * 8},
-        {M->col_link.data(), M->col_link.size() * 4}};
+        {M->col_link.data(), M->col_link.size() * 4}, {M->tj_i.data(), M->tj_i.size() * 4},
+        {M->tj_f.data(), M->tj_f.size() * 8}, {M->tp.data(), M->tp.size() * 8}};
     size_t total = 0;
     std::vector<size_t> offs;
     for (auto& q : parts) {
@@ -706,6 +740,10 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     D.link_anc = (const unsigned long long*)(b + offs[13]);
     D.col_anc = (const unsigned long long*)(b + offs[14]);
     D.col_link = (const int*)(b + offs[15]);
+    D.n_tj = (int)M->tj_f.size();
+    D.tj_i = (const int*)(b + offs[16]);
+    D.tj_f = (const double*)(b + offs[17]);
+    D.tp = (const double*)(b + offs[18]);
     T.body_pairs = M->body_pairs;
     T.adj = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), kAdjRows);
     T.adj_bytes = (size_t)T.adj.n_real * (adj_fp64(*p) ? sizeof(double) : sizeof(float)) + (size_t)T.adj.n_int * sizeof(int);
@@ -932,6 +970,8 @@ namespace {
 // what the adjoint does not differentiate, or NULL
 const char* adjoint_unsupported(const ags_sim* S) {
   if (S->params.solver != AGS_SOLVER_PGS) return "adjoint: supports the projected Gauss-Seidel solver only";
+  for (const TypeDev& T : S->types)
+    if (T.dm.n_tj > 0) return "adjoint: models with tendons are not supported";
   for (int w = AGS_BODY_MASS_SCALE; w <= AGS_ENV_GRAVITY; ++w)
     if (S->bound[w]) return "adjoint: per-env property tensors are not supported";
   return nullptr;

@@ -65,6 +65,12 @@ struct DevModel {
   const unsigned long long* link_anc;  // per link: bit j set iff link j is an ancestor of it or itself
   const unsigned long long* col_anc;   // per column: bit j set iff column j precedes it on its path to the root
   const int* col_link;                 // per column: the link that owns it
+  // fixed tendons: n_tj tendon joints (4 ints each: tendon, DOF, column, parent joint or -1; coefficient),
+  // 6 doubles per tendon (stiffness, damping, rest length, lower, upper, limit stiffness)
+  int n_tj;
+  const int* tj_i;
+  const double* tj_f;
+  const double* tp;
 };
 
 // one environment type of a step launch: its model tables, LDS layout, environments and scratch

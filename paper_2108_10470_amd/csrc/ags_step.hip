@@ -369,6 +369,9 @@ struct Tab {
   const int *li, *level_begin, *level_links, *children, *anc_link, *dof_link, *ai;
   const int *si, *body_slot_begin, *body_slot;
   const double *lf, *sf;
+  int n_tj;  // fixed tendons (global memory)
+  const int* tj_i;
+  const double *tj_f, *tp;
 };
 
 // Copies the integer model tables into this workgroup's LDS (all lanes cooperate) and returns the view.
@@ -397,6 +400,10 @@ __device__ __forceinline__ Tab<R> stage_tables(const DevModel& G, R* smem, const
   T.body_slot = G.body_slot;
   T.lf = G.lf;
   T.sf = G.sf;
+  T.n_tj = G.n_tj;
+  T.tj_i = G.tj_i;
+  T.tj_f = G.tj_f;
+  T.tp = G.tp;
   return T;
 }
 
@@ -739,6 +746,30 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       s.arm[c] = R(lf[LF_ARM]) + h * kd + h * h * kp;
     }
     __syncthreads();
+    if (M.n_tj > 0) {
+      // fixed tendons, explicit: lengths and rates down each tendon tree (one lane per env; the articulated
+      // inertia region is free until the forward sweep), then every tendon joint's spring, damper and limit
+      // force on the DOFs of its path as -f coef
+      if (tt == 0) {
+        const auto len = s.IA;
+        const auto rate = s.IA + M.n_tj;
+        for (int j = 0; j < M.n_tj; ++j) {
+          const int* ti = M.tj_i + 4 * j;
+          const R cf = R(M.tj_f[j]);
+          len[j] = (ti[3] >= 0 ? len[ti[3]] : R(0)) + cf * s.qj[ti[1]];
+          rate[j] = (ti[3] >= 0 ? rate[ti[3]] : R(0)) + cf * s.qd[ti[2]];
+        }
+        for (int j = 0; j < M.n_tj; ++j) {
+          const double* tp = M.tp + 6 * M.tj_i[4 * j];
+          const R l = len[j];
+          R f = R(tp[0]) * (l - R(tp[2])) + R(tp[1]) * rate[j];
+          if (l > R(tp[4])) f += R(tp[5]) * (l - R(tp[4]));
+          if (l < R(tp[3])) f += R(tp[5]) * (l - R(tp[3]));
+          for (int p = j; p >= 0; p = M.tj_i[4 * p + 3]) s.tau[M.tj_i[4 * p + 2]] -= f * R(M.tj_f[p]);
+        }
+      }
+      __syncthreads();
+    }
 
     PHASE_MARK(1);
     // ---------------------------------------------------- forward sweep by depth

@@ -88,12 +88,30 @@ class Link:
 
 
 @dataclass
+class Tendon:
+    """Fixed tendon (appendix on tendons): a tree of tendon joints, each following the incoming joint of one
+    link with a coefficient; the length at a tendon joint is its parent's length plus coefficient x joint
+    position.  At every tendon joint a spring (stiffness about rest_length), a damper on the length rate and a
+    limit spring (limit_stiffness beyond [lower, upper]) act along the path from the tendon's root."""
+    links: List[int]               # per tendon joint: actor-local link (not the root) whose joint it follows
+    parents: List[int]             # per tendon joint: parent tendon joint, -1 for the root (parents first)
+    coefs: List[float]
+    stiffness: float = 0.0
+    damping: float = 0.0
+    rest_length: float = 0.0
+    lower: float = -INF
+    upper: float = INF
+    limit_stiffness: float = 0.0
+
+
+@dataclass
 class Actor:
     name: str
     links: List[Link]
     root_pos: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     root_quat: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 1.0)  # xyzw
     init_q_halfwidth: float = 0.0  # joints start at U[-w, w] clipped into limits
+    tendons: List[Tendon] = field(default_factory=list)
 
     @property
     def fixed_base(self) -> bool:
@@ -357,10 +375,29 @@ def env_arm_box() -> EnvSpec:
     return EnvSpec("arm_box", actors, pairs)
 
 
-def env_hand_cube(z: float = 0.3) -> EnvSpec:
+def add_finger_tendons(h: Actor, stiffness: float = 0.3, damping: float = 0.01, lower: float = -0.4,
+                       upper: float = 1.6, limit_stiffness: float = 3.0) -> Actor:
+    """One fixed tendon per finger of the hand coupling its last two flexions (as the hand of the paper's
+    Shadow Hand experiments couples a finger's distal joints): root tendon joint on the third flexion
+    (coefficient 1), child on the fourth (coefficient -1), rest length 0, so the child's length is the
+    difference of the two flexions.  The forces are explicit (start-of-substep state): the stiffnesses are
+    chosen so that (k + limit k) h^2 stays well below the joints' effective inertia (about 1e-3 kg m^2, most
+    of it the implicit drive's h kd + h^2 kp)."""
+    names = [l.name for l in h.links]
+    for i in range(4):
+        a, b = names.index(f"finger{i}_f3"), names.index(f"finger{i}_f4")
+        h.tendons.append(Tendon([a, b], [-1, 0], [1.0, -1.0], stiffness=stiffness, damping=damping,
+                                lower=lower, upper=upper, limit_stiffness=limit_stiffness))
+    return h
+
+
+def env_hand_cube(z: float = 0.3, tendons: bool = False) -> EnvSpec:
     """The hand holding a free cube (edge 0.065 m, 0.1 kg) that rests on the palm-top capsules; pairs: every
-    capsule of the hand against the cube, and the cube against the ground."""
+    capsule of the hand against the cube, and the cube against the ground.  tendons: add the finger
+    tendons (add_finger_tendons)."""
     h = hand(z=z)
+    if tendons:
+        add_finger_tendons(h)
     cube = free_box(half=(0.0325, 0.0325, 0.0325), mass=0.1, pos=(0.0, 0.0, z + 0.01 + 0.0325))
     actors = [h, cube]
     pairs = []
@@ -445,6 +482,10 @@ def as_f32(env: EnvSpec) -> EnvSpec:
                 sh.half = tuple(_r32(v) for v in sh.half)
                 sh.radius = _r32(sh.radius)
                 sh.density = _r32(sh.density)
+        for t in a.tendons:
+            t.coefs = [_r32(c) for c in t.coefs]
+            for f in ("stiffness", "damping", "rest_length", "lower", "upper", "limit_stiffness"):
+                setattr(t, f, _r32(getattr(t, f)))
     return e
 
 

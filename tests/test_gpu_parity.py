@@ -163,6 +163,46 @@ def test_hand_cube_parity(fp64):
     _assert_pass(s) if fp64 else _assert_fp32(s)
 
 
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_hand_cube_tendons_parity(fp64):
+    """The hand with one fixed tendon per finger coupling its last two flexions (spring, damper and length
+    limits, appendix on tendons), holding the cube; states from a 60-step oracle rollout of the same model,
+    including steps where the tendon limits act.  The adjoint refuses the model."""
+    env = W.env_hand_cube(tendons=True)
+    p = W.HAND_PARAMS
+    E, T, every = 16, 60, 6
+    envf, pf = W.as_f32(env), W.params_f32(p)
+    oe = O.OracleEnv(envf)
+    root, dof = W.initial_state(envf, E, 0)
+    tg = W.pd_targets(envf, E, T, 0)
+    act = np.zeros((E, env.n_dof))
+    roots, dofs, tgts = [], [], []
+    for t in range(T):
+        if t % every == 0:
+            roots.append(root)
+            dofs.append(dof)
+            tgts.append(tg[t])
+        o = oe.step(pf, root, dof, act, pos_tgt=tg[t])
+        root, dof = o["root"], o["dof"]
+    root, dof, tg = np.concatenate(roots), np.concatenate(dofs), np.concatenate(tgts)
+    # the finger tendons' child lengths (third minus fourth flexion) leave [-0.4, 1.6] in some states
+    names = [l.name for l in envf.actors[0].links]
+    diff = np.stack([dof[:, names.index(f"finger{i}_f3") - 1, 0] - dof[:, names.index(f"finger{i}_f4") - 1, 0]
+                     for i in range(4)], axis=1)
+    assert (diff < -0.4).any()
+    g, o = PT.run(env, p, root, dof, np.zeros((root.shape[0], env.n_dof)), oe=oe, pos_tgt=tg, fp64=fp64)
+    s = PT.summarize(PT.compare(env, p, g, o))
+    s["mean_rows"] = float(o["row_count"].mean())
+    _report(f"hand_cube_tendons_{'fp64' if fp64 else 'fp32'}", s)
+    assert np.isfinite(g["root"]).all() and np.isfinite(g["dof"]).all()
+    _assert_pass(s) if fp64 else _assert_fp32(s)
+    sim = ags.Sim([ags.Model(envf)], [0] * 2, pf, device="cuda:0", fp64=fp64)
+    z = lambda t: torch.zeros_like(t)
+    with pytest.raises(RuntimeError, match="tendons"):
+        sim.step_backward(sim.root_state, sim.dof_state, sim.actuation, z(sim.root_state), z(sim.dof_state),
+                          z(sim.actuation))
+
+
 def _quat_to_R(q):
     x, y, z, w = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
     return np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),

@@ -28,6 +28,22 @@ def _env(actors, pairs=None, name="t"):
     return W.EnvSpec(name, list(actors), pairs)
 
 
+def test_as_f32_rounds_every_number():
+    """Parity feeds both sides the same FP32 model description: every number of the oracle's tables (and
+    of the tendons) of a rounded environment is representable in float32."""
+    for make in (W.env_ant, W.env_humanoid, W.env_arm_box, lambda: W.env_hand_cube(tendons=True)):
+        env = W.as_f32(make())
+        links, shapes, pairs = O.env_tables(env)
+        vals = [links.ravel(), shapes.ravel()]
+        for a in env.actors:
+            for t in a.tendons:
+                vals.append(np.array(t.coefs + [t.stiffness, t.damping, t.rest_length, t.lower, t.upper,
+                                                t.limit_stiffness]))
+        v = np.concatenate(vals)
+        v = v[np.isfinite(v)]
+        assert (v.astype(np.float32).astype(np.float64) == v).all(), make
+
+
 # ----------------------------------------------------------------------------- mass properties
 def _mc_mass_props(inside, lo, hi, n, seed):
     """Monte Carlo volume, centroid and inertia (unit density) of the set `inside` within a box."""
@@ -604,6 +620,47 @@ def test_tgs_one_sweep_is_pgs():
         assert np.array_equal(a[k], b[k]), k
     c = oe.step(_params(pgs_iters=8, solver=1), root, dof, acts[0])
     assert np.abs(c["row_lambda"] - oe.step(_params(pgs_iters=8, solver=0), root, dof, acts[0])["row_lambda"]).max() > 1e-6
+
+
+@pytest.mark.parametrize("q,qd", [((0.2, -0.1), (0.0, 0.0)), ((0.9, -0.4), (1.5, -2.0)), ((-0.6, 0.3), (-0.7, 0.4))])
+def test_fixed_tendon_force_is_the_energy_gradient(q, qd):
+    """A fixed tendon (appendix on tendons) on a double pendulum without gravity: root tendon joint on
+    joint 1 (coefficient c1), child on joint 2 (c2); lengths l1 = c1 q1, l2 = l1 + c2 q2.  The tendon's
+    generalized force must be -dU/dq - d sum_j g_j (g_j . qd) with U = 1/2 k sum_j (l_j - l0)^2 plus
+    1/2 k_lim (l_j - bound)^2 outside [lower, upper] and g_j = dl_j/dq: checked through the step's
+    unconstrained acceleration, M~ qdd = tau - C, with U differentiated numerically here."""
+    actor = W.double_pendulum()
+    c1, c2, k, d, l0, lo, hi, kl = 0.7, -1.3, 2.0, 0.3, 0.1, -0.5, 0.5, 5.0
+    actor.tendons.append(W.Tendon([1, 2], [-1, 0], [c1, c2], stiffness=k, damping=d, rest_length=l0, lower=lo,
+                                  upper=hi, limit_stiffness=kl))
+    env = _env([actor], [])
+    oe = O.OracleEnv(env)
+    p = _params(substeps=1, gravity=(0.0, 0.0, 0.0))
+    root, _ = W.initial_state(env, 1, 0)
+    dof = np.array([[[q[0], qd[0]], [q[1], qd[1]]]])
+
+    def U(x):
+        l1 = c1 * x[0]
+        l2 = l1 + c2 * x[1]
+        u = 0.0
+        for l in (l1, l2):
+            u += 0.5 * k * (l - l0) ** 2
+            if l > hi:
+                u += 0.5 * kl * (l - hi) ** 2
+            if l < lo:
+                u += 0.5 * kl * (l - lo) ** 2
+        return u
+
+    x = np.array(q, dtype=float)
+    eps = 1e-6
+    grad = np.array([(U(x + eps * e) - U(x - eps * e)) / (2 * eps) for e in np.eye(2)])
+    g = [np.array([c1, 0.0]), np.array([c1, c2])]
+    tau = -grad - d * sum(gj * (gj @ np.array(qd)) for gj in g)
+    M, C, _, _ = oe.dynamics(p, root[0], dof[0], np.zeros(2))
+    o = oe.step(p, root, dof, np.zeros((1, 2)))
+    qdd = o["qdd_free"][0, 0]
+    assert np.abs(M @ qdd + C - tau).max() <= 1e-7 * (1 + np.abs(tau).max()), (M @ qdd + C, tau)
+    assert np.abs(tau).max() > 0.1
 
 
 def test_sphere_slides_then_rolls_closed_form():
