@@ -670,7 +670,9 @@ __device__ __forceinline__ void jrow_point(const Tab<R>& M, const Ctx<R, EPW>& s
 
 // One env-step of the environments of group `group` of type T (EPW environments per wavefront).
 // stage: copy T's model tables into LDS (false when the previous group of this workgroup had the same type).
-template <typename R, int TEAM>
+// TGS: the temporal Gauss-Seidel variant (a separate instantiation, so that the default solver's registers
+// are not shared with the variant's extra per-row state).
+template <typename R, int TEAM, bool TGS>
 __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T, int group, bool stage) {
   R* smem = reinterpret_cast<R*>(g_lds);
   const Lds& L = T.lds;
@@ -692,9 +694,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   const int nl = M.n_links, nd = M.n_dof, nv = M.n_v, ns = M.n_slots, na = M.n_actors;
   const int abase = P.env_actor_base[env], dbase = P.env_dof_base[env], bbase = P.env_body_base[env];
   const R h = R(P.h);
-  const bool tgs = P.solver == 1;  // temporal Gauss-Seidel variant
-  const V3<R> grav = P.env_gravity ? mk(R(P.env_gravity[3 * env]), R(P.env_gravity[3 * env + 1]), R(P.env_gravity[3 * env + 2]))
-                                   : mk(R(P.gx), R(P.gy), R(P.gz));
+  constexpr bool tgs = TGS;
   R* Jg = reinterpret_cast<R*>(T.scratch) + (long long)gidx * T.scratch_stride;
   R* Wg = Jg + (long long)M.r_cap * nv;
 
@@ -809,6 +809,10 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         // bias force p = v x* (I v) - f_gravity (gravity m g at the COM)
         V3<R> ha, hl;
         si_mul(I, w, vl, ha, hl);
+        // gravity of this env, read where it is used (a per-env value held across the substep loop would cost
+        // registers the kernel does not have)
+        const V3<R> grav = P.env_gravity ? mk(R(P.env_gravity[3 * env]), R(P.env_gravity[3 * env + 1]), R(P.env_gravity[3 * env + 2]))
+                                         : mk(R(P.gx), R(P.gy), R(P.gz));
         const V3<R> fg = mul(grav, m);
         const V3<R> pn = sub(add(cross(w, ha), cross(vl, hl)), cross(d, fg));
         const V3<R> pf = sub(cross(w, hl), fg);
@@ -1501,20 +1505,20 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 template <typename R, int TEAM>
 constexpr int kWavesPerEU = (sizeof(R) == 4 || TEAM == 64) ? 2 : 1;
 
-template <typename R, int TEAM>
+template <typename R, int TEAM, bool TGS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<R, TEAM>))) void step_kernel(StepArgs P) {
-  step_group<R, TEAM>(P, P.ty, blockIdx.x, true);
+  step_group<R, TEAM, TGS>(P, P.ty, blockIdx.x, true);
 }
 
 // persistent form: each workgroup walks the work list with a grid stride; the list is ordered by
 // estimated cost, so the heaviest groups start first and the tail is made of the cheapest ones
-template <typename R, int TEAM>
+template <typename R, int TEAM, bool TGS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<R, TEAM>))) void step_fused(FusedArgs A) {
   int prev = -1;
   for (int u = blockIdx.x; u < A.n_units; u += gridDim.x) {
     const int ty = A.units[2 * u], grp = A.units[2 * u + 1];
     __syncthreads();
-    step_group<R, TEAM>(A.base, A.types[ty], grp, ty != prev);
+    step_group<R, TEAM, TGS>(A.base, A.types[ty], grp, ty != prev);
     prev = ty;
   }
 }
@@ -1545,17 +1549,24 @@ static hipError_t launch_one(const StepArgs& a, int n_envs, hipStream_t stream) 
   constexpr int EPW = kTeam / TEAM;
   const size_t lds = (size_t)a.ty.lds.total * sizeof(R);
   const int grid = (n_envs + EPW - 1) / EPW;
-  hipLaunchKernelGGL((step_kernel<R, TEAM>), dim3(grid), dim3(kTeam), lds, stream, a);
+  if (a.solver == 1) hipLaunchKernelGGL((step_kernel<R, TEAM, true>), dim3(grid), dim3(kTeam), lds, stream, a);
+  else hipLaunchKernelGGL((step_kernel<R, TEAM, false>), dim3(grid), dim3(kTeam), lds, stream, a);
   return hipGetLastError();
 }
 
-template <typename R, int TEAM>
+template <typename R, int TEAM, bool TGS>
 static const void* fused_fn() {
-  return (const void*)step_fused<R, TEAM>;
+  return (const void*)step_fused<R, TEAM, TGS>;
 }
+template <bool TGS>
 static const void* fused_kernel(int fp64, int team) {
-  return fp64 ? (team == 32 ? fused_fn<double, 32>() : fused_fn<double, 64>())
-              : (team == 32 ? fused_fn<float, 32>() : fused_fn<float, 64>());
+  return fp64 ? (team == 32 ? fused_fn<double, 32, TGS>() : fused_fn<double, 64, TGS>())
+              : (team == 32 ? fused_fn<float, 32, TGS>() : fused_fn<float, 64, TGS>());
+}
+template <bool TGS>
+static const void* step_fn(int fp64, int team) {
+  return fp64 ? (team == 32 ? (const void*)step_kernel<double, 32, TGS> : (const void*)step_kernel<double, 64, TGS>)
+              : (team == 32 ? (const void*)step_kernel<float, 32, TGS> : (const void*)step_kernel<float, 64, TGS>);
 }
 
 hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStream_t stream) {
@@ -1570,30 +1581,38 @@ hipError_t launch_scale_by_kp(float* x, const float* kp, int n, hipStream_t stre
   return hipGetLastError();
 }
 
+template <bool TGS>
+static void launch_fused_solver(const FusedArgs& a, int grid, size_t lds_bytes, int fp64, int team, hipStream_t stream) {
+  if (fp64) {
+    if (team == 32) hipLaunchKernelGGL((step_fused<double, 32, TGS>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
+    else hipLaunchKernelGGL((step_fused<double, 64, TGS>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
+  } else {
+    if (team == 32) hipLaunchKernelGGL((step_fused<float, 32, TGS>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
+    else hipLaunchKernelGGL((step_fused<float, 64, TGS>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
+  }
+}
+
 hipError_t launch_step_fused(const FusedArgs& a, int grid, size_t lds_bytes, int fp64, int team, hipStream_t stream) {
   if (a.n_units <= 0) return hipSuccess;
-  if (fp64) {
-    if (team == 32) hipLaunchKernelGGL((step_fused<double, 32>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
-    else hipLaunchKernelGGL((step_fused<double, 64>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
-  } else {
-    if (team == 32) hipLaunchKernelGGL((step_fused<float, 32>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
-    else hipLaunchKernelGGL((step_fused<float, 64>), dim3(grid), dim3(kTeam), lds_bytes, stream, a);
-  }
+  if (a.base.solver == 1) launch_fused_solver<true>(a, grid, lds_bytes, fp64, team, stream);
+  else launch_fused_solver<false>(a, grid, lds_bytes, fp64, team, stream);
   return hipGetLastError();
 }
 
 hipError_t set_fused_lds_limit(int fp64, int team, size_t bytes) {
-  return hipFuncSetAttribute(fused_kernel(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  hipError_t e = hipFuncSetAttribute(fused_kernel<false>(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute(fused_kernel<true>(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return e;
 }
 
 hipError_t fused_blocks_per_cu(int fp64, int team, size_t lds_bytes, int* blocks) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fused_kernel(fp64, team), kTeam, lds_bytes);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, fused_kernel<false>(fp64, team), kTeam, lds_bytes);
 }
 
 hipError_t set_lds_limit(int fp64, int team, size_t bytes) {
-  const void* f = fp64 ? (team == 32 ? (const void*)step_kernel<double, 32> : (const void*)step_kernel<double, 64>)
-                       : (team == 32 ? (const void*)step_kernel<float, 32> : (const void*)step_kernel<float, 64>);
-  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  hipError_t e = hipFuncSetAttribute(step_fn<false>(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) e = hipFuncSetAttribute(step_fn<true>(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return e;
 }
 
 hipError_t launch_set_rows(float* dst, const float* src, const int* idx, int n, int n_actors, const int* table,
