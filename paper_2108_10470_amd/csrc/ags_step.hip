@@ -773,61 +773,70 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 
     PHASE_MARK(1);
     // ---------------------------------------------------- forward sweep by depth
+    // Poses and velocities chain from parent to child, level by level; the spatial inertia and bias force
+    // of each link need only its own pose and velocity, so they are formed afterwards for all links at
+    // once (lanes over links) instead of by the one or two lanes a level occupies.
     for (int d = 0; d < M.n_levels; ++d) {
       for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
-        const double* lf = M.lf + i * LF_COLS;
         R Rw[9], qq[4];
         V3<R> o, w, vl, ax;
         link_kinematics(M, s, i, origin, Rw, qq, o, w, vl, ax);
-        // spatial inertia about o (world axes): A = Ic_w + m (|d|^2 1 - d d^T), B = m d^, M = m 1
-        const double msc = P.mass_scale ? double(P.mass_scale[bbase + i]) : 1.0;  // per-env mass factor
-        const R m = R(lf[LF_MASS] * msc);
-        const V3<R> d = mv(Rw, ld3<R>(lf + LF_COM));
-        const double* Icl = lf + LF_IC;
-        const R Ic[9] = {R(Icl[0] * msc), R(Icl[3] * msc), R(Icl[4] * msc), R(Icl[3] * msc), R(Icl[1] * msc),
-                         R(Icl[5] * msc), R(Icl[4] * msc), R(Icl[5] * msc), R(Icl[2] * msc)};
-        R Tm[9], Iw[9];
-        mm3(Rw, Ic, Tm);
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b)
-            Iw[3 * a + b] = Tm[3 * a] * Rw[3 * b] + Tm[3 * a + 1] * Rw[3 * b + 1] + Tm[3 * a + 2] * Rw[3 * b + 2];
-        SI<R> I;
-        const R dd = dot(d, d), half = R(0.5);
-        I.A[0] = Iw[0] + m * (dd - d.x * d.x);
-        I.A[1] = Iw[4] + m * (dd - d.y * d.y);
-        I.A[2] = Iw[8] + m * (dd - d.z * d.z);
-        I.A[3] = half * (Iw[1] + Iw[3]) - m * d.x * d.y;
-        I.A[4] = half * (Iw[2] + Iw[6]) - m * d.x * d.z;
-        I.A[5] = half * (Iw[5] + Iw[7]) - m * d.y * d.z;
-        I.B[0] = R(0); I.B[1] = -m * d.z; I.B[2] = m * d.y;
-        I.B[3] = m * d.z; I.B[4] = R(0); I.B[5] = -m * d.x;
-        I.B[6] = -m * d.y; I.B[7] = m * d.x; I.B[8] = R(0);
-        I.M[0] = m; I.M[1] = m; I.M[2] = m; I.M[3] = R(0); I.M[4] = R(0); I.M[5] = R(0);
-        // bias force p = v x* (I v) - f_gravity (gravity m g at the COM)
-        V3<R> ha, hl;
-        si_mul(I, w, vl, ha, hl);
-        // gravity of this env, read where it is used (a per-env value held across the substep loop would cost
-        // registers the kernel does not have)
-        const V3<R> grav = P.env_gravity ? mk(R(P.env_gravity[3 * env]), R(P.env_gravity[3 * env + 1]), R(P.env_gravity[3 * env + 2]))
-                                         : mk(R(P.gx), R(P.gy), R(P.gz));
-        const V3<R> fg = mul(grav, m);
-        const V3<R> pn = sub(add(cross(w, ha), cross(vl, hl)), cross(d, fg));
-        const V3<R> pf = sub(cross(w, hl), fg);
 #pragma unroll
         for (int k = 0; k < 4; ++k) s.q[4 * i + k] = qq[k];
         st3(s.o + 3 * i, o);
         st3(s.ax + 3 * i, ax);
         st3(s.v + 6 * i, w);
         st3(s.v + 6 * i + 3, vl);
-        si_store(I, s.IA + 21 * i);
-        st3(s.pA + 6 * i, pn);
-        st3(s.pA + 6 * i + 3, pf);
       }
       __syncthreads();
     }
+    for (int i = tt; i < nl; i += TEAM) {
+      const double* lf = M.lf + i * LF_COLS;
+      R Rw[9];
+      quat_R(s.q + 4 * i, Rw);
+      const V3<R> w = ld3<R>(s.v + 6 * i), vl = ld3<R>(s.v + 6 * i + 3);
+      // spatial inertia about o (world axes): A = Ic_w + m (|d|^2 1 - d d^T), B = m d^, M = m 1
+      const double msc = P.mass_scale ? double(P.mass_scale[bbase + i]) : 1.0;  // per-env mass factor
+      const R m = R(lf[LF_MASS] * msc);
+      const V3<R> d = mv(Rw, ld3<R>(lf + LF_COM));
+      const double* Icl = lf + LF_IC;
+      const R Ic[9] = {R(Icl[0] * msc), R(Icl[3] * msc), R(Icl[4] * msc), R(Icl[3] * msc), R(Icl[1] * msc),
+                       R(Icl[5] * msc), R(Icl[4] * msc), R(Icl[5] * msc), R(Icl[2] * msc)};
+      R Tm[9], Iw[9];
+      mm3(Rw, Ic, Tm);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          Iw[3 * a + b] = Tm[3 * a] * Rw[3 * b] + Tm[3 * a + 1] * Rw[3 * b + 1] + Tm[3 * a + 2] * Rw[3 * b + 2];
+      SI<R> I;
+      const R dd = dot(d, d), half = R(0.5);
+      I.A[0] = Iw[0] + m * (dd - d.x * d.x);
+      I.A[1] = Iw[4] + m * (dd - d.y * d.y);
+      I.A[2] = Iw[8] + m * (dd - d.z * d.z);
+      I.A[3] = half * (Iw[1] + Iw[3]) - m * d.x * d.y;
+      I.A[4] = half * (Iw[2] + Iw[6]) - m * d.x * d.z;
+      I.A[5] = half * (Iw[5] + Iw[7]) - m * d.y * d.z;
+      I.B[0] = R(0); I.B[1] = -m * d.z; I.B[2] = m * d.y;
+      I.B[3] = m * d.z; I.B[4] = R(0); I.B[5] = -m * d.x;
+      I.B[6] = -m * d.y; I.B[7] = m * d.x; I.B[8] = R(0);
+      I.M[0] = m; I.M[1] = m; I.M[2] = m; I.M[3] = R(0); I.M[4] = R(0); I.M[5] = R(0);
+      // bias force p = v x* (I v) - f_gravity (gravity m g at the COM)
+      V3<R> ha, hl;
+      si_mul(I, w, vl, ha, hl);
+      // gravity of this env, read where it is used (a per-env value held across the substep loop would cost
+      // registers the kernel does not have)
+      const V3<R> grav = P.env_gravity ? mk(R(P.env_gravity[3 * env]), R(P.env_gravity[3 * env + 1]), R(P.env_gravity[3 * env + 2]))
+                                       : mk(R(P.gx), R(P.gy), R(P.gz));
+      const V3<R> fg = mul(grav, m);
+      const V3<R> pn = sub(add(cross(w, ha), cross(vl, hl)), cross(d, fg));
+      const V3<R> pf = sub(cross(w, hl), fg);
+      si_store(I, s.IA + 21 * i);
+      st3(s.pA + 6 * i, pn);
+      st3(s.pA + 6 * i + 3, pf);
+    }
+    __syncthreads();
 
     PHASE_MARK(2);
     // ---------------------------------------------------- ABA inward sweep (deepest level first)

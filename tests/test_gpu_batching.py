@@ -159,13 +159,14 @@ def test_full_size_batch_sampled_parity():
 
 
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
-def test_persistent_launch_is_bitwise_equal_to_per_type_launches(fp64):
+@pytest.mark.parametrize("solver", [0, 1], ids=["pgs", "tgs"])
+def test_persistent_launch_is_bitwise_equal_to_per_type_launches(fp64, solver):
     """The one-launch persistent form over a heterogeneous batch gives exactly the per-type launches'
-    results (same arithmetic, different work distribution), over several steps."""
+    results (same arithmetic, different work distribution), over several steps, for both solvers."""
     specs = [W.env_ant(), W.env_humanoid(), W.env_arm_box()]
     E, T = 3 * 200 + 1, 5
     env_model = [(e * 7) % 3 for e in range(E)]
-    p = W.SimParams()
+    p = W.SimParams(solver=solver)
     sims = [ags.Sim([ags.Model(s) for s in specs], env_model, p, device="cuda:0", fp64=fp64, persistent=per)
             for per in (False, True)]
     roots, dofs, acts = [], [], []
