@@ -966,6 +966,23 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 
     PHASE_MARK(4);
     // ---------------------------------------------------- link velocities under v*, U about roots, G table
+    // U about the root point and the G table need only the inward sweep's results, so every link forms its
+    // own at once (lanes over links); the velocities chain level by level.
+    for (int i = tt; i < nl; i += TEAM) {
+      const int* li = M.li + i * LI_COLS;
+      if (li[LI_PARENT] < 0) continue;
+      // U moved to the root point (its linear half is unchanged), and G_ik = U_i . (s_k moved to o_i)
+      // for every ancestor joint k
+      const V3<R> oi = ld3<R>(s.o + 3 * i);
+      const V3<R> Ua = ld3<R>(s.U + 6 * i), Ul = ld3<R>(s.U + 6 * i + 3);
+      st3(s.Ubar + 3 * i, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * li[LI_ROOT])), Ul)));
+      for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q) {
+        const int k = M.anc_link[q];
+        const V3<R> ak = ld3<R>(s.ax + 3 * k);
+        s.G[q] = M.li[k * LI_COLS + LI_JTYPE] == J_REV ? dot(ak, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * k)), Ul)))
+                                                      : dot(ak, Ul);
+      }
+    }
     for (int d = 0; d < M.n_levels; ++d) {
       for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
@@ -988,16 +1005,6 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           const R qd = s.vs[li[LI_COL]];
           if (jt == J_REV) w = add(w, mul(ax, qd));
           else vl = add(vl, mul(ax, qd));
-          // U moved to the root point (its linear half is unchanged), and G_ik = U_i . (s_k moved to o_i)
-          // for every ancestor joint k
-          const V3<R> Ua = ld3<R>(s.U + 6 * i), Ul = ld3<R>(s.U + 6 * i + 3);
-          st3(s.Ubar + 3 * i, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * li[LI_ROOT])), Ul)));
-          for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q) {
-            const int k = M.anc_link[q];
-            const V3<R> ak = ld3<R>(s.ax + 3 * k);
-            s.G[q] = M.li[k * LI_COLS + LI_JTYPE] == J_REV ? dot(ak, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * k)), Ul)))
-                                                          : dot(ak, Ul);
-          }
         }
         st3(s.v + 6 * i, w);
         st3(s.v + 6 * i + 3, vl);
