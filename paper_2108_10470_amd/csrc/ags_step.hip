@@ -415,6 +415,14 @@ __device__ __forceinline__ int actor_of_root(const Tab<R>& M, int link) {
   return a;
 }
 
+// clamp to [lo, hi] (lo <= hi): one median-of-three in FP32
+__device__ __forceinline__ float clamp_(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+__device__ __forceinline__ double clamp_(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
+
+// upper impulse bound of rows without one (contact normals, limits): far above any impulse, finite so that
+// the friction-bound arithmetic of the register Gauss-Seidel stays free of infinities
+constexpr double kOpenBound = 1e30;
+
 // bias of a limit or contact-normal row from its position error C: speculative C / h when separated, the
 // Baumgarte fraction beta C / h when penetrating
 template <typename R>
@@ -1276,12 +1284,19 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       // broadcast.  A friction lane follows its normal row's impulse through those broadcasts and keeps its
       // box bounds +-mu lambda_n.  Rows without a response (1/A_rr = 0: dropped, or lanes past the row count)
       // hold lambda = 0 and their update is a clamp of 0, so they need no test.  c = lambda - b / A_rr.
-      R lam = R(0), hi = fric ? R(0) : R(INFINITY), lo = R(0), c = -bias * ia;
+      // The bounds are updated by arithmetic on every row (hi += mu dl with dl zero unless the broadcast row
+      // is the lane's normal row; lo = -hi for friction rows, -0 for the others, whose upper bound is a
+      // finite stand-in for infinity): values that come out of arithmetic need no canonicalizing before the
+      // clamp, and no selects are needed.
+      const R fsign = fric ? R(1) : R(0);
+      R lam = R(0), hi = fric ? R(0) : R(kOpenBound), lo = R(0), bia = bias * ia;
+      R c = -bia;
       const R hstep = h / R(max(P.iters, 1));
       for (int it = 0; it < P.iters; ++it) {
         if (tgs && it > 0 && own && !fric) {
           bias = row_bias(pos, h, R(P.beta));
-          c = lam - bias * ia;
+          bia = bias * ia;
+          c = lam - bia;
         }
         // opaque copies of the lane's row and normal-row indices and of the row count: keeps the per-row
         // compares inside the sweep instead of 3 x FR hoisted (and spilled) masks
@@ -1291,16 +1306,12 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 #pragma unroll
         for (int r = 0; r < FR; ++r) {
           if (r < rw) {
-            const R cand = min_(max_(fma_(-y, ia, c), lo), hi);
+            const R cand = clamp_(fma_(-y, ia, c), lo, hi);
             const R dl = team_read<TEAM>(tm, cand - lam, r);
-            if (me == r) {
-              lam = cand;
-              c = cand - bias * ia;
-            }
-            if (mn == r) {
-              hi += muv * dl;
-              lo = -hi;
-            }
+            lam = me == r ? cand : lam;
+            c = lam - bia;
+            hi = fma_(mn == r ? muv : R(0), dl, hi);
+            lo = -(hi * fsign);
             y += Acol[r] * dl;
           }
         }
