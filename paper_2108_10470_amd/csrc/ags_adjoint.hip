@@ -534,7 +534,8 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     arm[c] = R(lf[LF_ARM]) + h * kd + h * h * kp;
   }
   sync<R>();
-  // ---- kinematics, link inertias and velocities (outward by level)
+  // ---- kinematics and velocities (outward by level); then every link's COM, world inertia and own
+  // composite inertia at once (lanes over links): they need only the link's own pose
   for (int lev = 0; lev < E.nlev; ++lev) {
     const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
     for (int t = b + lane; t < e; t += 64) {
@@ -583,29 +584,9 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
         pw = add(ld3<R>(E.at(L.p, p, 3)), mv(Rp, tl));
       }
       st3(E.at(L.p, i, 3), pw);
-      // COM and world inertia
-      const V3<R> cw = add(pw, mv(Rm, ld3<R>(lf + LF_COM)));
-      st3(E.at(L.c, i, 3), cw);
-      const R I0[9] = {R(lf[LF_IC + 0]), R(lf[LF_IC + 3]), R(lf[LF_IC + 4]), R(lf[LF_IC + 3]), R(lf[LF_IC + 1]),
-                       R(lf[LF_IC + 5]), R(lf[LF_IC + 4]), R(lf[LF_IC + 5]), R(lf[LF_IC + 2])};
-      R T[9];  // Rm I0
-#pragma unroll
-      for (int r0 = 0; r0 < 3; ++r0)
-#pragma unroll
-        for (int c0 = 0; c0 < 3; ++c0) T[3 * r0 + c0] = Rm[3 * r0] * I0[c0] + Rm[3 * r0 + 1] * I0[3 + c0] + Rm[3 * r0 + 2] * I0[6 + c0];
-      R* Iw = E.at(L.Iw, i, 6);
-      auto TRt = [&](int a, int b2) { return T[3 * a] * Rm[3 * b2] + T[3 * a + 1] * Rm[3 * b2 + 1] + T[3 * a + 2] * Rm[3 * b2 + 2]; };
-      Iw[0] = TRt(0, 0); Iw[1] = TRt(1, 1); Iw[2] = TRt(2, 2); Iw[3] = TRt(0, 1); Iw[4] = TRt(0, 2); Iw[5] = TRt(1, 2);
-      // own part of the composite inertia
-      const R m = R(lf[LF_MASS]);
-      R* Ic = E.at(L.Ic, i, 10);
-      Ic[0] = m; Ic[1] = m * cw.x; Ic[2] = m * cw.y; Ic[3] = m * cw.z;
-      const R cc = dot(cw, cw);
-      Ic[4] = Iw[0] + m * (cc - cw.x * cw.x); Ic[5] = Iw[1] + m * (cc - cw.y * cw.y); Ic[6] = Iw[2] + m * (cc - cw.z * cw.z);
-      Ic[7] = Iw[3] - m * cw.x * cw.y; Ic[8] = Iw[4] - m * cw.x * cw.z; Ic[9] = Iw[5] - m * cw.y * cw.z;
-      // velocity
+      // velocity (a free root's needs its COM, the root frame's origin)
       if (li[LI_PARENT] < 0) {
-        V = li[LI_JTYPE] == J_FREE ? root_vel(cw, nu + li[LI_ROOTCOL]) : sz<R>();
+        V = li[LI_JTYPE] == J_FREE ? root_vel(add(pw, mv(Rm, ld3<R>(lf + LF_COM))), nu + li[LI_ROOTCOL]) : sz<R>();
       } else {
         V = sadd(lds6(E.at(L.V, li[LI_PARENT], 6)), smul(joint_s(E, i), nu[li[LI_COL]]));
       }
@@ -613,6 +594,31 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     }
     sync<R>();
   }
+  for (int i = lane; i < E.nl; i += 64) {
+    const double* lf = E.lf(i);
+    const R* Rm = E.at(L.Rm, i, 9);
+    // COM and world inertia
+    const V3<R> cw = add(ld3<R>(E.at(L.p, i, 3)), mv(Rm, ld3<R>(lf + LF_COM)));
+    st3(E.at(L.c, i, 3), cw);
+    const R I0[9] = {R(lf[LF_IC + 0]), R(lf[LF_IC + 3]), R(lf[LF_IC + 4]), R(lf[LF_IC + 3]), R(lf[LF_IC + 1]),
+                     R(lf[LF_IC + 5]), R(lf[LF_IC + 4]), R(lf[LF_IC + 5]), R(lf[LF_IC + 2])};
+    R T[9];  // Rm I0
+#pragma unroll
+    for (int r0 = 0; r0 < 3; ++r0)
+#pragma unroll
+      for (int c0 = 0; c0 < 3; ++c0) T[3 * r0 + c0] = Rm[3 * r0] * I0[c0] + Rm[3 * r0 + 1] * I0[3 + c0] + Rm[3 * r0 + 2] * I0[6 + c0];
+    R* Iw = E.at(L.Iw, i, 6);
+    auto TRt = [&](int a, int b2) { return T[3 * a] * Rm[3 * b2] + T[3 * a + 1] * Rm[3 * b2 + 1] + T[3 * a + 2] * Rm[3 * b2 + 2]; };
+    Iw[0] = TRt(0, 0); Iw[1] = TRt(1, 1); Iw[2] = TRt(2, 2); Iw[3] = TRt(0, 1); Iw[4] = TRt(0, 2); Iw[5] = TRt(1, 2);
+    // own part of the composite inertia
+    const R m = R(lf[LF_MASS]);
+    R* Ic = E.at(L.Ic, i, 10);
+    Ic[0] = m; Ic[1] = m * cw.x; Ic[2] = m * cw.y; Ic[3] = m * cw.z;
+    const R cc = dot(cw, cw);
+    Ic[4] = Iw[0] + m * (cc - cw.x * cw.x); Ic[5] = Iw[1] + m * (cc - cw.y * cw.y); Ic[6] = Iw[2] + m * (cc - cw.z * cw.z);
+    Ic[7] = Iw[3] - m * cw.x * cw.y; Ic[8] = Iw[4] - m * cw.x * cw.z; Ic[9] = Iw[5] - m * cw.y * cw.z;
+  }
+  sync<R>();
   // ---- composite inertias (inward by level, children gathered)
   for (int lev = E.nlev - 2; lev >= 0; --lev) {
     const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
@@ -681,14 +687,19 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
         A = sadd(lds6(E.at(L.X1, li[LI_PARENT], 6)), smul(crm(lds6(E.at(L.V, li[LI_PARENT], 6)), joint_s(E, i)), nu[li[LI_COL]]));
       }
       sts6(E.at(L.X1, i, 6), A);
-      const R m = R(E.lf(i)[LF_MASS]);
-      const V3<R> cw = ld3<R>(E.at(L.c, i, 3));
-      const R* Iw = E.at(L.Iw, i, 6);
-      const SV<R> V = lds6(E.at(L.V, i, 6));
-      sts6(E.at(L.X2, i, 6), sadd(body_mul(m, cw, Iw, A), crf(V, body_mul(m, cw, Iw, V))));
     }
     sync<R>();
   }
+  // body forces of every link at once: they need only its own acceleration and velocity
+  for (int i = lane; i < E.nl; i += 64) {
+    const SV<R> A = lds6(E.at(L.X1, i, 6));
+    const R m = R(E.lf(i)[LF_MASS]);
+    const V3<R> cw = ld3<R>(E.at(L.c, i, 3));
+    const R* Iw = E.at(L.Iw, i, 6);
+    const SV<R> V = lds6(E.at(L.V, i, 6));
+    sts6(E.at(L.X2, i, 6), sadd(body_mul(m, cw, Iw, A), crf(V, body_mul(m, cw, Iw, V))));
+  }
+  sync<R>();
   for (int lev = E.nlev - 2; lev >= 0; --lev) {
     const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
     for (int t = b + lane; t < e; t += 64) {
