@@ -1273,10 +1273,8 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   E.phase(5);
   // ---- C(q, qd) reverse (weight -1, seed w): W_hat, A (RNEA accelerations) outward
   link_vel(E, ww, L.X0);
-  for (int lev = 0; lev < E.nlev; ++lev) {
-    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
-    for (int t = b + lane; t < e; t += 64) {
-      const int i = M.level_links[t];
+  {  // per-link terms, independent across links: all links at once
+    for (int i = lane; i < E.nl; i += 64) {
       const int* li = E.li(i);
       // X1 still holds the RNEA accelerations of the forward pass; per-link terms:
       const R m = R(E.lf(i)[LF_MASS]);
