@@ -1315,13 +1315,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
       sts6(E.at(L.X2, i, 6), F);
       sts6(E.at(L.X3, i, 6), Ab_);
       sts6(E.at(L.X0, i, 6), Vb);
-      if (li[LI_PARENT] >= 0) {
-        const int c = li[LI_COL];
-        const SV<R> s = joint_s(E, i), Vp = lds6(E.at(L.V, li[LI_PARENT], 6));
-        const SV<R> sb = sadd(sadd(smul(F, ww[c]), smul(crf(Vp, Ab_), -nu[c])), smul(Vb, nu[c]));
-        acc6(E.at(L.sb, i, 6), sb);
-        nui[c] += sdot(Ab_, crm(Vp, s)) + sdot(s, Vb);
-      } else if (li[LI_JTYPE] == J_FREE) {
+      if (li[LI_PARENT] < 0 && li[LI_JTYPE] == J_FREE) {
         const int c = li[LI_ROOTCOL];
         const V3<R> v = mk(nu[c], nu[c + 1], nu[c + 2]), w = mk(nu[c + 3], nu[c + 4], nu[c + 5]);
         const V3<R> wwv = mk(ww[c + 3], ww[c + 4], ww[c + 5]);
@@ -1336,6 +1330,18 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
     }
     sync<R>();
   }
+  // joint terms of every non-root link at once from its summed F, Abar, Vbar
+  for (int i = lane; i < E.nl; i += 64) {
+    const int* li = E.li(i);
+    if (li[LI_PARENT] < 0) continue;
+    const SV<R> F = lds6(E.at(L.X2, i, 6)), Ab_ = lds6(E.at(L.X3, i, 6)), Vb = lds6(E.at(L.X0, i, 6));
+    const int c = li[LI_COL];
+    const SV<R> s = joint_s(E, i), Vp = lds6(E.at(L.V, li[LI_PARENT], 6));
+    const SV<R> sb = sadd(sadd(smul(F, ww[c]), smul(crf(Vp, Ab_), -nu[c])), smul(Vb, nu[c]));
+    acc6(E.at(L.sb, i, 6), sb);
+    nui[c] += sdot(Ab_, crm(Vp, s)) + sdot(s, Vb);
+  }
+  sync<R>();
   E.phase(6);
   // ---- constraint rows: per row, the adjoints of its contact point (x) and direction (d) from the
   // velocities Jbar_r induces on its bodies; limit rows: the bias adjoint of the joint position
@@ -1482,9 +1488,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
       SV<R> Wc = lds6(E.at(L.wr, i, 6));
       for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) Wc = sadd(Wc, lds6(E.at(L.wr, M.children[k], 6)));
       sts6(E.at(L.wr, i, 6), Wc);
-      if (li[LI_PARENT] >= 0) {
-        qb[li[LI_DOF]] += sdot(joint_s(E, i), Wc);
-      } else if (li[LI_JTYPE] == J_FREE) {
+      if (li[LI_PARENT] < 0 && li[LI_JTYPE] == J_FREE) {
         int a = 0;
         while (M.ai[a * AI_COLS + AI_ROOT] != i) ++a;
         const V3<R> p0 = ld3<R>(E.at(L.p, i, 3));
@@ -1501,6 +1505,11 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
     }
     sync<R>();
   }
+  for (int i = lane; i < E.nl; i += 64) {  // joint-position adjoints of every non-root link at once
+    const int* li = E.li(i);
+    if (li[LI_PARENT] >= 0) qb[li[LI_DOF]] += sdot(joint_s(E, i), lds6(E.at(L.wr, i, 6)));
+  }
+  sync<R>();
   E.phase(7);
   // ---- adjoint of the substep's start state
   for (int j = lane; j < nd; j += 64) {
