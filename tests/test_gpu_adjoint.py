@@ -190,21 +190,28 @@ def test_rollout_equals_chained_step_adjoints(fp64, case):
         assert (rel <= 1e-3).mean() >= 0.75, rel
 
 
-@pytest.mark.parametrize("case", ["ant", "humanoid_many_rows"])
+@pytest.mark.parametrize("case", ["ant", "humanoid_many_rows", "hand_targets"])
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
 def test_rollout_tape_equals_checkpoints(fp64, case):
     """A rollout whose forward pass stores the whole tape (every = 0: states before every step, substep
     states, row-count flags) and whose backward pass recomputes nothing gives the same final state and
     the same gradients, bit for bit, as the checkpointed rollout (every 4) that recomputes them: the
     stored values are the ones the recomputation produces."""
+    from paper_2108_10470_amd import ags
+    control = ags.DOF_ACTUATION
     if case == "ant":
         E, T = 16, 16
         env, params, oe, root, dof, acts = _ant_rollout_case(E, T)
-    else:
+    elif case == "humanoid_many_rows":
         E, T = 16, 8
         env, params, oe, root, dof, acts = _humanoid_rows_case(T)
-    from paper_2108_10470_amd import ags
-    sim = ags.Sim([ags.Model(env)], [0] * E, params, device="cuda:0", fp64=fp64)
+    else:  # hand + cube driven by PD position targets (the actions are the targets)
+        E, T = 8, 8
+        env, params = W.as_f32(W.env_hand_cube()), W.params_f32(W.HAND_PARAMS)
+        root, dof = W.initial_state(env, E, 0)
+        acts = W.pd_targets(env, E, T, 0).astype(np.float32).astype(np.float64)
+        control = ags.DOF_POS_TARGET
+    sim = ags.Sim([ags.Model(env)], [0] * E, params, device="cuda:0", fp64=fp64, pd=control == ags.DOF_POS_TARGET)
     f32 = dict(dtype=torch.float32, device="cuda:0")
     wr = torch.tensor(np.random.default_rng(11).standard_normal(E * env.n_actors * 13), **f32)
     wd = torch.tensor(np.random.default_rng(12).standard_normal(E * env.n_dof * 2), **f32)
@@ -213,7 +220,7 @@ def test_rollout_tape_equals_checkpoints(fp64, case):
         a = torch.tensor(acts.reshape(T, E * env.n_dof), **f32).requires_grad_(True)
         r0 = torch.tensor(root.reshape(-1, 13), **f32).requires_grad_(True)
         d0 = torch.tensor(dof.reshape(-1, 2), **f32).requires_grad_(True)
-        r, d = ags.rollout(sim, a, r0, d0, every=every)
+        r, d = ags.rollout(sim, a, r0, d0, every=every, control=control)
         ((r.reshape(-1) * wr).sum() + (d.reshape(-1) * wd).sum()).backward()
         torch.cuda.synchronize()
         out[every] = [x.detach().clone() for x in (r, d, a.grad, r0.grad, d0.grad)]
