@@ -366,7 +366,8 @@ struct Ctx {
 template <typename R>
 struct Tab {
   int n_links, n_actors, n_dof, n_v, n_slots, n_levels, n_anc, r_cap, jfast;
-  const int *li, *level_begin, *level_links, *children, *anc_link, *dof_link, *ai;
+  const int *li, *level_begin, *level_links, *children, *dof_link, *ai;
+  const int* anc_link;  // per ancestor entry: link | (column << 16)
   const int *si, *body_slot_begin, *body_slot;
   const double *lf, *sf;
   int n_tj;  // fixed tendons (global memory)
@@ -392,7 +393,16 @@ __device__ __forceinline__ Tab<R> stage_tables(const DevModel& G, R* smem, const
   T.level_begin = copy_i(L.t_lev, G.level_begin, G.n_levels + 1);
   T.level_links = copy_i(L.t_links, G.level_links, G.n_links);
   T.children = copy_i(L.t_child, G.children, G.n_links - G.n_actors);
-  T.anc_link = copy_i(L.t_anc, G.anc_link, G.n_anc);
+  {  // ancestor entries packed as link | (its generalized column << 16): the row responses then index their
+     // rows with one LDS read per ancestor instead of two dependent ones
+    int* dst = reinterpret_cast<int*>(smem + L.t_anc);
+    if (copy)
+      for (int k = t; k < G.n_anc; k += nthreads) {
+        const int a = G.anc_link[k];
+        dst[k] = a | (G.li[a * LI_COLS + LI_COL] << 16);
+      }
+    T.anc_link = dst;
+  }
   T.dof_link = copy_i(L.t_dof, G.dof_link, G.n_dof);
   T.ai = copy_i(L.t_ai, G.ai, G.n_actors * AI_COLS);
   T.si = G.si;
@@ -985,7 +995,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       const V3<R> Ua = ld3<R>(s.U + 6 * i), Ul = ld3<R>(s.U + 6 * i + 3);
       st3(s.Ubar + 3 * i, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * li[LI_ROOT])), Ul)));
       for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q) {
-        const int k = M.anc_link[q];
+        const int k = M.anc_link[q] & 0xffff;
         const V3<R> ak = ld3<R>(s.ax + 3 * k);
         s.G[q] = M.li[k * LI_COLS + LI_JTYPE] == J_REV ? dot(ak, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * k)), Ul)))
                                                       : dot(ak, Ul);
@@ -1229,7 +1239,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
                   ul[1] * Wrow[rc + 1] + ul[2] * Wrow[rc + 2];
           }
           for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q)
-            acc += s.G[q] * Wrow[M.li[M.anc_link[q] * LI_COLS + LI_COL]];
+            acc += s.G[q] * Wrow[M.anc_link[q] >> 16];
           const int c = li[LI_COL];
           Wrow[c] = (Wrow[c] - acc) * s.Dinv[i];
         }
