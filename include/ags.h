@@ -308,7 +308,8 @@ int ags_rollout_backward_tape(ags_sim* sim, int32_t n_steps, int32_t control, co
                               void* hip_stream);
 
 /* Copy rows of src (same shape as the bound tensor) into the bound root / DOF state tensor for the
- * actors listed in actor_idx (device int32 array of n global actor indices; NULL = all actors).
+ * actors listed in actor_idx (device int32 array of n global actor indices; NULL with n equal to the
+ * total actor count = all actors; n = 0 sets nothing, whatever actor_idx is).
  * Setting a root teleports the actor without changing its DOF poses; setting DOFs leaves roots
  * unchanged (Section 2.3.2). */
 int ags_sim_set_root_state_indexed(ags_sim* sim, const float* src, const int32_t* actor_idx, int32_t n,

@@ -1413,6 +1413,7 @@ extern "C" int ags_autotune(const ags_model* const* models, int32_t n_models, co
 static int set_indexed(ags_sim* S, int which, const float* src, const int32_t* idx, int32_t n, void* stream) {
   if (!S || !src || n < 0 || (!idx && n != 0 && n != S->n_actors_total)) return fail(AGS_E_ARG, "set: bad arguments");
   if (!S->bound[which]) return fail(AGS_E_UNBOUND, "set: target tensor not bound");
+  if (n == 0) return AGS_OK;  // an empty list sets nothing (its pointer may be NULL)
   const int width = which == AGS_ROOT_STATE ? 13 : 2;
   hipError_t e = launch_set_rows((float*)S->bound[which], src, idx, idx ? n : S->n_actors_total, S->n_actors_total,
                                  S->actor_rows, which == AGS_ROOT_STATE ? 0 : 2, width, (hipStream_t)stream);

@@ -244,3 +244,51 @@ def test_rigid_body_states_match_oracle(make, fp64):
         assert np.isfinite(g).all()
     _report(f"rigid_body_state_{env.name}_{'fp64' if fp64 else 'fp32'}", {"envs": E, "max_ratio": worst})
     assert worst <= 1.0
+
+
+@pytest.mark.parametrize("fp64,lanes", [(True, 64), (True, 32), (False, 0)], ids=["fp64_l64", "fp64_l32", "fp32"])
+def test_ragged_batches_and_no_writes_past_the_last_env(fp64, lanes):
+    """Batches of 65, 1 and 3 humanoid-like envs (odd counts leave a spare team in the last wavefront when
+    two envs share one): the 65-env batch matches the oracle; every env of the smaller batches is bitwise
+    the same env of the 65-env batch (a team never reads or writes a neighbour's data); the state and
+    output tensors are bound as prefixes of larger buffers whose NaN tails must survive the step; and an
+    indexed set with an empty index list changes nothing."""
+    env = W.as_f32(W.env_humanoid())
+    p = W.params_f32(W.SimParams())
+    oe, root, dof, act = PT.oracle_states(env, p, n_envs=13, n_steps=120, every=24)
+    r32 = lambda x: x.astype(np.float32).astype(np.float64)
+    root, dof, act = r32(root), r32(dof), r32(act)
+    assert root.shape[0] == 65
+    model = ags.Model(env)
+    full = None
+    keys = ("root", "dof", "qdd_free", "row_count", "row_key", "row_lambda", "contact_force", "dof_force")
+    for E in (65, 1, 3):
+        print("ragged batch", E, flush=True)
+        sim = ags.Sim([model], [0] * E, p, device="cuda:0", debug=True, fp64=fp64, lanes_per_env=lanes)
+        bufs = {}
+        for which, name in ((ags.ROOT_STATE, "root_state"), (ags.DOF_STATE, "dof_state"),
+                            (ags.NET_CONTACT_FORCE, "contact_force"), (ags.DOF_FORCE, "dof_force")):
+            t = getattr(sim, name)
+            buf = torch.full((t.shape[0] + 64,) + tuple(t.shape[1:]), float("nan"), dtype=t.dtype, device=t.device)
+            view = buf[:t.shape[0]]
+            view.zero_()
+            sim.bind(which, view)
+            setattr(sim, name, view)
+            bufs[name] = (buf, t.shape[0])
+        g = PT.gpu_step(sim, env, root[:E], dof[:E], act[:E])
+        for name, (buf, n) in bufs.items():
+            assert torch.isnan(buf[n:]).all(), (E, name)
+        before = sim.root_state.clone()
+        sim.set_root_state_indexed(torch.zeros_like(sim.root_state), torch.zeros(0, dtype=torch.int32, device="cuda:0"))
+        torch.cuda.synchronize()
+        assert torch.equal(before, sim.root_state)
+        if full is None:
+            full = g
+            o = oe.step(p, root, dof, act, r_cap=g["row_key"].shape[2])
+            s = PT.summarize(PT.compare(env, p, g, o))
+            _report(f"ragged_65_{'fp64' if fp64 else 'fp32'}_l{lanes}", s)
+            _assert_pass(s) if fp64 else _assert_fp32(s)
+        else:
+            for k in keys:
+                a, b = g[k], full[k][:E]
+                assert np.array_equal(a, b, equal_nan=True), (E, k)

@@ -70,3 +70,19 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text and "oracle.h" not in text, f
+
+
+def test_sim_argument_errors_are_reported_before_any_device_work():
+    """An empty batch, an env naming a model that does not exist, a non-positive dt, zero substeps and
+    an unknown solver are refused by ags_sim_create with an error message (host checks only: these run
+    before the library touches a device)."""
+    m = ags.Model(W.as_f32(W.env_ant()))
+    with pytest.raises(RuntimeError, match="bad arguments"):
+        ags.Sim([m], [], W.SimParams(), device="cpu")
+    with pytest.raises(RuntimeError, match="bad env model index"):
+        ags.Sim([m], [0, 1], W.SimParams(), device="cpu")
+    for bad in (W.SimParams(dt=0.0), W.SimParams(substeps=0)):
+        with pytest.raises(RuntimeError, match="bad parameters"):
+            ags.Sim([m], [0], bad, device="cpu")
+    with pytest.raises(RuntimeError, match="unknown solver"):
+        ags.Sim([m], [0], W.SimParams(solver=2), device="cpu")
