@@ -1068,7 +1068,7 @@ extern "C" int ags_sim_jacobian_mass(ags_sim* S, int32_t model, float* jac, floa
   for (const TypeDev& t : S->types)
     if (t.model == model) T = &t;
   if (!T) return fail(AGS_E_ARG, "jacobian_mass: no environment uses this model");
-  if (jacmass_lds_bytes(T->dm.n_links) > 64 * 1024) return fail(AGS_E_ARG, "jacobian_mass: model too large");
+  if (jacmass_lds_bytes(T->dm.n_links, T->dm.n_v) > 64 * 1024) return fail(AGS_E_ARG, "jacobian_mass: model too large");
   JacMassArgs a{};
   a.m = T->dm;
   a.env_list = T->env_list;

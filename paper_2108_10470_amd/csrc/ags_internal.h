@@ -150,7 +150,7 @@ struct JacMassArgs {
   const int* env_body_base;
   const float* mass_scale;  // optional (N_B): per-link factor on mass and inertia
 };
-size_t jacmass_lds_bytes(int n_links);
+size_t jacmass_lds_bytes(int n_links, int n_v);
 hipError_t launch_jacmass(const JacMassArgs& a, hipStream_t stream);
 
 // ---------------------------------------------------------------- adjoint of one env-step
