@@ -2,7 +2,7 @@
 // state tensors, articulated actors expose Jacobian matrices and generalized mass matrices, per
 // homogeneous group of actors, for operational-space control and inverse kinematics; Table 1).
 //
-// One 256-lane workgroup (four wavefronts) per environment, FP64 throughout (outputs FP32):
+// One 128-lane workgroup (two wavefronts) per environment, FP64 throughout (outputs FP32):
 //   1. forward kinematics level by level (lanes over the links of a level): link rotation, origin and
 //      world joint axis, in LDS;
 //   2. composite inertias: every link's mass, first moment and rotational inertia about a reference
@@ -66,7 +66,7 @@ __device__ __forceinline__ Kin kin_arrays(double* base, int nl) {
   return k;
 }
 
-constexpr int kJmThreads = 256;
+constexpr int kJmThreads = 128;
 constexpr int kJmLf = LF_IC + 6;  // float columns the kinematics and inertias use
 
 __global__ __launch_bounds__(kJmThreads) void jacmass_kernel(JacMassArgs A) {
