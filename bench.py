@@ -272,7 +272,9 @@ def run_jacmass(env, params, n_envs, root0, dof0, reps=20):
     torch.cuda.synchronize()
     ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     out_bytes = 4 * (J.numel() + M.numel())
-    return {"envs": n_envs, "ms": ms, "output_bytes": out_bytes, "output_GB_per_s": out_bytes / (ms / 1e3) / 1e9,
+    gbs = out_bytes / (ms / 1e3) / 1e9
+    return {"envs": n_envs, "ms": ms, "output_bytes": out_bytes, "output_GB_per_s": gbs,
+            "frac_of_hbm_peak": gbs / PEAK_HBM_GBS,
             "finite": bool(torch.isfinite(J).all() and torch.isfinite(M).all())}
 
 
