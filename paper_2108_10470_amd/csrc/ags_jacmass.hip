@@ -53,7 +53,7 @@ __device__ __forceinline__ void rot(const double* q, double* R) {
 
 // per-link LDS arrays (FP64 words)
 struct Kin {
-  double *R, *q, *o, *ax, *c, *I;
+  double *R, *q, *o, *ax;
 };
 __device__ __forceinline__ Kin kin_arrays(double* base, int nl) {
   Kin k;
@@ -61,15 +61,14 @@ __device__ __forceinline__ Kin kin_arrays(double* base, int nl) {
   k.q = k.R + 9 * nl;
   k.o = k.q + 4 * nl;
   k.ax = k.o + 3 * nl;
-  k.c = k.ax + 3 * nl;
-  k.I = k.c + 3 * nl;
   return k;
 }
 
 constexpr int kJmThreads = 128;
-constexpr int kJmLf = LF_IC + 6;  // float columns the kinematics and inertias use
 
-__global__ __launch_bounds__(kJmThreads) void jacmass_kernel(JacMassArgs A) {
+// Eight wavefronts per SIMD: at ~10 KB of LDS per env a CU holds fifteen workgroups, and the compiler's
+// default register budget would admit only six wavefronts per SIMD (one FP64 register pair spills).
+__global__ __launch_bounds__(kJmThreads) __attribute__((amdgpu_waves_per_eu(8))) void jacmass_kernel(JacMassArgs A) {
   extern __shared__ double g_jm_lds[];
   const DevModel& M = A.m;
   const int nl = M.n_links, nv = M.n_v, lane = threadIdx.x;
@@ -77,15 +76,14 @@ __global__ __launch_bounds__(kJmThreads) void jacmass_kernel(JacMassArgs A) {
   if (ei >= A.n_envs) return;
   const int env = A.env_list[ei];
   const int abase = A.env_actor_base[env], dbase = A.env_dof_base[env], bbase = A.env_body_base[env];
-  const Kin K = kin_arrays(g_jm_lds, nl);  // R, q, o, ax used; c and I unused
-  double* const own = K.I + 6 * nl;  // per link: mass, first moment (3), rotational inertia (6) about the
+  const Kin K = kin_arrays(g_jm_lds, nl);
+  double* const own = K.ax + 3 * nl; // per link: mass, first moment (3), rotational inertia (6) about the
   double* const cmp = own + 10 * nl; //   reference point; the same summed over the link's subtree
   double* const sc = cmp + 10 * nl;  // per column: motion axis w, v at the reference point (6)
   double* const fc = sc + 6 * nv;    // per column: momentum L, p (6)
   double* const qv = fc + 6 * nv;    // per link: joint position (0 for roots)
   unsigned long long* const anc = reinterpret_cast<unsigned long long*>(qv + nl);  // per link: ancestor mask
-  double* const lfs = reinterpret_cast<double*>(anc + nl);  // per link: the first kJmLf float columns
-  int* const jtp = reinterpret_cast<int*>(lfs + kJmLf * nl); // per link: joint type | parent << 8
+  int* const jtp = reinterpret_cast<int*>(anc + nl);        // per link: joint type | parent << 8
   int* const lvl = jtp + nl;                                 // links in level order
   int* const colk = lvl + nl;                                // per column: its link
   // 0. tables every later phase reads, staged once (independent loads spread over the lanes)
@@ -97,14 +95,13 @@ __global__ __launch_bounds__(kJmThreads) void jacmass_kernel(JacMassArgs A) {
     lvl[i] = M.level_links[i];
     qv[i] = (jt == J_FREE || jt == J_FIXED) ? 0.0 : double(A.dof_state[(long long)(dbase + li[LI_DOF]) * 2]);
   }
-  for (int x = lane; x < kJmLf * nl; x += kJmThreads) lfs[x] = M.lf[(x / kJmLf) * LF_COLS + x % kJmLf];
   for (int k = lane; k < nv; k += kJmThreads) colk[k] = M.col_link[k];
   __syncthreads();
   // 1. forward kinematics, one level at a time: only what a child needs of its parent
   for (int lv = 0; lv < M.n_levels; ++lv) {
     for (int t = M.level_begin[lv] + lane; t < M.level_begin[lv + 1]; t += kJmThreads) {
       const int i = lvl[t];
-      const double* lf = lfs + kJmLf * i;
+      const double* lf = M.lf + i * LF_COLS;
       const int jt = jtp[i] & 0xff;
       double* q = K.q + 4 * i;
       if (jt == J_FREE || jt == J_FIXED) {
@@ -148,7 +145,7 @@ __global__ __launch_bounds__(kJmThreads) void jacmass_kernel(JacMassArgs A) {
     // 2a. every link's own mass terms at once (lanes over links): mass f m, first moment f m c and
     //     rotational inertia f (R Ic R^T + m (|c|^2 1 - c c^T)) about the reference point, c its COM
     for (int i = lane; i < nl; i += kJmThreads) {
-      const double* lf = lfs + kJmLf * i;
+      const double* lf = M.lf + i * LF_COLS;
       const double* R = K.R + 9 * i;
       const double f = A.mass_scale ? double(A.mass_scale[bbase + i]) : 1.0;
       const double m = f * lf[LF_MASS];
@@ -262,9 +259,9 @@ __global__ __launch_bounds__(kJmThreads) void jacmass_kernel(JacMassArgs A) {
 }  // namespace
 
 size_t jacmass_lds_bytes(int n_links, int n_v) {
-  // per link: kinematics 28, own and subtree mass terms 20, q and ancestor mask 2, staged float columns
-  // kJmLf, joint type and level order 1; per column: axes and momenta 12, link 1
-  return ((size_t)(51 + kJmLf) * std::max(1, n_links) + (size_t)13 * std::max(1, n_v)) * sizeof(double);
+  // per link: kinematics 19, own and subtree mass terms 20, q and ancestor mask 2, joint type and level
+  // order 1; per column: axes and momenta 12, link 1
+  return ((size_t)42 * std::max(1, n_links) + (size_t)13 * std::max(1, n_v)) * sizeof(double);
 }
 
 hipError_t launch_jacmass(const JacMassArgs& a, hipStream_t stream) {
