@@ -301,6 +301,8 @@ class Sim:
         """Jacobian (n, n_links, 6, n_v) and generalized mass matrix (n, n_v, n_v) tensors of the n envs
         that use models[model], in env order, at the bound state (ags_sim_jacobian_mass); None for an
         output not asked for."""
+        if not 0 <= model < len(self.models):
+            raise ValueError(f"jacobian_mass: model {model} is not one of this sim's {len(self.models)} models")
         n = sum(1 for m in self.env_model if m == model)
         info = self.models[model].info
         f32 = dict(dtype=torch.float32, device=self.device)

@@ -130,3 +130,23 @@ def test_jacobian_mass_full_batch_sampled():
         T_J = 0.5 * (m * (vc * vc).sum(1)).sum() + 0.5 * np.einsum("bi,bij,bj->", w, Iw, w)
         assert abs(T_J - T_M[e]) <= 1e-4 * abs(T_J) + 1e-5, (e, T_J, T_M[e])
     assert np.isfinite(M).all() and (np.linalg.eigvalsh(M[::64]).min() > 0)
+
+
+def test_single_output_calls_equal_the_combined_call():
+    """Asking for J alone or M alone (the kernel then skips the other output's phases) returns bitwise
+    what the call asking for both returns; asking for neither output, or for a model the sim does not
+    have, is an error."""
+    env = W.as_f32(W.env_hand_cube())
+    n = 33
+    root, dof = _poses(env, n, 5)
+    sim = ags.Sim([ags.Model(env)], [0] * n, W.SimParams(), device="cuda:0")
+    J, M = _gpu(sim, 0, root, dof)
+    J1, M1 = sim.jacobian_mass(0, jacobian=True, mass=False)
+    J2, M2 = sim.jacobian_mass(0, jacobian=False, mass=True)
+    torch.cuda.synchronize()
+    assert M1 is None and J2 is None
+    assert np.array_equal(J1.double().cpu().numpy(), J) and np.array_equal(M2.double().cpu().numpy(), M)
+    with pytest.raises(RuntimeError, match="bad arguments"):
+        sim.jacobian_mass(0, jacobian=False, mass=False)
+    with pytest.raises(ValueError, match="not one of this sim's 1 models"):
+        sim.jacobian_mass(1)
