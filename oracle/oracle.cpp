@@ -692,7 +692,7 @@ struct Row {
 
 struct StepOut {
   double* qdd_free; int r_cap; int* row_count; int* row_key; double* row_lambda;
-  double* contact_force; double* dof_force; int* near; unsigned long long* mode;
+  double* contact_force; double* contact_scale; double* dof_force; int* near; unsigned long long* mode;
 };
 
 // FNV-1a over the discrete decisions of a step
@@ -735,7 +735,7 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
       dtype[A.dof_off + j] = A.links[j + 1].jtype;
       dlink[A.dof_off + j] = &A.links[j + 1];
     }
-  std::vector<double> cforce(3 * E.n_bodies, 0.0), dforce(nd, 0.0);
+  std::vector<double> cforce(3 * E.n_bodies, 0.0), cscale(2 * E.n_bodies, 0.0), dforce(nd, 0.0);
   const double h = P.h;
   ModeHash mode;
 
@@ -893,6 +893,8 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
         if (r.kind >= 4) { hi = P.mu * lam[r.normal_row]; lo = -hi; }
         double nl = std::min(std::max(x, lo), hi);
         mode.mix(x > hi ? 2 : (x < lo ? 1 : 0));
+        if (std::fabs(x - lo) < 1e-6 * (1.0 + std::fabs(lo)) || std::fabs(x - hi) < 1e-6 * (1.0 + std::fabs(hi)))
+          near |= ORC_NEAR_CLAMP;
         double dl = nl - lam[ri];
         for (int c = 0; c < nv; ++c) v[c] += r.W[c] * dl;
         lam[ri] = nl;
@@ -917,9 +919,13 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
       v3 F = scl(d, lam[ri] / P.dt);
       int ba = E.actors[s.a_actor].body_off + s.a_link;
       for (int k = 0; k < 3; ++k) cforce[3 * ba + k] += F[k];
+      cscale[2 * ba] += 1.0;
+      cscale[2 * ba + 1] += std::fabs(lam[ri]) / P.dt;
       if (s.b_actor >= 0) {
         int bb = E.actors[s.b_actor].body_off + s.b_link;
         for (int k = 0; k < 3; ++k) cforce[3 * bb + k] -= F[k];
+        cscale[2 * bb] += 1.0;
+        cscale[2 * bb + 1] += std::fabs(lam[ri]) / P.dt;
       }
     }
     // ---- semi-implicit integration: qd+ = v; q+ = q + h qd+; root quat+ = normalize(Exp(h w+) (x) quat)
@@ -964,6 +970,8 @@ void step_env(const Env& E, const Params& P, const double* root_in, const double
   }
   if (O.contact_force)
     for (int k = 0; k < 3 * E.n_bodies; ++k) O.contact_force[k] = cforce[k];
+  if (O.contact_scale)
+    for (int k = 0; k < 2 * E.n_bodies; ++k) O.contact_scale[k] = cscale[k];
   if (O.dof_force)
     for (int j = 0; j < nd; ++j) O.dof_force[j] = dforce[j] / P.substeps;
   if (O.mode) *O.mode = mode.h;
@@ -1199,7 +1207,8 @@ int orc_slots(const void* env, const double* root_state, const double* dof_state
 int orc_step(const void* env, const double* params, int n_envs, const double* root_in, const double* dof_in,
              const double* act, const double* pos_tgt, const double* vel_tgt, double* root_out, double* dof_out,
              double* qdd_free, int r_cap, int* row_count, int* row_key, double* row_lambda,
-             double* contact_force, double* dof_force, int* near, unsigned long long* mode, int n_threads) {
+             double* contact_force, double* contact_scale, double* dof_force, int* near, unsigned long long* mode,
+             int n_threads) {
   const Env* E = static_cast<const Env*>(env);
   if (!E || n_envs < 0 || !root_in || !dof_in || !act || !root_out || !dof_out) return -1;
   Params P = read_params(params);
@@ -1215,6 +1224,7 @@ int orc_step(const void* env, const double* params, int n_envs, const double* ro
       O.row_key = row_key ? row_key + (size_t)e * S * r_cap : nullptr;
       O.row_lambda = row_lambda ? row_lambda + (size_t)e * S * r_cap : nullptr;
       O.contact_force = contact_force ? contact_force + (size_t)e * nb * 3 : nullptr;
+      O.contact_scale = contact_scale ? contact_scale + (size_t)e * nb * 2 : nullptr;
       O.dof_force = dof_force ? dof_force + (size_t)e * nd : nullptr;
       O.near = near ? near + (size_t)e * S : nullptr;
       O.mode = mode ? mode + e : nullptr;

@@ -43,9 +43,12 @@ enum {
 /* row key: kind * 2^24 + a * 2^8 + b; kind 1 lower limit / 2 upper limit (a = env DOF index),
  * 3 contact normal / 4 tangent 1 / 5 tangent 2 (a = pair index, b = slot index) */
 
-/* near-switch flag bits (per env, per substep) */
+/* near-switch flag bits (per env, per substep).  ORC_NEAR_CLAMP: some Gauss-Seidel update's unclamped
+ * impulse lies within 1e-6 (1 + |bound|) of a bound it is projected onto; the projection is continuous, so
+ * this flag marks a switch of the step's derivative, not a jump of its value */
 enum {
-  ORC_NEAR_CONTACT = 1, ORC_NEAR_LIMIT = 2, ORC_NEAR_GEOM = 4, ORC_NEAR_SKIP = 8, ORC_NEAR_TANGENT = 16
+  ORC_NEAR_CONTACT = 1, ORC_NEAR_LIMIT = 2, ORC_NEAR_GEOM = 4, ORC_NEAR_SKIP = 8, ORC_NEAR_TANGENT = 16,
+  ORC_NEAR_CLAMP = 32
 };
 
 void* orc_env_create(int n_actors, int n_links, const double* links, int n_shapes, const double* shapes,
@@ -81,6 +84,8 @@ int orc_slots(const void* env, const double* root_state, const double* dof_state
  * root_in/out (n_envs, n_actors, 13); dof_in/out (n_envs, n_dof, 2); act/pos_tgt/vel_tgt (n_envs, n_dof);
  * qdd_free (n_envs, substeps, n_v); row_count (n_envs, substeps); row_key/row_lambda
  * (n_envs, substeps, r_cap); contact_force (n_envs, n_bodies, 3); dof_force (n_envs, n_dof);
+ * contact_scale (n_envs, n_bodies, 2): per body, over the step's substeps, the number of contact rows
+ * acting on it (either side) and the sum of their |impulse| / dt (the scale of its net contact force);
  * near (n_envs, substeps); mode (n_envs): a hash of every discrete decision of the step (row keys, the
  * bias branch of each row, the clamp taken by each Gauss-Seidel update), equal for two inputs exactly when
  * they lie in the same smooth piece of the step (up to hash collisions).  Output pointers may be NULL.
@@ -88,7 +93,8 @@ int orc_slots(const void* env, const double* root_state, const double* dof_state
 int orc_step(const void* env, const double* params, int n_envs, const double* root_in, const double* dof_in,
              const double* act, const double* pos_tgt, const double* vel_tgt, double* root_out, double* dof_out,
              double* qdd_free, int r_cap, int* row_count, int* row_key, double* row_lambda,
-             double* contact_force, double* dof_force, int* near, unsigned long long* mode, int n_threads);
+             double* contact_force, double* contact_scale, double* dof_force, int* near, unsigned long long* mode,
+             int n_threads);
 
 #ifdef __cplusplus
 }

@@ -20,7 +20,10 @@ P_COLS = 13
 _JOINT = {"free": 0, "fixed": 1, "revolute": 2, "prismatic": 3}
 _KIND = {"sphere": 0, "capsule": 1, "box": 2}
 
-NEAR_CONTACT, NEAR_LIMIT, NEAR_GEOM, NEAR_SKIP, NEAR_TANGENT = 1, 2, 4, 8, 16
+NEAR_CONTACT, NEAR_LIMIT, NEAR_GEOM, NEAR_SKIP, NEAR_TANGENT, NEAR_CLAMP = 1, 2, 4, 8, 16, 32
+# the bits that mark a possible jump of the step's value (a row that may or may not exist, an ambiguous
+# geometric choice); NEAR_CLAMP marks only a switch of its derivative (the projection is continuous)
+NEAR_VALUE = NEAR_CONTACT | NEAR_LIMIT | NEAR_GEOM | NEAR_SKIP | NEAR_TANGENT
 
 # guard widths of the mode-switch test: an env-substep is "near a switch" when a contact
 # activation test lies within GUARD_C metres, or a limit activation test within GUARD_L rad (m),
@@ -63,7 +66,7 @@ def lib():
         L.orc_slots.argtypes = [ctypes.c_void_p, dp, dp, dp, dp, dp, ip, ip]
         L.orc_slots.restype = ctypes.c_int
         L.orc_step.argtypes = [ctypes.c_void_p, dp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, dp, ctypes.c_int, ip,
-                               ip, dp, dp, dp, ip, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
+                               ip, dp, dp, dp, dp, ip, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int]
         L.orc_step.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -259,13 +262,15 @@ class OracleEnv:
             root=np.zeros_like(root), dof=np.zeros_like(dof), qdd_free=np.zeros((E, S, self.n_v)),
             row_count=np.zeros((E, S), dtype=np.int32), row_key=np.full((E, S, r_cap), -1, dtype=np.int32),
             row_lambda=np.zeros((E, S, r_cap)), contact_force=np.zeros((E, self.n_bodies, 3)),
+            contact_scale=np.zeros((E, self.n_bodies, 2)),
             dof_force=np.zeros((E, self.n_dof)), near=np.zeros((E, S), dtype=np.int32),
             mode=np.zeros(E, dtype=np.uint64))
         nt = n_threads or os.cpu_count() or 1
         rc = lib().orc_step(self.h, _dp(params_vector(params, guard_c, guard_l)), E, _dp(root), _dp(dof), _dp(act),
                             _dp(pt), _dp(vt), _dp(out["root"]), _dp(out["dof"]), _dp(out["qdd_free"]), r_cap,
                             _ip(out["row_count"]), _ip(out["row_key"]), _dp(out["row_lambda"]),
-                            _dp(out["contact_force"]), _dp(out["dof_force"]), _ip(out["near"]),
+                            _dp(out["contact_force"]), _dp(out["contact_scale"]), _dp(out["dof_force"]),
+                            _ip(out["near"]),
                             out["mode"].ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), nt)
         if rc != 0:
             raise ValueError("oracle: bad step arguments")

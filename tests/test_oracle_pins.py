@@ -919,3 +919,175 @@ def test_capsule_box_slots_brute_force():
             np.testing.assert_allclose(x[k], centre - 0.03 * n[k], atol=1e-12)
             if not inside:
                 assert n[k] @ (centre - (cb + Rb @ np.clip(xl, -half, half))) > 0
+
+
+# ----------------------------------------------------------------------------- two-body contacts and outputs
+def _quat_R(q):
+    x, y, z, w = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+                     [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+                     [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)]])
+
+
+def _sphere_box_env(r, half, box_pos, box_quat=(0, 0, 0, 1), ground=False):
+    sphere = W.free_sphere(radius=r, z=1.0)
+    box = W.free_box(half=half, pos=box_pos)
+    box.root_quat = tuple(box_quat)
+    actors = [sphere, box]
+    pairs = [W.Pair(0, 0, 0, 1, 0, 0)]
+    if ground:
+        pairs.append(W.Pair(1, 0, 0))
+    return _env(actors, pairs)
+
+
+@pytest.mark.parametrize("offset", [(0.0, 0.0), (0.03, -0.02)])
+def test_sphere_box_contact_conserves_momentum(offset):
+    """Gravity-free sphere hitting a free box (two-body rows: the partner's Jacobian enters with the opposite
+    sign): over one substep the contact impulses are internal, so total linear momentum and angular momentum
+    about the origin (sum of m c x v + I_world w, at the substep's start pose) are unchanged to rounding; each
+    body's momentum change is its own net contact force x dt, and the two forces are equal and opposite.  The
+    off-centre hit (with a sliding component, so friction rows act) spins the box."""
+    r, half = 0.05, (0.1, 0.08, 0.06)
+    env = _sphere_box_env(r, half, (0.0, 0.0, 0.0), box_quat=(0.1, -0.2, 0.05, 0.97))
+    oe = O.OracleEnv(env)
+    p = _params(substeps=1, gravity=(0.0, 0.0, 0.0), pgs_iters=20)
+    h = p.dt
+    q_box = np.array([0.1, -0.2, 0.05, 0.97])
+    q_box /= np.linalg.norm(q_box)
+    Rb = _quat_R(q_box)
+    # sphere 4 mm off the box's +x face (in box coordinates), at an offset on that face, moving towards it
+    loc = np.array([half[0] + r + 0.004, offset[0], offset[1]])
+    cs = Rb @ loc
+    vs = Rb @ np.array([-2.0, 0.6, -0.3])
+    root = np.array([[[*cs, 0, 0, 0, 1, *vs, 0, 0, 0],
+                      [0, 0, 0, *q_box, 0.1, -0.05, 0.02, 0, 0, 0]]])
+    o = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))
+    assert o["row_count"][0, 0] == 3 and (o["row_key"][0, 0, 0] >> 24) == 3
+    assert abs(o["row_lambda"][0, 0, 0]) > 1e-3 and abs(o["row_lambda"][0, 0, 1]) > 1e-5
+    m, com, Ic = oe.mass_props()
+    assert np.allclose(com, 0.0)
+    Iw = [Ic[0], Rb @ Ic[1] @ Rb.T]  # the sphere's inertia is isotropic
+    c = root[0, :, :3]
+
+    def momenta(state):
+        P = sum(m[b] * state[b, 7:10] for b in range(2))
+        L = sum(m[b] * np.cross(c[b], state[b, 7:10]) + Iw[b] @ state[b, 10:13] for b in range(2))
+        return P, L
+
+    P0, L0 = momenta(root[0])
+    P1, L1 = momenta(o["root"][0])
+    scale = m[0] * np.linalg.norm(vs)
+    assert np.abs(P1 - P0).max() < 1e-13 * scale
+    assert np.abs(L1 - L0).max() < 1e-13 * scale
+    dp = np.array([m[b] * (o["root"][0, b, 7:10] - root[0, b, 7:10]) for b in range(2)])
+    F = o["contact_force"][0]
+    np.testing.assert_allclose(F * p.dt, dp, rtol=1e-12, atol=1e-14 * scale)
+    np.testing.assert_array_equal(F[0], -F[1])
+    # the box turns about its COM by the moment of the force applied at the contact point on the sphere side
+    x = cs - r * (cs - Rb @ np.array([half[0], offset[0], offset[1]])) / np.linalg.norm(cs - Rb @ np.array([half[0], offset[0], offset[1]]))
+    dL_box = Iw[1] @ o["root"][0, 1, 10:13]
+    np.testing.assert_allclose(dL_box, np.cross(x - c[1], F[1] * p.dt), atol=1e-12 * scale)
+    if offset != (0.0, 0.0):
+        assert np.linalg.norm(o["root"][0, 1, 10:13]) > 1e-2
+
+
+def test_sphere_on_box_on_plane_converged_impulses():
+    """A sphere resting on the centre of a box that rests on the plane, at rest, touching (gap 0), with
+    gravity: with the sweeps converged the sphere-box normal impulse is m_s g h (the sphere stays at rest)
+    and the box's four bottom-corner impulses sum to (m_s + m_b) g h; the net contact forces are m_s g up on
+    the sphere and m_b g up on the box (the plane's (m_s + m_b) g minus the sphere's reaction)."""
+    r, half = 0.05, (0.1, 0.08, 0.06)
+    env = _sphere_box_env(r, half, (0.0, 0.0, half[2]), ground=True)
+    oe = O.OracleEnv(env)
+    p = _params(substeps=1, pgs_iters=400)
+    h = p.dt
+    root = np.array([[[0, 0, 2 * half[2] + r, 0, 0, 0, 1] + [0] * 6, [0, 0, half[2], 0, 0, 0, 1] + [0] * 6]])
+    o = oe.step(p, root, np.zeros((1, 0, 2)), np.zeros((1, 0)))
+    m = oe.mass_props()[0]
+    keys = o["row_key"][0, 0, :o["row_count"][0, 0]]
+    lam = o["row_lambda"][0, 0, :o["row_count"][0, 0]]
+    normal = (keys >> 24) == 3
+    pair = (keys >> 8) & 0xFFFF
+    assert normal.sum() == 5  # sphere-box, then the four bottom corners (the top ones are far above)
+    assert abs(lam[normal & (pair == 0)][0] - m[0] * G * h) < 1e-9 * m[0] * G * h
+    assert abs(lam[normal & (pair == 1)].sum() - (m[0] + m[1]) * G * h) < 1e-9 * (m[0] + m[1]) * G * h
+    np.testing.assert_allclose(o["contact_force"][0, 0], [0, 0, m[0] * G], atol=1e-9 * m[0] * G)
+    np.testing.assert_allclose(o["contact_force"][0, 1], [0, 0, m[1] * G], atol=1e-9 * (m[0] + m[1]) * G)
+    np.testing.assert_allclose(o["root"][0, :, 7:13], 0.0, atol=1e-9)
+    # the per-body scale of the contact force: rows acting on each body and the sum of their |impulse| / dt
+    cs = o["contact_scale"][0]
+    assert cs[0, 0] == 3 and cs[1, 0] == 15
+    assert abs(cs[0, 1] - m[0] * G) < 1e-9 * m[0] * G
+
+
+def test_dof_force_is_the_generalized_momentum_change_from_rest():
+    """DOF force = the joint force applied in the step, the drive evaluated at the new velocity.  From rest,
+    without gravity, contacts or active limits and with one substep, the generalized momentum balance is
+    (M(q) + diag(armature)) qd+ / h = that force (the implicit drive's h kd + h^2 kp armature only moves
+    the drive's evaluation from qd to qd+), with M the kinetic-energy matrix pinned separately."""
+    arm = W.arm_with_gripper()
+    rng = np.random.default_rng(3)
+    for k, l in enumerate(arm.links[1:]):
+        l.kp, l.kd = float(rng.uniform(5, 40)), float(rng.uniform(0.5, 4))
+        l.lower, l.upper = -math.inf, math.inf
+    env = _env([arm], [])
+    oe = O.OracleEnv(env)
+    p = _params(substeps=1, gravity=(0.0, 0.0, 0.0))
+    h = p.dt
+    nd = env.n_dof
+    root = np.zeros((1, 1, 13))
+    root[0, 0, 6] = 1.0
+    dof = np.zeros((1, nd, 2))
+    dof[0, :, 0] = rng.uniform(-1, 1, nd)
+    act = rng.uniform(-5, 5, (1, nd))
+    tgt = rng.uniform(-1, 1, (1, nd))
+    o = oe.step(p, root, dof, act, pos_tgt=tgt)
+    assert o["row_count"][0, 0] == 0
+    M = oe.mass_matrix(root[0], dof[0])
+    arm_diag = np.array([l.armature for l in arm.links[1:]])
+    qd1 = o["dof"][0, :, 1]
+    expect = (M + np.diag(arm_diag)) @ qd1 / h
+    np.testing.assert_allclose(o["dof_force"][0], expect, rtol=1e-10, atol=1e-10 * np.abs(expect).max())
+    assert np.abs(o["dof_force"][0] - act[0]).max() > 1.0  # the drive contributes
+
+
+def test_dof_force_averages_over_substeps():
+    """A single revolute DOF without gravity (constant inertia, no velocity-product force): every substep's
+    applied force is (I + armature) (qd_{s+1} - qd_s) / h, so the step's DOF force, their average over the
+    substeps, is (I + armature) (qd_end - qd_start) / dt for any number of substeps."""
+    l, r, kp, kd, arm = 0.3, 0.04, 30.0, 1.5, 0.01
+    a = _bob_pendulum(l, r)
+    a.links[1].kp, a.links[1].kd, a.links[1].armature = kp, kd, arm
+    env = _env([a], [])
+    oe = O.OracleEnv(env)
+    mb = 1000 * 4 / 3 * math.pi * r ** 3
+    I = mb * (l * l + 0.4 * r * r)
+    root = np.array([[[0, 0, 2, 0, 0, 0, 1] + [0] * 6]])
+    for sub in (1, 2, 5):
+        p = _params(gravity=(0, 0, 0), substeps=sub)
+        dof = np.array([[[0.2, -1.3]]])
+        o = oe.step(p, root, dof, np.array([[0.7]]), pos_tgt=np.array([[0.9]]), vel_tgt=np.array([[0.4]]))
+        expect = (I + arm) * (o["dof"][0, 0, 1] - dof[0, 0, 1]) / p.dt
+        assert abs(o["dof_force"][0, 0] - expect) < 1e-11 * max(1.0, abs(expect)), sub
+
+
+@pytest.mark.parametrize("delta,flagged", [(0.0, True), (1e-9, True), (0.2, False), (-0.2, False)])
+def test_clamp_near_switch_flag(delta, flagged):
+    """The near-switch flags mark a Gauss-Seidel update whose unclamped impulse lies within 1e-6 (1 + |bound|)
+    of the bound it is projected onto: a pendulum approaching its lower limit at exactly the speed that closes
+    the gap in one substep has a zero unclamped impulse on the speculative limit row (delta = 0); a few
+    per cent faster or slower it is far from the bound.  The flag is not one of the value-jump bits."""
+    a = _bob_pendulum(0.5, 0.05)
+    a.links[1].lower, a.links[1].upper = -0.2, 3.0
+    env = _env([a], [])
+    oe = O.OracleEnv(env)
+    p = _params(substeps=1, pgs_iters=1, gravity=(0, 0, 0))
+    h = p.dt
+    gap = 0.01
+    q0 = -0.2 + gap
+    qd0 = -(q0 - (-0.2)) / h * (1.0 + delta)
+    o = oe.step(p, np.array([[[0, 0, 2, 0, 0, 0, 1] + [0] * 6]]), np.array([[[q0, qd0]]]), np.zeros((1, 1)))
+    assert o["row_count"][0, 0] == 1
+    assert bool(o["near"][0, 0] & O.NEAR_CLAMP) == flagged
+    assert not (o["near"][0, 0] & O.NEAR_VALUE)
+    assert O.NEAR_VALUE & O.NEAR_CLAMP == 0
