@@ -149,6 +149,9 @@ typedef struct {
                                the velocity times h / pgs_iters is accumulated per row as J_r v, and each
                                contact-normal and limit row's bias is recomputed from its position error
                                plus that accumulated displacement.  The adjoint supports PGS only. */
+  int32_t adjoint_max_rows; /* 0: 64; 1..64: constraint rows per substep the adjoint accepts (an environment
+                               whose substep has more gets a zero adjoint and status 1); a smaller cap
+                               shrinks the adjoint's LDS layout */
 } ags_sim_params;
 
 enum { AGS_SOLVER_PGS = 0, AGS_SOLVER_TGS = 1 };
@@ -229,8 +232,8 @@ int ags_sim_step(ags_sim* sim, void* hip_stream);
  * the recomputed step takes (a mode switch is where the step is not differentiable).  Quaternion
  * adjoints are tangent to the unit sphere; the pose of a fixed root is a constant (its adjoint rows
  * come back zero); PD targets receive no adjoint.
- * Limits: at most 32 Gauss-Seidel sweeps, at most 64 constraint rows per environment and substep: an environment
- * whose substep has more gets zero adjoints and status[env] = 1 (status: optional device int32 per
+ * Limits: at most 32 Gauss-Seidel sweeps, at most adjoint_max_rows (default 64) constraint rows per environment
+ * and substep: an environment whose substep has more gets zero adjoints and status[env] = 1 (status: optional device int32 per
  * environment, 0 on success).  Computes in the precision chosen by adjoint_precision. */
 int ags_sim_step_backward(ags_sim* sim, const float* root_state, const float* dof_state, const float* actuation,
                           float* root_adj, float* dof_adj, float* act_adj, int32_t* status, void* hip_stream);
@@ -280,10 +283,12 @@ int ags_rollout_forward(ags_sim* sim, int32_t n_steps, int32_t every, int32_t co
  * target enters the step only through the drive force kp (q* - q - h qd)).  seg is caller-owned device
  * scratch of ags_rollout_seg_bytes(sim, every) bytes (two segment buffers): each segment is recomputed
  * from its checkpoint with ags_sim_step (output tensors untouched), keeping every step's substep states,
- * and its steps are reversed with ags_sim_step_backward (status as there), which then starts from those
- * states instead of recomputing them.  The recomputation of the next (earlier) segment runs on a second
- * stream the sim owns, overlapping the current segment's adjoint; events order the two buffers, and all
- * work is joined into hip_stream before the call's last launch. */
+ * and its steps are reversed with ags_sim_step_backward, which then starts from those states instead of
+ * recomputing them.  status (optional, device int32 per environment) is cleared by the call and set to 1
+ * for every environment that exceeded the adjoint's row capacity at ANY step of the rollout (its zero
+ * adjoint at that step also zeroes the gradients of all earlier steps).  The recomputation of the next
+ * (earlier) segment runs on a second stream the sim owns, overlapping the current segment's adjoint;
+ * events order the two buffers, and all work is joined into hip_stream before the call's last launch. */
 int ags_rollout_seg_bytes(const ags_sim* sim, int32_t every, int64_t* bytes);
 int ags_rollout_backward(ags_sim* sim, int32_t n_steps, int32_t every, int32_t control, const float* actions,
                          const float* ckpt, void* seg, float* root_adj, float* dof_adj, float* act_adj,
@@ -297,7 +302,7 @@ int ags_rollout_backward(ags_sim* sim, int32_t n_steps, int32_t every, int32_t c
  * steps with many constraint rows (which adjoint layout to use).  ags_rollout_forward_tape advances the
  * bound state tensors like ags_rollout_forward (same actions and control conventions, output tensors
  * written by every step); ags_rollout_backward_tape, with the same n_steps, control, actions and tape,
- * returns the same adjoints as ags_rollout_backward (root_adj / dof_adj in-out, act_adj, status), bit
+ * returns the same adjoints as ags_rollout_backward (root_adj / dof_adj in-out, act_adj, status as there), bit
  * for bit, since the stored states are the ones a recomputation would produce.  The tape is read only;
  * flagged envs' adjoints run on a stream the sim owns, joined into hip_stream after every step. */
 int ags_rollout_tape_bytes(const ags_sim* sim, int32_t n_steps, int64_t* bytes);

@@ -66,7 +66,8 @@ class SimParams(ctypes.Structure):
                 ("contact_margin", ctypes.c_float), ("limit_margin_rev", ctypes.c_float),
                 ("limit_margin_pri", ctypes.c_float), ("compute_fp64", ctypes.c_int32),
                 ("lanes_per_env", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("adjoint_precision", ctypes.c_int32), ("solver", ctypes.c_int32)]
+                ("adjoint_precision", ctypes.c_int32), ("solver", ctypes.c_int32),
+                ("adjoint_max_rows", ctypes.c_int32)]
 
 
 _lib = None
@@ -184,10 +185,10 @@ class Model:
 
 
 def sim_params(p, fp64: bool = False, lanes_per_env: int = 0, persistent: bool = False,
-               adjoint_precision: int = 0) -> SimParams:
+               adjoint_precision: int = 0, adjoint_max_rows: int = 0) -> SimParams:
     return SimParams(p.dt, p.substeps, _f3(p.gravity), p.pgs_iters, p.mu, p.baumgarte, p.contact_margin,
                      p.limit_margin_rev, p.limit_margin_pri, 1 if fp64 else 0, lanes_per_env, 1 if persistent else 0,
-                     adjoint_precision, int(getattr(p, "solver", 0)))
+                     adjoint_precision, int(getattr(p, "solver", 0)), adjoint_max_rows)
 
 
 class Sim:
@@ -196,7 +197,7 @@ class Sim:
     def __init__(self, models: Sequence[Model], env_model: Sequence[int], params, device="cuda:0",
                  debug: bool = False, pd: bool = False, fp64: bool = False, phase_cycles: bool = False,
                  lanes_per_env: int = 0, persistent: bool = False, adjoint_precision: int = 0,
-                 rigid_body_state: bool = False, status: bool = False):
+                 rigid_body_state: bool = False, status: bool = False, adjoint_max_rows: int = 0):
         self.models = list(models)
         self.env_model = [int(x) for x in env_model]
         self.params = params
@@ -205,7 +206,7 @@ class Sim:
         handles = (ctypes.c_void_p * len(self.models))(*[m.h for m in self.models])
         ids = (ctypes.c_int32 * self.n_envs)(*[int(x) for x in env_model])
         h = ctypes.c_void_p()
-        self._p = sim_params(params, fp64, lanes_per_env, persistent, adjoint_precision)
+        self._p = sim_params(params, fp64, lanes_per_env, persistent, adjoint_precision, adjoint_max_rows)
         _check(lib().ags_sim_create(handles, len(self.models), ids, self.n_envs, ctypes.byref(self._p), ctypes.byref(h)),
                "ags_sim_create")
         self.h = h
@@ -398,9 +399,11 @@ class Rollout(torch.autograd.Function):
                                               ctypes.c_void_p(root_adj.data_ptr()), ctypes.c_void_p(dof_adj.data_ptr()),
                                               ctypes.c_void_p(act_adj.data_ptr()), ctypes.c_void_p(status.data_ptr()),
                                               ctypes.c_void_p(s.cuda_stream)), "ags_rollout_backward")
+        sim.last_rollout_status = status
         bad = int((status != 0).sum())
         if bad:
-            raise RuntimeError(f"adjoint: {bad} environments exceeded the adjoint's row capacity (64 rows per substep)")
+            raise RuntimeError(f"adjoint: {bad} environments exceeded the adjoint's row capacity at some step "
+                               f"(adjoint_max_rows, default 64 rows per substep)")
         return act_adj, root_adj, dof_adj, None, None, None
 
 

@@ -1593,7 +1593,7 @@ __device__ __forceinline__ void adjoint_env(const AdjArgs& P, int ei) {
   for (int k = lane; k < 13 * na; k += 64) P.root_adj[(long long)E.abase * 13 + k] = ok ? float(E.r[L.rbar + k]) : 0.0f;
   for (int k = lane; k < 2 * nd; k += 64) P.dof_adj[(long long)E.dbase * 2 + k] = ok ? float(E.r[L.dbar + k]) : 0.0f;
   for (int j = lane; j < nd; j += 64) P.act_adj[E.dbase + j] = ok ? float(E.r[L.ab + j]) : 0.0f;
-  if (P.status && lane == 0) P.status[env] = ok ? 0 : 1;
+  if (P.status && lane == 0 && (!ok || !P.status_sticky)) P.status[env] = ok ? 0 : 1;
   E.phase(-1);
   if (P.cycles && lane == 0)
     for (int k = 0; k < kAdjPhases; ++k) P.cycles[(long long)env * kAdjPhases + k] = E.cyc[k];
@@ -1649,6 +1649,17 @@ hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t st
 hipError_t launch_compact_flags(const int* env_list, int n, const int* flags, int* list, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(compact_flags_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, env_list, n, flags, list);
+  return hipGetLastError();
+}
+
+__global__ void fill_int_kernel(int* p, int n, int value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
+hipError_t launch_fill_int(int* p, int n, int value, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n, value);
   return hipGetLastError();
 }
 

@@ -586,6 +586,9 @@ struct ags_sim {
   // layout on a third stream beside the small-layout pass (adj_big: this step's flags, or none)
   int* big_out = nullptr;
   const int* adj_big = nullptr;
+  // set while a rollout reverses its steps: the adjoint writes only failures into the status array, which the
+  // rollout cleared first, so an env over the row capacity at any step stays flagged
+  int adj_sticky = 0;
   hipStream_t aux2 = nullptr;
   hipEvent_t ev_big_start = nullptr, ev_big_done = nullptr;
   // persistent (fused) launch
@@ -601,6 +604,8 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
   if (!(p->dt > 0) || p->substeps < 1 || p->pgs_iters < 0) return fail(AGS_E_ARG, "sim: bad parameters");
   if (p->adjoint_precision != 0 && p->adjoint_precision != 32 && p->adjoint_precision != 64)
     return fail(AGS_E_ARG, "sim: adjoint_precision must be 0, 32 or 64");
+  if (p->adjoint_max_rows < 0 || p->adjoint_max_rows > kAdjRows)
+    return fail(AGS_E_ARG, "sim: adjoint_max_rows must be 0 (default 64) or 1..64");
   if (p->solver != AGS_SOLVER_PGS && p->solver != AGS_SOLVER_TGS) return fail(AGS_E_ARG, "sim: unknown solver");
   *out = nullptr;
   for (int e = 0; e < n_envs; ++e)
@@ -745,10 +750,12 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     D.tj_f = (const double*)(b + offs[17]);
     D.tp = (const double*)(b + offs[18]);
     T.body_pairs = M->body_pairs;
-    T.adj = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), kAdjRows);
+    const int adj_cap = p->adjoint_max_rows > 0 ? p->adjoint_max_rows : kAdjRows;
+    const int adj_small_cap = std::min(adj_cap, kAdjSmallRows);
+    T.adj = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), adj_cap);
     T.adj_bytes = (size_t)T.adj.n_real * (adj_fp64(*p) ? sizeof(double) : sizeof(float)) + (size_t)T.adj.n_int * sizeof(int);
-    T.adj_two = M->info.max_rows > kAdjSmallRows;
-    T.adj_small = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), kAdjSmallRows);
+    T.adj_two = std::min(M->info.max_rows, adj_cap) > adj_small_cap;
+    T.adj_small = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), adj_small_cap);
     T.adj_small_bytes = (size_t)T.adj_small.n_real * (adj_fp64(*p) ? sizeof(double) : sizeof(float)) +
                         (size_t)T.adj_small.n_int * sizeof(int);
     max_type_envs = std::max(max_type_envs, T.n_envs);
@@ -1005,6 +1012,7 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
     a.dof_adj = dof_adj;
     a.act_adj = act_adj;
     a.status = status;
+    a.status_sticky = S->adj_sticky;
     a.cycles = (long long*)S->bound[AGS_DEBUG_ADJ_CYCLES];
     a.mid_root = S->mid_root;
     a.mid_dof = S->mid_root ? S->mid_root + 13ll * S->n_actors_total : nullptr;
@@ -1134,6 +1142,11 @@ int reverse_steps(ags_sim* S, int t0, int t1, int control, const float* actions,
   const size_t nr = 13ull * S->n_actors_total, sw = nr + 2ull * S->n_dof_total;
   const size_t na = (size_t)S->n_dof_total;
   const int nmid = std::max(0, S->params.substeps - 1);
+  S->adj_sticky = 1;
+  struct Unsticky {
+    ags_sim* s;
+    ~Unsticky() { s->adj_sticky = 0; }
+  } unsticky{S};
   for (int t = t1 - 1; t >= t0; --t) {
     const float* xt = x + (size_t)(t - t0) * sw;
     void* saved = S->bound[control];
@@ -1258,6 +1271,8 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
   // both buffers start free once the caller's earlier work on the stream is done
   for (int k = 0; k < 2; ++k)
     if ((e = hipEventRecord(S->ev_free[k], st)) != hipSuccess) return hip_fail(e, "rollout_backward: record");
+  if (status && (e = launch_fill_int(status, S->n_envs, 0, st)) != hipSuccess)
+    return hip_fail(e, "rollout_backward: clear status");
   int rc = recompute(n_seg - 1);
   if (rc != AGS_OK) return rc;
   for (int g = n_seg - 1; g >= 0; --g) {
@@ -1327,6 +1342,8 @@ extern "C" int ags_rollout_backward_tape(ags_sim* S, int32_t n_steps, int32_t co
   double* mid;
   int* flags;
   seg_parts(S, const_cast<void*>(tape), n_steps, &x, &mid, &flags);
+  if (status && (e = launch_fill_int(status, S->n_envs, 0, (hipStream_t)stream)) != hipSuccess)
+    return hip_fail(e, "rollout_backward_tape: clear status");
   return reverse_steps(S, 0, n_steps, control, actions, x, mid, flags, root_adj, dof_adj, act_adj, status,
                        (hipStream_t)stream);
 }

@@ -197,6 +197,7 @@ struct AdjArgs {
   float* dof_adj;
   float* act_adj;
   int* status;
+  int status_sticky;  // 0: status[env] = 0 or 1; 1: only failures are written (status kept across a rollout's steps)
   long long* cycles;  // optional, per env: kAdjPhases shader-clock counters
   const double* mid_root;  // optional: substep start states from the forward step (see StepArgs)
   const double* mid_dof;
@@ -216,6 +217,7 @@ hipError_t launch_adjoint(const AdjArgs& a, int n_envs, int fp64, hipStream_t st
 hipError_t launch_compact_flags(const int* env_list, int n, const int* flags, int* list, hipStream_t stream);
 hipError_t set_adjoint_lds_limit(int fp64, size_t bytes);
 hipError_t launch_zero_count(int* c, hipStream_t stream);
+hipError_t launch_fill_int(int* p, int n, int value, hipStream_t stream);
 
 hipError_t launch_scale_by_kp(float* x, const float* kp, int n, hipStream_t stream);
 

@@ -354,3 +354,44 @@ def test_adjoint_is_linear_in_the_seed(fp64):
     # FP64 adjoint: each gradient is rounded to FP32 (6e-8 relative) and 2 g(a) - 3 g(b) carries ~5 such
     # roundings; FP32 adjoint: its own rounding, bounded like the finite-difference checks (FLOOR)
     assert err <= (1e-6 if fp64 else FLOOR[False]), err
+
+
+@pytest.mark.parametrize("every", [0, 2], ids=["tape", "ckpt2"])
+def test_rollout_status_keeps_env_over_row_cap_at_any_step(every):
+    """An env whose substep has more rows than the adjoint accepts gets a zero adjoint at that step, which
+    also zeroes the gradients of every earlier step: the rollout's status must flag it even when the steps
+    reversed after it (the earlier ones) fit.  The adjoint's row capacity is lowered (adjoint_max_rows) to
+    a value that humanoids lying on the ground cross between steps; the row counts of every step come from
+    the GPU forward itself (debug row-count output of the same FP64 steps)."""
+    from paper_2108_10470_amd import ags
+    E, T = 64, 4
+    env, params, oe, root, dof, _, _, _ = A.f32_inputs(W.env_humanoid(), W.SimParams(), E, 120)
+    acts = W.actuation(env, E, T, 3).astype(np.float32).astype(np.float64)
+    f32 = dict(dtype=torch.float32, device="cuda:0")
+    probe = ags.Sim([ags.Model(env)], [0] * E, params, device="cuda:0", fp64=True, debug=True)
+    probe.root_state.copy_(torch.tensor(root.reshape(-1, 13), **f32))
+    probe.dof_state.copy_(torch.tensor(dof.reshape(-1, 2), **f32))
+    rc = np.zeros((T, E), dtype=np.int64)
+    for t in range(T):
+        probe.actuation.copy_(torch.tensor(acts[t].reshape(-1), **f32))
+        probe.step()
+        torch.cuda.synchronize()
+        rc[t] = probe.dbg_rc.cpu().numpy().reshape(E, -1).max(axis=1)
+    # the largest capacity at which some env fits at step 0 and exceeds it at a later step
+    cap = next((c for c in range(int(rc.max()) - 1, 0, -1) if ((rc[0] <= c) & (rc[1:] > c).any(axis=0)).any()), 0)
+    assert cap > 0, rc
+    want = (rc > cap).any(axis=0)
+    late_only = (rc[0] <= cap) & want
+    sim = ags.Sim([ags.Model(env)], [0] * E, params, device="cuda:0", fp64=True, adjoint_max_rows=cap)
+    a = torch.tensor(acts.reshape(T, -1), **f32).requires_grad_(True)
+    r0 = torch.tensor(root.reshape(-1, 13), **f32)
+    d0 = torch.tensor(dof.reshape(-1, 2), **f32)
+    r, d = ags.rollout(sim, a, r0, d0, every=every)
+    with pytest.raises(RuntimeError, match="row capacity"):
+        r[:, 0].sum().backward()
+    got = sim.last_rollout_status.cpu().numpy() != 0
+    _report(f"rollout_status_{'tape' if every == 0 else 'ckpt'}", {"cap": cap, "flagged": int(got.sum()),
+                                                                   "expected": int(want.sum()),
+                                                                   "over_cap_only_after_step0": int(late_only.sum())})
+    assert late_only.any()
+    assert np.array_equal(got, want), (np.nonzero(got)[0].tolist(), np.nonzero(want)[0].tolist())

@@ -64,11 +64,16 @@ def test_heterogeneous_batch_matches_per_type_oracle(fp64):
     lam = sim.dbg_lam.double().cpu().numpy().reshape(E, S, -1)
     abase = np.cumsum([0] + [specs[m].n_actors for m in env_model])
     dbase = np.cumsum([0] + [specs[m].n_dof for m in env_model])
+    bbase = np.cumsum([0] + [specs[m].n_bodies for m in env_model])
+    cf = sim.contact_force.double().cpu().numpy()
+    df = sim.dof_force.double().cpu().numpy()
     for t, (spec, oe, _, _, _) in enumerate(per):
         ids = [e for e in range(E) if env_model[e] == t]
         g = dict(root=np.stack([root_out[abase[e]:abase[e + 1]] for e in ids]),
                  dof=np.stack([dof_out[dbase[e]:dbase[e + 1]] for e in ids]),
-                 qdd_free=qdd[ids][:, :, :spec.n_v], row_count=rc[ids], row_key=key[ids], row_lambda=lam[ids])
+                 qdd_free=qdd[ids][:, :, :spec.n_v], row_count=rc[ids], row_key=key[ids], row_lambda=lam[ids],
+                 contact_force=np.stack([cf[bbase[e]:bbase[e + 1]] for e in ids]),
+                 dof_force=np.stack([df[dbase[e]:dbase[e + 1]] for e in ids]))
         o = oe.step(p, np.stack([roots[e].reshape(spec.n_actors, 13) for e in ids]),
                     np.stack([dofs[e].reshape(spec.n_dof, 2) for e in ids]), np.stack([acts[e] for e in ids]),
                     r_cap=key.shape[2])
@@ -78,7 +83,7 @@ def test_heterogeneous_batch_matches_per_type_oracle(fp64):
         assert np.isfinite(g["root"]).all() and np.isfinite(g["dof"]).all()
         assert s["rows_mismatch_not_near"] == 0, s
         if fp64:
-            for k in ("qdd_free", "q", "lambda"):
+            for k in PT.GATED:
                 assert s[k + "_pass_rate"] == 1.0, (spec.name, k, s)
         else:  # FP32 compute: positions within ten times the FP64 bound (see test_gpu_parity._assert_fp32)
             assert s["q_max_ratio"] <= 10.0, (spec.name, s)
@@ -148,7 +153,7 @@ def test_full_size_batch_sampled_parity():
             r_out = sim.root_state.double().cpu().numpy().reshape(E, 1, 13)[sample]
             d_out = sim.dof_state.double().cpu().numpy().reshape(E, nd, 2)[sample]
             o = oe.step(p, r_in, d_in, acts[t][sample].astype(np.float64))
-            near = (o["near"] != 0).any(axis=1)
+            near = ((o["near"] & O.NEAR_VALUE) != 0).any(axis=1)
             pos_g = np.concatenate([r_out[:, :, :7].reshape(64, -1), d_out[:, :, 0]], axis=1)
             pos_o = np.concatenate([o["root"][:, :, :7].reshape(64, -1), o["dof"][:, :, 0]], axis=1)
             ratio = PT.ratio(pos_g, pos_o).max(axis=1)

@@ -27,7 +27,7 @@ def _report(name, summary):
 
 def _assert_pass(s):
     assert s["rows_mismatch_not_near"] == 0, s
-    for k in ("qdd_free", "q", "lambda"):
+    for k in PT.GATED:
         assert s[k + "_pass_rate"] == 1.0, (k, s)
 
 

@@ -86,7 +86,7 @@ def test_randomized_properties_match_per_env_oracle(case, fp64):
     assert np.isfinite(g["root"]).all()
     assert s["rows_mismatch_not_near"] == 0, s
     if fp64:
-        for k in ("qdd_free", "q", "lambda"):
+        for k in PT.GATED:
             assert s[k + "_pass_rate"] == 1.0, (k, s)
     else:
         assert s["q_max_ratio"] <= 10.0, s
