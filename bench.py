@@ -3,7 +3,10 @@
 
 Workload: humanoid-like robot (13 capsule bodies, free root + 21 revolute DOFs), 4096 envs,
 dt = 1/60 s with 2 substeps, 8 PGS sweeps, seeded actions U[-1, 1] x 67.5, ground contact on every
-body, starting from the seeded standing pose.  One step = one env-step of every env (both substeps).
+body.  With random actions and no resets the humanoids fall within ~60 steps and spend the rest of a
+1000-step run on the ground, so every measurement starts from the state an untimed pre-roll of
+--preroll steps (default 200, FP32 kernel) reaches from the seeded standing pose: the timed window is
+the same regime whatever --steps is.  One step = one env-step of every env (both substeps).
 
 Prints one JSON line.  `value` is env-steps/s of the step that meets the stated tolerance against
 the FP64 oracle (FP64 compute, FP32 tensors); the FP32-compute step is reported beside it.
@@ -60,10 +63,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--preroll", type=int, default=200,
+                    help="untimed steps (FP32 kernel) from the standing start before every measurement")
+    ap.add_argument("--rows-ref-steps", type=int, default=1000,
+                    help="length of the run from the standing start whose mean row count is reported beside "
+                         "the window's (FP32 kernel; 0 skips it)")
     ap.add_argument("--envs", type=int, default=4096)
     ap.add_argument("--precision", choices=["both", "fp64", "fp32"], default="both")
-    ap.add_argument("--cpu-envs", type=int, default=4096, help="oracle sample: envs")
-    ap.add_argument("--cpu-steps", type=int, default=600, help="oracle sample: steps from the seeded start")
+    ap.add_argument("--cpu-envs", type=int, default=4096, help="oracle sample: envs (all host threads)")
+    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle sample: steps of the timed window")
+    ap.add_argument("--cpu-envs-1core", type=int, default=512, help="oracle sample on one thread: envs")
+    ap.add_argument("--cpu-steps-1core", type=int, default=10, help="oracle sample on one thread: steps")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-rows", action="store_true", help="skip the replay that measures mean active rows")
     ap.add_argument("--no-fwd-bwd", action="store_true", help="skip the forward+adjoint rollout measurement")
@@ -78,6 +88,10 @@ def parse():
                     help="skip the temporal Gauss-Seidel and randomized-property variants' measurements")
     ap.add_argument("--hetero-envs", type=int, default=16384)
     ap.add_argument("--hetero-steps", type=int, default=100)
+    ap.add_argument("--hetero-preroll", type=int, default=100)
+    ap.add_argument("--no-ant-grad", action="store_true",
+                    help="skip the differentiation workload (4096 ant-like envs, 64-step rollout, checkpoints "
+                         "every 16)")
     ap.add_argument("--no-hand", action="store_true", help="skip the 65536-env hand+cube measurement")
     ap.add_argument("--hand-envs", type=int, default=65536)
     ap.add_argument("--hand-steps", type=int, default=32)
@@ -86,7 +100,25 @@ def parse():
     return ap.parse_args()
 
 
+def preroll(env, params, n_envs, steps, actions_dev, root0, dof0):
+    """Untimed steps with the FP32 kernel from the standing start; returns copies of the state reached."""
+    import torch
+    from paper_2108_10470_amd import ags
+    sim = ags.Sim([ags.Model(env)], [0] * n_envs, params, device="cuda:0", fp64=False)
+    sim.root_state.copy_(root0)
+    sim.dof_state.copy_(dof0)
+    for t in range(steps):
+        sim.bind(ags.DOF_ACTUATION, actions_dev[t])
+        sim.step()
+    torch.cuda.synchronize()
+    return sim.root_state.clone(), sim.dof_state.clone()
+
+
 def run_gpu(env, params, n_envs, steps, warmup, fp64, actions_dev, root0, dof0, props=None):
+    """warmup untimed steps from (root0, dof0) with actions_dev[0:warmup], then `steps` timed steps with
+    the following actions (HIP events around each launch and around the whole window); then the first
+    chunk of the same window captured in a HIP graph whose first nodes restore the window's start state,
+    replayed, and the same chunk run eagerly from the same state (like-for-like graph vs eager)."""
     import torch
     from paper_2108_10470_amd import ags
     model = ags.Model(env)
@@ -100,11 +132,11 @@ def run_gpu(env, params, n_envs, steps, warmup, fp64, actions_dev, root0, dof0, 
     sim.root_state.copy_(root0)
     sim.dof_state.copy_(dof0)
     stream = torch.cuda.current_stream()
-    nd = env.n_dof
     for t in range(warmup):
         sim.bind(ags.DOF_ACTUATION, actions_dev[t])
         sim.step()
     torch.cuda.synchronize()
+    win_root, win_dof = sim.root_state.clone(), sim.dof_state.clone()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
@@ -122,21 +154,28 @@ def run_gpu(env, params, n_envs, steps, warmup, fp64, actions_dev, root0, dof0, 
     total_ms = start.elapsed_time(stop)
     launch_ms = np.array([a.elapsed_time(b) for a, b in ev])
     finite = bool(torch.isfinite(sim.root_state).all() and torch.isfinite(sim.dof_state).all())
-    # the same steps captured once in a HIP graph (one graph per 50 steps, replayed)
-    graph_ms = None
+    graph_ms = eager_ms = None
     chunk = min(50, steps)
     if chunk > 0:
-        sim.root_state.copy_(root0)
-        sim.dof_state.copy_(dof0)
-        torch.cuda.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
+        def body():
+            sim.root_state.copy_(win_root)
+            sim.dof_state.copy_(win_dof)
             for t in range(chunk):
                 sim.bind(ags.DOF_ACTUATION, actions_dev[warmup + t])
                 sim.step()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        body()  # eager, same steps
+        torch.cuda.synchronize()
+        a.record(stream)
+        body()
+        b.record(stream)
+        torch.cuda.synchronize()
+        eager_ms = a.elapsed_time(b) / chunk
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            body()
         g.replay()
         torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         reps = max(1, steps // chunk)
         a.record(stream)
         for _ in range(reps):
@@ -144,11 +183,13 @@ def run_gpu(env, params, n_envs, steps, warmup, fp64, actions_dev, root0, dof0, 
         b.record(stream)
         torch.cuda.synchronize()
         graph_ms = a.elapsed_time(b) / (reps * chunk)
-    return dict(total_ms=total_ms, wall_s=wall, launch_ms=launch_ms, finite=finite, graph_ms=graph_ms)
+    return dict(total_ms=total_ms, wall_s=wall, launch_ms=launch_ms, finite=finite, graph_ms=graph_ms,
+                eager_same_steps_ms=eager_ms, graph_chunk=chunk, window_root=win_root, window_dof=win_dof)
 
 
-def mean_rows(env, params, n_envs, steps, fp64, actions_dev, root0, dof0):
-    """Replays the same (deterministic) run with the row-count output bound."""
+def mean_rows(env, params, n_envs, steps, fp64, actions_dev, root0, dof0, skip=0):
+    """Replays the same (deterministic) run with the row-count output bound: mean rows per env-substep
+    over steps [skip, steps)."""
     import torch
     from paper_2108_10470_amd import ags
     model = ags.Model(env)
@@ -159,9 +200,10 @@ def mean_rows(env, params, n_envs, steps, fp64, actions_dev, root0, dof0):
     for t in range(steps):
         sim.bind(ags.DOF_ACTUATION, actions_dev[t])
         sim.step()
-        acc += sim.dbg_rc.double().mean()
+        if t >= skip:
+            acc += sim.dbg_rc.double().mean()
     torch.cuda.synchronize()
-    return float(acc.item() / steps)
+    return float(acc.item() / max(1, steps - skip))
 
 
 def run_fwd_bwd(env, params, n_envs, fp64, actions, root0, dof0, every, reps, adjoint_precision=0, control=None):
@@ -278,17 +320,19 @@ def run_jacmass(env, params, n_envs, root0, dof0, reps=20):
             "finite": bool(torch.isfinite(J).all() and torch.isfinite(M).all())}
 
 
-def run_hetero(params, n_envs, steps, fp64):
+def run_hetero(params, n_envs, steps, fp64, preroll_steps):
     """Heterogeneous batch: ant-like, humanoid-like and arm+gripper+box environments in equal thirds,
-    interleaved; per-type launches vs the persistent launch, and the autotuner's pick."""
+    interleaved.  From the state an untimed pre-roll reaches, the same `steps` steps are timed with per-type
+    launches, with the persistent launch, and with the mapping the autotuner picks on that state."""
     import torch
     from paper_2108_10470_amd import ags, workloads as W
     specs = [W.env_ant(), W.env_humanoid(), W.env_arm_box()]
     models = [ags.Model(s) for s in specs]
     env_model = [e % 3 for e in range(n_envs)]
     counts = [env_model.count(k) for k in range(3)]
+    n_act = preroll_steps + steps
     init = [W.initial_state(specs[k], counts[k], 0) for k in range(3)]
-    acts = [W.actuation(specs[k], counts[k], steps, 0).astype(np.float32) for k in range(3)]
+    acts = [W.actuation(specs[k], counts[k], n_act, 0).astype(np.float32) for k in range(3)]
     roots, dofs, act_cols = [], [], []
     seen = [0, 0, 0]
     for e in range(n_envs):
@@ -303,32 +347,43 @@ def run_hetero(params, n_envs, steps, fp64):
     d0 = torch.tensor(np.concatenate(dofs), dtype=torch.float32, device=dev)
     a = torch.tensor(np.concatenate(act_cols, axis=1), dtype=torch.float32, device=dev)
     out = {"workload": f"{n_envs} envs: ant-like, humanoid-like and arm+gripper+box (capsule-box and box-plane "
-                       f"contacts) in equal thirds, interleaved", "envs": n_envs, "steps": steps,
+                       f"contacts) in equal thirds, interleaved; {steps} steps timed after an untimed "
+                       f"{preroll_steps}-step pre-roll", "envs": n_envs, "steps": steps,
            "dtype": "f64" if fp64 else "f32"}
     stream = torch.cuda.current_stream()
-    for name, per in (("per_type", False), ("persistent", True)):
-        sim = ags.Sim(models, env_model, params, device=dev, fp64=fp64, persistent=per)
-        sim.root_state.copy_(r0)
-        sim.dof_state.copy_(d0)
-        for t in range(min(10, steps)):
-            sim.bind(ags.DOF_ACTUATION, a[t])
-            sim.step()
-        sim.root_state.copy_(r0)
-        sim.dof_state.copy_(d0)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for t in range(steps):
-            sim.bind(ags.DOF_ACTUATION, a[t])
-            sim.step()
-        e1.record(stream)
-        torch.cuda.synchronize()
+    pre = ags.Sim(models, env_model, params, device=dev, fp64=fp64)
+    pre.root_state.copy_(r0)
+    pre.dof_state.copy_(d0)
+    for t in range(preroll_steps):
+        pre.bind(ags.DOF_ACTUATION, a[t])
+        pre.step()
+    torch.cuda.synchronize()
+    rp, dp = pre.root_state.clone(), pre.dof_state.clone()
+    del pre
+
+    def timed(**mapping):
+        sim = ags.Sim(models, env_model, params, device=dev, fp64=fp64, **mapping)
+        for rep in range(2):  # the first pass warms up
+            sim.root_state.copy_(rp)
+            sim.dof_state.copy_(dp)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for t in range(steps):
+                sim.bind(ags.DOF_ACTUATION, a[preroll_steps + t])
+                sim.step()
+            e1.record(stream)
+            torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        out[name] = {"ms_per_step": ms, "env_steps_per_s": n_envs / (ms / 1e3),
-                     "finite": bool(torch.isfinite(sim.root_state).all())}
-        del sim
-    lanes, per, ms = ags.autotune(models, env_model, params, r0, d0, a[0].contiguous(), fp64=fp64, n_steps=10)
-    out["autotuned"] = {"lanes_per_env": lanes, "persistent": per, "ms_per_step": ms}
+        return {"ms_per_step": ms, "env_steps_per_s": n_envs / (ms / 1e3),
+                "finite": bool(torch.isfinite(sim.root_state).all())}
+
+    out["per_type"] = timed(persistent=False)
+    out["persistent"] = timed(persistent=True)
+    lanes, per, ms = ags.autotune(models, env_model, params, rp, dp, a[preroll_steps].contiguous(), fp64=fp64,
+                                  n_steps=10)
+    out["autotuned"] = {"lanes_per_env": lanes, "persistent": per, "autotuner_ms_per_step": ms,
+                        **timed(persistent=per, lanes_per_env=lanes)}
     return out
 
 
@@ -383,22 +438,51 @@ def run_hand_fwd_bwd(n_envs, steps, fp64, every):
     return out
 
 
-def cpu_baseline(env, params, n_envs, n_steps):
-    """The FP64 oracle on the host cores over a bounded sample of the same workload."""
+def cpu_baseline(env, params, root, dof, acts, n_envs, n_steps, n_envs_1, n_steps_1):
+    """The FP64 oracle on the host over a bounded sample of the timed window: the GPU's state at the window's
+    start (envs [0, n_envs)) stepped n_steps times with the window's actions, on every thread of the host's
+    CPU share, and a smaller sample on one thread."""
     from oracle import oracle as O
-    from paper_2108_10470_amd import workloads as W
-    threads = max(1, min(16, os.cpu_count() or 1))
     oe = O.OracleEnv(env)
-    root, dof = W.initial_state(env, n_envs, 0)
-    acts = W.actuation(env, n_envs, n_steps, 0)
-    t0 = time.perf_counter()
-    for t in range(n_steps):
-        o = oe.step(params, root, dof, acts[t], n_threads=threads)
-        root, dof = o["root"], o["dof"]
-    dt = time.perf_counter() - t0
-    return {"value": n_envs * n_steps / dt, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_envs} humanoid envs x {n_steps} env-steps from the seeded standing start "
-                      f"(standing, falling, lying), FP64, {dt:.1f} s"}
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    threads = max(1, min(16, avail))  # the GPU box's CPU share is 16 cores, whatever the machine shows
+
+    def timed(n, k, nt):
+        r, d = root[:n].copy(), dof[:n].copy()
+        t0 = time.perf_counter()
+        for t in range(k):
+            o = oe.step(params, r, d, acts[t][:n], n_threads=nt)
+            r, d = o["root"], o["dof"]
+        return n * k / (time.perf_counter() - t0), time.perf_counter() - t0
+
+    v, dt = timed(n_envs, n_steps, threads)
+    v1, dt1 = timed(n_envs_1, n_steps_1, 1)
+    return {"value": v, "unit": "env-steps/s", "cores": threads, "kind": "oracle",
+            "value_1core": v1, "host_cpus_visible": avail,
+            "sample": f"the GPU's FP32 state at the timed window's start, {n_envs} humanoid envs x {n_steps} env-steps "
+                      f"with the window's actions on {threads} threads ({dt:.1f} s); one thread: {n_envs_1} envs x "
+                      f"{n_steps_1} steps ({dt1:.1f} s); FP64"}
+
+
+def run_ant_grad(fp64, reps):
+    """Differentiation workload: 4096 ant-like envs from the seeded start, 64-step rollout with a checkpoint
+    every 16 steps, loss = sum over envs of the final torso x position, gradient w.r.t. all 64 x 8 actions
+    per env (FP32 adjoint)."""
+    import torch
+    from paper_2108_10470_amd import workloads as W
+    env = W.env_ant()
+    params = W.SimParams()
+    E, T, every = 4096, 64, 16
+    root, dof = W.initial_state(env, E, 0)
+    r0 = torch.tensor(root.reshape(-1, 13), dtype=torch.float32, device="cuda:0")
+    d0 = torch.tensor(dof.reshape(-1, 2), dtype=torch.float32, device="cuda:0")
+    acts = torch.tensor(W.actuation(env, E, T, 0).astype(np.float32).reshape(T, -1), device="cuda:0")
+    out = run_fwd_bwd(env, params, E, fp64, acts, r0, d0, every, reps, adjoint_precision=32)
+    out["workload"] = "ant-like, 4096 envs, 64-step rollout from the seeded start, checkpoints every 16"
+    return out
 
 
 def main():
@@ -411,15 +495,15 @@ def main():
     from paper_2108_10470_amd import workloads as W
     env = W.env_humanoid()
     params = W.SimParams()
-    E, K, Wm = args.envs, args.steps, args.warmup
+    E, K, Wm, P = args.envs, args.steps, args.warmup, args.preroll
     root, dof = W.initial_state(env, E, 0)
-    n_act = max(Wm + K, args.fwd_bwd_steps)
+    n_act = P + max(Wm + K, args.fwd_bwd_steps, args.rows_ref_steps - P)
     acts = W.actuation(env, E, n_act, 0).astype(np.float32)
     actions_dev = torch.from_numpy(acts).to("cuda:0").reshape(n_act, -1)
     actions_dev = [actions_dev[t] for t in range(n_act)]
-    root0 = torch.from_numpy(root.reshape(-1, 13).astype(np.float32)).to("cuda:0")
-    dof0 = torch.from_numpy(dof.reshape(-1, 2).astype(np.float32)).to("cuda:0")
-    print(f"[bench] humanoid envs={E} steps={K} warmup={Wm}", file=sys.stderr, flush=True)
+    root_stand = torch.from_numpy(root.reshape(-1, 13).astype(np.float32)).to("cuda:0")
+    dof_stand = torch.from_numpy(dof.reshape(-1, 2).astype(np.float32)).to("cuda:0")
+    print(f"[bench] humanoid envs={E} preroll={P} warmup={Wm} steps={K}", file=sys.stderr, flush=True)
     if args.calib_copy_mb:
         n = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda:0")
@@ -428,21 +512,30 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    root0, dof0 = preroll(env, params, E, P, actions_dev, root_stand, dof_stand)
+    win_actions = actions_dev[P:]
 
     variants = {"both": [True, False], "fp64": [True], "fp32": [False]}[args.precision]
     res = {}
     for fp64 in variants:
         name = "fp64" if fp64 else "fp32"
-        r = run_gpu(env, params, E, K, Wm, fp64, actions_dev, root0, dof0)
-        r["rows"] = None if args.no_rows else mean_rows(env, params, E, Wm + K, fp64, actions_dev, root0, dof0)
+        r = run_gpu(env, params, E, K, Wm, fp64, win_actions, root0, dof0)
+        r["rows"] = None if args.no_rows else mean_rows(env, params, E, Wm + K, fp64, win_actions, root0, dof0,
+                                                         skip=Wm)
         res[name] = r
         print(f"[bench] {name}: {K} steps in {r['total_ms']:.1f} ms, launch mean {r['launch_ms'].mean():.3f} ms, "
-              f"rows/substep {r['rows']}, finite {r['finite']}", file=sys.stderr, flush=True)
+              f"rows/substep {r['rows']}, graph {r['graph_ms']} vs eager {r['eager_same_steps_ms']} ms/step, "
+              f"finite {r['finite']}", file=sys.stderr, flush=True)
+    rows_ref = None
+    if not args.no_rows and args.rows_ref_steps > 0:
+        rows_ref = mean_rows(env, params, E, args.rows_ref_steps, False, actions_dev, root_stand, dof_stand)
+        print(f"[bench] rows/substep over steps 0-{args.rows_ref_steps} from the standing start: {rows_ref}",
+              file=sys.stderr, flush=True)
 
     head = "fp64" if "fp64" in res else "fp32"
     hetero = None
     if not args.no_hetero:
-        hetero = run_hetero(params, args.hetero_envs, args.hetero_steps, head == "fp64")
+        hetero = run_hetero(params, args.hetero_envs, args.hetero_steps, head == "fp64", args.hetero_preroll)
         print(f"[bench] heterogeneous batch: {json.dumps(hetero)}", file=sys.stderr, flush=True)
     hand = None
     if not args.no_hand:
@@ -454,15 +547,14 @@ def main():
     tgs = None
     if not args.no_tgs:  # the temporal Gauss-Seidel variant of the solver, same workload and precision
         import dataclasses
-        r = run_gpu(env, dataclasses.replace(params, solver=1), E, K, Wm, head == "fp64", actions_dev, root0, dof0)
+        r = run_gpu(env, dataclasses.replace(params, solver=1), E, K, Wm, head == "fp64", win_actions, root0, dof0)
         tgs = {"env_steps_per_s": E * K / (r["total_ms"] / 1e3), "ms_per_step": r["total_ms"] / K,
                "launch_ms": float(r["launch_ms"].mean()), "finite": r["finite"], "dtype": head.replace("fp", "f")}
         print(f"[bench] tgs: {json.dumps(tgs)}", file=sys.stderr, flush=True)
     randomized = None
     if not args.no_tgs:  # every property tensor bound (masses, gains, limits, friction, gravity per env)
-        from paper_2108_10470_amd import workloads as W_
-        r = run_gpu(env, params, E, K, Wm, head == "fp64", actions_dev, root0, dof0,
-                    props=W_.random_properties(env, params, E, seed=0))
+        r = run_gpu(env, params, E, K, Wm, head == "fp64", win_actions, root0, dof0,
+                    props=W.random_properties(env, params, E, seed=0))
         randomized = {"env_steps_per_s": E * K / (r["total_ms"] / 1e3), "ms_per_step": r["total_ms"] / K,
                       "launch_ms": float(r["launch_ms"].mean()), "finite": r["finite"],
                       "dtype": head.replace("fp", "f")}
@@ -472,7 +564,7 @@ def main():
     fwd_bwd = None
     if not args.no_fwd_bwd:
         T = args.fwd_bwd_steps
-        acts_fb = torch.stack(actions_dev[:T]).contiguous()
+        acts_fb = torch.stack(win_actions[:T]).contiguous()
         fwd_bwd = run_fwd_bwd(env, params, E, head == "fp64", acts_fb, root0, dof0, args.fwd_bwd_every,
                               args.fwd_bwd_reps, adjoint_precision=32)
         print(f"[bench] fwd+bwd ({head} forward, f32 adjoint): {json.dumps(fwd_bwd)}", file=sys.stderr, flush=True)
@@ -486,6 +578,11 @@ def main():
             print(f"[bench] fwd+bwd ({head} forward, f32 adjoint, checkpoints every {args.fwd_bwd_ckpt_every}): "
                   f"{json.dumps(fbc)}", file=sys.stderr, flush=True)
             fwd_bwd["checkpointed"] = {k: fbc[k] for k in ("value", "checkpoint_every", "ms_forward", "ms_backward")}
+        fwd_bwd["start"] = f"the state of the pre-roll ({P} steps from standing)"
+        if not args.no_ant_grad:
+            fwd_bwd["ant_differentiation"] = run_ant_grad(head == "fp64", args.fwd_bwd_reps)
+            print(f"[bench] ant differentiation: {json.dumps(fwd_bwd['ant_differentiation'])}", file=sys.stderr,
+                  flush=True)
     h = res[head]
     value = E * K / (h["total_ms"] / 1e3)
     t_launch = float(h["launch_ms"].mean()) / 1e3
@@ -497,9 +594,11 @@ def main():
         "ms_per_step": h["total_ms"] / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if head == "fp64" else "f32", "data": "synthetic",
         "config": {"workload": "humanoid-like, 4096 envs (13 capsules, free root + 21 revolute DOFs), "
-                               "dt 1/60 s x 2 substeps, 8 PGS sweeps, actions U[-1,1] x 67.5",
-                   "envs": E, "substeps": params.substeps, "pgs_iters": params.pgs_iters,
-                   "tensors": "f32", "compute": head, "mean_rows_per_substep": rows},
+                               "dt 1/60 s x 2 substeps, 8 PGS sweeps, actions U[-1,1] x 67.5; window after an "
+                               f"untimed {P}-step pre-roll from the standing start (humanoids on the ground)",
+                   "envs": E, "substeps": params.substeps, "pgs_iters": params.pgs_iters, "preroll_steps": P,
+                   "tensors": "f32", "compute": head, "mean_rows_per_substep": rows,
+                   "mean_rows_per_substep_steps_0_to_%d" % args.rows_ref_steps: rows_ref},
         "roofline": {"bound": "alu", "achieved": ach_tf, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": None if ach_tf is None else ach_tf / PEAK_VALU_TFLOPS, "traffic": measured_traffic(head),
                      "kernel": "step_kernel<double>" if head == "fp64" else "step_kernel<float>",
@@ -515,11 +614,16 @@ def main():
         "randomized_properties": randomized,
         "variants": {k: {"env_steps_per_s": E * K / (v["total_ms"] / 1e3), "ms_per_step": v["total_ms"] / K,
                          "launch_ms": float(v["launch_ms"].mean()), "mean_rows_per_substep": v["rows"],
-                         "graph_ms_per_step": v["graph_ms"],
-                         "finite": v["finite"]} for k, v in res.items()},
+                         "graph_ms_per_step": v["graph_ms"], "eager_ms_per_step_same_steps": v["eager_same_steps_ms"],
+                         "graph_steps": v["graph_chunk"], "finite": v["finite"]} for k, v in res.items()},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W.env_humanoid(), params, args.cpu_envs, args.cpu_steps)
+        wr = h["window_root"].double().cpu().numpy().reshape(E, env.n_actors, 13)
+        wd = h["window_dof"].double().cpu().numpy().reshape(E, env.n_dof, 2)
+        wa = acts[P + Wm:P + Wm + args.cpu_steps].astype(np.float64)
+        out["cpu_baseline"] = cpu_baseline(W.as_f32(env), W.params_f32(params), wr, wd, wa,
+                                           min(args.cpu_envs, E), min(args.cpu_steps, len(wa)),
+                                           min(args.cpu_envs_1core, E), min(args.cpu_steps_1core, len(wa)))
     print(json.dumps(out), flush=True)
 
 
