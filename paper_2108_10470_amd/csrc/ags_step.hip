@@ -690,7 +690,7 @@ __device__ __forceinline__ void jrow_point(const Tab<R>& M, const Ctx<R, EPW>& s
 // stage: copy T's model tables into LDS (false when the previous group of this workgroup had the same type).
 // TGS: the temporal Gauss-Seidel variant (a separate instantiation, so that the default solver's registers
 // are not shared with the variant's extra per-row state).
-template <typename R, int TEAM, bool TGS>
+template <typename R, int TEAM, bool TGS, bool CYC>
 __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T, int group, bool stage) {
   R* smem = reinterpret_cast<R*>(g_lds);
   const Lds& L = T.lds;
@@ -735,12 +735,13 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   int rows_max = 0;       // most rows of a substep
   __syncthreads();
   const V3<R> origin = ld3<R>(s.root);
-  // optional per-phase clock accounting (lane 0; only when the debug tensor is bound)
+  // optional per-phase clock accounting (lane 0), compiled only into the instantiation launched when the
+  // debug tensor is bound: the counters would otherwise hold registers through the whole kernel
   long long cyc[kPhases] = {0};
   int cur_phase = -1;
   long long t_mark = 0;
 #define PHASE_MARK(ph)                                              \
-  if (P.dbg_cycles) {                                               \
+  if (CYC) {                                                        \
     const long long now = (long long)clock64();                     \
     if (cur_phase >= 0) cyc[cur_phase] += now - t_mark;             \
     cur_phase = (ph);                                               \
@@ -1528,7 +1529,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     P.dof_state[2ll * (dbase + j) + 1] = float(s.qd[M.li[lk * LI_COLS + LI_COL]]);
     if (P.dof_force) P.dof_force[dbase + j] = float(dof_force_acc / R(P.substeps));
   }
-  if (P.dbg_cycles && tt == 0)
+  if (CYC && P.dbg_cycles && tt == 0)
     for (int k = 0; k < kPhases; ++k) P.dbg_cycles[(long long)env * kPhases + k] = cyc[k];
 #undef PHASE_MARK
   if (P.contact_force) {
@@ -1542,9 +1543,9 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 template <typename R, int TEAM>
 constexpr int kWavesPerEU = (sizeof(R) == 4 || TEAM == 64) ? 2 : 1;
 
-template <typename R, int TEAM, bool TGS>
+template <typename R, int TEAM, bool TGS, bool CYC = false>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<R, TEAM>))) void step_kernel(StepArgs P) {
-  step_group<R, TEAM, TGS>(P, P.ty, blockIdx.x, true);
+  step_group<R, TEAM, TGS, CYC>(P, P.ty, blockIdx.x, true);
 }
 
 // persistent form: each workgroup walks the work list with a grid stride; the list is ordered by
@@ -1555,7 +1556,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<
   for (int u = blockIdx.x; u < A.n_units; u += gridDim.x) {
     const int ty = A.units[2 * u], grp = A.units[2 * u + 1];
     __syncthreads();
-    step_group<R, TEAM, TGS>(A.base, A.types[ty], grp, ty != prev);
+    step_group<R, TEAM, TGS, false>(A.base, A.types[ty], grp, ty != prev);
     prev = ty;
   }
 }
@@ -1586,8 +1587,14 @@ static hipError_t launch_one(const StepArgs& a, int n_envs, hipStream_t stream) 
   constexpr int EPW = kTeam / TEAM;
   const size_t lds = (size_t)a.ty.lds.total * sizeof(R);
   const int grid = (n_envs + EPW - 1) / EPW;
-  if (a.solver == 1) hipLaunchKernelGGL((step_kernel<R, TEAM, true>), dim3(grid), dim3(kTeam), lds, stream, a);
-  else hipLaunchKernelGGL((step_kernel<R, TEAM, false>), dim3(grid), dim3(kTeam), lds, stream, a);
+  if (a.dbg_cycles) {  // the instrumented instantiation (per-phase clock counters)
+    if (a.solver == 1) hipLaunchKernelGGL((step_kernel<R, TEAM, true, true>), dim3(grid), dim3(kTeam), lds, stream, a);
+    else hipLaunchKernelGGL((step_kernel<R, TEAM, false, true>), dim3(grid), dim3(kTeam), lds, stream, a);
+  } else if (a.solver == 1) {
+    hipLaunchKernelGGL((step_kernel<R, TEAM, true>), dim3(grid), dim3(kTeam), lds, stream, a);
+  } else {
+    hipLaunchKernelGGL((step_kernel<R, TEAM, false>), dim3(grid), dim3(kTeam), lds, stream, a);
+  }
   return hipGetLastError();
 }
 
@@ -1600,10 +1607,10 @@ static const void* fused_kernel(int fp64, int team) {
   return fp64 ? (team == 32 ? fused_fn<double, 32, TGS>() : fused_fn<double, 64, TGS>())
               : (team == 32 ? fused_fn<float, 32, TGS>() : fused_fn<float, 64, TGS>());
 }
-template <bool TGS>
+template <bool TGS, bool CYC = false>
 static const void* step_fn(int fp64, int team) {
-  return fp64 ? (team == 32 ? (const void*)step_kernel<double, 32, TGS> : (const void*)step_kernel<double, 64, TGS>)
-              : (team == 32 ? (const void*)step_kernel<float, 32, TGS> : (const void*)step_kernel<float, 64, TGS>);
+  return fp64 ? (team == 32 ? (const void*)step_kernel<double, 32, TGS, CYC> : (const void*)step_kernel<double, 64, TGS, CYC>)
+              : (team == 32 ? (const void*)step_kernel<float, 32, TGS, CYC> : (const void*)step_kernel<float, 64, TGS, CYC>);
 }
 
 hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStream_t stream) {
@@ -1649,6 +1656,10 @@ hipError_t fused_blocks_per_cu(int fp64, int team, size_t lds_bytes, int* blocks
 hipError_t set_lds_limit(int fp64, int team, size_t bytes) {
   hipError_t e = hipFuncSetAttribute(step_fn<false>(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e == hipSuccess) e = hipFuncSetAttribute(step_fn<true>(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(step_fn<false, true>(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(step_fn<true, true>(fp64, team), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   return e;
 }
 

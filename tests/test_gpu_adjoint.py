@@ -395,3 +395,52 @@ def test_rollout_status_keeps_env_over_row_cap_at_any_step(every):
                                                                    "over_cap_only_after_step0": int(late_only.sum())})
     assert late_only.any()
     assert np.array_equal(got, want), (np.nonzero(got)[0].tolist(), np.nonzero(want)[0].tolist())
+
+
+@pytest.mark.parametrize("adj", [64, 32], ids=["adj64", "adj32"])
+def test_rollout_gradient_ant_4096_envs_64_steps(adj):
+    """The differentiation workload as stated: 4096 ant-like envs from the seeded start, a 64-step rollout
+    with a checkpoint every 16 steps, loss = sum over envs of the final torso x, gradient w.r.t. every one
+    of the 64 x 8 actions per env.  Envs 0-15 are checked against central differences (H = 1e-6) of FP64
+    oracle rollouts, with the allowances and the on-path rule of the 16-step ant test; the FP64 forward
+    keeps its state in FP32 between steps, so over 64 steps some envs leave the oracle's path (reported)."""
+    E, T, every, n_fd = 4096, 64, 16, 16
+    env, params = W.as_f32(W.env_ant()), W.params_f32(W.SimParams())
+    oe = A.O.OracleEnv(env)
+    root, dof = W.initial_state(env, E, 0)
+    r32 = lambda x: x.astype(np.float32).astype(np.float64)
+    root, dof = r32(root), r32(dof)
+    acts = r32(W.actuation(env, E, T, 0))
+    g, _ = A.gpu_rollout_grad(env, params, root, dof, acts, every, True, adjoint_precision=adj)
+    assert np.isfinite(g).all()
+    sl = slice(0, n_fd)
+    fd, modes = A.fd_rollout(oe, params, root[sl], dof[sl], acts[:, sl])
+    fd10, _ = A.fd_rollout(oe, params, root[sl], dof[sl], acts[:, sl], h=10 * A.H)
+    rng = np.random.default_rng(5)
+    ulp = lambda x: x * (1.0 + rng.choice([-1.0, 1.0], size=x.shape) * 2.0 ** -23)
+    fdp, _ = A.fd_rollout(oe, params, ulp(root[sl]), ulp(dof[sl]), acts[:, sl])
+    roots, dofs = A.gpu_trajectory(env, params, root[sl], dof[sl], acts[:, sl], True)
+    on_path = np.ones(n_fd, dtype=bool)
+    for t in range(T):
+        o = oe.step(params, roots[t], dofs[t], acts[t, sl])
+        on_path &= o["mode"] == modes[:, t]
+        st_g = np.concatenate([roots[t + 1].reshape(n_fd, -1), dofs[t + 1].reshape(n_fd, -1)], axis=1)
+        st_o = np.concatenate([o["root"].reshape(n_fd, -1), o["dof"].reshape(n_fd, -1)], axis=1)
+        on_path &= (np.abs(st_g - st_o) <= 1e-5 + 1e-4 * np.abs(st_o)).all(axis=1)
+    gf, fdf = g[sl].reshape(n_fd, -1), fd.reshape(n_fd, -1)
+    unc = (np.abs(fd - fd10) + np.abs(fd - fdp)).reshape(n_fd, -1)
+    ok = ~np.isnan(fdf) & ~np.isnan(unc) & on_path[:, None]
+    scale = np.nanmax(np.abs(fdf), axis=1, keepdims=True)
+    base = A.RTOL * np.abs(fdf) + FLOOR[adj == 64] * scale
+    ratio = np.where(ok, np.abs(gf - fdf) / (base + unc + 1e-30), 0.0)
+    strict = np.where(ok, np.abs(gf - fdf) / (base + 1e-30), 0.0)
+    norm_rel = [float(np.linalg.norm((gf - fdf)[e][ok[e]]) / (np.linalg.norm(fdf[e][ok[e]]) + 1e-30))
+                for e in range(n_fd) if ok[e].any()]
+    d = {"envs": E, "steps": T, "every": every, "fd_envs": n_fd, "envs_on_oracle_path": int(on_path.sum()),
+         "entries_checked": int(ok.sum()), "excluded_switch_fraction": float(np.isnan(fdf).mean()),
+         "worst_ratio": float(ratio.max()), "worst_ratio_without_allowances": float(strict.max()),
+         "worst_normwise_rel_err_on_path": max(norm_rel) if norm_rel else None,
+         "grad_abs_max_all_envs": float(np.abs(g).max()), "grad_abs_median_all_envs": float(np.median(np.abs(g))),
+         "fd_abs_max": float(np.nanmax(np.abs(fdf)))}
+    _report(f"rollout_ant4096_T64_adj{adj}", d)
+    assert (ratio <= 1.0).all(), d
