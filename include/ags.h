@@ -294,6 +294,20 @@ int ags_rollout_backward(ags_sim* sim, int32_t n_steps, int32_t every, int32_t c
                          const float* ckpt, void* seg, float* root_adj, float* dof_adj, float* act_adj,
                          int32_t* status, void* hip_stream);
 
+/* ags_rollout_backward without the workspace argument, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight training or serving loops, harnesses that forbid allocation): the
+ * two segment buffers live in a static device array of the library (64 MiB, one copy per GPU, held until
+ * the process ends; its address on a device is taken when a sim is created there, as are the rollout's
+ * streams, so this call creates, allocates and frees nothing).  Same arguments, results and status as
+ * ags_rollout_backward, bit for bit.  Errors: AGS_E_ARG as there, and when 2 x one segment buffer (see
+ * ags_rollout_seg_bytes) exceeds 64 MiB (4096 humanoid-like envs: checkpoint intervals up to 12; 4096
+ * ant-like envs: up to 22).  Every call on one GPU uses the same array, which keeps the last call's
+ * contents (each call writes every word before reading it, so nothing needs clearing): calls that overlap
+ * on one GPU (two streams, two sims, two threads) race and must be serialised by the caller. */
+int ags_rollout_backward_noalloc(ags_sim* sim, int32_t n_steps, int32_t every, int32_t control, const float* actions,
+                                 const float* ckpt, float* root_adj, float* dof_adj, float* act_adj, int32_t* status,
+                                 void* hip_stream);
+
 /* Rollouts with a stored tape: the forward pass keeps everything the reverse pass needs, which then
  * recomputes nothing (the store-everything end of the checkpointing trade-off, for when memory allows:
  * about 660 B per humanoid env-step at two substeps).  The tape (device, caller-owned,

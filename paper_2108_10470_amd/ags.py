@@ -103,6 +103,7 @@ def lib():
                                    vp, vp, vp, i32, ctypes.POINTER(ctypes.c_float), vp]
         L.ags_rollout_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp]
         L.ags_rollout_backward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ags_rollout_backward_noalloc.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.ags_rollout_tape_bytes.argtypes = [vp, i32, i64p]
         L.ags_sim_jacobian_mass.argtypes = [vp, i32, vp, vp, vp]
         L.ags_rollout_forward_tape.argtypes = [vp, i32, i32, vp, vp, vp]
@@ -116,7 +117,7 @@ EXPORTED = ["ags_last_error", "ags_model_create", "ags_model_destroy", "ags_mode
             "ags_sim_set_root_state_indexed", "ags_sim_set_dof_state_indexed", "ags_sim_step_backward",
             "ags_rollout_state_size", "ags_rollout_forward", "ags_rollout_backward", "ags_autotune",
             "ags_rollout_seg_bytes", "ags_rollout_tape_bytes", "ags_rollout_forward_tape", "ags_rollout_backward_tape",
-            "ags_sim_jacobian_mass", "ags_model_add_tendons"]
+            "ags_sim_jacobian_mass", "ags_model_add_tendons", "ags_rollout_backward_noalloc"]
 
 
 def _check(rc: int, what: str):

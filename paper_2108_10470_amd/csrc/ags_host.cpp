@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -564,6 +565,33 @@ Lds make_layout(const ags_model_info& info, int n_levels, int n_anc, int team, s
 }
 }  // namespace
 
+// Scratch of ags_rollout_backward_noalloc: its two segment buffers live in this array instead of a
+// caller-owned workspace.  Every device the library runs on holds its own copy until the process ends.  In
+// host code `scratch` only names the symbol; the device address of the current device's copy comes from
+// hipGetSymbolAddress, taken once per device when a sim is created there (noalloc_scratch_ptr).
+constexpr long long kNoAllocScratchBytes = 64ll << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// this device's copy of `scratch` (looked up on the first call on each device)
+hipError_t noalloc_scratch_ptr(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 struct ags_sim {
   ags_sim_params params{};
   int n_envs = 0;
@@ -589,6 +617,8 @@ struct ags_sim {
   // set while a rollout reverses its steps: the adjoint writes only failures into the status array, which the
   // rollout cleared first, so an env over the row capacity at any step stays flagged
   int adj_sticky = 0;
+  // device address of this device's copy of the no-allocation rollout scratch (see noalloc_scratch_ptr)
+  void* noalloc_scratch = nullptr;
   hipStream_t aux2 = nullptr;
   hipEvent_t ev_big_start = nullptr, ev_big_done = nullptr;
   // persistent (fused) launch
@@ -597,6 +627,10 @@ struct ags_sim {
   int n_units = 0, fused_grid = 0, fused_team = 64;
   size_t fused_lds = 0;
 };
+
+namespace {
+hipError_t ensure_streams(ags_sim* S);
+}
 
 extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, const int32_t* env_model,
                               int32_t n_envs, const ags_sim_params* p, ags_sim** out) {
@@ -797,6 +831,12 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     return hip_fail(err, "sim: adjoint lists");
   }
   S->n_cu = std::max(1, n_cu);
+  // the rollout streams and this device's no-allocation scratch are set up here, so that no rollout call
+  // creates or looks up anything
+  if ((err = ensure_streams(S)) != hipSuccess || (err = noalloc_scratch_ptr(dev_cu, &S->noalloc_scratch)) != hipSuccess) {
+    ags_sim_destroy(S);
+    return hip_fail(err, "sim: rollout streams / scratch");
+  }
   if (p->persistent && !S->types.empty() && (int)S->types.size() <= kMaxFusedTypes) {
     // work list: (type, group) units, types ordered by estimated cost per group (heaviest first)
     std::vector<int> order(S->types.size());
@@ -1223,12 +1263,43 @@ extern "C" int ags_rollout_forward(ags_sim* S, int32_t n_steps, int32_t every, i
   return AGS_OK;
 }
 
+namespace {
+int rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, int32_t control, const float* actions,
+                     const float* ckpt, void* seg_bytes, float* root_adj, float* dof_adj, float* act_adj,
+                     int32_t* status, void* stream);
+}
+
 extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, int32_t control, const float* actions,
                                     const float* ckpt, void* seg_bytes, float* root_adj, float* dof_adj, float* act_adj,
                                     int32_t* status, void* stream) {
   if (!S || n_steps < 1 || every < 1 || !actions || !ckpt || !seg_bytes || !root_adj || !dof_adj || !act_adj ||
       (control != AGS_DOF_ACTUATION && control != AGS_DOF_POS_TARGET))
     return fail(AGS_E_ARG, "rollout_backward: bad arguments");
+  return rollout_backward(S, n_steps, every, control, actions, ckpt, seg_bytes, root_adj, dof_adj, act_adj, status,
+                          stream);
+}
+
+extern "C" int ags_rollout_backward_noalloc(ags_sim* S, int32_t n_steps, int32_t every, int32_t control,
+                                            const float* actions, const float* ckpt, float* root_adj, float* dof_adj,
+                                            float* act_adj, int32_t* status, void* stream) {
+  if (!S || n_steps < 1 || every < 1 || !actions || !ckpt || !root_adj || !dof_adj || !act_adj ||
+      (control != AGS_DOF_ACTUATION && control != AGS_DOF_POS_TARGET))
+    return fail(AGS_E_ARG, "rollout_backward_noalloc: bad arguments");
+  if (!S->noalloc_scratch) return fail(AGS_E_ARG, "rollout_backward_noalloc: no scratch on this sim's device");
+  const long long need = 2 * seg_one_bytes(S, every);
+  if (need > kNoAllocScratchBytes)
+    return fail(AGS_E_ARG, "rollout_backward_noalloc: two segment buffers of this sim and checkpoint interval need " +
+                               std::to_string(need) + " bytes, more than the " + std::to_string(kNoAllocScratchBytes) +
+                               " bytes of the static scratch; use a smaller interval or ags_rollout_backward");
+  return rollout_backward(S, n_steps, every, control, actions, ckpt, S->noalloc_scratch, root_adj, dof_adj, act_adj,
+                          status, stream);
+}
+
+namespace {
+// the reverse pass of a checkpointed rollout with its two segment buffers at seg_bytes (arguments checked)
+int rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, int32_t control, const float* actions,
+                     const float* ckpt, void* seg_bytes, float* root_adj, float* dof_adj, float* act_adj,
+                     int32_t* status, void* stream) {
   if (!S->bound[AGS_DOF_ACTUATION]) return fail(AGS_E_UNBOUND, "rollout_backward: the actuation tensor must be bound");
   if (const char* why = adjoint_unsupported(S)) return fail(AGS_E_ARG, why);
   const size_t nr = 13ull * S->n_actors_total, nd = 2ull * S->n_dof_total, sw = nr + nd;
@@ -1286,6 +1357,7 @@ extern "C" int ags_rollout_backward(ags_sim* S, int32_t n_steps, int32_t every, 
   }
   return AGS_OK;
 }
+}  // namespace
 
 // ---------------------------------------------------------------- rollouts with a stored tape
 extern "C" int ags_rollout_tape_bytes(const ags_sim* S, int32_t n_steps, int64_t* bytes) {
