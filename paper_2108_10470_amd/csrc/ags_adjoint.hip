@@ -351,6 +351,9 @@ __device__ __forceinline__ void wave_gemm(int M, int N, int K, int lane, const F
 }
 
 // ---------------------------------------------------------------- per-environment context
+// per-phase clock counters of the debug accounting, then the current phase and the last mark (lane 0)
+__shared__ long long g_adj_clock[kAdjPhases + 2];
+
 template <typename R>
 struct Env {
   const AdjArgs* P;
@@ -362,17 +365,17 @@ struct Env {
   R h;
   V3<R> g, ref;
   int R_;    // rows of the current substep
-  long long cyc[kAdjPhases];  // shader-clock cycles per phase (lane 0 keeps them; only when requested)
-  int cur;
-  long long mark;
+  // per-phase shader-clock accounting, only when the debug tensor is bound: the counters, the current phase
+  // and the last mark live in LDS (g_adj_clock), so that no register is held for them through the kernel
   __device__ __forceinline__ void phase(int ph) {
     if (!P->cycles) return;
-    const long long now = (long long)clock64();
-#pragma unroll
-    for (int k = 0; k < kAdjPhases; ++k)  // selects, not an indexed store: the counters stay in registers
-      if (cur == k) cyc[k] += now - mark;
-    cur = ph;
-    mark = now;
+    if (lane == 0) {
+      const long long now = (long long)clock64();
+      const int cur = (int)g_adj_clock[kAdjPhases];
+      if (cur >= 0) g_adj_clock[cur] += now - g_adj_clock[kAdjPhases + 1];
+      g_adj_clock[kAdjPhases] = ph;
+      g_adj_clock[kAdjPhases + 1] = now;
+    }
   }
   // table access
   __device__ const int* li(int i) const { return P->m.li + i * LI_COLS; }
@@ -1553,9 +1556,10 @@ __device__ __forceinline__ void adjoint_env(const AdjArgs& P, int ei) {
   E.dbase = P.env_dof_base[env];
   E.h = R(P.h);
   E.g = mk(R(P.gx), R(P.gy), R(P.gz));
-  for (int k = 0; k < kAdjPhases; ++k) E.cyc[k] = 0;
-  E.cur = -1;
-  E.mark = 0;
+  if (P.cycles && E.lane == 0) {
+    for (int k = 0; k < kAdjPhases; ++k) g_adj_clock[k] = 0;
+    g_adj_clock[kAdjPhases] = -1;
+  }
   const int lane = E.lane, na = E.na, nd = E.nd, sw = L.state_words, S = P.substeps;
   R* st = E.r + L.st;
   // step start state and the adjoint of the step's end state
@@ -1596,12 +1600,17 @@ __device__ __forceinline__ void adjoint_env(const AdjArgs& P, int ei) {
   if (P.status && lane == 0 && (!ok || !P.status_sticky)) P.status[env] = ok ? 0 : 1;
   E.phase(-1);
   if (P.cycles && lane == 0)
-    for (int k = 0; k < kAdjPhases; ++k) P.cycles[(long long)env * kAdjPhases + k] = E.cyc[k];
+    for (int k = 0; k < kAdjPhases; ++k) P.cycles[(long long)env * kAdjPhases + k] = g_adj_clock[k];
 }
+
+// Register budget: FP32 forms at two wavefronts per SIMD (<= 256 registers: LDS admits five workgroups per
+// CU with the small layout); FP64 forms at one (their LDS admits two workgroups per CU anyway)
+template <typename R>
+constexpr int kAdjWavesPerEU = sizeof(R) == 4 ? 2 : 1;
 
 // one env per workgroup
 template <typename R>
-__global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAdjWavesPerEU<R>))) void adjoint_kernel(AdjArgs P, int n_envs) {
   const int ei = blockIdx.x;
   if (ei >= n_envs || (P.list_count && ei >= *P.list_count)) return;
   adjoint_env<R>(P, ei);
@@ -1609,7 +1618,7 @@ __global__ __launch_bounds__(64) void adjoint_kernel(AdjArgs P, int n_envs) {
 // fewer workgroups than list entries, each striding over the device list (the flagged-env pass); kept apart
 // from adjoint_kernel because the loop costs registers (a few spilled in the FP32 form)
 template <typename R>
-__global__ __launch_bounds__(64) void adjoint_list_kernel(AdjArgs P, int n_envs) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAdjWavesPerEU<R>))) void adjoint_list_kernel(AdjArgs P, int n_envs) {
   for (int ei = blockIdx.x; ei < n_envs; ei += gridDim.x) {
     if (ei >= *P.list_count) return;
     adjoint_env<R>(P, ei);

@@ -476,55 +476,6 @@ struct TypeDev {
 
 int adj_fp64(const ags_sim_params& p) { return p.adjoint_precision == 64 || (p.adjoint_precision == 0 && p.compute_fp64); }
 
-// LDS layout of the adjoint kernel for one environment (one wavefront per environment)
-AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters, int row_cap) {
-  AdjLds L{};
-  int off = 0;
-  auto take = [&](int n) {
-    const int o = off;
-    off += std::max(n, 1);
-    return o;
-  };
-  const int nl = info.n_links, nv = std::max(1, info.n_v), nd = std::max(1, info.n_dof), na = info.n_actors;
-  const int rc = std::min(std::max(1, info.max_rows), row_cap);
-  L.rows_cap = rc;
-  L.Rm = take(9 * nl); L.p = take(3 * nl); L.ax = take(3 * nl); L.c = take(3 * nl); L.Iw = take(6 * nl);
-  L.Ic = take(10 * nl); L.V = take(6 * nl); L.Vs = take(6 * nl); L.X0 = take(6 * nl); L.X1 = take(6 * nl);
-  L.X2 = take(6 * nl); L.X3 = take(6 * nl); L.wr = take(6 * nl); L.sb = take(6 * nl); L.cb = take(3 * nl);
-  L.tI = take(3 * nl);
-  L.nu = take(nv); L.qdd = take(nv); L.vs = take(nv); L.nu1 = take(nv); L.tau = take(nv); L.arm = take(nv);
-  L.z = take(nv); L.w = take(nv); L.nub = take(nv); L.vsb = take(nv); L.nui = take(nv); L.tmp = take(nv);
-  L.cs = take(6 * nv);
-  L.q = take(nd); L.qb = take(nd); L.ab = take(nd);
-  L.state_words = 13 * na + 2 * info.n_dof;
-  L.st = take((substeps + 1) * L.state_words);
-  L.rbar = take(13 * na); L.dbar = take(2 * nd); L.nrb = take(13 * na);
-  L.nvp = nv | 1;
-  L.Lm = take(nv * L.nvp);
-  L.ldi = take(nv);
-  L.rcp = rc | 1;
-  // arrays with disjoint lifetimes in a reverse substep share words: W is dead once P is formed, when the
-  // mass-matrix terms' column vectors are written; A and S = Abar + Abar^T are dead after the reverse
-  // Gauss-Seidel and T = S W, when the rows' reverse arrays are written
-  L.J = take(rc * L.nvp);
-  L.W = take(std::max(rc * L.nvp, 18 * nv));
-  L.colS = L.W; L.colY = L.W + 6 * nv; L.colYv = L.W + 12 * nv;
-  const int ntri = rc * (rc + 1) / 2;
-  L.A = take(std::max(2 * ntri, 19 * rc)); L.Ab = L.A + ntri;
-  L.rxb = L.A; L.rdb = L.A + 3 * rc; L.rqb = L.A + 6 * rc; L.rwa = L.A + 7 * rc; L.rwb = L.A + 13 * rc;
-  L.rbc = take(rc); L.rb = take(rc); L.rinvA = take(rc); L.rlam = take(rc); L.rybar = take(rc); L.rbbar = take(rc);
-  L.rx = take(3 * rc); L.rcen = take(3 * rc); L.rd = take(3 * rc);
-  L.hlo = take(iters * L.rcp); L.hres = take(iters * L.rcp);
-  L.misc = take(8);
-  L.n_real = (off + 1) & ~1;
-  off = 0;
-  L.rkind = take(rc); L.rlink = take(rc); L.rdof = take(rc); L.rnrm = take(rc); L.rmap = take(rc);
-  L.rlinkb = take(rc); L.rslot = take(rc);
-  L.hst = take(iters * L.rcp); L.flags = take(64);
-  L.n_int = off;
-  return L;
-}
-
 Lds make_layout(const ags_model_info& info, int n_levels, int n_anc, int team, size_t elem) {
   Lds L{};
   int off = 0;
@@ -1080,9 +1031,12 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
       const hipStream_t st = (hipStream_t)stream;
       if (S->adj_big) {
         // environments the forward flagged run with the full layout on the third stream, concurrently with
-        // pass 1 (which skips them): a device list of them, strided over by one workgroup per CU (a launch
-        // of one workgroup per env would wait for LDS room for each of its mostly empty workgroups); the
-        // caller's stream waits for them before its next work
+        // pass 1 (which skips them): a device list of them, strided over by as many workgroups per CU as the
+        // CU's LDS holds beside one of pass 1 (at most two; a launch of one workgroup per env would wait for
+        // LDS room for each of its mostly empty workgroups); the caller's stream waits for them before its
+        // next work
+        const int big_per_cu =
+            std::max(1, std::min(2, (int)((160 * 1024 - (long long)T.adj_small_bytes) / (long long)T.adj_bytes)));
         a1.skip_flags = S->adj_big;
         AdjArgs ab = a;
         ab.env_list = S->adj_big_list + 1;
@@ -1091,7 +1045,7 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
             (e = hipStreamWaitEvent(S->aux2, S->ev_big_start, 0)) == hipSuccess &&
             (e = launch_zero_count(S->adj_big_list, S->aux2)) == hipSuccess &&
             (e = launch_compact_flags(T.env_list, T.n_envs, S->adj_big, S->adj_big_list, S->aux2)) == hipSuccess &&
-            (e = launch_adjoint(ab, T.n_envs, adj_fp64(p), S->aux2, S->n_cu)) == hipSuccess)
+            (e = launch_adjoint(ab, T.n_envs, adj_fp64(p), S->aux2, S->n_cu * big_per_cu)) == hipSuccess)
           e = hipEventRecord(S->ev_big_done, S->aux2);
         if (e != hipSuccess) return hip_fail(e, "step_backward: flagged pass");
       }

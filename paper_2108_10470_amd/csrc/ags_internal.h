@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ags_adj_layout.h"
+
 namespace ags {
 
 constexpr int kTeam = 64;       // lanes per environment: one wavefront
@@ -154,34 +156,6 @@ size_t jacmass_lds_bytes(int n_links, int n_v);
 hipError_t launch_jacmass(const JacMassArgs& a, hipStream_t stream);
 
 // ---------------------------------------------------------------- adjoint of one env-step
-constexpr int kAdjRows = 64;   // constraint rows per substep the adjoint handles (one lane each)
-constexpr int kAdjSmallRows = 32;  // row capacity of the first, smaller-LDS adjoint pass
-constexpr int kAdjBigRowsAt = 29;  // rows above which the forward flags an env for the larger layout (one contact's margin)
-constexpr int kAdjIters = 32;  // Gauss-Seidel sweeps the adjoint's tape holds
-constexpr int kAdjPhases = 8;
-
-// per-environment LDS layout of the adjoint kernel: offsets in elements of the compute type (reals)
-// or in ints (integer region, placed after the reals)
-struct AdjLds {
-  int Rm, p, ax, c, Iw, Ic, V, Vs, X0, X1, X2, X3, wr, sb, cb, tI;  // per link
-  int nu, qdd, vs, nu1, tau, arm, z, w, nub, vsb, nui, tmp;        // per column
-  int colS, colY, colYv, cs;                                       // per column, 6 each
-  int q, qb, ab;                                                   // per DOF
-  int st, rbar, dbar, nrb;                                             // state of each substep start, state adjoint
-  int Lm, nvp, ldi;                                                // dense n_v x nvp matrix (factor, then P); 1 / diag of the factor
-  int J, W, A, Ab, rcp;  // rows: J, W (rows x nvp); A and S = Abar + Abar^T (packed symmetric)
-  int rbc, rb, rinvA, rlam, rybar, rbbar, rx, rcen, rd, rxb, rqb;  // per row reals
-  int rdb, rwa, rwb;                                               // per row: d adjoint, wrenches of bodies a, b
-  int hlo, hres;                                                   // tape: iters x rcp
-  int misc;
-  int n_real;
-  // integer region
-  int rkind, rlink, rdof, rnrm, rmap, rlinkb, rslot, hst, flags;
-  int n_int;
-  int state_words;  // reals of one stored state: 13 per actor + 2 per DOF
-  int rows_cap;     // min(max rows, kAdjRows)
-};
-
 struct AdjArgs {
   DevModel m;
   AdjLds L;

@@ -1,0 +1,78 @@
+"""Host-side checks of the adjoint kernel's LDS use (CPU only).
+
+1. tests/adj_lds_check.cpp replays make_adj_layout (the header the runtime uses) for every workload model
+   and a grid of substeps, Gauss-Seidel sweeps and row capacities, touching every index the kernel's
+   indexing can reach in buffers of exactly the layout's size, built with AddressSanitizer and UBSan.
+2. The adjoint kernels of this build reach LDS only through DS instructions: no FLAT memory instruction
+   and no call appears in their gfx950 assembly.  (An earlier instrumented build, in which the compiler
+   outlined the reverse substep into a real call and reached LDS through FLAT instructions with offsets
+   beyond 64 KiB, faulted with a memory-aperture violation; the FP64 layouts put their row and tape arrays
+   above 64 KiB, as the replay reports.)
+"""
+import json
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2108_10470_amd import ags, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2108_10470_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def checker(tmp_path_factory):
+    exe = str(tmp_path_factory.mktemp("adjlds") / "adj_lds_check")
+    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                           "-I", CSRC, "-I", os.path.join(ROOT, "include"), "-o", exe,
+                           os.path.join(ROOT, "tests", "adj_lds_check.cpp")])
+    return exe
+
+
+MODELS = {"humanoid": W.env_humanoid, "ant": W.env_ant, "arm_box": W.env_arm_box, "hand_cube": W.env_hand_cube,
+          "pendulum": lambda: W.EnvSpec("pend", [W.pendulum()], [])}
+
+
+@pytest.mark.parametrize("model", sorted(MODELS))
+def test_adjoint_lds_layout_replay(checker, model):
+    info = ags.Model(MODELS[model]()).info
+    out = []
+    for substeps in (1, 2, 3):
+        for iters in (1, 8, 12, 32):
+            for cap in (5, 32, 64):
+                args = [str(x) for x in (info.n_links, info.n_v, info.n_dof, info.n_actors, info.max_rows, substeps,
+                                         iters, cap)]
+                r = subprocess.run([checker, *args], capture_output=True, text=True)
+                assert r.returncode == 0, (args, r.stderr)
+                d = json.loads(r.stdout)
+                assert d["ok"], (args, d)
+                out.append(d)
+    print(model, out[-1])
+
+
+def test_humanoid_fp64_full_layout_reaches_beyond_64_kib(checker):
+    """The configuration of the earlier fault: the FP64 full (64-row) layout of the humanoid-like model puts
+    its Delassus, row and tape arrays above 64 KiB of LDS."""
+    info = ags.Model(W.env_humanoid()).info
+    r = subprocess.run([checker, *[str(x) for x in (info.n_links, info.n_v, info.n_dof, info.n_actors, info.max_rows,
+                                                    2, 8, 64)]], capture_output=True, text=True, check=True)
+    d = json.loads(r.stdout)
+    assert d["bytes_f64"] > 65536 and "hst" in d["above_64KiB_f64"] and "A" in d["above_64KiB_f64"], d
+
+
+def test_adjoint_kernels_reach_lds_through_ds_instructions_only(tmp_path):
+    asm = tmp_path / "adj.s"
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "--cuda-device-only", "-S", "-O3",
+                           "-std=c++17", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                           "-I", os.path.join(ROOT, "include"), os.path.join(CSRC, "ags_adjoint.hip"), "-o", str(asm)],
+                          stderr=subprocess.DEVNULL)
+    text = asm.read_text()
+    kernels = re.findall(r"^(_ZN3ags\w*adjoint\w*kernel\w*):", text, flags=re.M)
+    assert len(kernels) >= 4, kernels
+    for k in kernels:
+        body = text.split(f"\n{k}:", 1)[1].split("s_endpgm", 1)[0]
+        assert not re.search(r"\bflat_(load|store|atomic)", body), k
+        assert "s_swappc" not in body and "s_setpc" not in body, k
+        assert re.search(r"\bds_(read|write|load|store)", body), k

@@ -183,6 +183,9 @@ def test_rollout_equals_chained_step_adjoints(fp64, case):
     scale = np.abs(chain).reshape(E, -1).max(axis=1) + 1e-30
     rel = np.abs(chain - g).reshape(E, -1).max(axis=1) / scale
     print("rollout vs chained step adjoints: max difference / env gradient scale per env", rel.tolist(), flush=True)
+    nrm = np.linalg.norm((chain - g).reshape(E, -1), axis=1) / (np.linalg.norm(chain.reshape(E, -1), axis=1) + 1e-30)
+    _report(f"rollout_vs_chained_{case}_{'fp64' if fp64 else 'fp32'}",
+            {"envs": E, "max_rel_per_env": rel.tolist(), "normwise_rel_per_env": nrm.tolist()})
     if fp64:
         assert (rel <= 1e-7).all(), rel
     else:
