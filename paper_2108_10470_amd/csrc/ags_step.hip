@@ -1226,33 +1226,60 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           Wrow[c + 0] = x6[3]; Wrow[c + 1] = x6[4]; Wrow[c + 2] = x6[5];
           Wrow[c + 3] = x6[0]; Wrow[c + 4] = x6[1]; Wrow[c + 5] = x6[2];
         }
-        // outward: qdd_i = (u_i - Ubar_i . a_root - sum_k G_ik qdd_k) / D_i in topological order
-        for (int i = 0; i < nl; ++i) {
-          const int* li = M.li + i * LI_COLS;
-          const int jt = li[LI_JTYPE];
-          if (jt == J_FREE || jt == J_FIXED) continue;
-          R acc = R(0);
-          const int rc = li[LI_ROOTCOL];
-          if (rc >= 0) {
-            const auto ub = s.Ubar + 3 * i;
-            const auto ul = s.U + 6 * i + 3;
-            acc = ub[0] * Wrow[rc + 3] + ub[1] * Wrow[rc + 4] + ub[2] * Wrow[rc + 5] + ul[0] * Wrow[rc + 0] +
-                  ul[1] * Wrow[rc + 1] + ul[2] * Wrow[rc + 2];
+      }
+      __syncthreads();
+      // outward: qdd_i = (u_i - Ubar_i . a_root - sum_k G_ik qdd_k) / D_i, level by level with lanes over the
+      // (row, link) pairs of a level, so that the chain has one step per tree level instead of one per link
+      {
+        const int rows_here = min(FR, max(0, Rn - rb));
+        for (int d = 1; d < M.n_levels; ++d) {
+          const int b = M.level_begin[d], n_at = M.level_begin[d + 1] - b;
+          const int pairs = rows_here * n_at;
+          for (int pi = tt; pi < pairs; pi += TEAM) {
+            const int q_ = pi / n_at;
+            const int i = M.level_links[b + pi - q_ * n_at];
+            const int* li = M.li + i * LI_COLS;
+            const int jt = li[LI_JTYPE];
+            if (jt == J_FREE || jt == J_FIXED) continue;
+            const auto Wq = s.W + q_ * L.wstride;
+            R acc = R(0);
+            const int rc = li[LI_ROOTCOL];
+            if (rc >= 0) {
+              const auto ub = s.Ubar + 3 * i;
+              const auto ul = s.U + 6 * i + 3;
+              acc = ub[0] * Wq[rc + 3] + ub[1] * Wq[rc + 4] + ub[2] * Wq[rc + 5] + ul[0] * Wq[rc + 0] +
+                    ul[1] * Wq[rc + 1] + ul[2] * Wq[rc + 2];
+            }
+            for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q)
+              acc += s.G[q] * Wq[M.anc_link[q] >> 16];
+            const int c = li[LI_COL];
+            Wq[c] = (Wq[c] - acc) * s.Dinv[i];
           }
-          for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q)
-            acc += s.G[q] * Wrow[M.anc_link[q] >> 16];
-          const int c = li[LI_COL];
-          Wrow[c] = (Wrow[c] - acc) * s.Dinv[i];
+          __syncthreads();
         }
-        // A_rr = J_r W_r
+      }
+      if (r < Rn) {
+        // A_rr = J_r W_r (the slow path re-derives its row's direction and point from the row tables)
         R A;
         if (fast) {
           A = jrow_dot(jr, Wrow);
-        } else if (kind <= 2) {
-          A = sg * Wrow[M.li[lk * LI_COLS + LI_COL]];
         } else {
-          A = point_row(M, s, ka, x, dd, R(1), Wrow, Wrow, false, true);
-          if (kb >= 0) A += point_row(M, s, kb, x, dd, R(-1), Wrow, Wrow, false, true);
+          const int kr = s.rkr[r];
+          const int kind = kr >> 16, ref = kr & 0xffff;
+          if (kind <= 2) {
+            A = (kind == 1 ? R(1) : R(-1)) * Wrow[M.li[M.dof_link[ref] * LI_COLS + LI_COL]];
+          } else {
+            V3<R> dd = ld3<R>(s.n + 3 * ref);
+            if (kind != 3) {
+              V3<R> t1, t2;
+              tangents(dd, t1, t2);
+              dd = kind == 4 ? t1 : t2;
+            }
+            const V3<R> x = ld3<R>(s.x + 3 * ref);
+            const int ka = M.si[ref * SI_COLS + SI_LINK_A], kb = M.si[ref * SI_COLS + SI_LINK_B];
+            A = point_row(M, s, ka, x, dd, R(1), Wrow, Wrow, false, true);
+            if (kb >= 0) A += point_row(M, s, kb, x, dd, R(-1), Wrow, Wrow, false, true);
+          }
         }
         s.rinvA[r] = A >= R(kMinRowMass) ? R(1) / A : R(0);
         s.rlam[r] = R(0);

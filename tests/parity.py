@@ -105,6 +105,58 @@ def summarize(c):
     return s
 
 
+def fp32_envelope(oe, params, root, dof, act, o, pos_tgt=None, n=4, seed=0):
+    """The step's sensitivity at FP32 resolution: over n seeded moves of every input position to an adjacent
+    float32 value, the largest change of each oracle output (FP64 steps of FP32 inputs).  An FP32 evaluation
+    rounds the kinematics it starts from at that level, so its errors are expected to be of this size."""
+    rng = np.random.default_rng(seed)
+    env_o = {k: np.zeros_like(o[k], dtype=np.float64) for k in ("qdd_free", "root", "dof", "dof_force", "contact_force")}
+    lam = np.zeros_like(o["row_lambda"])
+    for _ in range(n):
+        def move(x, mask):
+            x32 = x.astype(np.float32)
+            up = rng.integers(0, 2, size=x.shape).astype(bool)
+            y = np.where(up, np.nextafter(x32, np.float32(np.inf)), np.nextafter(x32, np.float32(-np.inf)))
+            return np.where(mask, y.astype(np.float64), x)
+        rm = np.zeros(root.shape, bool)
+        rm[..., :7] = True
+        dm = np.zeros(dof.shape, bool)
+        dm[..., 0] = True
+        o1 = oe.step(params, move(root, rm), move(dof, dm), act, pos_tgt=pos_tgt, r_cap=o["row_key"].shape[2])
+        for k in env_o:
+            env_o[k] = np.maximum(env_o[k], np.abs(o1[k] - o[k]))
+        same = (o1["row_key"] == o["row_key"])
+        lam = np.maximum(lam, np.where(same, np.abs(o1["row_lambda"] - o["row_lambda"]), 0.0))
+    env_o["row_lambda"] = lam
+    return env_o
+
+
+def compare_envelope(env, params, g, o, S, factor):
+    """Per-env worst ratio |g - o| / (tolerance + factor x the FP32-resolution sensitivity S) for the
+    accelerations, positions, velocities and impulses (rows matched by key); near-jump envs masked."""
+    E = g["root"].shape[0]
+    near = ((o["near"] & O.NEAR_VALUE) != 0).any(axis=1)
+
+    def r(a, b, s):
+        return (np.abs(a - b) / (ATOL + RTOL * np.abs(b) + factor * s)).reshape(E, -1).max(axis=1)
+
+    out = {"near": near, "qdd_free": r(g["qdd_free"], o["qdd_free"], S["qdd_free"]),
+           "q": np.maximum(r(g["root"][:, :, :7], o["root"][:, :, :7], S["root"][:, :, :7]),
+                           r(g["dof"][:, :, 0], o["dof"][:, :, 0], S["dof"][:, :, 0])),
+           "qd": np.maximum(r(g["root"][:, :, 7:], o["root"][:, :, 7:], S["root"][:, :, 7:]),
+                            r(g["dof"][:, :, 1], o["dof"][:, :, 1], S["dof"][:, :, 1]))}
+    lam = np.zeros(E)
+    for e in range(E):
+        for s_ in range(params.substeps):
+            n = o["row_count"][e, s_]
+            if n and g["row_count"][e, s_] == n and np.array_equal(g["row_key"][e, s_, :n], o["row_key"][e, s_, :n]):
+                gl, ol, sl = g["row_lambda"][e, s_, :n], o["row_lambda"][e, s_, :n], S["row_lambda"][e, s_, :n]
+                lam[e] = max(lam[e], float((np.abs(gl - ol) / (ATOL + RTOL * np.abs(ol) + factor * sl)).max()))
+    out["lambda"] = lam
+    ok = ~near
+    return {k + "_envelope_max_ratio": float(v[ok].max()) if ok.any() else 0.0 for k, v in out.items() if k != "near"}
+
+
 def oracle_states(env, params, n_envs, n_steps, every, seed=0):
     """Seeded initial states rolled out by the FP64 oracle; returns the states before every
     `every`-th step and the actions applied there, stacked along the env axis."""
@@ -139,4 +191,5 @@ def run(env, params, root, dof, act, oe=None, pos_tgt=None, device="cuda:0", fp6
                   lanes_per_env=lanes_per_env)
     g = gpu_step(sim, env, root32, dof32, act32, pt32)
     o = oe.step(params, root32, dof32, act32, pos_tgt=pt32, r_cap=g["row_key"].shape[2])
+    g["_inputs"] = (oe, params, root32, dof32, act32, pt32)
     return g, o
