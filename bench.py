@@ -95,6 +95,9 @@ def parse():
     ap.add_argument("--no-hand", action="store_true", help="skip the 65536-env hand+cube measurement")
     ap.add_argument("--hand-envs", type=int, default=65536)
     ap.add_argument("--hand-steps", type=int, default=32)
+    ap.add_argument("--phase-report", action="store_true",
+                    help="instead of the benchmark: per-phase shader-clock cycles of the step (FP64, FP32) and of the "
+                         "adjoint's dense row responses on the pre-rolled window, one JSON line")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="first run one plain device copy of this many MiB (scale reference for HBM counters)")
     return ap.parse_args()
@@ -487,6 +490,49 @@ def run_ant_grad(fp64, reps):
     return out
 
 
+def phase_report(env, params, E, P, actions_dev, root_stand, dof_stand, steps=5):
+    """Per-phase shader-clock cycles per substep (mean over envs) of the step kernel (FP64 and FP32) and of the
+    adjoint's recomputation in its dense form (composite inertias + M~ + Cholesky; J rows + W = M~^-1 J^T by
+    triangular solves; A = J W^T on the matrix cores), FP64 and FP32 adjoint, on the pre-rolled window."""
+    import torch
+    from paper_2108_10470_amd import ags
+    root0, dof0 = preroll(env, params, E, P, actions_dev, root_stand, dof_stand)
+    out = {"envs": E, "preroll_steps": P}
+    names = ["controls", "forward", "inward", "outward", "vstar", "narrow", "rows", "responses", "pgs", "outputs"]
+    for fp64 in (True, False):
+        sim = ags.Sim([ags.Model(env)], [0] * E, params, device="cuda:0", fp64=fp64, phase_cycles=True)
+        sim.root_state.copy_(root0)
+        sim.dof_state.copy_(dof0)
+        acc = torch.zeros(E, len(names), dtype=torch.float64, device="cuda:0")
+        for t in range(steps):
+            sim.bind(ags.DOF_ACTUATION, actions_dev[P + t])
+            sim.step()
+            acc += sim.dbg_cycles.double()
+        torch.cuda.synchronize()
+        c = (acc / steps).mean(0).cpu().numpy() / params.substeps
+        out[f"step_{'fp64' if fp64 else 'fp32'}_cycles_per_substep"] = {n: round(float(v)) for n, v in zip(names, c)}
+    an = ["recompute_other", "recompute_gauss_seidel", "reverse_gauss_seidel", "reverse_dense_products",
+          "reverse_mass_terms", "reverse_rnea", "reverse_rows", "reverse_integration", "dense_crba_cholesky",
+          "dense_rows_J_W", "dense_delassus_mfma"]
+    for prec in (64, 32):
+        sim = ags.Sim([ags.Model(env)], [0] * E, params, device="cuda:0", fp64=True, adjoint_precision=prec)
+        cyc = torch.zeros((E, len(an)), dtype=torch.int64, device="cuda:0")
+        sim.bind(ags.DEBUG_ADJ_CYCLES, cyc)
+        acc = torch.zeros(E, len(an), dtype=torch.float64, device="cuda:0")
+        aa = torch.zeros(actions_dev[0].shape, dtype=torch.float32, device="cuda:0")
+        for t in range(3):
+            ra = torch.zeros_like(root0)
+            ra[:, 0] = 1.0
+            sim.step_backward(root0, dof0, actions_dev[P + t], ra, torch.zeros_like(dof0), aa)
+            acc += cyc.double()
+        torch.cuda.synchronize()
+        # one call recomputes 2 S - 1 substeps (S - 1 to reach the last, then each again before its reverse)
+        c = (acc / 3).mean(0).cpu().numpy() / (2 * params.substeps - 1)
+        out[f"adjoint_fp{prec}_cycles_per_recomputed_substep"] = {
+            n: round(float(v)) for n, v in zip(an, c) if n.startswith("recompute") or n.startswith("dense")}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -514,6 +560,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.phase_report:
+        phase_report(env, params, E, P, actions_dev, root_stand, dof_stand)
+        return
     root0, dof0 = preroll(env, params, E, P, actions_dev, root_stand, dof_stand)
     win_actions = actions_dev[P:]
 

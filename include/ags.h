@@ -182,10 +182,11 @@ void ags_sim_destroy(ags_sim* sim);
  *   AGS_DEBUG_ROW_COUNT    (E, substeps)  int32          constraint rows per substep
  *   AGS_DEBUG_ROW_KEY      (E, substeps * max rows) int32  row keys (kind << 24 | a << 8 | b)
  *   AGS_DEBUG_ROW_LAMBDA   (E, substeps * max rows)      row impulses after the last sweep
- *   AGS_DEBUG_ADJ_CYCLES   (E, 8)   int64                shader-clock cycles per phase of ags_sim_step_backward
- *                          (recompute except Gauss-Seidel, recompute Gauss-Seidel, reverse Gauss-Seidel, reverse
- *                          dense products, reverse mass-matrix terms, reverse RNEA, reverse rows and wrenches,
- *                          reverse integration and solves), for profiling
+ *   AGS_DEBUG_ADJ_CYCLES   (E, 11)  int64                shader-clock cycles per phase of ags_sim_step_backward
+ *                          (recompute: other parts, Gauss-Seidel; reverse: Gauss-Seidel, dense products,
+ *                          mass-matrix terms, RNEA, rows and wrenches, integration and solves; recompute:
+ *                          composite inertias + dense M~ + its Cholesky factor, J rows + W = M~^-1 J^T,
+ *                          Delassus A = J W^T on the matrix cores), for profiling
  *   AGS_DEBUG_PHASE_CYCLES (E, 10)  int64                shader-clock cycles per phase of the step (controls,
  *                          forward sweep, inward sweep, outward sweep, v* sweep, narrow phase, rows,
  *                          row responses, Gauss-Seidel, outputs), for profiling

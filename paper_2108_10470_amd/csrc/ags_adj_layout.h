@@ -12,7 +12,7 @@ constexpr int kAdjRows = 64;   // constraint rows per substep the adjoint handle
 constexpr int kAdjSmallRows = 32;  // row capacity of the first, smaller-LDS adjoint pass
 constexpr int kAdjBigRowsAt = 29;  // rows above which the forward flags an env for the larger layout (one contact's margin)
 constexpr int kAdjIters = 32;  // Gauss-Seidel sweeps the adjoint's tape holds
-constexpr int kAdjPhases = 8;
+constexpr int kAdjPhases = 11;  // see AGS_DEBUG_ADJ_CYCLES
 
 // per-environment LDS layout of the adjoint kernel: offsets in elements of the compute type (reals)
 // or in ints (integer region, placed after the reals)

@@ -622,6 +622,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     Ic[7] = Iw[3] - m * cw.x * cw.y; Ic[8] = Iw[4] - m * cw.x * cw.z; Ic[9] = Iw[5] - m * cw.y * cw.z;
   }
   sync<R>();
+  E.phase(8);
   // ---- composite inertias (inward by level, children gathered)
   for (int lev = E.nlev - 2; lev >= 0; --lev) {
     const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
@@ -673,6 +674,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     if (lane == 0) E.r[L.ldi + k] = di;
     sync<R>();
   }
+  E.phase(0);
   // ---- C(q, qd): RNEA with zero joint accelerations, gravity as a base acceleration
   for (int lev = 0; lev < E.nlev; ++lev) {
     const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
@@ -838,6 +840,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   }
   if (nrows > rcap) return false;
   sync<R>();
+  E.phase(9);
   // ---- J rows and responses W = M~^-1 J^T (one row per lane)
   R* J = E.r + L.J;
   R* W = E.r + L.W;
@@ -947,6 +950,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   nrm = lane < nkeep && g_kind >= 4 ? g_nrm : -1;
   sync<R>();
   const int Rn = nkeep;
+  E.phase(10);
   // ---- Delassus matrix A = J W^T (symmetric, packed lower), on the matrix cores
   R* A = E.r + L.A;
   const int rcp = L.rcp;

@@ -915,10 +915,13 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         const R ud = u * Dinv;
         pn = add(add(pn, ia), mul(Ua, ud));
         pf = add(add(pf, il), mul(Ul, ud));
-        // move to the parent's point
+        // move to the parent's point (nothing to move for a joint anchored at its parent's origin, such as the
+        // massless links of per-axis joint chains)
         const V3<R> r = sub(ld3<R>(s.o + 3 * i), ld3<R>(s.o + 3 * li[LI_PARENT]));
-        si_shift(I, r);
-        pn = add(pn, cross(r, pf));
+        if (r.x != R(0) || r.y != R(0) || r.z != R(0)) {
+          si_shift(I, r);
+          pn = add(pn, cross(r, pf));
+        }
         si_store(I, s.IA + 21 * i);
         st3(s.pA + 6 * i, pn);
         st3(s.pA + 6 * i + 3, pf);

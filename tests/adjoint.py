@@ -86,6 +86,15 @@ def compare(g, fd, floor_frac):
     return ratio.max(axis=1), ok
 
 
+def normwise(g, fd):
+    """Per-env relative error of the gradient vector, |g - fd| / |fd|, over the entries away from switches
+    (no floor: the reading of a relative gradient error that does not depend on an absolute scale)."""
+    ok = ~np.isnan(fd)
+    d = np.where(ok, g - fd, 0.0)
+    f = np.where(ok, fd, 0.0)
+    return np.linalg.norm(d, axis=1) / (np.linalg.norm(f, axis=1) + 1e-300)
+
+
 def f32_inputs(env, params, n_envs, steps_before, seed=0):
     """Seeded start states rolled out by the oracle for `steps_before` steps, rounded to FP32, with the
     next step's actions and seeded loss weights."""

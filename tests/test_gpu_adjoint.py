@@ -40,8 +40,11 @@ def test_step_adjoint_vs_finite_differences(model, steps_before, fp64):
     g, status = A.gpu_grads(env, params, root, dof, act, wr, wd, fp64)
     assert (status == 0).all(), status
     worst, ok = A.compare(g, fd, FLOOR[fp64])
+    worst_f64floor, _ = A.compare(g, fd, FLOOR[True])
+    nrm = A.normwise(g, fd)
     d = {"envs": int(root.shape[0]), "entries": int(ok.size), "excluded_switch": int((~ok).sum()),
          "worst_ratio": float(worst.max()), "pass_rate": float((worst <= 1.0).mean()),
+         "worst_ratio_at_fp64_floor": float(worst_f64floor.max()), "worst_normwise_rel_err": float(nrm.max()),
          "rel_err_act_median": float(np.nanmedian(np.abs(g - fd)[:, :env.n_dof] / (np.abs(fd[:, :env.n_dof]) + 1e-12)))}
     _report(f"adjoint_{model}_{steps_before}_{'fp64' if fp64 else 'fp32'}", d)
     if not (worst <= 1.0).all():
@@ -49,6 +52,8 @@ def test_step_adjoint_vs_finite_differences(model, steps_before, fp64):
         k = int(np.nanargmax(np.where(ok[e], np.abs(g[e] - fd[e]), -1)))
         print("worst env", e, "entry", ent[k], "gpu", g[e, k], "fd", fd[e, k], flush=True)
     assert (worst <= 1.0).all()
+    # the gradient as a vector, without any floor: |g - fd| / |fd| over the entries away from switches
+    assert (nrm <= A.RTOL).all(), nrm
 
 
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
@@ -66,11 +71,13 @@ def test_step_adjoint_rows_beyond_first_pass(fp64):
     g, status = A.gpu_grads(env, params, root, dof, act, wr, wd, fp64)
     assert (status == 0).all(), status
     worst, ok = A.compare(g, fd, FLOOR[fp64])
+    nrm = A.normwise(g, fd)
     d = {"envs": int(root.shape[0]), "envs_over_32_rows": int((rc[pick] > 32).sum()), "entries": int(ok.size),
          "excluded_switch": int((~ok).sum()), "worst_ratio": float(worst.max()),
-         "pass_rate": float((worst <= 1.0).mean())}
+         "pass_rate": float((worst <= 1.0).mean()), "worst_normwise_rel_err": float(nrm.max())}
     _report(f"adjoint_humanoid_many_rows_{'fp64' if fp64 else 'fp32'}", d)
     assert (worst <= 1.0).all()
+    assert (nrm <= A.RTOL).all(), nrm
 
 
 def _ant_rollout_case(E=16, T=16, warm=30):
@@ -189,8 +196,9 @@ def test_rollout_equals_chained_step_adjoints(fp64, case):
     if fp64:
         assert (rel <= 1e-7).all(), rel
     else:
-        # FP32: the two substep states differ by FP32 rounding, which can flip a clamp in a few envs
-        assert (rel <= 1e-3).mean() >= 0.75, rel
+        # FP32: the rollout's adjoint starts its second substep from the forward's stored state, the chained
+        # single steps from their own FP32 recomputation of it (measured: at most ~1e-4 of the gradient scale)
+        assert (rel <= 1e-3).all(), rel
 
 
 @pytest.mark.parametrize("case", ["ant", "humanoid_many_rows", "hand_targets"])
