@@ -177,7 +177,9 @@ void ags_sim_destroy(ags_sim* sim);
  *                          orientation quaternion xyzw, velocity of the origin, angular velocity (world)
  *   AGS_ENV_STATUS         (E, 1)  int32  get  per-env status of the last step: bit 0 the new state is not
  *                          finite, bit 1 a substep had more than 32 rows (or a Jacobian row too long for the
- *                          register form) and took the slower row-response path; failures never fail the call
+ *                          register form) and took one of the slower row paths (responses in chunks of 32
+ *                          rows; with 64 lanes per env and up to 64 rows the Delassus columns are streamed
+ *                          from scratch, otherwise rows and cross-lane sums); failures never fail the call
  *   AGS_DEBUG_QDD_FREE     (E, substeps * max n_v)       unconstrained joint accelerations per substep
  *   AGS_DEBUG_ROW_COUNT    (E, substeps)  int32          constraint rows per substep
  *   AGS_DEBUG_ROW_KEY      (E, substeps * max rows) int32  row keys (kind << 24 | a << 8 | b)

@@ -750,7 +750,8 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
       ags_sim_destroy(S);
       return hip_fail(err, "sim: adjoint LDS limit");
     }
-    T.scratch_stride = 2ll * D.r_cap * std::max(1, D.n_v);
+    // J and W rows (slow path), then the wide path's columns of A (one entry per lane of a 64-lane team)
+    T.scratch_stride = 2ll * D.r_cap * std::max(1, D.n_v) + (T.team == 64 ? 64ll * 64 : 0);
     T.scratch_stride = (T.scratch_stride + 63) & ~63ll;
     const size_t elem = p->compute_fp64 ? sizeof(double) : sizeof(float);
     const int epw = kTeam / T.team;

@@ -697,6 +697,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   const int n_envs = T.n_envs;
   constexpr int EPW = kTeam / TEAM;  // environments per wavefront
   constexpr int FR = kFastRows;      // rows of the register Gauss-Seidel path and of one response chunk
+  constexpr int kWideAhead = 8;      // wide path: rows of A columns in flight ahead of the Gauss-Seidel updates
   static_assert(FR <= TEAM, "fast rows exceed the lanes of an environment");
   const int t = threadIdx.x;         // lane in the wavefront
   const int tm = EPW == 1 ? 0 : t / TEAM;  // team (environment slot) of this lane
@@ -715,6 +716,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   constexpr bool tgs = TGS;
   R* Jg = reinterpret_cast<R*>(T.scratch) + (long long)gidx * T.scratch_stride;
   R* Wg = Jg + (long long)M.r_cap * nv;
+  R* Ag = Wg + (long long)M.r_cap * nv;  // wide path: columns of A, TEAM entries per row
 
   // ---------------------------------------------------------------- load state
   for (int k = tt; k < 13 * na; k += TEAM) s.root[k] = R(P.root_state[(long long)abase * 13 + k]);
@@ -1167,14 +1169,37 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     // Up to FR rows (one per lane) keep their Jacobian in registers (compact form) and W in LDS and are
     // solved in registers below; more rows (or rows too long for the compact form) go through global scratch.
     const bool fast = Rn <= FR && M.jfast;
+    // more rows than one chunk but no more than the lanes of the environment: every lane keeps its own row's
+    // compact Jacobian (lane k: row k), the responses still go in chunks of FR rows, and Gauss-Seidel runs
+    // in the Delassus form with the columns of A streamed from global scratch instead of held in registers
+    const bool wide = !fast && TEAM == 64 && M.jfast && Rn <= TEAM;
     slow_any = slow_any || !fast;
     rows_max = max(rows_max, Rn);
-    if (!fast)
+    if (!fast && !wide)
       for (int k = tt; k < Rn * nv; k += TEAM) Jg[k] = R(0);
-    JRow<R> jr;  // fast path: this lane's row
+    JRow<R> jr;  // fast and wide paths: this lane's row
     jrow_clear(jr);
+    if (wide && tt >= FR && tt < Rn) {  // rows past the first chunk: their lanes form the compact row here
+      const int kr = s.rkr[tt];
+      const int kind = kr >> 16, ref = kr & 0xffff;
+      if (kind <= 2) {
+        jr.c[0] = M.li[M.dof_link[ref] * LI_COLS + LI_COL];
+        jr.val[0] = kind == 1 ? R(1) : R(-1);
+      } else {
+        V3<R> dd = ld3<R>(s.n + 3 * ref);
+        if (kind != 3) {
+          V3<R> t1, t2;
+          tangents(dd, t1, t2);
+          dd = kind == 4 ? t1 : t2;
+        }
+        jrow_point(M, s, M.si[ref * SI_COLS + SI_LINK_A], M.si[ref * SI_COLS + SI_LINK_B], ld3<R>(s.x + 3 * ref), dd,
+                   jr);
+      }
+    }
     __syncthreads();
     for (int rb = 0; rb < Rn; rb += FR) {  // chunks of FR rows, one per lane
+      // the lanes of this chunk form their compact rows (fast path, and the first chunk of the wide path)
+      const bool jreg = fast || (wide && rb == 0);
       const int r = tt < FR ? rb + tt : Rn;
       const auto Wrow = s.W + tt * L.wstride;  // only lanes tt < FR own a row of the block
       R* const JrowG = Jg + (long long)r * nv;
@@ -1190,10 +1215,10 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           lk = M.dof_link[ref];
           sg = kind == 1 ? R(1) : R(-1);
           const int col = M.li[lk * LI_COLS + LI_COL];
-          if (fast) {
+          if (jreg) {
             jr.c[0] = col;
             jr.val[0] = sg;
-          } else {
+          } else if (!wide) {
             JrowG[col] = sg;
           }
           unit_load_inward(M, s, lk, mk(R(0), R(0), R(0)), mk(R(0), R(0), R(0)), sg, Wrow);
@@ -1208,9 +1233,9 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           x = ld3<R>(s.x + 3 * ref);
           ka = M.si[ref * SI_COLS + SI_LINK_A];
           kb = M.si[ref * SI_COLS + SI_LINK_B];
-          if (fast) {
+          if (jreg) {
             jrow_point(M, s, ka, kb, x, dd, jr);
-          } else {
+          } else if (!wide) {
             point_row(M, s, ka, x, dd, R(1), JrowG, Wrow, true, false);
             if (kb >= 0) point_row(M, s, kb, x, dd, R(-1), JrowG, Wrow, true, false);
           }
@@ -1264,7 +1289,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       if (r < Rn) {
         // A_rr = J_r W_r (the slow path re-derives its row's direction and point from the row tables)
         R A;
-        if (fast) {
+        if (jreg) {
           A = jrow_dot(jr, Wrow);
         } else {
           const int kr = s.rkr[r];
@@ -1288,6 +1313,19 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         s.rlam[r] = R(0);
       }
       __syncthreads();
+      if (wide) {
+        // column block of A: lane k forms A[k][r] = J_k W_r for this chunk's rows (A_rk in the column of row r,
+        // A being symmetric), and its own row's 1/A_kk from the same product
+        const int rows_here = min(FR, Rn - rb);
+        R diag = R(0);
+        if (tt < Rn)
+          for (int q = 0; q < rows_here; ++q) {
+            const R a = jrow_dot(jr, s.W + q * L.wstride);
+            Ag[(long long)(rb + q) * TEAM + tt] = a;
+            diag = rb + q == tt ? a : diag;
+          }
+        if (tt >= rb && tt < rb + rows_here) s.rinvA[tt] = diag >= R(kMinRowMass) ? R(1) / diag : R(0);
+      }
       if (!fast) {
         const int rows_here = min(FR, Rn - rb);
         for (int q = 0; q < rows_here; ++q)
@@ -1364,6 +1402,60 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       vj = tt < nv ? s.vs[tt] : R(0);
       if (tt < nv)
         for (int r = 0; r < Rn; ++r) vj += s.rlam[r] * s.W[r * L.wstride + tt];
+    } else if (wide) {
+      // the register form above with up to TEAM rows: lane k holds y_k = J_k v and reads A[k][r] from the column
+      // of row r in global scratch, kWideAhead rows ahead of the update that uses it
+      R y = tt < Rn ? jrow_dot(jr, s.vs) : R(0);
+      const bool own = tt < Rn;
+      const R ia = own ? s.rinvA[tt] : R(0);
+      const int kindv = own ? (s.rkr[tt] >> 16) : 0;
+      const bool fric = kindv >= 4;
+      const int nrmv = fric ? tt - (kindv - 3) : -1;
+      R pos = own && tgs ? s.rbias[tt] : R(0);
+      R bias = own ? (tgs ? (fric ? R(0) : row_bias(pos, h, R(P.beta))) : s.rbias[tt]) : R(0);
+      const R fsign = fric ? R(1) : R(0);
+      R lam = R(0), hi = fric ? R(0) : R(kOpenBound), lo = R(0), bia = bias * ia;
+      R c = -bia;
+      const R hstep = h / R(max(P.iters, 1));
+      const R* const acol = Ag + tt;
+      for (int it = 0; it < P.iters; ++it) {
+        if (tgs && it > 0 && own && !fric) {
+          bias = row_bias(pos, h, R(P.beta));
+          bia = bias * ia;
+          c = lam - bia;
+        }
+        R nx[kWideAhead];
+#pragma unroll
+        for (int q = 0; q < kWideAhead; ++q) nx[q] = own && q < Rn ? acol[q * TEAM] : R(0);
+        for (int r0 = 0; r0 < Rn; r0 += kWideAhead) {
+          R cur[kWideAhead];
+#pragma unroll
+          for (int q = 0; q < kWideAhead; ++q) {
+            cur[q] = nx[q];
+            const int rn = r0 + kWideAhead + q;
+            nx[q] = own && rn < Rn ? acol[rn * TEAM] : R(0);  // lanes without a row read nothing
+          }
+#pragma unroll
+          for (int q = 0; q < kWideAhead; ++q) {
+            const int r = r0 + q;
+            if (r < Rn) {
+              const R cand = clamp_(fma_(-y, ia, c), lo, hi);
+              const R dl = team_read<TEAM>(tm, cand - lam, r);
+              lam = tt == r ? cand : lam;
+              c = lam - bia;
+              hi = fma_(nrmv == r ? mu : R(0), dl, hi);
+              lo = -(hi * fsign);
+              y += cur[q] * dl;
+            }
+          }
+        }
+        if (tgs) pos += hstep * y;
+      }
+      if (own) s.rlam[tt] = lam;
+      __syncthreads();
+      vj = tt < nv ? s.vs[tt] : R(0);
+      if (tt < nv)
+        for (int r = 0; r < Rn; ++r) vj += s.rlam[r] * Wg[(long long)r * nv + tt];
     } else {
       // lanes over velocity columns, rows streamed from global scratch
       vj = tt < nv ? s.vs[tt] : R(0);

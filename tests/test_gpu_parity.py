@@ -73,6 +73,9 @@ def test_pendulum_free_swing():
 @pytest.mark.parametrize("lanes", [32, 64])
 @pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
 def test_humanoid_parity_from_oracle_states(fp64, lanes):
+    """Humanoid-like envs, states every 8 steps of a 120-step oracle rollout.  Some substeps have more than 32
+    rows: with 64 lanes per env they take the wide Gauss-Seidel path (one row per lane, columns of the Delassus
+    matrix streamed from scratch), with 32 lanes the slow path (rows streamed, one cross-lane sum per row)."""
     env = W.env_humanoid()
     p = W.SimParams()
     oe, root, dof, act = PT.oracle_states(env, p, n_envs=32, n_steps=120, every=8)
@@ -80,7 +83,9 @@ def test_humanoid_parity_from_oracle_states(fp64, lanes):
     s = _summary(env, p, g, o, fp64)
     s["mean_rows"] = float(o["row_count"].mean())
     s["max_rows"] = int(o["row_count"].max())
+    s["substeps_over_32_rows"] = int((o["row_count"] > 32).sum())
     _report(f"humanoid_{'fp64' if fp64 else 'fp32'}_l{lanes}", s)
+    assert s["substeps_over_32_rows"] >= 10, s
     _assert_pass(s) if fp64 else _assert_fp32(s)
 
 
