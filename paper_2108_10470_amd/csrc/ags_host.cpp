@@ -463,6 +463,10 @@ struct TypeDev {
   Lds lds{};
   void* block = nullptr;       // device tables
   int* env_list = nullptr;     // device env ids of this type
+  // per-type launches with one environment per wavefront: the env ids in the order the next step dispatches
+  // them (most rows in the previous step first), and the reordering's buffer
+  int* step_order = nullptr;
+  int* order_tmp = nullptr;
   int n_envs = 0;
   void* scratch = nullptr;
   long long scratch_stride = 0;  // elements of the compute type per env
@@ -556,6 +560,7 @@ struct ags_sim {
   double* mid_root = nullptr;  // set while a rollout recomputes: where the step writes substep states
   int* adj_retry = nullptr;    // device: count, then the environments the small adjoint layout could not hold
   int* adj_big_list = nullptr; // device: count, then the flagged environments of the current type
+  int* env_rows = nullptr;     // device: most rows of a substep in each env's last step (dispatch order)
   int n_cu = 1;                // compute units of the sim's device
   // rollout backward: a second stream (default priority) recomputes the next segment while the adjoint of
   // the current one runs; events order the two segment buffers between the streams
@@ -753,6 +758,15 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     // J and W rows (slow path), then the wide path's columns of A (one entry per lane of a 64-lane team)
     T.scratch_stride = 2ll * D.r_cap * std::max(1, D.n_v) + (T.team == 64 ? 64ll * 64 : 0);
     T.scratch_stride = (T.scratch_stride + 63) & ~63ll;
+    if (T.team == 64) {
+      if ((err = hipMalloc(&T.step_order, 2 * sizeof(int) * T.n_envs)) != hipSuccess ||
+          (err = hipMemcpy(T.step_order, lists[t].data(), sizeof(int) * T.n_envs, hipMemcpyHostToDevice)) != hipSuccess) {
+        S->types.push_back(T);
+        ags_sim_destroy(S);
+        return hip_fail(err, "sim: dispatch order");
+      }
+      T.order_tmp = T.step_order + T.n_envs;
+    }
     const size_t elem = p->compute_fp64 ? sizeof(double) : sizeof(float);
     const int epw = kTeam / T.team;
     const size_t padded = (size_t)((T.n_envs + epw - 1) / epw) * epw;
@@ -775,7 +789,9 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     S->types.push_back(T);
   }
   int dev_cu = 0, n_cu = 0;
-  if ((err = hipMalloc(&S->adj_retry, ((size_t)max_type_envs + 1) * sizeof(int))) != hipSuccess ||
+  if ((err = hipMalloc(&S->env_rows, (size_t)S->n_envs * sizeof(int))) != hipSuccess ||
+      (err = hipMemset(S->env_rows, 0, (size_t)S->n_envs * sizeof(int))) != hipSuccess ||
+      (err = hipMalloc(&S->adj_retry, ((size_t)max_type_envs + 1) * sizeof(int))) != hipSuccess ||
       (err = hipMalloc(&S->adj_big_list, ((size_t)max_type_envs + 1) * sizeof(int))) != hipSuccess ||
       (err = hipGetDevice(&dev_cu)) != hipSuccess ||
       (err = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_cu)) != hipSuccess) {
@@ -838,8 +854,10 @@ extern "C" void ags_sim_destroy(ags_sim* S) {
   for (TypeDev& T : S->types) {
     if (T.block) (void)hipFree(T.block);
     if (T.scratch) (void)hipFree(T.scratch);
+    if (T.step_order) (void)hipFree(T.step_order);
   }
   if (S->adj_retry) (void)hipFree(S->adj_retry);
+  if (S->env_rows) (void)hipFree(S->env_rows);
   if (S->adj_big_list) (void)hipFree(S->adj_big_list);
   for (int k = 0; k < 2; ++k) {
     if (S->ev_ready[k]) (void)hipEventDestroy(S->ev_ready[k]);
@@ -957,9 +975,17 @@ extern "C" int ags_sim_step(ags_sim* S, void* stream) {
     if (e != hipSuccess) return hip_fail(e, "step: launch");
     return AGS_OK;
   }
+  // A launch ends with its slowest workgroups, and an env-step's cost grows with its constraint rows (those
+  // past 32 take the chunked response path): one-env-per-wavefront types dispatch their envs in order of
+  // the rows of their previous step, most first, so that the likely slow ones start in the first round of
+  // workgroups.  The order changes no result: every env is computed on its own.
+  a.env_rows = S->env_rows;
   for (TypeDev& T : S->types) {
     a.ty = type_args(T);
+    if (T.step_order) a.ty.env_list = T.step_order;
     hipError_t e = launch_step(a, T.n_envs, p.compute_fp64, T.team, (hipStream_t)stream);
+    if (e == hipSuccess && T.step_order)
+      e = launch_order_by_rows(T.step_order, T.order_tmp, S->env_rows, T.n_envs, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "step: launch");
   }
   return AGS_OK;

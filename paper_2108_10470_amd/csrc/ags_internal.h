@@ -99,6 +99,7 @@ struct StepArgs {
   float* rb_state;  // optional (N_B, 13): link origin, quaternion, origin velocity, angular velocity
   int* env_status;  // optional (E): bit 0 non-finite new state, bit 1 row-response slow path taken
   int* big_rows;    // optional (E): 1 where a substep had more than kAdjBigRowsAt rows (adjoint layout hint)
+  int* env_rows;    // optional (E): the most rows of a substep of the step (dispatch order of the next step)
   // optional per-env properties replacing the model's: link mass / inertia factor (N_B), drive kp, kd (N_D),
   // limits (N_D x 2), friction (E), gravity (E x 3)
   const float* mass_scale;
@@ -196,6 +197,8 @@ hipError_t launch_fill_int(int* p, int n, int value, hipStream_t stream);
 hipError_t launch_scale_by_kp(float* x, const float* kp, int n, hipStream_t stream);
 
 hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStream_t stream);
+// reorders the env ids order[0, n) by rows[env], most first (tmp: n ints)
+hipError_t launch_order_by_rows(int* order, int* tmp, const int* rows, int n, hipStream_t stream);
 hipError_t set_lds_limit(int fp64, int team, size_t bytes);
 hipError_t launch_set_rows(float* dst, const float* src, const int* idx, int n, int n_actors, const int* table,
                            int field, int width, hipStream_t stream);

@@ -1636,6 +1636,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
   }
 
   if (P.big_rows && valid && tt == 0) P.big_rows[env] = rows_max > kAdjBigRowsAt ? 1 : 0;
+  if (P.env_rows && valid && tt == 0) P.env_rows[env] = rows_max;
 
   // ---------------------------------------------------------------- write back
   if (!valid) return;
@@ -1733,6 +1734,41 @@ template <bool TGS, bool CYC = false>
 static const void* step_fn(int fp64, int team) {
   return fp64 ? (team == 32 ? (const void*)step_kernel<double, 32, TGS, CYC> : (const void*)step_kernel<double, 64, TGS, CYC>)
               : (team == 32 ? (const void*)step_kernel<float, 32, TGS, CYC> : (const void*)step_kernel<float, 64, TGS, CYC>);
+}
+
+// Counting sort of the env ids of one type by the rows of their last step, most rows first (rows of
+// kOrderBuckets - 1 or more share the first bucket).  One workgroup; the order within a bucket is whichever
+// the LDS atomics give, which no result depends on.
+constexpr int kOrderBuckets = 128;
+__global__ __launch_bounds__(1024) void order_by_rows_kernel(int* order, int* tmp, const int* rows, int n) {
+  __shared__ int start[kOrderBuckets];
+  const int t = threadIdx.x;
+  auto bucket = [&](int e) { return kOrderBuckets - 1 - min(max(rows[e], 0), kOrderBuckets - 1); };
+  if (t < kOrderBuckets) start[t] = 0;
+  __syncthreads();
+  for (int i = t; i < n; i += blockDim.x) atomicAdd(&start[bucket(order[i])], 1);
+  __syncthreads();
+  if (t == 0) {
+    int run = 0;
+    for (int b = 0; b < kOrderBuckets; ++b) {
+      const int c = start[b];
+      start[b] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += blockDim.x) {
+    const int e = order[i];
+    tmp[atomicAdd(&start[bucket(e)], 1)] = e;
+  }
+  __syncthreads();
+  for (int i = t; i < n; i += blockDim.x) order[i] = tmp[i];
+}
+
+hipError_t launch_order_by_rows(int* order, int* tmp, const int* rows, int n, hipStream_t stream) {
+  if (n <= 1) return hipSuccess;
+  hipLaunchKernelGGL(order_by_rows_kernel, dim3(1), dim3(1024), 0, stream, order, tmp, rows, n);
+  return hipGetLastError();
 }
 
 hipError_t launch_step(const StepArgs& a, int n_envs, int fp64, int team, hipStream_t stream) {
