@@ -156,6 +156,13 @@ __device__ __forceinline__ R si_at(const SI<R>& I, int r, int c) {
   if (c < 3) return I.B[3 * c + (r - 3)];
   return I.M[sidx[3 * (r - 3) + (c - 3)]];
 }
+// stored index of entry (m, n) of a spatial inertia [A B; B^T M] in the 21-word layout
+__device__ __forceinline__ int si_index(int m, int n) {
+  const int lo = min(m, n), hi = max(m, n);
+  if (hi < 3) return lo == hi ? lo : lo + hi + 2;              // A: xx yy zz xy xz yz
+  if (lo >= 3) return lo == hi ? 12 + lo : 15 + lo + hi - 4;  // M: xx yy zz xy xz yz
+  return 6 + 3 * lo + (hi - 3);                                // B row-major (B^T entries read B)
+}
 // Move an inertia from point Q to point P = Q - r (translation only): I_P = X^T I_Q X with
 // X = [1 0; -r^ 1].  Then M' = M, B' = B + r^ M, A' = A - B r^ + r^ B'^T.
 template <typename R>
@@ -861,78 +868,205 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 
     PHASE_MARK(2);
     // ---------------------------------------------------- ABA inward sweep (deepest level first)
-    for (int d = M.n_levels - 1; d >= 0; --d) {
-      for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
-        const int i = M.level_links[idx];
-        const int* li = M.li + i * LI_COLS;
-        const int jt = li[LI_JTYPE];
-        if (jt == J_FIXED) continue;
-        SI<R> I;
-        si_load(I, s.IA + 21 * i);
-        V3<R> pn = ld3<R>(s.pA + 6 * i), pf = ld3<R>(s.pA + 6 * i + 3);
-        for (int q = li[LI_CHILD_BEGIN]; q < li[LI_CHILD_END]; ++q) {  // children hold I^a, p^a moved to o_i
-          const int ch = M.children[q];
-          si_addload(I, s.IA + 21 * ch);
-          pn = add(pn, ld3<R>(s.pA + 6 * ch));
-          pf = add(pf, ld3<R>(s.pA + 6 * ch + 3));
+    if constexpr (TEAM == 64) {
+      // Up to three links of a level at a time, 21 lanes each, one per stored entry of the 6x6 articulated
+      // inertia (A: xx yy zz xy xz yz, B row-major, M: xx yy zz xy xz yz).  Per link: (1) every entry lane adds
+      // the children's entry (lanes 0-5 also the bias force), (2) every lane of the link forms U = I^A S, D,
+      // 1/D, u and the articulated bias force moved to the parent's origin (its lane 0 stores them), (3) every
+      // entry lane forms its entry of X^T (I^A - U U^T / D) X, X moving the inertia from o_i to o_parent, from
+      // the nine entries of I^A it combines.  The per-link work of one lane shrinks from the whole 6x6 update
+      // and move to its own entry.
+      const int slot = tt / 21, el = tt - 21 * slot;
+      int ep, eq;  // the lane's entry (ep, eq)
+      if (el < 6) {
+        ep = el < 3 ? el : (el == 5 ? 1 : 0);
+        eq = el < 3 ? el : (el == 3 ? 1 : 2);
+      } else if (el < 15) {
+        ep = (el - 6) / 3;
+        eq = 3 + (el - 6) % 3;
+      } else {
+        const int k = el - 15;
+        ep = 3 + (k < 3 ? k : (k == 5 ? 1 : 0));
+        eq = 3 + (k < 3 ? k : (k == 3 ? 1 : 2));
+      }
+      // rows of X in column p: p itself and, for an angular p, the linear rows 3 + (p+1)%3 (coefficient
+      // -r[(p+2)%3]) and 3 + (p+2)%3 (coefficient r[(p+1)%3])
+      const int mr[3] = {ep, ep < 3 ? 3 + (ep + 1) % 3 : ep, ep < 3 ? 3 + (ep + 2) % 3 : ep};
+      const int nc[3] = {eq, eq < 3 ? 3 + (eq + 1) % 3 : eq, eq < 3 ? 3 + (eq + 2) % 3 : eq};
+      for (int d = M.n_levels - 1; d >= 0; --d) {
+        const int lb = M.level_begin[d], le = M.level_begin[d + 1];
+        for (int b0 = lb; b0 < le; b0 += 3) {
+          const int idx = b0 + slot;
+          const bool act = slot < 3 && idx < le;
+          const int i = act ? M.level_links[idx] : 0;
+          const int* li = M.li + i * LI_COLS;
+          const int jt = act ? li[LI_JTYPE] : J_FIXED;
+          if (jt != J_FIXED) {  // (1) children hold I^a, p^a moved to o_i
+            R a = s.IA[21 * i + el];
+            R pa = el < 6 ? s.pA[6 * i + el] : R(0);
+            for (int q = li[LI_CHILD_BEGIN]; q < li[LI_CHILD_END]; ++q) {
+              const int ch = M.children[q];
+              a += s.IA[21 * ch + el];
+              if (el < 6) pa += s.pA[6 * ch + el];
+            }
+            s.IA[21 * i + el] = a;
+            if (el < 6) s.pA[6 * i + el] = pa;
+          }
+          __syncthreads();
+          if (jt == J_FREE && el == 0) {
+            SI<R> I;
+            si_load(I, s.IA + 21 * i);
+            const int a = actor_of_root(M, i);
+            chol6(I, s.L0 + 27 * a, s.L0 + 27 * a + 21);
+          }
+          const bool one = jt == J_REV || jt == J_PRI;  // a one-DOF joint
+          R Dinv = R(0);
+          V3<R> r = mk(R(0), R(0), R(0));
+          if (one) {  // (2)
+            SI<R> I;
+            si_load(I, s.IA + 21 * i);
+            const V3<R> pn = ld3<R>(s.pA + 6 * i), pf = ld3<R>(s.pA + 6 * i + 3);
+            const int c = li[LI_COL];
+            const V3<R> ax = ld3<R>(s.ax + 3 * i);
+            V3<R> Ua, Ul;
+            R D, u;
+            if (jt == J_REV) {
+              Ua = symv(I.A, ax);
+              Ul = mtv(I.B, ax);
+              D = dot(ax, Ua);
+              u = s.tau[c] - dot(ax, pn);
+            } else {
+              Ua = mv(I.B, ax);
+              Ul = symv(I.M, ax);
+              D = dot(ax, Ul);
+              u = s.tau[c] - dot(ax, pf);
+            }
+            D += s.arm[c];
+            Dinv = R(1) / D;
+            // p^a = p^A + I^a c + U u / D = p^A + I^A c + U (u - U . c) / D, then moved to the parent's origin
+            V3<R> ca, cl, ia, il;
+            vel_product(s, i, jt, ax, s.qd[c], ca, cl);
+            si_mul(I, ca, cl, ia, il);
+            const R g = (u - dot(Ua, ca) - dot(Ul, cl)) * Dinv;
+            const V3<R> pfa = add(add(pf, il), mul(Ul, g));
+            r = sub(ld3<R>(s.o + 3 * i), ld3<R>(s.o + 3 * li[LI_PARENT]));
+            const V3<R> pna = add(add(add(pn, ia), mul(Ua, g)), cross(r, pfa));
+            if (el == 0) {
+              st3(s.pA + 6 * i, pna);
+              st3(s.pA + 6 * i + 3, pfa);
+              st3(s.U + 6 * i, Ua);
+              st3(s.U + 6 * i + 3, Ul);
+              s.Dinv[i] = Dinv;
+              s.u[i] = u;
+            }
+          }
+          __syncthreads();
+          R val = R(0);
+          if (one) {  // (3)
+            // all fifteen reads first, then the arithmetic
+            R um[3], un[3], ia[9];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              um[a] = s.U[6 * i + mr[a]];
+              un[a] = s.U[6 * i + nc[a]];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+              for (int b = 0; b < 3; ++b) ia[3 * a + b] = s.IA[21 * i + si_index(mr[a], nc[b])];
+            // coefficients: -r[(p+2)%3] and r[(p+1)%3] for an angular p, by selects on p
+            const R rp1 = ep == 0 ? r.z : (ep == 1 ? r.x : r.y), rp2 = ep == 0 ? r.y : (ep == 1 ? r.z : r.x);
+            const R rq1 = eq == 0 ? r.z : (eq == 1 ? r.x : r.y), rq2 = eq == 0 ? r.y : (eq == 1 ? r.z : r.x);
+            const R xp[3] = {R(1), ep < 3 ? -rp1 : R(0), ep < 3 ? rp2 : R(0)};
+            const R xq[3] = {R(1), eq < 3 ? -rq1 : R(0), eq < 3 ? rq2 : R(0)};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+              R acc = R(0);
+#pragma unroll
+              for (int b = 0; b < 3; ++b) acc += xq[b] * (ia[3 * a + b] - um[a] * un[b] * Dinv);
+              val += xp[a] * acc;
+            }
+          }
+          __syncthreads();
+          if (one) s.IA[21 * i + el] = val;
+          __syncthreads();
         }
-        if (jt == J_FREE) {
+      }
+    } else {
+      for (int d = M.n_levels - 1; d >= 0; --d) {
+        for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
+          const int i = M.level_links[idx];
+          const int* li = M.li + i * LI_COLS;
+          const int jt = li[LI_JTYPE];
+          if (jt == J_FIXED) continue;
+          SI<R> I;
+          si_load(I, s.IA + 21 * i);
+          V3<R> pn = ld3<R>(s.pA + 6 * i), pf = ld3<R>(s.pA + 6 * i + 3);
+          for (int q = li[LI_CHILD_BEGIN]; q < li[LI_CHILD_END]; ++q) {  // children hold I^a, p^a moved to o_i
+            const int ch = M.children[q];
+            si_addload(I, s.IA + 21 * ch);
+            pn = add(pn, ld3<R>(s.pA + 6 * ch));
+            pf = add(pf, ld3<R>(s.pA + 6 * ch + 3));
+          }
+          if (jt == J_FREE) {
+            st3(s.pA + 6 * i, pn);
+            st3(s.pA + 6 * i + 3, pf);
+            const int a = actor_of_root(M, i);
+            chol6(I, s.L0 + 27 * a, s.L0 + 27 * a + 21);
+            continue;
+          }
+          const int c = li[LI_COL];
+          const V3<R> ax = ld3<R>(s.ax + 3 * i);
+          V3<R> Ua, Ul;
+          R D, u;
+          if (jt == J_REV) {
+            Ua = symv(I.A, ax);
+            Ul = mtv(I.B, ax);
+            D = dot(ax, Ua);
+            u = s.tau[c] - dot(ax, pn);
+          } else {
+            Ua = mv(I.B, ax);
+            Ul = symv(I.M, ax);
+            D = dot(ax, Ul);
+            u = s.tau[c] - dot(ax, pf);
+          }
+          D += s.arm[c];
+          const R Dinv = R(1) / D;
+          // I^a = I^A - U U^T / D
+          I.A[0] -= Ua.x * Ua.x * Dinv; I.A[1] -= Ua.y * Ua.y * Dinv; I.A[2] -= Ua.z * Ua.z * Dinv;
+          I.A[3] -= Ua.x * Ua.y * Dinv; I.A[4] -= Ua.x * Ua.z * Dinv; I.A[5] -= Ua.y * Ua.z * Dinv;
+          I.M[0] -= Ul.x * Ul.x * Dinv; I.M[1] -= Ul.y * Ul.y * Dinv; I.M[2] -= Ul.z * Ul.z * Dinv;
+          I.M[3] -= Ul.x * Ul.y * Dinv; I.M[4] -= Ul.x * Ul.z * Dinv; I.M[5] -= Ul.y * Ul.z * Dinv;
+          const R ua[3] = {Ua.x, Ua.y, Ua.z}, ul[3] = {Ul.x, Ul.y, Ul.z};
+  #pragma unroll
+          for (int a = 0; a < 3; ++a)
+  #pragma unroll
+            for (int b = 0; b < 3; ++b) I.B[3 * a + b] -= ua[a] * ul[b] * Dinv;
+          // p^a = p^A + I^a c + U u / D
+          V3<R> ca, cl, ia, il;
+          vel_product(s, i, jt, ax, s.qd[c], ca, cl);
+          si_mul(I, ca, cl, ia, il);
+          const R ud = u * Dinv;
+          pn = add(add(pn, ia), mul(Ua, ud));
+          pf = add(add(pf, il), mul(Ul, ud));
+          // move to the parent's point (nothing to move for a joint anchored at its parent's origin, such as the
+          // massless links of per-axis joint chains)
+          const V3<R> r = sub(ld3<R>(s.o + 3 * i), ld3<R>(s.o + 3 * li[LI_PARENT]));
+          if (r.x != R(0) || r.y != R(0) || r.z != R(0)) {
+            si_shift(I, r);
+            pn = add(pn, cross(r, pf));
+          }
+          si_store(I, s.IA + 21 * i);
           st3(s.pA + 6 * i, pn);
           st3(s.pA + 6 * i + 3, pf);
-          const int a = actor_of_root(M, i);
-          chol6(I, s.L0 + 27 * a, s.L0 + 27 * a + 21);
-          continue;
+          st3(s.U + 6 * i, Ua);
+          st3(s.U + 6 * i + 3, Ul);
+          s.Dinv[i] = Dinv;
+          s.u[i] = u;
         }
-        const int c = li[LI_COL];
-        const V3<R> ax = ld3<R>(s.ax + 3 * i);
-        V3<R> Ua, Ul;
-        R D, u;
-        if (jt == J_REV) {
-          Ua = symv(I.A, ax);
-          Ul = mtv(I.B, ax);
-          D = dot(ax, Ua);
-          u = s.tau[c] - dot(ax, pn);
-        } else {
-          Ua = mv(I.B, ax);
-          Ul = symv(I.M, ax);
-          D = dot(ax, Ul);
-          u = s.tau[c] - dot(ax, pf);
-        }
-        D += s.arm[c];
-        const R Dinv = R(1) / D;
-        // I^a = I^A - U U^T / D
-        I.A[0] -= Ua.x * Ua.x * Dinv; I.A[1] -= Ua.y * Ua.y * Dinv; I.A[2] -= Ua.z * Ua.z * Dinv;
-        I.A[3] -= Ua.x * Ua.y * Dinv; I.A[4] -= Ua.x * Ua.z * Dinv; I.A[5] -= Ua.y * Ua.z * Dinv;
-        I.M[0] -= Ul.x * Ul.x * Dinv; I.M[1] -= Ul.y * Ul.y * Dinv; I.M[2] -= Ul.z * Ul.z * Dinv;
-        I.M[3] -= Ul.x * Ul.y * Dinv; I.M[4] -= Ul.x * Ul.z * Dinv; I.M[5] -= Ul.y * Ul.z * Dinv;
-        const R ua[3] = {Ua.x, Ua.y, Ua.z}, ul[3] = {Ul.x, Ul.y, Ul.z};
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 3; ++b) I.B[3 * a + b] -= ua[a] * ul[b] * Dinv;
-        // p^a = p^A + I^a c + U u / D
-        V3<R> ca, cl, ia, il;
-        vel_product(s, i, jt, ax, s.qd[c], ca, cl);
-        si_mul(I, ca, cl, ia, il);
-        const R ud = u * Dinv;
-        pn = add(add(pn, ia), mul(Ua, ud));
-        pf = add(add(pf, il), mul(Ul, ud));
-        // move to the parent's point (nothing to move for a joint anchored at its parent's origin, such as the
-        // massless links of per-axis joint chains)
-        const V3<R> r = sub(ld3<R>(s.o + 3 * i), ld3<R>(s.o + 3 * li[LI_PARENT]));
-        if (r.x != R(0) || r.y != R(0) || r.z != R(0)) {
-          si_shift(I, r);
-          pn = add(pn, cross(r, pf));
-        }
-        si_store(I, s.IA + 21 * i);
-        st3(s.pA + 6 * i, pn);
-        st3(s.pA + 6 * i + 3, pf);
-        st3(s.U + 6 * i, Ua);
-        st3(s.U + 6 * i + 3, Ul);
-        s.Dinv[i] = Dinv;
-        s.u[i] = u;
+        __syncthreads();
       }
-      __syncthreads();
+
     }
 
     PHASE_MARK(3);
