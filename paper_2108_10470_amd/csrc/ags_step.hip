@@ -464,6 +464,39 @@ __device__ __forceinline__ void quat_R(const P& q, R* M) {
 // orientation (quaternion), origin and velocity and the joint's own position and rate: rotation Rw and
 // quaternion qq (xyzw), joint origin o, world joint axis ax (zero at a root), angular velocity w and
 // velocity vl of the point o.
+// Joint-local parts of every link's pose, which need only the link's own joint coordinate: the joint's
+// rotation as a quaternion (axis sin(q/2), cos(q/2); identity for a prismatic joint) into q, the joint anchor
+// in the parent frame (moved along the axis by a prismatic coordinate) into o, the local axis into ax.  The
+// level-by-level sweep then only composes them with the parent's pose, and the sines and cosines of all
+// joints are taken at once instead of one tree level after the other.
+template <typename R, int EPW, int TEAM>
+__device__ __forceinline__ void stage_joint_locals(const Tab<R>& M, const Ctx<R, EPW>& s, int tt) {
+  for (int i = tt; i < M.n_links; i += TEAM) {
+    const int* li = M.li + i * LI_COLS;
+    const int jt = li[LI_JTYPE];
+    if (jt != J_REV && jt != J_PRI) continue;
+    const double* lf = M.lf + i * LF_COLS;
+    const V3<R> axl = ld3<R>(lf + LF_AXIS);
+    V3<R> tl = ld3<R>(lf + LF_ANCHOR);
+    const R q = s.qj[li[LI_DOF]];
+    R lq[4] = {R(0), R(0), R(0), R(1)};
+    if (jt == J_REV) {
+      R sh, ch;
+      sincos_(R(0.5) * q, &sh, &ch);
+      lq[0] = axl.x * sh;
+      lq[1] = axl.y * sh;
+      lq[2] = axl.z * sh;
+      lq[3] = ch;
+    } else {
+      tl = add(tl, mul(axl, q));
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s.q[4 * i + k] = lq[k];
+    st3(s.o + 3 * i, tl);
+    st3(s.ax + 3 * i, axl);
+  }
+}
+
 template <typename R, int EPW>
 __device__ __forceinline__ void link_kinematics(const Tab<R>& M, const Ctx<R, EPW>& s, int i, V3<R> origin, R* Rw,
                                                 R* qq, V3<R>& o, V3<R>& w, V3<R>& vl, V3<R>& ax) {
@@ -488,20 +521,18 @@ __device__ __forceinline__ void link_kinematics(const Tab<R>& M, const Ctx<R, EP
     }
     return;
   }
-  const double* lf = M.lf + i * LF_COLS;
+  // the joint's local rotation, anchor and axis, staged by stage_joint_locals
   const int p = li[LI_PARENT];
   const auto qp = s.q + 4 * p;
   const R px = qp[0], py = qp[1], pz = qp[2], pw = qp[3];
   R Rp[9];
   quat_R(px, py, pz, pw, Rp);
-  const V3<R> axl = ld3<R>(lf + LF_AXIS);
-  V3<R> tl = ld3<R>(lf + LF_ANCHOR);
-  const R q = s.qj[li[LI_DOF]], qd = s.qd[li[LI_COL]];
+  const V3<R> axl = ld3<R>(s.ax + 3 * i);
+  const V3<R> tl = ld3<R>(s.o + 3 * i);
+  const R rx = s.q[4 * i], ry = s.q[4 * i + 1], rz = s.q[4 * i + 2], ch = s.q[4 * i + 3];
+  const R qd = s.qd[li[LI_COL]];
   if (jt == J_REV) {
     // parent orientation composed with the joint rotation (angle q about the local axis)
-    R sh, ch;
-    sincos_(R(0.5) * q, &sh, &ch);
-    const R rx = axl.x * sh, ry = axl.y * sh, rz = axl.z * sh;
     qq[0] = pw * rx + ch * px + (py * rz - pz * ry);
     qq[1] = pw * ry + ch * py + (pz * rx - px * rz);
     qq[2] = pw * rz + ch * pz + (px * ry - py * rx);
@@ -511,7 +542,6 @@ __device__ __forceinline__ void link_kinematics(const Tab<R>& M, const Ctx<R, EP
     qq[0] = px; qq[1] = py; qq[2] = pz; qq[3] = pw;
 #pragma unroll
     for (int k = 0; k < 9; ++k) Rw[k] = Rp[k];
-    tl = add(tl, mul(axl, q));
   }
   ax = mv(Rp, axl);
   const V3<R> op = ld3<R>(s.o + 3 * p);
@@ -804,6 +834,8 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
     // Poses and velocities chain from parent to child, level by level; the spatial inertia and bias force
     // of each link need only its own pose and velocity, so they are formed afterwards for all links at
     // once (lanes over links) instead of by the one or two lanes a level occupies.
+    stage_joint_locals<R, EPW, TEAM>(M, s, tt);
+    __syncthreads();
     for (int d = 0; d < M.n_levels; ++d) {
       for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
@@ -1367,14 +1399,14 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
           x = ld3<R>(s.x + 3 * ref);
           ka = M.si[ref * SI_COLS + SI_LINK_A];
           kb = M.si[ref * SI_COLS + SI_LINK_B];
+          unit_load_inward(M, s, ka, mul(cross(sub(x, ld3<R>(s.o + 3 * ka)), dd), R(-1)), mul(dd, R(-1)), R(0), Wrow);
+          if (kb >= 0) unit_load_inward(M, s, kb, cross(sub(x, ld3<R>(s.o + 3 * kb)), dd), dd, R(0), Wrow);
           if (jreg) {
             jrow_point(M, s, ka, kb, x, dd, jr);
           } else if (!wide) {
             point_row(M, s, ka, x, dd, R(1), JrowG, Wrow, true, false);
             if (kb >= 0) point_row(M, s, kb, x, dd, R(-1), JrowG, Wrow, true, false);
           }
-          unit_load_inward(M, s, ka, mul(cross(sub(x, ld3<R>(s.o + 3 * ka)), dd), R(-1)), mul(dd, R(-1)), R(0), Wrow);
-          if (kb >= 0) unit_load_inward(M, s, kb, cross(sub(x, ld3<R>(s.o + 3 * kb)), dd), dd, R(0), Wrow);
         }
         // roots: a = -(I^A_root)^-1 (accumulated bias force); generalized root columns are (v_com, w)
         for (int k = 0; k < na; ++k) {
@@ -1397,25 +1429,36 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         for (int d = 1; d < M.n_levels; ++d) {
           const int b = M.level_begin[d], n_at = M.level_begin[d + 1] - b;
           const int pairs = rows_here * n_at;
+          const float inv_at = __builtin_amdgcn_rcpf(float(n_at));  // within an ulp: the rounding below has margin
           for (int pi = tt; pi < pairs; pi += TEAM) {
-            const int q_ = pi / n_at;
+            // row and link of the pair without an integer division ((pi + 1/2) / n_at is at least 1/(2 n_at) from
+            // an integer, far above the rounding of the product for pi < 2^16)
+            const int q_ = int((float(pi) + 0.5f) * inv_at);
             const int i = M.level_links[b + pi - q_ * n_at];
+            // the link's record, then every operand read before the arithmetic and no branch on the link
+            // (past level 0 every link has a one-DOF joint; entries past the last ancestor read the last one
+            // again and add zero)
             const int* li = M.li + i * LI_COLS;
-            const int jt = li[LI_JTYPE];
-            if (jt == J_FREE || jt == J_FIXED) continue;
+            const int rc = li[LI_ROOTCOL], qb = li[LI_ANC_BEGIN], qe = li[LI_ANC_END], c = li[LI_COL];
             const auto Wq = s.W + q_ * L.wstride;
-            R acc = R(0);
-            const int rc = li[LI_ROOTCOL];
-            if (rc >= 0) {
-              const auto ub = s.Ubar + 3 * i;
-              const auto ul = s.U + 6 * i + 3;
-              acc = ub[0] * Wq[rc + 3] + ub[1] * Wq[rc + 4] + ub[2] * Wq[rc + 5] + ul[0] * Wq[rc + 0] +
-                    ul[1] * Wq[rc + 1] + ul[2] * Wq[rc + 2];
+            const int rcs = max(rc, 0);
+            const V3<R> ub = ld3<R>(s.Ubar + 3 * i), ul = ld3<R>(s.U + 6 * i + 3);
+            const R w0 = Wq[rcs + 0], w1 = Wq[rcs + 1], w2 = Wq[rcs + 2], w3 = Wq[rcs + 3], w4 = Wq[rcs + 4],
+                    w5 = Wq[rcs + 5];
+            const R wc = Wq[c], dinv = s.Dinv[i];
+            R acc = rc >= 0 ? ub.x * w3 + ub.y * w4 + ub.z * w5 + ul.x * w0 + ul.y * w1 + ul.z * w2 : R(0);
+            for (int q0 = qb; q0 < qe; q0 += 8) {
+              R g[8], wv[8];
+#pragma unroll
+              for (int k = 0; k < 8; ++k) {
+                const int q = min(q0 + k, qe - 1);
+                g[k] = s.G[q];
+                wv[k] = Wq[M.anc_link[q] >> 16];
+              }
+#pragma unroll
+              for (int k = 0; k < 8; ++k) acc += (q0 + k < qe ? g[k] : R(0)) * wv[k];
             }
-            for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q)
-              acc += s.G[q] * Wq[M.anc_link[q] >> 16];
-            const int c = li[LI_COL];
-            Wq[c] = (Wq[c] - acc) * s.Dinv[i];
+            Wq[c] = (wc - acc) * dinv;
           }
           __syncthreads();
         }
@@ -1733,6 +1776,8 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 
   // ---------------------------------------------------------------- rigid-body states of the new state
   if (P.rb_state) {
+    stage_joint_locals<R, EPW, TEAM>(M, s, tt);
+    __syncthreads();
     for (int d = 0; d < M.n_levels; ++d) {
       for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
