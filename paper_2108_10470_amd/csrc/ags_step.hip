@@ -499,11 +499,12 @@ __device__ __forceinline__ void stage_joint_locals(const Tab<R>& M, const Ctx<R,
 
 template <typename R, int EPW>
 __device__ __forceinline__ void link_kinematics(const Tab<R>& M, const Ctx<R, EPW>& s, int i, V3<R> origin, R* Rw,
-                                                R* qq, V3<R>& o, V3<R>& w, V3<R>& vl, V3<R>& ax) {
+                                                R* qq, V3<R>& o, V3<R>& w, V3<R>& vl, V3<R>& ax, bool root_level) {
+  // root_level: the links of tree level 0, the roots; every deeper link has a one-DOF joint
   const int* li = M.li + i * LI_COLS;
   const int jt = li[LI_JTYPE];
   ax = mk(R(0), R(0), R(0));
-  if (jt == J_FREE || jt == J_FIXED) {
+  if (root_level) {
     // root pose from the root state (quaternion xyzw, normalised on read)
     const auto rs = s.root + 13 * actor_of_root(M, i);
     const R qx = rs[3], qy = rs[4], qz = rs[5], qw = rs[6];
@@ -657,18 +658,19 @@ __device__ __forceinline__ void jrow_clear(JRow<R>& J) {
 // sum_j J_j w_j
 template <typename R, typename WP>
 __device__ __forceinline__ R jrow_dot(const JRow<R>& J, const WP& w) {
-  R acc = R(0);
+  // two partial sums: a chain of 11 fused multiply-adds instead of 22
+  R a[2] = {R(0), R(0)};
 #pragma unroll
-  for (int e = 0; e < kJointEntries; ++e) acc += J.val[e] * w[J.c[e]];
+  for (int e = 0; e < kJointEntries; ++e) a[e & 1] += J.val[e] * w[J.c[e]];
   if (J.ra >= 0) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) acc += J.ja[q] * w[J.ra + q];
+    for (int q = 0; q < 6; ++q) a[q & 1] += J.ja[q] * w[J.ra + q];
   }
   if (J.rb >= 0) {
 #pragma unroll
-    for (int q = 0; q < 6; ++q) acc += J.jb[q] * w[J.rb + q];
+    for (int q = 0; q < 6; ++q) a[(q + 1) & 1] += J.jb[q] * w[J.rb + q];
   }
-  return acc;
+  return a[0] + a[1];
 }
 
 // root part of a point load along d at x on the articulation of link k: sign (d, (x - o_root) x d)
@@ -841,7 +843,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         const int i = M.level_links[idx];
         R Rw[9], qq[4];
         V3<R> o, w, vl, ax;
-        link_kinematics(M, s, i, origin, Rw, qq, o, w, vl, ax);
+        link_kinematics(M, s, i, origin, Rw, qq, o, w, vl, ax, d == 0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) s.q[4 * i + k] = qq[k];
         st3(s.o + 3 * i, o);
@@ -1103,41 +1105,48 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 
     PHASE_MARK(3);
     // ---------------------------------------------------- root solve and ABA outward sweep
-    // link accelerations overwrite the (consumed) bias forces: a_i lives in pA_i
+    // link accelerations overwrite the (consumed) bias forces: a_i lives in pA_i.  Level 0 holds the roots
+    // and every deeper link has a one-DOF joint, so the deeper levels read all their operands at once and
+    // do not branch on the joint type.
     for (int d = 0; d < M.n_levels; ++d) {
       for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
         const int* li = M.li + i * LI_COLS;
-        const int jt = li[LI_JTYPE];
         V3<R> aa, al;
-        if (jt == J_FIXED) {
+        if (d == 0) {
+          const int jt = li[LI_JTYPE];
           aa = mk(R(0), R(0), R(0));
           al = aa;
-        } else if (jt == J_FREE) {
-          const int a = actor_of_root(M, i);
-          R x[6];
+          if (jt == J_FREE) {
+            const int a = actor_of_root(M, i);
+            R x[6];
 #pragma unroll
-          for (int q = 0; q < 6; ++q) x[q] = -s.pA[6 * i + q];
-          chol6_solve(s.L0 + 27 * a, s.L0 + 27 * a + 21, x);
-          aa = mk(x[0], x[1], x[2]);
-          al = mk(x[3], x[4], x[5]);
-          // classical acceleration of the centre of mass: a_lin + w x v_com
-          const int c = li[LI_ROOTCOL];
-          st3(s.vs + c, add(al, cross(ld3<R>(s.qd + c + 3), ld3<R>(s.qd + c))));
-          st3(s.vs + c + 3, aa);
+            for (int q = 0; q < 6; ++q) x[q] = -s.pA[6 * i + q];
+            chol6_solve(s.L0 + 27 * a, s.L0 + 27 * a + 21, x);
+            aa = mk(x[0], x[1], x[2]);
+            al = mk(x[3], x[4], x[5]);
+            // classical acceleration of the centre of mass: a_lin + w x v_com
+            const int c = li[LI_ROOTCOL];
+            st3(s.vs + c, add(al, cross(ld3<R>(s.qd + c + 3), ld3<R>(s.qd + c))));
+            st3(s.vs + c + 3, aa);
+          }
         } else {
-          const int p = li[LI_PARENT];
-          const int c = li[LI_COL];
+          const int jt = li[LI_JTYPE], p = li[LI_PARENT], c = li[LI_COL];
+          const bool rev = jt == J_REV;
           const V3<R> r = sub(ld3<R>(s.o + 3 * i), ld3<R>(s.o + 3 * p));
           const V3<R> ax = ld3<R>(s.ax + 3 * i);
-          V3<R> ca, cl;
-          vel_product(s, i, jt, ax, s.qd[c], ca, cl);
-          aa = ld3<R>(s.pA + 6 * p);
-          al = add(ld3<R>(s.pA + 6 * p + 3), cross(aa, r));
-          aa = add(aa, ca);
-          al = add(al, cl);
-          const R qdd = (s.u[i] - dot(ld3<R>(s.U + 6 * i), aa) - dot(ld3<R>(s.U + 6 * i + 3), al)) * s.Dinv[i];
-          if (jt == J_REV) aa = add(aa, mul(ax, qdd));
+          const V3<R> w = ld3<R>(s.v + 6 * i), vl = ld3<R>(s.v + 6 * i + 3);
+          const R qd = s.qd[c];
+          const V3<R> pa = ld3<R>(s.pA + 6 * p), pl = ld3<R>(s.pA + 6 * p + 3);
+          const V3<R> Ua = ld3<R>(s.U + 6 * i), Ul = ld3<R>(s.U + 6 * i + 3);
+          const R ui = s.u[i], dinv = s.Dinv[i];
+          // velocity product: revolute ((w x s) qd, (v x s) qd), prismatic (0, (w x s) qd)
+          const V3<R> wxs = mul(cross(w, ax), qd), vxs = mul(cross(vl, ax), qd);
+          const V3<R> ca = rev ? wxs : mk(R(0), R(0), R(0)), cl = rev ? vxs : wxs;
+          aa = add(pa, ca);
+          al = add(add(pl, cross(pa, r)), cl);
+          const R qdd = (ui - dot(Ua, aa) - dot(Ul, al)) * dinv;
+          if (rev) aa = add(aa, mul(ax, qdd));
           else al = add(al, mul(ax, qdd));
           s.vs[c] = qdd;
         }
@@ -1166,33 +1175,47 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
       const V3<R> oi = ld3<R>(s.o + 3 * i);
       const V3<R> Ua = ld3<R>(s.U + 6 * i), Ul = ld3<R>(s.U + 6 * i + 3);
       st3(s.Ubar + 3 * i, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * li[LI_ROOT])), Ul)));
-      for (int q = li[LI_ANC_BEGIN]; q < li[LI_ANC_END]; ++q) {
-        const int k = M.anc_link[q] & 0xffff;
-        const V3<R> ak = ld3<R>(s.ax + 3 * k);
-        s.G[q] = M.li[k * LI_COLS + LI_JTYPE] == J_REV ? dot(ak, add(Ua, cross(sub(oi, ld3<R>(s.o + 3 * k)), Ul)))
-                                                      : dot(ak, Ul);
+      // four ancestors at a time, their reads issued together (entries past the last one recompute the
+      // last one's value)
+      const int qb = li[LI_ANC_BEGIN], qe = li[LI_ANC_END];
+      for (int q0 = qb; q0 < qe; q0 += 4) {
+        R gv[4];
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4) {
+          const int k = M.anc_link[min(q0 + k4, qe - 1)] & 0xffff;
+          const V3<R> ak = ld3<R>(s.ax + 3 * k);
+          const V3<R> ok = ld3<R>(s.o + 3 * k);
+          const bool rev = M.li[k * LI_COLS + LI_JTYPE] == J_REV;
+          gv[k4] = rev ? dot(ak, add(Ua, cross(sub(oi, ok), Ul))) : dot(ak, Ul);
+        }
+#pragma unroll
+        for (int k4 = 0; k4 < 4; ++k4)
+          if (q0 + k4 < qe) s.G[q0 + k4] = gv[k4];
       }
     }
+    // velocities under v*: roots at level 0, one-DOF joints below (operands read at once, no branch on the
+    // joint type)
     for (int d = 0; d < M.n_levels; ++d) {
       for (int idx = M.level_begin[d] + tt; idx < M.level_begin[d + 1]; idx += TEAM) {
         const int i = M.level_links[idx];
         const int* li = M.li + i * LI_COLS;
-        const int jt = li[LI_JTYPE];
         V3<R> w, vl;
-        if (jt == J_FIXED) {
+        if (d == 0) {
           w = mk(R(0), R(0), R(0));
           vl = w;
-        } else if (jt == J_FREE) {
-          const int c = li[LI_ROOTCOL];
-          vl = ld3<R>(s.vs + c);
-          w = ld3<R>(s.vs + c + 3);
+          if (li[LI_JTYPE] == J_FREE) {
+            const int c = li[LI_ROOTCOL];
+            vl = ld3<R>(s.vs + c);
+            w = ld3<R>(s.vs + c + 3);
+          }
         } else {
-          const int p = li[LI_PARENT];
-          const V3<R> oi = ld3<R>(s.o + 3 * i);
-          w = ld3<R>(s.v + 6 * p);
-          vl = add(ld3<R>(s.v + 6 * p + 3), cross(w, sub(oi, ld3<R>(s.o + 3 * p))));
+          const int jt = li[LI_JTYPE], p = li[LI_PARENT], c = li[LI_COL];
+          const V3<R> oi = ld3<R>(s.o + 3 * i), op = ld3<R>(s.o + 3 * p);
+          const V3<R> wp = ld3<R>(s.v + 6 * p), vp = ld3<R>(s.v + 6 * p + 3);
           const V3<R> ax = ld3<R>(s.ax + 3 * i);
-          const R qd = s.vs[li[LI_COL]];
+          const R qd = s.vs[c];
+          w = wp;
+          vl = add(vp, cross(wp, sub(oi, op)));
           if (jt == J_REV) w = add(w, mul(ax, qd));
           else vl = add(vl, mul(ax, qd));
         }
@@ -1783,7 +1806,7 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
         const int i = M.level_links[idx];
         R Rw[9], qq[4];
         V3<R> o, w, vl, ax;
-        link_kinematics(M, s, i, origin, Rw, qq, o, w, vl, ax);
+        link_kinematics(M, s, i, origin, Rw, qq, o, w, vl, ax, d == 0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) s.q[4 * i + k] = qq[k];
         st3(s.o + 3 * i, o);
