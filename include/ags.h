@@ -139,7 +139,8 @@ typedef struct {
   float limit_margin_rev;   /* same test for revolute limits (rad) */
   float limit_margin_pri;   /* and prismatic limits (m) */
   int32_t compute_fp64;     /* 0: compute in FP32; 1: compute in FP64 (tensors stay FP32) */
-  int32_t lanes_per_env;    /* 0: automatic (FP64: 64; FP32: 32 when n_v <= 32); 32 or 64: lanes of a wavefront per environment */
+  int32_t lanes_per_env;    /* 0 or 64: one environment per 64-lane wavefront; 32: two environments per wavefront
+                               (only for models with n_v <= 32) */
   int32_t persistent;       /* 1: one launch for all environment types (a grid sized to the device walks a work
                                list ordered by estimated cost, heaviest first); 0: one launch per type */
   int32_t adjoint_precision;  /* ags_sim_step_backward computes in: 0 the precision of compute_fp64, 32 FP32,

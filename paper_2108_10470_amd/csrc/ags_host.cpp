@@ -661,13 +661,12 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     TypeDev T;
     T.model = t;
     T.n_envs = (int)lists[t].size();
-    // lanes per environment: 32 (two environments per wavefront) when every per-lane loop fits
-    // automatic: FP64 compute gives each environment a whole wavefront (its LDS then allows two wavefronts
-    // per SIMD); FP32 packs two environments per wavefront when every per-lane loop fits in 32 lanes
-    const bool auto32 = !p->compute_fp64 && M->info.n_v <= 32;
-    T.team = (p->lanes_per_env == 32 || (p->lanes_per_env == 0 && auto32)) && M->info.n_v <= 32 ? 32 : 64;
-    if (p->persistent) {  // one lane count for all types: 32 only if every type fits
-      bool all32 = p->lanes_per_env == 32 || (p->lanes_per_env == 0 && !p->compute_fp64);
+    // lanes per environment: 64 unless 32 (two environments per wavefront) is asked for and every per-lane
+    // loop fits; the 64-lane form has the wide row path, the dispatch order by rows and the inward sweep by
+    // matrix entry, and is the faster one for both precisions on the humanoid-like workload
+    T.team = p->lanes_per_env == 32 && M->info.n_v <= 32 ? 32 : 64;
+    if (p->persistent) {  // one lane count for all types: 32 only if asked for and every type fits
+      bool all32 = p->lanes_per_env == 32;
       for (int u = 0; u < n_models; ++u)
         if (!lists[u].empty() && models[u]->info.n_v > 32) all32 = false;
       T.team = all32 ? 32 : 64;
