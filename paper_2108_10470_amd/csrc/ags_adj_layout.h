@@ -13,6 +13,7 @@ constexpr int kAdjSmallRows = 32;  // row capacity of the first, smaller-LDS adj
 constexpr int kAdjBigRowsAt = 29;  // rows above which the forward flags an env for the larger layout (one contact's margin)
 constexpr int kAdjIters = 32;  // Gauss-Seidel sweeps the adjoint's tape holds
 constexpr int kAdjPhases = 11;  // see AGS_DEBUG_ADJ_CYCLES
+constexpr int kLinkIntCols = 10;  // ints per link of the model's link table
 
 // per-environment LDS layout of the adjoint kernel: offsets in elements of the compute type (reals)
 // or in ints (integer region, placed after the reals)
@@ -31,13 +32,19 @@ struct AdjLds {
   int n_real;
   // integer region
   int rkind, rlink, rdof, rnrm, rmap, rlinkb, rslot, hst, flags;
+  // the model's integer tables staged once per workgroup: link table, level starts (at most one level per
+  // link, plus the end), links by level, children, link of each column, link of each DOF
+  int t_li, t_lev, t_links, t_child, t_col, t_dof;
   int n_int;
   int state_words;  // reals of one stored state: 13 per actor + 2 per DOF
   int rows_cap;     // min(max rows, kAdjRows)
 };
 
 // LDS layout of the adjoint kernel for one environment (one wavefront per environment)
-inline AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters, int row_cap) {
+// stage_tables: room for the model's integer tables in the integer region (the FP64 forms, whose LDS holds two
+// workgroups per CU with room to spare; the FP32 forms keep reading them through the caches, since the
+// tables would cost their small layout a workgroup per CU)
+inline AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iters, int row_cap, bool stage_tables) {
   AdjLds L{};
   int off = 0;
   auto take = [&](int n) {
@@ -81,6 +88,11 @@ inline AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iter
   L.rkind = take(rc); L.rlink = take(rc); L.rdof = take(rc); L.rnrm = take(rc); L.rmap = take(rc);
   L.rlinkb = take(rc); L.rslot = take(rc);
   L.hst = take(iters * L.rcp); L.flags = take(64);
+  L.t_li = L.t_lev = L.t_links = L.t_child = L.t_col = L.t_dof = -1;
+  if (stage_tables) {
+    L.t_li = take(kLinkIntCols * nl); L.t_lev = take(nl + 1); L.t_links = take(nl); L.t_child = take(nl);
+    L.t_col = take(nv); L.t_dof = take(nd);
+  }
   L.n_int = off;
   return L;
 }

@@ -31,6 +31,7 @@
 #include "ags_internal.h"
 
 namespace ags {
+static_assert(LI_COLS == kLinkIntCols, "the adjoint's staged link table and the model's link table differ in width");
 namespace {
 
 __device__ __forceinline__ float sqrt_(float x) { return sqrtf(x); }
@@ -378,10 +379,35 @@ struct Env {
     }
   }
   // table access
-  __device__ const int* li(int i) const { return P->m.li + i * LI_COLS; }
+  // the model's integer tables: staged in LDS by adjoint_env in the FP64 forms, read through the caches in the
+  // FP32 forms (whose small layout would lose a workgroup per CU to them)
+  static constexpr bool kStaged = sizeof(R) == 8;
+  __device__ const int* li(int i) const { return (kStaged ? ix + P->L.t_li : P->m.li) + i * LI_COLS; }
+  __device__ int lev_begin(int d) const { return kStaged ? ix[P->L.t_lev + d] : P->m.level_begin[d]; }
+  __device__ int lev_link(int t) const { return kStaged ? ix[P->L.t_links + t] : P->m.level_links[t]; }
+  __device__ int child(int k) const { return kStaged ? ix[P->L.t_child + k] : P->m.children[k]; }
+  __device__ int col_link(int c) const { return kStaged ? ix[P->L.t_col + c] : P->m.col_link[c]; }
+  __device__ int dof_link(int j) const { return kStaged ? ix[P->L.t_dof + j] : P->m.dof_link[j]; }
   __device__ const double* lf(int i) const { return P->m.lf + i * LF_COLS; }
   __device__ R* at(int off, int i, int w) const { return r + off + i * w; }
 };
+
+// One inward step of a children gather: every link of tree level lev adds its children's W-word records
+// (at off, one per link) to its own, with lanes over (link, word) pairs instead of one lane walking a link's
+// children record by record (the same sums in the same order).
+template <typename R, int W>
+__device__ __forceinline__ void gather_children_level(const Env<R>& E, int off, int lev) {
+  const auto& M = E.P->m;
+  const int b = E.lev_begin(lev), n_at = E.lev_begin(lev + 1) - b;
+  for (int pi = E.lane; pi < n_at * W; pi += 64) {
+    const int slot = pi / W, w = pi - slot * W;
+    const int i = E.lev_link(b + slot);
+    const int* li = E.li(i);
+    R acc = E.r[off + i * W + w];
+    for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) acc += E.r[off + E.child(k) * W + w];
+    E.r[off + i * W + w] = acc;
+  }
+}
 
 template <typename R>
 __device__ __forceinline__ void sync() {
@@ -399,7 +425,7 @@ __device__ __forceinline__ SV<R> joint_s(const Env<R>& E, int i) {
 // motion vector of generalized column k (a joint's, or one of a free root's six), from geometry
 template <typename R>
 __device__ __forceinline__ SV<R> col_s_geo(const Env<R>& E, int k) {
-  const int i = E.P->m.col_link[k];
+  const int i = E.col_link(k);
   const int* li = E.li(i);
   if (li[LI_PARENT] >= 0) return joint_s(E, i);
   const int a = k - li[LI_ROOTCOL];
@@ -429,9 +455,9 @@ __device__ void link_vel(const Env<R>& E, const R* x, int out) {
   const AdjLds& L = E.P->L;
   const DevModel& M = E.P->m;
   for (int lev = 0; lev < E.nlev; ++lev) {
-    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    const int b = E.lev_begin(lev), e = E.lev_begin(lev + 1);
     for (int t = b + E.lane; t < e; t += 64) {
-      const int i = M.level_links[t];
+      const int i = E.lev_link(t);
       const int* li = E.li(i);
       SV<R> V;
       if (li[LI_PARENT] < 0) {
@@ -524,7 +550,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     for (int k = 0; k < 6; ++k) nu[c + k] = sin[13 * a + 7 + k];
   }
   for (int j = lane; j < nd; j += 64) {
-    const int i = M.dof_link[j];
+    const int i = E.dof_link(j);
     const int c = E.li(i)[LI_COL];
     const double* lf = E.lf(i);
     const R qj = sin[13 * na + 2 * j], qdj = sin[13 * na + 2 * j + 1];
@@ -537,12 +563,37 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     arm[c] = R(lf[LF_ARM]) + h * kd + h * h * kp;
   }
   sync<R>();
+  // ---- joint-local rotation, anchor and axis of every link at once (lanes over links): they need only the
+  // link's own joint coordinate, so the sines and cosines are not taken one tree level after the other.
+  // Staged in the link's own Rm, p and ax words, which the level loop below overwrites with world values.
+  for (int i = lane; i < E.nl; i += 64) {
+    const int* li = E.li(i);
+    if (li[LI_PARENT] < 0) continue;
+    const double* lf = E.lf(i);
+    const V3<R> axl = ld3<R>(lf + LF_AXIS);
+    V3<R> tl = ld3<R>(lf + LF_ANCHOR);
+    const R qi = q[li[LI_DOF]];
+    R* Rr = E.at(L.Rm, i, 9);
+    if (li[LI_JTYPE] == J_REV) {
+      R s, c;
+      sincos_(qi, &s, &c);
+      const R t1 = R(1) - c;
+      Rr[0] = c + t1 * axl.x * axl.x; Rr[1] = t1 * axl.x * axl.y - s * axl.z; Rr[2] = t1 * axl.x * axl.z + s * axl.y;
+      Rr[3] = t1 * axl.x * axl.y + s * axl.z; Rr[4] = c + t1 * axl.y * axl.y; Rr[5] = t1 * axl.y * axl.z - s * axl.x;
+      Rr[6] = t1 * axl.x * axl.z - s * axl.y; Rr[7] = t1 * axl.y * axl.z + s * axl.x; Rr[8] = c + t1 * axl.z * axl.z;
+    } else {
+      tl = add(tl, mul(axl, qi));
+    }
+    st3(E.at(L.p, i, 3), tl);
+    st3(E.at(L.ax, i, 3), axl);
+  }
+  sync<R>();
   // ---- kinematics and velocities (outward by level); then every link's COM, world inertia and own
   // composite inertia at once (lanes over links): they need only the link's own pose
   for (int lev = 0; lev < E.nlev; ++lev) {
-    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    const int b = E.lev_begin(lev), e = E.lev_begin(lev + 1);
     for (int t = b + lane; t < e; t += 64) {
-      const int i = M.level_links[t];
+      const int i = E.lev_link(t);
       const int* li = E.li(i);
       const double* lf = E.lf(i);
       R* Rm = E.at(L.Rm, i, 9);
@@ -561,18 +612,15 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
         pw = sub(ld3<R>(rs), E.ref);
         st3(E.at(L.ax, i, 3), zero3<R>());
       } else {
+        // the staged joint-local parts (read whole before this link's words are overwritten)
         const int p = li[LI_PARENT];
         const R* Rp = E.at(L.Rm, p, 9);
-        const V3<R> axl = ld3<R>(lf + LF_AXIS);
-        V3<R> tl = ld3<R>(lf + LF_ANCHOR);
-        const R qi = q[li[LI_DOF]];
+        const V3<R> axl = ld3<R>(E.at(L.ax, i, 3));
+        const V3<R> tl = ld3<R>(E.at(L.p, i, 3));
         if (li[LI_JTYPE] == J_REV) {
-          R s, c;
-          sincos_(qi, &s, &c);
-          const R t1 = R(1) - c;
-          const R Rr[9] = {c + t1 * axl.x * axl.x, t1 * axl.x * axl.y - s * axl.z, t1 * axl.x * axl.z + s * axl.y,
-                           t1 * axl.x * axl.y + s * axl.z, c + t1 * axl.y * axl.y, t1 * axl.y * axl.z - s * axl.x,
-                           t1 * axl.x * axl.z - s * axl.y, t1 * axl.y * axl.z + s * axl.x, c + t1 * axl.z * axl.z};
+          R Rr[9];
+#pragma unroll
+          for (int k = 0; k < 9; ++k) Rr[k] = Rm[k];
 #pragma unroll
           for (int r0 = 0; r0 < 3; ++r0)
 #pragma unroll
@@ -581,7 +629,6 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
         } else {
 #pragma unroll
           for (int k = 0; k < 9; ++k) Rm[k] = Rp[k];
-          tl = add(tl, mul(axl, qi));
         }
         st3(E.at(L.ax, i, 3), mv(Rp, axl));
         pw = add(ld3<R>(E.at(L.p, p, 3)), mv(Rp, tl));
@@ -625,17 +672,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   E.phase(8);
   // ---- composite inertias (inward by level, children gathered)
   for (int lev = E.nlev - 2; lev >= 0; --lev) {
-    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
-    for (int t = b + lane; t < e; t += 64) {
-      const int i = M.level_links[t];
-      const int* li = E.li(i);
-      R* Ic = E.at(L.Ic, i, 10);
-      for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) {
-        const R* Cc = E.at(L.Ic, M.children[k], 10);
-#pragma unroll
-        for (int w = 0; w < 10; ++w) Ic[w] += Cc[w];
-      }
-    }
+    gather_children_level<R, 10>(E, L.Ic, lev);
     sync<R>();
   }
   for (int k = lane; k < nv; k += 64) sts6(E.r + L.cs + 6 * k, col_s_geo(E, k));
@@ -645,7 +682,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   const int nvp = L.nvp;
   for (int k = lane; k < nv; k += 64) {
     const SV<R> sk = col_s(E, k);
-    const SV<R> F = comp_mul(E.at(L.Ic, M.col_link[k], 10), sk);
+    const SV<R> F = comp_mul(E.at(L.Ic, E.col_link(k), 10), sk);
     const unsigned long long anc = M.col_anc[k];
     for (int j = 0; j < k; ++j) Lm[k * nvp + j] = ((anc >> j) & 1ull) ? sdot(col_s(E, j), F) : R(0);
     Lm[k * nvp + k] = sdot(sk, F) + arm[k];
@@ -677,9 +714,9 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   E.phase(0);
   // ---- C(q, qd): RNEA with zero joint accelerations, gravity as a base acceleration
   for (int lev = 0; lev < E.nlev; ++lev) {
-    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    const int b = E.lev_begin(lev), e = E.lev_begin(lev + 1);
     for (int t = b + lane; t < e; t += 64) {
-      const int i = M.level_links[t];
+      const int i = E.lev_link(t);
       const int* li = E.li(i);
       SV<R> A;
       if (li[LI_PARENT] < 0) {
@@ -706,22 +743,12 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   }
   sync<R>();
   for (int lev = E.nlev - 2; lev >= 0; --lev) {
-    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
-    for (int t = b + lane; t < e; t += 64) {
-      const int i = M.level_links[t];
-      const int* li = E.li(i);
-      R* F = E.at(L.X2, i, 6);
-      for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) {
-        const R* Fc = E.at(L.X2, M.children[k], 6);
-#pragma unroll
-        for (int w = 0; w < 6; ++w) F[w] += Fc[w];
-      }
-    }
+    gather_children_level<R, 6>(E, L.X2, lev);
     sync<R>();
   }
   R rhs = R(0);
   if (lane < nv) {
-    const int i = M.col_link[lane];
+    const int i = E.col_link(lane);
     const int* li = E.li(i);
     const SV<R> F = lds6(E.at(L.X2, i, 6));
     R C;
@@ -759,7 +786,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     R glo = R(0), ghi = R(0);
     int i = 0;
     if (lane < nd) {
-      i = M.dof_link[lane];
+      i = E.dof_link(lane);
       const double* lf = E.lf(i);
       const R lo = R(lf[LF_LO]), hi = R(lf[LF_HI]), ml = R(lf[LF_ML]);
       const R rate = vs[E.li(i)[LI_COL]];
@@ -977,12 +1004,17 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   // entry of the next row's column of A is loaded one row ahead.
   const bool fric = kind >= 4;
   const int nrm_own = fric ? nrm : -1;
+  const bool own = lane < Rn;
   R lamn = R(0);
   for (int it = 0; it < P.iters; ++it) {
-    R a_next = lane < Rn && Rn > 0 ? A[tri(lane, 0)] : R(0);
+    R a_next = own && Rn > 0 ? A[tri(lane, 0)] : R(0);
+    // the lane's own row's tape entries of this sweep, kept in registers by selects and stored once after
+    // the sweep (no branch per row)
+    R t_lo = R(0), t_res = R(0);
+    int t_st = 0;
     for (int r = 0; r < Rn; ++r) {
       const R a_r = a_next;
-      if (r + 1 < Rn) a_next = lane < Rn ? A[tri(lane, r + 1)] : R(0);
+      if (r + 1 < Rn) a_next = own ? A[tri(lane, r + 1)] : R(0);
       const R res = y + bias;
       const R x = lam - res * invA;
       const R hi = fric ? mu * lamn : R(INFINITY);
@@ -990,14 +1022,18 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
       const int st = x > hi ? 2 : (x < lo ? 1 : 0);
       const R nl = st == 2 ? hi : (st == 1 ? lo : x);
       const R dl = lane_read(nl - lam, r);
-      if (lane == r) {
-        hlo[it * rcp + r] = lam;
-        hres[it * rcp + r] = res;
-        hst[it * rcp + r] = st;
-        lam = nl;
-      }
-      if (nrm_own == r) lamn += dl;
+      const bool me = lane == r;
+      t_lo = me ? lam : t_lo;
+      t_res = me ? res : t_res;
+      t_st = me ? st : t_st;
+      lam = me ? nl : lam;
+      lamn += nrm_own == r ? dl : R(0);
       y += a_r * dl;
+    }
+    if (own) {
+      hlo[it * rcp + lane] = t_lo;
+      hres[it * rcp + lane] = t_res;
+      hst[it * rcp + lane] = t_st;
     }
   }
   if (lane < Rn) E.r[L.rlam + lane] = lam;
@@ -1012,7 +1048,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
   sync<R>();
   // ---- semi-implicit integration into sout
   for (int j = lane; j < nd; j += 64) {
-    const int c = E.li(M.dof_link[j])[LI_COL];
+    const int c = E.li(E.dof_link(j))[LI_COL];
     sout[13 * na + 2 * j] = q[j] + h * nu1[c];
     sout[13 * na + 2 * j + 1] = nu1[c];
   }
@@ -1088,7 +1124,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   sync<R>();
   // ---- integration reverse
   for (int j = lane; j < nd; j += 64) {
-    const int c = E.li(M.dof_link[j])[LI_COL];
+    const int c = E.li(E.dof_link(j))[LI_COL];
     nub[c] = dbar[2 * j + 1] + h * dbar[2 * j];
     qb[j] = dbar[2 * j];
   }
@@ -1149,28 +1185,34 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   const int* hst = E.ix + L.hst;
   R qv = R(0);
   E.phase(2);
+  const bool own = lane < Rn;
   for (int it = P.iters - 1; it >= 0; --it) {
+    // the lane's own row's tape entries of this sweep, read once; row r's are then taken from lane r
+    const int st_own = own ? hst[it * rcp + lane] : 0;
+    const R lo_own = own ? hlo[it * rcp + lane] : R(0);
+    // lambda after this update: the next sweep's lambda before it, or the final lambda
+    const R dl_own = own ? (it + 1 < P.iters ? hlo[(it + 1) * rcp + lane] : rlam[lane]) - lo_own : R(0);
+    const R res_own = own ? hres[it * rcp + lane] : R(0);
+    R a_next = own && Rn > 0 ? A[tri(lane, Rn - 1)] : R(0);
     for (int r = Rn - 1; r >= 0; --r) {
-      const int st = hst[it * rcp + r];
-      // lambda after this update: the next sweep's lambda before it, or the final lambda
-      const R dl = (it + 1 < P.iters ? hlo[(it + 1) * rcp + r] : rlam[r]) - hlo[it * rcp + r];
-      const R Asr = lane < Rn ? A[tri(lane, r)] : R(0);
+      const R Asr = a_next;
+      if (r > 0) a_next = own ? A[tri(lane, r - 1)] : R(0);
+      const int st = lane_read(st_own, r);
+      const R dl = lane_read(dl_own, r);
       const R sum = lane_read(qv, r);
       const R g = lane_read(lamb, r) + sum;
       // Abar[s][r] += ybar_s dl enters S[s][r] and S[r][s]: one packed element, twice on the diagonal
-      if (lane < Rn) Ab[tri(lane, r)] += (lane == r ? R(2) : R(1)) * ybar * dl;
-      const int kr = lane_read(kind, r);
-      if (lane == r) lamb = -sum;
+      if (own) Ab[tri(lane, r)] += (lane == r ? R(2) : R(1)) * ybar * dl;
+      const bool me = lane == r;
+      lamb = me ? -sum : lamb;
       if (st == 0) {
         const R dy = -lane_read(invA, r) * g;
-        if (lane == r) {
-          lamb += g;
-          ybar += dy;
-          bbar += dy;
-          invAb -= hres[it * rcp + r] * g;
-        }
+        lamb = me ? lamb + g : lamb;
+        ybar = me ? ybar + dy : ybar;
+        bbar = me ? bbar + dy : bbar;
+        invAb = me ? invAb - res_own * g : invAb;
         qv += Asr * dy;
-      } else if (kr >= 4) {
+      } else if (lane_read(kind, r) >= 4) {
         const int nr = lane_read(nrm, r);
         if (lane == nr) lamb += (st == 2 ? mu : -mu) * g;
       }
@@ -1217,7 +1259,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   for (int c = lane; c < nv; c += 64) nui[c] = vsb[c];
   sync<R>();
   for (int j = lane; j < nd; j += 64) {
-    const int i = M.dof_link[j];
+    const int i = E.dof_link(j);
     const int c = E.li(i)[LI_COL];
     const double* lf = E.lf(i);
     const R kp = R(lf[LF_KP]), kd = R(lf[LF_KD]);
@@ -1236,7 +1278,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
     SV<R> y = sz<R>();
     for (int j = 0; j < k; ++j)
       if ((anc >> j) & 1ull) y = sadd(y, smul(col_s(E, j), Lm[k * nvp + j]));
-    const R* Ic = E.at(L.Ic, M.col_link[k], 10);
+    const R* Ic = E.at(L.Ic, E.col_link(k), 10);
     const SV<R> Is = comp_mul(Ic, sk), Iy = comp_mul(Ic, y);
     sts6(colS + 6 * k, smul(sadd(Iy, smul(Is, Lm[k * nvp + k])), R(-2)));
     sts6(colY + 6 * k, smul(Is, R(-2)));
@@ -1260,7 +1302,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
     V3<R> cb = zero3<R>(), tI = zero3<R>();
     const unsigned long long la = M.link_anc[i];
     for (int k = 0; k < nv; ++k) {
-      if (!((la >> M.col_link[k]) & 1ull)) continue;
+      if (!((la >> E.col_link(k)) & 1ull)) continue;
       const SV<R> sk = col_s(E, k);
       bil(m, cw, Iw, sk, lds6(colYv + 6 * k), R(-2), cb, tI);
       bil(m, cw, Iw, sk, sk, -Lm[k * nvp + k], cb, tI);
@@ -1307,13 +1349,13 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   sync<R>();
   // inward: subtree sums of F, Abar, Vbar (Vbar of a parent also receives qd crf(s, Abar) of each child)
   for (int lev = E.nlev - 1; lev >= 0; --lev) {
-    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    const int b = E.lev_begin(lev), e = E.lev_begin(lev + 1);
     for (int t = b + lane; t < e; t += 64) {
-      const int i = M.level_links[t];
+      const int i = E.lev_link(t);
       const int* li = E.li(i);
       SV<R> F = lds6(E.at(L.X2, i, 6)), Ab_ = lds6(E.at(L.X3, i, 6)), Vb = lds6(E.at(L.X0, i, 6));
       for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) {
-        const int ch = M.children[k];
+        const int ch = E.child(k);
         const SV<R> Ach = lds6(E.at(L.X3, ch, 6));
         F = sadd(F, lds6(E.at(L.X2, ch, 6)));
         Ab_ = sadd(Ab_, Ach);
@@ -1488,12 +1530,12 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   sync<R>();
   // subtree sums (inward), position adjoints
   for (int lev = E.nlev - 1; lev >= 0; --lev) {
-    const int b = M.level_begin[lev], e = M.level_begin[lev + 1];
+    const int b = E.lev_begin(lev), e = E.lev_begin(lev + 1);
     for (int t = b + lane; t < e; t += 64) {
-      const int i = M.level_links[t];
+      const int i = E.lev_link(t);
       const int* li = E.li(i);
       SV<R> Wc = lds6(E.at(L.wr, i, 6));
-      for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) Wc = sadd(Wc, lds6(E.at(L.wr, M.children[k], 6)));
+      for (int k = li[LI_CHILD_BEGIN]; k < li[LI_CHILD_END]; ++k) Wc = sadd(Wc, lds6(E.at(L.wr, E.child(k), 6)));
       sts6(E.at(L.wr, i, 6), Wc);
       if (li[LI_PARENT] < 0 && li[LI_JTYPE] == J_FREE) {
         int a = 0;
@@ -1521,7 +1563,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   // ---- adjoint of the substep's start state
   for (int j = lane; j < nd; j += 64) {
     dbar[2 * j] = qb[j];
-    dbar[2 * j + 1] = nui[E.li(M.dof_link[j])[LI_COL]];
+    dbar[2 * j + 1] = nui[E.li(E.dof_link(j))[LI_COL]];
   }
   for (int a = lane; a < na; a += 64) {
     const int* ai = M.ai + a * AI_COLS;
@@ -1554,6 +1596,16 @@ __device__ __forceinline__ void adjoint_env(const AdjArgs& P, int ei) {
   E.ns = P.m.n_slots;
   E.nlev = P.m.n_levels;
   E.rc = L.rows_cap;
+  if (Env<R>::kStaged) {  // stage the model's integer tables (every lane copies; the sync below orders them)
+    const DevModel& G = P.m;
+    int* ix = E.ix;
+    for (int k = E.lane; k < G.n_links * LI_COLS; k += 64) ix[L.t_li + k] = G.li[k];
+    for (int k = E.lane; k <= G.n_levels; k += 64) ix[L.t_lev + k] = G.level_begin[k];
+    for (int k = E.lane; k < G.n_links; k += 64) ix[L.t_links + k] = G.level_links[k];
+    for (int k = E.lane; k < G.n_links - G.n_actors; k += 64) ix[L.t_child + k] = G.children[k];
+    for (int k = E.lane; k < G.n_v; k += 64) ix[L.t_col + k] = G.col_link[k];
+    for (int k = E.lane; k < G.n_dof; k += 64) ix[L.t_dof + k] = G.dof_link[k];
+  }
   const int env = P.env_list[ei];
   if (P.skip_flags && P.skip_flags[env] != 0) return;  // another launch runs this env
   E.abase = P.env_actor_base[env];

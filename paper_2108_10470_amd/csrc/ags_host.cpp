@@ -741,10 +741,10 @@ extern "C" int ags_sim_create(const ags_model* const* models, int32_t n_models, 
     T.body_pairs = M->body_pairs;
     const int adj_cap = p->adjoint_max_rows > 0 ? p->adjoint_max_rows : kAdjRows;
     const int adj_small_cap = std::min(adj_cap, kAdjSmallRows);
-    T.adj = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), adj_cap);
+    T.adj = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), adj_cap, adj_fp64(*p));
     T.adj_bytes = (size_t)T.adj.n_real * (adj_fp64(*p) ? sizeof(double) : sizeof(float)) + (size_t)T.adj.n_int * sizeof(int);
     T.adj_two = std::min(M->info.max_rows, adj_cap) > adj_small_cap;
-    T.adj_small = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), adj_small_cap);
+    T.adj_small = make_adj_layout(M->info, p->substeps, std::min(p->pgs_iters, kAdjIters), adj_small_cap, adj_fp64(*p));
     T.adj_small_bytes = (size_t)T.adj_small.n_real * (adj_fp64(*p) ? sizeof(double) : sizeof(float)) +
                         (size_t)T.adj_small.n_int * sizeof(int);
     max_type_envs = std::max(max_type_envs, T.n_envs);

@@ -5,7 +5,7 @@
 // of exactly n_real reals and n_int ints, so any formula that runs past the layout fails under the
 // sanitizer or the explicit checks.  Prints one JSON line (byte offsets of every array, the total LDS
 // bytes in FP32 and FP64, and the arrays that start beyond 64 KiB) and exits nonzero on a violation.
-//   adj_lds_check n_links n_v n_dof n_actors max_rows substeps iters row_cap
+//   adj_lds_check n_links n_v n_dof n_actors max_rows substeps iters row_cap stage_tables
 #include <cstdio>
 #include <cstdlib>
 #include <string>
@@ -46,8 +46,8 @@ void touch(std::vector<double>& real, std::vector<int>& in, const Arr& a) {
 }  // namespace
 
 int main(int argc, char** argv) {
-  if (argc != 9) {
-    std::fprintf(stderr, "usage: adj_lds_check n_links n_v n_dof n_actors max_rows substeps iters row_cap\n");
+  if (argc != 10) {
+    std::fprintf(stderr, "usage: adj_lds_check n_links n_v n_dof n_actors max_rows substeps iters row_cap stage_tables\n");
     return 2;
   }
   ags_model_info info{};
@@ -57,7 +57,8 @@ int main(int argc, char** argv) {
   info.n_actors = std::atoi(argv[4]);
   info.max_rows = std::atoi(argv[5]);
   const int substeps = std::atoi(argv[6]), iters = std::atoi(argv[7]), row_cap = std::atoi(argv[8]);
-  const AdjLds L = make_adj_layout(info, substeps, iters, row_cap);
+  const bool staged = std::atoi(argv[9]) != 0;
+  const AdjLds L = make_adj_layout(info, substeps, iters, row_cap, staged);
   const int nl = info.n_links, nv = std::max(1, info.n_v), nd = std::max(1, info.n_dof), na = info.n_actors;
   const int rc = L.rows_cap, nvp = L.nvp, rcp = L.rcp;
   const long ntri = (long)rc * (rc + 1) / 2;
@@ -105,10 +106,17 @@ int main(int argc, char** argv) {
       {"rkind", L.rkind, rc, true}, {"rlink", L.rlink, rc, true}, {"rdof", L.rdof, rc, true},
       {"rnrm", L.rnrm, rc, true}, {"rmap", L.rmap, rc, true}, {"rlinkb", L.rlinkb, rc, true},
       {"rslot", L.rslot, rc, true}, {"hst", L.hst, (long)(iters - 1) * rcp + rc, true}, {"flags", L.flags, 64, true},
+      // staged model tables: link table, level starts (a level has at least one link), links by level,
+      // children (fewer than the links), link of each column and of each DOF
   };
+  std::vector<Arr> all = arrays;
+  if (staged)
+    all.insert(all.end(), {{"t_li", L.t_li, (long)kLinkIntCols * nl, true}, {"t_lev", L.t_lev, nl + 1l, true},
+                           {"t_links", L.t_links, nl, true}, {"t_child", L.t_child, nl, true},
+                           {"t_col", L.t_col, nv, true}, {"t_dof", L.t_dof, nd, true}});
   std::vector<double> real((size_t)L.n_real, 0.0);
   std::vector<int> in((size_t)L.n_int, 0);
-  for (const Arr& a : arrays) touch(real, in, a);
+  for (const Arr& a : all) touch(real, in, a);
   // arrays that share words in time must stay inside their host array
   auto inside = [&](const char* what, long off, long use, long host, long host_words) {
     if (off < host || off + use > host + host_words) {
@@ -140,12 +148,12 @@ int main(int argc, char** argv) {
     }
   }
   std::vector<int> iowner((size_t)L.n_int, -1);
-  for (size_t k = 0; k < arrays.size(); ++k) {
-    const Arr& a = arrays[k];
+  for (size_t k = 0; k < all.size(); ++k) {
+    const Arr& a = all[k];
     if (!a.ints) continue;
     for (long i = a.off; i < a.off + a.use && i < L.n_int; ++i) {
       if (iowner[i] >= 0) {
-        std::fprintf(stderr, "%s overlaps %s at int %ld\n", a.name, arrays[iowner[i]].name, i);
+        std::fprintf(stderr, "%s overlaps %s at int %ld\n", a.name, all[iowner[i]].name, i);
         g_fail = 1;
         break;
       }
@@ -156,7 +164,7 @@ int main(int argc, char** argv) {
   std::printf("{\"rows_cap\": %d, \"n_real\": %d, \"n_int\": %d, \"bytes_f32\": %ld, \"bytes_f64\": %ld, \"above_64KiB_f64\": [",
               rc, L.n_real, L.n_int, bytes32, bytes64);
   bool first = true;
-  for (const Arr& a : arrays) {
+  for (const Arr& a : all) {
     const long b = a.ints ? 8l * L.n_real + 4l * a.off : 8l * a.off;
     if (b + (a.ints ? 4 : 8) * (a.use > 0 ? a.use : 1) > 65536) {
       std::printf("%s\"%s\"", first ? "" : ", ", a.name);

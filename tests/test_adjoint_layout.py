@@ -1,7 +1,7 @@
 """Host-side checks of the adjoint kernel's LDS use (CPU only).
 
 1. tests/adj_lds_check.cpp replays make_adj_layout (the header the runtime uses) for every workload model
-   and a grid of substeps, Gauss-Seidel sweeps and row capacities, touching every index the kernel's
+   and a grid of substeps, Gauss-Seidel sweeps, row capacities and with or without the staged model tables, touching every index the kernel's
    indexing can reach in buffers of exactly the layout's size, built with AddressSanitizer and UBSan.
 2. The adjoint kernels of this build reach LDS only through DS instructions: no FLAT memory instruction
    and no call appears in their gfx950 assembly.  (An earlier instrumented build, in which the compiler
@@ -41,9 +41,9 @@ def test_adjoint_lds_layout_replay(checker, model):
     out = []
     for substeps in (1, 2, 3):
         for iters in (1, 8, 12, 32):
-            for cap in (5, 32, 64):
+            for cap, staged in ((5, 0), (32, 0), (32, 1), (64, 1)):
                 args = [str(x) for x in (info.n_links, info.n_v, info.n_dof, info.n_actors, info.max_rows, substeps,
-                                         iters, cap)]
+                                         iters, cap, staged)]
                 r = subprocess.run([checker, *args], capture_output=True, text=True)
                 assert r.returncode == 0, (args, r.stderr)
                 d = json.loads(r.stdout)
@@ -57,7 +57,7 @@ def test_humanoid_fp64_full_layout_reaches_beyond_64_kib(checker):
     its Delassus, row and tape arrays above 64 KiB of LDS."""
     info = ags.Model(W.env_humanoid()).info
     r = subprocess.run([checker, *[str(x) for x in (info.n_links, info.n_v, info.n_dof, info.n_actors, info.max_rows,
-                                                    2, 8, 64)]], capture_output=True, text=True, check=True)
+                                                    2, 8, 64, 1)]], capture_output=True, text=True, check=True)
     d = json.loads(r.stdout)
     assert d["bytes_f64"] > 65536 and "hst" in d["above_64KiB_f64"] and "A" in d["above_64KiB_f64"], d
 
