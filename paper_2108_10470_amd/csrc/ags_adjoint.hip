@@ -490,11 +490,46 @@ __device__ R chol_solve_lanes(const Env<R>& E, R b) {
   return c < nv ? b : R(0);
 }
 // solve in place on one LDS row per lane (row pointer y, length nv); four partial sums per dot product
+constexpr int kRegSolve = 32;  // models with at most this many columns solve a row in registers
+
 template <typename R>
 __device__ void chol_solve_row(const Env<R>& E, R* y) {
   const R* Lm = E.r + E.P->L.Lm;
   const R* ldi = E.r + E.P->L.ldi;
   const int nvp = E.P->L.nvp, nv = E.nv;
+  if (nv <= kRegSolve) {
+    // the lane's row in registers: the substitutions' chains run through registers instead of a store and a
+    // load of every solved entry (entries past n_v are zero and their factor reads are masked)
+    R v[kRegSolve];
+#pragma unroll
+    for (int k = 0; k < kRegSolve; ++k) v[k] = k < nv ? y[k] : R(0);
+#pragma unroll
+    for (int k = 0; k < kRegSolve; ++k) {
+      if (k < nv) {
+        const R* Lk = Lm + k * nvp;
+        R t[4] = {v[k], R(0), R(0), R(0)};
+#pragma unroll
+        for (int j = 0; j < k; ++j) t[j & 3] -= Lk[j] * v[j];
+        v[k] = ((t[0] + t[1]) + (t[2] + t[3])) * ldi[k];
+      }
+    }
+#pragma unroll
+    for (int k = kRegSolve - 1; k >= 0; --k) {
+      if (k < nv) {
+        R t[4] = {v[k], R(0), R(0), R(0)};
+#pragma unroll
+        for (int j = k + 1; j < kRegSolve; ++j) {
+          const R l = Lm[min(j, nv - 1) * nvp + k];
+          t[j & 3] -= (j < nv ? l : R(0)) * v[j];
+        }
+        v[k] = ((t[0] + t[1]) + (t[2] + t[3])) * ldi[k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRegSolve; ++k)
+      if (k < nv) y[k] = v[k];
+    return;
+  }
   for (int k = 0; k < nv; ++k) {
     const R* Lk = Lm + k * nvp;
     R t0 = y[k], t1 = R(0), t2 = R(0), t3 = R(0);
