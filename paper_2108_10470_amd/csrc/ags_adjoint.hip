@@ -923,10 +923,22 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
         const SV<R> s = joint_s(E, i);
         Jr[li[LI_COL]] = dot(d, add(s.v, cross(s.w, x)));
       }
-      for (int k = li[LI_ANC_BEGIN]; k < li[LI_ANC_END]; ++k) {
-        const int a = M.anc_link[k];
-        const SV<R> s = joint_s(E, a);
-        Jr[E.li(a)[LI_COL]] = dot(d, add(s.v, cross(s.w, x)));
+      {  // ancestors four at a time, their reads issued together (entries past the last one are not written)
+        const int qb = li[LI_ANC_BEGIN], qe = li[LI_ANC_END];
+        for (int q0 = qb; q0 < qe; q0 += 4) {
+          int col[4];
+          R jv[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const int a = M.anc_link[min(q0 + k, qe - 1)];
+            const SV<R> s = joint_s(E, a);
+            col[k] = E.li(a)[LI_COL];
+            jv[k] = dot(d, add(s.v, cross(s.w, x)));
+          }
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (q0 + k < qe) Jr[col[k]] = jv[k];
+        }
       }
       const int rt = li[LI_ROOT];
       if (E.li(rt)[LI_JTYPE] == J_FREE) {
@@ -1437,9 +1449,21 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
     const int* li = E.li(i);
     SV<R> Vt = sz<R>();
     if (li[LI_PARENT] >= 0) Vt = smul(joint_s(E, i), Jr[li[LI_COL]]);
-    for (int k = li[LI_ANC_BEGIN]; k < li[LI_ANC_END]; ++k) {
-      const int a = M.anc_link[k];
-      Vt = sadd(Vt, smul(joint_s(E, a), Jr[E.li(a)[LI_COL]]));
+    // ancestors four at a time, their reads issued together (entries past the last one read the last one
+    // again and add zero)
+    const int qb = li[LI_ANC_BEGIN], qe = li[LI_ANC_END];
+    for (int q0 = qb; q0 < qe; q0 += 4) {
+      SV<R> sv[4];
+      R jc[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int a = M.anc_link[min(q0 + k, qe - 1)];
+        sv[k] = joint_s(E, a);
+        const R j = Jr[E.li(a)[LI_COL]];
+        jc[k] = q0 + k < qe ? j : R(0);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Vt = sadd(Vt, smul(sv[k], jc[k]));
     }
     const int rt = li[LI_ROOT];
     if (E.li(rt)[LI_JTYPE] == J_FREE) Vt = sadd(Vt, root_vel(ld3<R>(E.at(L.c, rt, 3)), Jr + li[LI_ROOTCOL]));
@@ -1481,7 +1505,9 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
     const V3<R> c = ld3<R>(E.r + L.rcen + 3 * lane), n = ld3<R>(E.r + L.rd + 3 * lane);
     V3<R> cb = ld3<R>(rxb + 3 * lane), t1b = zero3<R>(), t2b = zero3<R>();
     V3<R> nb = ld3<R>(rdb + 3 * lane);
-    for (int r = 0; r < Rn; ++r) {
+    // a contact's friction rows are generated right after its normal row and compaction keeps the order,
+    // so only the next two rows can refer to this one
+    for (int r = lane + 1; r <= lane + 2 && r < Rn; ++r) {
       if (rnrm[r] != lane) continue;
       cb = add(cb, ld3<R>(rxb + 3 * r));
       if (rkind[r] == 4) t1b = add(t1b, ld3<R>(rdb + 3 * r));
