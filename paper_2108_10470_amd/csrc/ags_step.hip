@@ -1939,16 +1939,33 @@ static const void* step_fn(int fp64, int team) {
 }
 
 // Counting sort of the env ids of one type by the rows of their last step, most rows first (rows of
-// kOrderBuckets - 1 or more share the first bucket).  One workgroup; the order within a bucket is whichever
-// the LDS atomics give, which no result depends on.
+// kOrderBuckets - 1 or more share the first bucket).  One workgroup; each thread keeps the ids and buckets
+// of its kOrderPer entries in registers between the count and the scatter, and batches of up to
+// kOrderLds ids are placed in LDS before one coalesced write (larger batches go through tmp).  The order
+// within a bucket is whichever the LDS atomics give, which no result depends on.
 constexpr int kOrderBuckets = 128;
-__global__ __launch_bounds__(1024) void order_by_rows_kernel(int* order, int* tmp, const int* rows, int n) {
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderPer = 8;
+constexpr int kOrderLds = kOrderThreads * kOrderPer;
+__global__ __launch_bounds__(kOrderThreads) void order_by_rows_kernel(int* order, int* tmp, const int* rows, int n) {
   __shared__ int start[kOrderBuckets];
+  __shared__ int placed[kOrderLds];
   const int t = threadIdx.x;
+  const bool in_lds = n <= kOrderLds;
   auto bucket = [&](int e) { return kOrderBuckets - 1 - min(max(rows[e], 0), kOrderBuckets - 1); };
   if (t < kOrderBuckets) start[t] = 0;
   __syncthreads();
-  for (int i = t; i < n; i += blockDim.x) atomicAdd(&start[bucket(order[i])], 1);
+  int ids[kOrderPer], bk[kOrderPer];
+#pragma unroll
+  for (int k = 0; k < kOrderPer; ++k) {
+    const int i = t + k * kOrderThreads;
+    ids[k] = i < n ? order[i] : 0;
+    bk[k] = i < n ? bucket(ids[k]) : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < kOrderPer; ++k)
+    if (t + k * kOrderThreads < n) atomicAdd(&start[bk[k]], 1);
+  for (int i = t + kOrderLds; i < n; i += kOrderThreads) atomicAdd(&start[bucket(order[i])], 1);
   __syncthreads();
   if (t == 0) {
     int run = 0;
@@ -1959,17 +1976,28 @@ __global__ __launch_bounds__(1024) void order_by_rows_kernel(int* order, int* tm
     }
   }
   __syncthreads();
-  for (int i = t; i < n; i += blockDim.x) {
+#pragma unroll
+  for (int k = 0; k < kOrderPer; ++k) {
+    if (t + k * kOrderThreads < n) {
+      const int pos = atomicAdd(&start[bk[k]], 1);
+      if (in_lds) placed[pos] = ids[k];
+      else tmp[pos] = ids[k];
+    }
+  }
+  for (int i = t + kOrderLds; i < n; i += kOrderThreads) {
     const int e = order[i];
     tmp[atomicAdd(&start[bucket(e)], 1)] = e;
   }
   __syncthreads();
-  for (int i = t; i < n; i += blockDim.x) order[i] = tmp[i];
+  if (in_lds)
+    for (int i = t; i < n; i += kOrderThreads) order[i] = placed[i];
+  else
+    for (int i = t; i < n; i += kOrderThreads) order[i] = tmp[i];
 }
 
 hipError_t launch_order_by_rows(int* order, int* tmp, const int* rows, int n, hipStream_t stream) {
   if (n <= 1) return hipSuccess;
-  hipLaunchKernelGGL(order_by_rows_kernel, dim3(1), dim3(1024), 0, stream, order, tmp, rows, n);
+  hipLaunchKernelGGL(order_by_rows_kernel, dim3(1), dim3(kOrderThreads), 0, stream, order, tmp, rows, n);
   return hipGetLastError();
 }
 

@@ -272,3 +272,31 @@ def test_results_do_not_depend_on_env_position_or_dispatch_order(fp64):
         for x, y in zip(a[:4], b[:4]):
             assert torch.isfinite(x).all()
             assert torch.equal(x, y[inv])
+
+
+def test_dispatch_order_beyond_one_lds_batch():
+    """More envs of one type than the ordering kernel places in LDS at once (8192): a permuted copy of a
+    9000-env ant batch reproduces every env bitwise over 4 steps, so the order list stays a permutation."""
+    env = W.env_ant()
+    E, T = 9000, 4
+    p = W.SimParams()
+    root, dof = W.initial_state(env, E, 3)
+    acts = torch.tensor(W.actuation(env, E, T, 3).reshape(T, E, -1), dtype=torch.float32, device="cuda:0")
+    nd = env.n_dof
+    r0 = torch.tensor(root.reshape(E, -1), dtype=torch.float32, device="cuda:0")
+    d0 = torch.tensor(dof.reshape(E, nd, 2), dtype=torch.float32, device="cuda:0")
+    perm = torch.from_numpy(np.random.default_rng(9).permutation(E)).to("cuda:0")
+    outs = []
+    for ix in (torch.arange(E, device="cuda:0"), perm):
+        sim = ags.Sim([ags.Model(env)], [0] * E, p, device="cuda:0", fp64=True)
+        sim.root_state.copy_(r0[ix].reshape(-1, 13))
+        sim.dof_state.copy_(d0[ix].reshape(-1, 2))
+        for t in range(T):
+            sim.actuation.copy_(acts[t][ix].reshape(-1))
+            sim.step()
+        torch.cuda.synchronize()
+        outs.append((sim.root_state.reshape(E, -1).clone(), sim.dof_state.reshape(E, nd, 2).clone()))
+    inv = torch.argsort(perm)
+    for x, y in zip(*outs):
+        assert torch.isfinite(x).all()
+        assert torch.equal(x, y[inv])
