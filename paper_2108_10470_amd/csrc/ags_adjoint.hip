@@ -1736,6 +1736,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAdjWavesPer
 // from adjoint_kernel because the loop costs registers (a few spilled in the FP32 form)
 template <typename R>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kAdjWavesPerEU<R>))) void adjoint_list_kernel(AdjArgs P, int n_envs) {
+  // The flagged envs (more rows, the larger layout) share their CUs with the first pass and would otherwise
+  // finish last and set the step's time: their wavefronts take the highest issue priority on their SIMD.
+  __builtin_amdgcn_s_setprio(3);
   for (int ei = blockIdx.x; ei < n_envs; ei += gridDim.x) {
     if (ei >= *P.list_count) return;
     adjoint_env<R>(P, ei);

@@ -576,7 +576,7 @@ struct ags_sim {
   // device address of this device's copy of the no-allocation rollout scratch (see noalloc_scratch_ptr)
   void* noalloc_scratch = nullptr;
   hipStream_t aux2 = nullptr;
-  hipEvent_t ev_big_start = nullptr, ev_big_done = nullptr;
+  hipEvent_t ev_big_start = nullptr, ev_big_done = nullptr, ev_big_listed = nullptr;
   // persistent (fused) launch
   bool fused_ok = false;
   int* units = nullptr;  // device: (type, group) pairs
@@ -865,6 +865,7 @@ extern "C" void ags_sim_destroy(ags_sim* S) {
   if (S->aux) (void)hipStreamDestroy(S->aux);
   if (S->ev_big_start) (void)hipEventDestroy(S->ev_big_start);
   if (S->ev_big_done) (void)hipEventDestroy(S->ev_big_done);
+  if (S->ev_big_listed) (void)hipEventDestroy(S->ev_big_listed);
   if (S->aux2) (void)hipStreamDestroy(S->aux2);
   if (S->env_tables) (void)hipFree(S->env_tables);
   if (S->units) (void)hipFree(S->units);
@@ -1067,12 +1068,20 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
         AdjArgs ab = a;
         ab.env_list = S->adj_big_list + 1;
         ab.list_count = S->adj_big_list;
+        // With one flagged workgroup per CU (the FP64 layouts), pass 1 is released only once the flagged list
+        // is built, when the flagged launch is already queued behind it on the third stream: its workgroups
+        // then find LDS room before pass 1's fill the CUs (started together, they waited for pass 1's
+        // workgroups to finish and ended last; 64-step humanoid reverse pass 319 -> 299 ms).  With two per CU
+        // (FP32) the same head start left pass 1 one workgroup per CU and was slower (145 vs 136 ms).
+        const bool gate = big_per_cu == 1;
         if ((e = hipEventRecord(S->ev_big_start, st)) == hipSuccess &&
             (e = hipStreamWaitEvent(S->aux2, S->ev_big_start, 0)) == hipSuccess &&
             (e = launch_zero_count(S->adj_big_list, S->aux2)) == hipSuccess &&
             (e = launch_compact_flags(T.env_list, T.n_envs, S->adj_big, S->adj_big_list, S->aux2)) == hipSuccess &&
+            (e = hipEventRecord(S->ev_big_listed, S->aux2)) == hipSuccess &&
             (e = launch_adjoint(ab, T.n_envs, adj_fp64(p), S->aux2, S->n_cu * big_per_cu)) == hipSuccess)
           e = hipEventRecord(S->ev_big_done, S->aux2);
+        if (e == hipSuccess && gate) e = hipStreamWaitEvent(st, S->ev_big_listed, 0);
         if (e != hipSuccess) return hip_fail(e, "step_backward: flagged pass");
       }
       if ((e = launch_zero_count(S->adj_retry, st)) == hipSuccess &&
@@ -1200,6 +1209,7 @@ hipError_t ensure_streams(ags_sim* S) {
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->aux2, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_big_start, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_big_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->ev_big_listed, hipEventDisableTiming);
   return e;
 }
 
