@@ -300,3 +300,34 @@ def test_dispatch_order_beyond_one_lds_batch():
     for x, y in zip(*outs):
         assert torch.isfinite(x).all()
         assert torch.equal(x, y[inv])
+
+
+@pytest.mark.parametrize("fp64", [True, False], ids=["fp64", "fp32"])
+def test_resume_from_a_saved_state_in_a_fresh_sim(fp64):
+    """Checkpoint and resume: N steps in one sim equal k steps, a copy of the state to the host, and N - k
+    steps in a newly created sim started from that copy, bitwise (the state tensors are the whole state
+    of an env-step; the dispatch order a sim builds up changes no result)."""
+    env = W.env_humanoid()
+    E, N, k = 256, 12, 5
+    p = W.SimParams()
+    root, dof = W.initial_state(env, E, 4)
+    acts = torch.tensor(W.actuation(env, E, N, 4).reshape(N, -1), dtype=torch.float32, device="cuda:0")
+    r0 = torch.tensor(root.reshape(-1, 13), dtype=torch.float32, device="cuda:0")
+    d0 = torch.tensor(dof.reshape(-1, 2), dtype=torch.float32, device="cuda:0")
+
+    def run(r, d, t0, t1):
+        sim = ags.Sim([ags.Model(env)], [0] * E, p, device="cuda:0", fp64=fp64)
+        sim.root_state.copy_(r)
+        sim.dof_state.copy_(d)
+        for t in range(t0, t1):
+            sim.actuation.copy_(acts[t])
+            sim.step()
+        torch.cuda.synchronize()
+        return sim.root_state.clone(), sim.dof_state.clone()
+
+    ra, da = run(r0, d0, 0, N)
+    rk, dk = run(r0, d0, 0, k)
+    saved = (rk.cpu().numpy().copy(), dk.cpu().numpy().copy())  # the checkpoint leaves the device
+    rb, db = run(torch.from_numpy(saved[0]).to("cuda:0"), torch.from_numpy(saved[1]).to("cuda:0"), k, N)
+    assert torch.isfinite(ra).all()
+    assert torch.equal(ra, rb) and torch.equal(da, db)
