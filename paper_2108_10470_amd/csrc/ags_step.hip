@@ -1867,9 +1867,13 @@ __device__ __forceinline__ void step_group(const StepArgs& P, const TypeArgs& T,
 // for the FP64 two-environments-per-wavefront form whose LDS allows one workgroup per SIMD anyway.
 template <typename R, int TEAM>
 constexpr int kWavesPerEU = (sizeof(R) == 4 || TEAM == 64) ? 2 : 1;
+// the per-type FP32 launch with one env per wavefront fits three wavefronts per SIMD (<= 168 registers; its
+// ~9 KB of LDS admits twelve workgroups per CU)
+template <typename R, int TEAM>
+constexpr int kStepWavesPerEU = (sizeof(R) == 4 && TEAM == 64) ? 3 : kWavesPerEU<R, TEAM>;
 
 template <typename R, int TEAM, bool TGS, bool CYC = false>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kWavesPerEU<R, TEAM>))) void step_kernel(StepArgs P) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kStepWavesPerEU<R, TEAM>))) void step_kernel(StepArgs P) {
   step_group<R, TEAM, TGS, CYC>(P, P.ty, blockIdx.x, true);
 }
 
