@@ -23,7 +23,7 @@ struct AdjLds {
   int colS, colY, colYv, cs;                                       // per column, 6 each
   int q, qb, ab;                                                   // per DOF
   int st, rbar, dbar, nrb;                                             // state of each substep start, state adjoint
-  int Lm, nvp, ldi;                                                // dense n_v x nvp matrix (factor, then P); 1 / diag of the factor
+  int Lm, nvp, ldi;  // packed lower triangle of an n_v x n_v matrix (factor, then P); row stride of J, W; 1 / diag of the factor
   int J, W, A, Ab, rcp;  // rows: J, W (rows x nvp); A and S = Abar + Abar^T (packed symmetric)
   int rbc, rb, rinvA, rlam, rybar, rbbar, rx, rcen, rd, rxb, rqb;  // per row reals
   int rdb, rwa, rwb;                                               // per row: d adjoint, wrenches of bodies a, b
@@ -67,7 +67,7 @@ inline AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iter
   L.st = take((substeps + 1) * L.state_words);
   L.rbar = take(13 * na); L.dbar = take(2 * nd); L.nrb = take(13 * na);
   L.nvp = nv | 1;
-  L.Lm = take(nv * L.nvp);
+  L.Lm = take(nv * (nv + 1) / 2);  // entry (i, j), j <= i, at i (i + 1) / 2 + j
   L.ldi = take(nv);
   L.rcp = rc | 1;
   // arrays with disjoint lifetimes in a reverse substep share words: W is dead once P is formed, when the

@@ -305,6 +305,8 @@ __device__ __forceinline__ void sphere_box(V3<R> c, const R* Rb, V3<R> b, V3<R> 
 
 // packed symmetric storage: element (i, j) of a symmetric matrix
 __device__ __forceinline__ int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
+// start of row i of a packed lower triangle (entries (i, j), j <= i)
+__device__ __forceinline__ int lrow(int i) { return i * (i + 1) / 2; }
 
 // ---------------------------------------------------------------- wavefront GEMM on the matrix cores
 // C = X Y (M x N, inner dimension K, each at most 64) by one wavefront with 16x16x4 MFMA tiles.  x(i, k)
@@ -476,16 +478,16 @@ template <typename R>
 __device__ R chol_solve_lanes(const Env<R>& E, R b) {
   const R* Lm = E.r + E.P->L.Lm;
   const R* ldi = E.r + E.P->L.ldi;
-  const int nvp = E.P->L.nvp, nv = E.nv, c = E.lane;
+  const int nv = E.nv, c = E.lane;
   for (int k = 0; k < nv; ++k) {
     const R xk = lane_read(b, k) * ldi[k];
     if (c == k) b = xk;
-    if (c > k && c < nv) b -= Lm[c * nvp + k] * xk;
+    if (c > k && c < nv) b -= Lm[lrow(c) + k] * xk;
   }
   for (int k = nv - 1; k >= 0; --k) {
     const R xk = lane_read(b, k) * ldi[k];
     if (c == k) b = xk;
-    if (c < k) b -= Lm[k * nvp + c] * xk;
+    if (c < k) b -= Lm[lrow(k) + c] * xk;
   }
   return c < nv ? b : R(0);
 }
@@ -496,7 +498,7 @@ template <typename R>
 __device__ void chol_solve_row(const Env<R>& E, R* y) {
   const R* Lm = E.r + E.P->L.Lm;
   const R* ldi = E.r + E.P->L.ldi;
-  const int nvp = E.P->L.nvp, nv = E.nv;
+  const int nv = E.nv;
   if (nv <= kRegSolve) {
     // the lane's row in registers: the substitutions' chains run through registers instead of a store and a
     // load of every solved entry (entries past n_v are zero and their factor reads are masked)
@@ -506,7 +508,7 @@ __device__ void chol_solve_row(const Env<R>& E, R* y) {
 #pragma unroll
     for (int k = 0; k < kRegSolve; ++k) {
       if (k < nv) {
-        const R* Lk = Lm + k * nvp;
+        const R* Lk = Lm + lrow(k);
         R t[4] = {v[k], R(0), R(0), R(0)};
 #pragma unroll
         for (int j = 0; j < k; ++j) t[j & 3] -= Lk[j] * v[j];
@@ -519,7 +521,7 @@ __device__ void chol_solve_row(const Env<R>& E, R* y) {
         R t[4] = {v[k], R(0), R(0), R(0)};
 #pragma unroll
         for (int j = k + 1; j < kRegSolve; ++j) {
-          const R l = Lm[min(j, nv - 1) * nvp + k];
+          const R l = Lm[lrow(min(j, nv - 1)) + k];
           t[j & 3] -= (j < nv ? l : R(0)) * v[j];
         }
         v[k] = ((t[0] + t[1]) + (t[2] + t[3])) * ldi[k];
@@ -531,7 +533,7 @@ __device__ void chol_solve_row(const Env<R>& E, R* y) {
     return;
   }
   for (int k = 0; k < nv; ++k) {
-    const R* Lk = Lm + k * nvp;
+    const R* Lk = Lm + lrow(k);
     R t0 = y[k], t1 = R(0), t2 = R(0), t3 = R(0);
     int j = 0;
     for (; j + 3 < k; j += 4) {
@@ -547,12 +549,12 @@ __device__ void chol_solve_row(const Env<R>& E, R* y) {
     R t0 = y[k], t1 = R(0), t2 = R(0), t3 = R(0);
     int j = k + 1;
     for (; j + 3 < nv; j += 4) {
-      t0 -= Lm[j * nvp + k] * y[j];
-      t1 -= Lm[(j + 1) * nvp + k] * y[j + 1];
-      t2 -= Lm[(j + 2) * nvp + k] * y[j + 2];
-      t3 -= Lm[(j + 3) * nvp + k] * y[j + 3];
+      t0 -= Lm[lrow(j) + k] * y[j];
+      t1 -= Lm[lrow(j + 1) + k] * y[j + 1];
+      t2 -= Lm[lrow(j + 2) + k] * y[j + 2];
+      t3 -= Lm[lrow(j + 3) + k] * y[j + 3];
     }
-    for (; j < nv; ++j) t0 -= Lm[j * nvp + k] * y[j];
+    for (; j < nv; ++j) t0 -= Lm[lrow(j) + k] * y[j];
     y[k] = ((t0 + t1) + (t2 + t3)) * ldi[k];
   }
 }
@@ -719,16 +721,16 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     const SV<R> sk = col_s(E, k);
     const SV<R> F = comp_mul(E.at(L.Ic, E.col_link(k), 10), sk);
     const unsigned long long anc = M.col_anc[k];
-    for (int j = 0; j < k; ++j) Lm[k * nvp + j] = ((anc >> j) & 1ull) ? sdot(col_s(E, j), F) : R(0);
-    Lm[k * nvp + k] = sdot(sk, F) + arm[k];
+    for (int j = 0; j < k; ++j) Lm[lrow(k) + j] = ((anc >> j) & 1ull) ? sdot(col_s(E, j), F) : R(0);
+    Lm[lrow(k) + k] = sdot(sk, F) + arm[k];
   }
   sync<R>();
   // ---- dense Cholesky in place, left-looking: column k from the finished columns j < k (lane = row)
   for (int k = 0; k < nv; ++k) {
     R sacc = R(0);
     if (lane >= k && lane < nv) {
-      const R* Li = Lm + lane * nvp;
-      const R* Lk = Lm + k * nvp;
+      const R* Li = Lm + lrow(lane);
+      const R* Lk = Lm + lrow(k);
       R t0 = Li[k], t1 = R(0), t2 = R(0), t3 = R(0);
       int j = 0;
       for (; j + 3 < k; j += 4) {
@@ -742,7 +744,7 @@ __device__ __forceinline__ bool fwd_substep(Env<R>& E, const R* sin, R* sout) {
     }
     const R d = sqrt_(lane_read(sacc, k));
     const R di = R(1) / d;
-    if (lane >= k && lane < nv) Lm[lane * nvp + k] = lane == k ? d : sacc * di;
+    if (lane >= k && lane < nv) Lm[lrow(lane) + k] = lane == k ? d : sacc * di;
     if (lane == 0) E.r[L.ldi + k] = di;
     sync<R>();
   }
@@ -1293,7 +1295,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   wave_gemm<R>(
       nv, nv, Rn, lane, [&](int i, int s2) { return J[rmap[s2] * nvp + i]; }, [&](int s2, int k) { return W[rmap[s2] * nvp + k]; },
       [&](int i, int k, R t) {
-        Lm[i * nvp + k] = R(0.5) * (t + (nu1[i] - vs[i]) * zz[k] + zz[i] * (nu1[k] - vs[k]) + qdd[i] * ww[k] + ww[i] * qdd[k]);
+        if (k <= i) Lm[lrow(i) + k] = R(0.5) * (t + (nu1[i] - vs[i]) * zz[k] + zz[i] * (nu1[k] - vs[k]) + qdd[i] * ww[k] + ww[i] * qdd[k]);
       });
   sync<R>();
   // ---- Jbar = T + lambda z^T + ybar v*^T
@@ -1324,10 +1326,10 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
     const unsigned long long anc = M.col_anc[k];
     SV<R> y = sz<R>();
     for (int j = 0; j < k; ++j)
-      if ((anc >> j) & 1ull) y = sadd(y, smul(col_s(E, j), Lm[k * nvp + j]));
+      if ((anc >> j) & 1ull) y = sadd(y, smul(col_s(E, j), Lm[lrow(k) + j]));
     const R* Ic = E.at(L.Ic, E.col_link(k), 10);
     const SV<R> Is = comp_mul(Ic, sk), Iy = comp_mul(Ic, y);
-    sts6(colS + 6 * k, smul(sadd(Iy, smul(Is, Lm[k * nvp + k])), R(-2)));
+    sts6(colS + 6 * k, smul(sadd(Iy, smul(Is, Lm[lrow(k) + k])), R(-2)));
     sts6(colY + 6 * k, smul(Is, R(-2)));
     sts6(colYv + 6 * k, y);
   }
@@ -1335,7 +1337,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   for (int j = lane; j < nv; j += 64) {
     SV<R> a = lds6(colS + 6 * j);
     for (int k = j + 1; k < nv; ++k)
-      if ((M.col_anc[k] >> j) & 1ull) a = sadd(a, smul(lds6(colY + 6 * k), Lm[k * nvp + j]));
+      if ((M.col_anc[k] >> j) & 1ull) a = sadd(a, smul(lds6(colY + 6 * k), Lm[lrow(k) + j]));
     sts6(colS + 6 * j, a);
   }
   sync<R>();
@@ -1352,7 +1354,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
       if (!((la >> E.col_link(k)) & 1ull)) continue;
       const SV<R> sk = col_s(E, k);
       bil(m, cw, Iw, sk, lds6(colYv + 6 * k), R(-2), cb, tI);
-      bil(m, cw, Iw, sk, sk, -Lm[k * nvp + k], cb, tI);
+      bil(m, cw, Iw, sk, sk, -Lm[lrow(k) + k], cb, tI);
     }
     if (li[LI_PARENT] >= 0) {
       acc6(E.at(L.sb, i, 6), lds6(colS + 6 * li[LI_COL]));

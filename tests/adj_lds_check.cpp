@@ -85,8 +85,9 @@ int main(int argc, char** argv) {
       // the start state of every substep and the end state (st + s * state_words, s <= substeps)
       {"st", L.st, (long)(substeps + 1) * L.state_words, false},
       {"rbar", L.rbar, 13l * na, false}, {"dbar", L.dbar, 2l * nd, false}, {"nrb", L.nrb, 13l * na, false},
-      // dense n_v x nvp factor (then P) and its reciprocal diagonal
-      {"Lm", L.Lm, (long)nv * nvp, false}, {"ldi", L.ldi, nv, false},
+      // packed lower triangle of the factor (then P): entry (i, j), j <= i < n_v, at i (i + 1) / 2 + j; the
+      // reciprocal diagonal
+      {"Lm", L.Lm, (long)nv * (nv + 1) / 2, false}, {"ldi", L.ldi, nv, false},
       // rows: J and W rows (row < rows_cap, column < n_v at stride nvp)
       {"J", L.J, (long)(rc - 1) * nvp + nv, false}, {"W", L.W, (long)(rc - 1) * nvp + nv, false},
       // mass-matrix column vectors, alive after W is dead, in W's words
