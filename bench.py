@@ -27,9 +27,10 @@ sys.path.insert(0, ROOT)
 METRIC = "env-steps/s fwd and fwd+bwd, 4096-env humanoid, at stated err vs FP64 oracle"
 
 # algorithmic cost per env-step of the humanoid workload (two substeps), R = mean constraint rows per
-# substep: flops ~ 37e3 + 5.1e3 R; bytes = state + actions read, state + contact forces written
+# substep: flops ~ 37e3 + 5.1e3 R; bytes = state (55 floats) + actions (21) read, state + the 13 bodies' contact
+# forces (39) + the DOF forces (21, an output the bench binds) written
 FLOPS_BASE, FLOPS_PER_ROW = 37.0e3, 5.1e3
-BYTES_PER_ENV_STEP = 680.0
+BYTES_PER_ENV_STEP = 764.0
 PEAK_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP32 unpacked == FP64 vector)
 PEAK_HBM_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2108_10470_amd", "csrc")
