@@ -18,7 +18,7 @@ constexpr int kLinkIntCols = 10;  // ints per link of the model's link table
 // per-environment LDS layout of the adjoint kernel: offsets in elements of the compute type (reals)
 // or in ints (integer region, placed after the reals)
 struct AdjLds {
-  int Rm, p, ax, c, Iw, Ic, V, Vs, X0, X1, X2, X3, wr, sb, cb, tI;  // per link
+  int Rm, p, ax, c, Iw, Ic, V, Vs, X0, X1, X2, X3, wr, sb, cb, tI;  // per link (X0, X2, X3 in A's words; wr..tI in the tape's)
   int nu, qdd, vs, nu1, tau, arm, z, w, nub, vsb, nui, tmp;        // per column
   int colS, colY, colYv, cs;                                       // per column, 6 each
   int q, qb, ab;                                                   // per DOF
@@ -56,9 +56,7 @@ inline AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iter
   const int rc = std::min(std::max(1, info.max_rows), row_cap);
   L.rows_cap = rc;
   L.Rm = take(9 * nl); L.p = take(3 * nl); L.ax = take(3 * nl); L.c = take(3 * nl); L.Iw = take(6 * nl);
-  L.Ic = take(10 * nl); L.V = take(6 * nl); L.Vs = take(6 * nl); L.X0 = take(6 * nl); L.X1 = take(6 * nl);
-  L.X2 = take(6 * nl); L.X3 = take(6 * nl); L.wr = take(6 * nl); L.sb = take(6 * nl); L.cb = take(3 * nl);
-  L.tI = take(3 * nl);
+  L.Ic = take(10 * nl); L.V = take(6 * nl); L.Vs = take(6 * nl); L.X1 = take(6 * nl);
   L.nu = take(nv); L.qdd = take(nv); L.vs = take(nv); L.nu1 = take(nv); L.tau = take(nv); L.arm = take(nv);
   L.z = take(nv); L.w = take(nv); L.nub = take(nv); L.vsb = take(nv); L.nui = take(nv); L.tmp = take(nv);
   L.cs = take(6 * nv);
@@ -70,18 +68,22 @@ inline AdjLds make_adj_layout(const ags_model_info& info, int substeps, int iter
   L.Lm = take(nv * (nv + 1) / 2);  // entry (i, j), j <= i, at i (i + 1) / 2 + j
   L.ldi = take(nv);
   L.rcp = rc | 1;
-  // arrays with disjoint lifetimes in a reverse substep share words: W is dead once P is formed, when the
-  // mass-matrix terms' column vectors are written; A and S = Abar + Abar^T are dead after the reverse
-  // Gauss-Seidel and T = S W, when the rows' reverse arrays are written
+  // arrays with disjoint lifetimes share words: W is dead once P is formed, when the mass-matrix terms' column
+  // vectors are written; A and S = Abar + Abar^T are dead after the reverse Gauss-Seidel and T = S W, when
+  // the reverse RNEA's per-link temporaries X0, X2, X3 and then the rows' reverse arrays are written (X2 also
+  // holds the forward RNEA's forces, before A is formed); the Gauss-Seidel tape is dead after the reverse
+  // Gauss-Seidel, when the reverse pass's per-link accumulators wr, sb, cb, tI are cleared
   L.J = take(rc * L.nvp);
   L.W = take(std::max(rc * L.nvp, 18 * nv));
   L.colS = L.W; L.colY = L.W + 6 * nv; L.colYv = L.W + 12 * nv;
   const int ntri = rc * (rc + 1) / 2;
-  L.A = take(std::max(2 * ntri, 19 * rc)); L.Ab = L.A + ntri;
+  L.A = take(std::max({2 * ntri, 19 * rc, 18 * nl})); L.Ab = L.A + ntri;
+  L.X0 = L.A; L.X2 = L.A + 6 * nl; L.X3 = L.A + 12 * nl;
   L.rxb = L.A; L.rdb = L.A + 3 * rc; L.rqb = L.A + 6 * rc; L.rwa = L.A + 7 * rc; L.rwb = L.A + 13 * rc;
   L.rbc = take(rc); L.rb = take(rc); L.rinvA = take(rc); L.rlam = take(rc); L.rybar = take(rc); L.rbbar = take(rc);
   L.rx = take(3 * rc); L.rcen = take(3 * rc); L.rd = take(3 * rc);
-  L.hlo = take(iters * L.rcp); L.hres = take(iters * L.rcp);
+  L.hlo = take(std::max(2 * iters * L.rcp, 18 * nl)); L.hres = L.hlo + iters * L.rcp;
+  L.wr = L.hlo; L.sb = L.hlo + 6 * nl; L.cb = L.hlo + 12 * nl; L.tI = L.hlo + 15 * nl;
   L.misc = take(8);
   L.n_real = (off + 1) & ~1;
   off = 0;

@@ -1159,15 +1159,7 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
   const int* rdof = E.ix + L.rdof;
   const int* rnrm = E.ix + L.rnrm;
   E.phase(7);
-  // ---- clear accumulators
-  for (int k = lane; k < 6 * nl; k += 64) {
-    E.r[L.wr + k] = R(0);
-    E.r[L.sb + k] = R(0);
-  }
-  for (int k = lane; k < 3 * nl; k += 64) {
-    E.r[L.cb + k] = R(0);
-    E.r[L.tI + k] = R(0);
-  }
+  // ---- clear accumulators (the per-link ones further down: they share the words of the Gauss-Seidel tape)
   for (int c = lane; c < nv; c += 64) nub[c] = R(0);
   for (int k = lane; k < 13 * na; k += 64) nrb[k] = R(0);
   sync<R>();
@@ -1316,6 +1308,17 @@ __device__ __forceinline__ void rev_substep(Env<R>& E, const R* sin) {
     qb[j] -= kp * ww[c];
     nui[c] -= (h * kp + kd) * ww[c];
   }
+  // ---- per-link accumulators, in the words of the Gauss-Seidel tape (read for the last time above)
+  sync<R>();
+  for (int k = lane; k < 6 * nl; k += 64) {
+    E.r[L.wr + k] = R(0);
+    E.r[L.sb + k] = R(0);
+  }
+  for (int k = lane; k < 3 * nl; k += 64) {
+    E.r[L.cb + k] = R(0);
+    E.r[L.tI + k] = R(0);
+  }
+  sync<R>();
   E.phase(4);
   // ---- d tr(M P)/dq, weight -1: per column y_k, s_bar and y_bar
   R* colS = E.r + L.colS;

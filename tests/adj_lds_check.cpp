@@ -71,8 +71,10 @@ int main(int argc, char** argv) {
       // per link i < n_links: a fixed width each
       {"Rm", L.Rm, 9l * nl, false}, {"p", L.p, 3l * nl, false}, {"ax", L.ax, 3l * nl, false},
       {"c", L.c, 3l * nl, false}, {"Iw", L.Iw, 6l * nl, false}, {"Ic", L.Ic, 10l * nl, false},
-      {"V", L.V, 6l * nl, false}, {"Vs", L.Vs, 6l * nl, false}, {"X0", L.X0, 6l * nl, false},
-      {"X1", L.X1, 6l * nl, false}, {"X2", L.X2, 6l * nl, false}, {"X3", L.X3, 6l * nl, false},
+      {"V", L.V, 6l * nl, false}, {"Vs", L.Vs, 6l * nl, false}, {"X1", L.X1, 6l * nl, false},
+      // the RNEA's per-link temporaries, in A's words (A is dead while they live)
+      {"X0", L.X0, 6l * nl, false}, {"X2", L.X2, 6l * nl, false}, {"X3", L.X3, 6l * nl, false},
+      // the reverse pass's per-link accumulators, in the Gauss-Seidel tape's words (cleared after its last read)
       {"wr", L.wr, 6l * nl, false}, {"sb", L.sb, 6l * nl, false}, {"cb", L.cb, 3l * nl, false},
       {"tI", L.tI, 3l * nl, false},
       // per generalized velocity column
@@ -125,19 +127,29 @@ int main(int argc, char** argv) {
       g_fail = 1;
     }
   };
-  const long w_words = std::max((long)rc * nvp, 18l * nv), a_words = std::max(2 * ntri, 19l * rc);
+  const long w_words = std::max((long)rc * nvp, 18l * nv), a_words = std::max({2 * ntri, 19l * rc, 18l * nl});
+  const long t_words = std::max(2l * iters * rcp, 18l * nl);
   inside("colS", L.colS, 6l * nv, L.W, w_words);
   inside("colY", L.colY, 6l * nv, L.W, w_words);
   inside("colYv", L.colYv, 6l * nv, L.W, w_words);
   inside("Ab", L.Ab, ntri, L.A, a_words);
   inside("rxb..rwb", L.rxb, 19l * rc, L.A, a_words);
+  inside("X0", L.X0, 6l * nl, L.A, a_words);
+  inside("X2", L.X2, 6l * nl, L.A, a_words);
+  inside("X3", L.X3, 6l * nl, L.A, a_words);
+  inside("wr", L.wr, 6l * nl, L.hlo, t_words);
+  inside("sb", L.sb, 6l * nl, L.hlo, t_words);
+  inside("cb", L.cb, 3l * nl, L.hlo, t_words);
+  inside("tI", L.tI, 3l * nl, L.hlo, t_words);
+  inside("hres", L.hres, (long)(iters - 1) * rcp + rc, L.hlo, t_words);
   // arrays with their own words do not overlap: a word touched twice belongs to a shared region
   std::vector<int> owner((size_t)L.n_real, -1);
   for (size_t k = 0; k < arrays.size(); ++k) {
     const Arr& a = arrays[k];
     const std::string n = a.name;
     if (a.ints || n == "colS" || n == "colY" || n == "colYv" || n == "Ab" || n == "rxb" || n == "rdb" || n == "rqb" ||
-        n == "rwa" || n == "rwb")
+        n == "rwa" || n == "rwb" || n == "X0" || n == "X2" || n == "X3" || n == "wr" || n == "sb" || n == "cb" ||
+        n == "tI")
       continue;
     for (long i = a.off; i < a.off + a.use && i < L.n_real; ++i) {
       if (owner[i] >= 0) {
