@@ -1725,8 +1725,8 @@ __device__ __forceinline__ void adjoint_env(const AdjArgs& P, int ei) {
     for (int k = 0; k < kAdjPhases; ++k) P.cycles[(long long)env * kAdjPhases + k] = g_adj_clock[k];
 }
 
-// Register budget: FP32 forms at two wavefronts per SIMD (<= 256 registers: LDS admits five workgroups per
-// CU with the small layout); FP64 forms at one (their LDS admits two workgroups per CU anyway)
+// Register budget: FP32 forms at two wavefronts per SIMD (<= 256 registers: LDS admits six workgroups per
+// CU with the humanoid's small layout); FP64 forms at one (their LDS admits three workgroups per CU anyway)
 template <typename R>
 constexpr int kAdjWavesPerEU = sizeof(R) == 4 ? 2 : 1;
 
