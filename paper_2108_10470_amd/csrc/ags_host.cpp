@@ -1072,7 +1072,8 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
         // is built, when the flagged launch is already queued behind it on the third stream: its workgroups
         // then find LDS room before pass 1's fill the CUs (started together, they waited for pass 1's
         // workgroups to finish and ended last; 64-step humanoid reverse pass 319 -> 299 ms).  With two per CU
-        // (FP32) the same head start left pass 1 one workgroup per CU and was slower (145 vs 136 ms).
+        // (FP32) the same head start was slower with the earlier five-per-CU small layout (145 vs 136 ms) and is
+        // no faster with the six-per-CU one (126.6 vs 126.7 ms).
         const bool gate = big_per_cu == 1;
         if ((e = hipEventRecord(S->ev_big_start, st)) == hipSuccess &&
             (e = hipStreamWaitEvent(S->aux2, S->ev_big_start, 0)) == hipSuccess &&
