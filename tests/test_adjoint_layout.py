@@ -63,6 +63,23 @@ def test_humanoid_fp64_full_layout_reaches_beyond_64_kib(checker):
     assert d["bytes_f64"] > 65536 and all(x in above for x in ("hst", "Ab", "rbc", "hlo")), d
 
 
+def test_humanoid_small_layouts_fit_six_fp32_or_three_fp64_workgroups_per_cu(checker):
+    """The pass-1 (32-row) layouts of the humanoid-like model, as the runtime builds them (FP32 without and FP64
+    with the staged model tables; two substeps, eight sweeps), plus the kernels' 104 B of static LDS, fit six
+    (FP32) or three (FP64) workgroups in a CU's 163,840 B of LDS: the reverse pass's throughput rests on it."""
+    info = ags.Model(W.env_humanoid()).info
+    static_lds, cu_lds = 104, 163840
+    sizes = {}
+    for staged, key, per_cu in ((0, "bytes_f32", 6), (1, "bytes_f64", 3)):
+        r = subprocess.run([checker, *[str(x) for x in (info.n_links, info.n_v, info.n_dof, info.n_actors,
+                                                        info.max_rows, 2, 8, 32, staged)]],
+                           capture_output=True, text=True, check=True)
+        d = json.loads(r.stdout)
+        sizes[key] = d[key]
+        assert per_cu * (d[key] + static_lds) <= cu_lds, (key, d[key])
+    print(sizes)
+
+
 def test_adjoint_kernels_reach_lds_through_ds_instructions_only(tmp_path):
     asm = tmp_path / "adj.s"
     subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "--cuda-device-only", "-S", "-O3",
