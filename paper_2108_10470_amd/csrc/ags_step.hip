@@ -434,7 +434,13 @@ __device__ __forceinline__ int actor_of_root(const Tab<R>& M, int link) {
 
 // clamp to [lo, hi] (lo <= hi): one median-of-three in FP32
 __device__ __forceinline__ float clamp_(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
-__device__ __forceinline__ double clamp_(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
+// in FP64 a max then a min, written out: fmin/fmax of loop-carried bounds compile to two more instructions per
+// call that quiet signalling NaNs, which no operand here can be
+__device__ __forceinline__ double clamp_(double x, double lo, double hi) {
+  double r;
+  asm("v_max_f64 %0, %1, %2\n\tv_min_f64 %0, %0, %3" : "=&v"(r) : "v"(x), "v"(lo), "v"(hi));
+  return r;
+}
 
 // upper impulse bound of rows without one (contact normals, limits): far above any impulse, finite so that
 // the friction-bound arithmetic of the register Gauss-Seidel stays free of infinities
