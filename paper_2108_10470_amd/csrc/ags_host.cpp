@@ -1071,7 +1071,8 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
         // With one flagged workgroup per CU (the FP64 layouts), pass 1 is released only once the flagged list
         // is built, when the flagged launch is already queued behind it on the third stream: its workgroups
         // then find LDS room before pass 1's fill the CUs (started together, they waited for pass 1's
-        // workgroups to finish and ended last; 64-step humanoid reverse pass 319 -> 299 ms).  With two per CU
+        // workgroups to finish and ended last; 64-step humanoid reverse pass 319 -> 299 ms with two pass-1 workgroups
+        // per CU, 236 -> 213 ms with three).  With two per CU
         // (FP32) the same head start was slower with the earlier five-per-CU small layout (145 vs 136 ms) and is
         // no faster with the six-per-CU one (126.6 vs 126.7 ms).
         const bool gate = big_per_cu == 1;
