@@ -1058,15 +1058,21 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
       const hipStream_t st = (hipStream_t)stream;
       if (S->adj_big) {
         // environments the forward flagged run with the full layout on the third stream, concurrently with
-        // pass 1 (which skips them): a device list of them, strided over by one workgroup per CU (a launch of
-        // one workgroup per env would wait for LDS room for each of its mostly empty workgroups); the caller's
-        // stream waits for them before its next work.  Pass 1 is released only once the flagged list is
-        // built, when the flagged launch is already queued behind it on the third stream: its workgroups then
-        // find LDS room before pass 1's fill the CUs (started together, they waited for pass 1's workgroups
-        // to finish and ended last).  64-step humanoid reverse pass, FP64 adjoint: 236 -> 213 ms; FP32
-        // adjoint: 127.0 ms with two flagged workgroups per CU started together with pass 1, 124.1 ms with
-        // one per CU queued first (the CU keeps room for four pass-1 workgroups beside it).
-        const int big_per_cu = 1;
+        // pass 1 (which skips them): a device list of them, strided over by a few workgroups per CU (a launch
+        // of one workgroup per env would wait for LDS room for each of its mostly empty workgroups); the
+        // caller's stream waits for them before its next work.  A batch of at most 16 envs per CU has about
+        // as many flagged envs as CUs: one workgroup per CU, and pass 1 released only once the flagged list
+        // is built, when the flagged launch is already queued behind it on the third stream, so that its
+        // workgroups find LDS room before pass 1's fill the CUs (started together, they waited for pass 1's
+        // workgroups to finish and ended last).  64-step reverse pass of 4096 humanoids: FP64 adjoint 236 ->
+        // 213 ms, FP32 adjoint 127.0 ms (two per CU, started together) -> 124.1 ms.  Larger batches have many
+        // flagged envs and the launch is bound by throughput: as many workgroups per CU as LDS holds beside one
+        // of pass 1 (at most two), started together with pass 1 unless that is one (32-step reverse pass of
+        // 65536 hand-like envs, FP32 adjoint: 1144 ms, against 1236 ms with one per CU queued first).
+        const int fit =
+            std::max(1, std::min(2, (int)((160 * 1024 - (long long)T.adj_small_bytes) / (long long)T.adj_bytes)));
+        const int big_per_cu = T.n_envs <= 16 * S->n_cu ? 1 : fit;
+        const bool gate = big_per_cu == 1;
         a1.skip_flags = S->adj_big;
         AdjArgs ab = a;
         ab.env_list = S->adj_big_list + 1;
@@ -1078,7 +1084,7 @@ extern "C" int ags_sim_step_backward(ags_sim* S, const float* root_state, const 
             (e = hipEventRecord(S->ev_big_listed, S->aux2)) == hipSuccess &&
             (e = launch_adjoint(ab, T.n_envs, adj_fp64(p), S->aux2, S->n_cu * big_per_cu)) == hipSuccess)
           e = hipEventRecord(S->ev_big_done, S->aux2);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, S->ev_big_listed, 0);
+        if (e == hipSuccess && gate) e = hipStreamWaitEvent(st, S->ev_big_listed, 0);
         if (e != hipSuccess) return hip_fail(e, "step_backward: flagged pass");
       }
       if ((e = launch_zero_count(S->adj_retry, st)) == hipSuccess &&
